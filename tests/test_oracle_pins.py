@@ -1,0 +1,418 @@
+"""Pins of the CPU oracle against definitions that do not go through it.
+
+Each test fixes one building block by something other than the oracle's own
+code: brute-force convolution, direct polynomial evaluation, exact CRT,
+closed forms, brute force over tiny inputs, the paper's printed sizes.
+"""
+import hashlib
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import bfv, compress as C, decompress as D, rng, slots
+from oracle.params import make_params, is_prime
+from oracle.ring import Poly, automorphism, negacyclic_mul_limb, ntt_limb, intt_limb, psi_for
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------- ring
+
+def brute_negacyclic(a, b, q):
+    n = len(a)
+    out = [0] * n
+    for i in range(n):
+        for j in range(n):
+            k = i + j
+            if k < n:
+                out[k] += int(a[i]) * int(b[j])
+            else:
+                out[k - n] -= int(a[i]) * int(b[j])
+    return [x % q for x in out]
+
+
+@pytest.mark.parametrize("n,q", [(8, 17), (16, 97), (64, 18014398509309953), (32, 1152921504606830593)])
+def test_ring_product_matches_brute_force(n, q):
+    r = np.random.default_rng(n)
+    for _ in range(3):
+        a = np.array([int(x) for x in r.integers(0, 2**62, n)], dtype=object) % q
+        b = np.array([int(x) for x in r.integers(0, 2**62, n)], dtype=object) % q
+        got = negacyclic_mul_limb(a.astype(np.uint64), b.astype(np.uint64), q)
+        assert [int(x) for x in got] == brute_negacyclic(a, b, q)
+
+
+def test_ntt_is_evaluation_at_odd_powers():
+    n, q = 16, 97
+    psi = psi_for(n, q)
+    assert pow(psi, n, q) == q - 1
+    a = np.arange(3, 3 + n, dtype=np.uint64)
+    ev = ntt_limb(a, q)
+    for i in range(n):
+        x = pow(psi, 2 * i + 1, q)
+        assert int(ev[i]) == sum(int(a[j]) * pow(x, j, q) for j in range(n)) % q
+    assert np.array_equal(intt_limb(ev, q), a)
+
+
+# --------------------------------------------------------------------------- params
+
+def fermat_probable_prime(x):
+    return all(pow(b, x - 1, x) == 1 for b in (2, 3, 5, 7))
+
+
+@pytest.mark.parametrize("n,p,L,qb,K,pb", [
+    (4096, 65537, 2, 54, 1, 60), (1 << 15, 65537, 14, 55, 2, 60), (1 << 16, 786433, 24, 55, 3, 60)])
+def test_primes_rule(n, p, L, qb, K, pb):
+    pr = make_params(n, p, L, qb, K, pb)
+    assert len(set(pr.q + pr.sp)) == L + K
+    assert pr.q == sorted(pr.q, reverse=True)
+    for bits, ps in ((qb, pr.q), (pb, pr.sp)):
+        for x in ps:
+            assert x < 2 ** bits and x % (2 * n) == 1 and fermat_probable_prime(x)
+        # no skipped candidate between consecutive chosen primes (largest-first rule)
+        for y in range(ps[0] + 2 * n, 2 ** bits, 2 * n):
+            assert not fermat_probable_prime(y)
+        for a, b in zip(ps, ps[1:]):
+            for y in range(b + 2 * n, a, 2 * n):
+                assert not fermat_probable_prime(y) or y in pr.q
+    assert pr.delta == pr.Q // p
+    assert pow(pr.zeta, n, p) == p - 1
+    assert all(pow(x, n, p) != p - 1 for x in range(2, pr.zeta))
+
+
+def test_is_prime_small_table():
+    sieve = [True] * 2000
+    sieve[0] = sieve[1] = False
+    for i in range(2, 2000):
+        if sieve[i]:
+            for j in range(i * i, 2000, i):
+                sieve[j] = False
+    assert [i for i in range(2000) if is_prime(i)] == [i for i in range(2000) if sieve[i]]
+
+
+# --------------------------------------------------------------------------- slots
+
+def small_params():
+    # n = 16, p = 97 (97 = 1 mod 32); tiny moduli keep brute force cheap
+    return make_params(16, 97, 2, 30, 1, 31)
+
+
+def test_encode_matches_closed_form_and_evaluation():
+    pr = small_params()
+    r = np.random.default_rng(0)
+    sl = r.integers(0, pr.p, size=(2, pr.nh))
+    m = slots.encode(sl, pr)
+    assert [int(x) for x in m] == slots.encode_closed_form(sl, pr.n, pr.p, pr.zeta)
+    for row in range(2):
+        for c in range(pr.nh):
+            x = pow(pr.zeta, slots.exponent(pr.n, row, c), pr.p)
+            assert sum(int(m[i]) * pow(x, i, pr.p) for i in range(pr.n)) % pr.p == sl[row][c]
+    assert np.array_equal(slots.decode(m, pr), sl)
+
+
+def test_exponents_cover_odd_residues():
+    for n in (16, 1024):
+        ex = slots.slot_exponents(n)
+        assert sorted(ex.ravel().tolist()) == list(range(1, 2 * n, 2))
+
+
+def plain_automorphism(coeffs, k, p):
+    n = len(coeffs)
+    out = [0] * n
+    for i, c in enumerate(coeffs):
+        j = i * k % (2 * n)
+        if j < n:
+            out[j] = (out[j] + int(c)) % p
+        else:
+            out[j - n] = (out[j - n] - int(c)) % p
+    return out
+
+
+def test_rotations_are_slot_permutations():
+    """Rot_row(.; r) <-> X -> X^(3^r), Rot_col <-> X -> X^(2n-1) (Sec. 5.1)."""
+    pr = small_params()
+    sl = np.random.default_rng(1).integers(0, pr.p, size=(2, pr.nh))
+    m = slots.encode(sl, pr)
+    for r in range(pr.nh):
+        got = slots.decode(plain_automorphism(m, pow(3, r, 2 * pr.n), pr.p), pr)
+        assert np.array_equal(got, np.roll(sl, -r, axis=1))   # left rotation
+    got = slots.decode(plain_automorphism(m, 2 * pr.n - 1, pr.p), pr)
+    assert np.array_equal(got, sl[::-1])
+    # the RNS automorphism of the oracle agrees with the plain one
+    poly = Poly([pr.p], np.array([m], dtype=np.uint64))
+    assert [int(x) for x in automorphism(poly, 3, ).c[0]] == plain_automorphism(m, 3, pr.p)
+
+
+# --------------------------------------------------------------------------- randomness
+
+def test_shake128_known_answer():
+    # FIPS 202 / NIST example: SHAKE128 of the empty message
+    assert hashlib.shake_128(b"").hexdigest(16) == "7f9c2ba4e88f827d616045507605853e"
+
+
+def test_stream_framing_layout():
+    seed = bytes(range(32))
+    msg = seed + b"pk_a\0\0\0\0" + (5).to_bytes(8, "little") + (2).to_bytes(8, "little") \
+        + (7).to_bytes(8, "little")
+    assert rng.stream(seed, "pk_a", 5, 2, 7, 40) == hashlib.shake_128(msg).digest(40)
+
+
+def test_cdt_table_margin_and_double_precision_agreement():
+    T = rng.cdt_table(3.2)
+    rho = [math.exp(-x * x / (2 * 3.2 * 3.2)) for x in range(20)]
+    S = rho[0] + 2 * sum(rho[1:])
+    acc = 0.0
+    for k in range(20):
+        acc += rho[0] if k == 0 else 2 * rho[k]
+        scaled = acc / S * 2 ** 32
+        if k < 19:
+            assert T[k] == math.floor(scaled + 0.5)
+            assert abs((scaled - math.floor(scaled)) - 0.5) > 2 ** -12  # far from a tie
+    assert T[19] == 2 ** 32 and T == sorted(T)
+
+
+def test_samplers_distribution():
+    seed = bytes(32)
+    g = rng.gaussian(seed, "pk_e", 0, 1 << 14)
+    assert abs(g.std() - 3.2) < 0.15 and abs(g.mean()) < 0.15 and np.abs(g).max() <= 19
+    t = rng.ternary(seed, "sk", 0, 1 << 14)
+    counts = np.bincount(t + 1)
+    assert set(np.unique(t)) <= {-1, 0, 1} and counts.min() > 5000
+    q = 18014398509309953
+    u = rng.uniform_limb(seed, "pk_a", 0, 0, q, 4096)
+    assert u.max() < q and abs(u.astype(float).mean() / q - 0.5) < 0.03
+
+
+# --------------------------------------------------------------------------- BFV
+
+@pytest.fixture(scope="module")
+def p4096():
+    pr = make_params(4096, 65537, 2, 54, 1, 60)
+    sk, pk = bfv.keygen(pr, bytes(32))
+    return pr, sk, pk
+
+
+def test_encrypt_decrypt_and_noise(p4096):
+    pr, sk, pk = p4096
+    sl = np.random.default_rng(2).integers(0, pr.p, size=(2, pr.nh))
+    ct = bfv.encrypt(pr, pk, sl, bytes([1] * 32))
+    assert np.array_equal(bfv.decrypt(pr, sk, ct), sl)
+    assert bfv.noise_bits(pr, sk, ct) < 20 < bfv.noise_budget_bits(pr)
+
+
+def test_plain_product_is_slotwise(p4096):
+    pr, sk, pk = p4096
+    r = np.random.default_rng(3)
+    a = r.integers(0, pr.p, size=(2, pr.nh))
+    m = r.integers(0, pr.p, size=(2, pr.nh))
+    ct = bfv.mul_plain(pr, bfv.encrypt(pr, pk, a, bytes([4] * 32)), bfv.plain_poly(pr, m))
+    assert np.array_equal(bfv.decrypt(pr, sk, ct), a * m % pr.p)
+
+
+def exact_crt(res, mods):
+    M = math.prod(mods)
+    return sum(int(r) * (M // m) * pow(M // m, -1, m) for r, m in zip(res, mods)) % M
+
+
+def test_modup_is_exact_crt_plus_small_multiple(p4096):
+    pr = make_params(4096, 65537, 4, 54, 2, 60)  # two primes per digit
+    r = np.random.default_rng(5)
+    d = Poly(pr.q, np.stack([r.integers(0, q, pr.n, dtype=np.uint64) for q in pr.q]))
+    for j in range(pr.dnum):
+        X = bfv.modup(pr, d, j)
+        I = pr.digit_limbs(j)
+        Dj = math.prod(pr.q[i] for i in I)
+        for coef in range(0, pr.n, 97):
+            x = exact_crt([d.c[i, coef] for i in I], [pr.q[i] for i in I])
+            ok = [all(int(X.c[l, coef]) == (x + u * Dj) % m for l, m in enumerate(pr.qp))
+                  for u in range(len(I))]
+            assert any(ok)
+
+
+def test_moddown_is_division_by_P(p4096):
+    pr = make_params(4096, 65537, 2, 54, 2, 60)
+    r = np.random.default_rng(6)
+    x = [int(v) for v in r.integers(-2**40, 2**40, pr.n)]
+    e = [int(v) for v in r.integers(-2**20, 2**20, pr.n)]
+    T = Poly.from_ints(pr.qp, [pr.P * a + b for a, b in zip(x, e)])
+    out = bfv.moddown(pr, T)
+    for coef in range(0, pr.n, 61):
+        val = exact_crt(out.c[:, coef], pr.q)
+        val = val - pr.Q if val > pr.Q // 2 else val
+        # floor((P x + e) / P) minus a BConv overflow u in [0, K]
+        base = (pr.P * x[coef] + e[coef]) // pr.P
+        assert base - pr.K <= val <= base
+
+
+def test_galois_key_encrypts_gadget_times_rotated_secret(p4096):
+    pr, sk, pk = p4096
+    k = pow(3, 7, 2 * pr.n)
+    gk = bfv.galois_keygen(pr, sk, k, bytes([9] * 32))
+    s = sk.on(pr.qp)
+    srot = automorphism(s, k)
+    for j, (b, a) in enumerate(gk.digits):
+        lhs = b + a * s - srot.scale([bfv.gadget_constant(pr, j, m) for m in pr.qp])
+        for coef in range(0, pr.n, 101):
+            v = exact_crt(lhs.c[:, coef], pr.qp)
+            M = math.prod(pr.qp)
+            v = v - M if v > M // 2 else v
+            assert abs(v) <= 19
+
+
+@pytest.mark.parametrize("r_step", [1, 5, 2047])
+def test_rotation_forms_decrypt_alike(p4096, r_step):
+    pr, sk, pk = p4096
+    sl = np.random.default_rng(r_step).integers(0, pr.p, size=(2, pr.nh))
+    ct = bfv.encrypt(pr, pk, sl, bytes([r_step % 256] * 32))
+    k = bfv.rot_row_element(pr, r_step)
+    gk = bfv.galois_keygen(pr, sk, k, bytes([7] * 32))
+    plain = bfv.rotate(pr, ct, gk)
+    hoisted = bfv.rotate_hoisted(pr, ct, [gk])[0]
+    want = np.roll(sl, -r_step, axis=1)
+    assert np.array_equal(bfv.decrypt(pr, sk, plain), want)
+    assert np.array_equal(bfv.decrypt(pr, sk, hoisted), want)
+    assert not (plain == hoisted)  # hoisting changes bits, not values
+
+
+# --------------------------------------------------------------------------- decompression
+
+def test_newton_matches_direct_expansion():
+    p = 65537
+    r = np.random.default_rng(7)
+    for _ in range(20):
+        s = int(r.integers(1, 9))
+        J = [int(x) for x in r.integers(0, 50, s)]
+        w = [sum(pow(x, j, p) for x in J) % p for j in range(1, s + 1)]
+        poly = [1]
+        for x in J:  # multiply by (X - x), highest degree first
+            poly = [(a - x * b) % p for a, b in zip(poly + [0], [0] + poly)]
+        assert D.f_coefficients(w, p) == poly
+
+
+def test_reconstruction_all_subsets_brute_force():
+    p, N, s = 17, 8, 4
+    for t in range(0, s + 1):
+        for I in itertools.combinations(range(1, N + 1), t):
+            vals = [(3 * i + 1) % p for i in I]
+            d = [0] * N
+            for i, x in zip(I, vals):
+                d[i - 1] = x
+            v = [1 if x else 0 for x in [int(i + 1 in I) for i in range(N)]]
+            w = [sum(pow(i, j, p) * v[i - 1] for i in range(1, N + 1)) % p for j in range(1, s + 1)]
+            e = [sum(pow(i, j, p) * d[i - 1] for i in range(1, N + 1)) % p for j in range(1, s + 1)]
+            idx, got = D.decompress_group(p, N, w, [e])
+            assert idx == list(I) and got == [vals]
+
+
+def test_too_many_matches_is_reported():
+    p, N, s = 65537, 4096, 8
+    r = np.random.default_rng(11)
+    failures = 0
+    for _ in range(10):
+        I = sorted(int(x) + 1 for x in r.choice(N, size=s + 3, replace=False))
+        w = [sum(pow(i, j, p) for i in I) % p for j in range(1, s + 1)]
+        try:
+            idx = D.reconst_idx(w, p, N)
+            assert idx != I
+        except D.DecodeError:
+            failures += 1
+    assert failures >= 8
+
+
+def test_vandermonde_product_definition():
+    p, s = 97, 5
+    x = [3, 0, 7, 1, 0, 96]
+    want = [sum((i + 1) ** j * x[i] for i in range(len(x))) % p for j in range(1, s + 1)]
+    assert C.vandermonde_product(p, s, x) == want
+
+
+# --------------------------------------------------------------------------- schedule
+
+def test_baby_step_rule():
+    # k (B-1) + (s/B - 1) minimised over powers of two, ties to the larger B
+    for s, k in [(16, 2), (256, 2), (1024, 16), (16, 8), (1, 3), (1024, 1)]:
+        costs = {B: k * (B - 1) + (s // B - 1) for B in [2 ** i for i in range(11)] if B <= s}
+        best = min(costs.values())
+        assert C.choose_B(s, k) == max(B for B, c in costs.items() if c == best)
+
+
+def test_group_split_keeps_indices_below_p():
+    for n, p, N in [(4096, 65537, 4096), (1 << 16, 786433, 1 << 20), (1 << 15, 65537, 32 << 15),
+                    (2048, 12289, 7 * 2048), (1 << 15, 65537, 3 << 15)]:
+        sc = C.make_schedule(n, p, N, 1, 16)
+        assert sum(g.n_rec for g in sc.groups) == N
+        assert all(g.n_rec <= p - 1 for g in sc.groups)
+        counts = [g.ct_count for g in sc.groups]
+        assert max(counts) - min(counts) <= 1
+
+
+def test_band_overflow_rejected():
+    with pytest.raises(C.ScheduleError):
+        C.make_schedule(1024, 12289, 1024, 4, 200)   # 3 bands x 256 > 512 slots
+
+
+# --------------------------------------------------------------------------- the paper's sizes
+
+def test_paper_communication_sizes():
+    """Sec. 6.2: one output ciphertext of 110.6 KB, rotation keys of 442.4 KB
+    at n = 2^13 with two 54-bit primes (closed forms of the sizes)."""
+    with open(os.path.join(GOLDEN, "paper_sizes.json")) as f:
+        g = json.load(f)
+    n, bits = g["n"], g["prime_bits"]
+    ct_bytes = 2 * n * bits / 8                 # two ring elements mod one 54-bit prime
+    key_bytes = 4 * n * (2 * bits) / 8          # 2 digits x 2 ring elements mod q (108 bits)
+    assert round(ct_bytes / 1000, 1) == g["ciphertext_kB"]
+    assert round(key_bytes / 1000, 1) == g["rotation_key_kB"]
+
+
+# --------------------------------------------------------------------------- end to end
+
+def run_pipeline(wl_name):
+    import workloads as W
+    from oracle.params import make_params as mp
+    wl = W.WORKLOADS[wl_name]
+    ring = W.RINGS[wl.ring]
+    pr = mp(ring.n, ring.p, ring.L, ring.q_bits, ring.K, ring.p_bits)
+    v, db = W.query_inputs(wl)
+    sc = C.make_schedule(pr.n, pr.p, wl.N, wl.ncol, wl.t)
+    sk, pk = bfv.keygen(pr, W.seed32("sk", 0))
+    gks = {k: bfv.galois_keygen(pr, sk, k, W.seed32("gk", k)) for k in sc.keys}
+    vm = slots.vector_to_slot_matrices(v, pr.n, sc.n_ct)
+    cts = [bfv.encrypt(pr, pk, vm[i], W.seed32("enc", i)) for i in range(sc.n_ct)]
+    out = C.compress(pr, sc, cts, db, gks)
+    return pr, sc, sk, v, db, out
+
+
+@pytest.mark.parametrize("wl_name", ["tiny-1024", "plain-4096", "multi-2048"])
+def test_compress_decrypts_to_vandermonde_and_decompresses(wl_name):
+    pr, sc, sk, v, db, out = run_pipeline(wl_name)
+    assert bfv.noise_bits(pr, sk, out) < bfv.noise_budget_bits(pr)
+    dec = bfv.decrypt(pr, sk, out)
+    exp = C.expected_bands(sc, v, db)
+    S = len(sc.streams)
+    for b in range(sc.bands):
+        assert C.band_slots(sc, dec, b) == exp[b]
+    for gi, grp in enumerate(sc.groups):
+        rows = []
+        for st in range(S):
+            rows += list(C.band_slots(sc, dec, gi * S + st))
+        idx, vals = D.decompress_group(pr.p, grp.n_rec, rows[0], rows[1:1 + sc.ncol])
+        seg = v[grp.rec_start:grp.rec_start + grp.n_rec]
+        want = [int(i) + 1 for i in np.nonzero(seg)[0]]
+        assert idx == want
+        for c in range(sc.ncol):
+            assert vals[c] == [int(db[c][grp.rec_start + i - 1]) % pr.p for i in want]
+
+
+def test_missing_key_is_reported():
+    import workloads as W
+    pr = make_params(1024, 12289, 2, 54, 1, 60)
+    sc = C.make_schedule(pr.n, pr.p, 1024, 1, 5)
+    sk, pk = bfv.keygen(pr, bytes(32))
+    gks = {k: bfv.galois_keygen(pr, sk, k, bytes(32)) for k in sc.keys[1:]}
+    ct = bfv.encrypt(pr, pk, np.zeros((2, pr.nh), dtype=np.uint64), bytes(32))
+    with pytest.raises(KeyError):
+        C.compress(pr, sc, [ct], np.zeros((1, 1024), dtype=np.uint32), gks)
