@@ -1,0 +1,206 @@
+/*
+ * hc.h -- C ABI of libhc: SIMD-aware homomorphic compression for private
+ * database queries (Cheon, Lee, Park, Yeo, arXiv 2408.17063) on one MI355X.
+ *
+ * The calls follow the paper's statement of the problem:
+ *   - HE syntax KeyGen / Enc / Dec (Sec. 2.2)          -> hc_keygen, hc_galois_keygen,
+ *                                                         hc_encrypt, hc_decrypt
+ *   - homomorphic compression Comp / Decomp (Def. 3)   -> hc_compress, hc_decompress
+ *   - PDQ Query / Answer / Recover (Def. 7, Thm. 3, Alg. 7): Query = keygen +
+ *     encrypt of the index vector, Answer = hc_compress (Mask + Comp; the
+ *     index vector v is the input, Match is not part of this library),
+ *     Recover = hc_decrypt + hc_decompress.
+ *
+ * Conventions
+ *   - Every call returns hc_status; nothing throws across the ABI.
+ *   - Ciphertexts exchanged through the ABI are arrays of uint64_t laid out
+ *     [2][L][n] (component, prime, coefficient), coefficient domain, canonical
+ *     residues 0 <= x < q_i. "device" pointers are HIP device memory owned by
+ *     the caller; "host" pointers are ordinary host memory owned by the caller.
+ *   - Keys, the encoded database and the context are opaque handles owned by
+ *     the library and resident in device memory until their *_destroy call.
+ *   - hipStream_t arguments: the call enqueues its device work on that stream
+ *     and returns without waiting, unless stated otherwise. Calls that take
+ *     host buffers for output synchronise before returning.
+ *   - One context per device; calls on one context from several threads must
+ *     be serialised by the caller (the context owns a workspace).
+ *
+ * Scheme (BFV in RNS form; the paper's BGV slot algebra carries over unchanged):
+ *   - ring R = Z[X]/(X^n + 1), n = 2^log_n; plaintext prime p = 1 mod 2n, so a
+ *     plaintext is a 2 x (n/2) matrix of slots in Z_p (Sec. 5.1);
+ *   - ciphertext primes q_1 > ... > q_L: the L largest primes below 2^q_bits
+ *     with q = 1 mod 2n; special primes p_1 > ... > p_K: the K largest below
+ *     2^p_bits with the same congruence; Delta = floor(Q / p);
+ *   - hybrid key switching with digits of alpha = K consecutive primes
+ *     (dnum = L / K digits);
+ *   - all randomness comes from SHAKE-128 streams keyed by the 32-byte seed,
+ *     so every ciphertext is a deterministic function of its inputs.
+ */
+#ifndef HC_H
+#define HC_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HC_OK = 0,
+    HC_EINVAL = -1,   /* bad parameters or shapes */
+    HC_ENOMEM = -2,   /* device or host allocation failed */
+    HC_EDEVICE = -3,  /* a HIP call failed */
+    HC_ENOKEY = -4,   /* a rotation needs a Galois key that the key set lacks */
+    HC_EDECODE = -5,  /* decompression failed: more than s matches or an inconsistent input */
+    HC_ENOISE = -6    /* decryption rounding is ambiguous (noise at the budget) */
+} hc_status;
+
+typedef struct {
+    uint32_t log_n;   /* ring degree n = 2^log_n, 10 <= log_n <= 16 */
+    uint64_t p;       /* plaintext prime, p = 1 mod 2n, p < 2^30 */
+    uint32_t L;       /* ciphertext primes */
+    uint32_t q_bits;  /* bit size bound of the ciphertext primes, <= 61 */
+    uint32_t K;       /* special primes (= primes per key-switching digit); L % K == 0 */
+    uint32_t p_bits;  /* bit size bound of the special primes, <= 61 */
+} hc_params;
+
+typedef struct hc_context hc_context;
+typedef struct hc_sk hc_sk;
+typedef struct hc_pk hc_pk;
+typedef struct hc_gk hc_gk;
+typedef struct hc_db hc_db;
+
+/* What one compression did (filled by hc_compress / hc_plan). */
+typedef struct {
+    uint32_t s;            /* sparsity bound 2^ceil(log2 t_bound) = output slots per band */
+    uint32_t groups;       /* record groups of at most p-1 records */
+    uint32_t streams;      /* vector pairs (v,d_1), (d_2,d_3), ... */
+    uint32_t bands;        /* groups * streams; band b occupies slots [b s, (b+1) s) */
+    uint32_t n_ct;         /* input ciphertexts ceil(N / n) */
+    uint32_t n_keyswitch;  /* key switches performed */
+    uint64_t n_ptct;       /* plaintext-ciphertext products performed */
+    uint64_t n_diag;       /* diagonal plaintexts encoded */
+} hc_compress_info;
+
+/* ------------------------------------------------------------------ context */
+
+/* Derive primes and tables for `params` on HIP device `device` and upload
+ * them. Errors: HC_EINVAL (n not a power of two in range, p not prime or
+ * p != 1 mod 2n, L % K != 0, not enough primes), HC_EDEVICE, HC_ENOMEM. */
+hc_status hc_context_create(const hc_params* params, int device, hc_context** out);
+void hc_context_destroy(hc_context* ctx);
+
+/* Copy the derived primes: q_1..q_L then p_1..p_K (host array of L + K). */
+hc_status hc_context_primes(const hc_context* ctx, uint64_t* primes_out);
+
+/* ------------------------------------------------------------------ keys (Sec. 2.2, KeyGen) */
+
+/* Secret key s (ternary) and public key (b, a) = ([-a s + e]_Q, a).
+ * seed: 32 host bytes. Runs on the device; synchronises before returning. */
+hc_status hc_keygen(hc_context* ctx, const uint8_t seed[32], hc_sk** sk, hc_pk** pk);
+void hc_sk_destroy(hc_sk* sk);
+void hc_pk_destroy(hc_pk* pk);
+
+/* Galois (rotation) keys for the automorphisms X -> X^k, k odd in [1, 2n),
+ * one per entry of `elements` (duplicates ignored). Digit j of the key for k:
+ *   b_j = [-a_j s + e_j + P (Q/D_j) [(Q/D_j)^-1]_{D_j} sigma_k(s)]_{PQ},
+ * a_j uniform over PQ, D_j the product of the primes of digit j.
+ * Keys live in device memory (dnum * 2 * (L+K) * n * 8 bytes each).
+ * Errors: HC_EINVAL (even or out-of-range element), HC_ENOMEM. Synchronises. */
+hc_status hc_galois_keygen(hc_context* ctx, const hc_sk* sk, const uint32_t* elements,
+                           uint32_t count, const uint8_t seed[32], hc_gk** gk);
+void hc_gk_destroy(hc_gk* gk);
+
+/* The Galois elements a compression of N records, ncol value columns and
+ * sparsity bound t_bound needs (the schedule's key set, ascending).
+ * *count is the capacity of elements_out on entry and the number written on
+ * exit. Errors: HC_EINVAL (the bands do not fit in n/2 slots, s > n/2, N = 0,
+ * capacity too small -- *count then holds the size needed). */
+hc_status hc_plan(hc_context* ctx, uint64_t N, uint32_t ncol, uint32_t t_bound,
+                  uint32_t* elements_out, uint32_t* count, hc_compress_info* info);
+
+/* ------------------------------------------------------------------ database */
+
+/* Upload ncol value columns of N records (host, column c at cols + c*N,
+ * values < p) and encode them once as plaintext multipliers (the Mask
+ * operands of Alg. 7 step 2), resident in device memory. Synchronises. */
+hc_status hc_db_upload(hc_context* ctx, const uint32_t* cols, uint32_t ncol, uint64_t N, hc_db** db);
+void hc_db_destroy(hc_db* db);
+
+/* ------------------------------------------------------------------ encryption (Sec. 2.2, Enc) */
+
+/* Enc_pk of a slot matrix (host, 2 x n/2 row-major, values < p):
+ * ([b u + e0 + Delta m]_Q, [a u + e1]_Q), u ternary, e0, e1 Gaussian (sigma 3.2).
+ * ct_out: device [2][L][n]. Synchronises before returning. */
+hc_status hc_encrypt(hc_context* ctx, const hc_pk* pk, const uint32_t* slots,
+                     const uint8_t seed[32], uint64_t* ct_out, hipStream_t stream);
+
+/* ------------------------------------------------------------------ compression (Alg. 7 steps 2-3; Sec. 5.2) */
+
+/* Answer of a PDQ query: Mask every value column with the index vector and
+ * compress [v, d_1, .., d_ncol] with the Vandermonde matrix C[j,i] = i^j mod p
+ * (Eq. (1)) into one ciphertext.
+ *   ct_v: device, n_ct = ceil(N/n) ciphertexts [n_ct][2][L][n] of the index
+ *         vector; record r sits in ciphertext r / n, row (r % n) / (n/2),
+ *         column r % (n/2).
+ *   N, t_bound: records and an upper bound on the matches; s = 2^ceil(log2 t_bound).
+ *   db: columns uploaded with hc_db_upload for the same N (ncol may be 0).
+ *   ct_out: device [2][L][n]. Band g*streams + sigma, slots [b s, b s + s) of
+ *         row 0 / row 1, decrypts to (C a)_j / (C b)_j for group g and stream
+ *         sigma = (a, b). With a single band the slots beyond s are not masked.
+ *   info: optional, filled on success.
+ * The work is enqueued on `stream`; the call returns without waiting.
+ * Errors: HC_EINVAL (shapes, bands do not fit), HC_ENOKEY (gk lacks a needed
+ * element), HC_ENOMEM (workspace), HC_EDEVICE. */
+hc_status hc_compress(hc_context* ctx, const hc_gk* gk, const hc_db* db, const uint64_t* ct_v,
+                      uint64_t N, uint32_t t_bound, uint64_t* ct_out, hc_compress_info* info,
+                      hipStream_t stream);
+
+/* One entry of a batch for hc_compress_batch. */
+typedef struct {
+    const uint64_t* ct_v;   /* device, ceil(N/n) ciphertexts */
+    uint64_t N;
+    uint32_t t_bound;
+    uint64_t* ct_out;       /* device [2][L][n] */
+    hc_compress_info* info; /* optional */
+    hc_status status;       /* per-query result */
+} hc_query;
+
+/* Many independent compressions in one call. Each result is bit-identical
+ * to hc_compress of the same query; all queries share db and gk. Rotations
+ * by the same Galois element across queries are key-switched in one pass so
+ * each key byte read from device memory serves every query in the pass.
+ * Returns HC_OK if every query succeeded, else the first failing status (and
+ * each query's own status in q[i].status). */
+hc_status hc_compress_batch(hc_context* ctx, const hc_gk* gk, const hc_db* db,
+                            hc_query* q, uint32_t nq, hipStream_t stream);
+
+/* ------------------------------------------------------------------ client side (host CPU) */
+
+/* Dec: slots of round(p [c0 + c1 s]_Q / Q) mod p. ct: host [2][L][n],
+ * coefficient domain. slots_out: host 2 x n/2. Runs on the host.
+ * Errors: HC_EINVAL (non-canonical residue), HC_ENOISE (rounding within
+ * 2^-50 of a tie: the noise has reached the budget). */
+hc_status hc_decrypt(hc_context* ctx, const hc_sk* sk, const uint64_t* ct, uint32_t* slots_out);
+
+/* Decomp for one group (Alg. 6 with Alg. 1 and Alg. 4): from w = C v
+ * (s values) and e_c = C d_c (ncols x s values, host) recover the matched
+ * indices (1-based within the group, ascending) and their values.
+ * idx_out: capacity s; val_out: capacity ncols * s, column c at val_out + c*s.
+ * Roots are found by Cantor-Zassenhaus. Runs on the host.
+ * Errors: HC_EINVAL (p not prime, N_group >= p, s > p-1), HC_EDECODE (root
+ * count differs from the degree, a root outside [1, N_group], or the
+ * equations beyond the first `count` are violated). */
+hc_status hc_decompress(uint64_t p, uint64_t N_group, uint32_t s, uint32_t ncols,
+                        const uint32_t* w, const uint32_t* e, uint64_t* idx_out,
+                        uint32_t* val_out, uint32_t* count_out);
+
+/* Text of a status code (static string). */
+const char* hc_status_str(hc_status st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HC_H */

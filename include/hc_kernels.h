@@ -1,0 +1,91 @@
+/*
+ * hc_kernels.h -- C ABI of libhc's ring-level operations.
+ *
+ * These are the building blocks hc_compress is made of, exposed one by one
+ * so that each can be checked against a reference at full size: the
+ * negacyclic NTT per prime, the Galois automorphisms behind the paper's
+ * rotations Rot_row / Rot_col (Sec. 5.1), hybrid key switching (basis
+ * conversion up and down), the plaintext-ciphertext product (the boxtimes of
+ * Sec. 2.2 / Alg. 7 step 2) and the seeded samplers. Conventions as in hc.h:
+ * device pointers are caller-owned HIP memory, arrays are uint64_t with
+ * canonical residues, work is enqueued on `stream`.
+ *
+ * "Prime index" i refers to the basis q_1..q_L, p_1..p_K in that order
+ * (0-based; 0..L-1 are the ciphertext primes, L..L+K-1 the special primes).
+ */
+#ifndef HC_KERNELS_H
+#define HC_KERNELS_H
+
+#include "hc.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* In-place negacyclic NTT of `count` polynomials, each `nlimbs` consecutive
+ * rows of n residues for prime indices limb_first..limb_first+nlimbs-1.
+ * Forward: coefficients -> evaluations, entry i = a(psi^(2 brv(i) + 1)) with
+ * brv the log_n-bit reversal and psi the library's primitive 2n-th root mod
+ * the prime; inverse: the exact inverse. Output canonical.
+ * Errors: HC_EINVAL (limb range outside L+K). */
+hc_status hc_ntt(hc_context* ctx, uint64_t* data, uint32_t count, uint32_t limb_first,
+                 uint32_t nlimbs, int inverse, hipStream_t stream);
+
+/* Rotation of one ciphertext by sigma_k with key switching (Sec. 5.1: k = 3^r
+ * mod 2n moves both slot rows left by r, k = 2n-1 swaps the rows).
+ * Non-hoisted: (sigma_k(c0), sigma_k(c1)), ModUp of each digit of sigma_k(c1),
+ * inner product with the key over PQ, ModDown, added to sigma_k(c0).
+ * ct_in / ct_out: device [2][L][n], coefficient domain (may not alias).
+ * Errors: HC_ENOKEY. */
+hc_status hc_rotate(hc_context* ctx, const hc_gk* gk, uint32_t element, const uint64_t* ct_in,
+                    uint64_t* ct_out, hipStream_t stream);
+
+/* Hoisted rotations of one ciphertext by `count` elements: one ModUp of c1,
+ * then per element sigma_k applied to the raised digits, inner product and
+ * ModDown. cts_out: device [count][2][L][n]. Decrypts like hc_rotate but
+ * differs in bits (sigma and the basis conversion commute only modulo D_j). */
+hc_status hc_rotate_hoisted(hc_context* ctx, const hc_gk* gk, const uint32_t* elements,
+                            uint32_t count, const uint64_t* ct_in, uint64_t* cts_out,
+                            hipStream_t stream);
+
+/* ct boxtimes plaintext: both components multiplied by the centred lift
+ * (coefficients in (-p/2, p/2]) of the encoding of `slots` (host 2 x n/2).
+ * ct_in / ct_out device [2][L][n] coefficient domain (may alias). */
+hc_status hc_mul_plain(hc_context* ctx, const uint64_t* ct_in, const uint32_t* slots,
+                       uint64_t* ct_out, hipStream_t stream);
+
+/* Fast basis conversion of digit j of x (device [L][n], coefficient domain)
+ * to every prime of PQ: out (device [L+K][n]) holds x on the digit's primes
+ * and sum_{i in I_j} [x_i (D_j/q_i)^-1]_{q_i} (D_j/q_i) mod r elsewhere. */
+hc_status hc_modup(hc_context* ctx, const uint64_t* x, uint32_t digit, uint64_t* out,
+                   hipStream_t stream);
+
+/* ModDown: out_i = (T_i - Conv_{P->Q}([T]_P)_i) P^-1 mod q_i for T device
+ * [L+K][n] (coefficient domain); out device [L][n]. */
+hc_status hc_moddown(hc_context* ctx, const uint64_t* T, uint64_t* out, hipStream_t stream);
+
+/* Seeded samplers over SHAKE-128 stream(seed, tag, obj, limb, block):
+ * kind 0: uniform residues mod prime `limb` (16 bytes per coefficient);
+ * kind 1: ternary, kind 2: Gaussian sigma = 3.2 (limb ignored, stream limb
+ * field 2^64-1), written as int64_t values. out: device, n entries. tag: up to
+ * 8 ASCII characters (zero padded). */
+hc_status hc_sample(hc_context* ctx, int kind, const uint8_t seed[32], const char* tag,
+                    uint64_t obj, uint32_t limb, uint64_t* out, hipStream_t stream);
+
+/* Encoding of one compression diagonal, as a centred-lift polynomial reduced
+ * mod each ciphertext prime (device [L][n], coefficient domain): slot m of
+ * either row holds (beta n/2 + ((m + b) mod n/2) + 1)^(((m - gi B) mod s) + 1) mod p. */
+hc_status hc_encode_diagonal(hc_context* ctx, uint32_t s, uint32_t B, uint32_t beta, uint32_t gi,
+                             uint32_t b, uint64_t* out, hipStream_t stream);
+
+/* Export key material to host memory, coefficient domain, canonical:
+ * sk: n int64 coefficients in {-1,0,1}; pk: [2][L][n] (b then a);
+ * gk: the key for `element`, [dnum][2][L+K][n] (b_j then a_j). Synchronise. */
+hc_status hc_export_sk(hc_context* ctx, const hc_sk* sk, int64_t* out);
+hc_status hc_export_pk(hc_context* ctx, const hc_pk* pk, uint64_t* out);
+hc_status hc_export_gk(hc_context* ctx, const hc_gk* gk, uint32_t element, uint64_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HC_KERNELS_H */

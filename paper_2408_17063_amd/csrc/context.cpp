@@ -1,0 +1,383 @@
+// Context creation: parameter derivation and the constant tables every kernel uses.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "hc_internal.h"
+
+namespace hc {
+
+hc_status upload_keccak_constants(const uint64_t rc[24], const uint32_t rho[25], const uint32_t cdt[20]);
+
+hc_status fail_hip(hipError_t e, const char* what, const char* file, int line) {
+    fprintf(stderr, "libhc: %s failed at %s:%d: %s\n", what, file, line, hipGetErrorString(e));
+    return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? HC_ENOMEM : HC_EDEVICE;
+}
+
+hc_status Arena::reserve(size_t bytes) {
+    if (bytes <= cap) { used = 0; return HC_OK; }
+    release();
+    hipError_t e = hipMalloc((void**)&base, bytes);
+    if (e != hipSuccess) {
+        base = nullptr;
+        cap = 0;
+        return HC_ENOMEM;
+    }
+    cap = bytes;
+    used = 0;
+    return HC_OK;
+}
+
+void Arena::release() {
+    if (base) (void)hipFree(base);
+    base = nullptr;
+    cap = 0;
+    used = 0;
+}
+
+// ------------------------------------------------------------------ number theory (host)
+
+static bool is_prime_u64(uint64_t x) {
+    static const uint64_t bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+    if (x < 2) return false;
+    for (uint64_t b : bases) {
+        if (x % b == 0) return x == b;
+    }
+    uint64_t d = x - 1;
+    int r = 0;
+    while ((d & 1) == 0) { d >>= 1; r++; }
+    for (uint64_t a : bases) {
+        uint64_t y = h_powmod(a, d, x);
+        if (y == 1 || y == x - 1) continue;
+        bool comp = true;
+        for (int i = 1; i < r; i++) {
+            y = h_mulmod(y, y, x);
+            if (y == x - 1) { comp = false; break; }
+        }
+        if (comp) return false;
+    }
+    return true;
+}
+
+static bool ntt_primes(int bits, int count, uint64_t two_n, const std::vector<uint64_t>& skip,
+                       std::vector<uint64_t>& out) {
+    uint64_t top = (bits >= 64) ? ~0ull : ((1ull << bits) - 1);
+    uint64_t x = top / two_n * two_n + 1;
+    if (x > top) x -= two_n;
+    while ((int)out.size() < count) {
+        if (x <= two_n) return false;
+        if (std::find(skip.begin(), skip.end(), x) == skip.end() && is_prime_u64(x)) out.push_back(x);
+        x -= two_n;
+    }
+    return true;
+}
+
+static uint32_t brv(uint32_t i, int bits) {
+    uint32_t r = 0;
+    for (int k = 0; k < bits; k++) { r = (r << 1) | (i & 1); i >>= 1; }
+    return r;
+}
+
+// a primitive 2n-th root of unity mod q: g^((q-1)/2n) for the least g whose power has order 2n
+static uint64_t root_2n(uint64_t q, uint64_t n) {
+    for (uint64_t g = 2;; g++) {
+        uint64_t x = h_powmod(g, (q - 1) / (2 * n), q);
+        if (h_powmod(x, n, q) == q - 1) return x;
+    }
+}
+
+// Keccak-f[1600] constants from their FIPS 202 definitions.
+static void keccak_constants(uint64_t rc[24], uint32_t rho[25]) {
+    // rc(t): LFSR x^8 + x^6 + x^5 + x^4 + 1 (FIPS 202 Alg. 5)
+    auto rcbit = [](int t) -> int {
+        if (t % 255 == 0) return 1;
+        uint32_t R = 1;  // R[0] = 1, bits 0..7
+        for (int i = 1; i <= t % 255; i++) {
+            R <<= 1;     // R = 0 || R
+            uint32_t r8 = (R >> 8) & 1;
+            R ^= r8 << 0;
+            R ^= r8 << 4;
+            R ^= r8 << 5;
+            R ^= r8 << 6;
+            R &= 0xff;
+        }
+        return R & 1;
+    };
+    for (int ir = 0; ir < 24; ir++) {
+        uint64_t c = 0;
+        for (int j = 0; j <= 6; j++)
+            if (rcbit(j + 7 * ir)) c |= 1ull << ((1 << j) - 1);
+        rc[ir] = c;
+    }
+    // rho offsets: walk (x, y) <- (y, 2x + 3y) from (1, 0)
+    for (int i = 0; i < 25; i++) rho[i] = 0;
+    int x = 1, y = 0;
+    for (int t = 0; t < 24; t++) {
+        rho[x + 5 * y] = (uint32_t)(((t + 1) * (t + 2) / 2) % 64);
+        int nx = y, ny = (2 * x + 3 * y) % 5;
+        x = nx;
+        y = ny;
+    }
+}
+
+// CDF of |X| for P(X = x) ~ exp(-x^2 / (2 sigma^2)) on -19..19, scaled to 2^32.
+static void gaussian_cdt(double sigma, uint32_t T[20]) {
+    double rho[20], total;
+    for (int x = 0; x < 20; x++) rho[x] = exp(-(double)(x * x) / (2.0 * sigma * sigma));
+    total = rho[0];
+    for (int x = 1; x < 20; x++) total += 2 * rho[x];
+    double acc = 0;
+    for (int k = 0; k < 20; k++) {
+        acc += (k == 0) ? rho[0] : 2 * rho[k];
+        double v = floor(acc / total * 4294967296.0 + 0.5);
+        T[k] = (k == 19 || v >= 4294967295.0) ? 0xffffffffu : (uint32_t)v;
+    }
+}
+
+template <typename T>
+static hc_status upload(Ctx& c, T** dst, const std::vector<T>& src) {
+    HC_CHECK(hipMalloc((void**)dst, sizeof(T) * std::max<size_t>(src.size(), 1)));
+    c.owned.push_back(*dst);
+    if (!src.empty()) HC_CHECK(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
+    return HC_OK;
+}
+
+hc_status encode_plain(Ctx& c, uint64_t* out, const uint32_t* host_slots, int count, bool mont,
+                       hipStream_t st);
+
+}  // namespace hc
+
+using namespace hc;
+
+extern "C" hc_status hc_context_create(const hc_params* prm, int device, hc_context** out) {
+    if (!prm || !out) return HC_EINVAL;
+    *out = nullptr;
+    if (prm->log_n < 10 || prm->log_n > 16) return HC_EINVAL;
+    if (prm->K < 1 || prm->K > 4 || prm->L < 1 || prm->L % prm->K) return HC_EINVAL;
+    if (prm->q_bits < 30 || prm->q_bits > 61 || prm->p_bits < 30 || prm->p_bits > 61) return HC_EINVAL;
+    const uint64_t n = 1ull << prm->log_n;
+    if (prm->p >= (1ull << 26) || (prm->p - 1) % (2 * n) != 0 || !is_prime_u64(prm->p)) return HC_EINVAL;
+    if (prm->L + prm->K > 64) return HC_EINVAL;
+
+    int ndev = 0;
+    HC_CHECK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return HC_EINVAL;
+    HC_CHECK(hipSetDevice(device));
+
+    Ctx* cp = new Ctx();
+    Ctx& c = *cp;
+    c.device = device;
+    c.logn = prm->log_n;
+    c.n = (int)n;
+    c.nh = c.n / 2;
+    c.L = prm->L;
+    c.K = prm->K;
+    c.alpha = prm->K;
+    c.dnum = prm->L / prm->K;
+    c.nq = c.L + c.K;
+    c.p = prm->p;
+
+    std::vector<uint64_t> qs, sps;
+    if (!ntt_primes(prm->q_bits, c.L, 2 * n, {}, qs) || !ntt_primes(prm->p_bits, c.K, 2 * n, qs, sps)) {
+        delete cp;
+        return HC_EINVAL;
+    }
+    c.primes = qs;
+    c.primes.insert(c.primes.end(), sps.begin(), sps.end());
+    const int nq = c.nq, L = c.L, K = c.K, logn = c.logn;
+
+    // ---- NTT tables for every prime
+    c.h_tw.assign((size_t)nq * 4 * n, 0);
+    std::vector<uint64_t> ninv(2 * nq), qinv(nq), r2(nq);
+    for (int i = 0; i < nq; i++) {
+        uint64_t q = c.primes[i];
+        uint64_t psi = root_2n(q, n), psii = h_invmod(psi, q);
+        uint64_t* t = c.h_tw.data() + (size_t)i * 4 * n;
+        std::vector<uint64_t> pw(n), pwi(n);
+        pw[0] = pwi[0] = 1;
+        for (uint32_t k = 1; k < n; k++) {
+            pw[k] = h_mulmod(pw[k - 1], psi, q);
+            pwi[k] = h_mulmod(pwi[k - 1], psii, q);
+        }
+        for (uint32_t k = 0; k < n; k++) {
+            uint32_t e = brv(k, logn);
+            t[k] = pw[e];
+            t[n + k] = h_shoup_const(t[k], q);
+            t[2 * n + k] = pwi[e];
+            t[3 * n + k] = h_shoup_const(t[2 * n + k], q);
+        }
+        ninv[2 * i] = h_invmod(n % q, q);
+        ninv[2 * i + 1] = h_shoup_const(ninv[2 * i], q);
+        qinv[i] = h_mont_qinv(q);
+        r2[i] = h_mulmod(h_to_mont(1, q), h_to_mont(1, q), q);  // 2^128 mod q
+    }
+    c.h_qinv = qinv;
+    c.h_r2 = r2;
+
+    // ---- slot transform mod p: zeta = least x >= 2 with x^n = -1
+    uint32_t p = (uint32_t)c.p;
+    uint32_t zeta = 2;
+    while (h_powmod(zeta, n, p) != p - 1) zeta++;
+    c.zeta = zeta;
+    c.h_twp.assign((size_t)4 * n, 0);
+    uint32_t zinv = (uint32_t)h_invmod(zeta, p);
+    std::vector<uint32_t> zp(n), zpi(n);
+    zp[0] = zpi[0] = 1;
+    for (uint32_t k = 1; k < n; k++) {
+        zp[k] = (uint32_t)((uint64_t)zp[k - 1] * zeta % p);
+        zpi[k] = (uint32_t)((uint64_t)zpi[k - 1] * zinv % p);
+    }
+    for (uint32_t k = 0; k < n; k++) {
+        uint32_t e = brv(k, logn);
+        uint32_t w = zp[e], wi = zpi[e];
+        c.h_twp[k] = w;
+        c.h_twp[n + k] = (uint32_t)(((uint64_t)w << 32) / p);
+        c.h_twp[2 * n + k] = wi;
+        c.h_twp[3 * n + k] = (uint32_t)(((uint64_t)wi << 32) / p);
+    }
+    uint32_t ninvp = (uint32_t)h_invmod(n % p, p);
+    std::vector<uint32_t> ninvp_v = {ninvp, (uint32_t)(((uint64_t)ninvp << 32) / p)};
+    // slot (r, c) <-> evaluation at zeta^e, e = (-1)^r 3^c mod 2n; forward NTT entry i
+    // holds the evaluation at zeta^(2 brv(i) + 1)
+    c.h_slotpos.assign(n, 0);
+    std::vector<uint32_t> posslot(n);
+    uint64_t e = 1;
+    for (int col = 0; col < c.nh; col++) {
+        uint64_t e0 = e, e1 = (2 * n - e) % (2 * n);
+        c.h_slotpos[col] = brv((uint32_t)((e0 - 1) / 2), logn);
+        c.h_slotpos[c.nh + col] = brv((uint32_t)((e1 - 1) / 2), logn);
+        e = e * 3 % (2 * n);
+    }
+    for (uint32_t i = 0; i < n; i++) posslot[c.h_slotpos[i]] = i;
+
+    // ---- basis conversion constants
+    const int alpha = c.alpha, dnum = c.dnum;
+    std::vector<uint64_t> modup_inv((size_t)dnum * alpha * 2), modup_c((size_t)dnum * alpha * nq);
+    for (int j = 0; j < dnum; j++) {
+        for (int a = 0; a < alpha; a++) {
+            int i = j * alpha + a;
+            uint64_t qi = c.primes[i];
+            // (D_j / q_i) mod q_i and mod every r
+            uint64_t hat_qi = 1;
+            for (int a2 = 0; a2 < alpha; a2++)
+                if (a2 != a) hat_qi = h_mulmod(hat_qi, c.primes[j * alpha + a2] % qi, qi);
+            uint64_t iv = h_invmod(hat_qi, qi);
+            modup_inv[((size_t)j * alpha + a) * 2] = iv;
+            modup_inv[((size_t)j * alpha + a) * 2 + 1] = h_shoup_const(iv, qi);
+            for (int r = 0; r < nq; r++) {
+                uint64_t m = c.primes[r], h = 1;
+                for (int a2 = 0; a2 < alpha; a2++)
+                    if (a2 != a) h = h_mulmod(h, c.primes[j * alpha + a2] % m, m);
+                modup_c[((size_t)j * alpha + a) * nq + r] = h_to_mont(h, m);
+            }
+        }
+    }
+    std::vector<uint64_t> moddown_inv((size_t)K * 2), moddown_c((size_t)K * L), pinv((size_t)L * 2),
+        pmodq(L), delta((size_t)L * 2);
+    for (int k = 0; k < K; k++) {
+        uint64_t pk = c.primes[L + k];
+        uint64_t h = 1;
+        for (int k2 = 0; k2 < K; k2++)
+            if (k2 != k) h = h_mulmod(h, c.primes[L + k2] % pk, pk);
+        moddown_inv[2 * k] = h_invmod(h, pk);
+        moddown_inv[2 * k + 1] = h_shoup_const(moddown_inv[2 * k], pk);
+        for (int i = 0; i < L; i++) {
+            uint64_t qi = c.primes[i], hq = 1;
+            for (int k2 = 0; k2 < K; k2++)
+                if (k2 != k) hq = h_mulmod(hq, c.primes[L + k2] % qi, qi);
+            moddown_c[(size_t)k * L + i] = h_to_mont(hq, qi);
+        }
+    }
+    uint64_t Qmodp = 1;
+    for (int i = 0; i < L; i++) Qmodp = h_mulmod(Qmodp, c.primes[i] % c.p, c.p);
+    for (int i = 0; i < L; i++) {
+        uint64_t qi = c.primes[i], P = 1;
+        for (int k = 0; k < K; k++) P = h_mulmod(P, c.primes[L + k] % qi, qi);
+        pmodq[i] = P;
+        pinv[2 * i] = h_invmod(P, qi);
+        pinv[2 * i + 1] = h_shoup_const(pinv[2 * i], qi);
+        // Delta = (Q - (Q mod p)) / p, and Q = 0 mod q_i
+        uint64_t d = h_mulmod((qi - Qmodp % qi) % qi, h_invmod(c.p % qi, qi), qi);
+        delta[2 * i] = d;
+        delta[2 * i + 1] = h_shoup_const(d, qi);
+    }
+
+    // ---- samplers
+    uint64_t rc[24];
+    uint32_t rho[25];
+    keccak_constants(rc, rho);
+    c.h_cdt.assign(20, 0);
+    gaussian_cdt(3.2, c.h_cdt.data());
+
+    hc_status st = HC_OK;
+#define UP(dst, src) if ((st = upload(c, &dst, src)) != HC_OK) { hc_context_destroy(cp); return st; }
+    UP(c.d_mods, c.primes);
+    UP(c.d_qinv, qinv);
+    UP(c.d_r2, r2);
+    UP(c.d_tw, c.h_tw);
+    UP(c.d_ninv, ninv);
+    UP(c.d_modp, std::vector<uint32_t>{p});
+    UP(c.d_twp, c.h_twp);
+    UP(c.d_ninvp, ninvp_v);
+    UP(c.d_slotpos, c.h_slotpos);
+    UP(c.d_posslot, posslot);
+    UP(c.d_modup_inv, modup_inv);
+    UP(c.d_modup_c, modup_c);
+    UP(c.d_moddown_inv, moddown_inv);
+    UP(c.d_moddown_c, moddown_c);
+    UP(c.d_pinv, pinv);
+    UP(c.d_pmodq, pmodq);
+    UP(c.d_delta, delta);
+#undef UP
+    if ((st = upload_keccak_constants(rc, rho, c.h_cdt.data())) != HC_OK) { hc_context_destroy(cp); return st; }
+
+    // ---- row masks [1;0] and [0;1] as plaintext multipliers
+    std::vector<uint32_t> rows((size_t)2 * n, 0);
+    for (int col = 0; col < c.nh; col++) { rows[col] = 1; rows[(size_t)n + c.nh + col] = 1; }
+    for (int r = 0; r < 2; r++) {
+        if (hipMalloc((void**)&c.d_rowmask[r], sizeof(uint64_t) * (size_t)L * n) != hipSuccess) {
+            hc_context_destroy(cp);
+            return HC_ENOMEM;
+        }
+        c.owned.push_back(c.d_rowmask[r]);
+    }
+    if ((st = encode_plain(c, c.d_rowmask[0], rows.data(), 1, true, 0)) != HC_OK ||
+        (st = encode_plain(c, c.d_rowmask[1], rows.data() + n, 1, true, 0)) != HC_OK) {
+        hc_context_destroy(cp);
+        return st;
+    }
+    if (hipDeviceSynchronize() != hipSuccess) { hc_context_destroy(cp); return HC_EDEVICE; }
+    *out = cp;
+    return HC_OK;
+}
+
+extern "C" void hc_context_destroy(hc_context* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (void* p : c->owned) (void)hipFree(p);
+    for (auto& kv : c->prefix_masks) (void)hipFree(kv.second);
+    c->ws.release();
+    delete c;
+}
+
+extern "C" hc_status hc_context_primes(const hc_context* c, uint64_t* out) {
+    if (!c || !out) return HC_EINVAL;
+    for (size_t i = 0; i < c->primes.size(); i++) out[i] = c->primes[i];
+    return HC_OK;
+}
+
+extern "C" const char* hc_status_str(hc_status s) {
+    switch (s) {
+        case HC_OK: return "ok";
+        case HC_EINVAL: return "invalid argument";
+        case HC_ENOMEM: return "out of memory";
+        case HC_EDEVICE: return "device error";
+        case HC_ENOKEY: return "missing Galois key";
+        case HC_EDECODE: return "decoding failed";
+        case HC_ENOISE: return "noise at the decryption budget";
+    }
+    return "unknown status";
+}

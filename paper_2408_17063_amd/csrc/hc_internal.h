@@ -1,0 +1,179 @@
+// Internal declarations of libhc: the context, key and database objects and
+// the device launchers the host orchestration calls.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/hc.h"
+#include "../../include/hc_kernels.h"
+#include "modarith.h"
+
+#define HC_CHECK(x)                                            \
+    do {                                                       \
+        hipError_t e_ = (x);                                   \
+        if (e_ != hipSuccess) return hc::fail_hip(e_, #x, __FILE__, __LINE__); \
+    } while (0)
+
+namespace hc {
+
+hc_status fail_hip(hipError_t e, const char* what, const char* file, int line);
+
+// A grow-only device arena for per-call temporaries.
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+    hc_status reserve(size_t bytes);   // (re)allocates; invalidates earlier pointers
+    void reset() { used = 0; }
+    template <typename T> T* take(size_t count) {
+        size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
+        if (used + bytes > cap) return nullptr;
+        T* p = reinterpret_cast<T*>(base + used);
+        used += bytes;
+        return p;
+    }
+    void release();
+};
+
+}  // namespace hc
+
+struct hc_context {
+    int device = 0;
+    int logn = 0, n = 0, nh = 0;
+    int L = 0, K = 0, dnum = 0, alpha = 0, nq = 0;
+    uint64_t p = 0;
+    uint32_t zeta = 0;
+    std::vector<uint64_t> primes;          // q_1..q_L, p_1..p_K
+    std::vector<uint64_t> h_qinv, h_r2;    // Montgomery constants per prime
+    std::vector<uint64_t> h_tw;            // host copy of the NTT tables [nq][4][n]
+    std::vector<uint32_t> h_twp;           // mod-p tables [4][n]
+    std::vector<uint32_t> h_slotpos;       // NTT-mod-p position of slot r*nh + c
+    std::vector<uint32_t> h_cdt;           // Gaussian CDT (20 entries)
+
+    // device tables
+    uint64_t* d_mods = nullptr;     // [nq]
+    uint64_t* d_qinv = nullptr;     // [nq] -q^-1 mod 2^64
+    uint64_t* d_r2 = nullptr;       // [nq] 2^128 mod q
+    uint64_t* d_tw = nullptr;       // [nq][4][n] fwd W, W', inv W, W'
+    uint64_t* d_ninv = nullptr;     // [nq][2]
+    uint32_t* d_modp = nullptr;     // [1] p
+    uint32_t* d_twp = nullptr;      // [4][n] mod p
+    uint32_t* d_ninvp = nullptr;    // [2]
+    uint32_t* d_slotpos = nullptr;  // [n]
+    uint32_t* d_posslot = nullptr;  // [n] inverse of slotpos
+    uint64_t* d_modup_inv = nullptr;  // [dnum][alpha][2]  (D_j/q_i)^-1 mod q_i and Shoup
+    uint64_t* d_modup_c = nullptr;    // [dnum][alpha][nq] (D_j/q_i) mod r, Montgomery form mod r
+    uint64_t* d_moddown_inv = nullptr;  // [K][2] (P/p_k)^-1 mod p_k and Shoup
+    uint64_t* d_moddown_c = nullptr;    // [K][L] (P/p_k) mod q_i, Montgomery form
+    uint64_t* d_pinv = nullptr;         // [L][2] P^-1 mod q_i and Shoup
+    uint64_t* d_pmodq = nullptr;        // [L] P mod q_i
+    uint64_t* d_delta = nullptr;        // [L][2] Delta mod q_i and Shoup
+    uint32_t* d_cdt = nullptr;          // [20]
+    uint64_t* d_keccak_rc = nullptr;    // [24]
+
+    // plaintext multipliers owned by the context (NTT domain, Montgomery form, [L][n])
+    uint64_t* d_rowmask[2] = {nullptr, nullptr};
+    std::map<uint32_t, uint64_t*> prefix_masks;  // keyed by s
+
+    hc::Arena ws;      // per-call workspace
+    std::vector<void*> owned;  // device allocations freed at destroy
+};
+
+struct hc_sk {
+    std::vector<int8_t> s;        // host copy of the ternary secret
+    uint64_t* d_s_mont = nullptr; // NTT domain over PQ, Montgomery form [nq][n]
+};
+
+struct hc_pk {
+    uint64_t* d_b = nullptr;  // NTT domain, normal form, [L][n]
+    uint64_t* d_a = nullptr;
+};
+
+struct hc_gk {
+    int dnum = 0, nq = 0, n = 0;
+    std::map<uint32_t, uint64_t*> keys;  // element -> [dnum][2][nq][n], NTT domain, Montgomery form
+};
+
+struct hc_db {
+    uint32_t ncol = 0;
+    uint64_t N = 0;
+    uint32_t n_ct = 0;
+    uint64_t* d_pt = nullptr;  // [ncol][n_ct][L][n] NTT domain, Montgomery form
+};
+
+namespace hc {
+
+using Ctx = hc_context;
+
+// ------------------------------------------------------------------ NTT (ntt.hip)
+// data: `count` polynomials spaced poly_stride elements apart; data points at
+// the first transformed row, whose prime index is limb_first.
+void ntt64(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb_first, int nlimbs,
+           bool inverse, hipStream_t stream);
+// mod-p transforms of `count` contiguous length-n rows.
+void ntt32(const Ctx& c, uint32_t* data, int count, bool inverse, hipStream_t stream);
+
+// ------------------------------------------------------------------ kernels (ops.hip)
+// All arrays are [rows][n] per polynomial; "nl" rows starting at prime index lf.
+
+// out = in permuted by sigma_k in the NTT domain (k = 1: copy), for nl rows.
+void k_permute(const Ctx& c, uint64_t* out, const uint64_t* in, int nl, uint32_t k, int count,
+               size_t stride, hipStream_t st);
+// out = a + b (mod), nl rows starting at prime lf, `count` polynomials of stride.
+void k_add(const Ctx& c, uint64_t* out, const uint64_t* a, const uint64_t* b, int lf, int nl,
+           int count, size_t stride, hipStream_t st);
+// out[c] = ct[c] * pt (Montgomery pt) for c = 0, 1 over the L ciphertext primes.
+void k_mul_plain(const Ctx& c, uint64_t* out, const uint64_t* ct, const uint64_t* pt_mont,
+                 hipStream_t st);
+// ModUp of all digits: X [dnum][nq][n] (coefficient domain) from x [L][n] (coefficient domain).
+void k_modup(const Ctx& c, uint64_t* X, const uint64_t* x, int digit_first, int ndigits,
+             hipStream_t st);
+// inner product: T [2][nq][n] = sum_j sigma_k(X_j) * key_j ; k = 1: no permutation.
+void k_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const uint64_t* key, uint32_t k,
+             hipStream_t st);
+// Conv_{P->Q}: conv [2][L][n] (coefficient) from T [2][nq][n] (special rows coefficient domain).
+void k_moddown_conv(const Ctx& c, uint64_t* conv, const uint64_t* T, hipStream_t st);
+// out0 = sigma_k(c0) + (T0 - conv0) P^-1 ; out1 = (T1 - conv1) P^-1  (NTT domain)
+void k_moddown_final(const Ctx& c, uint64_t* out, const uint64_t* T, const uint64_t* conv,
+                     const uint64_t* c0, uint32_t k, hipStream_t st);
+// slots (device u32 [count][2][nh]) -> NTT-mod-p positions [count][n]
+void k_slots_to_eval(const Ctx& c, uint32_t* out, const uint32_t* slots, int count, hipStream_t st);
+// centred lift of mod-p coefficients [count][n] into [count][L][n]; Montgomery form if mont
+void k_lift(const Ctx& c, uint64_t* out, const uint32_t* in, int count, bool mont, hipStream_t st);
+// compression diagonals in NTT-mod-p positions: out [count][n], params [count][3] (beta, gi, b)
+void k_diag_gen(const Ctx& c, uint32_t* out, const uint32_t* params, int count, uint32_t s,
+                uint32_t B, hipStream_t st);
+// samplers: uniform residues for rows lf..lf+nl-1 (stream limb index = row prime index)
+void k_sample_uniform(const Ctx& c, uint64_t* out, const uint8_t* seed_dev, uint64_t tag,
+                      uint64_t obj, int lf, int nl, hipStream_t st);
+// small samplers (kind 1 ternary, 2 Gaussian): residues over rows lf..lf+nl-1 and,
+// if raw != nullptr, the signed values.
+void k_sample_small(const Ctx& c, uint64_t* out, int64_t* raw, const uint8_t* seed_dev,
+                    uint64_t tag, uint64_t obj, int kind, int lf, int nl, hipStream_t st);
+// pointwise multiply-add helpers for key generation (NTT domain):
+// out = e - a * s_mont + g * rot_s_mont (g per row, may be null), rows lf..lf+nl-1
+void k_keyrow(const Ctx& c, uint64_t* out, const uint64_t* e, const uint64_t* a,
+              const uint64_t* s_mont, const uint64_t* rot_s_mont, const uint64_t* grow, int lf,
+              int nl, hipStream_t st);
+// x -> x * 2^64 mod q (to Montgomery form), rows lf..lf+nl-1, count polys of stride
+void k_to_mont(const Ctx& c, uint64_t* x, int lf, int nl, int count, size_t stride, hipStream_t st);
+// x -> x * 2^-64 mod q (from Montgomery form)
+void k_from_mont(const Ctx& c, uint64_t* x, int lf, int nl, int count, size_t stride, hipStream_t st);
+// out = a * bm (Montgomery bm), rows lf..lf+nl-1
+void k_mul_mont(const Ctx& c, uint64_t* out, const uint64_t* a, const uint64_t* bm, int lf, int nl,
+                hipStream_t st);
+// encryption finish (coefficient domain): c0 += e0 + Delta m ; c1 += e1
+void k_enc_finish(const Ctx& c, uint64_t* ct, const uint64_t* e0, const uint64_t* e1,
+                  const uint32_t* m, hipStream_t st);
+// diagonal multiply-accumulate:
+//   A[pp][g] (+)= sum_{beta < kb, b < B} D[beta][g][b] * R[pp][beta][b]
+// R, A given as device arrays of ciphertext pointers; D contiguous
+// [kb][G][B][L][n] (Montgomery). accumulate: add to the existing A.
+void k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* const* R, const uint64_t* D,
+                int npairs, int kb, int G, int B, bool accumulate, hipStream_t st);
+
+}  // namespace hc

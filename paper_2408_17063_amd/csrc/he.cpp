@@ -1,0 +1,494 @@
+// Host orchestration of the HE operations: encoding, key generation,
+// encryption, key switching (plain and hoisted rotations) and the
+// kernel-level ABI. Every step runs in the device kernels of ntt.hip / ops.hip.
+#include <string.h>
+
+#include <algorithm>
+
+#include "he.h"
+
+namespace hc {
+
+uint64_t tag_u64(const char* s) {
+    uint64_t t = 0;
+    for (int i = 0; i < 8 && s[i]; i++) t |= (uint64_t)(uint8_t)s[i] << (8 * i);
+    return t;
+}
+
+// slots (host, count x 2 x nh) -> plaintext multipliers [count][L][n] in the NTT
+// domain (Montgomery form if mont), via the inverse slot transform mod p and the
+// centred lift.
+hc_status encode_plain(Ctx& c, uint64_t* out, const uint32_t* host_slots, int count, bool mont,
+                       hipStream_t st) {
+    const size_t n = c.n;
+    uint32_t *d_slots = nullptr, *d_eval = nullptr;
+    HC_CHECK(hipMalloc((void**)&d_slots, sizeof(uint32_t) * n * count));
+    HC_CHECK(hipMalloc((void**)&d_eval, sizeof(uint32_t) * n * count));
+    HC_CHECK(hipMemcpyAsync(d_slots, host_slots, sizeof(uint32_t) * n * count, hipMemcpyHostToDevice, st));
+    k_slots_to_eval(c, d_eval, d_slots, count, st);
+    ntt32(c, d_eval, count, true, st);
+    k_lift(c, out, d_eval, count, mont, st);
+    ntt64(c, out, (size_t)c.L * n, count, 0, c.L, false, st);
+    HC_CHECK(hipStreamSynchronize(st));
+    HC_CHECK(hipFree(d_slots));
+    HC_CHECK(hipFree(d_eval));
+    return HC_OK;
+}
+
+// encode from device slots already in [count][2][nh] u32 form (no host staging)
+void encode_plain_dev(Ctx& c, uint64_t* out, const uint32_t* d_slots, uint32_t* d_eval, int count,
+                      bool mont, hipStream_t st) {
+    k_slots_to_eval(c, d_eval, d_slots, count, st);
+    ntt32(c, d_eval, count, true, st);
+    k_lift(c, out, d_eval, count, mont, st);
+    ntt64(c, out, (size_t)c.L * c.n, count, 0, c.L, false, st);
+}
+
+hc_status prefix_mask(Ctx& c, uint32_t s, const uint64_t** out) {
+    auto it = c.prefix_masks.find(s);
+    if (it != c.prefix_masks.end()) { *out = it->second; return HC_OK; }
+    std::vector<uint32_t> sl((size_t)c.n, 0);
+    for (uint32_t i = 0; i < s; i++) { sl[i] = 1; sl[c.nh + i] = 1; }
+    uint64_t* d = nullptr;
+    HC_CHECK(hipMalloc((void**)&d, sizeof(uint64_t) * (size_t)c.L * c.n));
+    hc_status stt = encode_plain(c, d, sl.data(), 1, true, 0);
+    if (stt != HC_OK) { (void)hipFree(d); return stt; }
+    c.prefix_masks[s] = d;
+    *out = d;
+    return HC_OK;
+}
+
+// ------------------------------------------------------------------ key switching
+
+size_t ks_scratch_words(const Ctx& c) {
+    const size_t n = c.n;
+    return (size_t)c.L * n + (size_t)c.dnum * c.nq * n + 2 * (size_t)c.nq * n + 2 * (size_t)c.L * n + 1024;
+}
+
+KSBuf ks_take(Ctx& c, Arena& a) {
+    KSBuf b;
+    const size_t n = c.n;
+    b.tmpC = a.take<uint64_t>((size_t)c.L * n);
+    b.X = a.take<uint64_t>((size_t)c.dnum * c.nq * n);
+    b.T = a.take<uint64_t>(2 * (size_t)c.nq * n);
+    b.conv = a.take<uint64_t>(2 * (size_t)c.L * n);
+    return b;
+}
+
+size_t ks_take_bytes(const Ctx& c) {
+    const size_t n = c.n;
+    auto r = [](size_t w) { return (w * 8 + 255) & ~(size_t)255; };
+    return r((size_t)c.L * n) + r((size_t)c.dnum * c.nq * n) + r(2 * (size_t)c.nq * n) + r(2 * (size_t)c.L * n);
+}
+
+// T -> (sigma_k(c0) + ModDown(T0), ModDown(T1))
+static void moddown_into(Ctx& c, uint64_t* out, const uint64_t* c0, uint32_t k, KSBuf& b,
+                         hipStream_t st) {
+    const size_t n = c.n;
+    // special rows to coefficients (data points at the first transformed row)
+    ntt64(c, b.T + (size_t)c.L * n, (size_t)c.nq * n, 2, c.L, c.K, true, st);
+    k_moddown_conv(c, b.conv, b.T, st);
+    ntt64(c, b.conv, (size_t)c.L * n, 2, 0, c.L, false, st);
+    k_moddown_final(c, out, b.T, b.conv, c0, k, st);
+}
+
+// out = Rot(in) by sigma_k, non-hoisted. in, out: NTT domain [2][L][n]; out != in.
+void rotate_plain(Ctx& c, const uint64_t* key, uint32_t k, uint64_t* out, const uint64_t* in,
+                  KSBuf& b, hipStream_t st) {
+    const size_t n = c.n, Ln = (size_t)c.L * n;
+    k_permute(c, b.tmpC, in + Ln, c.L, k, 1, 0, st);
+    ntt64(c, b.tmpC, Ln, 1, 0, c.L, true, st);
+    k_modup(c, b.X, b.tmpC, 0, c.dnum, st);
+    ntt64(c, b.X, (size_t)c.nq * n, c.dnum, 0, c.nq, false, st);
+    k_inner(c, b.T, b.X, key, 1, st);
+    moddown_into(c, out, in, k, b, st);
+}
+
+// ModUp of c1 once (into b.X, NTT domain), shared by rotate_hoisted_one calls.
+void hoist_prepare(Ctx& c, const uint64_t* in, KSBuf& b, hipStream_t st) {
+    const size_t n = c.n, Ln = (size_t)c.L * n;
+    (void)hipMemcpyAsync(b.tmpC, in + Ln, sizeof(uint64_t) * Ln, hipMemcpyDeviceToDevice, st);
+    ntt64(c, b.tmpC, Ln, 1, 0, c.L, true, st);
+    k_modup(c, b.X, b.tmpC, 0, c.dnum, st);
+    ntt64(c, b.X, (size_t)c.nq * n, c.dnum, 0, c.nq, false, st);
+}
+
+void rotate_hoisted_one(Ctx& c, const uint64_t* key, uint32_t k, uint64_t* out, const uint64_t* in,
+                        KSBuf& b, hipStream_t st) {
+    k_inner(c, b.T, b.X, key, k, st);
+    moddown_into(c, out, in, k, b, st);
+}
+
+const uint64_t* find_key(const hc_gk* gk, uint32_t k) {
+    auto it = gk->keys.find(k);
+    return it == gk->keys.end() ? nullptr : it->second;
+}
+
+}  // namespace hc
+
+using namespace hc;
+
+// ------------------------------------------------------------------ keys
+
+extern "C" hc_status hc_keygen(hc_context* cp, const uint8_t seed[32], hc_sk** skp, hc_pk** pkp) {
+    if (!cp || !seed || !skp || !pkp) return HC_EINVAL;
+    Ctx& c = *cp;
+    HC_CHECK(hipSetDevice(c.device));
+    const size_t n = c.n, nq = c.nq, L = c.L;
+    hipStream_t st = 0;
+    hc_sk* sk = new hc_sk();
+    hc_pk* pk = new hc_pk();
+    int64_t* d_raw = nullptr;
+    uint64_t *d_e = nullptr;
+    HC_CHECK(hipMalloc((void**)&sk->d_s_mont, sizeof(uint64_t) * nq * n));
+    HC_CHECK(hipMalloc((void**)&pk->d_a, sizeof(uint64_t) * L * n));
+    HC_CHECK(hipMalloc((void**)&pk->d_b, sizeof(uint64_t) * L * n));
+    HC_CHECK(hipMalloc((void**)&d_raw, sizeof(int64_t) * n));
+    HC_CHECK(hipMalloc((void**)&d_e, sizeof(uint64_t) * L * n));
+    // s: ternary, the same integer on every prime of PQ
+    k_sample_small(c, sk->d_s_mont, d_raw, seed, tag_u64("sk"), 0, 1, 0, (int)nq, st);
+    ntt64(c, sk->d_s_mont, nq * n, 1, 0, (int)nq, false, st);
+    k_to_mont(c, sk->d_s_mont, 0, (int)nq, 1, 0, st);
+    // pk = (e - a s, a) over Q
+    k_sample_uniform(c, pk->d_a, seed, tag_u64("pk_a"), 0, 0, (int)L, st);
+    ntt64(c, pk->d_a, L * n, 1, 0, (int)L, false, st);
+    k_sample_small(c, d_e, nullptr, seed, tag_u64("pk_e"), 0, 2, 0, (int)L, st);
+    ntt64(c, d_e, L * n, 1, 0, (int)L, false, st);
+    k_keyrow(c, pk->d_b, d_e, pk->d_a, sk->d_s_mont, nullptr, nullptr, 0, (int)L, st);
+    std::vector<int64_t> raw(n);
+    HC_CHECK(hipMemcpyAsync(raw.data(), d_raw, sizeof(int64_t) * n, hipMemcpyDeviceToHost, st));
+    HC_CHECK(hipStreamSynchronize(st));
+    sk->s.resize(n);
+    for (size_t i = 0; i < n; i++) sk->s[i] = (int8_t)raw[i];
+    HC_CHECK(hipFree(d_raw));
+    HC_CHECK(hipFree(d_e));
+    *skp = sk;
+    *pkp = pk;
+    return HC_OK;
+}
+
+extern "C" void hc_sk_destroy(hc_sk* sk) {
+    if (!sk) return;
+    (void)hipFree(sk->d_s_mont);
+    delete sk;
+}
+
+extern "C" void hc_pk_destroy(hc_pk* pk) {
+    if (!pk) return;
+    (void)hipFree(pk->d_a);
+    (void)hipFree(pk->d_b);
+    delete pk;
+}
+
+extern "C" hc_status hc_galois_keygen(hc_context* cp, const hc_sk* sk, const uint32_t* elements,
+                                      uint32_t count, const uint8_t seed[32], hc_gk** out) {
+    if (!cp || !sk || !seed || !out || (count && !elements)) return HC_EINVAL;
+    Ctx& c = *cp;
+    for (uint32_t i = 0; i < count; i++)
+        if ((elements[i] & 1) == 0 || elements[i] >= 2u * c.n) return HC_EINVAL;
+    HC_CHECK(hipSetDevice(c.device));
+    const size_t n = c.n, nq = c.nq;
+    hipStream_t st = 0;
+    hc_gk* gk = new hc_gk();
+    gk->dnum = c.dnum;
+    gk->nq = c.nq;
+    gk->n = c.n;
+    uint64_t *d_e = nullptr, *d_rs = nullptr, *d_g = nullptr;
+    HC_CHECK(hipMalloc((void**)&d_e, sizeof(uint64_t) * nq * n));
+    HC_CHECK(hipMalloc((void**)&d_rs, sizeof(uint64_t) * nq * n));
+    HC_CHECK(hipMalloc((void**)&d_g, sizeof(uint64_t) * c.dnum * nq));
+    // gadget P (Q/D_j) [(Q/D_j)^-1]_{D_j}: P mod q_i on the digit's primes, 0 elsewhere
+    std::vector<uint64_t> hmod(c.L);
+    HC_CHECK(hipMemcpy(hmod.data(), c.d_pmodq, sizeof(uint64_t) * c.L, hipMemcpyDeviceToHost));
+    std::vector<uint64_t> g((size_t)c.dnum * nq, 0);
+    for (int j = 0; j < c.dnum; j++)
+        for (int a = 0; a < c.alpha; a++) g[(size_t)j * nq + j * c.alpha + a] = hmod[j * c.alpha + a];
+    HC_CHECK(hipMemcpy(d_g, g.data(), sizeof(uint64_t) * g.size(), hipMemcpyHostToDevice));
+    std::vector<uint32_t> uniq(elements, elements + count);
+    std::sort(uniq.begin(), uniq.end());
+    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+    for (uint32_t k : uniq) {
+        uint64_t* key = nullptr;
+        if (hipMalloc((void**)&key, sizeof(uint64_t) * c.dnum * 2 * nq * n) != hipSuccess) {
+            hc_gk_destroy(gk);
+            (void)hipFree(d_e); (void)hipFree(d_rs); (void)hipFree(d_g);
+            return HC_ENOMEM;
+        }
+        gk->keys[k] = key;
+        k_permute(c, d_rs, sk->d_s_mont, (int)nq, k, 1, 0, st);  // sigma_k(s), NTT domain
+        for (int j = 0; j < c.dnum; j++) {
+            uint64_t obj = ((uint64_t)k << 16) | (uint64_t)j;
+            uint64_t* b = key + (size_t)j * 2 * nq * n;
+            uint64_t* a = b + nq * n;
+            k_sample_uniform(c, a, seed, tag_u64("gk_a"), obj, 0, (int)nq, st);
+            ntt64(c, a, nq * n, 1, 0, (int)nq, false, st);
+            k_sample_small(c, d_e, nullptr, seed, tag_u64("gk_e"), obj, 2, 0, (int)nq, st);
+            ntt64(c, d_e, nq * n, 1, 0, (int)nq, false, st);
+            k_keyrow(c, b, d_e, a, sk->d_s_mont, d_rs, d_g + (size_t)j * nq, 0, (int)nq, st);
+        }
+        k_to_mont(c, key, 0, (int)nq, 2 * c.dnum, nq * n, st);
+    }
+    HC_CHECK(hipStreamSynchronize(st));
+    HC_CHECK(hipFree(d_e));
+    HC_CHECK(hipFree(d_rs));
+    HC_CHECK(hipFree(d_g));
+    *out = gk;
+    return HC_OK;
+}
+
+extern "C" void hc_gk_destroy(hc_gk* gk) {
+    if (!gk) return;
+    for (auto& kv : gk->keys) (void)hipFree(kv.second);
+    delete gk;
+}
+
+// ------------------------------------------------------------------ database
+
+extern "C" hc_status hc_db_upload(hc_context* cp, const uint32_t* cols, uint32_t ncol, uint64_t N,
+                                  hc_db** out) {
+    if (!cp || !out || N == 0 || (ncol && !cols)) return HC_EINVAL;
+    Ctx& c = *cp;
+    HC_CHECK(hipSetDevice(c.device));
+    const size_t n = c.n;
+    hc_db* db = new hc_db();
+    db->ncol = ncol;
+    db->N = N;
+    db->n_ct = (uint32_t)((N + n - 1) / n);
+    if (ncol) {
+        HC_CHECK(hipMalloc((void**)&db->d_pt, sizeof(uint64_t) * ncol * db->n_ct * c.L * n));
+        std::vector<uint32_t> sl(n * db->n_ct);
+        for (uint32_t col = 0; col < ncol; col++) {
+            std::fill(sl.begin(), sl.end(), 0u);
+            for (uint64_t r = 0; r < N; r++) sl[r] = cols[(size_t)col * N + r] % (uint32_t)c.p;
+            // record r: ciphertext r / n, row (r % n) / nh, column r % nh = flat r % n
+            hc_status s = encode_plain(c, db->d_pt + (size_t)col * db->n_ct * c.L * n, sl.data(),
+                                       (int)db->n_ct, true, 0);
+            if (s != HC_OK) { hc_db_destroy(db); return s; }
+        }
+    }
+    *out = db;
+    return HC_OK;
+}
+
+extern "C" void hc_db_destroy(hc_db* db) {
+    if (!db) return;
+    (void)hipFree(db->d_pt);
+    delete db;
+}
+
+// ------------------------------------------------------------------ encryption
+
+extern "C" hc_status hc_encrypt(hc_context* cp, const hc_pk* pk, const uint32_t* slots,
+                                const uint8_t seed[32], uint64_t* ct_out, hipStream_t st) {
+    if (!cp || !pk || !slots || !seed || !ct_out) return HC_EINVAL;
+    Ctx& c = *cp;
+    HC_CHECK(hipSetDevice(c.device));
+    const size_t n = c.n, L = c.L;
+    uint64_t *u = nullptr, *e0 = nullptr, *e1 = nullptr;
+    uint32_t *d_sl = nullptr, *d_m = nullptr;
+    HC_CHECK(hipMalloc((void**)&u, sizeof(uint64_t) * L * n));
+    HC_CHECK(hipMalloc((void**)&e0, sizeof(uint64_t) * L * n));
+    HC_CHECK(hipMalloc((void**)&e1, sizeof(uint64_t) * L * n));
+    HC_CHECK(hipMalloc((void**)&d_sl, sizeof(uint32_t) * n));
+    HC_CHECK(hipMalloc((void**)&d_m, sizeof(uint32_t) * n));
+    HC_CHECK(hipMemcpyAsync(d_sl, slots, sizeof(uint32_t) * n, hipMemcpyHostToDevice, st));
+    k_slots_to_eval(c, d_m, d_sl, 1, st);
+    ntt32(c, d_m, 1, true, st);  // m: coefficients in [0, p)
+    k_sample_small(c, u, nullptr, seed, tag_u64("enc_u"), 0, 1, 0, (int)L, st);
+    ntt64(c, u, L * n, 1, 0, (int)L, false, st);
+    k_to_mont(c, u, 0, (int)L, 1, 0, st);
+    k_sample_small(c, e0, nullptr, seed, tag_u64("enc_e0"), 0, 2, 0, (int)L, st);
+    k_sample_small(c, e1, nullptr, seed, tag_u64("enc_e1"), 0, 2, 0, (int)L, st);
+    k_mul_mont(c, ct_out, pk->d_b, u, 0, (int)L, st);
+    k_mul_mont(c, ct_out + L * n, pk->d_a, u, 0, (int)L, st);
+    ntt64(c, ct_out, L * n, 2, 0, (int)L, true, st);
+    k_enc_finish(c, ct_out, e0, e1, d_m, st);
+    HC_CHECK(hipStreamSynchronize(st));
+    HC_CHECK(hipFree(u));
+    HC_CHECK(hipFree(e0));
+    HC_CHECK(hipFree(e1));
+    HC_CHECK(hipFree(d_sl));
+    HC_CHECK(hipFree(d_m));
+    return HC_OK;
+}
+
+// ------------------------------------------------------------------ kernel-level ABI
+
+extern "C" hc_status hc_ntt(hc_context* cp, uint64_t* data, uint32_t count, uint32_t limb_first,
+                            uint32_t nlimbs, int inverse, hipStream_t st) {
+    if (!cp || !data || limb_first + nlimbs > (uint32_t)cp->nq) return HC_EINVAL;
+    HC_CHECK(hipSetDevice(cp->device));
+    ntt64(*cp, data, (size_t)nlimbs * cp->n, (int)count, (int)limb_first, (int)nlimbs, inverse != 0, st);
+    HC_CHECK(hipGetLastError());
+    return HC_OK;
+}
+
+static hc_status rotate_common(hc_context* cp, const hc_gk* gk, const uint32_t* elts, uint32_t count,
+                               const uint64_t* ct_in, uint64_t* cts_out, bool hoisted, hipStream_t st) {
+    if (!cp || !gk || !elts || !ct_in || !cts_out || count == 0) return HC_EINVAL;
+    Ctx& c = *cp;
+    HC_CHECK(hipSetDevice(c.device));
+    std::vector<const uint64_t*> keys(count);
+    for (uint32_t i = 0; i < count; i++) {
+        keys[i] = find_key(gk, elts[i]);
+        if (!keys[i]) return HC_ENOKEY;
+    }
+    const size_t Ln2 = 2 * (size_t)c.L * c.n;
+    HC_CHECK(hipStreamSynchronize(st));
+    if (c.ws.reserve(ks_take_bytes(c) + 256 * 4 + sizeof(uint64_t) * Ln2 * 2) != HC_OK) return HC_ENOMEM;
+    KSBuf b = ks_take(c, c.ws);
+    uint64_t* inN = c.ws.take<uint64_t>(Ln2);
+    uint64_t* outN = c.ws.take<uint64_t>(Ln2);
+    if (!b.tmpC || !b.X || !b.T || !b.conv || !inN || !outN) return HC_ENOMEM;
+    HC_CHECK(hipMemcpyAsync(inN, ct_in, sizeof(uint64_t) * Ln2, hipMemcpyDeviceToDevice, st));
+    ntt64(c, inN, (size_t)c.L * c.n, 2, 0, c.L, false, st);
+    if (hoisted) hoist_prepare(c, inN, b, st);
+    for (uint32_t i = 0; i < count; i++) {
+        if (hoisted) rotate_hoisted_one(c, keys[i], elts[i], outN, inN, b, st);
+        else rotate_plain(c, keys[i], elts[i], outN, inN, b, st);
+        ntt64(c, outN, (size_t)c.L * c.n, 2, 0, c.L, true, st);
+        HC_CHECK(hipMemcpyAsync(cts_out + i * Ln2, outN, sizeof(uint64_t) * Ln2, hipMemcpyDeviceToDevice, st));
+    }
+    HC_CHECK(hipGetLastError());
+    HC_CHECK(hipStreamSynchronize(st));
+    return HC_OK;
+}
+
+extern "C" hc_status hc_rotate(hc_context* cp, const hc_gk* gk, uint32_t element, const uint64_t* ct_in,
+                               uint64_t* ct_out, hipStream_t st) {
+    return rotate_common(cp, gk, &element, 1, ct_in, ct_out, false, st);
+}
+
+extern "C" hc_status hc_rotate_hoisted(hc_context* cp, const hc_gk* gk, const uint32_t* elements,
+                                       uint32_t count, const uint64_t* ct_in, uint64_t* cts_out,
+                                       hipStream_t st) {
+    return rotate_common(cp, gk, elements, count, ct_in, cts_out, true, st);
+}
+
+extern "C" hc_status hc_mul_plain(hc_context* cp, const uint64_t* ct_in, const uint32_t* slots,
+                                  uint64_t* ct_out, hipStream_t st) {
+    if (!cp || !ct_in || !slots || !ct_out) return HC_EINVAL;
+    Ctx& c = *cp;
+    HC_CHECK(hipSetDevice(c.device));
+    const size_t Ln = (size_t)c.L * c.n;
+    HC_CHECK(hipStreamSynchronize(st));
+    if (c.ws.reserve(sizeof(uint64_t) * Ln * 3 + 1024) != HC_OK) return HC_ENOMEM;
+    uint64_t* pt = c.ws.take<uint64_t>(Ln);
+    uint64_t* tmp = c.ws.take<uint64_t>(2 * Ln);
+    if (!pt || !tmp) return HC_ENOMEM;
+    hc_status s = encode_plain(c, pt, slots, 1, true, st);
+    if (s != HC_OK) return s;
+    HC_CHECK(hipMemcpyAsync(tmp, ct_in, sizeof(uint64_t) * 2 * Ln, hipMemcpyDeviceToDevice, st));
+    ntt64(c, tmp, Ln, 2, 0, c.L, false, st);
+    k_mul_plain(c, tmp, tmp, pt, st);
+    ntt64(c, tmp, Ln, 2, 0, c.L, true, st);
+    HC_CHECK(hipMemcpyAsync(ct_out, tmp, sizeof(uint64_t) * 2 * Ln, hipMemcpyDeviceToDevice, st));
+    HC_CHECK(hipStreamSynchronize(st));
+    return HC_OK;
+}
+
+extern "C" hc_status hc_modup(hc_context* cp, const uint64_t* x, uint32_t digit, uint64_t* out,
+                              hipStream_t st) {
+    if (!cp || !x || !out || digit >= (uint32_t)cp->dnum) return HC_EINVAL;
+    HC_CHECK(hipSetDevice(cp->device));
+    k_modup(*cp, out, x, (int)digit, 1, st);
+    HC_CHECK(hipGetLastError());
+    return HC_OK;
+}
+
+extern "C" hc_status hc_moddown(hc_context* cp, const uint64_t* T, uint64_t* out, hipStream_t st) {
+    if (!cp || !T || !out) return HC_EINVAL;
+    Ctx& c = *cp;
+    HC_CHECK(hipSetDevice(c.device));
+    const size_t n = c.n;
+    HC_CHECK(hipStreamSynchronize(st));
+    if (c.ws.reserve(sizeof(uint64_t) * (2 * c.nq * n + 5 * c.L * n) + 4096) != HC_OK) return HC_ENOMEM;
+    // T as component 0 of a [2][nq][n] pair (component 1 zero); the conversion and
+    // the final combination are element-wise, so they apply in the coefficient domain
+    uint64_t* TT = c.ws.take<uint64_t>(2 * c.nq * n);
+    uint64_t* conv = c.ws.take<uint64_t>(2 * c.L * n);
+    uint64_t* zero = c.ws.take<uint64_t>(c.L * n);
+    uint64_t* o2 = c.ws.take<uint64_t>(2 * c.L * n);
+    if (!TT || !conv || !zero || !o2) return HC_ENOMEM;
+    HC_CHECK(hipMemsetAsync(TT, 0, sizeof(uint64_t) * 2 * c.nq * n, st));
+    HC_CHECK(hipMemsetAsync(zero, 0, sizeof(uint64_t) * c.L * n, st));
+    HC_CHECK(hipMemcpyAsync(TT, T, sizeof(uint64_t) * c.nq * n, hipMemcpyDeviceToDevice, st));
+    k_moddown_conv(c, conv, TT, st);
+    k_moddown_final(c, o2, TT, conv, zero, 1, st);
+    HC_CHECK(hipMemcpyAsync(out, o2, sizeof(uint64_t) * c.L * n, hipMemcpyDeviceToDevice, st));
+    HC_CHECK(hipStreamSynchronize(st));
+    return HC_OK;
+}
+
+extern "C" hc_status hc_sample(hc_context* cp, int kind, const uint8_t seed[32], const char* tag,
+                               uint64_t obj, uint32_t limb, uint64_t* out, hipStream_t st) {
+    if (!cp || !seed || !tag || !out || kind < 0 || kind > 2 || strlen(tag) > 8) return HC_EINVAL;
+    Ctx& c = *cp;
+    HC_CHECK(hipSetDevice(c.device));
+    if (kind == 0) {
+        if (limb >= (uint32_t)c.nq) return HC_EINVAL;
+        k_sample_uniform(c, out, seed, tag_u64(tag), obj, (int)limb, 1, st);
+    } else {
+        uint64_t* tmp = nullptr;
+        HC_CHECK(hipMalloc((void**)&tmp, sizeof(uint64_t) * c.n));
+        k_sample_small(c, tmp, reinterpret_cast<int64_t*>(out), seed, tag_u64(tag), obj, kind, 0, 1, st);
+        HC_CHECK(hipStreamSynchronize(st));
+        HC_CHECK(hipFree(tmp));
+    }
+    HC_CHECK(hipGetLastError());
+    return HC_OK;
+}
+
+extern "C" hc_status hc_encode_diagonal(hc_context* cp, uint32_t s, uint32_t B, uint32_t beta,
+                                        uint32_t gi, uint32_t b, uint64_t* out, hipStream_t st) {
+    if (!cp || !out || s == 0 || B == 0 || s > (uint32_t)cp->nh) return HC_EINVAL;
+    Ctx& c = *cp;
+    HC_CHECK(hipSetDevice(c.device));
+    uint32_t* d = nullptr;
+    HC_CHECK(hipMalloc((void**)&d, sizeof(uint32_t) * (c.n + 4)));
+    uint32_t prm[3] = {beta, gi, b};
+    HC_CHECK(hipMemcpyAsync(d + c.n, prm, sizeof(prm), hipMemcpyHostToDevice, st));
+    k_diag_gen(c, d, d + c.n, 1, s, B, st);
+    ntt32(c, d, 1, true, st);
+    k_lift(c, out, d, 1, false, st);
+    HC_CHECK(hipStreamSynchronize(st));
+    HC_CHECK(hipFree(d));
+    return HC_OK;
+}
+
+// ------------------------------------------------------------------ exports
+
+extern "C" hc_status hc_export_sk(hc_context* cp, const hc_sk* sk, int64_t* out) {
+    if (!cp || !sk || !out) return HC_EINVAL;
+    for (size_t i = 0; i < sk->s.size(); i++) out[i] = sk->s[i];
+    return HC_OK;
+}
+
+static hc_status export_rows(Ctx& c, const uint64_t* d, int count, int nl, bool from_mont, uint64_t* out) {
+    const size_t n = c.n;
+    uint64_t* tmp = nullptr;
+    HC_CHECK(hipMalloc((void**)&tmp, sizeof(uint64_t) * count * nl * n));
+    HC_CHECK(hipMemcpy(tmp, d, sizeof(uint64_t) * count * nl * n, hipMemcpyDeviceToDevice));
+    if (from_mont) k_from_mont(c, tmp, 0, nl, count, (size_t)nl * n, 0);
+    ntt64(c, tmp, (size_t)nl * n, count, 0, nl, true, 0);
+    HC_CHECK(hipMemcpy(out, tmp, sizeof(uint64_t) * count * nl * n, hipMemcpyDeviceToHost));
+    HC_CHECK(hipFree(tmp));
+    return HC_OK;
+}
+
+extern "C" hc_status hc_export_pk(hc_context* cp, const hc_pk* pk, uint64_t* out) {
+    if (!cp || !pk || !out) return HC_EINVAL;
+    HC_CHECK(hipSetDevice(cp->device));
+    const size_t Ln = (size_t)cp->L * cp->n;
+    hc_status s = export_rows(*cp, pk->d_b, 1, cp->L, false, out);
+    if (s != HC_OK) return s;
+    return export_rows(*cp, pk->d_a, 1, cp->L, false, out + Ln);
+}
+
+extern "C" hc_status hc_export_gk(hc_context* cp, const hc_gk* gk, uint32_t element, uint64_t* out) {
+    if (!cp || !gk || !out) return HC_EINVAL;
+    const uint64_t* key = find_key(gk, element);
+    if (!key) return HC_ENOKEY;
+    HC_CHECK(hipSetDevice(cp->device));
+    return export_rows(*cp, key, 2 * cp->dnum, cp->nq, true, out);
+}

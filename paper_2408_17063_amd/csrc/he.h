@@ -1,0 +1,30 @@
+// Declarations shared by the host orchestration files (he.cpp, compress.cpp).
+#pragma once
+#include "hc_internal.h"
+
+namespace hc {
+
+// key-switching temporaries: tmpC [L][n], X [dnum][nq][n], T [2][nq][n], conv [2][L][n]
+struct KSBuf {
+    uint64_t* tmpC = nullptr;
+    uint64_t* X = nullptr;
+    uint64_t* T = nullptr;
+    uint64_t* conv = nullptr;
+};
+
+uint64_t tag_u64(const char* s);
+hc_status encode_plain(Ctx& c, uint64_t* out, const uint32_t* host_slots, int count, bool mont,
+                       hipStream_t st);
+void encode_plain_dev(Ctx& c, uint64_t* out, const uint32_t* d_slots, uint32_t* d_eval, int count,
+                      bool mont, hipStream_t st);
+hc_status prefix_mask(Ctx& c, uint32_t s, const uint64_t** out);
+size_t ks_take_bytes(const Ctx& c);
+KSBuf ks_take(Ctx& c, Arena& a);
+void rotate_plain(Ctx& c, const uint64_t* key, uint32_t k, uint64_t* out, const uint64_t* in,
+                  KSBuf& b, hipStream_t st);
+void hoist_prepare(Ctx& c, const uint64_t* in, KSBuf& b, hipStream_t st);
+void rotate_hoisted_one(Ctx& c, const uint64_t* key, uint32_t k, uint64_t* out, const uint64_t* in,
+                        KSBuf& b, hipStream_t st);
+const uint64_t* find_key(const hc_gk* gk, uint32_t k);
+
+}  // namespace hc

@@ -1,0 +1,571 @@
+// Device kernels of libhc other than the NTT.
+//
+// Layout: a ring element over a set of primes is rows of n uint64_t residues
+// ([row][coefficient]); a ciphertext is [2][L][n]. Every kernel below is
+// element-wise over (row, coefficient) -- one thread per coefficient, rows
+// along grid.y -- so all accesses are unit-stride across a wavefront, except
+// the automorphism gathers (a fixed permutation within a row).
+#include <cstring>
+
+#include "hc_internal.h"
+
+namespace hc {
+
+constexpr int EW_THREADS = 256;
+
+static inline dim3 ew_grid(int n, int rows, int count = 1) {
+    return dim3((n + EW_THREADS - 1) / EW_THREADS, rows, count);
+}
+
+// NTT-domain index that sigma_k pulls from: entry i holds a(psi^(2 brv(i)+1)),
+// so sigma_k(a) at i equals a at the entry whose exponent is (2 brv(i)+1) k.
+__device__ __forceinline__ uint32_t galois_src(uint32_t i, uint32_t k, int logn) {
+    uint32_t e = (__brev(i) >> (32 - logn)) * 2u + 1u;
+    uint32_t e2 = (e * k) & ((2u << logn) - 1u);
+    return __brev((e2 - 1u) >> 1) >> (32 - logn);
+}
+
+// ------------------------------------------------------------------ basic element-wise
+
+__global__ void permute_kernel(uint64_t* __restrict__ out, const uint64_t* __restrict__ in, int n,
+                               int logn, uint32_t k, size_t stride) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    size_t off = (size_t)blockIdx.z * stride + (size_t)blockIdx.y * n;
+    uint32_t src = (k == 1) ? x : galois_src(x, k, logn);
+    out[off + x] = in[off + src];
+}
+
+void k_permute(const Ctx& c, uint64_t* out, const uint64_t* in, int nl, uint32_t k, int count,
+               size_t stride, hipStream_t st) {
+    hipLaunchKernelGGL(permute_kernel, ew_grid(c.n, nl, count), dim3(EW_THREADS), 0, st, out, in,
+                       c.n, c.logn, k, stride);
+}
+
+__global__ void add_kernel(uint64_t* out, const uint64_t* a, const uint64_t* b, const uint64_t* mods,
+                           int n, int lf, size_t stride) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    size_t off = (size_t)blockIdx.z * stride + (size_t)blockIdx.y * n + x;
+    out[off] = add_mod(a[off], b[off], mods[lf + blockIdx.y]);
+}
+
+void k_add(const Ctx& c, uint64_t* out, const uint64_t* a, const uint64_t* b, int lf, int nl,
+           int count, size_t stride, hipStream_t st) {
+    hipLaunchKernelGGL(add_kernel, ew_grid(c.n, nl, count), dim3(EW_THREADS), 0, st, out, a, b,
+                       c.d_mods, c.n, lf, stride);
+}
+
+__global__ void mul_plain_kernel(uint64_t* out, const uint64_t* ct, const uint64_t* pt,
+                                 const uint64_t* mods, const uint64_t* qinv, int n, int L) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    int r = blockIdx.y;
+    uint64_t q = mods[r], qi = qinv[r];
+    uint64_t m = pt[(size_t)r * n + x];
+    size_t o0 = (size_t)r * n + x, o1 = o0 + (size_t)L * n;
+    uint64_t v0 = ct[o0], v1 = ct[o1];
+    out[o0] = mont_mul(v0, m, q, qi);
+    out[o1] = mont_mul(v1, m, q, qi);
+}
+
+void k_mul_plain(const Ctx& c, uint64_t* out, const uint64_t* ct, const uint64_t* pt_mont,
+                 hipStream_t st) {
+    hipLaunchKernelGGL(mul_plain_kernel, ew_grid(c.n, c.L), dim3(EW_THREADS), 0, st, out, ct,
+                       pt_mont, c.d_mods, c.d_qinv, c.n, c.L);
+}
+
+__global__ void mul_mont_kernel(uint64_t* out, const uint64_t* a, const uint64_t* bm,
+                                const uint64_t* mods, const uint64_t* qinv, int n, int lf) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    int r = blockIdx.y;
+    size_t o = (size_t)r * n + x;
+    out[o] = mont_mul(a[o], bm[o], mods[lf + r], qinv[lf + r]);
+}
+
+void k_mul_mont(const Ctx& c, uint64_t* out, const uint64_t* a, const uint64_t* bm, int lf, int nl,
+                hipStream_t st) {
+    hipLaunchKernelGGL(mul_mont_kernel, ew_grid(c.n, nl), dim3(EW_THREADS), 0, st, out, a, bm,
+                       c.d_mods, c.d_qinv, c.n, lf);
+}
+
+__global__ void to_mont_kernel(uint64_t* x, const uint64_t* mods, const uint64_t* qinv,
+                               const uint64_t* r2, int n, int lf, size_t stride, int inverse) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int r = lf + blockIdx.y;
+    size_t o = (size_t)blockIdx.z * stride + (size_t)blockIdx.y * n + i;
+    uint64_t q = mods[r];
+    // x * 2^128 * 2^-64 = x 2^64 ; or x * 1 * 2^-64
+    x[o] = inverse ? redc(u128p{x[o], 0}, q, qinv[r]) : mont_mul(x[o], r2[r], q, qinv[r]);
+}
+
+void k_to_mont(const Ctx& c, uint64_t* x, int lf, int nl, int count, size_t stride, hipStream_t st) {
+    hipLaunchKernelGGL(to_mont_kernel, ew_grid(c.n, nl, count), dim3(EW_THREADS), 0, st, x,
+                       c.d_mods, c.d_qinv, c.d_r2, c.n, lf, stride, 0);
+}
+
+void k_from_mont(const Ctx& c, uint64_t* x, int lf, int nl, int count, size_t stride, hipStream_t st) {
+    hipLaunchKernelGGL(to_mont_kernel, ew_grid(c.n, nl, count), dim3(EW_THREADS), 0, st, x,
+                       c.d_mods, c.d_qinv, c.d_r2, c.n, lf, stride, 1);
+}
+
+// ------------------------------------------------------------------ key switching
+
+// One thread per coefficient; for each digit j: y_a = [x_{j,a} (D_j/q_{j,a})^-1]_{q},
+// then for every prime r of PQ outside the digit sum_a y_a (D_j/q_{j,a}) mod r
+// (128-bit sum, one Montgomery reduction); on the digit's own primes a copy of x.
+__global__ void modup_kernel(uint64_t* __restrict__ X, const uint64_t* __restrict__ x,
+                             const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv,
+                             const uint64_t* __restrict__ inv, const uint64_t* __restrict__ cst,
+                             int n, int nq, int alpha, int digit_first) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int j = digit_first + blockIdx.y;
+    uint64_t y[4];
+    uint64_t* out = X + (size_t)blockIdx.y * nq * n;
+    for (int a = 0; a < alpha; a++) {
+        int r = j * alpha + a;
+        uint64_t v = x[(size_t)r * n + i];
+        out[(size_t)r * n + i] = v;
+        const uint64_t* iv = inv + ((size_t)j * alpha + a) * 2;
+        y[a] = shoup(v, iv[0], iv[1], mods[r]);
+    }
+    const uint64_t* cj = cst + (size_t)j * alpha * nq;
+    for (int r = 0; r < nq; r++) {
+        if (r >= j * alpha && r < (j + 1) * alpha) continue;
+        u128p acc{0, 0};
+        for (int a = 0; a < alpha; a++) add128(acc, mul128(y[a], cj[(size_t)a * nq + r]));
+        out[(size_t)r * n + i] = redc(acc, mods[r], qinv[r]);
+    }
+}
+
+void k_modup(const Ctx& c, uint64_t* X, const uint64_t* x, int digit_first, int ndigits,
+             hipStream_t st) {
+    hipLaunchKernelGGL(modup_kernel, ew_grid(c.n, ndigits), dim3(EW_THREADS), 0, st, X, x, c.d_mods,
+                       c.d_qinv, c.d_modup_inv, c.d_modup_c, c.n, c.nq, c.alpha, digit_first);
+}
+
+// T[c][r][i] = sum_j X_j[r][src(i)] * key_j[c][r][i]; key in Montgomery form, so one
+// reduction of the 128-bit sum gives the plain product sum (dnum q^2 < q 2^64).
+__global__ void inner_kernel(uint64_t* __restrict__ T, const uint64_t* __restrict__ X,
+                             const uint64_t* __restrict__ key, const uint64_t* __restrict__ mods,
+                             const uint64_t* __restrict__ qinv, int n, int logn, int nq, int dnum,
+                             uint32_t k) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int r = blockIdx.y;
+    const uint32_t src = (k == 1) ? i : galois_src(i, k, logn);
+    const size_t row = (size_t)nq * n;
+    u128p a0{0, 0}, a1{0, 0};
+    for (int j = 0; j < dnum; j++) {
+        uint64_t xv = X[(size_t)j * row + (size_t)r * n + src];
+        const uint64_t* kj = key + (size_t)j * 2 * row + (size_t)r * n + i;
+        add128(a0, mul128(xv, kj[0]));
+        add128(a1, mul128(xv, kj[row]));
+    }
+    uint64_t q = mods[r], qi = qinv[r];
+    T[(size_t)r * n + i] = redc(a0, q, qi);
+    T[row + (size_t)r * n + i] = redc(a1, q, qi);
+}
+
+void k_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const uint64_t* key, uint32_t k,
+             hipStream_t st) {
+    hipLaunchKernelGGL(inner_kernel, ew_grid(c.n, c.nq), dim3(EW_THREADS), 0, st, T, X, key,
+                       c.d_mods, c.d_qinv, c.n, c.logn, c.nq, c.dnum, k);
+}
+
+// conv[c][i][x] = sum_k [T_{p_k}(x) (P/p_k)^-1]_{p_k} (P/p_k) mod q_i
+__global__ void moddown_conv_kernel(uint64_t* __restrict__ conv, const uint64_t* __restrict__ T,
+                                    const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv,
+                                    const uint64_t* __restrict__ inv, const uint64_t* __restrict__ cst,
+                                    int n, int L, int K) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int comp = blockIdx.z;
+    const int nq = L + K;
+    const uint64_t* Tc = T + (size_t)comp * nq * n;
+    uint64_t y[4];
+    for (int k = 0; k < K; k++) {
+        uint64_t pk = mods[L + k];
+        y[k] = shoup(Tc[(size_t)(L + k) * n + x], inv[2 * k], inv[2 * k + 1], pk);
+    }
+    int i = blockIdx.y;
+    u128p acc{0, 0};
+    for (int k = 0; k < K; k++) add128(acc, mul128(y[k], cst[(size_t)k * L + i]));
+    conv[(size_t)comp * L * n + (size_t)i * n + x] = redc(acc, mods[i], qinv[i]);
+}
+
+void k_moddown_conv(const Ctx& c, uint64_t* conv, const uint64_t* T, hipStream_t st) {
+    hipLaunchKernelGGL(moddown_conv_kernel, ew_grid(c.n, c.L, 2), dim3(EW_THREADS), 0, st, conv, T,
+                       c.d_mods, c.d_qinv, c.d_moddown_inv, c.d_moddown_c, c.n, c.L, c.K);
+}
+
+__global__ void moddown_final_kernel(uint64_t* __restrict__ out, const uint64_t* __restrict__ T,
+                                     const uint64_t* __restrict__ conv, const uint64_t* __restrict__ c0,
+                                     const uint64_t* __restrict__ mods, const uint64_t* __restrict__ pinv,
+                                     int n, int logn, int L, int K, uint32_t k) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int i = blockIdx.y;
+    const int nq = L + K;
+    const uint64_t q = mods[i];
+    const uint64_t pi = pinv[2 * i], pis = pinv[2 * i + 1];
+    size_t o = (size_t)i * n + x;
+    uint64_t d0 = sub_mod(T[o], conv[o], q);
+    uint64_t d1 = sub_mod(T[(size_t)nq * n + o], conv[(size_t)L * n + o], q);
+    d0 = shoup(d0, pi, pis, q);
+    d1 = shoup(d1, pi, pis, q);
+    uint32_t src = (k == 1) ? x : galois_src(x, k, logn);
+    out[o] = add_mod(d0, c0[(size_t)i * n + src], q);
+    out[(size_t)L * n + o] = d1;
+}
+
+void k_moddown_final(const Ctx& c, uint64_t* out, const uint64_t* T, const uint64_t* conv,
+                     const uint64_t* c0, uint32_t k, hipStream_t st) {
+    hipLaunchKernelGGL(moddown_final_kernel, ew_grid(c.n, c.L), dim3(EW_THREADS), 0, st, out, T, conv,
+                       c0, c.d_mods, c.d_pinv, c.n, c.logn, c.L, c.K, k);
+}
+
+// ------------------------------------------------------------------ encoding
+
+__global__ void slots_to_eval_kernel(uint32_t* out, const uint32_t* slots, const uint32_t* slotpos,
+                                     int n, uint32_t p) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    size_t base = (size_t)blockIdx.z * n;
+    out[base + slotpos[x]] = slots[base + x] % p;
+}
+
+void k_slots_to_eval(const Ctx& c, uint32_t* out, const uint32_t* slots, int count, hipStream_t st) {
+    hipLaunchKernelGGL(slots_to_eval_kernel, ew_grid(c.n, 1, count), dim3(EW_THREADS), 0, st, out,
+                       slots, c.d_slotpos, c.n, (uint32_t)c.p);
+}
+
+__global__ void lift_kernel(uint64_t* out, const uint32_t* in, const uint64_t* mods,
+                            const uint64_t* qinv, const uint64_t* r2, int n, int L, uint32_t p,
+                            int mont) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int r = blockIdx.y;
+    uint32_t m = in[(size_t)blockIdx.z * n + x];
+    uint64_t q = mods[r];
+    uint64_t v = (m > p / 2) ? q - (uint64_t)(p - m) : (uint64_t)m;  // centred lift
+    if (mont) v = mont_mul(v, r2[r], q, qinv[r]);
+    out[((size_t)blockIdx.z * L + r) * n + x] = v;
+}
+
+void k_lift(const Ctx& c, uint64_t* out, const uint32_t* in, int count, bool mont, hipStream_t st) {
+    hipLaunchKernelGGL(lift_kernel, ew_grid(c.n, c.L, count), dim3(EW_THREADS), 0, st, out, in,
+                       c.d_mods, c.d_qinv, c.d_r2, c.n, c.L, (uint32_t)c.p, mont ? 1 : 0);
+}
+
+__device__ __forceinline__ uint32_t mulmod_p(uint32_t a, uint32_t b, uint32_t p, double pinv) {
+    uint64_t x = (uint64_t)a * b;
+    uint64_t qt = (uint64_t)((double)x * pinv);
+    int64_t r = (int64_t)(x - qt * p);
+    if (r < 0) r += p;
+    if (r >= (int64_t)p) r -= p;
+    return (uint32_t)r;
+}
+
+// slot (row, m) of the diagonal (beta, gi, b): alpha^e mod p with
+// alpha = beta nh + ((m + b) mod nh) + 1, e = ((m - gi B) mod s) + 1; written
+// at its NTT-mod-p position.
+__global__ void diag_gen_kernel(uint32_t* out, const uint32_t* params, const uint32_t* posslot,
+                                int n, int nh, uint32_t p, uint32_t s, uint32_t B) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const uint32_t* pr = params + 3 * blockIdx.z;
+    uint32_t beta = pr[0], gi = pr[1], b = pr[2];
+    uint32_t m = posslot[x] % nh;  // column (both rows equal)
+    uint64_t alpha = ((uint64_t)beta * nh + ((m + b) % nh) + 1) % p;
+    uint32_t e = ((m + s * (uint32_t)nh - (gi * B) % s) % s) + 1;
+    double pinv = 1.0 / (double)p;
+    uint32_t base = (uint32_t)alpha, acc = 1;
+    while (e) {
+        if (e & 1) acc = mulmod_p(acc, base, p, pinv);
+        base = mulmod_p(base, base, p, pinv);
+        e >>= 1;
+    }
+    out[(size_t)blockIdx.z * n + x] = acc;
+}
+
+void k_diag_gen(const Ctx& c, uint32_t* out, const uint32_t* params, int count, uint32_t s,
+                uint32_t B, hipStream_t st) {
+    hipLaunchKernelGGL(diag_gen_kernel, ew_grid(c.n, 1, count), dim3(EW_THREADS), 0, st, out, params,
+                       c.d_posslot, c.n, c.nh, (uint32_t)c.p, s, B);
+}
+
+// ------------------------------------------------------------------ encryption helpers
+
+__global__ void enc_finish_kernel(uint64_t* ct, const uint64_t* e0, const uint64_t* e1,
+                                  const uint32_t* m, const uint64_t* mods, const uint64_t* delta,
+                                  int n, int L) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    int r = blockIdx.y;
+    uint64_t q = mods[r];
+    size_t o = (size_t)r * n + x;
+    uint64_t dm = shoup((uint64_t)m[x], delta[2 * r], delta[2 * r + 1], q);
+    ct[o] = add_mod(add_mod(ct[o], e0[o], q), dm, q);
+    ct[(size_t)L * n + o] = add_mod(ct[(size_t)L * n + o], e1[o], q);
+}
+
+void k_enc_finish(const Ctx& c, uint64_t* ct, const uint64_t* e0, const uint64_t* e1,
+                  const uint32_t* m, hipStream_t st) {
+    hipLaunchKernelGGL(enc_finish_kernel, ew_grid(c.n, c.L), dim3(EW_THREADS), 0, st, ct, e0, e1, m,
+                       c.d_mods, c.d_delta, c.n, c.L);
+}
+
+// out = e - a s + g sigma(s)   (s, sigma(s) in Montgomery form; g per row or none)
+__global__ void keyrow_kernel(uint64_t* out, const uint64_t* e, const uint64_t* a,
+                              const uint64_t* s_mont, const uint64_t* rs_mont, const uint64_t* grow,
+                              const uint64_t* mods, const uint64_t* qinv, int n, int lf) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    int rr = blockIdx.y, r = lf + rr;
+    uint64_t q = mods[r], qi = qinv[r];
+    size_t o = (size_t)rr * n + x;
+    uint64_t v = sub_mod(e[o], mont_mul(a[o], s_mont[(size_t)r * n + x], q, qi), q);
+    if (grow != nullptr && grow[r] != 0)
+        v = add_mod(v, mont_mul(grow[r], rs_mont[(size_t)r * n + x], q, qi), q);
+    out[o] = v;
+}
+
+void k_keyrow(const Ctx& c, uint64_t* out, const uint64_t* e, const uint64_t* a,
+              const uint64_t* s_mont, const uint64_t* rot_s_mont, const uint64_t* grow, int lf, int nl,
+              hipStream_t st) {
+    hipLaunchKernelGGL(keyrow_kernel, ew_grid(c.n, nl), dim3(EW_THREADS), 0, st, out, e, a, s_mont,
+                       rot_s_mont, grow, c.d_mods, c.d_qinv, c.n, lf);
+}
+
+// ------------------------------------------------------------------ SHAKE-128 samplers (FIPS 202)
+
+__constant__ uint64_t c_keccak_rc[24];
+__constant__ uint32_t c_keccak_rho[25];
+__constant__ uint32_t c_cdt[20];
+
+__device__ __forceinline__ uint64_t rotl64(uint64_t x, uint32_t r) {
+    return r == 0 ? x : ((x << r) | (x >> (64 - r)));
+}
+
+// Keccak-f[1600]: lanes A[x + 5y]; theta, rho+pi, chi, iota per round.
+__device__ void keccak_f1600(uint64_t A[25]) {
+    for (int round = 0; round < 24; round++) {
+        uint64_t C[5], D[5], Bm[25];
+        #pragma unroll
+        for (int x = 0; x < 5; x++) C[x] = A[x] ^ A[x + 5] ^ A[x + 10] ^ A[x + 15] ^ A[x + 20];
+        #pragma unroll
+        for (int x = 0; x < 5; x++) D[x] = C[(x + 4) % 5] ^ rotl64(C[(x + 1) % 5], 1);
+        #pragma unroll
+        for (int i = 0; i < 25; i++) A[i] ^= D[i % 5];
+        #pragma unroll
+        for (int x = 0; x < 5; x++)
+            #pragma unroll
+            for (int y = 0; y < 5; y++)
+                Bm[y + 5 * ((2 * x + 3 * y) % 5)] = rotl64(A[x + 5 * y], c_keccak_rho[x + 5 * y]);
+        #pragma unroll
+        for (int x = 0; x < 5; x++)
+            #pragma unroll
+            for (int y = 0; y < 5; y++)
+                A[x + 5 * y] = Bm[x + 5 * y] ^ (~Bm[(x + 1) % 5 + 5 * y] & Bm[(x + 2) % 5 + 5 * y]);
+        A[0] ^= c_keccak_rc[round];
+    }
+}
+
+struct Seed32 { uint64_t w[4]; };
+
+// SHAKE-128 of seed || tag || le64(obj) || le64(limb) || le64(block): the
+// 64-byte message fits one 168-byte rate block.
+struct Shake {
+    uint64_t A[25];
+    int pos;
+    __device__ void init(const Seed32& sd, uint64_t tag, uint64_t obj, uint64_t limb, uint64_t block) {
+        #pragma unroll
+        for (int i = 0; i < 25; i++) A[i] = 0;
+        A[0] = sd.w[0]; A[1] = sd.w[1]; A[2] = sd.w[2]; A[3] = sd.w[3];
+        A[4] = tag; A[5] = obj; A[6] = limb; A[7] = block;
+        A[8] ^= 0x1Full;                  // SHAKE domain bits + first pad bit
+        A[20] ^= 0x8000000000000000ull;   // last pad bit at byte 167
+        keccak_f1600(A);
+        pos = 0;
+    }
+    __device__ uint64_t next_lane() {
+        if (pos == 21) { keccak_f1600(A); pos = 0; }
+        return A[pos++];
+    }
+};
+
+// x mod q for a 64-bit x (q < 2^62): quotient estimate in double, corrected.
+__device__ __forceinline__ uint64_t mod64(uint64_t x, uint64_t q) {
+    uint64_t est = (uint64_t)((double)x / (double)q);
+    int64_t r = (int64_t)(x - est * q);
+    while (r < 0) r += (int64_t)q;
+    while (r >= (int64_t)q) r -= (int64_t)q;
+    return (uint64_t)r;
+}
+
+__global__ void sample_uniform_kernel(uint64_t* out, Seed32 sd, uint64_t tag, uint64_t obj, int lf,
+                                      int n, const uint64_t* mods, const uint64_t* qinv,
+                                      const uint64_t* r2) {
+    const int nblk = n / 256;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nblk) return;
+    const int row = blockIdx.y;
+    const int prime = lf + row;
+    const uint64_t q = mods[prime];
+    Shake sh;
+    sh.init(sd, tag, obj, (uint64_t)prime, (uint64_t)t);
+    uint64_t* o = out + (size_t)row * n + (size_t)t * 256;
+    for (int c = 0; c < 256; c++) {
+        uint64_t lo = sh.next_lane();
+        uint64_t hi = sh.next_lane();
+        // (hi 2^64 + lo) mod q = (hi mod q) 2^64 + lo mod q
+        uint64_t h = mont_mul(mod64(hi, q), r2[prime], q, qinv[prime]);
+        o[c] = add_mod(h, mod64(lo, q), q);
+    }
+}
+
+void k_sample_uniform(const Ctx& c, uint64_t* out, const uint8_t* seed, uint64_t tag, uint64_t obj,
+                      int lf, int nl, hipStream_t st) {
+    Seed32 sd;
+    std::memcpy(sd.w, seed, 32);
+    int nblk = c.n / 256;
+    hipLaunchKernelGGL(sample_uniform_kernel, dim3((nblk + 63) / 64, nl), dim3(64), 0, st, out, sd,
+                       tag, obj, lf, c.n, c.d_mods, c.d_qinv, c.d_r2);
+}
+
+__global__ void sample_small_kernel(uint64_t* out, int64_t* raw, Seed32 sd, uint64_t tag,
+                                    uint64_t obj, int kind, int lf, int nl, int n,
+                                    const uint64_t* mods) {
+    const int nblk = n / 256;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nblk) return;
+    Shake sh;
+    sh.init(sd, tag, obj, ~0ull, (uint64_t)t);
+    uint64_t lane = 0;
+    for (int c = 0; c < 256; c++) {
+        int64_t v;
+        if (kind == 1) {  // ternary: 4 bytes per coefficient
+            if ((c & 1) == 0) lane = sh.next_lane();
+            uint64_t w = (c & 1) ? (lane >> 32) : (lane & 0xffffffffull);
+            v = (int64_t)((3ull * w) >> 32) - 1;
+        } else {          // Gaussian: 8 bytes per coefficient
+            lane = sh.next_lane();
+            uint32_t r = (uint32_t)lane;
+            uint32_t neg = (uint32_t)(lane >> 32) & 1u;
+            int mag = 0;
+            for (int k = 0; k < 19; k++) mag += (r >= c_cdt[k]) ? 1 : 0;
+            v = neg ? -mag : mag;
+        }
+        size_t idx = (size_t)t * 256 + c;
+        if (raw) raw[idx] = v;
+        for (int rr = 0; rr < nl; rr++) {
+            uint64_t q = mods[lf + rr];
+            out[(size_t)rr * n + idx] = v < 0 ? q - (uint64_t)(-v) : (uint64_t)v;
+        }
+    }
+}
+
+void k_sample_small(const Ctx& c, uint64_t* out, int64_t* raw, const uint8_t* seed, uint64_t tag,
+                    uint64_t obj, int kind, int lf, int nl, hipStream_t st) {
+    Seed32 sd;
+    std::memcpy(sd.w, seed, 32);
+    int nblk = c.n / 256;
+    hipLaunchKernelGGL(sample_small_kernel, dim3((nblk + 63) / 64), dim3(64), 0, st, out, raw, sd,
+                       tag, obj, kind, lf, nl, c.n, c.d_mods);
+}
+
+hc_status upload_keccak_constants(const uint64_t rc[24], const uint32_t rho[25], const uint32_t cdt[20]) {
+    HC_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_keccak_rc), rc, sizeof(uint64_t) * 24));
+    HC_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_keccak_rho), rho, sizeof(uint32_t) * 25));
+    HC_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_cdt), cdt, sizeof(uint32_t) * 20));
+    return HC_OK;
+}
+
+// ------------------------------------------------------------------ diagonal multiply-accumulate
+
+// A[pp][g] = (A[pp][g] +) sum_{beta, b} D[beta][g][b] * R[pp][beta][b], per
+// (row, coefficient). Each thread keeps GC giant accumulators (both
+// ciphertext components) as 128-bit sums, folded through a Montgomery
+// reduction every `chunk` terms, and reads each R value once per GC giants.
+template <int GC>
+__global__ void diag_mac_kernel(uint64_t* const* __restrict__ A, const uint64_t* const* __restrict__ R,
+                                const uint64_t* __restrict__ D, const uint64_t* __restrict__ mods,
+                                const uint64_t* __restrict__ qinv, int n, int L, int kb, int G, int B,
+                                int g0, int chunk, int accumulate) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int r = blockIdx.y;
+    const int pp = blockIdx.z;
+    const uint64_t q = mods[r], qi = qinv[r];
+    const size_t ln = (size_t)L * n;
+    const size_t off = (size_t)r * n + x;
+    const int gc = (G - g0) < GC ? (G - g0) : GC;
+
+    u128p acc0[GC], acc1[GC];
+    uint64_t sum0[GC], sum1[GC];
+    #pragma unroll
+    for (int g = 0; g < GC; g++) { acc0[g] = u128p{0, 0}; acc1[g] = u128p{0, 0}; sum0[g] = 0; sum1[g] = 0; }
+    int terms = 0;
+    for (int beta = 0; beta < kb; beta++) {
+        for (int b = 0; b < B; b++) {
+            const uint64_t* rp = R[((size_t)pp * kb + beta) * B + b];
+            if (rp == nullptr) continue;
+            uint64_t r0 = rp[off], r1 = rp[ln + off];
+            const uint64_t* dp = D + (((size_t)beta * G + g0) * B + b) * ln + off;
+            #pragma unroll
+            for (int g = 0; g < GC; g++) {
+                if (g < gc) {
+                    uint64_t d = dp[(size_t)g * B * ln];
+                    add128(acc0[g], mul128(r0, d));
+                    add128(acc1[g], mul128(r1, d));
+                }
+            }
+            if (++terms == chunk) {
+                #pragma unroll
+                for (int g = 0; g < GC; g++) {
+                    sum0[g] = add_mod(sum0[g], redc(acc0[g], q, qi), q);
+                    sum1[g] = add_mod(sum1[g], redc(acc1[g], q, qi), q);
+                    acc0[g] = u128p{0, 0};
+                    acc1[g] = u128p{0, 0};
+                }
+                terms = 0;
+            }
+        }
+    }
+    #pragma unroll
+    for (int g = 0; g < GC; g++) {
+        if (g < gc) {
+            uint64_t v0 = add_mod(sum0[g], redc(acc0[g], q, qi), q);
+            uint64_t v1 = add_mod(sum1[g], redc(acc1[g], q, qi), q);
+            uint64_t* ap = A[(size_t)pp * G + g0 + g];
+            if (accumulate) {
+                v0 = add_mod(v0, ap[off], q);
+                v1 = add_mod(v1, ap[ln + off], q);
+            }
+            ap[off] = v0;
+            ap[ln + off] = v1;
+        }
+    }
+}
+
+void k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* const* R, const uint64_t* D,
+                int npairs, int kb, int G, int B, bool accumulate, hipStream_t st) {
+    // terms per 128-bit accumulator before it must be folded: t q^2 < q 2^64
+    uint64_t qmax = 0;
+    for (int i = 0; i < c.L; i++) qmax = qmax > c.primes[i] ? qmax : c.primes[i];
+    uint64_t chunk = (~0ull) / qmax;
+    if (chunk > 1024) chunk = 1024;
+    if (chunk < 1) chunk = 1;
+    constexpr int GC = 4;
+    for (int g0 = 0; g0 < G; g0 += GC) {
+        hipLaunchKernelGGL((diag_mac_kernel<GC>), ew_grid(c.n, c.L, npairs), dim3(EW_THREADS), 0, st,
+                           A, R, D, c.d_mods, c.d_qinv, c.n, c.L, kb, G, B, g0, (int)chunk,
+                           accumulate ? 1 : 0);
+    }
+}
+
+}  // namespace hc

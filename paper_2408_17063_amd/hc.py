@@ -1,0 +1,361 @@
+"""Python binding of libhc (include/hc.h, include/hc_kernels.h).
+
+Argument marshalling only: every operation runs in the library's HIP kernels
+(or, for decryption and decompression, its host C++). Device buffers are torch
+tensors (int64, reinterpreted as uint64 residues) on the GPU; streams are
+torch's current stream. There is no fallback: if libhc.so cannot be loaded,
+importing this module raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libhc.so is not built (run paper_2408_17063_amd.build.build())")
+# torch first: libhc.so links the HIP runtime torch ships, which must be the one
+# loaded (and initialised) in this process
+import torch  # noqa: E402,F401
+_lib = ctypes.CDLL(LIB_PATH)
+
+c_u8p = ctypes.POINTER(ctypes.c_uint8)
+c_u32p = ctypes.POINTER(ctypes.c_uint32)
+c_u64p = ctypes.POINTER(ctypes.c_uint64)
+c_i64p = ctypes.POINTER(ctypes.c_int64)
+c_vp = ctypes.c_void_p
+
+HC_OK, HC_EINVAL, HC_ENOMEM, HC_EDEVICE, HC_ENOKEY, HC_EDECODE, HC_ENOISE = 0, -1, -2, -3, -4, -5, -6
+
+
+class HcError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        msg = _lib.hc_status_str(status).decode()
+        super().__init__("%s: %s (%d)" % (what, msg, status))
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_uint32), ("p", ctypes.c_uint64), ("L", ctypes.c_uint32),
+                ("q_bits", ctypes.c_uint32), ("K", ctypes.c_uint32), ("p_bits", ctypes.c_uint32)]
+
+
+class CompressInfo(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_uint32), ("groups", ctypes.c_uint32), ("streams", ctypes.c_uint32),
+                ("bands", ctypes.c_uint32), ("n_ct", ctypes.c_uint32),
+                ("n_keyswitch", ctypes.c_uint32), ("n_ptct", ctypes.c_uint64),
+                ("n_diag", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Query(ctypes.Structure):
+    _fields_ = [("ct_v", c_vp), ("N", ctypes.c_uint64), ("t_bound", ctypes.c_uint32),
+                ("ct_out", c_vp), ("info", ctypes.POINTER(CompressInfo)), ("status", ctypes.c_int)]
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_st = ctypes.c_int
+_sig("hc_status_str", ctypes.c_char_p, _st)
+_sig("hc_context_create", _st, ctypes.POINTER(Params), ctypes.c_int, ctypes.POINTER(c_vp))
+_sig("hc_context_destroy", None, c_vp)
+_sig("hc_context_primes", _st, c_vp, c_u64p)
+_sig("hc_keygen", _st, c_vp, c_u8p, ctypes.POINTER(c_vp), ctypes.POINTER(c_vp))
+_sig("hc_sk_destroy", None, c_vp)
+_sig("hc_pk_destroy", None, c_vp)
+_sig("hc_galois_keygen", _st, c_vp, c_vp, c_u32p, ctypes.c_uint32, c_u8p, ctypes.POINTER(c_vp))
+_sig("hc_gk_destroy", None, c_vp)
+_sig("hc_plan", _st, c_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, c_u32p,
+     ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(CompressInfo))
+_sig("hc_db_upload", _st, c_vp, c_u32p, ctypes.c_uint32, ctypes.c_uint64, ctypes.POINTER(c_vp))
+_sig("hc_db_destroy", None, c_vp)
+_sig("hc_encrypt", _st, c_vp, c_vp, c_u32p, c_u8p, c_vp, c_vp)
+_sig("hc_compress", _st, c_vp, c_vp, c_vp, c_vp, ctypes.c_uint64, ctypes.c_uint32, c_vp,
+     ctypes.POINTER(CompressInfo), c_vp)
+_sig("hc_compress_batch", _st, c_vp, c_vp, c_vp, ctypes.POINTER(Query), ctypes.c_uint32, c_vp)
+_sig("hc_decrypt", _st, c_vp, c_vp, c_u64p, c_u32p)
+_sig("hc_decompress", _st, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+     c_u32p, c_u32p, c_u64p, c_u32p, c_u32p)
+_sig("hc_ntt", _st, c_vp, c_vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, c_vp)
+_sig("hc_rotate", _st, c_vp, c_vp, ctypes.c_uint32, c_vp, c_vp, c_vp)
+_sig("hc_rotate_hoisted", _st, c_vp, c_vp, c_u32p, ctypes.c_uint32, c_vp, c_vp, c_vp)
+_sig("hc_mul_plain", _st, c_vp, c_vp, c_u32p, c_vp, c_vp)
+_sig("hc_modup", _st, c_vp, c_vp, ctypes.c_uint32, c_vp, c_vp)
+_sig("hc_moddown", _st, c_vp, c_vp, c_vp, c_vp)
+_sig("hc_sample", _st, c_vp, ctypes.c_int, c_u8p, ctypes.c_char_p, ctypes.c_uint64, ctypes.c_uint32,
+     c_vp, c_vp)
+_sig("hc_encode_diagonal", _st, c_vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+     ctypes.c_uint32, ctypes.c_uint32, c_vp, c_vp)
+_sig("hc_export_sk", _st, c_vp, c_vp, c_i64p)
+_sig("hc_export_pk", _st, c_vp, c_vp, c_u64p)
+_sig("hc_export_gk", _st, c_vp, c_vp, ctypes.c_uint32, c_u64p)
+
+EXPORTED = [
+    "hc_status_str", "hc_context_create", "hc_context_destroy", "hc_context_primes", "hc_keygen",
+    "hc_sk_destroy", "hc_pk_destroy", "hc_galois_keygen", "hc_gk_destroy", "hc_plan",
+    "hc_db_upload", "hc_db_destroy", "hc_encrypt", "hc_compress", "hc_compress_batch",
+    "hc_decrypt", "hc_decompress", "hc_ntt", "hc_rotate", "hc_rotate_hoisted", "hc_mul_plain",
+    "hc_modup", "hc_moddown", "hc_sample", "hc_encode_diagonal", "hc_export_sk", "hc_export_pk",
+    "hc_export_gk",
+]
+
+
+def lib():
+    return _lib
+
+
+def _check(st, what):
+    if st != HC_OK:
+        raise HcError(st, what)
+
+
+def _u8(b):
+    assert len(b) == 32
+    return (ctypes.c_uint8 * 32).from_buffer_copy(b)
+
+
+def _np_ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _dev(t):
+    import torch
+    assert t.is_cuda and t.dtype == torch.int64 and t.is_contiguous()
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """A library context for one ring/modulus setting on one device."""
+
+    def __init__(self, log_n, p, L, q_bits, K, p_bits, device=0):
+        self.params = Params(log_n, p, L, q_bits, K, p_bits)
+        self.n = 1 << log_n
+        self.nh = self.n // 2
+        self.p, self.L, self.K = p, L, K
+        self.nq = L + K
+        self.dnum = L // K
+        self.device = device
+        h = c_vp()
+        _check(_lib.hc_context_create(ctypes.byref(self.params), device, ctypes.byref(h)),
+               "hc_context_create")
+        self.h = h
+        pr = np.zeros(L + K, dtype=np.uint64)
+        _check(_lib.hc_context_primes(self.h, _np_ptr(pr, ctypes.c_uint64)), "hc_context_primes")
+        self.primes = [int(x) for x in pr]
+
+    def close(self):
+        if self.h:
+            _lib.hc_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- torch helpers
+    def ct_tensor(self, count=1):
+        import torch
+        return torch.empty((count, 2, self.L, self.n), dtype=torch.int64, device="cuda:%d" % self.device)
+
+    # ---- keys
+    def keygen(self, seed):
+        sk, pk = c_vp(), c_vp()
+        _check(_lib.hc_keygen(self.h, _u8(seed), ctypes.byref(sk), ctypes.byref(pk)), "hc_keygen")
+        return SecretKey(self, sk), PublicKey(self, pk)
+
+    def galois_keygen(self, sk, elements, seed):
+        arr = np.asarray(elements, dtype=np.uint32)
+        gk = c_vp()
+        _check(_lib.hc_galois_keygen(self.h, sk.h, _np_ptr(arr, ctypes.c_uint32), len(arr), _u8(seed),
+                                     ctypes.byref(gk)), "hc_galois_keygen")
+        return GaloisKeys(self, gk, [int(x) for x in arr])
+
+    def plan(self, N, ncol, t_bound):
+        cnt = ctypes.c_uint32(0)
+        info = CompressInfo()
+        st = _lib.hc_plan(self.h, N, ncol, t_bound, None, ctypes.byref(cnt), ctypes.byref(info))
+        if st not in (HC_OK, HC_EINVAL) or (st == HC_EINVAL and cnt.value == 0):
+            _check(st, "hc_plan")
+        arr = np.zeros(max(cnt.value, 1), dtype=np.uint32)
+        cap = ctypes.c_uint32(len(arr))
+        _check(_lib.hc_plan(self.h, N, ncol, t_bound, _np_ptr(arr, ctypes.c_uint32), ctypes.byref(cap),
+                            ctypes.byref(info)), "hc_plan")
+        return [int(x) for x in arr[:cap.value]], info.as_dict()
+
+    def db_upload(self, cols):
+        cols = np.ascontiguousarray(cols, dtype=np.uint32)
+        ncol, N = (cols.shape[0], cols.shape[1]) if cols.ndim == 2 else (0, int(cols))
+        db = c_vp()
+        _check(_lib.hc_db_upload(self.h, _np_ptr(cols, ctypes.c_uint32), ncol, N, ctypes.byref(db)),
+               "hc_db_upload")
+        return Database(self, db, ncol, N)
+
+    def db_empty(self, N):
+        db = c_vp()
+        _check(_lib.hc_db_upload(self.h, None, 0, N, ctypes.byref(db)), "hc_db_upload")
+        return Database(self, db, 0, N)
+
+    # ---- encryption / compression
+    def encrypt(self, pk, slots, seed, out=None, stream=None):
+        sl = np.ascontiguousarray(slots, dtype=np.uint32).reshape(2, self.nh)
+        out = self.ct_tensor(1)[0] if out is None else out
+        _check(_lib.hc_encrypt(self.h, pk.h, _np_ptr(sl, ctypes.c_uint32), _u8(seed), _dev(out),
+                               _stream(stream)), "hc_encrypt")
+        return out
+
+    def compress(self, gk, db, ct_v, N, t_bound, out=None, stream=None):
+        out = self.ct_tensor(1)[0] if out is None else out
+        info = CompressInfo()
+        _check(_lib.hc_compress(self.h, gk.h, db.h if db is not None else None, _dev(ct_v), N, t_bound,
+                                _dev(out), ctypes.byref(info), _stream(stream)), "hc_compress")
+        return out, info.as_dict()
+
+    def compress_batch(self, gk, db, queries, stream=None):
+        """queries: list of (ct_v tensor, N, t_bound, out tensor)."""
+        arr = (Query * len(queries))()
+        infos = [CompressInfo() for _ in queries]
+        for i, (ctv, N, t, out) in enumerate(queries):
+            arr[i].ct_v = _dev(ctv).value
+            arr[i].N = N
+            arr[i].t_bound = t
+            arr[i].ct_out = _dev(out).value
+            arr[i].info = ctypes.pointer(infos[i])
+        st = _lib.hc_compress_batch(self.h, gk.h, db.h if db is not None else None, arr, len(queries),
+                                    _stream(stream))
+        return st, [arr[i].status for i in range(len(queries))], [x.as_dict() for x in infos]
+
+    def decrypt(self, sk, ct_host):
+        ct = np.ascontiguousarray(ct_host, dtype=np.uint64).reshape(2, self.L, self.n)
+        out = np.zeros((2, self.nh), dtype=np.uint32)
+        _check(_lib.hc_decrypt(self.h, sk.h, _np_ptr(ct, ctypes.c_uint64), _np_ptr(out, ctypes.c_uint32)),
+               "hc_decrypt")
+        return out
+
+    # ---- kernel-level
+    def ntt(self, data, limb_first, nlimbs, inverse=False, stream=None):
+        count = data.numel() // (nlimbs * self.n)
+        _check(_lib.hc_ntt(self.h, _dev(data), count, limb_first, nlimbs, 1 if inverse else 0,
+                           _stream(stream)), "hc_ntt")
+
+    def rotate(self, gk, element, ct_in, out=None, stream=None):
+        out = self.ct_tensor(1)[0] if out is None else out
+        _check(_lib.hc_rotate(self.h, gk.h, element, _dev(ct_in), _dev(out), _stream(stream)), "hc_rotate")
+        return out
+
+    def rotate_hoisted(self, gk, elements, ct_in, stream=None):
+        arr = np.asarray(elements, dtype=np.uint32)
+        out = self.ct_tensor(len(arr))
+        _check(_lib.hc_rotate_hoisted(self.h, gk.h, _np_ptr(arr, ctypes.c_uint32), len(arr), _dev(ct_in),
+                                      _dev(out), _stream(stream)), "hc_rotate_hoisted")
+        return out
+
+    def mul_plain(self, ct_in, slots, out=None, stream=None):
+        sl = np.ascontiguousarray(slots, dtype=np.uint32).reshape(2, self.nh)
+        out = self.ct_tensor(1)[0] if out is None else out
+        _check(_lib.hc_mul_plain(self.h, _dev(ct_in), _np_ptr(sl, ctypes.c_uint32), _dev(out),
+                                 _stream(stream)), "hc_mul_plain")
+        return out
+
+    def modup(self, x, digit, out, stream=None):
+        _check(_lib.hc_modup(self.h, _dev(x), digit, _dev(out), _stream(stream)), "hc_modup")
+
+    def moddown(self, T, out, stream=None):
+        _check(_lib.hc_moddown(self.h, _dev(T), _dev(out), _stream(stream)), "hc_moddown")
+
+    def sample(self, kind, seed, tag, obj, limb, out, stream=None):
+        _check(_lib.hc_sample(self.h, kind, _u8(seed), tag.encode(), obj, limb, _dev(out), _stream(stream)),
+               "hc_sample")
+
+    def encode_diagonal(self, s, B, beta, gi, b, out, stream=None):
+        _check(_lib.hc_encode_diagonal(self.h, s, B, beta, gi, b, _dev(out), _stream(stream)),
+               "hc_encode_diagonal")
+
+    def export_sk(self, sk):
+        out = np.zeros(self.n, dtype=np.int64)
+        _check(_lib.hc_export_sk(self.h, sk.h, _np_ptr(out, ctypes.c_int64)), "hc_export_sk")
+        return out
+
+    def export_pk(self, pk):
+        out = np.zeros((2, self.L, self.n), dtype=np.uint64)
+        _check(_lib.hc_export_pk(self.h, pk.h, _np_ptr(out, ctypes.c_uint64)), "hc_export_pk")
+        return out
+
+    def export_gk(self, gk, element):
+        out = np.zeros((self.dnum, 2, self.nq, self.n), dtype=np.uint64)
+        _check(_lib.hc_export_gk(self.h, gk.h, element, _np_ptr(out, ctypes.c_uint64)), "hc_export_gk")
+        return out
+
+
+def decompress(p, N_group, s, w, es):
+    """Decomp for one group: (indices 1-based ascending, values [ncols][count])."""
+    w = np.ascontiguousarray(w, dtype=np.uint32)
+    es = np.ascontiguousarray(es, dtype=np.uint32).reshape(-1, s) if len(es) else np.zeros((0, s), np.uint32)
+    ncols = es.shape[0]
+    idx = np.zeros(s, dtype=np.uint64)
+    vals = np.zeros((max(ncols, 1), s), dtype=np.uint32)
+    cnt = ctypes.c_uint32(0)
+    _check(_lib.hc_decompress(p, N_group, s, ncols, _np_ptr(w, ctypes.c_uint32),
+                              _np_ptr(es, ctypes.c_uint32) if ncols else None, _np_ptr(idx, ctypes.c_uint64),
+                              _np_ptr(vals, ctypes.c_uint32) if ncols else None, ctypes.byref(cnt)),
+           "hc_decompress")
+    l = cnt.value
+    return [int(x) for x in idx[:l]], [[int(x) for x in vals[c, :l]] for c in range(ncols)]
+
+
+class _Handle:
+    _destroy = None
+
+    def __init__(self, ctx, h):
+        self.ctx, self.h = ctx, h
+
+    def close(self):
+        if self.h and self.ctx.h:
+            getattr(_lib, self._destroy)(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SecretKey(_Handle):
+    _destroy = "hc_sk_destroy"
+
+
+class PublicKey(_Handle):
+    _destroy = "hc_pk_destroy"
+
+
+class GaloisKeys(_Handle):
+    _destroy = "hc_gk_destroy"
+
+    def __init__(self, ctx, h, elements):
+        super().__init__(ctx, h)
+        self.elements = elements
+
+
+class Database(_Handle):
+    _destroy = "hc_db_destroy"
+
+    def __init__(self, ctx, h, ncol, N):
+        super().__init__(ctx, h)
+        self.ncol, self.N = ncol, N

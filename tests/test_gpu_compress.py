@@ -1,0 +1,120 @@
+"""GPU parity of the whole compression (Mask + Comp, Alg. 7) against the oracle.
+
+Small workloads: the output ciphertext is compared bit for bit with the
+oracle's, and both decrypt to the plain Vandermonde products (Eq. (1)) that
+decompress (Alg. 6) back to every matched record. Full-size workloads (the
+oracle cannot run them whole): the library's output is decrypted and checked
+against the Vandermonde products computed from the definition, and
+decompressed exactly; per-operation parity at those sizes is covered by the
+kernel tests.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_common import context, oracle_params, to_dev, to_host, say
+
+pytestmark = pytest.mark.gpu
+
+
+def lib_run(wl_name, t=None, N=None, query=0, t_bound=None):
+    from oracle import compress as C, slots
+    wl = W.WORKLOADS[wl_name]
+    ctx = context(wl.ring)
+    N = wl.N if N is None else N
+    t_matches = wl.t if t is None else t
+    t = t_matches if t_bound is None else t_bound
+    v, db = W.query_inputs(wl, query=query, t=t_matches, N=N)
+    keys, info = ctx.plan(N, wl.ncol, t)
+    sk_seed, gk_seed = W.seed32("sk", 0), W.seed32("gk", 0)
+    sk, pk = ctx.keygen(sk_seed)
+    gk = ctx.galois_keygen(sk, keys, gk_seed)
+    dbh = ctx.db_upload(db[:, :N]) if wl.ncol else ctx.db_empty(N)
+    n_ct = -(-N // ctx.n)
+    vm = slots.vector_to_slot_matrices(v, ctx.n, n_ct)
+    cts = ctx.ct_tensor(n_ct)
+    for i in range(n_ct):
+        ctx.encrypt(pk, vm[i], W.seed32("enc", query, i), out=cts[i])
+    out, info = ctx.compress(gk, dbh, cts, N, t)
+    return dict(ctx=ctx, sk=sk, pk=pk, gk=gk, db=dbh, v=v, dbv=db, cts=cts, out=out, info=info,
+                keys=keys, N=N, t=t, wl=wl)
+
+
+def check_decrypts(run):
+    from oracle import compress as C
+    from paper_2408_17063_amd import hc
+    ctx, wl = run["ctx"], run["wl"]
+    sched = C.make_schedule(ctx.n, ctx.p, run["N"], wl.ncol, run["t"])
+    dec = ctx.decrypt(run["sk"], to_host(run["out"]))
+    exp = C.expected_bands(sched, run["v"], run["dbv"])
+    for b in range(sched.bands):
+        assert C.band_slots(sched, dec, b) == exp[b], b
+    S = len(sched.streams)
+    for gi, grp in enumerate(sched.groups):
+        rows = []
+        for st in range(S):
+            rows += list(C.band_slots(sched, dec, gi * S + st))
+        idx, vals = hc.decompress(ctx.p, grp.n_rec, sched.s, rows[0], rows[1:1 + wl.ncol])
+        seg = run["v"][grp.rec_start:grp.rec_start + grp.n_rec]
+        want = [int(i) + 1 for i in np.nonzero(seg)[0]]
+        assert idx == want
+        for c in range(wl.ncol):
+            assert vals[c] == [int(run["dbv"][c][grp.rec_start + i - 1]) % ctx.p for i in want]
+    return sched
+
+
+@pytest.mark.parametrize("wl_name", ["tiny-1024", "plain-4096", "multi-2048"])
+def test_compress_bit_identical_to_oracle(wl_name):
+    from oracle import bfv, compress as C, slots
+    say("compress parity", wl_name)
+    run = lib_run(wl_name)
+    wl = run["wl"]
+    pr = oracle_params(wl.ring)
+    sched = C.make_schedule(pr.n, pr.p, wl.N, wl.ncol, wl.t)
+    assert sorted(run["keys"]) == sched.keys
+    osk, opk = bfv.keygen(pr, W.seed32("sk", 0))
+    gks = {k: bfv.galois_keygen(pr, osk, k, W.seed32("gk", 0)) for k in sched.keys}
+    vm = slots.vector_to_slot_matrices(run["v"], pr.n, sched.n_ct)
+    octs = [bfv.encrypt(pr, opk, vm[i], W.seed32("enc", 0, i)) for i in range(sched.n_ct)]
+    for i in range(sched.n_ct):
+        assert np.array_equal(to_host(run["cts"][i]), octs[i].stack()), i
+    want = C.compress(pr, sched, octs, run["dbv"], gks)
+    got = to_host(run["out"])
+    assert np.array_equal(got, want.stack())
+    # decryption on the library's host path agrees with the oracle's
+    assert np.array_equal(run["ctx"].decrypt(run["sk"], got), bfv.decrypt(pr, osk, want))
+    check_decrypts(run)
+    assert run["info"]["bands"] == sched.bands and run["info"]["s"] == sched.s
+
+
+def test_compress_edge_cases():
+    """No matches; a single match; t equal to a power of two; a partly filled last ciphertext."""
+    say("edge cases")
+    for t_actual, t_bound, N in [(0, 1, 1024), (1, 1, 1024), (8, 8, 1024), (3, 4, 700)]:
+        run = lib_run("tiny-1024", t=t_actual, N=N, t_bound=t_bound)
+        check_decrypts(run)
+
+
+@pytest.mark.parametrize("wl_name", ["single-32768"])
+def test_full_size_decrypts_to_vandermonde(wl_name):
+    say("full size", wl_name)
+    run = lib_run(wl_name)
+    check_decrypts(run)
+
+
+def test_missing_key_and_bad_shapes():
+    from paper_2408_17063_amd import hc
+    ctx = context("ring-1024-p12289")
+    say("errors")
+    sk, pk = ctx.keygen(W.seed32("sk", 5))
+    keys, _ = ctx.plan(1024, 1, 5)
+    gk = ctx.galois_keygen(sk, keys[1:], W.seed32("gk", 5))
+    db = ctx.db_upload(np.zeros((1, 1024), dtype=np.uint32))
+    cts = ctx.ct_tensor(1)
+    ctx.encrypt(pk, np.zeros((2, ctx.nh)), W.seed32("enc", 5), out=cts[0])
+    with pytest.raises(hc.HcError) as e:
+        ctx.compress(gk, db, cts, 1024, 5)
+    assert e.value.status == hc.HC_ENOKEY
+    with pytest.raises(hc.HcError) as e:
+        ctx.plan(1024, 4, 300)  # 3 bands x 512 slots > 512
+    assert e.value.status == hc.HC_EINVAL
