@@ -85,6 +85,34 @@ hc_status hc_export_sk(hc_context* ctx, const hc_sk* sk, int64_t* out);
 hc_status hc_export_pk(hc_context* ctx, const hc_pk* pk, uint64_t* out);
 hc_status hc_export_gk(hc_context* ctx, const hc_gk* gk, uint32_t element, uint64_t* out);
 
+/* ------------------------------------------------------------------ measurement
+ * Kernel timing: while enabled, each launch of a kernel of the given class is
+ * bracketed by HIP events recorded on the stream it is launched on, so the
+ * totals are device time of exactly those launches. Classes: */
+enum {
+    HC_KT_NTT_FWD = 0,   /* forward NTT passes (64-bit primes) */
+    HC_KT_NTT_INV = 1,   /* inverse NTT passes (64-bit primes) */
+    HC_KT_KS_INNER = 2,  /* key-switch inner product with the Galois key */
+    HC_KT_DIAG_MAC = 3,  /* diagonal multiply-accumulate */
+    HC_KT_MODUP = 4,     /* ModUp basis conversion */
+    HC_KT_COUNT = 5
+};
+
+/* Start (enable = 1) or stop timing; starting clears the totals. */
+hc_status hc_timing_enable(hc_context* ctx, int enable);
+
+/* Totals since timing was enabled for class `kind`: device milliseconds,
+ * launches, and the class's algorithmic work summed over those launches
+ * (work_bytes: bytes the kernels must read and write; work_ops: butterflies
+ * for the NTT classes, modular multiply-adds otherwise). Synchronises. */
+hc_status hc_timing_read(hc_context* ctx, int kind, double* total_ms, uint64_t* launches,
+                         double* work_bytes, double* work_ops);
+
+/* Throughput probe: runs a register-only kernel of independent 32 x 32 -> 64-bit
+ * multiply-adds on every compute unit for about `ms` milliseconds and returns
+ * the measured rate in multiply-adds per second (device-wide). */
+hc_status hc_probe_mul32_rate(hc_context* ctx, double ms, double* rate_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -381,3 +381,67 @@ extern "C" const char* hc_status_str(hc_status s) {
     }
     return "unknown status";
 }
+
+// ------------------------------------------------------------------ kernel timing
+
+namespace hc {
+
+static hipEvent_t pool_get(const hc_context& c) {
+    if (!c.event_pool.empty()) {
+        hipEvent_t e = c.event_pool.back();
+        c.event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+TimeScope::TimeScope(const hc_context& c_, int kind_, hipStream_t st_, double bytes_, double ops_)
+    : c(c_), kind(kind_), st(st_), bytes(bytes_), ops(ops_) {
+    if (!c.timing) return;
+    a = pool_get(c);
+    b = pool_get(c);
+    if (a && b) (void)hipEventRecord(a, st);
+}
+
+TimeScope::~TimeScope() {
+    if (!c.timing || !a || !b) return;
+    (void)hipEventRecord(b, st);
+    c.tlaunches.push_back({kind, a, b, bytes, ops});
+}
+
+}  // namespace hc
+
+extern "C" hc_status hc_timing_enable(hc_context* c, int enable) {
+    if (!c) return HC_EINVAL;
+    HC_CHECK(hipSetDevice(c->device));
+    HC_CHECK(hipDeviceSynchronize());
+    for (auto& t : c->tlaunches) { c->event_pool.push_back(t.a); c->event_pool.push_back(t.b); }
+    c->tlaunches.clear();
+    c->timing = enable != 0;
+    return HC_OK;
+}
+
+extern "C" hc_status hc_timing_read(hc_context* c, int kind, double* total_ms, uint64_t* launches,
+                                    double* work_bytes, double* work_ops) {
+    if (!c || kind < 0 || kind >= HC_KT_COUNT) return HC_EINVAL;
+    HC_CHECK(hipSetDevice(c->device));
+    HC_CHECK(hipDeviceSynchronize());
+    double ms = 0, by = 0, op = 0;
+    uint64_t cnt = 0;
+    for (auto& t : c->tlaunches) {
+        if (t.kind != kind) continue;
+        float e = 0;
+        HC_CHECK(hipEventElapsedTime(&e, t.a, t.b));
+        ms += e;
+        by += t.bytes;
+        op += t.ops;
+        cnt++;
+    }
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = cnt;
+    if (work_bytes) *work_bytes = by;
+    if (work_ops) *work_ops = op;
+    return HC_OK;
+}

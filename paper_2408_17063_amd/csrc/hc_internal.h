@@ -81,6 +81,12 @@ struct hc_context {
 
     hc::Arena ws;      // per-call workspace
     std::vector<void*> owned;  // device allocations freed at destroy
+
+    // kernel timing (measurement only)
+    struct TimedLaunch { int kind; hipEvent_t a, b; double bytes, ops; };
+    bool timing = false;
+    mutable std::vector<TimedLaunch> tlaunches;
+    mutable std::vector<hipEvent_t> event_pool;
 };
 
 struct hc_sk {
@@ -108,6 +114,17 @@ struct hc_db {
 namespace hc {
 
 using Ctx = hc_context;
+
+// Brackets one kernel launch with events when timing is enabled.
+struct TimeScope {
+    const hc_context& c;
+    int kind;
+    hipStream_t st;
+    double bytes, ops;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimeScope(const hc_context& c_, int kind_, hipStream_t st_, double bytes_, double ops_);
+    ~TimeScope();
+};
 
 // ------------------------------------------------------------------ NTT (ntt.hip)
 // data: `count` polynomials spaced poly_stride elements apart; data points at

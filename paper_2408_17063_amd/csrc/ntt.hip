@@ -185,31 +185,43 @@ ntt_pass_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, int lo
 }
 
 template <typename T, bool INVERSE>
-static void run_ntt(T* data, size_t poly_stride, int count, int limb_first, int nlimbs, int logn,
-                    NttTab<T> tab, hipStream_t stream) {
+static void run_ntt(const Ctx& c, T* data, size_t poly_stride, int count, int limb_first, int nlimbs,
+                    int logn, NttTab<T> tab, hipStream_t stream) {
     const int n = 1 << logn;
+    // timing class (64-bit transforms only), bytes moved and butterflies per pass
+    const int kind = sizeof(T) == 8 ? (INVERSE ? HC_KT_NTT_INV : HC_KT_NTT_FWD) : -1;
+    const double pass_bytes = 2.0 * sizeof(T) * (double)count * nlimbs * n;
+    auto bfly = [&](int S) { return (double)count * nlimbs * (n / 2) * S; };
     const size_t smem = sizeof(T) * (size_t)((logn < NTT_TILE_LOG) ? n : (1 << NTT_TILE_LOG));
     const int threads = ((logn < NTT_TILE_LOG) ? n : (1 << NTT_TILE_LOG)) / 16;
     if (logn <= NTT_TILE_LOG) {
         dim3 grid(1, nlimbs, count);
-        hipLaunchKernelGGL((ntt_pass_kernel<T, INVERSE>), grid, dim3(threads), smem, stream,
-                           data, poly_stride, limb_first, logn, 0, logn, 0, 1, tab);
+        if (kind >= 0) {
+            TimeScope ts(c, kind, stream, pass_bytes, bfly(logn));
+            hipLaunchKernelGGL((ntt_pass_kernel<T, INVERSE>), grid, dim3(threads), smem, stream,
+                               data, poly_stride, limb_first, logn, 0, logn, 0, 1, tab);
+        } else {
+            hipLaunchKernelGGL((ntt_pass_kernel<T, INVERSE>), grid, dim3(threads), smem, stream,
+                               data, poly_stride, limb_first, logn, 0, logn, 0, 1, tab);
+        }
         return;
     }
     const int S_lo = 8, S_hi = logn - 8;
     const int tiles = n >> NTT_TILE_LOG;
     dim3 grid(tiles, nlimbs, count);
-    if (!INVERSE) {
-        // stages 0..S_hi-1 on the high bits, then the low 8 bits
-        hipLaunchKernelGGL((ntt_pass_kernel<T, false>), grid, dim3(threads), smem, stream,
-                           data, poly_stride, limb_first, logn, S_lo, S_hi, 0, 0, tab);
-        hipLaunchKernelGGL((ntt_pass_kernel<T, false>), grid, dim3(threads), smem, stream,
-                           data, poly_stride, limb_first, logn, 0, S_lo, S_hi, 1, tab);
-    } else {
-        hipLaunchKernelGGL((ntt_pass_kernel<T, true>), grid, dim3(threads), smem, stream,
-                           data, poly_stride, limb_first, logn, 0, S_lo, 0, 0, tab);
-        hipLaunchKernelGGL((ntt_pass_kernel<T, true>), grid, dim3(threads), smem, stream,
-                           data, poly_stride, limb_first, logn, S_lo, S_hi, S_lo, 1, tab);
+    // pass 1 then pass 2: (blo, S, first stage, last pass?)
+    const int fwd[2][4] = {{S_lo, S_hi, 0, 0}, {0, S_lo, S_hi, 1}};
+    const int inv[2][4] = {{0, S_lo, 0, 0}, {S_lo, S_hi, S_lo, 1}};
+    for (int ps = 0; ps < 2; ps++) {
+        const int* a = INVERSE ? inv[ps] : fwd[ps];
+        if (kind >= 0) {
+            TimeScope ts(c, kind, stream, pass_bytes, bfly(a[1]));
+            hipLaunchKernelGGL((ntt_pass_kernel<T, INVERSE>), grid, dim3(threads), smem, stream,
+                               data, poly_stride, limb_first, logn, a[0], a[1], a[2], a[3], tab);
+        } else {
+            hipLaunchKernelGGL((ntt_pass_kernel<T, INVERSE>), grid, dim3(threads), smem, stream,
+                               data, poly_stride, limb_first, logn, a[0], a[1], a[2], a[3], tab);
+        }
     }
 }
 
@@ -217,15 +229,15 @@ void ntt64(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb
            bool inverse, hipStream_t stream) {
     if (count <= 0 || nlimbs <= 0) return;
     NttTab<uint64_t> tab{c.d_tw, c.d_ninv, c.d_mods};
-    if (inverse) run_ntt<uint64_t, true>(data, poly_stride, count, limb_first, nlimbs, c.logn, tab, stream);
-    else run_ntt<uint64_t, false>(data, poly_stride, count, limb_first, nlimbs, c.logn, tab, stream);
+    if (inverse) run_ntt<uint64_t, true>(c, data, poly_stride, count, limb_first, nlimbs, c.logn, tab, stream);
+    else run_ntt<uint64_t, false>(c, data, poly_stride, count, limb_first, nlimbs, c.logn, tab, stream);
 }
 
 void ntt32(const Ctx& c, uint32_t* data, int count, bool inverse, hipStream_t stream) {
     if (count <= 0) return;
     NttTab<uint32_t> tab{c.d_twp, c.d_ninvp, c.d_modp};
-    if (inverse) run_ntt<uint32_t, true>(data, (size_t)c.n, count, 0, 1, c.logn, tab, stream);
-    else run_ntt<uint32_t, false>(data, (size_t)c.n, count, 0, 1, c.logn, tab, stream);
+    if (inverse) run_ntt<uint32_t, true>(c, data, (size_t)c.n, count, 0, 1, c.logn, tab, stream);
+    else run_ntt<uint32_t, false>(c, data, (size_t)c.n, count, 0, 1, c.logn, tab, stream);
 }
 
 }  // namespace hc

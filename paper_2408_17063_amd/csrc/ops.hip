@@ -143,6 +143,9 @@ __global__ void modup_kernel(uint64_t* __restrict__ X, const uint64_t* __restric
 
 void k_modup(const Ctx& c, uint64_t* X, const uint64_t* x, int digit_first, int ndigits,
              hipStream_t st) {
+    const double n = c.n;
+    TimeScope ts(c, HC_KT_MODUP, st, 8.0 * n * ((double)ndigits * c.alpha + (double)ndigits * c.nq),
+                 n * ndigits * (double)(c.nq - c.alpha) * c.alpha);
     hipLaunchKernelGGL(modup_kernel, ew_grid(c.n, ndigits), dim3(EW_THREADS), 0, st, X, x, c.d_mods,
                        c.d_qinv, c.d_modup_inv, c.d_modup_c, c.n, c.nq, c.alpha, digit_first);
 }
@@ -172,6 +175,10 @@ __global__ void inner_kernel(uint64_t* __restrict__ T, const uint64_t* __restric
 
 void k_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const uint64_t* key, uint32_t k,
              hipStream_t st) {
+    // must read the key (dnum x 2 rows per prime) and the raised digits, write T
+    const double rows = (double)c.nq * c.n;
+    TimeScope ts(c, HC_KT_KS_INNER, st, 8.0 * rows * (2.0 * c.dnum + c.dnum + 2.0),
+                 2.0 * c.dnum * rows);
     hipLaunchKernelGGL(inner_kernel, ew_grid(c.n, c.nq), dim3(EW_THREADS), 0, st, T, X, key,
                        c.d_mods, c.d_qinv, c.n, c.logn, c.nq, c.dnum, k);
 }
@@ -562,10 +569,70 @@ void k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* const* R, cons
     if (chunk < 1) chunk = 1;
     constexpr int GC = 4;
     for (int g0 = 0; g0 < G; g0 += GC) {
+        const int gc = (G - g0) < GC ? (G - g0) : GC;
+        const double ln = (double)c.L * c.n;
+        // reads each R (both components) and each D once, writes each A once
+        TimeScope ts(c, HC_KT_DIAG_MAC, st,
+                     8.0 * ln * (2.0 * npairs * kb * B + (double)kb * gc * B +
+                                 (accumulate ? 4.0 : 2.0) * npairs * gc),
+                     2.0 * ln * npairs * kb * B * gc);
         hipLaunchKernelGGL((diag_mac_kernel<GC>), ew_grid(c.n, c.L, npairs), dim3(EW_THREADS), 0, st,
                            A, R, D, c.d_mods, c.d_qinv, c.n, c.L, kb, G, B, g0, (int)chunk,
                            accumulate ? 1 : 0);
     }
 }
 
+
+// ------------------------------------------------------------------ throughput probe
+
+// Eight independent chains of acc = lo32(acc) * b + acc per thread: each step is
+// one 32 x 32 -> 64-bit multiply-add (v_mad_u64_u32); registers only.
+__global__ void probe_mul32_kernel(uint64_t* sink, uint32_t iters) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t b = tid * 2654435761u + 12345u;
+    uint64_t acc[8];
+    #pragma unroll
+    for (int k = 0; k < 8; k++) acc[k] = (uint64_t)(tid + k) * 0x9E3779B97F4A7C15ull;
+    for (uint32_t i = 0; i < iters; i++) {
+        #pragma unroll
+        for (int k = 0; k < 8; k++) acc[k] = (uint64_t)(uint32_t)acc[k] * b + acc[k];
+    }
+    uint64_t x = 0;
+    #pragma unroll
+    for (int k = 0; k < 8; k++) x ^= acc[k];
+    sink[tid] = x;
+}
+
 }  // namespace hc
+
+extern "C" hc_status hc_probe_mul32_rate(hc_context* c, double ms, double* rate_out) {
+    if (!c || !rate_out || ms <= 0) return HC_EINVAL;
+    HC_CHECK(hipSetDevice(c->device));
+    int cus = 0;
+    HC_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    const int threads = 256, blocks = cus * 16;
+    uint64_t* sink = nullptr;
+    HC_CHECK(hipMalloc((void**)&sink, sizeof(uint64_t) * threads * blocks));
+    hipEvent_t a, b;
+    HC_CHECK(hipEventCreate(&a));
+    HC_CHECK(hipEventCreate(&b));
+    uint32_t iters = 1024;
+    double rate = 0;
+    for (int rep = 0; rep < 3; rep++) {
+        HC_CHECK(hipEventRecord(a, 0));
+        hipLaunchKernelGGL(hc::probe_mul32_kernel, dim3(blocks), dim3(threads), 0, 0, sink, iters);
+        HC_CHECK(hipEventRecord(b, 0));
+        HC_CHECK(hipEventSynchronize(b));
+        float el = 0;
+        HC_CHECK(hipEventElapsedTime(&el, a, b));
+        rate = (double)threads * blocks * iters * 8.0 / (el * 1e-3);
+        double scale = ms / (el > 0 ? el : 1e-3);
+        if (scale > 64) scale = 64;
+        if (rep < 2) iters = (uint32_t)(iters * scale) + 1;
+    }
+    HC_CHECK(hipEventDestroy(a));
+    HC_CHECK(hipEventDestroy(b));
+    HC_CHECK(hipFree(sink));
+    *rate_out = rate;
+    return HC_OK;
+}

@@ -98,6 +98,14 @@ _sig("hc_encode_diagonal", _st, c_vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c
 _sig("hc_export_sk", _st, c_vp, c_vp, c_i64p)
 _sig("hc_export_pk", _st, c_vp, c_vp, c_u64p)
 _sig("hc_export_gk", _st, c_vp, c_vp, ctypes.c_uint32, c_u64p)
+_sig("hc_timing_enable", _st, c_vp, ctypes.c_int)
+_sig("hc_timing_read", _st, c_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+     ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
+_sig("hc_probe_mul32_rate", _st, c_vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double))
+
+KT_NTT_FWD, KT_NTT_INV, KT_KS_INNER, KT_DIAG_MAC, KT_MODUP = 0, 1, 2, 3, 4
+KT_NAMES = {KT_NTT_FWD: "ntt_forward", KT_NTT_INV: "ntt_inverse", KT_KS_INNER: "keyswitch_inner",
+            KT_DIAG_MAC: "diag_mac", KT_MODUP: "modup"}
 
 EXPORTED = [
     "hc_status_str", "hc_context_create", "hc_context_destroy", "hc_context_primes", "hc_keygen",
@@ -105,7 +113,7 @@ EXPORTED = [
     "hc_db_upload", "hc_db_destroy", "hc_encrypt", "hc_compress", "hc_compress_batch",
     "hc_decrypt", "hc_decompress", "hc_ntt", "hc_rotate", "hc_rotate_hoisted", "hc_mul_plain",
     "hc_modup", "hc_moddown", "hc_sample", "hc_encode_diagonal", "hc_export_sk", "hc_export_pk",
-    "hc_export_gk",
+    "hc_export_gk", "hc_timing_enable", "hc_timing_read", "hc_probe_mul32_rate",
 ]
 
 
@@ -286,6 +294,21 @@ class Context:
     def encode_diagonal(self, s, B, beta, gi, b, out, stream=None):
         _check(_lib.hc_encode_diagonal(self.h, s, B, beta, gi, b, _dev(out), _stream(stream)),
                "hc_encode_diagonal")
+
+    def timing(self, enable):
+        _check(_lib.hc_timing_enable(self.h, 1 if enable else 0), "hc_timing_enable")
+
+    def timing_read(self, kind):
+        ms, by, op = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        cnt = ctypes.c_uint64()
+        _check(_lib.hc_timing_read(self.h, kind, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(by),
+                                   ctypes.byref(op)), "hc_timing_read")
+        return dict(ms=ms.value, launches=cnt.value, bytes=by.value, ops=op.value)
+
+    def probe_mul32_rate(self, ms=50.0):
+        r = ctypes.c_double()
+        _check(_lib.hc_probe_mul32_rate(self.h, ms, ctypes.byref(r)), "hc_probe_mul32_rate")
+        return r.value
 
     def export_sk(self, sk):
         out = np.zeros(self.n, dtype=np.int64)
