@@ -201,12 +201,13 @@ extern "C" hc_status hc_context_create(const hc_params* prm, int device, hc_cont
             pw[k] = h_mulmod(pw[k - 1], psi, q);
             pwi[k] = h_mulmod(pwi[k - 1], psii, q);
         }
+        // layout [direction][k][(w, w')]
         for (uint32_t k = 0; k < n; k++) {
             uint32_t e = brv(k, logn);
-            t[k] = pw[e];
-            t[n + k] = h_shoup_const(t[k], q);
-            t[2 * n + k] = pwi[e];
-            t[3 * n + k] = h_shoup_const(t[2 * n + k], q);
+            t[2 * k] = pw[e];
+            t[2 * k + 1] = h_shoup_const(pw[e], q);
+            t[2 * n + 2 * k] = pwi[e];
+            t[2 * n + 2 * k + 1] = h_shoup_const(pwi[e], q);
         }
         ninv[2 * i] = h_invmod(n % q, q);
         ninv[2 * i + 1] = h_shoup_const(ninv[2 * i], q);
@@ -232,10 +233,10 @@ extern "C" hc_status hc_context_create(const hc_params* prm, int device, hc_cont
     for (uint32_t k = 0; k < n; k++) {
         uint32_t e = brv(k, logn);
         uint32_t w = zp[e], wi = zpi[e];
-        c.h_twp[k] = w;
-        c.h_twp[n + k] = (uint32_t)(((uint64_t)w << 32) / p);
-        c.h_twp[2 * n + k] = wi;
-        c.h_twp[3 * n + k] = (uint32_t)(((uint64_t)wi << 32) / p);
+        c.h_twp[2 * k] = w;
+        c.h_twp[2 * k + 1] = (uint32_t)(((uint64_t)w << 32) / p);
+        c.h_twp[2 * n + 2 * k] = wi;
+        c.h_twp[2 * n + 2 * k + 1] = (uint32_t)(((uint64_t)wi << 32) / p);
     }
     uint32_t ninvp = (uint32_t)h_invmod(n % p, p);
     std::vector<uint32_t> ninvp_v = {ninvp, (uint32_t)(((uint64_t)ninvp << 32) / p)};

@@ -25,12 +25,13 @@ namespace hc {
 
 // ------------------------------------------------------------------ host NTT (same ordering as the device)
 
-static void host_ntt(uint64_t* a, int n, int logn, const uint64_t* W, const uint64_t* Wp, uint64_t q) {
+// tw: (w, w') pairs, forward direction
+static void host_ntt(uint64_t* a, int n, int logn, const uint64_t* tw, uint64_t q) {
     int t = n;
     for (int m = 1; m < n; m <<= 1) {
         t >>= 1;
         for (int i = 0; i < m; i++) {
-            uint64_t w = W[m + i], wp = Wp[m + i];
+            uint64_t w = tw[2 * (m + i)], wp = tw[2 * (m + i) + 1];
             int j1 = 2 * i * t;
             for (int j = j1; j < j1 + t; j++) {
                 uint64_t U = a[j], V = shoup(a[j + t], w, wp, q);
@@ -42,12 +43,12 @@ static void host_ntt(uint64_t* a, int n, int logn, const uint64_t* W, const uint
     (void)logn;
 }
 
-static void host_intt(uint64_t* a, int n, const uint64_t* W, const uint64_t* Wp, uint64_t q,
-                      uint64_t ninv, uint64_t ninvp) {
+// tw: (w, w') pairs, inverse direction
+static void host_intt(uint64_t* a, int n, const uint64_t* tw, uint64_t q, uint64_t ninv, uint64_t ninvp) {
     int t = 1;
     for (int m = n >> 1; m >= 1; m >>= 1) {
         for (int i = 0; i < m; i++) {
-            uint64_t w = W[m + i], wp = Wp[m + i];
+            uint64_t w = tw[2 * (m + i)], wp = tw[2 * (m + i) + 1];
             int j1 = 2 * i * t;
             for (int j = j1; j < j1 + t; j++) {
                 uint64_t U = a[j], V = a[j + t];
@@ -80,11 +81,11 @@ extern "C" hc_status hc_decrypt(hc_context* cp, const hc_sk* sk, const uint64_t*
             s[j] = sk->s[j] < 0 ? q - 1 : (uint64_t)sk->s[j];
             t[j] = c1[j];
         }
-        host_ntt(s.data(), n, c.logn, tw, tw + n, q);
-        host_ntt(t.data(), n, c.logn, tw, tw + n, q);
+        host_ntt(s.data(), n, c.logn, tw, q);
+        host_ntt(t.data(), n, c.logn, tw, q);
         for (int j = 0; j < n; j++) t[j] = h_mulmod(t[j], s[j], q);
         uint64_t ninv = h_invmod((uint64_t)n % q, q);
-        host_intt(t.data(), n, tw + 2 * n, tw + 3 * n, q, ninv, h_shoup_const(ninv, q));
+        host_intt(t.data(), n, tw + 2 * n, q, ninv, h_shoup_const(ninv, q));
         for (int j = 0; j < n; j++) x[(size_t)i * n + j] = add_mod(c0[j], t[j], q);
     }
     // y_i multipliers (Q/q_i)^-1 mod q_i
@@ -114,9 +115,9 @@ extern "C" hc_status hc_decrypt(hc_context* cp, const hc_sk* sk, const uint64_t*
         m[j] = (ip + rnd % p) % p;
     }
     // decode: forward transform mod p, slot (r, col) at its evaluation position
-    std::vector<uint64_t> W(n), Wp(n);
-    for (int k = 0; k < n; k++) { W[k] = c.h_twp[k]; Wp[k] = h_shoup_const(W[k], p); }
-    host_ntt(m.data(), n, c.logn, W.data(), Wp.data(), p);
+    std::vector<uint64_t> W(2 * (size_t)n);
+    for (int k = 0; k < n; k++) { W[2 * k] = c.h_twp[2 * k]; W[2 * k + 1] = h_shoup_const(W[2 * k], p); }
+    host_ntt(m.data(), n, c.logn, W.data(), p);
     for (int i = 0; i < n; i++) slots_out[i] = (uint32_t)m[c.h_slotpos[i]];
     return HC_OK;
 }

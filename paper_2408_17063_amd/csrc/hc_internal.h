@@ -49,8 +49,8 @@ struct hc_context {
     uint32_t zeta = 0;
     std::vector<uint64_t> primes;          // q_1..q_L, p_1..p_K
     std::vector<uint64_t> h_qinv, h_r2;    // Montgomery constants per prime
-    std::vector<uint64_t> h_tw;            // host copy of the NTT tables [nq][4][n]
-    std::vector<uint32_t> h_twp;           // mod-p tables [4][n]
+    std::vector<uint64_t> h_tw;            // host copy of the NTT tables [nq][2][n][2]
+    std::vector<uint32_t> h_twp;           // mod-p tables [2][n][2]
     std::vector<uint32_t> h_slotpos;       // NTT-mod-p position of slot r*nh + c
     std::vector<uint32_t> h_cdt;           // Gaussian CDT (20 entries)
 
@@ -58,10 +58,10 @@ struct hc_context {
     uint64_t* d_mods = nullptr;     // [nq]
     uint64_t* d_qinv = nullptr;     // [nq] -q^-1 mod 2^64
     uint64_t* d_r2 = nullptr;       // [nq] 2^128 mod q
-    uint64_t* d_tw = nullptr;       // [nq][4][n] fwd W, W', inv W, W'
+    uint64_t* d_tw = nullptr;       // [nq][2][n][2]: (w, w') forward then inverse
     uint64_t* d_ninv = nullptr;     // [nq][2]
     uint32_t* d_modp = nullptr;     // [1] p
-    uint32_t* d_twp = nullptr;      // [4][n] mod p
+    uint32_t* d_twp = nullptr;      // [2][n][2] mod p
     uint32_t* d_ninvp = nullptr;    // [2]
     uint32_t* d_slotpos = nullptr;  // [n]
     uint32_t* d_posslot = nullptr;  // [n] inverse of slotpos

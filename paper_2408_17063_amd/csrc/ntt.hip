@@ -8,16 +8,20 @@
 // twiddle Winv[n/2^(u+1) + (j >> (u+1))], Winv[k] = psi^-brv(k), then a
 // final multiplication by n^-1.
 //
-// A launch runs S consecutive stages on tiles held in LDS. The stages touch
-// the index bits [blo, blo+S); a tile is P independent sub-problems (values
-// of the other bits) times the 2^S elements of each. Every thread owns 16
-// elements per round and runs up to 4 stages in registers between LDS
-// exchanges. Rings up to 2^12 take one launch per transform; larger rings
-// take two (high bits, then the low 8 bits for the forward direction, the
-// reverse order for the inverse).
+// A launch runs S consecutive stages on tiles of 4096 elements (the whole
+// ring below 2^12) held in LDS. The stages touch the index bits [BLO, BLO+S);
+// a tile is P = 4096 / 2^S independent sub-problems (consecutive values of
+// the other bits, so global accesses are contiguous runs) times the 2^S
+// elements of each. 256 threads each own 16 elements per round and run up to
+// 4 stages in registers between LDS exchanges. Every parameter is a template
+// constant, so rounds are fully unrolled. Within a round the twiddles of stage
+// u are the 2^u (forward) or 2^(R-1-u) (inverse) consecutive table entries the
+// thread's group needs, each one 16-byte load of (w, w') from the interleaved
+// table. Rings up to 2^12 take one launch per transform; larger rings take two
+// (high bits then the low 8 bits forward, the reverse order inverse).
 //
 // Butterflies are lazy (Harvey): forward values stay in [0, 4q), inverse
-// values in [0, 2q); the last launch reduces to [0, q).
+// values in [0, 2q); the last launch reduces to [0, q) (and scales by n^-1).
 #include "hc_internal.h"
 
 namespace hc {
@@ -25,8 +29,14 @@ namespace hc {
 template <typename T> struct Ar;
 
 template <> struct Ar<uint64_t> {
+    typedef ulonglong2 Pair;
     static __device__ __forceinline__ uint64_t shoup_lazy(uint64_t x, uint64_t w, uint64_t wp, uint64_t q) {
         return x * w - __umul64hi(x, wp) * q;
+    }
+    static __device__ __forceinline__ void load_pair(const uint64_t* p, uint64_t& w, uint64_t& wp) {
+        ulonglong2 v = *reinterpret_cast<const ulonglong2*>(p);
+        w = v.x;
+        wp = v.y;
     }
 };
 
@@ -34,194 +44,210 @@ template <> struct Ar<uint32_t> {
     static __device__ __forceinline__ uint32_t shoup_lazy(uint32_t x, uint32_t w, uint32_t wp, uint32_t q) {
         return x * w - __umulhi(x, wp) * q;
     }
+    static __device__ __forceinline__ void load_pair(const uint32_t* p, uint32_t& w, uint32_t& wp) {
+        uint2 v = *reinterpret_cast<const uint2*>(p);
+        w = v.x;
+        wp = v.y;
+    }
 };
 
 template <typename T>
 __device__ __forceinline__ T csubT(T x, T q) { return x >= q ? x - q : x; }
 
-// Tables for one prime: fwd W, fwd W', inv W, inv W' (each n entries), plus
-// n^-1 and its Shoup constant.
+// Tables for one prime: [2 directions][n][2] = (w, w') pairs, forward then
+// inverse; plus n^-1 and its Shoup constant.
 template <typename T> struct NttTab {
-    const T* base;  // [nprime][4][n]
+    const T* base;  // [nprime][2][n][2]
     const T* ninv;  // [nprime][2]
     const T* mods;  // [nprime]
 };
 
-constexpr int NTT_TILE_LOG = 12;          // 4096 elements per tile (32 KiB for u64)
-constexpr int NTT_THREADS = (1 << NTT_TILE_LOG) / 16;
+constexpr int TILE_LOG = 12;
+constexpr int NTT_THREADS = 256;
 
 __device__ __forceinline__ uint32_t insert_bits(uint32_t g, uint32_t v, int pos, int width) {
     uint32_t lowmask = (1u << pos) - 1u;
     return ((g >> pos) << (pos + width)) | (v << pos) | (g & lowmask);
 }
 
-// data: polynomial-major, each polynomial `nl` rows of n residues; row r of
-// polynomial c uses prime index limb_first + r.
-template <typename T, bool INVERSE>
-__global__ void __launch_bounds__(NTT_THREADS)
-ntt_pass_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, int logn, int blo, int S,
-                int stage0, int last, NttTab<T> tab) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* lds = reinterpret_cast<T*>(smem_raw);
+template <typename T, bool INV, int LOGN, int S, int BLO, int ST0>
+struct Tile {
+    static constexpr int TLOG = LOGN < TILE_LOG ? LOGN : TILE_LOG;
+    static constexpr int TSIZE = 1 << TLOG;
+    static constexpr int LOGP = TLOG - S;
+    static constexpr int P = 1 << LOGP;
+    static constexpr int N = 1 << LOGN;
 
-    const int n = 1 << logn;
-    const int row = blockIdx.y;
-    const int poly = blockIdx.z;
-    const int prime = limb_first + row;
-    const T q = tab.mods[prime];
-    const T* W = tab.base + (size_t)prime * 4 * n + (INVERSE ? 2 * n : 0);
-    const T* Wp = W + n;
-    T* a = data + (size_t)poly * poly_stride + (size_t)row * n;
-
-    const int tile_log = (logn < NTT_TILE_LOG) ? logn : NTT_TILE_LOG;
-    const int tile = 1 << tile_log;
-    const int logP = tile_log - S;
-    const int P = 1 << logP;
-    const uint32_t sp0 = blockIdx.x * P;
-    const uint32_t blomask = (1u << blo) - 1u;
-    const int nthreads = blockDim.x;
-
-    // global index of tile element e = (k << logP) | spl
-    auto gidx = [&](uint32_t e) -> uint32_t {
-        uint32_t k = e >> logP;
+    // global index of tile element e = (k << LOGP) | spl, sub-problem base sp0
+    static __device__ __forceinline__ uint32_t gidx(uint32_t e, uint32_t sp0) {
+        uint32_t k = e >> LOGP;
         uint32_t sp = sp0 + (e & (P - 1));
-        return ((sp >> blo) << (blo + S)) | (k << blo) | (sp & blomask);
-    };
-
-    // load, in global-contiguous order
-    for (int f = threadIdx.x; f < tile; f += nthreads) {
-        uint32_t k, spl;
-        if (blo == 0) { spl = f >> S; k = f & ((1 << S) - 1); }
-        else { k = f >> logP; spl = f & (P - 1); }
-        uint32_t e = (k << logP) | spl;
-        lds[e] = a[gidx(e)];
+        return ((sp >> BLO) << (BLO + S)) | (k << BLO) | (sp & ((1u << BLO) - 1u));
     }
-    __syncthreads();
 
-    int done = 0;
-    while (done < S) {
-        const int R = (S - done) >= 4 ? 4 : (S - done);
-        const int gsize = 1 << R;
-        // butterfly bits of k for this round
-        const int kbit = INVERSE ? done : (S - done - R);
-        const int pos = logP + kbit;
-        const int ngroups = tile >> R;
-        for (int g = threadIdx.x; g < ngroups; g += nthreads) {
-            T x[16];
-            uint32_t e0 = insert_bits(g, 0, pos, R);
+    // one round of R stages; butterfly bits [KBIT, KBIT+R) of k; DONE stages before it
+    template <int R, int KBIT, int DONE>
+    static __device__ __forceinline__ void round(T* lds, uint32_t sp0, const T* tw, T q) {
+        constexpr int POS = LOGP + KBIT;
+        constexpr int GS = 1 << R;
+        constexpr int PER = 16 >> R;  // groups per thread
+        #pragma unroll
+        for (int sub = 0; sub < PER; sub++) {
+            const uint32_t g = threadIdx.x * PER + sub;
+            T x[GS];
             #pragma unroll
-            for (int v = 0; v < 16; v++)
-                if (v < gsize) x[v] = lds[insert_bits(g, v, pos, R)];
-            const uint32_t j0 = gidx(e0);  // global index with the butterfly bits zero
-            if (!INVERSE) {
-                // stages st = stage0 + done .. + R-1, partner bit (within v) R-1-u
-                #pragma unroll
-                for (int u = 0; u < 4; u++) {
-                    if (u < R) {
-                        const int st = stage0 + done + u;
-                        const int hb = R - 1 - u;       // partner bit in v
-                        const int half = 1 << hb;
-                        #pragma unroll
-                        for (int v = 0; v < 16; v++) {
-                            if (v < gsize && !(v & half)) {
-                                // global index of element v: j0 | (v << (blo + kbit))
-                                uint32_t j = j0 | ((uint32_t)v << (blo + kbit));
-                                uint32_t widx = (1u << st) + (j >> (logn - st));
-                                T w = W[widx], wp = Wp[widx];
-                                T X = x[v], Y = x[v | half];
-                                T twoq = q << 1;
-                                X = csubT<T>(X, twoq);
-                                T t = Ar<T>::shoup_lazy(Y, w, wp, q);
-                                x[v] = X + t;
-                                x[v | half] = X - t + twoq;
-                            }
+            for (int v = 0; v < GS; v++) x[v] = lds[insert_bits(g, v, POS, R)];
+            const uint32_t j0 = gidx(insert_bits(g, 0, POS, R), sp0);
+            const T twoq = q << 1;
+            #pragma unroll
+            for (int u = 0; u < R; u++) {
+                const int st = ST0 + DONE + u;
+                if (!INV) {
+                    // partner bit R-1-u of v; twiddle 2^st + (j0 >> (LOGN-st)) + (v >> (R-u))
+                    const int half = 1 << (R - 1 - u);
+                    const uint32_t base = (1u << st) + (j0 >> (LOGN - st));
+                    T w[8], wp[8];
+                    #pragma unroll
+                    for (int t = 0; t < (1 << u); t++) Ar<T>::load_pair(tw + 2 * (base + t), w[t], wp[t]);
+                    #pragma unroll
+                    for (int v = 0; v < GS; v++) {
+                        if (!(v & half)) {
+                            const int t = v >> (R - u);
+                            T X = csubT<T>(x[v], twoq);
+                            T y = Ar<T>::shoup_lazy(x[v | half], w[t], wp[t], q);
+                            x[v] = X + y;
+                            x[v | half] = X - y + twoq;
                         }
                     }
-                }
-            } else {
-                #pragma unroll
-                for (int u = 0; u < 4; u++) {
-                    if (u < R) {
-                        const int st = stage0 + done + u;   // partner distance 2^st
-                        const int hb = u;
-                        const int half = 1 << hb;
-                        #pragma unroll
-                        for (int v = 0; v < 16; v++) {
-                            if (v < gsize && !(v & half)) {
-                                uint32_t j = j0 | ((uint32_t)v << (blo + kbit));
-                                uint32_t widx = ((uint32_t)n >> (st + 1)) + (j >> (st + 1));
-                                T w = W[widx], wp = Wp[widx];
-                                T X = x[v], Y = x[v | half];
-                                T twoq = q << 1;
-                                x[v] = csubT<T>(X + Y, twoq);
-                                x[v | half] = Ar<T>::shoup_lazy(X + twoq - Y, w, wp, q);
-                            }
+                } else {
+                    // partner bit u of v; twiddle n/2^(st+1) + (j0 >> (st+1)) + (v >> (u+1))
+                    const int half = 1 << u;
+                    const uint32_t base = ((uint32_t)N >> (st + 1)) + (j0 >> (st + 1));
+                    T w[8], wp[8];
+                    #pragma unroll
+                    for (int t = 0; t < (1 << (R - 1 - u)); t++)
+                        Ar<T>::load_pair(tw + 2 * (base + t), w[t], wp[t]);
+                    #pragma unroll
+                    for (int v = 0; v < GS; v++) {
+                        if (!(v & half)) {
+                            const int t = v >> (u + 1);
+                            T X = x[v], Y = x[v | half];
+                            x[v] = csubT<T>(X + Y, twoq);
+                            x[v | half] = Ar<T>::shoup_lazy(X + twoq - Y, w[t], wp[t], q);
                         }
                     }
                 }
             }
             #pragma unroll
-            for (int v = 0; v < 16; v++)
-                if (v < gsize) lds[insert_bits(g, v, pos, R)] = x[v];
+            for (int v = 0; v < GS; v++) lds[insert_bits(g, v, POS, R)] = x[v];
         }
-        done += R;
-        __syncthreads();
     }
 
-    // store (final reduction / scaling on the last launch)
-    const T* ninv = tab.ninv + 2 * prime;
-    for (int f = threadIdx.x; f < tile; f += nthreads) {
+    // rounds: forward processes k bits from the top down, inverse from the bottom up
+    template <int DONE>
+    static __device__ __forceinline__ void rounds(T* lds, uint32_t sp0, const T* tw, T q) {
+        if constexpr (DONE < S) {
+            constexpr int R = (S - DONE) >= 4 ? 4 : (S - DONE);
+            constexpr int KBIT = INV ? DONE : (S - DONE - R);
+            round<R, KBIT, DONE>(lds, sp0, tw, q);
+            __syncthreads();
+            rounds<DONE + R>(lds, sp0, tw, q);
+        }
+    }
+};
+
+template <typename T, bool INV, int LOGN, int S, int BLO, int ST0, bool LAST>
+__global__ void __launch_bounds__(NTT_THREADS)
+ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab<T> tab) {
+    typedef Tile<T, INV, LOGN, S, BLO, ST0> TL;
+    __shared__ T lds[TL::TSIZE];
+    const int row = blockIdx.y;
+    const int prime = limb_first + row;
+    const T q = tab.mods[prime];
+    const T* tw = tab.base + ((size_t)prime * 2 + (INV ? 1 : 0)) * 2 * TL::N;
+    T* a = data + (size_t)blockIdx.z * poly_stride + (size_t)row * TL::N;
+    const uint32_t sp0 = blockIdx.x * TL::P;
+
+    constexpr int THREADS = TL::TSIZE / 16;  // the launch's block size
+    // load in global-contiguous order
+    #pragma unroll
+    for (int i = 0; i < 16; i++) {
+        const uint32_t f = threadIdx.x + i * THREADS;
         uint32_t k, spl;
-        if (blo == 0) { spl = f >> S; k = f & ((1 << S) - 1); }
-        else { k = f >> logP; spl = f & (P - 1); }
-        uint32_t e = (k << logP) | spl;
+        if (BLO == 0) { spl = f >> S; k = f & ((1u << S) - 1u); }
+        else { k = f >> TL::LOGP; spl = f & (TL::P - 1); }
+        const uint32_t e = (k << TL::LOGP) | spl;
+        lds[e] = a[TL::gidx(e, sp0)];
+    }
+    __syncthreads();
+    TL::template rounds<0>(lds, sp0, tw, q);
+
+    const T* ni = tab.ninv + 2 * prime;
+    #pragma unroll
+    for (int i = 0; i < 16; i++) {
+        const uint32_t f = threadIdx.x + i * THREADS;
+        uint32_t k, spl;
+        if (BLO == 0) { spl = f >> S; k = f & ((1u << S) - 1u); }
+        else { k = f >> TL::LOGP; spl = f & (TL::P - 1); }
+        const uint32_t e = (k << TL::LOGP) | spl;
         T v = lds[e];
-        if (last) {
-            if (INVERSE) v = csubT<T>(Ar<T>::shoup_lazy(v, ninv[0], ninv[1], q), q);
+        if (LAST) {
+            if (INV) v = csubT<T>(Ar<T>::shoup_lazy(v, ni[0], ni[1], q), q);
             else { v = csubT<T>(v, q << 1); v = csubT<T>(v, q); }
         }
-        a[gidx(e)] = v;
+        a[TL::gidx(e, sp0)] = v;
     }
 }
 
-template <typename T, bool INVERSE>
-static void run_ntt(const Ctx& c, T* data, size_t poly_stride, int count, int limb_first, int nlimbs,
-                    int logn, NttTab<T> tab, hipStream_t stream) {
-    const int n = 1 << logn;
-    // timing class (64-bit transforms only), bytes moved and butterflies per pass
-    const int kind = sizeof(T) == 8 ? (INVERSE ? HC_KT_NTT_INV : HC_KT_NTT_FWD) : -1;
-    const double pass_bytes = 2.0 * sizeof(T) * (double)count * nlimbs * n;
-    auto bfly = [&](int S) { return (double)count * nlimbs * (n / 2) * S; };
-    const size_t smem = sizeof(T) * (size_t)((logn < NTT_TILE_LOG) ? n : (1 << NTT_TILE_LOG));
-    const int threads = ((logn < NTT_TILE_LOG) ? n : (1 << NTT_TILE_LOG)) / 16;
-    if (logn <= NTT_TILE_LOG) {
-        dim3 grid(1, nlimbs, count);
-        if (kind >= 0) {
-            TimeScope ts(c, kind, stream, pass_bytes, bfly(logn));
-            hipLaunchKernelGGL((ntt_pass_kernel<T, INVERSE>), grid, dim3(threads), smem, stream,
-                               data, poly_stride, limb_first, logn, 0, logn, 0, 1, tab);
-        } else {
-            hipLaunchKernelGGL((ntt_pass_kernel<T, INVERSE>), grid, dim3(threads), smem, stream,
-                               data, poly_stride, limb_first, logn, 0, logn, 0, 1, tab);
-        }
-        return;
+// Launch one pass; `ops` butterflies and `bytes` moved for the timing record.
+template <typename T, bool INV, int LOGN, int S, int BLO, int ST0, bool LAST>
+static void pass(const Ctx& c, int kind, T* data, size_t stride, int count, int lf, int nl,
+                 NttTab<T> tab, hipStream_t st) {
+    constexpr int TLOG = LOGN < TILE_LOG ? LOGN : TILE_LOG;
+    constexpr int THREADS = (1 << TLOG) / 16;
+    static_assert(THREADS <= NTT_THREADS, "tile");
+    dim3 grid(1 << (LOGN - TLOG), nl, count);
+    const double bytes = 2.0 * sizeof(T) * (double)count * nl * (1 << LOGN);
+    const double ops = (double)count * nl * (1 << (LOGN - 1)) * S;
+    if (kind >= 0) {
+        TimeScope ts(c, kind, st, bytes, ops);
+        hipLaunchKernelGGL((ntt_tile_kernel<T, INV, LOGN, S, BLO, ST0, LAST>), grid, dim3(THREADS), 0, st,
+                           data, stride, lf, tab);
+    } else {
+        hipLaunchKernelGGL((ntt_tile_kernel<T, INV, LOGN, S, BLO, ST0, LAST>), grid, dim3(THREADS), 0, st,
+                           data, stride, lf, tab);
     }
-    const int S_lo = 8, S_hi = logn - 8;
-    const int tiles = n >> NTT_TILE_LOG;
-    dim3 grid(tiles, nlimbs, count);
-    // pass 1 then pass 2: (blo, S, first stage, last pass?)
-    const int fwd[2][4] = {{S_lo, S_hi, 0, 0}, {0, S_lo, S_hi, 1}};
-    const int inv[2][4] = {{0, S_lo, 0, 0}, {S_lo, S_hi, S_lo, 1}};
-    for (int ps = 0; ps < 2; ps++) {
-        const int* a = INVERSE ? inv[ps] : fwd[ps];
-        if (kind >= 0) {
-            TimeScope ts(c, kind, stream, pass_bytes, bfly(a[1]));
-            hipLaunchKernelGGL((ntt_pass_kernel<T, INVERSE>), grid, dim3(threads), smem, stream,
-                               data, poly_stride, limb_first, logn, a[0], a[1], a[2], a[3], tab);
+}
+
+template <typename T, bool INV, int LOGN>
+static void run_logn(const Ctx& c, int kind, T* data, size_t stride, int count, int lf, int nl,
+                     NttTab<T> tab, hipStream_t st) {
+    if constexpr (LOGN <= TILE_LOG) {
+        pass<T, INV, LOGN, LOGN, 0, 0, true>(c, kind, data, stride, count, lf, nl, tab, st);
+    } else {
+        constexpr int SL = 8, SH = LOGN - 8;
+        if (!INV) {
+            pass<T, false, LOGN, SH, SL, 0, false>(c, kind, data, stride, count, lf, nl, tab, st);
+            pass<T, false, LOGN, SL, 0, SH, true>(c, kind, data, stride, count, lf, nl, tab, st);
         } else {
-            hipLaunchKernelGGL((ntt_pass_kernel<T, INVERSE>), grid, dim3(threads), smem, stream,
-                               data, poly_stride, limb_first, logn, a[0], a[1], a[2], a[3], tab);
+            pass<T, true, LOGN, SL, 0, 0, false>(c, kind, data, stride, count, lf, nl, tab, st);
+            pass<T, true, LOGN, SH, SL, SL, true>(c, kind, data, stride, count, lf, nl, tab, st);
         }
+    }
+}
+
+template <typename T, bool INV>
+static void run_ntt(const Ctx& c, int kind, T* data, size_t stride, int count, int lf, int nl,
+                    NttTab<T> tab, hipStream_t st) {
+    switch (c.logn) {
+        case 10: run_logn<T, INV, 10>(c, kind, data, stride, count, lf, nl, tab, st); break;
+        case 11: run_logn<T, INV, 11>(c, kind, data, stride, count, lf, nl, tab, st); break;
+        case 12: run_logn<T, INV, 12>(c, kind, data, stride, count, lf, nl, tab, st); break;
+        case 13: run_logn<T, INV, 13>(c, kind, data, stride, count, lf, nl, tab, st); break;
+        case 14: run_logn<T, INV, 14>(c, kind, data, stride, count, lf, nl, tab, st); break;
+        case 15: run_logn<T, INV, 15>(c, kind, data, stride, count, lf, nl, tab, st); break;
+        case 16: run_logn<T, INV, 16>(c, kind, data, stride, count, lf, nl, tab, st); break;
+        default: break;
     }
 }
 
@@ -229,15 +255,15 @@ void ntt64(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb
            bool inverse, hipStream_t stream) {
     if (count <= 0 || nlimbs <= 0) return;
     NttTab<uint64_t> tab{c.d_tw, c.d_ninv, c.d_mods};
-    if (inverse) run_ntt<uint64_t, true>(c, data, poly_stride, count, limb_first, nlimbs, c.logn, tab, stream);
-    else run_ntt<uint64_t, false>(c, data, poly_stride, count, limb_first, nlimbs, c.logn, tab, stream);
+    if (inverse) run_ntt<uint64_t, true>(c, HC_KT_NTT_INV, data, poly_stride, count, limb_first, nlimbs, tab, stream);
+    else run_ntt<uint64_t, false>(c, HC_KT_NTT_FWD, data, poly_stride, count, limb_first, nlimbs, tab, stream);
 }
 
 void ntt32(const Ctx& c, uint32_t* data, int count, bool inverse, hipStream_t stream) {
     if (count <= 0) return;
     NttTab<uint32_t> tab{c.d_twp, c.d_ninvp, c.d_modp};
-    if (inverse) run_ntt<uint32_t, true>(c, data, (size_t)c.n, count, 0, 1, c.logn, tab, stream);
-    else run_ntt<uint32_t, false>(c, data, (size_t)c.n, count, 0, 1, c.logn, tab, stream);
+    if (inverse) run_ntt<uint32_t, true>(c, -1, data, (size_t)c.n, count, 0, 1, tab, stream);
+    else run_ntt<uint32_t, false>(c, -1, data, (size_t)c.n, count, 0, 1, tab, stream);
 }
 
 }  // namespace hc
