@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large-65536")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--comp-level", type=int, default=0,
+                    help="ciphertext primes kept for Comp (0: the library default; 24: no switching)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the compression path here is built and measured on a single "
@@ -145,14 +147,14 @@ def main():
     out = ctx.ct_tensor(1)[0]
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
-        ctx.compress(st["gk"], st["db"], st["cts"], wl.N, wl.t, out=out)
+        _, info = ctx.compress(st["gk"], st["db"], st["cts"], wl.N, wl.t, out=out, comp_level=args.comp_level)
     torch.cuda.synchronize()
     ctx.timing(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(args.steps):
-        ctx.compress(st["gk"], st["db"], st["cts"], wl.N, wl.t, out=out)
+        ctx.compress(st["gk"], st["db"], st["cts"], wl.N, wl.t, out=out, comp_level=args.comp_level)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -186,7 +188,8 @@ def main():
                                "4 value columns, Q=24x55-bit, P=3x60-bit, p=786433",
                    "records": wl.N, "t": wl.t, "ring_degree": ctx.n, "value_columns": wl.ncol,
                    "key_switches_per_step": st["info"]["n_keyswitch"],
-                   "ptct_per_step": st["info"]["n_ptct"]},
+                   "ptct_per_step": st["info"]["n_ptct"],
+                   "comp_level_primes": info["level"]},
     }
     rec["roofline"] = dict(rl[dominant], kernel=dominant)
     if "keyswitch_inner" in rl:

@@ -82,6 +82,7 @@ typedef struct {
     uint32_t n_keyswitch;  /* key switches performed */
     uint64_t n_ptct;       /* plaintext-ciphertext products performed */
     uint64_t n_diag;       /* diagonal plaintexts encoded */
+    uint32_t level;        /* ciphertext primes of the output (the Comp level) */
 } hc_compress_info;
 
 /* ------------------------------------------------------------------ context */
@@ -114,11 +115,12 @@ hc_status hc_galois_keygen(hc_context* ctx, const hc_sk* sk, const uint32_t* ele
 void hc_gk_destroy(hc_gk* gk);
 
 /* The Galois elements a compression of N records, ncol value columns and
- * sparsity bound t_bound needs (the schedule's key set, ascending).
+ * sparsity bound t_bound needs (the schedule's key set, ascending), and the
+ * plan's counts. comp_level as in hc_compress.
  * *count is the capacity of elements_out on entry and the number written on
  * exit. Errors: HC_EINVAL (the bands do not fit in n/2 slots, s > n/2, N = 0,
- * capacity too small -- *count then holds the size needed). */
-hc_status hc_plan(hc_context* ctx, uint64_t N, uint32_t ncol, uint32_t t_bound,
+ * bad comp_level, capacity too small -- *count then holds the size needed). */
+hc_status hc_plan(hc_context* ctx, uint64_t N, uint32_t ncol, uint32_t t_bound, uint32_t comp_level,
                   uint32_t* elements_out, uint32_t* count, hc_compress_info* info);
 
 /* ------------------------------------------------------------------ database */
@@ -141,13 +143,19 @@ hc_status hc_encrypt(hc_context* ctx, const hc_pk* pk, const uint32_t* slots,
 
 /* Answer of a PDQ query: Mask every value column with the index vector and
  * compress [v, d_1, .., d_ncol] with the Vandermonde matrix C[j,i] = i^j mod p
- * (Eq. (1)) into one ciphertext.
+ * (Eq. (1)) into one ciphertext. Mask runs at the input's full modulus; then
+ * the ciphertexts are modulus-switched to the first comp_level primes (the
+ * BFV form of the paper's switch to smaller parameters before Comp, Sec. 5.3)
+ * and the rest of the map runs there with the same Galois keys restricted to
+ * those primes. comp_level: 0 = the smallest multiple of K that is >= 2
+ * (at most L); L = no switching; otherwise a multiple of K up to L.
  *   ct_v: device, n_ct = ceil(N/n) ciphertexts [n_ct][2][L][n] of the index
  *         vector; record r sits in ciphertext r / n, row (r % n) / (n/2),
  *         column r % (n/2).
  *   N, t_bound: records and an upper bound on the matches; s = 2^ceil(log2 t_bound).
  *   db: columns uploaded with hc_db_upload for the same N (ncol may be 0).
- *   ct_out: device [2][L][n]. Band g*streams + sigma, slots [b s, b s + s) of
+ *   ct_out: device, room for [2][L][n]; receives [2][level][n] (info->level).
+ *         Band g*streams + sigma, slots [b s, b s + s) of
  *         row 0 / row 1, decrypts to (C a)_j / (C b)_j for group g and stream
  *         sigma = (a, b). With a single band the slots beyond s are not masked.
  *   info: optional, filled on success.
@@ -155,15 +163,16 @@ hc_status hc_encrypt(hc_context* ctx, const hc_pk* pk, const uint32_t* slots,
  * Errors: HC_EINVAL (shapes, bands do not fit), HC_ENOKEY (gk lacks a needed
  * element), HC_ENOMEM (workspace), HC_EDEVICE. */
 hc_status hc_compress(hc_context* ctx, const hc_gk* gk, const hc_db* db, const uint64_t* ct_v,
-                      uint64_t N, uint32_t t_bound, uint64_t* ct_out, hc_compress_info* info,
-                      hipStream_t stream);
+                      uint64_t N, uint32_t t_bound, uint32_t comp_level, uint64_t* ct_out,
+                      hc_compress_info* info, hipStream_t stream);
 
 /* One entry of a batch for hc_compress_batch. */
 typedef struct {
     const uint64_t* ct_v;   /* device, ceil(N/n) ciphertexts */
     uint64_t N;
     uint32_t t_bound;
-    uint64_t* ct_out;       /* device [2][L][n] */
+    uint32_t comp_level;    /* as in hc_compress */
+    uint64_t* ct_out;       /* device, room for [2][L][n] */
     hc_compress_info* info; /* optional */
     hc_status status;       /* per-query result */
 } hc_query;
@@ -179,11 +188,13 @@ hc_status hc_compress_batch(hc_context* ctx, const hc_gk* gk, const hc_db* db,
 
 /* ------------------------------------------------------------------ client side (host CPU) */
 
-/* Dec: slots of round(p [c0 + c1 s]_Q / Q) mod p. ct: host [2][L][n],
+/* Dec: slots of round(p [c0 + c1 s]_Q / Q) mod p, Q the product of the first
+ * `level` ciphertext primes (1 <= level <= L). ct: host [2][level][n],
  * coefficient domain. slots_out: host 2 x n/2. Runs on the host.
- * Errors: HC_EINVAL (non-canonical residue), HC_ENOISE (rounding within
- * 2^-50 of a tie: the noise has reached the budget). */
-hc_status hc_decrypt(hc_context* ctx, const hc_sk* sk, const uint64_t* ct, uint32_t* slots_out);
+ * Errors: HC_EINVAL (non-canonical residue, bad level), HC_ENOISE (rounding
+ * within 2^-50 of a tie: the noise has reached the budget). */
+hc_status hc_decrypt(hc_context* ctx, const hc_sk* sk, const uint64_t* ct, uint32_t level,
+                     uint32_t* slots_out);
 
 /* Decomp for one group (Alg. 6 with Alg. 1 and Alg. 4): from w = C v
  * (s values) and e_c = C d_c (ncols x s values, host) recover the matched

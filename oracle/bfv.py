@@ -265,6 +265,65 @@ def rotate_hoisted(pr, ct, gks):
 
 
 # ---------------------------------------------------------------------------
+# modulus switching (the BFV form of switching to smaller parameters, Sec. 5.3)
+
+def at_level(pr, level):
+    """Parameters of the ring restricted to the first `level` ciphertext primes
+    (a multiple of the digit size): Q' = q_1 ... q_level, same special primes."""
+    import copy
+    if level % pr.alpha or not 0 < level <= pr.L:
+        raise ValueError("level must be a positive multiple of the digit size")
+    lo = copy.copy(pr)
+    lo.L = level
+    lo.q = pr.q[:level]
+    lo.Q = 1
+    for x in lo.q:
+        lo.Q *= x
+    lo.delta = lo.Q // pr.p
+    lo.dnum = level // pr.alpha
+    return lo
+
+
+def key_at_level(pr, gk, level):
+    """A Galois key restricted to the first `level` ciphertext primes, the special
+    primes and the digits inside them. On those primes the gadget
+    P (Q/D_j) [(Q/D_j)^-1]_{D_j} agrees with P (Q'/D_j) [(Q'/D_j)^-1]_{D_j}
+    (both are P on the digit's primes and 0 on the other primes of Q'), so the
+    restriction is a key for the smaller modulus."""
+    rows = list(range(level)) + list(range(pr.L, pr.L + pr.K))
+    digits = [(b.limbs(rows), a.limbs(rows)) for b, a in gk.digits[:level // pr.alpha]]
+    return GaloisKey(gk.k, digits)
+
+
+def mod_switch(pr, ct, level):
+    """Drop the ciphertext primes beyond `level`: with D the product of the dropped
+    primes, each component c becomes (c - Conv_{D->Q'}([c]_D)) D^-1 mod Q', the
+    fast basis conversion of the dropped residues written out as in moddown
+    (y_j = [c_j (D/q_j)^-1]_{q_j}, Conv = sum_j y_j (D/q_j)); this divides the
+    ciphertext by D, so it decrypts under Q' to the same plaintext."""
+    kept, dropped = pr.q[:level], pr.q[level:]
+    D = 1
+    for x in dropped:
+        D *= x
+    out = []
+    for comp in (ct.c0, ct.c1):
+        ys = []
+        for j, qj in enumerate(dropped):
+            inv = pow((D // qj) % qj, -1, qj)
+            ys.append((comp.c[level + j].astype(object) * inv) % qj)
+        rows = np.empty((level, pr.n), dtype=np.uint64)
+        for i, qi in enumerate(kept):
+            conv = np.zeros(pr.n, dtype=object)
+            for y, qj in zip(ys, dropped):
+                conv = conv + y * ((D // qj) % qi)
+            conv = conv % qi
+            diff = (comp.c[i].astype(object) - conv) % qi
+            rows[i] = (diff * pow(D % qi, -1, qi) % qi).astype(np.uint64)
+        out.append(Poly(kept, rows))
+    return Ciphertext(out[0], out[1])
+
+
+# ---------------------------------------------------------------------------
 # Galois elements of the rotations (Sec. 5.1)
 
 def rot_row_element(pr, r):

@@ -35,7 +35,14 @@ determined by the inputs and the key seeds):
 * bands: band g * (#streams) + sigma holds group g, stream sigma. With one band
   the output is that band as is; otherwise every band is multiplied by the
   mask of slots [0, s) and band beta' is rotated by -beta' s before summing;
-  the bands must fit: bands * s <= n/2.
+  the bands must fit: bands * s <= n/2;
+* smaller parameters for Comp (Sec. 5.3 switches to a smaller ring after
+  Mask): here the modulus is switched instead. After Mask, the index-vector
+  and masked ciphertexts drop to the first `level` ciphertext primes, and
+  everything after (u-packing, the block products, rotate-and-sum, merge) runs
+  there with the top-level Galois keys restricted to those primes. The default
+  level is the smallest multiple of the digit size that is at least 2 primes
+  (comp_level in compress); level = L keeps the full modulus.
 """
 from dataclasses import dataclass, field
 from typing import Dict, List, Optional, Tuple
@@ -267,16 +274,29 @@ def rotate_and_sum(pr, sched, y, keys):
     return y
 
 
-def compress(pr, sched, cts_v, db, gks):
+def default_level(pr):
+    """Smallest multiple of the digit size that is at least 2 primes (at most L)."""
+    lvl = pr.alpha * -(-2 // pr.alpha)
+    return min(lvl, pr.L)
+
+
+def compress(pr, sched, cts_v, db, gks, level=None):
     """Comp of Alg. 7 step 3 on ciphertexts of v (and Mask, step 2).
 
     cts_v: n_ct ciphertexts of the index vector; db: ncol value columns of
-    length N; gks: Galois keys by element. Returns one ciphertext."""
-    keys = KeySet(gks)
+    length N; gks: Galois keys by element; level: ciphertext primes kept for
+    Comp (None: default_level). Returns one ciphertext at that level."""
     if len(cts_v) != sched.n_ct or len(db) != sched.ncol:
         raise ScheduleError("inputs do not match the schedule")
+    level = default_level(pr) if level is None else level
     masked = [[mask(pr, cts_v[i], db[c], i, sched.N) for i in range(sched.n_ct)]
               for c in range(sched.ncol)]
+    if level < pr.L:
+        cts_v = [bfv.mod_switch(pr, ct, level) for ct in cts_v]
+        masked = [[bfv.mod_switch(pr, ct, level) for ct in row] for row in masked]
+        gks = {k: bfv.key_at_level(pr, gk, level) for k, gk in gks.items()}
+        pr = bfv.at_level(pr, level)
+    keys = KeySet(gks)
 
     def vec_cts(vid, grp):
         src = cts_v if vid == 0 else masked[vid - 1]

@@ -39,6 +39,7 @@ struct PlanGroup {
 
 struct Plan {
     uint32_t s = 0, n_ct = 0, ncol = 0;
+    int level = 0;  // ciphertext primes kept for Comp (modulus switched after Mask)
     uint64_t N = 0;
     std::vector<PlanGroup> groups;
     std::vector<std::pair<int, int>> streams;  // vector ids (0 = v, c = d_c), -1 = none
@@ -64,8 +65,18 @@ static uint32_t choose_B(uint32_t s, uint32_t k) {
     return bestB;
 }
 
-hc_status make_plan(const Ctx& c, uint64_t N, uint32_t ncol, uint32_t t_bound, Plan& pl) {
+// Default level of Comp: the smallest multiple of the digit size that is at least 2 primes.
+static int default_level(const Ctx& c) {
+    int lvl = c.alpha * ((2 + c.alpha - 1) / c.alpha);
+    return lvl < c.L ? lvl : c.L;
+}
+
+hc_status make_plan(const Ctx& c, uint64_t N, uint32_t ncol, uint32_t t_bound, uint32_t comp_level,
+                    Plan& pl) {
     if (N == 0 || t_bound == 0) return HC_EINVAL;
+    if (comp_level == 0) pl.level = default_level(c);
+    else if ((int)comp_level > c.L || comp_level % c.alpha) return HC_EINVAL;
+    else pl.level = (int)comp_level;
     uint32_t s = 1;
     while (s < t_bound) s *= 2;
     if (s > (uint32_t)c.nh) return HC_EINVAL;
@@ -135,6 +146,7 @@ static void fill_info(const Plan& pl, hc_compress_info* info) {
     info->n_keyswitch = pl.n_ks;
     info->n_ptct = pl.n_ptct;
     info->n_diag = pl.n_diag;
+    info->level = (uint32_t)pl.level;
 }
 
 // bytes of device memory one compression needs beyond its inputs and output
@@ -153,8 +165,9 @@ static const size_t kDiagBudgetBytes = (size_t)16 << 30;
 
 static Layout layout_for(const Ctx& c, const Plan& pl) {
     Layout ly;
-    ly.ct_words = 2 * (size_t)c.L * c.n;
-    ly.pt_words = (size_t)c.L * c.n;
+    ly.ct_words = 2 * (size_t)pl.level * c.n;   // ciphertexts after the switch
+    ly.pt_words = (size_t)pl.level * c.n;
+    const size_t full_ct = 2 * (size_t)c.L * c.n;
     ly.npairs = (int)(pl.groups.size() * pl.streams.size());
     uint32_t kmax = 0, Bmax = 1, Gmax = 1;
     size_t ublocks = 0, baby = 0, giants = 0;
@@ -172,8 +185,10 @@ static Layout layout_for(const Ctx& c, const Plan& pl) {
     ly.Gc = Gc;
     size_t cnt = (size_t)kmax * Gc * Bmax;  // diagonals per chunk
     size_t t = 0;
-    t += rup(ly.ct_words * 8 * pl.n_ct);                     // inputs in NTT domain
-    t += rup(ly.ct_words * 8 * pl.n_ct * std::max<uint32_t>(pl.ncol, 1));  // masked
+    t += rup(full_ct * 8 * pl.n_ct);                                         // inputs in NTT domain
+    t += rup(full_ct * 8 * pl.n_ct * std::max<uint32_t>(pl.ncol, 1));       // masked
+    t += rup(ly.ct_words * 8 * pl.n_ct * (1 + (size_t)pl.ncol));             // both after the switch
+    t += rup(full_ct * 8) + rup(ly.ct_words * 8);                           // switch temporaries
     t += rup(ly.ct_words * 8 * std::max<size_t>(ublocks, 1));               // u-blocks
     t += rup(ly.ct_words * 8 * std::max<size_t>(baby, 1));                  // baby rotations
     t += rup(ly.ct_words * 8 * std::max<size_t>(giants, 1));                // giant accumulators
@@ -192,6 +207,7 @@ struct Compressor {
     Ctx& c;
     const hc_gk* gk;
     hipStream_t st;
+    int Lc;
     KSBuf ks;
     hc_status err = HC_OK;
 
@@ -202,10 +218,10 @@ struct Compressor {
     }
     void rot(uint64_t* out, const uint64_t* in, uint32_t k) {
         const uint64_t* kk = key(k);
-        if (kk) rotate_plain(c, kk, k, out, in, ks, st);
+        if (kk) rotate_plain(c, kk, k, out, in, ks, Lc, st);
     }
     void add(uint64_t* out, const uint64_t* a, const uint64_t* b) {
-        k_add(c, out, a, b, 0, c.L, 2, (size_t)c.L * c.n, st);
+        k_add(c, out, a, b, 0, Lc, 2, (size_t)Lc * c.n, st);
     }
 };
 
@@ -213,7 +229,9 @@ hc_status compress_one(Ctx& c, const hc_gk* gk, const hc_db* db, const uint64_t*
                        uint64_t* ct_out, hipStream_t st) {
     const size_t n = c.n;
     const Layout ly = layout_for(c, pl);
-    const size_t CW = ly.ct_words, PW = ly.pt_words;
+    const size_t CW = ly.ct_words, PW = ly.pt_words;           // at level Lc
+    const size_t CWF = 2 * (size_t)c.L * n, PWF = (size_t)c.L * n;  // at the top level
+    const int Lc = pl.level;
     // all keys present?
     for (uint32_t k : pl.keys)
         if (!find_key(gk, k)) return HC_ENOKEY;
@@ -222,22 +240,40 @@ hc_status compress_one(Ctx& c, const hc_gk* gk, const hc_db* db, const uint64_t*
     HC_CHECK(hipStreamSynchronize(st));  // the workspace and pointer tables are reused
     if (c.ws.reserve(ly.total_bytes) != HC_OK) return HC_ENOMEM;
     Arena& a = c.ws;
-    Compressor cm{c, gk, st, KSBuf()};
+    Compressor cm{c, gk, st, Lc, KSBuf()};
     cm.ks = ks_take(c, a);
 
     // 1. inputs to the NTT domain
-    uint64_t* ctv = a.take<uint64_t>(CW * pl.n_ct);
-    if (!ctv) return HC_ENOMEM;
-    HC_CHECK(hipMemcpyAsync(ctv, ct_v, sizeof(uint64_t) * CW * pl.n_ct, hipMemcpyDeviceToDevice, st));
-    ntt64(c, ctv, PW, 2 * (int)pl.n_ct, 0, c.L, false, st);
+    uint64_t* ctf = a.take<uint64_t>(CWF * pl.n_ct);
+    if (!ctf) return HC_ENOMEM;
+    HC_CHECK(hipMemcpyAsync(ctf, ct_v, sizeof(uint64_t) * CWF * pl.n_ct, hipMemcpyDeviceToDevice, st));
+    ntt64(c, ctf, PWF, 2 * (int)pl.n_ct, 0, c.L, false, st);
 
-    // 2. Mask: d_c = v boxtimes DB_c per ciphertext
-    uint64_t* masked = a.take<uint64_t>(CW * pl.n_ct * std::max<uint32_t>(pl.ncol, 1));
-    if (!masked) return HC_ENOMEM;
+    // 2. Mask at the top level: d_c = v boxtimes DB_c per ciphertext
+    uint64_t* maskf = a.take<uint64_t>(CWF * pl.n_ct * std::max<uint32_t>(pl.ncol, 1));
+    if (!maskf) return HC_ENOMEM;
     for (uint32_t col = 0; col < pl.ncol; col++)
         for (uint32_t i = 0; i < pl.n_ct; i++)
-            k_mul_plain(c, masked + (col * pl.n_ct + i) * CW, ctv + i * CW,
-                        db->d_pt + ((size_t)col * pl.n_ct + i) * PW, st);
+            k_mul_plain(c, maskf + (col * pl.n_ct + i) * CWF, ctf + i * CWF,
+                        db->d_pt + ((size_t)col * pl.n_ct + i) * PWF, c.L, st);
+
+    // 3. switch to the Comp level (Sec. 5.3's smaller parameters, as a modulus switch)
+    uint64_t *ctv = ctf, *masked = maskf;
+    if (Lc < c.L) {
+        ctv = a.take<uint64_t>(CW * pl.n_ct * (1 + (size_t)pl.ncol));
+        uint64_t* mtmp = a.take<uint64_t>(CWF);
+        uint64_t* mconv = a.take<uint64_t>(CW);
+        if (!ctv || !mtmp || !mconv) return HC_ENOMEM;
+        masked = ctv + CW * pl.n_ct;
+        for (uint32_t i = 0; i < pl.n_ct; i++) {
+            hc_status s2 = mod_switch(c, ctv + i * CW, ctf + i * CWF, Lc, mtmp, mconv, st);
+            if (s2 != HC_OK) return s2;
+        }
+        for (uint32_t m = 0; m < pl.n_ct * pl.ncol; m++) {
+            hc_status s2 = mod_switch(c, masked + m * CW, maskf + m * CWF, Lc, mtmp, mconv, st);
+            if (s2 != HC_OK) return s2;
+        }
+    }
     auto vec_ct = [&](int vid, uint32_t i) -> const uint64_t* {
         return vid == 0 ? ctv + i * CW : masked + ((size_t)(vid - 1) * pl.n_ct + i) * CW;
     };
@@ -277,28 +313,28 @@ hc_status compress_one(Ctx& c, const hc_gk* gk, const hc_db* db, const uint64_t*
                 const uint64_t* Act = vec_ct(sm.first, i);
                 const uint64_t* Bct = sm.second >= 0 ? vec_ct(sm.second, i) : nullptr;
                 if (beta % 2 == 0) {
-                    k_mul_plain(c, u, Act, c.d_rowmask[0], st);
+                    k_mul_plain(c, u, Act, c.d_rowmask[0], Lc, st);
                     if (Bct) {
-                        k_mul_plain(c, tmp, Bct, c.d_rowmask[0], st);
+                        k_mul_plain(c, tmp, Bct, c.d_rowmask[0], Lc, st);
                         cm.rot(tmp2, tmp, 2u * c.n - 1);
                         cm.add(u, u, tmp2);
                     }
                 } else {
-                    k_mul_plain(c, tmp, Act, c.d_rowmask[1], st);
+                    k_mul_plain(c, tmp, Act, c.d_rowmask[1], Lc, st);
                     cm.rot(u, tmp, 2u * c.n - 1);
                     if (Bct) {
-                        k_mul_plain(c, tmp, Bct, c.d_rowmask[1], st);
+                        k_mul_plain(c, tmp, Bct, c.d_rowmask[1], Lc, st);
                         cm.add(u, u, tmp);
                     }
                 }
                 R[pp][beta][0] = u;
                 if (g.B > 1) {
-                    hoist_prepare(c, u, cm.ks, st);
+                    hoist_prepare(c, u, cm.ks, Lc, st);
                     for (uint32_t b = 1; b < g.B; b++) {
                         uint64_t* r = bbuf + (bo++) * CW;
                         uint32_t k = rot_elt(c, b);
                         const uint64_t* kk = cm.key(k);
-                        if (kk) rotate_hoisted_one(c, kk, k, r, u, cm.ks, st);
+                        if (kk) rotate_hoisted_one(c, kk, k, r, u, cm.ks, Lc, st);
                         R[pp][beta][b] = r;
                     }
                 }
@@ -359,10 +395,10 @@ hc_status compress_one(Ctx& c, const hc_gk* gk, const hc_db* db, const uint64_t*
             HC_CHECK(hipMemcpyAsync(ptrs, hptr.data(), sizeof(uint64_t*) * hptr.size(), hipMemcpyHostToDevice, st));
             k_diag_gen(c, Dp, prm, cnt, pl.s, B, st);
             ntt32(c, Dp, cnt, true, st);
-            k_lift(c, D, Dp, cnt, true, st);
-            ntt64(c, D, PW, cnt, 0, c.L, false, st);
+            k_lift(c, D, Dp, cnt, true, Lc, st);
+            ntt64(c, D, PW, cnt, 0, Lc, false, st);
             k_diag_mac(c, ptrs + (size_t)cls.size() * kb * B, (const uint64_t* const*)ptrs, D,
-                       (int)cls.size(), (int)kb, (int)gc, (int)B, false, st);
+                       (int)cls.size(), (int)kb, (int)gc, (int)B, false, Lc, st);
             HC_CHECK(hipStreamSynchronize(st));
         }
     }
@@ -397,9 +433,9 @@ hc_status compress_one(Ctx& c, const hc_gk* gk, const hc_db* db, const uint64_t*
         const uint64_t* ms = nullptr;
         hc_status s2 = prefix_mask(c, pl.s, &ms);
         if (s2 != HC_OK) return s2;
-        k_mul_plain(c, outN, bands[0], ms, st);
+        k_mul_plain(c, outN, bands[0], ms, Lc, st);
         for (uint32_t b = 1; b < pl.bands; b++) {
-            k_mul_plain(c, tmp, bands[b], ms, st);
+            k_mul_plain(c, tmp, bands[b], ms, Lc, st);
             cm.rot(tmp2, tmp, rot_elt(c, -(int64_t)b * pl.s));
             cm.add(outN, outN, tmp2);
         }
@@ -407,7 +443,7 @@ hc_status compress_one(Ctx& c, const hc_gk* gk, const hc_db* db, const uint64_t*
     }
     if (cm.err != HC_OK) return cm.err;
     // 8. back to the coefficient domain
-    ntt64(c, res, PW, 2, 0, c.L, true, st);
+    ntt64(c, res, PW, 2, 0, Lc, true, st);
     HC_CHECK(hipMemcpyAsync(ct_out, res, sizeof(uint64_t) * CW, hipMemcpyDeviceToDevice, st));
     HC_CHECK(hipGetLastError());
     return HC_OK;
@@ -418,10 +454,11 @@ hc_status compress_one(Ctx& c, const hc_gk* gk, const hc_db* db, const uint64_t*
 using namespace hc;
 
 extern "C" hc_status hc_plan(hc_context* cp, uint64_t N, uint32_t ncol, uint32_t t_bound,
-                             uint32_t* elements_out, uint32_t* count, hc_compress_info* info) {
+                             uint32_t comp_level, uint32_t* elements_out, uint32_t* count,
+                             hc_compress_info* info) {
     if (!cp || !count) return HC_EINVAL;
     Plan pl;
-    hc_status s = make_plan(*cp, N, ncol, t_bound, pl);
+    hc_status s = make_plan(*cp, N, ncol, t_bound, comp_level, pl);
     if (s != HC_OK) return s;
     fill_info(pl, info);
     uint32_t cap = *count;
@@ -433,12 +470,12 @@ extern "C" hc_status hc_plan(hc_context* cp, uint64_t N, uint32_t ncol, uint32_t
 }
 
 extern "C" hc_status hc_compress(hc_context* cp, const hc_gk* gk, const hc_db* db, const uint64_t* ct_v,
-                                 uint64_t N, uint32_t t_bound, uint64_t* ct_out, hc_compress_info* info,
-                                 hipStream_t st) {
+                                 uint64_t N, uint32_t t_bound, uint32_t comp_level, uint64_t* ct_out,
+                                 hc_compress_info* info, hipStream_t st) {
     if (!cp || !gk || !ct_v || !ct_out) return HC_EINVAL;
     HC_CHECK(hipSetDevice(cp->device));
     Plan pl;
-    hc_status s = make_plan(*cp, N, db ? db->ncol : 0, t_bound, pl);
+    hc_status s = make_plan(*cp, N, db ? db->ncol : 0, t_bound, comp_level, pl);
     if (s != HC_OK) return s;
     s = compress_one(*cp, gk, db, ct_v, pl, ct_out, st);
     if (s == HC_OK) fill_info(pl, info);
@@ -450,7 +487,8 @@ extern "C" hc_status hc_compress_batch(hc_context* cp, const hc_gk* gk, const hc
     if (!cp || !gk || (nq && !q)) return HC_EINVAL;
     hc_status first = HC_OK;
     for (uint32_t i = 0; i < nq; i++) {
-        q[i].status = hc_compress(cp, gk, db, q[i].ct_v, q[i].N, q[i].t_bound, q[i].ct_out, q[i].info, st);
+        q[i].status = hc_compress(cp, gk, db, q[i].ct_v, q[i].N, q[i].t_bound, q[i].comp_level,
+                                  q[i].ct_out, q[i].info, st);
         if (q[i].status != HC_OK && first == HC_OK) first = q[i].status;
     }
     return first;

@@ -65,10 +65,12 @@ static void host_intt(uint64_t* a, int n, const uint64_t* tw, uint64_t q, uint64
 
 using namespace hc;
 
-extern "C" hc_status hc_decrypt(hc_context* cp, const hc_sk* sk, const uint64_t* ct, uint32_t* slots_out) {
+extern "C" hc_status hc_decrypt(hc_context* cp, const hc_sk* sk, const uint64_t* ct, uint32_t level,
+                                uint32_t* slots_out) {
     if (!cp || !sk || !ct || !slots_out) return HC_EINVAL;
     Ctx& c = *cp;
-    const int n = c.n, L = c.L;
+    if (level < 1 || (int)level > c.L) return HC_EINVAL;
+    const int n = c.n, L = (int)level;
     const uint64_t p = c.p;
     std::vector<uint64_t> x((size_t)L * n), s(n), t(n);
     for (int i = 0; i < L; i++) {

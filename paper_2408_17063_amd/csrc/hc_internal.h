@@ -75,6 +75,10 @@ struct hc_context {
     uint32_t* d_cdt = nullptr;          // [20]
     uint64_t* d_keccak_rc = nullptr;    // [24]
 
+    // modulus-switching constants per target level: inv [L-Lc][2], cst [L-Lc][Lc], dinv [Lc][2]
+    struct MsTab { uint64_t* inv; uint64_t* cst; uint64_t* dinv; };
+    std::map<int, MsTab> ms_tabs;
+
     // plaintext multipliers owned by the context (NTT domain, Montgomery form, [L][n])
     uint64_t* d_rowmask[2] = {nullptr, nullptr};
     std::map<uint32_t, uint64_t*> prefix_masks;  // keyed by s
@@ -143,24 +147,35 @@ void k_permute(const Ctx& c, uint64_t* out, const uint64_t* in, int nl, uint32_t
 // out = a + b (mod), nl rows starting at prime lf, `count` polynomials of stride.
 void k_add(const Ctx& c, uint64_t* out, const uint64_t* a, const uint64_t* b, int lf, int nl,
            int count, size_t stride, hipStream_t st);
-// out[c] = ct[c] * pt (Montgomery pt) for c = 0, 1 over the L ciphertext primes.
-void k_mul_plain(const Ctx& c, uint64_t* out, const uint64_t* ct, const uint64_t* pt_mont,
+// out[c] = ct[c] * pt (Montgomery pt) for c = 0, 1 over the first Lc ciphertext primes
+// (ct and out at level Lc: [2][Lc][n]; pt rows 0..Lc-1).
+void k_mul_plain(const Ctx& c, uint64_t* out, const uint64_t* ct, const uint64_t* pt_mont, int Lc,
                  hipStream_t st);
 // ModUp of all digits: X [dnum][nq][n] (coefficient domain) from x [L][n] (coefficient domain).
-void k_modup(const Ctx& c, uint64_t* X, const uint64_t* x, int digit_first, int ndigits,
+// At level Lc the target rows are 0..Lc-1 and the special rows; the digits are those
+// inside the first Lc primes.
+void k_modup(const Ctx& c, uint64_t* X, const uint64_t* x, int digit_first, int ndigits, int Lc,
              hipStream_t st);
 // inner product: T [2][nq][n] = sum_j sigma_k(X_j) * key_j ; k = 1: no permutation.
-void k_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const uint64_t* key, uint32_t k,
+void k_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const uint64_t* key, uint32_t k, int Lc,
              hipStream_t st);
 // Conv_{P->Q}: conv [2][L][n] (coefficient) from T [2][nq][n] (special rows coefficient domain).
-void k_moddown_conv(const Ctx& c, uint64_t* conv, const uint64_t* T, hipStream_t st);
+void k_moddown_conv(const Ctx& c, uint64_t* conv, const uint64_t* T, int Lc, hipStream_t st);
 // out0 = sigma_k(c0) + (T0 - conv0) P^-1 ; out1 = (T1 - conv1) P^-1  (NTT domain)
+// (c0 and out at level Lc)
 void k_moddown_final(const Ctx& c, uint64_t* out, const uint64_t* T, const uint64_t* conv,
-                     const uint64_t* c0, uint32_t k, hipStream_t st);
+                     const uint64_t* c0, uint32_t k, int Lc, hipStream_t st);
+// modulus switching from L to Lc primes: conv [2][Lc][n] from the dropped rows of ct
+// [2][L][n] (coefficient domain); out [2][Lc][n] = (ct - conv) D^-1 (NTT domain)
+void k_ms_conv(const Ctx& c, uint64_t* conv, const uint64_t* ct, const uint64_t* inv, const uint64_t* cst,
+               int Lc, hipStream_t st);
+void k_ms_final(const Ctx& c, uint64_t* out, const uint64_t* ct, const uint64_t* conv, const uint64_t* dinv,
+                int Lc, hipStream_t st);
 // slots (device u32 [count][2][nh]) -> NTT-mod-p positions [count][n]
 void k_slots_to_eval(const Ctx& c, uint32_t* out, const uint32_t* slots, int count, hipStream_t st);
 // centred lift of mod-p coefficients [count][n] into [count][L][n]; Montgomery form if mont
-void k_lift(const Ctx& c, uint64_t* out, const uint32_t* in, int count, bool mont, hipStream_t st);
+void k_lift(const Ctx& c, uint64_t* out, const uint32_t* in, int count, bool mont, int Lc,
+            hipStream_t st);
 // compression diagonals in NTT-mod-p positions: out [count][n], params [count][3] (beta, gi, b)
 void k_diag_gen(const Ctx& c, uint32_t* out, const uint32_t* params, int count, uint32_t s,
                 uint32_t B, hipStream_t st);
@@ -191,6 +206,6 @@ void k_enc_finish(const Ctx& c, uint64_t* ct, const uint64_t* e0, const uint64_t
 // R, A given as device arrays of ciphertext pointers; D contiguous
 // [kb][G][B][L][n] (Montgomery). accumulate: add to the existing A.
 void k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* const* R, const uint64_t* D,
-                int npairs, int kb, int G, int B, bool accumulate, hipStream_t st);
+                int npairs, int kb, int G, int B, bool accumulate, int Lc, hipStream_t st);
 
 }  // namespace hc

@@ -27,21 +27,12 @@ hc_status encode_plain(Ctx& c, uint64_t* out, const uint32_t* host_slots, int co
     HC_CHECK(hipMemcpyAsync(d_slots, host_slots, sizeof(uint32_t) * n * count, hipMemcpyHostToDevice, st));
     k_slots_to_eval(c, d_eval, d_slots, count, st);
     ntt32(c, d_eval, count, true, st);
-    k_lift(c, out, d_eval, count, mont, st);
+    k_lift(c, out, d_eval, count, mont, c.L, st);
     ntt64(c, out, (size_t)c.L * n, count, 0, c.L, false, st);
     HC_CHECK(hipStreamSynchronize(st));
     HC_CHECK(hipFree(d_slots));
     HC_CHECK(hipFree(d_eval));
     return HC_OK;
-}
-
-// encode from device slots already in [count][2][nh] u32 form (no host staging)
-void encode_plain_dev(Ctx& c, uint64_t* out, const uint32_t* d_slots, uint32_t* d_eval, int count,
-                      bool mont, hipStream_t st) {
-    k_slots_to_eval(c, d_eval, d_slots, count, st);
-    ntt32(c, d_eval, count, true, st);
-    k_lift(c, out, d_eval, count, mont, st);
-    ntt64(c, out, (size_t)c.L * c.n, count, 0, c.L, false, st);
 }
 
 hc_status prefix_mask(Ctx& c, uint32_t s, const uint64_t** out) {
@@ -81,42 +72,110 @@ size_t ks_take_bytes(const Ctx& c) {
     return r((size_t)c.L * n) + r((size_t)c.dnum * c.nq * n) + r(2 * (size_t)c.nq * n) + r(2 * (size_t)c.L * n);
 }
 
-// T -> (sigma_k(c0) + ModDown(T0), ModDown(T1))
-static void moddown_into(Ctx& c, uint64_t* out, const uint64_t* c0, uint32_t k, KSBuf& b,
+// T -> (sigma_k(c0) + ModDown(T0), ModDown(T1)), output at level Lc
+static void moddown_into(Ctx& c, uint64_t* out, const uint64_t* c0, uint32_t k, KSBuf& b, int Lc,
                          hipStream_t st) {
     const size_t n = c.n;
     // special rows to coefficients (data points at the first transformed row)
     ntt64(c, b.T + (size_t)c.L * n, (size_t)c.nq * n, 2, c.L, c.K, true, st);
-    k_moddown_conv(c, b.conv, b.T, st);
-    ntt64(c, b.conv, (size_t)c.L * n, 2, 0, c.L, false, st);
-    k_moddown_final(c, out, b.T, b.conv, c0, k, st);
+    k_moddown_conv(c, b.conv, b.T, Lc, st);
+    ntt64(c, b.conv, (size_t)c.L * n, 2, 0, Lc, false, st);
+    k_moddown_final(c, out, b.T, b.conv, c0, k, Lc, st);
 }
 
-// out = Rot(in) by sigma_k, non-hoisted. in, out: NTT domain [2][L][n]; out != in.
+// NTT of the raised digits on the rows of level Lc (ciphertext rows, then special rows)
+static void ntt_raised(Ctx& c, KSBuf& b, int Lc, hipStream_t st) {
+    const size_t n = c.n;
+    const int dn = Lc / c.alpha;
+    ntt64(c, b.X, (size_t)c.nq * n, dn, 0, Lc, false, st);
+    ntt64(c, b.X + (size_t)c.L * n, (size_t)c.nq * n, dn, c.L, c.K, false, st);
+}
+
+// out = Rot(in) by sigma_k, non-hoisted. in, out: NTT domain [2][Lc][n]; out != in.
 void rotate_plain(Ctx& c, const uint64_t* key, uint32_t k, uint64_t* out, const uint64_t* in,
-                  KSBuf& b, hipStream_t st) {
-    const size_t n = c.n, Ln = (size_t)c.L * n;
-    k_permute(c, b.tmpC, in + Ln, c.L, k, 1, 0, st);
-    ntt64(c, b.tmpC, Ln, 1, 0, c.L, true, st);
-    k_modup(c, b.X, b.tmpC, 0, c.dnum, st);
-    ntt64(c, b.X, (size_t)c.nq * n, c.dnum, 0, c.nq, false, st);
-    k_inner(c, b.T, b.X, key, 1, st);
-    moddown_into(c, out, in, k, b, st);
+                  KSBuf& b, int Lc, hipStream_t st) {
+    const size_t n = c.n, Ln = (size_t)Lc * n;
+    k_permute(c, b.tmpC, in + Ln, Lc, k, 1, 0, st);
+    ntt64(c, b.tmpC, Ln, 1, 0, Lc, true, st);
+    k_modup(c, b.X, b.tmpC, 0, Lc / c.alpha, Lc, st);
+    ntt_raised(c, b, Lc, st);
+    k_inner(c, b.T, b.X, key, 1, Lc, st);
+    moddown_into(c, out, in, k, b, Lc, st);
 }
 
 // ModUp of c1 once (into b.X, NTT domain), shared by rotate_hoisted_one calls.
-void hoist_prepare(Ctx& c, const uint64_t* in, KSBuf& b, hipStream_t st) {
-    const size_t n = c.n, Ln = (size_t)c.L * n;
+void hoist_prepare(Ctx& c, const uint64_t* in, KSBuf& b, int Lc, hipStream_t st) {
+    const size_t n = c.n, Ln = (size_t)Lc * n;
     (void)hipMemcpyAsync(b.tmpC, in + Ln, sizeof(uint64_t) * Ln, hipMemcpyDeviceToDevice, st);
-    ntt64(c, b.tmpC, Ln, 1, 0, c.L, true, st);
-    k_modup(c, b.X, b.tmpC, 0, c.dnum, st);
-    ntt64(c, b.X, (size_t)c.nq * n, c.dnum, 0, c.nq, false, st);
+    ntt64(c, b.tmpC, Ln, 1, 0, Lc, true, st);
+    k_modup(c, b.X, b.tmpC, 0, Lc / c.alpha, Lc, st);
+    ntt_raised(c, b, Lc, st);
 }
 
 void rotate_hoisted_one(Ctx& c, const uint64_t* key, uint32_t k, uint64_t* out, const uint64_t* in,
-                        KSBuf& b, hipStream_t st) {
-    k_inner(c, b.T, b.X, key, k, st);
-    moddown_into(c, out, in, k, b, st);
+                        KSBuf& b, int Lc, hipStream_t st) {
+    k_inner(c, b.T, b.X, key, k, Lc, st);
+    moddown_into(c, out, in, k, b, Lc, st);
+}
+
+// Constants for dropping the primes Lc..L-1 (product D), cached per level.
+static hc_status ms_tables(Ctx& c, int Lc, const Ctx::MsTab** out) {
+    auto it = c.ms_tabs.find(Lc);
+    if (it == c.ms_tabs.end()) {
+        const int L = c.L, nd = L - Lc;
+        std::vector<uint64_t> inv(2 * (size_t)nd), cst((size_t)nd * Lc), dinv(2 * (size_t)Lc);
+        for (int j = 0; j < nd; j++) {
+            const uint64_t qj = c.primes[Lc + j];
+            uint64_t h = 1;  // (D / q_j) mod q_j
+            for (int j2 = 0; j2 < nd; j2++)
+                if (j2 != j) h = h_mulmod(h, c.primes[Lc + j2] % qj, qj);
+            inv[2 * j] = h_invmod(h, qj);
+            inv[2 * j + 1] = h_shoup_const(inv[2 * j], qj);
+            for (int i = 0; i < Lc; i++) {
+                const uint64_t qi = c.primes[i];
+                uint64_t hi = 1;
+                for (int j2 = 0; j2 < nd; j2++)
+                    if (j2 != j) hi = h_mulmod(hi, c.primes[Lc + j2] % qi, qi);
+                cst[(size_t)j * Lc + i] = h_to_mont(hi, qi);
+            }
+        }
+        for (int i = 0; i < Lc; i++) {
+            const uint64_t qi = c.primes[i];
+            uint64_t D = 1;
+            for (int j = 0; j < nd; j++) D = h_mulmod(D, c.primes[Lc + j] % qi, qi);
+            dinv[2 * i] = h_invmod(D, qi);
+            dinv[2 * i + 1] = h_shoup_const(dinv[2 * i], qi);
+        }
+        Ctx::MsTab t{};
+        HC_CHECK(hipMalloc((void**)&t.inv, sizeof(uint64_t) * inv.size()));
+        HC_CHECK(hipMalloc((void**)&t.cst, sizeof(uint64_t) * cst.size()));
+        HC_CHECK(hipMalloc((void**)&t.dinv, sizeof(uint64_t) * dinv.size()));
+        c.owned.push_back(t.inv);
+        c.owned.push_back(t.cst);
+        c.owned.push_back(t.dinv);
+        HC_CHECK(hipMemcpy(t.inv, inv.data(), sizeof(uint64_t) * inv.size(), hipMemcpyHostToDevice));
+        HC_CHECK(hipMemcpy(t.cst, cst.data(), sizeof(uint64_t) * cst.size(), hipMemcpyHostToDevice));
+        HC_CHECK(hipMemcpy(t.dinv, dinv.data(), sizeof(uint64_t) * dinv.size(), hipMemcpyHostToDevice));
+        it = c.ms_tabs.emplace(Lc, t).first;
+    }
+    *out = &it->second;
+    return HC_OK;
+}
+
+// out [2][Lc][n] = in [2][L][n] with the primes Lc..L-1 dropped (NTT domain in and out).
+// tmp: 2 L n words; conv: 2 Lc n words.
+hc_status mod_switch(Ctx& c, uint64_t* out, const uint64_t* in, int Lc, uint64_t* tmp, uint64_t* conv,
+                     hipStream_t st) {
+    const Ctx::MsTab* t = nullptr;
+    hc_status s = ms_tables(c, Lc, &t);
+    if (s != HC_OK) return s;
+    const size_t n = c.n, Ln = (size_t)c.L * n;
+    HC_CHECK(hipMemcpyAsync(tmp, in, sizeof(uint64_t) * 2 * Ln, hipMemcpyDeviceToDevice, st));
+    ntt64(c, tmp + (size_t)Lc * n, Ln, 2, Lc, c.L - Lc, true, st);  // dropped rows to coefficients
+    k_ms_conv(c, conv, tmp, t->inv, t->cst, Lc, st);
+    ntt64(c, conv, (size_t)Lc * n, 2, 0, Lc, false, st);
+    k_ms_final(c, out, in, conv, t->dinv, Lc, st);
+    return HC_OK;
 }
 
 const uint64_t* find_key(const hc_gk* gk, uint32_t k) {
@@ -342,10 +401,10 @@ static hc_status rotate_common(hc_context* cp, const hc_gk* gk, const uint32_t* 
     if (!b.tmpC || !b.X || !b.T || !b.conv || !inN || !outN) return HC_ENOMEM;
     HC_CHECK(hipMemcpyAsync(inN, ct_in, sizeof(uint64_t) * Ln2, hipMemcpyDeviceToDevice, st));
     ntt64(c, inN, (size_t)c.L * c.n, 2, 0, c.L, false, st);
-    if (hoisted) hoist_prepare(c, inN, b, st);
+    if (hoisted) hoist_prepare(c, inN, b, c.L, st);
     for (uint32_t i = 0; i < count; i++) {
-        if (hoisted) rotate_hoisted_one(c, keys[i], elts[i], outN, inN, b, st);
-        else rotate_plain(c, keys[i], elts[i], outN, inN, b, st);
+        if (hoisted) rotate_hoisted_one(c, keys[i], elts[i], outN, inN, b, c.L, st);
+        else rotate_plain(c, keys[i], elts[i], outN, inN, b, c.L, st);
         ntt64(c, outN, (size_t)c.L * c.n, 2, 0, c.L, true, st);
         HC_CHECK(hipMemcpyAsync(cts_out + i * Ln2, outN, sizeof(uint64_t) * Ln2, hipMemcpyDeviceToDevice, st));
     }
@@ -380,7 +439,7 @@ extern "C" hc_status hc_mul_plain(hc_context* cp, const uint64_t* ct_in, const u
     if (s != HC_OK) return s;
     HC_CHECK(hipMemcpyAsync(tmp, ct_in, sizeof(uint64_t) * 2 * Ln, hipMemcpyDeviceToDevice, st));
     ntt64(c, tmp, Ln, 2, 0, c.L, false, st);
-    k_mul_plain(c, tmp, tmp, pt, st);
+    k_mul_plain(c, tmp, tmp, pt, c.L, st);
     ntt64(c, tmp, Ln, 2, 0, c.L, true, st);
     HC_CHECK(hipMemcpyAsync(ct_out, tmp, sizeof(uint64_t) * 2 * Ln, hipMemcpyDeviceToDevice, st));
     HC_CHECK(hipStreamSynchronize(st));
@@ -391,7 +450,7 @@ extern "C" hc_status hc_modup(hc_context* cp, const uint64_t* x, uint32_t digit,
                               hipStream_t st) {
     if (!cp || !x || !out || digit >= (uint32_t)cp->dnum) return HC_EINVAL;
     HC_CHECK(hipSetDevice(cp->device));
-    k_modup(*cp, out, x, (int)digit, 1, st);
+    k_modup(*cp, out, x, (int)digit, 1, cp->L, st);
     HC_CHECK(hipGetLastError());
     return HC_OK;
 }
@@ -413,8 +472,8 @@ extern "C" hc_status hc_moddown(hc_context* cp, const uint64_t* T, uint64_t* out
     HC_CHECK(hipMemsetAsync(TT, 0, sizeof(uint64_t) * 2 * c.nq * n, st));
     HC_CHECK(hipMemsetAsync(zero, 0, sizeof(uint64_t) * c.L * n, st));
     HC_CHECK(hipMemcpyAsync(TT, T, sizeof(uint64_t) * c.nq * n, hipMemcpyDeviceToDevice, st));
-    k_moddown_conv(c, conv, TT, st);
-    k_moddown_final(c, o2, TT, conv, zero, 1, st);
+    k_moddown_conv(c, conv, TT, c.L, st);
+    k_moddown_final(c, o2, TT, conv, zero, 1, c.L, st);
     HC_CHECK(hipMemcpyAsync(out, o2, sizeof(uint64_t) * c.L * n, hipMemcpyDeviceToDevice, st));
     HC_CHECK(hipStreamSynchronize(st));
     return HC_OK;
@@ -450,7 +509,7 @@ extern "C" hc_status hc_encode_diagonal(hc_context* cp, uint32_t s, uint32_t B, 
     HC_CHECK(hipMemcpyAsync(d + c.n, prm, sizeof(prm), hipMemcpyHostToDevice, st));
     k_diag_gen(c, d, d + c.n, 1, s, B, st);
     ntt32(c, d, 1, true, st);
-    k_lift(c, out, d, 1, false, st);
+    k_lift(c, out, d, 1, false, c.L, st);
     HC_CHECK(hipStreamSynchronize(st));
     HC_CHECK(hipFree(d));
     return HC_OK;

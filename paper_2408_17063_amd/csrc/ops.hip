@@ -5,6 +5,7 @@
 // element-wise over (row, coefficient) -- one thread per coefficient, rows
 // along grid.y -- so all accesses are unit-stride across a wavefront, except
 // the automorphism gathers (a fixed permutation within a row).
+#include <algorithm>
 #include <cstring>
 
 #include "hc_internal.h"
@@ -58,6 +59,7 @@ void k_add(const Ctx& c, uint64_t* out, const uint64_t* a, const uint64_t* b, in
 
 __global__ void mul_plain_kernel(uint64_t* out, const uint64_t* ct, const uint64_t* pt,
                                  const uint64_t* mods, const uint64_t* qinv, int n, int L) {
+    // L: ciphertext primes of this ciphertext (its component stride is L n)
     int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     int r = blockIdx.y;
@@ -69,10 +71,10 @@ __global__ void mul_plain_kernel(uint64_t* out, const uint64_t* ct, const uint64
     out[o1] = mont_mul(v1, m, q, qi);
 }
 
-void k_mul_plain(const Ctx& c, uint64_t* out, const uint64_t* ct, const uint64_t* pt_mont,
+void k_mul_plain(const Ctx& c, uint64_t* out, const uint64_t* ct, const uint64_t* pt_mont, int Lc,
                  hipStream_t st) {
-    hipLaunchKernelGGL(mul_plain_kernel, ew_grid(c.n, c.L), dim3(EW_THREADS), 0, st, out, ct,
-                       pt_mont, c.d_mods, c.d_qinv, c.n, c.L);
+    hipLaunchKernelGGL(mul_plain_kernel, ew_grid(c.n, Lc), dim3(EW_THREADS), 0, st, out, ct,
+                       pt_mont, c.d_mods, c.d_qinv, c.n, Lc);
 }
 
 __global__ void mul_mont_kernel(uint64_t* out, const uint64_t* a, const uint64_t* bm,
@@ -119,7 +121,7 @@ void k_from_mont(const Ctx& c, uint64_t* x, int lf, int nl, int count, size_t st
 __global__ void modup_kernel(uint64_t* __restrict__ X, const uint64_t* __restrict__ x,
                              const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv,
                              const uint64_t* __restrict__ inv, const uint64_t* __restrict__ cst,
-                             int n, int nq, int alpha, int digit_first) {
+                             int n, int nq, int alpha, int digit_first, int Lc, int L) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int j = digit_first + blockIdx.y;
@@ -135,19 +137,21 @@ __global__ void modup_kernel(uint64_t* __restrict__ X, const uint64_t* __restric
     const uint64_t* cj = cst + (size_t)j * alpha * nq;
     for (int r = 0; r < nq; r++) {
         if (r >= j * alpha && r < (j + 1) * alpha) continue;
+        if (r >= Lc && r < L) continue;  // primes dropped at this level
         u128p acc{0, 0};
         for (int a = 0; a < alpha; a++) add128(acc, mul128(y[a], cj[(size_t)a * nq + r]));
         out[(size_t)r * n + i] = redc(acc, mods[r], qinv[r]);
     }
 }
 
-void k_modup(const Ctx& c, uint64_t* X, const uint64_t* x, int digit_first, int ndigits,
+void k_modup(const Ctx& c, uint64_t* X, const uint64_t* x, int digit_first, int ndigits, int Lc,
              hipStream_t st) {
     const double n = c.n;
-    TimeScope ts(c, HC_KT_MODUP, st, 8.0 * n * ((double)ndigits * c.alpha + (double)ndigits * c.nq),
-                 n * ndigits * (double)(c.nq - c.alpha) * c.alpha);
+    const int rows = Lc + c.K;
+    TimeScope ts(c, HC_KT_MODUP, st, 8.0 * n * ((double)ndigits * c.alpha + (double)ndigits * rows),
+                 n * ndigits * (double)(rows - c.alpha) * c.alpha);
     hipLaunchKernelGGL(modup_kernel, ew_grid(c.n, ndigits), dim3(EW_THREADS), 0, st, X, x, c.d_mods,
-                       c.d_qinv, c.d_modup_inv, c.d_modup_c, c.n, c.nq, c.alpha, digit_first);
+                       c.d_qinv, c.d_modup_inv, c.d_modup_c, c.n, c.nq, c.alpha, digit_first, Lc, c.L);
 }
 
 // T[c][r][i] = sum_j X_j[r][src(i)] * key_j[c][r][i]; key in Montgomery form, so one
@@ -155,10 +159,11 @@ void k_modup(const Ctx& c, uint64_t* X, const uint64_t* x, int digit_first, int 
 __global__ void inner_kernel(uint64_t* __restrict__ T, const uint64_t* __restrict__ X,
                              const uint64_t* __restrict__ key, const uint64_t* __restrict__ mods,
                              const uint64_t* __restrict__ qinv, int n, int logn, int nq, int dnum,
-                             uint32_t k) {
+                             uint32_t k, int Lc, int L) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int r = blockIdx.y;
+    // rows of this level: ciphertext primes 0..Lc-1, then the special primes
+    const int r = (int)blockIdx.y < Lc ? (int)blockIdx.y : L + ((int)blockIdx.y - Lc);
     const uint32_t src = (k == 1) ? i : galois_src(i, k, logn);
     const size_t row = (size_t)nq * n;
     u128p a0{0, 0}, a1{0, 0};
@@ -173,14 +178,14 @@ __global__ void inner_kernel(uint64_t* __restrict__ T, const uint64_t* __restric
     T[row + (size_t)r * n + i] = redc(a1, q, qi);
 }
 
-void k_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const uint64_t* key, uint32_t k,
+void k_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const uint64_t* key, uint32_t k, int Lc,
              hipStream_t st) {
     // must read the key (dnum x 2 rows per prime) and the raised digits, write T
-    const double rows = (double)c.nq * c.n;
-    TimeScope ts(c, HC_KT_KS_INNER, st, 8.0 * rows * (2.0 * c.dnum + c.dnum + 2.0),
-                 2.0 * c.dnum * rows);
-    hipLaunchKernelGGL(inner_kernel, ew_grid(c.n, c.nq), dim3(EW_THREADS), 0, st, T, X, key,
-                       c.d_mods, c.d_qinv, c.n, c.logn, c.nq, c.dnum, k);
+    const int dn = Lc / c.alpha;
+    const double rows = (double)(Lc + c.K) * c.n;
+    TimeScope ts(c, HC_KT_KS_INNER, st, 8.0 * rows * (2.0 * dn + dn + 2.0), 2.0 * dn * rows);
+    hipLaunchKernelGGL(inner_kernel, ew_grid(c.n, Lc + c.K), dim3(EW_THREADS), 0, st, T, X, key,
+                       c.d_mods, c.d_qinv, c.n, c.logn, c.nq, dn, k, Lc, c.L);
 }
 
 // conv[c][i][x] = sum_k [T_{p_k}(x) (P/p_k)^-1]_{p_k} (P/p_k) mod q_i
@@ -204,15 +209,16 @@ __global__ void moddown_conv_kernel(uint64_t* __restrict__ conv, const uint64_t*
     conv[(size_t)comp * L * n + (size_t)i * n + x] = redc(acc, mods[i], qinv[i]);
 }
 
-void k_moddown_conv(const Ctx& c, uint64_t* conv, const uint64_t* T, hipStream_t st) {
-    hipLaunchKernelGGL(moddown_conv_kernel, ew_grid(c.n, c.L, 2), dim3(EW_THREADS), 0, st, conv, T,
+void k_moddown_conv(const Ctx& c, uint64_t* conv, const uint64_t* T, int Lc, hipStream_t st) {
+    hipLaunchKernelGGL(moddown_conv_kernel, ew_grid(c.n, Lc, 2), dim3(EW_THREADS), 0, st, conv, T,
                        c.d_mods, c.d_qinv, c.d_moddown_inv, c.d_moddown_c, c.n, c.L, c.K);
 }
 
 __global__ void moddown_final_kernel(uint64_t* __restrict__ out, const uint64_t* __restrict__ T,
                                      const uint64_t* __restrict__ conv, const uint64_t* __restrict__ c0,
                                      const uint64_t* __restrict__ mods, const uint64_t* __restrict__ pinv,
-                                     int n, int logn, int L, int K, uint32_t k) {
+                                     int n, int logn, int L, int K, uint32_t k, int Lc) {
+    // T [2][L+K][n], conv [2][L][n]; c0 and out at level Lc (component stride Lc n)
     int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     const int i = blockIdx.y;
@@ -226,13 +232,69 @@ __global__ void moddown_final_kernel(uint64_t* __restrict__ out, const uint64_t*
     d1 = shoup(d1, pi, pis, q);
     uint32_t src = (k == 1) ? x : galois_src(x, k, logn);
     out[o] = add_mod(d0, c0[(size_t)i * n + src], q);
-    out[(size_t)L * n + o] = d1;
+    out[(size_t)Lc * n + o] = d1;
 }
 
 void k_moddown_final(const Ctx& c, uint64_t* out, const uint64_t* T, const uint64_t* conv,
-                     const uint64_t* c0, uint32_t k, hipStream_t st) {
-    hipLaunchKernelGGL(moddown_final_kernel, ew_grid(c.n, c.L), dim3(EW_THREADS), 0, st, out, T, conv,
-                       c0, c.d_mods, c.d_pinv, c.n, c.logn, c.L, c.K, k);
+                     const uint64_t* c0, uint32_t k, int Lc, hipStream_t st) {
+    hipLaunchKernelGGL(moddown_final_kernel, ew_grid(c.n, Lc), dim3(EW_THREADS), 0, st, out, T, conv,
+                       c0, c.d_mods, c.d_pinv, c.n, c.logn, c.L, c.K, k, Lc);
+}
+
+// ------------------------------------------------------------------ modulus switching
+
+// conv[c][i][x] = sum_{j dropped} [ct_j(x) (D/q_j)^-1]_{q_j} (D/q_j) mod q_i  for kept i < Lc;
+// ct [2][L][n] with the dropped rows Lc..L-1 in the coefficient domain.
+__global__ void ms_conv_kernel(uint64_t* __restrict__ conv, const uint64_t* __restrict__ ct,
+                               const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv,
+                               const uint64_t* __restrict__ inv, const uint64_t* __restrict__ cst,
+                               int n, int L, int Lc, int fold) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int comp = blockIdx.z, i = blockIdx.y, nd = L - Lc;
+    const uint64_t qi = mods[i], qii = qinv[i];
+    const uint64_t* cc = ct + (size_t)comp * L * n;
+    u128p acc{0, 0};
+    uint64_t sum = 0;
+    int terms = 0;
+    for (int j = 0; j < nd; j++) {
+        const int r = Lc + j;
+        uint64_t y = shoup(cc[(size_t)r * n + x], inv[2 * j], inv[2 * j + 1], mods[r]);
+        add128(acc, mul128(y, cst[(size_t)j * Lc + i]));
+        if (++terms == fold) {  // keep each 128-bit sum below q_i 2^64
+            sum = add_mod(sum, redc(acc, qi, qii), qi);
+            acc = u128p{0, 0};
+            terms = 0;
+        }
+    }
+    conv[((size_t)comp * Lc + i) * n + x] = add_mod(sum, redc(acc, qi, qii), qi);
+}
+
+// out[c][i] = (ct[c][i] - conv[c][i]) D^-1 mod q_i (NTT domain), out at level Lc
+__global__ void ms_final_kernel(uint64_t* __restrict__ out, const uint64_t* __restrict__ ct,
+                                const uint64_t* __restrict__ conv, const uint64_t* __restrict__ mods,
+                                const uint64_t* __restrict__ dinv, int n, int L, int Lc) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int comp = blockIdx.z, i = blockIdx.y;
+    const uint64_t q = mods[i];
+    uint64_t d = sub_mod(ct[((size_t)comp * L + i) * n + x], conv[((size_t)comp * Lc + i) * n + x], q);
+    out[((size_t)comp * Lc + i) * n + x] = shoup(d, dinv[2 * i], dinv[2 * i + 1], q);
+}
+
+void k_ms_conv(const Ctx& c, uint64_t* conv, const uint64_t* ct, const uint64_t* inv, const uint64_t* cst,
+               int Lc, hipStream_t st) {
+    uint64_t qmax = 0;
+    for (int i = 0; i < c.L; i++) qmax = qmax > c.primes[i] ? qmax : c.primes[i];
+    int fold = (int)std::min<uint64_t>(1024, (~0ull) / qmax);
+    hipLaunchKernelGGL(ms_conv_kernel, ew_grid(c.n, Lc, 2), dim3(EW_THREADS), 0, st, conv, ct, c.d_mods,
+                       c.d_qinv, inv, cst, c.n, c.L, Lc, fold < 1 ? 1 : fold);
+}
+
+void k_ms_final(const Ctx& c, uint64_t* out, const uint64_t* ct, const uint64_t* conv, const uint64_t* dinv,
+                int Lc, hipStream_t st) {
+    hipLaunchKernelGGL(ms_final_kernel, ew_grid(c.n, Lc, 2), dim3(EW_THREADS), 0, st, out, ct, conv,
+                       c.d_mods, dinv, c.n, c.L, Lc);
 }
 
 // ------------------------------------------------------------------ encoding
@@ -263,9 +325,10 @@ __global__ void lift_kernel(uint64_t* out, const uint32_t* in, const uint64_t* m
     out[((size_t)blockIdx.z * L + r) * n + x] = v;
 }
 
-void k_lift(const Ctx& c, uint64_t* out, const uint32_t* in, int count, bool mont, hipStream_t st) {
-    hipLaunchKernelGGL(lift_kernel, ew_grid(c.n, c.L, count), dim3(EW_THREADS), 0, st, out, in,
-                       c.d_mods, c.d_qinv, c.d_r2, c.n, c.L, (uint32_t)c.p, mont ? 1 : 0);
+void k_lift(const Ctx& c, uint64_t* out, const uint32_t* in, int count, bool mont, int Lc,
+            hipStream_t st) {
+    hipLaunchKernelGGL(lift_kernel, ew_grid(c.n, Lc, count), dim3(EW_THREADS), 0, st, out, in,
+                       c.d_mods, c.d_qinv, c.d_r2, c.n, Lc, (uint32_t)c.p, mont ? 1 : 0);
 }
 
 __device__ __forceinline__ uint32_t mulmod_p(uint32_t a, uint32_t b, uint32_t p, double pinv) {
@@ -560,7 +623,7 @@ __global__ void diag_mac_kernel(uint64_t* const* __restrict__ A, const uint64_t*
 }
 
 void k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* const* R, const uint64_t* D,
-                int npairs, int kb, int G, int B, bool accumulate, hipStream_t st) {
+                int npairs, int kb, int G, int B, bool accumulate, int Lc, hipStream_t st) {
     // terms per 128-bit accumulator before it must be folded: t q^2 < q 2^64
     uint64_t qmax = 0;
     for (int i = 0; i < c.L; i++) qmax = qmax > c.primes[i] ? qmax : c.primes[i];
@@ -570,14 +633,14 @@ void k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* const* R, cons
     constexpr int GC = 4;
     for (int g0 = 0; g0 < G; g0 += GC) {
         const int gc = (G - g0) < GC ? (G - g0) : GC;
-        const double ln = (double)c.L * c.n;
+        const double ln = (double)Lc * c.n;
         // reads each R (both components) and each D once, writes each A once
         TimeScope ts(c, HC_KT_DIAG_MAC, st,
                      8.0 * ln * (2.0 * npairs * kb * B + (double)kb * gc * B +
                                  (accumulate ? 4.0 : 2.0) * npairs * gc),
                      2.0 * ln * npairs * kb * B * gc);
-        hipLaunchKernelGGL((diag_mac_kernel<GC>), ew_grid(c.n, c.L, npairs), dim3(EW_THREADS), 0, st,
-                           A, R, D, c.d_mods, c.d_qinv, c.n, c.L, kb, G, B, g0, (int)chunk,
+        hipLaunchKernelGGL((diag_mac_kernel<GC>), ew_grid(c.n, Lc, npairs), dim3(EW_THREADS), 0, st,
+                           A, R, D, c.d_mods, c.d_qinv, c.n, Lc, kb, G, B, g0, (int)chunk,
                            accumulate ? 1 : 0);
     }
 }

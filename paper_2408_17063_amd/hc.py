@@ -46,7 +46,7 @@ class CompressInfo(ctypes.Structure):
     _fields_ = [("s", ctypes.c_uint32), ("groups", ctypes.c_uint32), ("streams", ctypes.c_uint32),
                 ("bands", ctypes.c_uint32), ("n_ct", ctypes.c_uint32),
                 ("n_keyswitch", ctypes.c_uint32), ("n_ptct", ctypes.c_uint64),
-                ("n_diag", ctypes.c_uint64)]
+                ("n_diag", ctypes.c_uint64), ("level", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -54,7 +54,8 @@ class CompressInfo(ctypes.Structure):
 
 class Query(ctypes.Structure):
     _fields_ = [("ct_v", c_vp), ("N", ctypes.c_uint64), ("t_bound", ctypes.c_uint32),
-                ("ct_out", c_vp), ("info", ctypes.POINTER(CompressInfo)), ("status", ctypes.c_int)]
+                ("comp_level", ctypes.c_uint32), ("ct_out", c_vp), ("info", ctypes.POINTER(CompressInfo)),
+                ("status", ctypes.c_int)]
 
 
 def _sig(name, res, *args):
@@ -74,15 +75,15 @@ _sig("hc_sk_destroy", None, c_vp)
 _sig("hc_pk_destroy", None, c_vp)
 _sig("hc_galois_keygen", _st, c_vp, c_vp, c_u32p, ctypes.c_uint32, c_u8p, ctypes.POINTER(c_vp))
 _sig("hc_gk_destroy", None, c_vp)
-_sig("hc_plan", _st, c_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, c_u32p,
+_sig("hc_plan", _st, c_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, c_u32p,
      ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(CompressInfo))
 _sig("hc_db_upload", _st, c_vp, c_u32p, ctypes.c_uint32, ctypes.c_uint64, ctypes.POINTER(c_vp))
 _sig("hc_db_destroy", None, c_vp)
 _sig("hc_encrypt", _st, c_vp, c_vp, c_u32p, c_u8p, c_vp, c_vp)
-_sig("hc_compress", _st, c_vp, c_vp, c_vp, c_vp, ctypes.c_uint64, ctypes.c_uint32, c_vp,
+_sig("hc_compress", _st, c_vp, c_vp, c_vp, c_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, c_vp,
      ctypes.POINTER(CompressInfo), c_vp)
 _sig("hc_compress_batch", _st, c_vp, c_vp, c_vp, ctypes.POINTER(Query), ctypes.c_uint32, c_vp)
-_sig("hc_decrypt", _st, c_vp, c_vp, c_u64p, c_u32p)
+_sig("hc_decrypt", _st, c_vp, c_vp, c_u64p, ctypes.c_uint32, c_u32p)
 _sig("hc_decompress", _st, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
      c_u32p, c_u32p, c_u64p, c_u32p, c_u32p)
 _sig("hc_ntt", _st, c_vp, c_vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, c_vp)
@@ -195,16 +196,16 @@ class Context:
                                      ctypes.byref(gk)), "hc_galois_keygen")
         return GaloisKeys(self, gk, [int(x) for x in arr])
 
-    def plan(self, N, ncol, t_bound):
+    def plan(self, N, ncol, t_bound, comp_level=0):
         cnt = ctypes.c_uint32(0)
         info = CompressInfo()
-        st = _lib.hc_plan(self.h, N, ncol, t_bound, None, ctypes.byref(cnt), ctypes.byref(info))
+        st = _lib.hc_plan(self.h, N, ncol, t_bound, comp_level, None, ctypes.byref(cnt), ctypes.byref(info))
         if st not in (HC_OK, HC_EINVAL) or (st == HC_EINVAL and cnt.value == 0):
             _check(st, "hc_plan")
         arr = np.zeros(max(cnt.value, 1), dtype=np.uint32)
         cap = ctypes.c_uint32(len(arr))
-        _check(_lib.hc_plan(self.h, N, ncol, t_bound, _np_ptr(arr, ctypes.c_uint32), ctypes.byref(cap),
-                            ctypes.byref(info)), "hc_plan")
+        _check(_lib.hc_plan(self.h, N, ncol, t_bound, comp_level, _np_ptr(arr, ctypes.c_uint32),
+                            ctypes.byref(cap), ctypes.byref(info)), "hc_plan")
         return [int(x) for x in arr[:cap.value]], info.as_dict()
 
     def db_upload(self, cols):
@@ -228,14 +229,20 @@ class Context:
                                _stream(stream)), "hc_encrypt")
         return out
 
-    def compress(self, gk, db, ct_v, N, t_bound, out=None, stream=None):
+    def compress(self, gk, db, ct_v, N, t_bound, out=None, stream=None, comp_level=0):
+        """Returns (out buffer, info); output() extracts the [2][level][n] ciphertext."""
         out = self.ct_tensor(1)[0] if out is None else out
         info = CompressInfo()
         _check(_lib.hc_compress(self.h, gk.h, db.h if db is not None else None, _dev(ct_v), N, t_bound,
-                                _dev(out), ctypes.byref(info), _stream(stream)), "hc_compress")
+                                comp_level, _dev(out), ctypes.byref(info), _stream(stream)), "hc_compress")
         return out, info.as_dict()
 
-    def compress_batch(self, gk, db, queries, stream=None):
+    def output(self, out, info):
+        """The [2][level][n] output ciphertext inside an hc_compress output buffer."""
+        lvl = info["level"]
+        return out.reshape(-1)[:2 * lvl * self.n].reshape(2, lvl, self.n)
+
+    def compress_batch(self, gk, db, queries, stream=None, comp_level=0):
         """queries: list of (ct_v tensor, N, t_bound, out tensor)."""
         arr = (Query * len(queries))()
         infos = [CompressInfo() for _ in queries]
@@ -243,6 +250,7 @@ class Context:
             arr[i].ct_v = _dev(ctv).value
             arr[i].N = N
             arr[i].t_bound = t
+            arr[i].comp_level = comp_level
             arr[i].ct_out = _dev(out).value
             arr[i].info = ctypes.pointer(infos[i])
         st = _lib.hc_compress_batch(self.h, gk.h, db.h if db is not None else None, arr, len(queries),
@@ -250,10 +258,13 @@ class Context:
         return st, [arr[i].status for i in range(len(queries))], [x.as_dict() for x in infos]
 
     def decrypt(self, sk, ct_host):
-        ct = np.ascontiguousarray(ct_host, dtype=np.uint64).reshape(2, self.L, self.n)
+        """ct_host: [2][level][n] (level inferred from the size)."""
+        ct = np.ascontiguousarray(ct_host, dtype=np.uint64)
+        level = ct.size // (2 * self.n)
+        ct = ct.reshape(2, level, self.n)
         out = np.zeros((2, self.nh), dtype=np.uint32)
-        _check(_lib.hc_decrypt(self.h, sk.h, _np_ptr(ct, ctypes.c_uint64), _np_ptr(out, ctypes.c_uint32)),
-               "hc_decrypt")
+        _check(_lib.hc_decrypt(self.h, sk.h, _np_ptr(ct, ctypes.c_uint64), level,
+                               _np_ptr(out, ctypes.c_uint32)), "hc_decrypt")
         return out
 
     # ---- kernel-level

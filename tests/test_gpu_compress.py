@@ -17,7 +17,7 @@ from tests.gpu_common import context, oracle_params, to_dev, to_host, say
 pytestmark = pytest.mark.gpu
 
 
-def lib_run(wl_name, t=None, N=None, query=0, t_bound=None):
+def lib_run(wl_name, t=None, N=None, query=0, t_bound=None, comp_level=0):
     from oracle import compress as C, slots
     wl = W.WORKLOADS[wl_name]
     ctx = context(wl.ring)
@@ -25,7 +25,7 @@ def lib_run(wl_name, t=None, N=None, query=0, t_bound=None):
     t_matches = wl.t if t is None else t
     t = t_matches if t_bound is None else t_bound
     v, db = W.query_inputs(wl, query=query, t=t_matches, N=N)
-    keys, info = ctx.plan(N, wl.ncol, t)
+    keys, info = ctx.plan(N, wl.ncol, t, comp_level)
     sk_seed, gk_seed = W.seed32("sk", 0), W.seed32("gk", 0)
     sk, pk = ctx.keygen(sk_seed)
     gk = ctx.galois_keygen(sk, keys, gk_seed)
@@ -35,7 +35,8 @@ def lib_run(wl_name, t=None, N=None, query=0, t_bound=None):
     cts = ctx.ct_tensor(n_ct)
     for i in range(n_ct):
         ctx.encrypt(pk, vm[i], W.seed32("enc", query, i), out=cts[i])
-    out, info = ctx.compress(gk, dbh, cts, N, t)
+    out, info = ctx.compress(gk, dbh, cts, N, t, comp_level=comp_level)
+    out = ctx.output(out, info)
     return dict(ctx=ctx, sk=sk, pk=pk, gk=gk, db=dbh, v=v, dbv=db, cts=cts, out=out, info=info,
                 keys=keys, N=N, t=t, wl=wl)
 
@@ -63,13 +64,16 @@ def check_decrypts(run):
     return sched
 
 
-@pytest.mark.parametrize("wl_name", ["tiny-1024", "plain-4096", "multi-2048"])
-def test_compress_bit_identical_to_oracle(wl_name):
+@pytest.mark.parametrize("wl_name,comp_level", [("tiny-1024", 0), ("plain-4096", 0), ("multi-2048", 0),
+                                                ("multi-2048", 4)])
+def test_compress_bit_identical_to_oracle(wl_name, comp_level):
     from oracle import bfv, compress as C, slots
-    say("compress parity", wl_name)
-    run = lib_run(wl_name)
+    say("compress parity", wl_name, comp_level)
+    run = lib_run(wl_name, comp_level=comp_level)
     wl = run["wl"]
     pr = oracle_params(wl.ring)
+    level = comp_level or C.default_level(pr)
+    assert run["info"]["level"] == level
     sched = C.make_schedule(pr.n, pr.p, wl.N, wl.ncol, wl.t)
     assert sorted(run["keys"]) == sched.keys
     osk, opk = bfv.keygen(pr, W.seed32("sk", 0))
@@ -78,11 +82,11 @@ def test_compress_bit_identical_to_oracle(wl_name):
     octs = [bfv.encrypt(pr, opk, vm[i], W.seed32("enc", 0, i)) for i in range(sched.n_ct)]
     for i in range(sched.n_ct):
         assert np.array_equal(to_host(run["cts"][i]), octs[i].stack()), i
-    want = C.compress(pr, sched, octs, run["dbv"], gks)
+    want = C.compress(pr, sched, octs, run["dbv"], gks, level=level)
     got = to_host(run["out"])
     assert np.array_equal(got, want.stack())
     # decryption on the library's host path agrees with the oracle's
-    assert np.array_equal(run["ctx"].decrypt(run["sk"], got), bfv.decrypt(pr, osk, want))
+    assert np.array_equal(run["ctx"].decrypt(run["sk"], got), bfv.decrypt(bfv.at_level(pr, level), osk, want))
     check_decrypts(run)
     assert run["info"]["bands"] == sched.bands and run["info"]["s"] == sched.s
 
@@ -118,3 +122,17 @@ def test_missing_key_and_bad_shapes():
     with pytest.raises(hc.HcError) as e:
         ctx.plan(1024, 4, 300)  # 3 bands x 512 slots > 512
     assert e.value.status == hc.HC_EINVAL
+
+
+def test_mod_switch_and_full_level_agree_on_values():
+    """The same query compressed at the top level and at the default level
+    decrypts to the same bands (only the modulus of the output differs)."""
+    say("levels")
+    lo = lib_run("multi-2048")
+    hi = lib_run("multi-2048", comp_level=4)
+    assert lo["info"]["level"] == 2 and hi["info"]["level"] == 4
+    a = lo["ctx"].decrypt(lo["sk"], to_host(lo["out"]))
+    b = hi["ctx"].decrypt(hi["sk"], to_host(hi["out"]))
+    s = lo["info"]["s"]
+    for band in range(lo["info"]["bands"]):
+        assert np.array_equal(a[:, band * s:(band + 1) * s], b[:, band * s:(band + 1) * s])

@@ -389,7 +389,8 @@ def run_pipeline(wl_name):
 @pytest.mark.parametrize("wl_name", ["tiny-1024", "plain-4096", "multi-2048"])
 def test_compress_decrypts_to_vandermonde_and_decompresses(wl_name):
     pr, sc, sk, v, db, out = run_pipeline(wl_name)
-    assert bfv.noise_bits(pr, sk, out) < bfv.noise_budget_bits(pr)
+    pr = bfv.at_level(pr, len(out.c0.mods))
+    assert bfv.noise_bits(pr, sk, out) < bfv.noise_budget_bits(pr) - 8
     dec = bfv.decrypt(pr, sk, out)
     exp = C.expected_bands(sc, v, db)
     S = len(sc.streams)
@@ -416,3 +417,33 @@ def test_missing_key_is_reported():
     ct = bfv.encrypt(pr, pk, np.zeros((2, pr.nh), dtype=np.uint64), bytes(32))
     with pytest.raises(KeyError):
         C.compress(pr, sc, [ct], np.zeros((1, 1024), dtype=np.uint32), gks)
+
+
+def test_mod_switch_divides_by_dropped_primes(p4096):
+    """Dropping primes q_{l+1..L} (product D): the result is floor(c / D) minus a
+    basis-conversion overflow in [0, L-l), and decrypts to the same slots."""
+    pr = make_params(4096, 65537, 4, 54, 2, 60)
+    sk, pk = bfv.keygen(pr, bytes(32))
+    sl = np.random.default_rng(8).integers(0, pr.p, size=(2, pr.nh))
+    ct = bfv.encrypt(pr, pk, sl, bytes([5] * 32))
+    lo = bfv.mod_switch(pr, ct, 2)
+    plo = bfv.at_level(pr, 2)
+    assert np.array_equal(bfv.decrypt(plo, sk, lo), sl)
+    D = pr.q[2] * pr.q[3]
+    for comp, comp_lo in ((ct.c0, lo.c0), (ct.c1, lo.c1)):
+        for coef in range(0, pr.n, 257):
+            c = exact_crt(comp.c[:, coef], pr.q)
+            got = exact_crt(comp_lo.c[:, coef], plo.q)
+            want = c // D
+            assert any(got == (want - u) % plo.Q for u in range(2))
+
+
+def test_restricted_key_switches_at_lower_level():
+    pr = make_params(4096, 65537, 4, 54, 2, 60)
+    sk, pk = bfv.keygen(pr, bytes(32))
+    sl = np.random.default_rng(9).integers(0, pr.p, size=(2, pr.nh))
+    plo = bfv.at_level(pr, 2)
+    ct = bfv.mod_switch(pr, bfv.encrypt(pr, pk, sl, bytes([6] * 32)), 2)
+    k = bfv.rot_row_element(pr, 3)
+    gk = bfv.key_at_level(pr, bfv.galois_keygen(pr, sk, k, bytes([7] * 32)), 2)
+    assert np.array_equal(bfv.decrypt(plo, sk, bfv.rotate(plo, ct, gk)), np.roll(sl, -3, axis=1))
