@@ -149,300 +149,302 @@ static void fill_info(const Plan& pl, hc_compress_info* info) {
     info->level = (uint32_t)pl.level;
 }
 
-// bytes of device memory one compression needs beyond its inputs and output
+// Device memory one compression needs beyond its inputs and output.
 struct Layout {
-    size_t ct_words;        // one ciphertext [2][L][n]
-    size_t pt_words;        // one plaintext [L][n]
+    size_t CW, PW, CWF;     // ciphertext at the Comp level, plaintext row block, top-level ciphertext
     int npairs;
-    uint32_t Gc;            // giant indices per diagonal chunk
+    uint32_t kmax, Bmax, Gmax, Gc;
+    size_t ntot, ub_total, baby_total, gi_total, diag_cnt;
     size_t total_bytes;
 };
 
 static size_t rup(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Device-memory budget for the diagonal chunk buffer (plaintexts [L][n] u64).
+// Device-memory budget for the diagonal chunk buffer (plaintexts [Lc][n] u64).
 static const size_t kDiagBudgetBytes = (size_t)16 << 30;
 
 static Layout layout_for(const Ctx& c, const Plan& pl) {
     Layout ly;
-    ly.ct_words = 2 * (size_t)pl.level * c.n;   // ciphertexts after the switch
-    ly.pt_words = (size_t)pl.level * c.n;
-    const size_t full_ct = 2 * (size_t)c.L * c.n;
+    const size_t n = c.n;
+    ly.CW = 2 * (size_t)pl.level * n;
+    ly.PW = (size_t)pl.level * n;
+    ly.CWF = 2 * (size_t)c.L * n;
     ly.npairs = (int)(pl.groups.size() * pl.streams.size());
-    uint32_t kmax = 0, Bmax = 1, Gmax = 1;
-    size_t ublocks = 0, baby = 0, giants = 0;
+    ly.kmax = 0;
+    ly.Bmax = 1;
+    ly.Gmax = 1;
+    ly.ub_total = ly.baby_total = ly.gi_total = 0;
     for (auto& g : pl.groups) {
-        kmax = std::max(kmax, g.k);
-        Bmax = std::max(Bmax, g.B);
-        Gmax = std::max(Gmax, pl.s / g.B);
-        ublocks += (size_t)g.k * pl.streams.size();
-        baby += (size_t)g.k * (g.B - 1) * pl.streams.size();
-        giants += (size_t)(pl.s / g.B) * pl.streams.size();
+        ly.kmax = std::max(ly.kmax, g.k);
+        ly.Bmax = std::max(ly.Bmax, g.B);
+        ly.Gmax = std::max(ly.Gmax, pl.s / g.B);
+        ly.ub_total += (size_t)g.k * pl.streams.size();
+        ly.baby_total += (size_t)g.k * (g.B - 1) * pl.streams.size();
+        ly.gi_total += (size_t)(pl.s / g.B) * pl.streams.size();
     }
-    size_t per_g = (size_t)kmax * Bmax * ly.pt_words * 8;
-    uint32_t Gc = (uint32_t)std::max<size_t>(1, kDiagBudgetBytes / std::max<size_t>(per_g, 1));
-    Gc = std::min(Gc, Gmax);
-    ly.Gc = Gc;
-    size_t cnt = (size_t)kmax * Gc * Bmax;  // diagonals per chunk
+    const size_t per_g = (size_t)ly.kmax * ly.Bmax * ly.PW * 8;
+    ly.Gc = (uint32_t)std::min<size_t>(ly.Gmax, std::max<size_t>(1, kDiagBudgetBytes / std::max<size_t>(per_g, 1)));
+    ly.diag_cnt = (size_t)ly.kmax * ly.Gc * ly.Bmax;
+    ly.ntot = (size_t)pl.n_ct * (1 + pl.ncol);
+    size_t max_jobs = std::max<size_t>({ly.ub_total, ly.baby_total, ly.gi_total, (size_t)pl.bands, 1});
     size_t t = 0;
-    t += rup(full_ct * 8 * pl.n_ct);                                         // inputs in NTT domain
-    t += rup(full_ct * 8 * pl.n_ct * std::max<uint32_t>(pl.ncol, 1));       // masked
-    t += rup(ly.ct_words * 8 * pl.n_ct * (1 + (size_t)pl.ncol));             // both after the switch
-    t += rup(full_ct * 8) + rup(ly.ct_words * 8);                           // switch temporaries
-    t += rup(ly.ct_words * 8 * std::max<size_t>(ublocks, 1));               // u-blocks
-    t += rup(ly.ct_words * 8 * std::max<size_t>(baby, 1));                  // baby rotations
-    t += rup(ly.ct_words * 8 * std::max<size_t>(giants, 1));                // giant accumulators
-    t += rup(ly.ct_words * 8 * 4);                           // y, tmp, tmp2, out
-    t += rup(ly.pt_words * 8 * cnt);                         // diagonal chunk
-    t += rup((size_t)c.n * 4 * cnt);                         // diagonal mod-p stage
-    t += rup(cnt * 3 * 4);                                   // diagonal params
-    t += rup(sizeof(void*) * ((size_t)ly.npairs * kmax * Bmax + (size_t)ly.npairs * Gmax));
-    t += ks_take_bytes(c);
+    t += rup(ly.CWF * 8 * ly.ntot);                      // inputs and masked, top level
+    if (pl.level < c.L) t += 2 * rup(ly.CW * 8 * ly.ntot);  // switched copies + conversion scratch
+    t += 4 * rup(ly.CW * 8 * std::max<size_t>(ly.ub_total, 1));   // u-blocks and packing temporaries
+    t += rup(ly.CW * 8 * std::max<size_t>(ly.baby_total, 1));     // baby-step rotations
+    t += 2 * rup(ly.CW * 8 * ly.gi_total);                        // giant accumulators and their rotations
+    t += 2 * rup(ly.CW * 8 * ly.npairs);                          // y and fold temporaries
+    t += 2 * rup(ly.CW * 8 * pl.bands) + rup(ly.CW * 8);          // merge and output
+    t += rup(ly.PW * 8 * ly.diag_cnt) + rup((size_t)n * 4 * ly.diag_cnt);  // diagonal chunk
+    t += ks_scratch_bytes(c, pl.level, (int)max_jobs);
     t += 64 * 256;
     ly.total_bytes = t;
     return ly;
 }
 
-struct Compressor {
-    Ctx& c;
-    const hc_gk* gk;
-    hipStream_t st;
-    int Lc;
-    KSBuf ks;
-    hc_status err = HC_OK;
-
-    const uint64_t* key(uint32_t k) {
-        const uint64_t* p = find_key(gk, k);
-        if (!p && err == HC_OK) err = HC_ENOKEY;
-        return p;
-    }
-    void rot(uint64_t* out, const uint64_t* in, uint32_t k) {
-        const uint64_t* kk = key(k);
-        if (kk) rotate_plain(c, kk, k, out, in, ks, Lc, st);
-    }
-    void add(uint64_t* out, const uint64_t* a, const uint64_t* b) {
-        k_add(c, out, a, b, 0, Lc, 2, (size_t)Lc * c.n, st);
-    }
-};
-
 hc_status compress_one(Ctx& c, const hc_gk* gk, const hc_db* db, const uint64_t* ct_v, const Plan& pl,
                        uint64_t* ct_out, hipStream_t st) {
     const size_t n = c.n;
     const Layout ly = layout_for(c, pl);
-    const size_t CW = ly.ct_words, PW = ly.pt_words;           // at level Lc
-    const size_t CWF = 2 * (size_t)c.L * n, PWF = (size_t)c.L * n;  // at the top level
+    const size_t CW = ly.CW, PW = ly.PW, CWF = ly.CWF, PWF = (size_t)c.L * n;
     const int Lc = pl.level;
-    // all keys present?
     for (uint32_t k : pl.keys)
         if (!find_key(gk, k)) return HC_ENOKEY;
     if (pl.ncol && (!db || db->ncol != pl.ncol || db->N != pl.N)) return HC_EINVAL;
 
-    HC_CHECK(hipStreamSynchronize(st));  // the workspace and pointer tables are reused
+    stage_reset(c, st);  // the workspace and staging area are reused call to call
     if (c.ws.reserve(ly.total_bytes) != HC_OK) return HC_ENOMEM;
     Arena& a = c.ws;
-    Compressor cm{c, gk, st, Lc, KSBuf()};
-    cm.ks = ks_take(c, a);
+    const size_t max_jobs = std::max<size_t>({ly.ub_total, ly.baby_total, ly.gi_total, (size_t)pl.bands, 1});
+    KsScratch ks = ks_scratch(c, a, Lc, (int)max_jobs);
+    hc_status err = HC_OK;
+#define RUN(x) do { if ((err = (x)) != HC_OK) return err; } while (0)
 
-    // 1. inputs to the NTT domain
-    uint64_t* ctf = a.take<uint64_t>(CWF * pl.n_ct);
+    // 1. inputs to the NTT domain; Mask at the top level (Alg. 7 step 2)
+    uint64_t* ctf = a.take<uint64_t>(CWF * ly.ntot);
     if (!ctf) return HC_ENOMEM;
     HC_CHECK(hipMemcpyAsync(ctf, ct_v, sizeof(uint64_t) * CWF * pl.n_ct, hipMemcpyDeviceToDevice, st));
     ntt64(c, ctf, PWF, 2 * (int)pl.n_ct, 0, c.L, false, st);
-
-    // 2. Mask at the top level: d_c = v boxtimes DB_c per ciphertext
-    uint64_t* maskf = a.take<uint64_t>(CWF * pl.n_ct * std::max<uint32_t>(pl.ncol, 1));
-    if (!maskf) return HC_ENOMEM;
-    for (uint32_t col = 0; col < pl.ncol; col++)
-        for (uint32_t i = 0; i < pl.n_ct; i++)
-            k_mul_plain(c, maskf + (col * pl.n_ct + i) * CWF, ctf + i * CWF,
-                        db->d_pt + ((size_t)col * pl.n_ct + i) * PWF, c.L, st);
-
-    // 3. switch to the Comp level (Sec. 5.3's smaller parameters, as a modulus switch)
-    uint64_t *ctv = ctf, *masked = maskf;
-    if (Lc < c.L) {
-        ctv = a.take<uint64_t>(CW * pl.n_ct * (1 + (size_t)pl.ncol));
-        uint64_t* mtmp = a.take<uint64_t>(CWF);
-        uint64_t* mconv = a.take<uint64_t>(CW);
-        if (!ctv || !mtmp || !mconv) return HC_ENOMEM;
-        masked = ctv + CW * pl.n_ct;
-        for (uint32_t i = 0; i < pl.n_ct; i++) {
-            hc_status s2 = mod_switch(c, ctv + i * CW, ctf + i * CWF, Lc, mtmp, mconv, st);
-            if (s2 != HC_OK) return s2;
-        }
-        for (uint32_t m = 0; m < pl.n_ct * pl.ncol; m++) {
-            hc_status s2 = mod_switch(c, masked + m * CW, maskf + m * CWF, Lc, mtmp, mconv, st);
-            if (s2 != HC_OK) return s2;
-        }
+    {
+        std::vector<EwJob> mj;
+        for (uint32_t col = 0; col < pl.ncol; col++)
+            for (uint32_t i = 0; i < pl.n_ct; i++)
+                mj.push_back(EwJob{ctf + ((size_t)(1 + col) * pl.n_ct + i) * CWF, ctf + i * CWF,
+                                   db->d_pt + ((size_t)col * pl.n_ct + i) * PWF});
+        RUN(ew_run(c, mj, c.L, true, st));
     }
-    auto vec_ct = [&](int vid, uint32_t i) -> const uint64_t* {
-        return vid == 0 ? ctv + i * CW : masked + ((size_t)(vid - 1) * pl.n_ct + i) * CW;
-    };
+    // 2. switch to the Comp level (Sec. 5.3's smaller parameters, as a modulus switch)
+    uint64_t* cts = ctf;
+    if (Lc < c.L) {
+        cts = a.take<uint64_t>(CW * ly.ntot);
+        uint64_t* conv = a.take<uint64_t>(CW * ly.ntot);
+        if (!cts || !conv) return HC_ENOMEM;
+        RUN(mod_switch_batch(c, cts, ctf, (int)ly.ntot, Lc, conv, st));
+    }
+    auto vec_ct = [&](int vid, uint32_t i) -> const uint64_t* { return cts + ((size_t)vid * pl.n_ct + i) * CW; };
 
-    // per (group, stream) pair storage
+    // per-pair storage
     const int npairs = ly.npairs;
+    uint64_t* ubuf = a.take<uint64_t>(CW * std::max<size_t>(ly.ub_total, 1));
+    uint64_t* tbuf = a.take<uint64_t>(CW * std::max<size_t>(ly.ub_total, 1));
+    uint64_t* rbuf = a.take<uint64_t>(CW * std::max<size_t>(ly.ub_total, 1));
+    uint64_t* wbuf = a.take<uint64_t>(CW * std::max<size_t>(ly.ub_total, 1));
+    uint64_t* bbuf = a.take<uint64_t>(CW * std::max<size_t>(ly.baby_total, 1));
+    uint64_t* gbuf = a.take<uint64_t>(CW * ly.gi_total);
+    uint64_t* gout = a.take<uint64_t>(CW * ly.gi_total);
+    uint64_t* ybuf = a.take<uint64_t>(CW * npairs);
+    uint64_t* ytmp = a.take<uint64_t>(CW * npairs);
+    uint64_t* mbuf = a.take<uint64_t>(CW * pl.bands);
+    uint64_t* mrot = a.take<uint64_t>(CW * pl.bands);
+    uint64_t* outN = a.take<uint64_t>(CW);
+    if (!ubuf || !tbuf || !rbuf || !wbuf || !bbuf || !gbuf || !gout || !ybuf || !ytmp || !mbuf || !mrot || !outN)
+        return HC_ENOMEM;
+    const uint32_t col_k = 2u * c.n - 1;
+    const uint64_t* col_key = find_key(gk, col_k);
+
+    // 3. u-blocks (Sec. 5.2 remark): row 0: A*[1;0] + Rot_col(B*[1;0]); row 1: Rot_col(A*[0;1]) + B*[0;1]
     std::vector<std::vector<uint64_t*>> U(npairs), A(npairs);
     std::vector<std::vector<std::vector<uint64_t*>>> R(npairs);
-    size_t ub_total = 0, baby_total = 0, gi_total = 0;
-    for (auto& g : pl.groups) {
-        ub_total += (size_t)g.k * pl.streams.size();
-        baby_total += (size_t)g.k * (g.B - 1) * pl.streams.size();
-        gi_total += (size_t)(pl.s / g.B) * pl.streams.size();
-    }
-    uint64_t* ubuf = a.take<uint64_t>(CW * std::max<size_t>(ub_total, 1));
-    uint64_t* bbuf = a.take<uint64_t>(CW * std::max<size_t>(baby_total, 1));
-    uint64_t* gbuf = a.take<uint64_t>(CW * std::max<size_t>(gi_total, 1));
-    uint64_t* y = a.take<uint64_t>(CW);
-    uint64_t* tmp = a.take<uint64_t>(CW);
-    uint64_t* tmp2 = a.take<uint64_t>(CW);
-    uint64_t* outN = a.take<uint64_t>(CW);
-    if (!cm.ks.tmpC || !cm.ks.X || !cm.ks.T || !cm.ks.conv || !ctv || !masked || !ubuf || !bbuf ||
-        !gbuf || !y || !tmp || !tmp2 || !outN)
-        return HC_ENOMEM;
-
-    // 3. u-blocks and 4. hoisted baby steps
-    size_t uo = 0, bo = 0, go = 0;
-    int pp = 0;
-    for (auto& g : pl.groups) {
-        for (auto& sm : pl.streams) {
-            U[pp].resize(g.k);
-            R[pp].assign(g.k, std::vector<uint64_t*>(g.B, nullptr));
-            for (uint32_t beta = 0; beta < g.k; beta++) {
-                uint64_t* u = ubuf + (uo++) * CW;
-                U[pp][beta] = u;
-                uint32_t i = g.ct_start + beta / 2;
-                const uint64_t* Act = vec_ct(sm.first, i);
-                const uint64_t* Bct = sm.second >= 0 ? vec_ct(sm.second, i) : nullptr;
-                if (beta % 2 == 0) {
-                    k_mul_plain(c, u, Act, c.d_rowmask[0], Lc, st);
-                    if (Bct) {
-                        k_mul_plain(c, tmp, Bct, c.d_rowmask[0], Lc, st);
-                        cm.rot(tmp2, tmp, 2u * c.n - 1);
-                        cm.add(u, u, tmp2);
-                    }
-                } else {
-                    k_mul_plain(c, tmp, Act, c.d_rowmask[1], Lc, st);
-                    cm.rot(u, tmp, 2u * c.n - 1);
-                    if (Bct) {
-                        k_mul_plain(c, tmp, Bct, c.d_rowmask[1], Lc, st);
-                        cm.add(u, u, tmp);
+    {
+        std::vector<EwJob> mul, add;
+        std::vector<KsJob> rot;
+        size_t uo = 0;
+        int pp = 0;
+        for (auto& g : pl.groups) {
+            for (auto& sm : pl.streams) {
+                U[pp].resize(g.k);
+                for (uint32_t beta = 0; beta < g.k; beta++, uo++) {
+                    uint64_t *u = ubuf + uo * CW, *t = tbuf + uo * CW, *r = rbuf + uo * CW, *w = wbuf + uo * CW;
+                    U[pp][beta] = u;
+                    const uint32_t i = g.ct_start + beta / 2;
+                    const uint64_t* Act = vec_ct(sm.first, i);
+                    const uint64_t* Bct = sm.second >= 0 ? vec_ct(sm.second, i) : nullptr;
+                    if (beta % 2 == 0) {
+                        mul.push_back(EwJob{u, Act, c.d_rowmask[0]});
+                        if (Bct) {
+                            mul.push_back(EwJob{t, Bct, c.d_rowmask[0]});
+                            rot.push_back(KsJob{t, r, col_key, col_k, 0});
+                            add.push_back(EwJob{u, u, r});
+                        }
+                    } else {
+                        mul.push_back(EwJob{t, Act, c.d_rowmask[1]});
+                        if (Bct) {
+                            rot.push_back(KsJob{t, r, col_key, col_k, 0});
+                            mul.push_back(EwJob{w, Bct, c.d_rowmask[1]});
+                            add.push_back(EwJob{u, r, w});
+                        } else {
+                            rot.push_back(KsJob{t, u, col_key, col_k, 0});
+                        }
                     }
                 }
-                R[pp][beta][0] = u;
-                if (g.B > 1) {
-                    hoist_prepare(c, u, cm.ks, Lc, st);
+                pp++;
+            }
+        }
+        RUN(ew_run(c, mul, Lc, true, st));
+        RUN(ks_run(c, ks, rot, nullptr, Lc, st));
+        RUN(ew_run(c, add, Lc, false, st));
+    }
+
+    // 4. hoisted baby steps Rot_row(u; b), b = 1..B-1, one raise per u-block
+    {
+        std::vector<const uint64_t*> srcs;
+        std::vector<KsJob> jobs;
+        size_t bo = 0;
+        int pp = 0;
+        for (auto& g : pl.groups) {
+            for (size_t si = 0; si < pl.streams.size(); si++, pp++) {
+                R[pp].assign(g.k, std::vector<uint64_t*>(g.B, nullptr));
+                for (uint32_t beta = 0; beta < g.k; beta++) {
+                    R[pp][beta][0] = U[pp][beta];
+                    if (g.B == 1) continue;
+                    const uint32_t xi = (uint32_t)srcs.size();
+                    srcs.push_back(U[pp][beta]);
                     for (uint32_t b = 1; b < g.B; b++) {
                         uint64_t* r = bbuf + (bo++) * CW;
-                        uint32_t k = rot_elt(c, b);
-                        const uint64_t* kk = cm.key(k);
-                        if (kk) rotate_hoisted_one(c, kk, k, r, u, cm.ks, Lc, st);
+                        const uint32_t k = rot_elt(c, b);
+                        jobs.push_back(KsJob{U[pp][beta], r, find_key(gk, k), k, xi});
                         R[pp][beta][b] = r;
                     }
                 }
             }
-            A[pp].resize(pl.s / g.B);
-            for (uint32_t gi = 0; gi < pl.s / g.B; gi++) A[pp][gi] = gbuf + (go++) * CW;
-            pp++;
         }
+        if (!jobs.empty()) RUN(ks_run(c, ks, jobs, &srcs, Lc, st));
     }
-    if (cm.err != HC_OK) return cm.err;
 
-    // 5. diagonals + multiply-accumulate, per class of pairs sharing B
-    std::set<uint32_t> Bs;
-    for (auto& g : pl.groups) Bs.insert(g.B);
-    const uint32_t Gc = ly.Gc;
-    uint32_t kmax_all = 0;
-    for (auto& g : pl.groups) kmax_all = std::max(kmax_all, g.k);
-    const size_t max_cnt = (size_t)kmax_all * Gc * (*Bs.rbegin());
-    uint64_t* D = a.take<uint64_t>(PW * max_cnt);
-    uint32_t* Dp = a.take<uint32_t>((size_t)n * max_cnt);
-    uint32_t* prm = a.take<uint32_t>(3 * max_cnt);
-    size_t maxG = 1;
-    for (auto& g : pl.groups) maxG = std::max<size_t>(maxG, pl.s / g.B);
-    uint64_t** ptrs = a.take<uint64_t*>((size_t)npairs * kmax_all * (*Bs.rbegin()) + (size_t)npairs * maxG);
-    if (!D || !Dp || !prm || !ptrs) return HC_ENOMEM;
-    std::vector<uint32_t> hprm;
-    std::vector<uint64_t*> hptr;
-    for (uint32_t B : Bs) {
-        std::vector<int> cls;
-        uint32_t kb = 0;
-        for (int q = 0; q < npairs; q++) {
-            const PlanGroup& g = pl.groups[q / pl.streams.size()];
-            if (g.B == B) { cls.push_back(q); kb = std::max(kb, g.k); }
-        }
-        const uint32_t G = pl.s / B;
-        for (uint32_t g0 = 0; g0 < G; g0 += Gc) {
-            uint32_t gc = std::min(Gc, G - g0);
-            hprm.clear();
-            for (uint32_t beta = 0; beta < kb; beta++)
-                for (uint32_t gi = 0; gi < gc; gi++)
-                    for (uint32_t b = 0; b < B; b++) {
-                        hprm.push_back(beta);
-                        hprm.push_back(g0 + gi);
-                        hprm.push_back(b);
-                    }
-            const int cnt = (int)(hprm.size() / 3);
-            // R pointers [cls][kb][B], A pointers [cls][gc]
-            hptr.assign((size_t)cls.size() * kb * B + cls.size() * gc, nullptr);
-            for (size_t ci = 0; ci < cls.size(); ci++) {
-                int q = cls[ci];
-                for (uint32_t beta = 0; beta < R[q].size(); beta++)
-                    for (uint32_t b = 0; b < B; b++) hptr[(ci * kb + beta) * B + b] = R[q][beta][b];
-                for (uint32_t gi = 0; gi < gc; gi++)
-                    hptr[(size_t)cls.size() * kb * B + ci * gc + gi] = A[q][g0 + gi];
+    // 5. diagonals encoded on the fly and accumulated into the giant accumulators,
+    //    one chunk of giant indices at a time for every pair that shares B
+    {
+        size_t go = 0;
+        int pp = 0;
+        for (auto& g : pl.groups)
+            for (size_t si = 0; si < pl.streams.size(); si++, pp++) {
+                A[pp].resize(pl.s / g.B);
+                for (uint32_t gi = 0; gi < pl.s / g.B; gi++) A[pp][gi] = gbuf + (go++) * CW;
             }
-            // synchronous copies: the host vectors are reused for the next chunk
-            HC_CHECK(hipMemcpyAsync(prm, hprm.data(), sizeof(uint32_t) * hprm.size(), hipMemcpyHostToDevice, st));
-            HC_CHECK(hipMemcpyAsync(ptrs, hptr.data(), sizeof(uint64_t*) * hptr.size(), hipMemcpyHostToDevice, st));
-            k_diag_gen(c, Dp, prm, cnt, pl.s, B, st);
-            ntt32(c, Dp, cnt, true, st);
-            k_lift(c, D, Dp, cnt, true, Lc, st);
-            ntt64(c, D, PW, cnt, 0, Lc, false, st);
-            k_diag_mac(c, ptrs + (size_t)cls.size() * kb * B, (const uint64_t* const*)ptrs, D,
-                       (int)cls.size(), (int)kb, (int)gc, (int)B, false, Lc, st);
-            HC_CHECK(hipStreamSynchronize(st));
+        std::set<uint32_t> Bs;
+        for (auto& g : pl.groups) Bs.insert(g.B);
+        uint64_t* D = a.take<uint64_t>(PW * ly.diag_cnt);
+        uint32_t* Dp = a.take<uint32_t>((size_t)n * ly.diag_cnt);
+        if (!D || !Dp) return HC_ENOMEM;
+        std::vector<uint32_t> hprm;
+        std::vector<const uint64_t*> hptr;
+        for (uint32_t B : Bs) {
+            std::vector<int> cls;
+            uint32_t kb = 0;
+            for (int q = 0; q < npairs; q++) {
+                const PlanGroup& g = pl.groups[q / pl.streams.size()];
+                if (g.B == B) { cls.push_back(q); kb = std::max(kb, g.k); }
+            }
+            const uint32_t G = pl.s / B;
+            for (uint32_t g0 = 0; g0 < G; g0 += ly.Gc) {
+                const uint32_t gc = std::min(ly.Gc, G - g0);
+                hprm.clear();
+                for (uint32_t beta = 0; beta < kb; beta++)
+                    for (uint32_t gi = 0; gi < gc; gi++)
+                        for (uint32_t b = 0; b < B; b++) {
+                            hprm.push_back(beta);
+                            hprm.push_back(g0 + gi);
+                            hprm.push_back(b);
+                        }
+                const int cnt = (int)(hprm.size() / 3);
+                // R pointers [cls][kb][B], then A pointers [cls][gc]
+                hptr.assign((size_t)cls.size() * kb * B + cls.size() * gc, nullptr);
+                for (size_t ci = 0; ci < cls.size(); ci++) {
+                    const int q = cls[ci];
+                    for (uint32_t beta = 0; beta < R[q].size(); beta++)
+                        for (uint32_t b = 0; b < B; b++) hptr[(ci * kb + beta) * B + b] = R[q][beta][b];
+                    for (uint32_t gi = 0; gi < gc; gi++)
+                        hptr[(size_t)cls.size() * kb * B + ci * gc + gi] = A[q][g0 + gi];
+                }
+                const uint32_t* dprm = (const uint32_t*)stage_bytes(c, hprm.data(), sizeof(uint32_t) * hprm.size(), st);
+                uint64_t** dptr = (uint64_t**)stage_bytes(c, hptr.data(), sizeof(uint64_t*) * hptr.size(), st);
+                if (!dprm || !dptr) return HC_ENOMEM;
+                k_diag_gen(c, Dp, dprm, cnt, pl.s, B, st);
+                ntt32(c, Dp, cnt, true, st);
+                k_lift(c, D, Dp, cnt, true, Lc, st);
+                ntt64(c, D, PW, cnt, 0, Lc, false, st);
+                k_diag_mac(c, dptr + (size_t)cls.size() * kb * B, (const uint64_t* const*)dptr, D,
+                           (int)cls.size(), (int)kb, (int)gc, (int)B, false, Lc, st);
+            }
         }
     }
 
-    // 6. giant steps and rotate-and-sum per pair
-    std::vector<uint64_t*> bands;
-    uint64_t* band_store = nullptr;
-    if (pl.bands > 1) {
-        // reuse the u-block buffer for the band results (u-blocks are no longer needed)
-        band_store = ubuf;
-    }
-    pp = 0;
-    for (auto& g : pl.groups) {
-        for (size_t si = 0; si < pl.streams.size(); si++, pp++) {
-            uint64_t* yy = (pl.bands > 1) ? band_store + (size_t)pp * CW : y;
-            const uint32_t G = pl.s / g.B;
-            HC_CHECK(hipMemcpyAsync(yy, A[pp][0], sizeof(uint64_t) * CW, hipMemcpyDeviceToDevice, st));
-            for (uint32_t gi = 1; gi < G; gi++) {
-                cm.rot(tmp, A[pp][gi], rot_elt(c, (int64_t)gi * g.B));
-                cm.add(yy, yy, tmp);
+    // 6. giant steps: y = A_0 + sum_g Rot_row(A_g; g B)
+    {
+        std::vector<KsJob> jobs;
+        size_t go = 0;
+        int pp = 0;
+        for (auto& g : pl.groups)
+            for (size_t si = 0; si < pl.streams.size(); si++, pp++) {
+                const uint32_t G = pl.s / g.B;
+                HC_CHECK(hipMemcpyAsync(gout + go * CW, A[pp][0], sizeof(uint64_t) * CW, hipMemcpyDeviceToDevice, st));
+                for (uint32_t gi = 1; gi < G; gi++) {
+                    const uint32_t k = rot_elt(c, (int64_t)gi * g.B);
+                    jobs.push_back(KsJob{A[pp][gi], gout + (go + gi) * CW, find_key(gk, k), k, 0});
+                }
+                go += G;
             }
-            for (uint64_t sh = pl.s; sh < (uint64_t)c.nh; sh *= 2) {
-                cm.rot(tmp, yy, rot_elt(c, (int64_t)sh));
-                cm.add(yy, yy, tmp);
+        if (!jobs.empty()) RUN(ks_run(c, ks, jobs, nullptr, Lc, st));
+        go = 0;
+        pp = 0;
+        for (auto& g : pl.groups)
+            for (size_t si = 0; si < pl.streams.size(); si++, pp++) {
+                const uint32_t G = pl.s / g.B;
+                k_sum_cts(c, ybuf + (size_t)pp * CW, gout + go * CW, 1, (int)G, Lc, st);
+                go += G;
             }
-            bands.push_back(yy);
-        }
     }
-    // 7. merge
-    uint64_t* res = bands[0];
+
+    // 7. rotate-and-sum, once after the block sums (Sec. 5.2): y += Rot_row(y; s 2^i), all pairs per step
+    for (uint64_t sh = pl.s; sh < (uint64_t)c.nh; sh *= 2) {
+        const uint32_t k = rot_elt(c, (int64_t)sh);
+        std::vector<KsJob> jobs;
+        for (int q = 0; q < npairs; q++) jobs.push_back(KsJob{ybuf + q * CW, ytmp + q * CW, find_key(gk, k), k, 0});
+        RUN(ks_run(c, ks, jobs, nullptr, Lc, st));
+        k_add(c, ybuf, ybuf, ytmp, 0, Lc, 2 * npairs, PW, st);
+    }
+
+    // 8. merge the bands into one ciphertext
+    uint64_t* res = ybuf;
     if (pl.bands > 1) {
         const uint64_t* ms = nullptr;
-        hc_status s2 = prefix_mask(c, pl.s, &ms);
-        if (s2 != HC_OK) return s2;
-        k_mul_plain(c, outN, bands[0], ms, Lc, st);
-        for (uint32_t b = 1; b < pl.bands; b++) {
-            k_mul_plain(c, tmp, bands[b], ms, Lc, st);
-            cm.rot(tmp2, tmp, rot_elt(c, -(int64_t)b * pl.s));
-            cm.add(outN, outN, tmp2);
+        RUN(prefix_mask(c, pl.s, &ms));
+        std::vector<EwJob> mul;
+        std::vector<KsJob> jobs;
+        for (uint32_t b = 0; b < pl.bands; b++) {
+            mul.push_back(EwJob{b == 0 ? mrot : mbuf + b * CW, ybuf + b * CW, ms});
+            if (b > 0) {
+                const uint32_t k = rot_elt(c, -(int64_t)b * pl.s);
+                jobs.push_back(KsJob{mbuf + b * CW, mrot + b * CW, find_key(gk, k), k, 0});
+            }
         }
+        RUN(ew_run(c, mul, Lc, true, st));
+        RUN(ks_run(c, ks, jobs, nullptr, Lc, st));
+        k_sum_cts(c, outN, mrot, 1, (int)pl.bands, Lc, st);
         res = outN;
     }
-    if (cm.err != HC_OK) return cm.err;
-    // 8. back to the coefficient domain
+#undef RUN
+    // 9. back to the coefficient domain
     ntt64(c, res, PW, 2, 0, Lc, true, st);
     HC_CHECK(hipMemcpyAsync(ct_out, res, sizeof(uint64_t) * CW, hipMemcpyDeviceToDevice, st));
     HC_CHECK(hipGetLastError());

@@ -349,6 +349,14 @@ extern "C" hc_status hc_context_create(const hc_params* prm, int device, hc_cont
         hc_context_destroy(cp);
         return st;
     }
+    // staging for per-call tables
+    c.stage_cap = (size_t)8 << 20;
+    if (hipHostMalloc((void**)&c.stage_host, c.stage_cap, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void**)&c.stage_dev, c.stage_cap) != hipSuccess) {
+        hc_context_destroy(cp);
+        return HC_ENOMEM;
+    }
+    c.owned.push_back(c.stage_dev);
     if (hipDeviceSynchronize() != hipSuccess) { hc_context_destroy(cp); return HC_EDEVICE; }
     *out = cp;
     return HC_OK;
@@ -359,6 +367,7 @@ extern "C" void hc_context_destroy(hc_context* c) {
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     for (void* p : c->owned) (void)hipFree(p);
+    if (c->stage_host) (void)hipHostFree(c->stage_host);
     for (auto& kv : c->prefix_masks) (void)hipFree(kv.second);
     c->ws.release();
     delete c;

@@ -84,6 +84,11 @@ struct hc_context {
     std::map<uint32_t, uint64_t*> prefix_masks;  // keyed by s
 
     hc::Arena ws;      // per-call workspace
+    // pinned host staging for per-call tables (job lists, pointer tables) and its device mirror
+    uint8_t* stage_host = nullptr;
+    uint8_t* stage_dev = nullptr;
+    size_t stage_cap = 0, stage_used = 0;
+    hipStream_t stage_stream = nullptr;
     std::vector<void*> owned;  // device allocations freed at destroy
 
     // kernel timing (measurement only)
@@ -119,6 +124,24 @@ namespace hc {
 
 using Ctx = hc_context;
 
+// One key-switching job: out = Rot_k(in) with `key` ([dnum][2][L+K][n], Montgomery
+// form); xidx selects the raised digits (its own for plain jobs, the shared
+// source's for hoisted jobs). in/out: [2][Lc][n] NTT domain, out != in.
+struct KsJob {
+    const uint64_t* in;
+    uint64_t* out;
+    const uint64_t* key;
+    uint32_t k;
+    uint32_t xidx;
+};
+
+// One element-wise job over a ciphertext [2][Lc][n]: out = a (*|+) b.
+struct EwJob {
+    uint64_t* out;
+    const uint64_t* a;
+    const uint64_t* b;
+};
+
 // Brackets one kernel launch with events when timing is enabled.
 struct TimeScope {
     const hc_context& c;
@@ -152,25 +175,31 @@ void k_add(const Ctx& c, uint64_t* out, const uint64_t* a, const uint64_t* b, in
 void k_mul_plain(const Ctx& c, uint64_t* out, const uint64_t* ct, const uint64_t* pt_mont, int Lc,
                  hipStream_t st);
 // ModUp of all digits: X [dnum][nq][n] (coefficient domain) from x [L][n] (coefficient domain).
-// At level Lc the target rows are 0..Lc-1 and the special rows; the digits are those
-// inside the first Lc primes.
-void k_modup(const Ctx& c, uint64_t* X, const uint64_t* x, int digit_first, int ndigits, int Lc,
-             hipStream_t st);
-// inner product: T [2][nq][n] = sum_j sigma_k(X_j) * key_j ; k = 1: no permutation.
-void k_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const uint64_t* key, uint32_t k, int Lc,
-             hipStream_t st);
-// Conv_{P->Q}: conv [2][L][n] (coefficient) from T [2][nq][n] (special rows coefficient domain).
-void k_moddown_conv(const Ctx& c, uint64_t* conv, const uint64_t* T, int Lc, hipStream_t st);
-// out0 = sigma_k(c0) + (T0 - conv0) P^-1 ; out1 = (T1 - conv1) P^-1  (NTT domain)
-// (c0 and out at level Lc)
-void k_moddown_final(const Ctx& c, uint64_t* out, const uint64_t* T, const uint64_t* conv,
-                     const uint64_t* c0, uint32_t k, int Lc, hipStream_t st);
-// modulus switching from L to Lc primes: conv [2][Lc][n] from the dropped rows of ct
-// [2][L][n] (coefficient domain); out [2][Lc][n] = (ct - conv) D^-1 (NTT domain)
+// ---- batched key switching (compact rows: Lc ciphertext primes, then K special primes)
+// tmpC[m] = c1 of job m's input (permuted by sigma_k unless k = 1), [M][Lc][n]
+void kb_take_c1(const Ctx& c, uint64_t* tmpC, const KsJob* jobs, int M, int Lc, bool permute,
+                hipStream_t st);
+// X [U][dn][Lc+K][n] raised digits of the coefficient-domain tmpC [U][Lc][n]
+void kb_modup(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, hipStream_t st);
+// T [M][2][Lc+K][n] = sum_j X[xidx_m][j] (rotated by k_m if hoisted) * key_m[j]
+void kb_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const KsJob* jobs, int M, int Lc, bool hoisted,
+              hipStream_t st);
+// conv [M][2][Lc][n] = Conv_{P->Q} of the special rows of T (coefficient domain)
+void kb_conv(const Ctx& c, uint64_t* conv, const uint64_t* T, int M, int Lc, hipStream_t st);
+// out_m = (sigma_k(c0_m) + (T0 - conv0) P^-1, (T1 - conv1) P^-1), NTT domain
+void kb_final(const Ctx& c, const KsJob* jobs, const uint64_t* T, const uint64_t* conv, int M, int Lc,
+              hipStream_t st);
+// y[g] = sum of `cnt` consecutive ciphertexts of src group g (level Lc, contiguous)
+void k_sum_cts(const Ctx& c, uint64_t* y, const uint64_t* src, int groups, int cnt, int Lc, hipStream_t st);
+// element-wise jobs at level Lc: out = a * b (b a Montgomery plaintext [Lc rows]) or out = a + b
+void k_ew_jobs(const Ctx& c, const EwJob* jobs, int M, int Lc, bool mul, hipStream_t st);
+// modulus switching of `count` contiguous ciphertexts from L to Lc primes:
+// conv [count][2][Lc][n] from the dropped rows of ct [count][2][L][n] (coefficient domain);
+// out [count][2][Lc][n] = (ct - conv) D^-1 (NTT domain)
 void k_ms_conv(const Ctx& c, uint64_t* conv, const uint64_t* ct, const uint64_t* inv, const uint64_t* cst,
-               int Lc, hipStream_t st);
+               int Lc, int count, hipStream_t st);
 void k_ms_final(const Ctx& c, uint64_t* out, const uint64_t* ct, const uint64_t* conv, const uint64_t* dinv,
-                int Lc, hipStream_t st);
+                int Lc, int count, hipStream_t st);
 // slots (device u32 [count][2][nh]) -> NTT-mod-p positions [count][n]
 void k_slots_to_eval(const Ctx& c, uint32_t* out, const uint32_t* slots, int count, hipStream_t st);
 // centred lift of mod-p coefficients [count][n] into [count][L][n]; Montgomery form if mont

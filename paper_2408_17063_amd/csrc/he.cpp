@@ -49,73 +49,127 @@ hc_status prefix_mask(Ctx& c, uint32_t s, const uint64_t** out) {
     return HC_OK;
 }
 
-// ------------------------------------------------------------------ key switching
+// ------------------------------------------------------------------ staging
 
-size_t ks_scratch_words(const Ctx& c) {
+void stage_reset(Ctx& c, hipStream_t st) {
+    // the previous call's asynchronous copies out of the staging area must be done
+    if (c.stage_stream != st) (void)hipStreamSynchronize(c.stage_stream);
+    (void)hipStreamSynchronize(st);
+    c.stage_used = 0;
+    c.stage_stream = st;
+}
+
+void* stage_bytes(Ctx& c, const void* data, size_t bytes, hipStream_t st) {
+    size_t off = (c.stage_used + 255) & ~(size_t)255;
+    if (off + bytes > c.stage_cap) return nullptr;
+    memcpy(c.stage_host + off, data, bytes);
+    if (hipMemcpyAsync(c.stage_dev + off, c.stage_host + off, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+        return nullptr;
+    c.stage_used = off + bytes;
+    return c.stage_dev + off;
+}
+
+// ------------------------------------------------------------------ batched key switching
+
+static size_t ks_src_words(const Ctx& c, int Lc) {
+    const int R = Lc + c.K, dn = Lc / c.alpha;
+    return (size_t)c.n * (Lc + (size_t)dn * R);
+}
+static size_t ks_job_words(const Ctx& c, int Lc) {
+    const int R = Lc + c.K;
+    return (size_t)c.n * (2 * (size_t)R + 2 * (size_t)Lc);
+}
+
+static const size_t kKsScratchBudget = (size_t)3 << 30;
+
+size_t ks_scratch_bytes(const Ctx& c, int Lc, int max_jobs) {
+    const size_t per = 8 * (ks_src_words(c, Lc) + ks_job_words(c, Lc));
+    size_t m = kKsScratchBudget / per;
+    if (m > (size_t)max_jobs) m = (size_t)max_jobs;
+    if (m < 1) m = 1;
+    return m * per + 4 * 256;
+}
+
+KsScratch ks_scratch(Ctx& c, Arena& a, int Lc, int max_jobs) {
+    KsScratch s;
+    const size_t per = 8 * (ks_src_words(c, Lc) + ks_job_words(c, Lc));
+    size_t m = kKsScratchBudget / per;
+    if (m > (size_t)max_jobs) m = (size_t)max_jobs;
+    if (m < 1) m = 1;
+    s.maxU = s.maxM = (int)m;
+    const int R = Lc + c.K, dn = Lc / c.alpha;
+    s.tmpC = a.take<uint64_t>(m * Lc * (size_t)c.n);
+    s.X = a.take<uint64_t>(m * (size_t)dn * R * c.n);
+    s.T = a.take<uint64_t>(m * 2 * (size_t)R * c.n);
+    s.conv = a.take<uint64_t>(m * 2 * (size_t)Lc * c.n);
+    return s;
+}
+
+// Rotations at level Lc. Plain (srcs == nullptr): each job raises its own rotated c1.
+// Hoisted: srcs[u] are raised once (unrotated) and every job with xidx = u rotates
+// the raised digits instead. Jobs are processed in passes of at most maxM.
+hc_status ks_run(Ctx& c, KsScratch& s, const std::vector<KsJob>& jobs,
+                 const std::vector<const uint64_t*>* srcs, int Lc, hipStream_t st) {
+    if (!s.tmpC || !s.X || !s.T || !s.conv) return HC_ENOMEM;
     const size_t n = c.n;
-    return (size_t)c.L * n + (size_t)c.dnum * c.nq * n + 2 * (size_t)c.nq * n + 2 * (size_t)c.L * n + 1024;
+    const int R = Lc + c.K, dn = Lc / c.alpha;
+    auto raise = [&](const KsJob* d, int U, bool permute) {
+        kb_take_c1(c, s.tmpC, d, U, Lc, permute, st);
+        ntt64(c, s.tmpC, (size_t)Lc * n, U, 0, Lc, true, st);
+        kb_modup(c, s.X, s.tmpC, U, Lc, st);
+        ntt64(c, s.X, (size_t)R * n, U * dn, 0, Lc, false, st);
+        ntt64(c, s.X + (size_t)Lc * n, (size_t)R * n, U * dn, c.L, c.K, false, st);
+    };
+    auto finish = [&](const KsJob* d, int M, bool hoisted) {
+        kb_inner(c, s.T, s.X, d, M, Lc, hoisted, st);
+        ntt64(c, s.T + (size_t)Lc * n, (size_t)R * n, 2 * M, c.L, c.K, true, st);
+        kb_conv(c, s.conv, s.T, M, Lc, st);
+        ntt64(c, s.conv, (size_t)Lc * n, 2 * M, 0, Lc, false, st);
+        kb_final(c, d, s.T, s.conv, M, Lc, st);
+    };
+    if (!srcs) {
+        for (size_t m0 = 0; m0 < jobs.size(); m0 += s.maxM) {
+            const int M = (int)std::min<size_t>(s.maxM, jobs.size() - m0);
+            std::vector<KsJob> jb(jobs.begin() + m0, jobs.begin() + m0 + M);
+            for (int i = 0; i < M; i++) jb[i].xidx = (uint32_t)i;
+            const KsJob* d = (const KsJob*)stage_bytes(c, jb.data(), sizeof(KsJob) * M, st);
+            if (!d) return HC_ENOMEM;
+            raise(d, M, true);
+            finish(d, M, false);
+        }
+        return HC_OK;
+    }
+    const size_t U = srcs->size();
+    for (size_t u0 = 0; u0 < U; u0 += s.maxU) {
+        const int Uc = (int)std::min<size_t>(s.maxU, U - u0);
+        std::vector<KsJob> sj(Uc);
+        for (int i = 0; i < Uc; i++) sj[i] = KsJob{(*srcs)[u0 + i], nullptr, nullptr, 1u, (uint32_t)i};
+        const KsJob* ds = (const KsJob*)stage_bytes(c, sj.data(), sizeof(KsJob) * Uc, st);
+        if (!ds) return HC_ENOMEM;
+        raise(ds, Uc, false);
+        std::vector<KsJob> mine;
+        for (const KsJob& j : jobs)
+            if (j.xidx >= u0 && j.xidx < u0 + Uc) {
+                KsJob t = j;
+                t.xidx = (uint32_t)(j.xidx - u0);
+                mine.push_back(t);
+            }
+        for (size_t m0 = 0; m0 < mine.size(); m0 += s.maxM) {
+            const int M = (int)std::min<size_t>(s.maxM, mine.size() - m0);
+            const KsJob* d = (const KsJob*)stage_bytes(c, mine.data() + m0, sizeof(KsJob) * M, st);
+            if (!d) return HC_ENOMEM;
+            finish(d, M, true);
+        }
+    }
+    return HC_OK;
 }
 
-KSBuf ks_take(Ctx& c, Arena& a) {
-    KSBuf b;
-    const size_t n = c.n;
-    b.tmpC = a.take<uint64_t>((size_t)c.L * n);
-    b.X = a.take<uint64_t>((size_t)c.dnum * c.nq * n);
-    b.T = a.take<uint64_t>(2 * (size_t)c.nq * n);
-    b.conv = a.take<uint64_t>(2 * (size_t)c.L * n);
-    return b;
-}
-
-size_t ks_take_bytes(const Ctx& c) {
-    const size_t n = c.n;
-    auto r = [](size_t w) { return (w * 8 + 255) & ~(size_t)255; };
-    return r((size_t)c.L * n) + r((size_t)c.dnum * c.nq * n) + r(2 * (size_t)c.nq * n) + r(2 * (size_t)c.L * n);
-}
-
-// T -> (sigma_k(c0) + ModDown(T0), ModDown(T1)), output at level Lc
-static void moddown_into(Ctx& c, uint64_t* out, const uint64_t* c0, uint32_t k, KSBuf& b, int Lc,
-                         hipStream_t st) {
-    const size_t n = c.n;
-    // special rows to coefficients (data points at the first transformed row)
-    ntt64(c, b.T + (size_t)c.L * n, (size_t)c.nq * n, 2, c.L, c.K, true, st);
-    k_moddown_conv(c, b.conv, b.T, Lc, st);
-    ntt64(c, b.conv, (size_t)c.L * n, 2, 0, Lc, false, st);
-    k_moddown_final(c, out, b.T, b.conv, c0, k, Lc, st);
-}
-
-// NTT of the raised digits on the rows of level Lc (ciphertext rows, then special rows)
-static void ntt_raised(Ctx& c, KSBuf& b, int Lc, hipStream_t st) {
-    const size_t n = c.n;
-    const int dn = Lc / c.alpha;
-    ntt64(c, b.X, (size_t)c.nq * n, dn, 0, Lc, false, st);
-    ntt64(c, b.X + (size_t)c.L * n, (size_t)c.nq * n, dn, c.L, c.K, false, st);
-}
-
-// out = Rot(in) by sigma_k, non-hoisted. in, out: NTT domain [2][Lc][n]; out != in.
-void rotate_plain(Ctx& c, const uint64_t* key, uint32_t k, uint64_t* out, const uint64_t* in,
-                  KSBuf& b, int Lc, hipStream_t st) {
-    const size_t n = c.n, Ln = (size_t)Lc * n;
-    k_permute(c, b.tmpC, in + Ln, Lc, k, 1, 0, st);
-    ntt64(c, b.tmpC, Ln, 1, 0, Lc, true, st);
-    k_modup(c, b.X, b.tmpC, 0, Lc / c.alpha, Lc, st);
-    ntt_raised(c, b, Lc, st);
-    k_inner(c, b.T, b.X, key, 1, Lc, st);
-    moddown_into(c, out, in, k, b, Lc, st);
-}
-
-// ModUp of c1 once (into b.X, NTT domain), shared by rotate_hoisted_one calls.
-void hoist_prepare(Ctx& c, const uint64_t* in, KSBuf& b, int Lc, hipStream_t st) {
-    const size_t n = c.n, Ln = (size_t)Lc * n;
-    (void)hipMemcpyAsync(b.tmpC, in + Ln, sizeof(uint64_t) * Ln, hipMemcpyDeviceToDevice, st);
-    ntt64(c, b.tmpC, Ln, 1, 0, Lc, true, st);
-    k_modup(c, b.X, b.tmpC, 0, Lc / c.alpha, Lc, st);
-    ntt_raised(c, b, Lc, st);
-}
-
-void rotate_hoisted_one(Ctx& c, const uint64_t* key, uint32_t k, uint64_t* out, const uint64_t* in,
-                        KSBuf& b, int Lc, hipStream_t st) {
-    k_inner(c, b.T, b.X, key, k, Lc, st);
-    moddown_into(c, out, in, k, b, Lc, st);
+hc_status ew_run(Ctx& c, const std::vector<EwJob>& jobs, int Lc, bool mul, hipStream_t st) {
+    if (jobs.empty()) return HC_OK;
+    const EwJob* d = (const EwJob*)stage_bytes(c, jobs.data(), sizeof(EwJob) * jobs.size(), st);
+    if (!d) return HC_ENOMEM;
+    k_ew_jobs(c, d, (int)jobs.size(), Lc, mul, st);
+    return HC_OK;
 }
 
 // Constants for dropping the primes Lc..L-1 (product D), cached per level.
@@ -147,8 +201,8 @@ static hc_status ms_tables(Ctx& c, int Lc, const Ctx::MsTab** out) {
             dinv[2 * i + 1] = h_shoup_const(dinv[2 * i], qi);
         }
         Ctx::MsTab t{};
-        HC_CHECK(hipMalloc((void**)&t.inv, sizeof(uint64_t) * inv.size()));
-        HC_CHECK(hipMalloc((void**)&t.cst, sizeof(uint64_t) * cst.size()));
+        HC_CHECK(hipMalloc((void**)&t.inv, sizeof(uint64_t) * std::max<size_t>(inv.size(), 1)));
+        HC_CHECK(hipMalloc((void**)&t.cst, sizeof(uint64_t) * std::max<size_t>(cst.size(), 1)));
         HC_CHECK(hipMalloc((void**)&t.dinv, sizeof(uint64_t) * dinv.size()));
         c.owned.push_back(t.inv);
         c.owned.push_back(t.cst);
@@ -162,19 +216,19 @@ static hc_status ms_tables(Ctx& c, int Lc, const Ctx::MsTab** out) {
     return HC_OK;
 }
 
-// out [2][Lc][n] = in [2][L][n] with the primes Lc..L-1 dropped (NTT domain in and out).
-// tmp: 2 L n words; conv: 2 Lc n words.
-hc_status mod_switch(Ctx& c, uint64_t* out, const uint64_t* in, int Lc, uint64_t* tmp, uint64_t* conv,
-                     hipStream_t st) {
+// out [count][2][Lc][n] = in [count][2][L][n] with the primes Lc..L-1 dropped (NTT domain
+// in and out). The dropped rows of `in` are left in the coefficient domain. conv: 2 Lc n
+// words per ciphertext.
+hc_status mod_switch_batch(Ctx& c, uint64_t* out, uint64_t* in, int count, int Lc, uint64_t* conv,
+                           hipStream_t st) {
     const Ctx::MsTab* t = nullptr;
     hc_status s = ms_tables(c, Lc, &t);
     if (s != HC_OK) return s;
     const size_t n = c.n, Ln = (size_t)c.L * n;
-    HC_CHECK(hipMemcpyAsync(tmp, in, sizeof(uint64_t) * 2 * Ln, hipMemcpyDeviceToDevice, st));
-    ntt64(c, tmp + (size_t)Lc * n, Ln, 2, Lc, c.L - Lc, true, st);  // dropped rows to coefficients
-    k_ms_conv(c, conv, tmp, t->inv, t->cst, Lc, st);
-    ntt64(c, conv, (size_t)Lc * n, 2, 0, Lc, false, st);
-    k_ms_final(c, out, in, conv, t->dinv, Lc, st);
+    ntt64(c, in + (size_t)Lc * n, Ln, 2 * count, Lc, c.L - Lc, true, st);
+    k_ms_conv(c, conv, in, t->inv, t->cst, Lc, count, st);
+    ntt64(c, conv, (size_t)Lc * n, 2 * count, 0, Lc, false, st);
+    k_ms_final(c, out, in, conv, t->dinv, Lc, count, st);
     return HC_OK;
 }
 
@@ -387,27 +441,27 @@ static hc_status rotate_common(hc_context* cp, const hc_gk* gk, const uint32_t* 
     if (!cp || !gk || !elts || !ct_in || !cts_out || count == 0) return HC_EINVAL;
     Ctx& c = *cp;
     HC_CHECK(hipSetDevice(c.device));
-    std::vector<const uint64_t*> keys(count);
-    for (uint32_t i = 0; i < count; i++) {
-        keys[i] = find_key(gk, elts[i]);
-        if (!keys[i]) return HC_ENOKEY;
-    }
     const size_t Ln2 = 2 * (size_t)c.L * c.n;
-    HC_CHECK(hipStreamSynchronize(st));
-    if (c.ws.reserve(ks_take_bytes(c) + 256 * 4 + sizeof(uint64_t) * Ln2 * 2) != HC_OK) return HC_ENOMEM;
-    KSBuf b = ks_take(c, c.ws);
+    std::vector<KsJob> jobs(count);
+    stage_reset(c, st);
+    if (c.ws.reserve(ks_scratch_bytes(c, c.L, (int)count) + sizeof(uint64_t) * Ln2 * (count + 1) + 4096) != HC_OK)
+        return HC_ENOMEM;
+    KsScratch s = ks_scratch(c, c.ws, c.L, (int)count);
     uint64_t* inN = c.ws.take<uint64_t>(Ln2);
-    uint64_t* outN = c.ws.take<uint64_t>(Ln2);
-    if (!b.tmpC || !b.X || !b.T || !b.conv || !inN || !outN) return HC_ENOMEM;
+    uint64_t* outN = c.ws.take<uint64_t>(Ln2 * count);
+    if (!inN || !outN) return HC_ENOMEM;
+    for (uint32_t i = 0; i < count; i++) {
+        const uint64_t* key = find_key(gk, elts[i]);
+        if (!key) return HC_ENOKEY;
+        jobs[i] = KsJob{inN, outN + i * Ln2, key, elts[i], 0};
+    }
     HC_CHECK(hipMemcpyAsync(inN, ct_in, sizeof(uint64_t) * Ln2, hipMemcpyDeviceToDevice, st));
     ntt64(c, inN, (size_t)c.L * c.n, 2, 0, c.L, false, st);
-    if (hoisted) hoist_prepare(c, inN, b, c.L, st);
-    for (uint32_t i = 0; i < count; i++) {
-        if (hoisted) rotate_hoisted_one(c, keys[i], elts[i], outN, inN, b, c.L, st);
-        else rotate_plain(c, keys[i], elts[i], outN, inN, b, c.L, st);
-        ntt64(c, outN, (size_t)c.L * c.n, 2, 0, c.L, true, st);
-        HC_CHECK(hipMemcpyAsync(cts_out + i * Ln2, outN, sizeof(uint64_t) * Ln2, hipMemcpyDeviceToDevice, st));
-    }
+    std::vector<const uint64_t*> srcs{inN};
+    hc_status stt = ks_run(c, s, jobs, hoisted ? &srcs : nullptr, c.L, st);
+    if (stt != HC_OK) return stt;
+    ntt64(c, outN, (size_t)c.L * c.n, 2 * (int)count, 0, c.L, true, st);
+    HC_CHECK(hipMemcpyAsync(cts_out, outN, sizeof(uint64_t) * Ln2 * count, hipMemcpyDeviceToDevice, st));
     HC_CHECK(hipGetLastError());
     HC_CHECK(hipStreamSynchronize(st));
     return HC_OK;
@@ -449,10 +503,24 @@ extern "C" hc_status hc_mul_plain(hc_context* cp, const uint64_t* ct_in, const u
 extern "C" hc_status hc_modup(hc_context* cp, const uint64_t* x, uint32_t digit, uint64_t* out,
                               hipStream_t st) {
     if (!cp || !x || !out || digit >= (uint32_t)cp->dnum) return HC_EINVAL;
-    HC_CHECK(hipSetDevice(cp->device));
-    k_modup(*cp, out, x, (int)digit, 1, cp->L, st);
-    HC_CHECK(hipGetLastError());
+    Ctx& c = *cp;
+    HC_CHECK(hipSetDevice(c.device));
+    const size_t n = c.n, R = (size_t)c.nq;
+    HC_CHECK(hipStreamSynchronize(st));
+    if (c.ws.reserve(sizeof(uint64_t) * (size_t)c.dnum * R * n + 4096) != HC_OK) return HC_ENOMEM;
+    uint64_t* X = c.ws.take<uint64_t>((size_t)c.dnum * R * n);
+    if (!X) return HC_ENOMEM;
+    // x is [L][n], the compact layout of one source at the top level
+    kb_modup(c, X, x, 1, c.L, st);
+    HC_CHECK(hipMemcpyAsync(out, X + (size_t)digit * R * n, sizeof(uint64_t) * R * n,
+                            hipMemcpyDeviceToDevice, st));
+    HC_CHECK(hipStreamSynchronize(st));
     return HC_OK;
+}
+
+__global__ void zero_fill_kernel(uint64_t* p, size_t count) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
 }
 
 extern "C" hc_status hc_moddown(hc_context* cp, const uint64_t* T, uint64_t* out, hipStream_t st) {
@@ -460,20 +528,24 @@ extern "C" hc_status hc_moddown(hc_context* cp, const uint64_t* T, uint64_t* out
     Ctx& c = *cp;
     HC_CHECK(hipSetDevice(c.device));
     const size_t n = c.n;
-    HC_CHECK(hipStreamSynchronize(st));
-    if (c.ws.reserve(sizeof(uint64_t) * (2 * c.nq * n + 5 * c.L * n) + 4096) != HC_OK) return HC_ENOMEM;
-    // T as component 0 of a [2][nq][n] pair (component 1 zero); the conversion and
-    // the final combination are element-wise, so they apply in the coefficient domain
+    stage_reset(c, st);
+    if (c.ws.reserve(sizeof(uint64_t) * (2 * c.nq * n + 6 * c.L * n) + 4096) != HC_OK) return HC_ENOMEM;
+    // T as component 0 of one job's [2][L+K][n] (component 1 zero); the conversion and the
+    // final combination are element-wise, so they apply in the coefficient domain too
     uint64_t* TT = c.ws.take<uint64_t>(2 * c.nq * n);
     uint64_t* conv = c.ws.take<uint64_t>(2 * c.L * n);
-    uint64_t* zero = c.ws.take<uint64_t>(c.L * n);
+    uint64_t* zero = c.ws.take<uint64_t>(2 * c.L * n);
     uint64_t* o2 = c.ws.take<uint64_t>(2 * c.L * n);
     if (!TT || !conv || !zero || !o2) return HC_ENOMEM;
-    HC_CHECK(hipMemsetAsync(TT, 0, sizeof(uint64_t) * 2 * c.nq * n, st));
-    HC_CHECK(hipMemsetAsync(zero, 0, sizeof(uint64_t) * c.L * n, st));
+    const size_t zc = 2 * c.nq * n, zc2 = 2 * c.L * n;
+    hipLaunchKernelGGL(zero_fill_kernel, dim3((zc + 255) / 256), dim3(256), 0, st, TT, zc);
+    hipLaunchKernelGGL(zero_fill_kernel, dim3((zc2 + 255) / 256), dim3(256), 0, st, zero, zc2);
     HC_CHECK(hipMemcpyAsync(TT, T, sizeof(uint64_t) * c.nq * n, hipMemcpyDeviceToDevice, st));
-    k_moddown_conv(c, conv, TT, c.L, st);
-    k_moddown_final(c, o2, TT, conv, zero, 1, c.L, st);
+    KsJob j{zero, o2, nullptr, 1u, 0u};
+    const KsJob* dj = (const KsJob*)stage_bytes(c, &j, sizeof(j), st);
+    if (!dj) return HC_ENOMEM;
+    kb_conv(c, conv, TT, 1, c.L, st);
+    kb_final(c, dj, TT, conv, 1, c.L, st);
     HC_CHECK(hipMemcpyAsync(out, o2, sizeof(uint64_t) * c.L * n, hipMemcpyDeviceToDevice, st));
     HC_CHECK(hipStreamSynchronize(st));
     return HC_OK;

@@ -4,30 +4,31 @@
 
 namespace hc {
 
-// key-switching temporaries: tmpC [L][n], X [dnum][nq][n], T [2][nq][n], conv [2][L][n]
-struct KSBuf {
-    uint64_t* tmpC = nullptr;
-    uint64_t* X = nullptr;
-    uint64_t* T = nullptr;
-    uint64_t* conv = nullptr;
+// key-switching scratch for passes of up to maxM jobs (and maxU raised sources)
+struct KsScratch {
+    uint64_t* tmpC = nullptr;  // [maxU][Lc][n]
+    uint64_t* X = nullptr;     // [maxU][dn][Lc+K][n]
+    uint64_t* T = nullptr;     // [maxM][2][Lc+K][n]
+    uint64_t* conv = nullptr;  // [maxM][2][Lc][n]
+    int maxU = 0, maxM = 0;
 };
 
 uint64_t tag_u64(const char* s);
 hc_status encode_plain(Ctx& c, uint64_t* out, const uint32_t* host_slots, int count, bool mont,
                        hipStream_t st);
 hc_status prefix_mask(Ctx& c, uint32_t s, const uint64_t** out);
-size_t ks_take_bytes(const Ctx& c);
-KSBuf ks_take(Ctx& c, Arena& a);
-// Key switching at level Lc (ciphertexts [2][Lc][n], NTT domain): rows 0..Lc-1 and
-// the special primes, digits inside the first Lc primes. Top-level keys serve every level.
-void rotate_plain(Ctx& c, const uint64_t* key, uint32_t k, uint64_t* out, const uint64_t* in,
-                  KSBuf& b, int Lc, hipStream_t st);
-void hoist_prepare(Ctx& c, const uint64_t* in, KSBuf& b, int Lc, hipStream_t st);
-void rotate_hoisted_one(Ctx& c, const uint64_t* key, uint32_t k, uint64_t* out, const uint64_t* in,
-                        KSBuf& b, int Lc, hipStream_t st);
-// Drop the primes Lc..L-1 of a top-level ciphertext (NTT domain); tmp 2 L n, conv 2 Lc n words.
-hc_status mod_switch(Ctx& c, uint64_t* out, const uint64_t* in, int Lc, uint64_t* tmp, uint64_t* conv,
-                     hipStream_t st);
+// per-call staging of small tables (pinned host -> device, in stream order)
+void stage_reset(Ctx& c, hipStream_t st);
+void* stage_bytes(Ctx& c, const void* data, size_t bytes, hipStream_t st);
+// batched key switching at level Lc (see ks_run in he.cpp)
+size_t ks_scratch_bytes(const Ctx& c, int Lc, int max_jobs);
+KsScratch ks_scratch(Ctx& c, Arena& a, int Lc, int max_jobs);
+hc_status ks_run(Ctx& c, KsScratch& s, const std::vector<KsJob>& jobs,
+                 const std::vector<const uint64_t*>* srcs, int Lc, hipStream_t st);
+hc_status ew_run(Ctx& c, const std::vector<EwJob>& jobs, int Lc, bool mul, hipStream_t st);
+// drop the primes Lc..L-1 of `count` contiguous top-level ciphertexts (NTT domain)
+hc_status mod_switch_batch(Ctx& c, uint64_t* out, uint64_t* in, int count, int Lc, uint64_t* conv,
+                           hipStream_t st);
 const uint64_t* find_key(const hc_gk* gk, uint32_t k);
 
 }  // namespace hc

@@ -113,147 +113,190 @@ void k_from_mont(const Ctx& c, uint64_t* x, int lf, int nl, int count, size_t st
                        c.d_mods, c.d_qinv, c.d_r2, c.n, lf, stride, 1);
 }
 
-// ------------------------------------------------------------------ key switching
+// ------------------------------------------------------------------ key switching (batched)
+//
+// Intermediates of key switching at level Lc use a compact row layout: rows
+// 0..Lc-1 are the first Lc ciphertext primes, rows Lc..Lc+K-1 the special primes
+// (prime index L + row - Lc). A pass handles M jobs (rotations); job m reads
+// the raised digits X[xidx_m] and its own key, and writes out_m.
 
-// One thread per coefficient; for each digit j: y_a = [x_{j,a} (D_j/q_{j,a})^-1]_{q},
-// then for every prime r of PQ outside the digit sum_a y_a (D_j/q_{j,a}) mod r
-// (128-bit sum, one Montgomery reduction); on the digit's own primes a copy of x.
-__global__ void modup_kernel(uint64_t* __restrict__ X, const uint64_t* __restrict__ x,
-                             const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv,
-                             const uint64_t* __restrict__ inv, const uint64_t* __restrict__ cst,
-                             int n, int nq, int alpha, int digit_first, int Lc, int L) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int j = digit_first + blockIdx.y;
+__device__ __forceinline__ int row_prime(int row, int Lc, int L) { return row < Lc ? row : L + row - Lc; }
+
+// tmpC[m] = c1 of job m's input, permuted by sigma_{k_m} (k = 1: plain copy)
+__global__ void kb_take_c1_kernel(uint64_t* __restrict__ tmpC, const KsJob* __restrict__ jobs, int n,
+                                  int logn, int Lc) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const KsJob jb = jobs[blockIdx.z];
+    const uint32_t src = (jb.k == 1) ? x : galois_src(x, jb.k, logn);
+    const size_t r = blockIdx.y;
+    tmpC[((size_t)blockIdx.z * Lc + r) * n + x] = jb.in[((size_t)Lc + r) * n + src];
+}
+
+void kb_take_c1(const Ctx& c, uint64_t* tmpC, const KsJob* jobs, int M, int Lc, bool permute,
+                hipStream_t st) {
+    (void)permute;
+    hipLaunchKernelGGL(kb_take_c1_kernel, ew_grid(c.n, Lc, M), dim3(EW_THREADS), 0, st, tmpC, jobs, c.n,
+                       c.logn, Lc);
+}
+
+// X[u][j] (compact rows) from the coefficient-domain tmpC[u]: the digit's own rows
+// are copied; row r outside the digit gets sum_a [x_a (D_j/q_a)^-1]_{q_a} (D_j/q_a) mod r.
+__global__ void kb_modup_kernel(uint64_t* __restrict__ X, const uint64_t* __restrict__ tmpC,
+                                const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv,
+                                const uint64_t* __restrict__ inv, const uint64_t* __restrict__ cst,
+                                int n, int nq, int alpha, int L, int Lc, int K, int dn) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int j = blockIdx.y, u = blockIdx.z, R = Lc + K;
+    const uint64_t* src = tmpC + (size_t)u * Lc * n;
+    uint64_t* out = X + ((size_t)u * dn + j) * R * n;
     uint64_t y[4];
-    uint64_t* out = X + (size_t)blockIdx.y * nq * n;
     for (int a = 0; a < alpha; a++) {
-        int r = j * alpha + a;
-        uint64_t v = x[(size_t)r * n + i];
-        out[(size_t)r * n + i] = v;
+        const int r = j * alpha + a;
+        const uint64_t v = src[(size_t)r * n + x];
+        out[(size_t)r * n + x] = v;
         const uint64_t* iv = inv + ((size_t)j * alpha + a) * 2;
         y[a] = shoup(v, iv[0], iv[1], mods[r]);
     }
     const uint64_t* cj = cst + (size_t)j * alpha * nq;
-    for (int r = 0; r < nq; r++) {
-        if (r >= j * alpha && r < (j + 1) * alpha) continue;
-        if (r >= Lc && r < L) continue;  // primes dropped at this level
+    for (int row = 0; row < R; row++) {
+        if (row >= j * alpha && row < (j + 1) * alpha) continue;
+        const int pr = row_prime(row, Lc, L);
         u128p acc{0, 0};
-        for (int a = 0; a < alpha; a++) add128(acc, mul128(y[a], cj[(size_t)a * nq + r]));
-        out[(size_t)r * n + i] = redc(acc, mods[r], qinv[r]);
+        for (int a = 0; a < alpha; a++) add128(acc, mul128(y[a], cj[(size_t)a * nq + pr]));
+        out[(size_t)row * n + x] = redc(acc, mods[pr], qinv[pr]);
     }
 }
 
-void k_modup(const Ctx& c, uint64_t* X, const uint64_t* x, int digit_first, int ndigits, int Lc,
-             hipStream_t st) {
+void kb_modup(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, hipStream_t st) {
+    const int dn = Lc / c.alpha, R = Lc + c.K;
     const double n = c.n;
-    const int rows = Lc + c.K;
-    TimeScope ts(c, HC_KT_MODUP, st, 8.0 * n * ((double)ndigits * c.alpha + (double)ndigits * rows),
-                 n * ndigits * (double)(rows - c.alpha) * c.alpha);
-    hipLaunchKernelGGL(modup_kernel, ew_grid(c.n, ndigits), dim3(EW_THREADS), 0, st, X, x, c.d_mods,
-                       c.d_qinv, c.d_modup_inv, c.d_modup_c, c.n, c.nq, c.alpha, digit_first, Lc, c.L);
+    TimeScope ts(c, HC_KT_MODUP, st, 8.0 * n * U * ((double)Lc + (double)dn * R),
+                 n * U * dn * (double)(R - c.alpha) * c.alpha);
+    hipLaunchKernelGGL(kb_modup_kernel, ew_grid(c.n, dn, U), dim3(EW_THREADS), 0, st, X, tmpC, c.d_mods,
+                       c.d_qinv, c.d_modup_inv, c.d_modup_c, c.n, c.nq, c.alpha, c.L, Lc, c.K, dn);
 }
 
-// T[c][r][i] = sum_j X_j[r][src(i)] * key_j[c][r][i]; key in Montgomery form, so one
-// reduction of the 128-bit sum gives the plain product sum (dnum q^2 < q 2^64).
-__global__ void inner_kernel(uint64_t* __restrict__ T, const uint64_t* __restrict__ X,
-                             const uint64_t* __restrict__ key, const uint64_t* __restrict__ mods,
-                             const uint64_t* __restrict__ qinv, int n, int logn, int nq, int dnum,
-                             uint32_t k, int Lc, int L) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    // rows of this level: ciphertext primes 0..Lc-1, then the special primes
-    const int r = (int)blockIdx.y < Lc ? (int)blockIdx.y : L + ((int)blockIdx.y - Lc);
-    const uint32_t src = (k == 1) ? i : galois_src(i, k, logn);
-    const size_t row = (size_t)nq * n;
-    u128p a0{0, 0}, a1{0, 0};
-    for (int j = 0; j < dnum; j++) {
-        uint64_t xv = X[(size_t)j * row + (size_t)r * n + src];
-        const uint64_t* kj = key + (size_t)j * 2 * row + (size_t)r * n + i;
-        add128(a0, mul128(xv, kj[0]));
-        add128(a1, mul128(xv, kj[row]));
-    }
-    uint64_t q = mods[r], qi = qinv[r];
-    T[(size_t)r * n + i] = redc(a0, q, qi);
-    T[row + (size_t)r * n + i] = redc(a1, q, qi);
-}
-
-void k_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const uint64_t* key, uint32_t k, int Lc,
-             hipStream_t st) {
-    // must read the key (dnum x 2 rows per prime) and the raised digits, write T
-    const int dn = Lc / c.alpha;
-    const double rows = (double)(Lc + c.K) * c.n;
-    TimeScope ts(c, HC_KT_KS_INNER, st, 8.0 * rows * (2.0 * dn + dn + 2.0), 2.0 * dn * rows);
-    hipLaunchKernelGGL(inner_kernel, ew_grid(c.n, Lc + c.K), dim3(EW_THREADS), 0, st, T, X, key,
-                       c.d_mods, c.d_qinv, c.n, c.logn, c.nq, dn, k, Lc, c.L);
-}
-
-// conv[c][i][x] = sum_k [T_{p_k}(x) (P/p_k)^-1]_{p_k} (P/p_k) mod q_i
-__global__ void moddown_conv_kernel(uint64_t* __restrict__ conv, const uint64_t* __restrict__ T,
-                                    const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv,
-                                    const uint64_t* __restrict__ inv, const uint64_t* __restrict__ cst,
-                                    int n, int L, int K) {
+// T[m][comp][row][x] = sum_j X[xidx][j][row][src(x)] * key_m[j][comp][prime(row)][x]; the key is
+// in Montgomery form, so one reduction of the 128-bit sum gives the plain sum (dnum q^2 < q 2^64).
+__global__ void kb_inner_kernel(uint64_t* __restrict__ T, const uint64_t* __restrict__ X,
+                                const KsJob* __restrict__ jobs, const uint64_t* __restrict__ mods,
+                                const uint64_t* __restrict__ qinv, int n, int logn, int nq, int L, int Lc,
+                                int K, int dn, int hoisted) {
     int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
-    const int comp = blockIdx.z;
-    const int nq = L + K;
-    const uint64_t* Tc = T + (size_t)comp * nq * n;
-    uint64_t y[4];
-    for (int k = 0; k < K; k++) {
-        uint64_t pk = mods[L + k];
-        y[k] = shoup(Tc[(size_t)(L + k) * n + x], inv[2 * k], inv[2 * k + 1], pk);
+    const int row = blockIdx.y, m = blockIdx.z, R = Lc + K;
+    const KsJob jb = jobs[m];
+    const int pr = row_prime(row, Lc, L);
+    // plain jobs raised their already-rotated c1; hoisted jobs rotate the shared raised digits
+    const uint32_t src = (!hoisted || jb.k == 1) ? x : galois_src(x, jb.k, logn);
+    const uint64_t* xs = X + (size_t)jb.xidx * dn * R * n + (size_t)row * n + src;
+    const size_t keyrow = (size_t)nq * n;
+    const uint64_t* kp = jb.key + (size_t)pr * n + x;
+    u128p a0{0, 0}, a1{0, 0};
+    for (int j = 0; j < dn; j++) {
+        const uint64_t xv = xs[(size_t)j * R * n];
+        const uint64_t* kj = kp + (size_t)j * 2 * keyrow;
+        add128(a0, mul128(xv, kj[0]));
+        add128(a1, mul128(xv, kj[keyrow]));
     }
-    int i = blockIdx.y;
+    const uint64_t q = mods[pr], qi = qinv[pr];
+    uint64_t* t = T + (size_t)m * 2 * R * n + (size_t)row * n + x;
+    t[0] = redc(a0, q, qi);
+    t[(size_t)R * n] = redc(a1, q, qi);
+}
+
+void kb_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const KsJob* jobs, int M, int Lc, bool hoisted,
+              hipStream_t st) {
+    const int dn = Lc / c.alpha, R = Lc + c.K;
+    // per job: reads the key (2 dn rows per prime) and the raised digits, writes T
+    const double rows = (double)R * c.n * M;
+    TimeScope ts(c, HC_KT_KS_INNER, st, 8.0 * rows * (2.0 * dn + dn + 2.0), 2.0 * dn * rows);
+    hipLaunchKernelGGL(kb_inner_kernel, ew_grid(c.n, R, M), dim3(EW_THREADS), 0, st, T, X, jobs, c.d_mods,
+                       c.d_qinv, c.n, c.logn, c.nq, c.L, Lc, c.K, dn, hoisted ? 1 : 0);
+}
+
+// conv[m][comp][i][x] = sum_k [T_{p_k}(x) (P/p_k)^-1]_{p_k} (P/p_k) mod q_i (coefficient domain)
+__global__ void kb_conv_kernel(uint64_t* __restrict__ conv, const uint64_t* __restrict__ T,
+                               const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv,
+                               const uint64_t* __restrict__ inv, const uint64_t* __restrict__ cst,
+                               int n, int L, int Lc, int K) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int i = blockIdx.y, mc = blockIdx.z, R = Lc + K;  // mc = m * 2 + comp
+    const uint64_t* Tc = T + (size_t)mc * R * n;
+    uint64_t y[4];
+    for (int k = 0; k < K; k++)
+        y[k] = shoup(Tc[(size_t)(Lc + k) * n + x], inv[2 * k], inv[2 * k + 1], mods[L + k]);
     u128p acc{0, 0};
     for (int k = 0; k < K; k++) add128(acc, mul128(y[k], cst[(size_t)k * L + i]));
-    conv[(size_t)comp * L * n + (size_t)i * n + x] = redc(acc, mods[i], qinv[i]);
+    conv[((size_t)mc * Lc + i) * n + x] = redc(acc, mods[i], qinv[i]);
 }
 
-void k_moddown_conv(const Ctx& c, uint64_t* conv, const uint64_t* T, int Lc, hipStream_t st) {
-    hipLaunchKernelGGL(moddown_conv_kernel, ew_grid(c.n, Lc, 2), dim3(EW_THREADS), 0, st, conv, T,
-                       c.d_mods, c.d_qinv, c.d_moddown_inv, c.d_moddown_c, c.n, c.L, c.K);
+void kb_conv(const Ctx& c, uint64_t* conv, const uint64_t* T, int M, int Lc, hipStream_t st) {
+    hipLaunchKernelGGL(kb_conv_kernel, ew_grid(c.n, Lc, 2 * M), dim3(EW_THREADS), 0, st, conv, T, c.d_mods,
+                       c.d_qinv, c.d_moddown_inv, c.d_moddown_c, c.n, c.L, Lc, c.K);
 }
 
-__global__ void moddown_final_kernel(uint64_t* __restrict__ out, const uint64_t* __restrict__ T,
-                                     const uint64_t* __restrict__ conv, const uint64_t* __restrict__ c0,
-                                     const uint64_t* __restrict__ mods, const uint64_t* __restrict__ pinv,
-                                     int n, int logn, int L, int K, uint32_t k, int Lc) {
-    // T [2][L+K][n], conv [2][L][n]; c0 and out at level Lc (component stride Lc n)
+// out_m = (sigma_k(c0_m) + (T0 - conv0) P^-1, (T1 - conv1) P^-1)   (NTT domain, level Lc)
+__global__ void kb_final_kernel(const KsJob* __restrict__ jobs, const uint64_t* __restrict__ T,
+                                const uint64_t* __restrict__ conv, const uint64_t* __restrict__ mods,
+                                const uint64_t* __restrict__ pinv, int n, int logn, int Lc, int K) {
     int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
-    const int i = blockIdx.y;
-    const int nq = L + K;
-    const uint64_t q = mods[i];
-    const uint64_t pi = pinv[2 * i], pis = pinv[2 * i + 1];
-    size_t o = (size_t)i * n + x;
-    uint64_t d0 = sub_mod(T[o], conv[o], q);
-    uint64_t d1 = sub_mod(T[(size_t)nq * n + o], conv[(size_t)L * n + o], q);
-    d0 = shoup(d0, pi, pis, q);
-    d1 = shoup(d1, pi, pis, q);
-    uint32_t src = (k == 1) ? x : galois_src(x, k, logn);
-    out[o] = add_mod(d0, c0[(size_t)i * n + src], q);
-    out[(size_t)Lc * n + o] = d1;
+    const int i = blockIdx.y, m = blockIdx.z, R = Lc + K;
+    const KsJob jb = jobs[m];
+    const uint64_t q = mods[i], pi = pinv[2 * i], pis = pinv[2 * i + 1];
+    const uint64_t* Tm = T + (size_t)m * 2 * R * n + (size_t)i * n + x;
+    const uint64_t* Cm = conv + (size_t)m * 2 * Lc * n + (size_t)i * n + x;
+    uint64_t d0 = shoup(sub_mod(Tm[0], Cm[0], q), pi, pis, q);
+    uint64_t d1 = shoup(sub_mod(Tm[(size_t)R * n], Cm[(size_t)Lc * n], q), pi, pis, q);
+    const uint32_t src = (jb.k == 1) ? x : galois_src(x, jb.k, logn);
+    const uint64_t c0 = jb.in[(size_t)i * n + src];
+    jb.out[(size_t)i * n + x] = add_mod(d0, c0, q);
+    jb.out[((size_t)Lc + i) * n + x] = d1;
 }
 
-void k_moddown_final(const Ctx& c, uint64_t* out, const uint64_t* T, const uint64_t* conv,
-                     const uint64_t* c0, uint32_t k, int Lc, hipStream_t st) {
-    hipLaunchKernelGGL(moddown_final_kernel, ew_grid(c.n, Lc), dim3(EW_THREADS), 0, st, out, T, conv,
-                       c0, c.d_mods, c.d_pinv, c.n, c.logn, c.L, c.K, k, Lc);
+void kb_final(const Ctx& c, const KsJob* jobs, const uint64_t* T, const uint64_t* conv, int M, int Lc,
+              hipStream_t st) {
+    hipLaunchKernelGGL(kb_final_kernel, ew_grid(c.n, Lc, M), dim3(EW_THREADS), 0, st, jobs, T, conv,
+                       c.d_mods, c.d_pinv, c.n, c.logn, Lc, c.K);
+}
+
+// y[g] = sum_{t < cnt} src[g][t] for `groups` groups of `cnt` ciphertexts (stride CW words
+// between ciphertexts, cnt*CW between groups); rows: 2 Lc per ciphertext.
+__global__ void sum_cts_kernel(uint64_t* __restrict__ y, const uint64_t* __restrict__ src,
+                               const uint64_t* __restrict__ mods, int n, int Lc, int cnt, size_t CW) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int rr = blockIdx.y, g = blockIdx.z;  // rr = comp * Lc + row
+    const uint64_t q = mods[rr % Lc];
+    const uint64_t* s = src + (size_t)g * cnt * CW + (size_t)rr * n + x;
+    uint64_t acc = 0;
+    for (int t = 0; t < cnt; t++) acc = add_mod(acc, s[(size_t)t * CW], q);
+    y[(size_t)g * CW + (size_t)rr * n + x] = acc;
+}
+
+void k_sum_cts(const Ctx& c, uint64_t* y, const uint64_t* src, int groups, int cnt, int Lc, hipStream_t st) {
+    const size_t CW = 2 * (size_t)Lc * c.n;
+    hipLaunchKernelGGL(sum_cts_kernel, ew_grid(c.n, 2 * Lc, groups), dim3(EW_THREADS), 0, st, y, src,
+                       c.d_mods, c.n, Lc, cnt, CW);
 }
 
 // ------------------------------------------------------------------ modulus switching
 
 // conv[c][i][x] = sum_{j dropped} [ct_j(x) (D/q_j)^-1]_{q_j} (D/q_j) mod q_i  for kept i < Lc;
-// ct [2][L][n] with the dropped rows Lc..L-1 in the coefficient domain.
+// ct [count][2][L][n] with the dropped rows Lc..L-1 in the coefficient domain; blockIdx.z = t*2+comp.
 __global__ void ms_conv_kernel(uint64_t* __restrict__ conv, const uint64_t* __restrict__ ct,
                                const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv,
                                const uint64_t* __restrict__ inv, const uint64_t* __restrict__ cst,
                                int n, int L, int Lc, int fold) {
     int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
-    const int comp = blockIdx.z, i = blockIdx.y, nd = L - Lc;
+    const int tc = blockIdx.z, i = blockIdx.y, nd = L - Lc;
     const uint64_t qi = mods[i], qii = qinv[i];
-    const uint64_t* cc = ct + (size_t)comp * L * n;
+    const uint64_t* cc = ct + (size_t)tc * L * n;
     u128p acc{0, 0};
     uint64_t sum = 0;
     int terms = 0;
@@ -267,34 +310,53 @@ __global__ void ms_conv_kernel(uint64_t* __restrict__ conv, const uint64_t* __re
             terms = 0;
         }
     }
-    conv[((size_t)comp * Lc + i) * n + x] = add_mod(sum, redc(acc, qi, qii), qi);
+    conv[((size_t)tc * Lc + i) * n + x] = add_mod(sum, redc(acc, qi, qii), qi);
 }
 
-// out[c][i] = (ct[c][i] - conv[c][i]) D^-1 mod q_i (NTT domain), out at level Lc
+// out[t][c][i] = (ct[t][c][i] - conv[t][c][i]) D^-1 mod q_i (NTT domain), out at level Lc
 __global__ void ms_final_kernel(uint64_t* __restrict__ out, const uint64_t* __restrict__ ct,
                                 const uint64_t* __restrict__ conv, const uint64_t* __restrict__ mods,
                                 const uint64_t* __restrict__ dinv, int n, int L, int Lc) {
     int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
-    const int comp = blockIdx.z, i = blockIdx.y;
+    const int tc = blockIdx.z, i = blockIdx.y;
     const uint64_t q = mods[i];
-    uint64_t d = sub_mod(ct[((size_t)comp * L + i) * n + x], conv[((size_t)comp * Lc + i) * n + x], q);
-    out[((size_t)comp * Lc + i) * n + x] = shoup(d, dinv[2 * i], dinv[2 * i + 1], q);
+    uint64_t d = sub_mod(ct[((size_t)tc * L + i) * n + x], conv[((size_t)tc * Lc + i) * n + x], q);
+    out[((size_t)tc * Lc + i) * n + x] = shoup(d, dinv[2 * i], dinv[2 * i + 1], q);
 }
 
 void k_ms_conv(const Ctx& c, uint64_t* conv, const uint64_t* ct, const uint64_t* inv, const uint64_t* cst,
-               int Lc, hipStream_t st) {
+               int Lc, int count, hipStream_t st) {
     uint64_t qmax = 0;
     for (int i = 0; i < c.L; i++) qmax = qmax > c.primes[i] ? qmax : c.primes[i];
     int fold = (int)std::min<uint64_t>(1024, (~0ull) / qmax);
-    hipLaunchKernelGGL(ms_conv_kernel, ew_grid(c.n, Lc, 2), dim3(EW_THREADS), 0, st, conv, ct, c.d_mods,
-                       c.d_qinv, inv, cst, c.n, c.L, Lc, fold < 1 ? 1 : fold);
+    hipLaunchKernelGGL(ms_conv_kernel, ew_grid(c.n, Lc, 2 * count), dim3(EW_THREADS), 0, st, conv, ct,
+                       c.d_mods, c.d_qinv, inv, cst, c.n, c.L, Lc, fold < 1 ? 1 : fold);
 }
 
 void k_ms_final(const Ctx& c, uint64_t* out, const uint64_t* ct, const uint64_t* conv, const uint64_t* dinv,
-                int Lc, hipStream_t st) {
-    hipLaunchKernelGGL(ms_final_kernel, ew_grid(c.n, Lc, 2), dim3(EW_THREADS), 0, st, out, ct, conv,
+                int Lc, int count, hipStream_t st) {
+    hipLaunchKernelGGL(ms_final_kernel, ew_grid(c.n, Lc, 2 * count), dim3(EW_THREADS), 0, st, out, ct, conv,
                        c.d_mods, dinv, c.n, c.L, Lc);
+}
+
+// element-wise jobs over ciphertexts at level Lc; blockIdx.y = comp * Lc + row
+__global__ void ew_jobs_kernel(const EwJob* __restrict__ jobs, const uint64_t* __restrict__ mods,
+                               const uint64_t* __restrict__ qinv, int n, int Lc, int mul) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const EwJob jb = jobs[blockIdx.z];
+    const int rr = blockIdx.y, row = rr % Lc;
+    const uint64_t q = mods[row];
+    const size_t o = (size_t)rr * n + x;
+    if (mul) jb.out[o] = mont_mul(jb.a[o], jb.b[(size_t)row * n + x], q, qinv[row]);
+    else jb.out[o] = add_mod(jb.a[o], jb.b[o], q);
+}
+
+void k_ew_jobs(const Ctx& c, const EwJob* jobs, int M, int Lc, bool mul, hipStream_t st) {
+    if (M <= 0) return;
+    hipLaunchKernelGGL(ew_jobs_kernel, ew_grid(c.n, 2 * Lc, M), dim3(EW_THREADS), 0, st, jobs, c.d_mods,
+                       c.d_qinv, c.n, Lc, mul ? 1 : 0);
 }
 
 // ------------------------------------------------------------------ encoding
