@@ -194,12 +194,16 @@ def powmod_vec(base, expo, p):
     return out
 
 
-def db_slots(db_col, n, ct_index, N):
-    """Slot matrix of the DB values of the records held by ciphertext ct_index."""
+def db_slots(db_col, n, ct_index):
+    """Slot matrix of the database values in the slots of ciphertext ct_index: the
+    records [ct_index n, (ct_index + 1) n) of the column (0 beyond its end). A query
+    over the first N records of a longer database uses the database's values in the
+    unused slots of its last ciphertext; its index vector is 0 there."""
     vals = np.zeros(n, dtype=np.uint64)
     lo = ct_index * n
-    hi = min(N, lo + n)
-    vals[:hi - lo] = np.asarray(db_col[lo:hi], dtype=np.uint64)
+    hi = min(len(db_col), lo + n)
+    if hi > lo:
+        vals[:hi - lo] = np.asarray(db_col[lo:hi], dtype=np.uint64)
     return vals.reshape(2, n // 2)
 
 
@@ -216,9 +220,9 @@ class KeySet:
         return self.gks[k]
 
 
-def mask(pr, ct_v, db_col, ct_index, N):
+def mask(pr, ct_v, db_col, ct_index):
     """ctxt(d) = ctxt(v) boxtimes DB (Alg. 7 step 2) for one ciphertext."""
-    return bfv.mul_plain(pr, ct_v, bfv.plain_poly(pr, db_slots(db_col, pr.n, ct_index, N)))
+    return bfv.mul_plain(pr, ct_v, bfv.plain_poly(pr, db_slots(db_col, pr.n, ct_index)))
 
 
 def u_blocks(pr, sched, grp, A_cts, B_cts, keys):
@@ -286,10 +290,10 @@ def compress(pr, sched, cts_v, db, gks, level=None):
     cts_v: n_ct ciphertexts of the index vector; db: ncol value columns of
     length N; gks: Galois keys by element; level: ciphertext primes kept for
     Comp (None: default_level). Returns one ciphertext at that level."""
-    if len(cts_v) != sched.n_ct or len(db) != sched.ncol:
+    if len(cts_v) != sched.n_ct or len(db) != sched.ncol or any(len(col) < sched.N for col in db):
         raise ScheduleError("inputs do not match the schedule")
     level = default_level(pr) if level is None else level
-    masked = [[mask(pr, cts_v[i], db[c], i, sched.N) for i in range(sched.n_ct)]
+    masked = [[mask(pr, cts_v[i], db[c], i) for i in range(sched.n_ct)]
               for c in range(sched.ncol)]
     if level < pr.L:
         cts_v = [bfv.mod_switch(pr, ct, level) for ct in cts_v]
@@ -337,9 +341,9 @@ def vandermonde_product(p, s, vec):
 def expected_bands(sched, v, db):
     """For each band, (row0, row1): the first s slots it must decrypt to."""
     p, s = sched.p, sched.s
-    vecs = [np.asarray(v, dtype=np.int64) % p]
+    vecs = [np.asarray(v, dtype=np.int64)[:sched.N] % p]
     for c in range(sched.ncol):
-        vecs.append(vecs[0] * (np.asarray(db[c], dtype=np.int64) % p) % p)
+        vecs.append(vecs[0] * (np.asarray(db[c][:sched.N], dtype=np.int64) % p) % p)
     out = []
     for grp in sched.groups:
         sl = slice(grp.rec_start, grp.rec_start + grp.n_rec)

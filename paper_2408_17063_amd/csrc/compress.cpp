@@ -149,155 +149,186 @@ static void fill_info(const Plan& pl, hc_compress_info* info) {
     info->level = (uint32_t)pl.level;
 }
 
-// Device memory one compression needs beyond its inputs and output.
-struct Layout {
-    size_t CW, PW, CWF;     // ciphertext at the Comp level, plaintext row block, top-level ciphertext
-    int npairs;
-    uint32_t kmax, Bmax, Gmax, Gc;
-    size_t ntot, ub_total, baby_total, gi_total, diag_cnt;
-    size_t total_bytes;
-};
-
 static size_t rup(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Device-memory budget for the diagonal chunk buffer (plaintexts [Lc][n] u64).
 static const size_t kDiagBudgetBytes = (size_t)16 << 30;
 
-static Layout layout_for(const Ctx& c, const Plan& pl) {
-    Layout ly;
-    const size_t n = c.n;
-    ly.CW = 2 * (size_t)pl.level * n;
-    ly.PW = (size_t)pl.level * n;
-    ly.CWF = 2 * (size_t)c.L * n;
-    ly.npairs = (int)(pl.groups.size() * pl.streams.size());
-    ly.kmax = 0;
-    ly.Bmax = 1;
-    ly.Gmax = 1;
-    ly.ub_total = ly.baby_total = ly.gi_total = 0;
-    for (auto& g : pl.groups) {
-        ly.kmax = std::max(ly.kmax, g.k);
-        ly.Bmax = std::max(ly.Bmax, g.B);
-        ly.Gmax = std::max(ly.Gmax, pl.s / g.B);
-        ly.ub_total += (size_t)g.k * pl.streams.size();
-        ly.baby_total += (size_t)g.k * (g.B - 1) * pl.streams.size();
-        ly.gi_total += (size_t)(pl.s / g.B) * pl.streams.size();
-    }
-    const size_t per_g = (size_t)ly.kmax * ly.Bmax * ly.PW * 8;
-    ly.Gc = (uint32_t)std::min<size_t>(ly.Gmax, std::max<size_t>(1, kDiagBudgetBytes / std::max<size_t>(per_g, 1)));
-    ly.diag_cnt = (size_t)ly.kmax * ly.Gc * ly.Bmax;
-    ly.ntot = (size_t)pl.n_ct * (1 + pl.ncol);
-    size_t max_jobs = std::max<size_t>({ly.ub_total, ly.baby_total, ly.gi_total, (size_t)pl.bands, 1});
-    size_t t = 0;
-    t += rup(ly.CWF * 8 * ly.ntot);                      // inputs and masked, top level
-    if (pl.level < c.L) t += 2 * rup(ly.CW * 8 * ly.ntot);  // switched copies + conversion scratch
-    t += 4 * rup(ly.CW * 8 * std::max<size_t>(ly.ub_total, 1));   // u-blocks and packing temporaries
-    t += rup(ly.CW * 8 * std::max<size_t>(ly.baby_total, 1));     // baby-step rotations
-    t += 2 * rup(ly.CW * 8 * ly.gi_total);                        // giant accumulators and their rotations
-    t += 2 * rup(ly.CW * 8 * ly.npairs);                          // y and fold temporaries
-    t += 2 * rup(ly.CW * 8 * pl.bands) + rup(ly.CW * 8);          // merge and output
-    t += rup(ly.PW * 8 * ly.diag_cnt) + rup((size_t)n * 4 * ly.diag_cnt);  // diagonal chunk
-    t += ks_scratch_bytes(c, pl.level, (int)max_jobs);
-    t += 64 * 256;
-    ly.total_bytes = t;
-    return ly;
-}
+// One query of a batch and its device regions.
+struct QueryRun {
+    const uint64_t* ct_v = nullptr;
+    uint64_t* ct_out = nullptr;
+    Plan pl;
+    size_t CW = 0, PW = 0, CWF = 0, ntot = 0, ub = 0, baby = 0, gi = 0;
+    int npairs = 0;
+    uint64_t *ctf = nullptr, *cts = nullptr, *ubuf = nullptr, *tbuf = nullptr, *rbuf = nullptr,
+             *wbuf = nullptr, *bbuf = nullptr, *gbuf = nullptr, *gout = nullptr, *ybuf = nullptr,
+             *ytmp = nullptr, *mbuf = nullptr, *mrot = nullptr, *outN = nullptr;
+    std::vector<std::vector<uint64_t*>> U, A;
+    std::vector<std::vector<std::vector<uint64_t*>>> R;
 
-hc_status compress_one(Ctx& c, const hc_gk* gk, const hc_db* db, const uint64_t* ct_v, const Plan& pl,
-                       uint64_t* ct_out, hipStream_t st) {
+    void sizes(const Ctx& c) {
+        const size_t n = c.n;
+        CW = 2 * (size_t)pl.level * n;
+        PW = (size_t)pl.level * n;
+        CWF = 2 * (size_t)c.L * n;
+        ntot = (size_t)pl.n_ct * (1 + pl.ncol);
+        npairs = (int)(pl.groups.size() * pl.streams.size());
+        ub = baby = gi = 0;
+        for (auto& g : pl.groups) {
+            ub += (size_t)g.k * pl.streams.size();
+            baby += (size_t)g.k * (g.B - 1) * pl.streams.size();
+            gi += (size_t)(pl.s / g.B) * pl.streams.size();
+        }
+    }
+    size_t bytes(const Ctx& c) const {
+        size_t t = rup(CWF * 8 * ntot);
+        if (pl.level < c.L) t += 2 * rup(CW * 8 * ntot);
+        t += 4 * rup(CW * 8 * std::max<size_t>(ub, 1)) + rup(CW * 8 * std::max<size_t>(baby, 1));
+        t += 2 * rup(CW * 8 * gi) + 2 * rup(CW * 8 * npairs) + 2 * rup(CW * 8 * pl.bands) + rup(CW * 8);
+        return t;
+    }
+    hc_status take(Arena& a) {
+        ctf = a.take<uint64_t>(CWF * ntot);
+        cts = ctf;
+        uint64_t* conv = nullptr;
+        if ((int)CW != (int)CWF) {
+            cts = a.take<uint64_t>(CW * ntot);
+            conv = a.take<uint64_t>(CW * ntot);
+            if (!conv) return HC_ENOMEM;
+        }
+        msconv = conv;
+        ubuf = a.take<uint64_t>(CW * std::max<size_t>(ub, 1));
+        tbuf = a.take<uint64_t>(CW * std::max<size_t>(ub, 1));
+        rbuf = a.take<uint64_t>(CW * std::max<size_t>(ub, 1));
+        wbuf = a.take<uint64_t>(CW * std::max<size_t>(ub, 1));
+        bbuf = a.take<uint64_t>(CW * std::max<size_t>(baby, 1));
+        gbuf = a.take<uint64_t>(CW * gi);
+        gout = a.take<uint64_t>(CW * gi);
+        ybuf = a.take<uint64_t>(CW * npairs);
+        ytmp = a.take<uint64_t>(CW * npairs);
+        mbuf = a.take<uint64_t>(CW * pl.bands);
+        mrot = a.take<uint64_t>(CW * pl.bands);
+        outN = a.take<uint64_t>(CW);
+        if (!ctf || !cts || !ubuf || !tbuf || !rbuf || !wbuf || !bbuf || !gbuf || !gout || !ybuf || !ytmp ||
+            !mbuf || !mrot || !outN)
+            return HC_ENOMEM;
+        return HC_OK;
+    }
+    uint64_t* msconv = nullptr;
+    const uint64_t* vec_ct(int vid, uint32_t i) const { return cts + ((size_t)vid * pl.n_ct + i) * CW; }
+};
+
+// A batch of compressions run as one sequence of batched phases: every phase
+// (Mask, switch, u-packing, baby steps, diagonal chunks, giant steps, each
+// rotate-and-sum shift, merge) handles all queries at once, so rotations by the
+// same Galois element across queries go through the same key-switching pass and
+// pairs with the same (s, B) share each diagonal chunk. All queries must have
+// the same Comp level. Each query's result equals its single-query compression.
+hc_status compress_many(Ctx& c, const hc_gk* gk, const hc_db* db, std::vector<QueryRun>& qs, hipStream_t st) {
+    if (qs.empty()) return HC_OK;
     const size_t n = c.n;
-    const Layout ly = layout_for(c, pl);
-    const size_t CW = ly.CW, PW = ly.PW, CWF = ly.CWF, PWF = (size_t)c.L * n;
-    const int Lc = pl.level;
-    for (uint32_t k : pl.keys)
-        if (!find_key(gk, k)) return HC_ENOKEY;
-    if (pl.ncol && (!db || db->ncol != pl.ncol || db->N != pl.N)) return HC_EINVAL;
+    const int Lc = qs[0].pl.level;
+    size_t total = 64 * 256, max_jobs = 1;
+    size_t diag_max = 1;
+    std::map<std::pair<uint32_t, uint32_t>, uint32_t> cls_k;  // (s, B) -> max k
+    for (auto& q : qs) {
+        if (q.pl.level != Lc) return HC_EINVAL;
+        for (uint32_t k : q.pl.keys)
+            if (!find_key(gk, k)) return HC_ENOKEY;
+        if (q.pl.ncol && (!db || db->ncol != q.pl.ncol || db->N < q.pl.N)) return HC_EINVAL;
+        q.sizes(c);
+        total += q.bytes(c);
+        max_jobs = std::max<size_t>({max_jobs, q.ub, q.baby, q.gi, (size_t)q.pl.bands});
+        for (auto& g : q.pl.groups) {
+            auto key = std::make_pair(q.pl.s, g.B);
+            cls_k[key] = std::max(cls_k[key], g.k);
+        }
+    }
+    size_t jobs_all = 0;
+    for (auto& q : qs) jobs_all = std::max(jobs_all, q.ub + q.baby + q.gi);
+    max_jobs = std::max(max_jobs, jobs_all * qs.size());
+    const size_t PW = (size_t)Lc * n;
+    std::map<std::pair<uint32_t, uint32_t>, uint32_t> cls_gc;
+    for (auto& kv : cls_k) {
+        const uint32_t s = kv.first.first, B = kv.first.second, kb = kv.second;
+        const size_t per_g = (size_t)kb * B * PW * 8;
+        const uint32_t Gc = (uint32_t)std::min<size_t>(s / B, std::max<size_t>(1, kDiagBudgetBytes / per_g));
+        cls_gc[kv.first] = Gc;
+        diag_max = std::max(diag_max, (size_t)kb * Gc * B);
+    }
+    total += rup(PW * 8 * diag_max) + rup(n * 4 * diag_max) + ks_scratch_bytes(c, Lc, (int)max_jobs);
 
     stage_reset(c, st);  // the workspace and staging area are reused call to call
-    if (c.ws.reserve(ly.total_bytes) != HC_OK) return HC_ENOMEM;
+    if (c.ws.reserve(total) != HC_OK) return HC_ENOMEM;
     Arena& a = c.ws;
-    const size_t max_jobs = std::max<size_t>({ly.ub_total, ly.baby_total, ly.gi_total, (size_t)pl.bands, 1});
     KsScratch ks = ks_scratch(c, a, Lc, (int)max_jobs);
+    for (auto& q : qs)
+        if (q.take(a) != HC_OK) return HC_ENOMEM;
+    uint64_t* D = a.take<uint64_t>(PW * diag_max);
+    uint32_t* Dp = a.take<uint32_t>(n * diag_max);
+    if (!D || !Dp) return HC_ENOMEM;
     hc_status err = HC_OK;
 #define RUN(x) do { if ((err = (x)) != HC_OK) return err; } while (0)
-
-    // 1. inputs to the NTT domain; Mask at the top level (Alg. 7 step 2)
-    uint64_t* ctf = a.take<uint64_t>(CWF * ly.ntot);
-    if (!ctf) return HC_ENOMEM;
-    HC_CHECK(hipMemcpyAsync(ctf, ct_v, sizeof(uint64_t) * CWF * pl.n_ct, hipMemcpyDeviceToDevice, st));
-    ntt64(c, ctf, PWF, 2 * (int)pl.n_ct, 0, c.L, false, st);
-    {
-        std::vector<EwJob> mj;
-        for (uint32_t col = 0; col < pl.ncol; col++)
-            for (uint32_t i = 0; i < pl.n_ct; i++)
-                mj.push_back(EwJob{ctf + ((size_t)(1 + col) * pl.n_ct + i) * CWF, ctf + i * CWF,
-                                   db->d_pt + ((size_t)col * pl.n_ct + i) * PWF});
-        RUN(ew_run(c, mj, c.L, true, st));
-    }
-    // 2. switch to the Comp level (Sec. 5.3's smaller parameters, as a modulus switch)
-    uint64_t* cts = ctf;
-    if (Lc < c.L) {
-        cts = a.take<uint64_t>(CW * ly.ntot);
-        uint64_t* conv = a.take<uint64_t>(CW * ly.ntot);
-        if (!cts || !conv) return HC_ENOMEM;
-        RUN(mod_switch_batch(c, cts, ctf, (int)ly.ntot, Lc, conv, st));
-    }
-    auto vec_ct = [&](int vid, uint32_t i) -> const uint64_t* { return cts + ((size_t)vid * pl.n_ct + i) * CW; };
-
-    // per-pair storage
-    const int npairs = ly.npairs;
-    uint64_t* ubuf = a.take<uint64_t>(CW * std::max<size_t>(ly.ub_total, 1));
-    uint64_t* tbuf = a.take<uint64_t>(CW * std::max<size_t>(ly.ub_total, 1));
-    uint64_t* rbuf = a.take<uint64_t>(CW * std::max<size_t>(ly.ub_total, 1));
-    uint64_t* wbuf = a.take<uint64_t>(CW * std::max<size_t>(ly.ub_total, 1));
-    uint64_t* bbuf = a.take<uint64_t>(CW * std::max<size_t>(ly.baby_total, 1));
-    uint64_t* gbuf = a.take<uint64_t>(CW * ly.gi_total);
-    uint64_t* gout = a.take<uint64_t>(CW * ly.gi_total);
-    uint64_t* ybuf = a.take<uint64_t>(CW * npairs);
-    uint64_t* ytmp = a.take<uint64_t>(CW * npairs);
-    uint64_t* mbuf = a.take<uint64_t>(CW * pl.bands);
-    uint64_t* mrot = a.take<uint64_t>(CW * pl.bands);
-    uint64_t* outN = a.take<uint64_t>(CW);
-    if (!ubuf || !tbuf || !rbuf || !wbuf || !bbuf || !gbuf || !gout || !ybuf || !ytmp || !mbuf || !mrot || !outN)
-        return HC_ENOMEM;
     const uint32_t col_k = 2u * c.n - 1;
     const uint64_t* col_key = find_key(gk, col_k);
 
+    // 1. inputs to the NTT domain; Mask at the top level (Alg. 7 step 2)
+    {
+        std::vector<EwJob> mj;
+        for (auto& q : qs) {
+            HC_CHECK(hipMemcpyAsync(q.ctf, q.ct_v, sizeof(uint64_t) * q.CWF * q.pl.n_ct, hipMemcpyDeviceToDevice, st));
+            ntt64(c, q.ctf, (size_t)c.L * n, 2 * (int)q.pl.n_ct, 0, c.L, false, st);
+            for (uint32_t col = 0; col < q.pl.ncol; col++)
+                for (uint32_t i = 0; i < q.pl.n_ct; i++)
+                    mj.push_back(EwJob{q.ctf + ((size_t)(1 + col) * q.pl.n_ct + i) * q.CWF, q.ctf + i * q.CWF,
+                                       db->d_pt + ((size_t)col * db->n_ct + i) * c.L * n});
+        }
+        RUN(ew_run(c, mj, c.L, true, st));
+    }
+    // 2. switch to the Comp level (Sec. 5.3's smaller parameters, as a modulus switch)
+    if (Lc < c.L)
+        for (auto& q : qs) RUN(mod_switch_batch(c, q.cts, q.ctf, (int)q.ntot, Lc, q.msconv, st));
+
     // 3. u-blocks (Sec. 5.2 remark): row 0: A*[1;0] + Rot_col(B*[1;0]); row 1: Rot_col(A*[0;1]) + B*[0;1]
-    std::vector<std::vector<uint64_t*>> U(npairs), A(npairs);
-    std::vector<std::vector<std::vector<uint64_t*>>> R(npairs);
     {
         std::vector<EwJob> mul, add;
         std::vector<KsJob> rot;
-        size_t uo = 0;
-        int pp = 0;
-        for (auto& g : pl.groups) {
-            for (auto& sm : pl.streams) {
-                U[pp].resize(g.k);
-                for (uint32_t beta = 0; beta < g.k; beta++, uo++) {
-                    uint64_t *u = ubuf + uo * CW, *t = tbuf + uo * CW, *r = rbuf + uo * CW, *w = wbuf + uo * CW;
-                    U[pp][beta] = u;
-                    const uint32_t i = g.ct_start + beta / 2;
-                    const uint64_t* Act = vec_ct(sm.first, i);
-                    const uint64_t* Bct = sm.second >= 0 ? vec_ct(sm.second, i) : nullptr;
-                    if (beta % 2 == 0) {
-                        mul.push_back(EwJob{u, Act, c.d_rowmask[0]});
-                        if (Bct) {
-                            mul.push_back(EwJob{t, Bct, c.d_rowmask[0]});
-                            rot.push_back(KsJob{t, r, col_key, col_k, 0});
-                            add.push_back(EwJob{u, u, r});
-                        }
-                    } else {
-                        mul.push_back(EwJob{t, Act, c.d_rowmask[1]});
-                        if (Bct) {
-                            rot.push_back(KsJob{t, r, col_key, col_k, 0});
-                            mul.push_back(EwJob{w, Bct, c.d_rowmask[1]});
-                            add.push_back(EwJob{u, r, w});
+        for (auto& q : qs) {
+            const size_t CW = q.CW;
+            q.U.assign(q.npairs, {});
+            size_t uo = 0;
+            int pp = 0;
+            for (auto& g : q.pl.groups) {
+                for (auto& sm : q.pl.streams) {
+                    q.U[pp].resize(g.k);
+                    for (uint32_t beta = 0; beta < g.k; beta++, uo++) {
+                        uint64_t *u = q.ubuf + uo * CW, *t = q.tbuf + uo * CW, *r = q.rbuf + uo * CW,
+                                 *w = q.wbuf + uo * CW;
+                        q.U[pp][beta] = u;
+                        const uint32_t i = g.ct_start + beta / 2;
+                        const uint64_t* Act = q.vec_ct(sm.first, i);
+                        const uint64_t* Bct = sm.second >= 0 ? q.vec_ct(sm.second, i) : nullptr;
+                        if (beta % 2 == 0) {
+                            mul.push_back(EwJob{u, Act, c.d_rowmask[0]});
+                            if (Bct) {
+                                mul.push_back(EwJob{t, Bct, c.d_rowmask[0]});
+                                rot.push_back(KsJob{t, r, col_key, col_k, 0});
+                                add.push_back(EwJob{u, u, r});
+                            }
                         } else {
-                            rot.push_back(KsJob{t, u, col_key, col_k, 0});
+                            mul.push_back(EwJob{t, Act, c.d_rowmask[1]});
+                            if (Bct) {
+                                rot.push_back(KsJob{t, r, col_key, col_k, 0});
+                                mul.push_back(EwJob{w, Bct, c.d_rowmask[1]});
+                                add.push_back(EwJob{u, r, w});
+                            } else {
+                                rot.push_back(KsJob{t, u, col_key, col_k, 0});
+                            }
                         }
                     }
+                    pp++;
                 }
-                pp++;
             }
         }
         RUN(ew_run(c, mul, Lc, true, st));
@@ -309,144 +340,160 @@ hc_status compress_one(Ctx& c, const hc_gk* gk, const hc_db* db, const uint64_t*
     {
         std::vector<const uint64_t*> srcs;
         std::vector<KsJob> jobs;
-        size_t bo = 0;
-        int pp = 0;
-        for (auto& g : pl.groups) {
-            for (size_t si = 0; si < pl.streams.size(); si++, pp++) {
-                R[pp].assign(g.k, std::vector<uint64_t*>(g.B, nullptr));
-                for (uint32_t beta = 0; beta < g.k; beta++) {
-                    R[pp][beta][0] = U[pp][beta];
-                    if (g.B == 1) continue;
-                    const uint32_t xi = (uint32_t)srcs.size();
-                    srcs.push_back(U[pp][beta]);
-                    for (uint32_t b = 1; b < g.B; b++) {
-                        uint64_t* r = bbuf + (bo++) * CW;
-                        const uint32_t k = rot_elt(c, b);
-                        jobs.push_back(KsJob{U[pp][beta], r, find_key(gk, k), k, xi});
-                        R[pp][beta][b] = r;
+        for (auto& q : qs) {
+            const size_t CW = q.CW;
+            q.R.assign(q.npairs, {});
+            size_t bo = 0;
+            int pp = 0;
+            for (auto& g : q.pl.groups)
+                for (size_t si = 0; si < q.pl.streams.size(); si++, pp++) {
+                    q.R[pp].assign(g.k, std::vector<uint64_t*>(g.B, nullptr));
+                    for (uint32_t beta = 0; beta < g.k; beta++) {
+                        q.R[pp][beta][0] = q.U[pp][beta];
+                        if (g.B == 1) continue;
+                        const uint32_t xi = (uint32_t)srcs.size();
+                        srcs.push_back(q.U[pp][beta]);
+                        for (uint32_t b = 1; b < g.B; b++) {
+                            uint64_t* r = q.bbuf + (bo++) * CW;
+                            const uint32_t k = rot_elt(c, b);
+                            jobs.push_back(KsJob{q.U[pp][beta], r, find_key(gk, k), k, xi});
+                            q.R[pp][beta][b] = r;
+                        }
                     }
                 }
-            }
         }
         if (!jobs.empty()) RUN(ks_run(c, ks, jobs, &srcs, Lc, st));
     }
 
-    // 5. diagonals encoded on the fly and accumulated into the giant accumulators,
-    //    one chunk of giant indices at a time for every pair that shares B
-    {
+    // 5. diagonals encoded on the fly, one chunk of giant indices at a time, accumulated
+    //    for every pair (of every query) with the same (s, B)
+    for (auto& q : qs) {
+        q.A.assign(q.npairs, {});
         size_t go = 0;
         int pp = 0;
-        for (auto& g : pl.groups)
-            for (size_t si = 0; si < pl.streams.size(); si++, pp++) {
-                A[pp].resize(pl.s / g.B);
-                for (uint32_t gi = 0; gi < pl.s / g.B; gi++) A[pp][gi] = gbuf + (go++) * CW;
+        for (auto& g : q.pl.groups)
+            for (size_t si = 0; si < q.pl.streams.size(); si++, pp++) {
+                q.A[pp].resize(q.pl.s / g.B);
+                for (uint32_t gi = 0; gi < q.pl.s / g.B; gi++) q.A[pp][gi] = q.gbuf + (go++) * q.CW;
             }
-        std::set<uint32_t> Bs;
-        for (auto& g : pl.groups) Bs.insert(g.B);
-        uint64_t* D = a.take<uint64_t>(PW * ly.diag_cnt);
-        uint32_t* Dp = a.take<uint32_t>((size_t)n * ly.diag_cnt);
-        if (!D || !Dp) return HC_ENOMEM;
+    }
+    for (auto& kv : cls_k) {
+        const uint32_t s = kv.first.first, B = kv.first.second, kb = kv.second, Gc = cls_gc[kv.first];
+        std::vector<std::pair<QueryRun*, int>> cls;
+        for (auto& q : qs)
+            for (int pp = 0; pp < q.npairs; pp++)
+                if (q.pl.s == s && q.pl.groups[pp / q.pl.streams.size()].B == B) cls.push_back({&q, pp});
+        const uint32_t G = s / B;
         std::vector<uint32_t> hprm;
         std::vector<const uint64_t*> hptr;
-        for (uint32_t B : Bs) {
-            std::vector<int> cls;
-            uint32_t kb = 0;
-            for (int q = 0; q < npairs; q++) {
-                const PlanGroup& g = pl.groups[q / pl.streams.size()];
-                if (g.B == B) { cls.push_back(q); kb = std::max(kb, g.k); }
+        for (uint32_t g0 = 0; g0 < G; g0 += Gc) {
+            const uint32_t gc = std::min(Gc, G - g0);
+            hprm.clear();
+            for (uint32_t beta = 0; beta < kb; beta++)
+                for (uint32_t gi = 0; gi < gc; gi++)
+                    for (uint32_t b = 0; b < B; b++) {
+                        hprm.push_back(beta);
+                        hprm.push_back(g0 + gi);
+                        hprm.push_back(b);
+                    }
+            const int cnt = (int)(hprm.size() / 3);
+            // R pointers [cls][kb][B], then A pointers [cls][gc]
+            hptr.assign(cls.size() * kb * B + cls.size() * gc, nullptr);
+            for (size_t ci = 0; ci < cls.size(); ci++) {
+                QueryRun& q = *cls[ci].first;
+                const int pp = cls[ci].second;
+                for (uint32_t beta = 0; beta < q.R[pp].size(); beta++)
+                    for (uint32_t b = 0; b < B; b++) hptr[(ci * kb + beta) * B + b] = q.R[pp][beta][b];
+                for (uint32_t gi = 0; gi < gc; gi++) hptr[cls.size() * kb * B + ci * gc + gi] = q.A[pp][g0 + gi];
             }
-            const uint32_t G = pl.s / B;
-            for (uint32_t g0 = 0; g0 < G; g0 += ly.Gc) {
-                const uint32_t gc = std::min(ly.Gc, G - g0);
-                hprm.clear();
-                for (uint32_t beta = 0; beta < kb; beta++)
-                    for (uint32_t gi = 0; gi < gc; gi++)
-                        for (uint32_t b = 0; b < B; b++) {
-                            hprm.push_back(beta);
-                            hprm.push_back(g0 + gi);
-                            hprm.push_back(b);
-                        }
-                const int cnt = (int)(hprm.size() / 3);
-                // R pointers [cls][kb][B], then A pointers [cls][gc]
-                hptr.assign((size_t)cls.size() * kb * B + cls.size() * gc, nullptr);
-                for (size_t ci = 0; ci < cls.size(); ci++) {
-                    const int q = cls[ci];
-                    for (uint32_t beta = 0; beta < R[q].size(); beta++)
-                        for (uint32_t b = 0; b < B; b++) hptr[(ci * kb + beta) * B + b] = R[q][beta][b];
-                    for (uint32_t gi = 0; gi < gc; gi++)
-                        hptr[(size_t)cls.size() * kb * B + ci * gc + gi] = A[q][g0 + gi];
-                }
-                const uint32_t* dprm = (const uint32_t*)stage_bytes(c, hprm.data(), sizeof(uint32_t) * hprm.size(), st);
-                uint64_t** dptr = (uint64_t**)stage_bytes(c, hptr.data(), sizeof(uint64_t*) * hptr.size(), st);
-                if (!dprm || !dptr) return HC_ENOMEM;
-                k_diag_gen(c, Dp, dprm, cnt, pl.s, B, st);
-                ntt32(c, Dp, cnt, true, st);
-                k_lift(c, D, Dp, cnt, true, Lc, st);
-                ntt64(c, D, PW, cnt, 0, Lc, false, st);
-                k_diag_mac(c, dptr + (size_t)cls.size() * kb * B, (const uint64_t* const*)dptr, D,
-                           (int)cls.size(), (int)kb, (int)gc, (int)B, false, Lc, st);
-            }
+            const uint32_t* dprm = (const uint32_t*)stage_bytes(c, hprm.data(), sizeof(uint32_t) * hprm.size(), st);
+            uint64_t** dptr = (uint64_t**)stage_bytes(c, hptr.data(), sizeof(uint64_t*) * hptr.size(), st);
+            if (!dprm || !dptr) return HC_ENOMEM;
+            k_diag_gen(c, Dp, dprm, cnt, s, B, st);
+            ntt32(c, Dp, cnt, true, st);
+            k_lift(c, D, Dp, cnt, true, Lc, st);
+            ntt64(c, D, PW, cnt, 0, Lc, false, st);
+            k_diag_mac(c, dptr + cls.size() * kb * B, (const uint64_t* const*)dptr, D, (int)cls.size(), (int)kb,
+                       (int)gc, (int)B, false, Lc, st);
         }
     }
 
     // 6. giant steps: y = A_0 + sum_g Rot_row(A_g; g B)
     {
         std::vector<KsJob> jobs;
-        size_t go = 0;
-        int pp = 0;
-        for (auto& g : pl.groups)
-            for (size_t si = 0; si < pl.streams.size(); si++, pp++) {
-                const uint32_t G = pl.s / g.B;
-                HC_CHECK(hipMemcpyAsync(gout + go * CW, A[pp][0], sizeof(uint64_t) * CW, hipMemcpyDeviceToDevice, st));
-                for (uint32_t gi = 1; gi < G; gi++) {
-                    const uint32_t k = rot_elt(c, (int64_t)gi * g.B);
-                    jobs.push_back(KsJob{A[pp][gi], gout + (go + gi) * CW, find_key(gk, k), k, 0});
+        for (auto& q : qs) {
+            size_t go = 0;
+            int pp = 0;
+            for (auto& g : q.pl.groups)
+                for (size_t si = 0; si < q.pl.streams.size(); si++, pp++) {
+                    const uint32_t G = q.pl.s / g.B;
+                    HC_CHECK(hipMemcpyAsync(q.gout + go * q.CW, q.A[pp][0], sizeof(uint64_t) * q.CW,
+                                            hipMemcpyDeviceToDevice, st));
+                    for (uint32_t gi = 1; gi < G; gi++) {
+                        const uint32_t k = rot_elt(c, (int64_t)gi * g.B);
+                        jobs.push_back(KsJob{q.A[pp][gi], q.gout + (go + gi) * q.CW, find_key(gk, k), k, 0});
+                    }
+                    go += G;
                 }
-                go += G;
-            }
+        }
         if (!jobs.empty()) RUN(ks_run(c, ks, jobs, nullptr, Lc, st));
-        go = 0;
-        pp = 0;
-        for (auto& g : pl.groups)
-            for (size_t si = 0; si < pl.streams.size(); si++, pp++) {
-                const uint32_t G = pl.s / g.B;
-                k_sum_cts(c, ybuf + (size_t)pp * CW, gout + go * CW, 1, (int)G, Lc, st);
-                go += G;
-            }
+        for (auto& q : qs) {
+            size_t go = 0;
+            int pp = 0;
+            for (auto& g : q.pl.groups)
+                for (size_t si = 0; si < q.pl.streams.size(); si++, pp++) {
+                    const uint32_t G = q.pl.s / g.B;
+                    k_sum_cts(c, q.ybuf + (size_t)pp * q.CW, q.gout + go * q.CW, 1, (int)G, Lc, st);
+                    go += G;
+                }
+        }
     }
 
-    // 7. rotate-and-sum, once after the block sums (Sec. 5.2): y += Rot_row(y; s 2^i), all pairs per step
-    for (uint64_t sh = pl.s; sh < (uint64_t)c.nh; sh *= 2) {
+    // 7. rotate-and-sum, once after the block sums (Sec. 5.2): y += Rot_row(y; sh) for
+    //    sh = s, 2s, .., n/4; one pass per shift over every query with s <= sh
+    for (uint64_t sh = 1; sh < (uint64_t)c.nh; sh *= 2) {
         const uint32_t k = rot_elt(c, (int64_t)sh);
         std::vector<KsJob> jobs;
-        for (int q = 0; q < npairs; q++) jobs.push_back(KsJob{ybuf + q * CW, ytmp + q * CW, find_key(gk, k), k, 0});
+        for (auto& q : qs)
+            if (q.pl.s <= sh)
+                for (int pp = 0; pp < q.npairs; pp++)
+                    jobs.push_back(KsJob{q.ybuf + pp * q.CW, q.ytmp + pp * q.CW, find_key(gk, k), k, 0});
+        if (jobs.empty()) continue;
         RUN(ks_run(c, ks, jobs, nullptr, Lc, st));
-        k_add(c, ybuf, ybuf, ytmp, 0, Lc, 2 * npairs, PW, st);
+        for (auto& q : qs)
+            if (q.pl.s <= sh) k_add(c, q.ybuf, q.ybuf, q.ytmp, 0, Lc, 2 * q.npairs, q.PW, st);
     }
 
-    // 8. merge the bands into one ciphertext
-    uint64_t* res = ybuf;
-    if (pl.bands > 1) {
-        const uint64_t* ms = nullptr;
-        RUN(prefix_mask(c, pl.s, &ms));
+    // 8. merge the bands of each query into one ciphertext
+    {
         std::vector<EwJob> mul;
         std::vector<KsJob> jobs;
-        for (uint32_t b = 0; b < pl.bands; b++) {
-            mul.push_back(EwJob{b == 0 ? mrot : mbuf + b * CW, ybuf + b * CW, ms});
-            if (b > 0) {
-                const uint32_t k = rot_elt(c, -(int64_t)b * pl.s);
-                jobs.push_back(KsJob{mbuf + b * CW, mrot + b * CW, find_key(gk, k), k, 0});
+        for (auto& q : qs) {
+            if (q.pl.bands <= 1) continue;
+            const uint64_t* ms = nullptr;
+            RUN(prefix_mask(c, q.pl.s, &ms));
+            for (uint32_t b = 0; b < q.pl.bands; b++) {
+                mul.push_back(EwJob{b == 0 ? q.mrot : q.mbuf + b * q.CW, q.ybuf + b * q.CW, ms});
+                if (b > 0) {
+                    const uint32_t k = rot_elt(c, -(int64_t)b * q.pl.s);
+                    jobs.push_back(KsJob{q.mbuf + b * q.CW, q.mrot + b * q.CW, find_key(gk, k), k, 0});
+                }
             }
         }
         RUN(ew_run(c, mul, Lc, true, st));
-        RUN(ks_run(c, ks, jobs, nullptr, Lc, st));
-        k_sum_cts(c, outN, mrot, 1, (int)pl.bands, Lc, st);
-        res = outN;
+        if (!jobs.empty()) RUN(ks_run(c, ks, jobs, nullptr, Lc, st));
+    }
+    // 9. outputs back to the coefficient domain
+    for (auto& q : qs) {
+        uint64_t* res = q.ybuf;
+        if (q.pl.bands > 1) {
+            k_sum_cts(c, q.outN, q.mrot, 1, (int)q.pl.bands, Lc, st);
+            res = q.outN;
+        }
+        ntt64(c, res, q.PW, 2, 0, Lc, true, st);
+        HC_CHECK(hipMemcpyAsync(q.ct_out, res, sizeof(uint64_t) * q.CW, hipMemcpyDeviceToDevice, st));
     }
 #undef RUN
-    // 9. back to the coefficient domain
-    ntt64(c, res, PW, 2, 0, Lc, true, st);
-    HC_CHECK(hipMemcpyAsync(ct_out, res, sizeof(uint64_t) * CW, hipMemcpyDeviceToDevice, st));
     HC_CHECK(hipGetLastError());
     return HC_OK;
 }
@@ -476,22 +523,51 @@ extern "C" hc_status hc_compress(hc_context* cp, const hc_gk* gk, const hc_db* d
                                  hc_compress_info* info, hipStream_t st) {
     if (!cp || !gk || !ct_v || !ct_out) return HC_EINVAL;
     HC_CHECK(hipSetDevice(cp->device));
-    Plan pl;
-    hc_status s = make_plan(*cp, N, db ? db->ncol : 0, t_bound, comp_level, pl);
+    std::vector<QueryRun> qs(1);
+    hc_status s = make_plan(*cp, N, db ? db->ncol : 0, t_bound, comp_level, qs[0].pl);
     if (s != HC_OK) return s;
-    s = compress_one(*cp, gk, db, ct_v, pl, ct_out, st);
-    if (s == HC_OK) fill_info(pl, info);
+    qs[0].ct_v = ct_v;
+    qs[0].ct_out = ct_out;
+    s = compress_many(*cp, gk, db, qs, st);
+    if (s == HC_OK) fill_info(qs[0].pl, info);
     return s;
 }
 
 extern "C" hc_status hc_compress_batch(hc_context* cp, const hc_gk* gk, const hc_db* db, hc_query* q,
                                        uint32_t nq, hipStream_t st) {
     if (!cp || !gk || (nq && !q)) return HC_EINVAL;
+    HC_CHECK(hipSetDevice(cp->device));
+    // plan every query; queries are batched by Comp level (normally all share one)
+    std::map<int, std::vector<QueryRun>> by_level;
+    std::map<int, std::vector<uint32_t>> idx;
     hc_status first = HC_OK;
     for (uint32_t i = 0; i < nq; i++) {
-        q[i].status = hc_compress(cp, gk, db, q[i].ct_v, q[i].N, q[i].t_bound, q[i].comp_level,
-                                  q[i].ct_out, q[i].info, st);
-        if (q[i].status != HC_OK && first == HC_OK) first = q[i].status;
+        QueryRun r;
+        q[i].status = (!q[i].ct_v || !q[i].ct_out)
+                          ? HC_EINVAL
+                          : make_plan(*cp, q[i].N, db ? db->ncol : 0, q[i].t_bound, q[i].comp_level, r.pl);
+        if (q[i].status == HC_OK) {
+            for (uint32_t k : r.pl.keys)
+                if (!find_key(gk, k)) q[i].status = HC_ENOKEY;
+            if (r.pl.ncol && (!db || db->N < r.pl.N)) q[i].status = HC_EINVAL;
+        }
+        if (q[i].status != HC_OK) {
+            if (first == HC_OK) first = q[i].status;
+            continue;
+        }
+        r.ct_v = q[i].ct_v;
+        r.ct_out = q[i].ct_out;
+        by_level[r.pl.level].push_back(std::move(r));
+        idx[r.pl.level].push_back(i);
+    }
+    for (auto& kv : by_level) {
+        hc_status s = compress_many(*cp, gk, db, kv.second, st);
+        auto& ids = idx[kv.first];
+        for (size_t j = 0; j < ids.size(); j++) {
+            q[ids[j]].status = s;
+            if (s == HC_OK) fill_info(kv.second[j].pl, q[ids[j]].info);
+        }
+        if (s != HC_OK && first == HC_OK) first = s;
     }
     return first;
 }

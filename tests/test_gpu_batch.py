@@ -1,0 +1,83 @@
+"""Batched compression (many queries in one call) against single-query calls and
+the oracle: every query's output must be bit-identical to its compression alone."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_common import context, oracle_params, to_host, say
+
+pytestmark = pytest.mark.gpu
+
+
+def make_queries(ctx, ring_name, specs, ncol, seed, values="zp"):
+    """specs: list of (N, t). One database of max N records shared by all queries."""
+    from oracle import slots
+    Nmax = max(N for N, _ in specs)
+    rng = W.rng_for(seed, 0)
+    db = W.value_columns(rng, Nmax, ncol, values, ctx.p)
+    sk, pk = ctx.keygen(W.seed32("sk", seed))
+    keys = set()
+    for N, t in specs:
+        keys.update(ctx.plan(N, ncol, t)[0])
+    gk = ctx.galois_keygen(sk, sorted(keys), W.seed32("gk", seed))
+    dbh = ctx.db_upload(db)
+    qs = []
+    for qi, (N, t) in enumerate(specs):
+        v = W.index_vector(W.rng_for(seed, qi + 1), N, t)
+        n_ct = -(-N // ctx.n)
+        vm = slots.vector_to_slot_matrices(v, ctx.n, n_ct)
+        cts = ctx.ct_tensor(n_ct)
+        for i in range(n_ct):
+            ctx.encrypt(pk, vm[i], W.seed32("enc", seed, qi, i), out=cts[i])
+        qs.append(dict(N=N, t=t, v=v, cts=cts))
+    return sk, pk, gk, dbh, db, qs
+
+
+def run_batch_vs_single(ring_name, specs, ncol, seed, values="zp"):
+    from paper_2408_17063_amd import hc
+    ctx = context(ring_name)
+    sk, pk, gk, dbh, db, qs = make_queries(ctx, ring_name, specs, ncol, seed, values)
+    outs = [ctx.ct_tensor(1)[0] for _ in qs]
+    st, statuses, infos = ctx.compress_batch(gk, dbh, [(q["cts"], q["N"], q["t"], o) for q, o in zip(qs, outs)])
+    assert st == hc.HC_OK and all(x == hc.HC_OK for x in statuses)
+    for q, o, info in zip(qs, outs, infos):
+        alone, ainfo = ctx.compress(gk, dbh, q["cts"], q["N"], q["t"])
+        assert ainfo == info
+        assert np.array_equal(to_host(ctx.output(o, info)), to_host(ctx.output(alone, ainfo)))
+    return ctx, sk, gk, dbh, db, qs, outs, infos
+
+
+def test_batch_equals_single_and_oracle_small_ring():
+    from oracle import bfv, compress as C, slots
+    say("batch small ring")
+    specs = [(3 * 2048, 5), (7 * 2048, 13), (1000, 1), (7 * 2048 - 100, 30), (2048, 0 + 2)]
+    ctx, sk, gk, dbh, db, qs, outs, infos = run_batch_vs_single("ring-2048-p12289", specs, 4, 21)
+    pr = oracle_params("ring-2048-p12289")
+    osk, opk = bfv.keygen(pr, W.seed32("sk", 21))
+    keys = set()
+    for N, t in specs:
+        keys.update(C.make_schedule(pr.n, pr.p, N, 4, t).keys)
+    gks = {k: bfv.galois_keygen(pr, osk, k, W.seed32("gk", 21)) for k in keys}
+    for qi in (0, 2):
+        q = qs[qi]
+        sched = C.make_schedule(pr.n, pr.p, q["N"], 4, q["t"])
+        vm = slots.vector_to_slot_matrices(q["v"], pr.n, sched.n_ct)
+        octs = [bfv.encrypt(pr, opk, vm[i], W.seed32("enc", 21, qi, i)) for i in range(sched.n_ct)]
+        want = C.compress(pr, sched, octs, db, gks, level=infos[qi]["level"])
+        assert np.array_equal(to_host(ctx.output(outs[qi], infos[qi])), want.stack()), qi
+
+
+def test_batch_uneven_queries_ring_32768():
+    """Queries over a 2^15 ring with uneven record counts and sparsities in one call
+    (the batched workload's shape at a test size); each decrypts to its own
+    Vandermonde products."""
+    from oracle import compress as C
+    say("batch ring 32768")
+    specs = [(1 << 15, 16), (3 << 15, 100), (2 << 15, 600), (1 << 15, 1024)]
+    ctx, sk, gk, dbh, db, qs, outs, infos = run_batch_vs_single("ring-32768", specs, 1, 22, values="u16")
+    for q, o, info in zip(qs, outs, infos):
+        sched = C.make_schedule(ctx.n, ctx.p, q["N"], 1, q["t"])
+        dec = ctx.decrypt(sk, to_host(ctx.output(o, info)))
+        exp = C.expected_bands(sched, q["v"], db)
+        for b in range(sched.bands):
+            assert C.band_slots(sched, dec, b) == exp[b]
