@@ -51,7 +51,7 @@ def setup(wl_name):
         ctx.encrypt(pk, vm[i], W.seed32("enc", 0, i), out=cts[i])
     torch.cuda.synchronize()
     log("setup %.1fs: %d Galois keys, %d ciphertexts, plan %s" % (time.time() - t0, len(keys), n_ct, info))
-    return dict(ctx=ctx, sk=sk, gk=gk, db=dbh, cts=cts, v=v, dbv=db, wl=wl, info=info, keys=keys)
+    return dict(ctx=ctx, sk=sk, pk=pk, gk=gk, db=dbh, cts=cts, v=v, dbv=db, wl=wl, info=info, keys=keys)
 
 
 # 32-bit integer multiply peak derived from the chip: 256 CUs x 4 SIMDs x 16 lanes
@@ -91,38 +91,175 @@ def kernel_rooflines(ctx, hc):
 
 
 def cpu_baseline(info):
-    """The CPU oracle on a bounded sample of the same workload: one plain
-    rotation (key switch), one diagonal encoding and one plaintext product at
-    the full ring size, scaled by the step's operation counts."""
+    """The CPU oracle on a bounded sample of the same workload, scaled by the step's
+    operation counts. The oracle runs the same schedule as the library: Mask at the
+    full modulus, a modulus switch of each ciphertext, then the rest at the Comp
+    level. Sample: one Mask product and one modulus switch at the full modulus; one
+    rotation (key switch), one diagonal encoding and one diagonal product at the Comp
+    level; all at ring 2^16."""
     import numpy as np
     import workloads as W
     from oracle import bfv, compress as C
     from oracle.params import make_params
     r = W.RINGS["ring-65536"]
     pr = make_params(r.n, r.p, r.L, r.q_bits, r.K, r.p_bits)
+    level = info["level"]
     sk, pk = bfv.keygen(pr, W.seed32("sk", 0))
     k = bfv.rot_row_element(pr, 8)
     gk = bfv.galois_keygen(pr, sk, k, W.seed32("gk", 0))
     ct = bfv.encrypt(pr, pk, np.zeros((2, pr.nh), dtype=np.uint64), W.seed32("enc", 0, 0))
+    dbm = bfv.plain_poly(pr, C.db_slots(np.arange(pr.n, dtype=np.uint32) % 65536, pr.n, 0))
+    t = {}
     t0 = time.perf_counter()
-    bfv.rotate(pr, ct, gk)
-    t_ks = time.perf_counter() - t0
+    bfv.mul_plain(pr, ct, dbm)
+    t["mask"] = time.perf_counter() - t0
     t0 = time.perf_counter()
-    m = bfv.plain_poly(pr, C.diagonal_slots(pr.p, pr.nh, 1024, 8, 3, 5, 2))
-    t_enc = time.perf_counter() - t0
+    lo = bfv.mod_switch(pr, ct, level) if level < pr.L else ct
+    t["switch"] = time.perf_counter() - t0
+    plo = bfv.at_level(pr, level)
+    gklo = bfv.key_at_level(pr, gk, level)
     t0 = time.perf_counter()
-    bfv.mul_plain(pr, ct, m)
-    t_pt = time.perf_counter() - t0
-    per_query = info["n_keyswitch"] * t_ks + info["n_diag"] * t_enc + info["n_ptct"] * t_pt
-    log("cpu oracle sample: keyswitch %.1fs, diagonal encode %.2fs, ptct %.2fs -> %.0fs per compression"
-        % (t_ks, t_enc, t_pt, per_query))
+    bfv.rotate(plo, lo, gklo)
+    t["keyswitch"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    m = bfv.plain_poly(plo, C.diagonal_slots(pr.p, pr.nh, 1024, 8, 3, 5, 2))
+    t["encode"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    bfv.mul_plain(plo, lo, m)
+    t["ptct"] = time.perf_counter() - t0
+    n_mask = 4 * 16                      # value columns x input ciphertexts
+    n_switch = 16 * (1 + 4)
+    per_query = (n_mask * t["mask"] + n_switch * t["switch"] + info["n_keyswitch"] * t["keyswitch"] +
+                 info["n_diag"] * t["encode"] + (info["n_ptct"] - n_mask) * t["ptct"])
+    log("cpu oracle sample: %s -> %.0f s per compression" % ({a: round(b, 3) for a, b in t.items()}, per_query))
     return {"value": 1.0 / per_query, "unit": "compressions/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle (single thread) timed on one plain rotation, one diagonal encoding and "
-                      "one plaintext-ciphertext product at ring 2^16 / 24+3 primes "
-                      "(%.1f s, %.2f s, %.2f s), scaled by the step's %d key switches, %d diagonal "
-                      "encodings and %d plaintext products" % (t_ks, t_enc, t_pt, info["n_keyswitch"],
-                                                               info["n_diag"], info["n_ptct"]),
+            "sample": "oracle (single thread) timed at ring 2^16 on one Mask product and one modulus switch "
+                      "at 24 primes, and one rotation, one diagonal encoding and one diagonal product at "
+                      "%d primes (%s s), scaled by the step's %d Mask products, %d switches, %d key switches, "
+                      "%d diagonal encodings and %d other plaintext products"
+                      % (level, ", ".join("%s %.3f" % kv for kv in t.items()), n_mask, n_switch,
+                         info["n_keyswitch"], info["n_diag"], info["n_ptct"] - n_mask),
             "extrapolated": True}
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    i = min(len(xs) - 1, max(0, int(math.ceil(q / 100.0 * len(xs))) - 1))
+    return xs[i]
+
+
+def encrypt_query(ctx, pk, v, n_ct, seed_ints):
+    import numpy as np
+    import workloads as W
+    vm = np.zeros(n_ct * ctx.n, dtype=np.uint32)
+    vm[:len(v)] = v
+    vm = vm.reshape(n_ct, 2, ctx.nh)
+    cts = ctx.ct_tensor(n_ct)
+    for i in range(n_ct):
+        ctx.encrypt(pk, vm[i], W.seed32("enc", *seed_ints, i), out=cts[i])
+    return cts
+
+
+def batched_large(st, Q, steps):
+    """Q queries of the headline workload (own index vectors) in one hc_compress_batch."""
+    import torch
+    import workloads as W
+    from paper_2408_17063_amd import hc
+    ctx, wl = st["ctx"], st["wl"]
+    pk = st["pk"]
+    qs = []
+    for qi in range(Q):
+        v, _ = W.query_inputs(wl, query=100 + qi)
+        qs.append((encrypt_query(ctx, pk, v, st["cts"].shape[0], (100 + qi,)), wl.N, wl.t, ctx.ct_tensor(1)[0]))
+    ctx.compress_batch(st["gk"], st["db"], qs)  # warm-up (workspace)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        rc, stats, _ = ctx.compress_batch(st["gk"], st["db"], qs)
+        assert rc == hc.HC_OK
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    del qs
+    torch.cuda.empty_cache()
+    return {"queries": Q, "ms_per_batch": round(ms, 2), "value": round(Q / (ms / 1e3), 4),
+            "unit": "compressions/s"}
+
+
+def mixed_batch(count=64):
+    """The batched configuration: `count` independent compressions over the 2^15 ring
+    (14 x 55-bit + 2 x 60-bit primes), ciphertexts per query uniform in 1..32, t
+    log-uniform in [16, 1024], one value column; one hc_compress_batch call vs the
+    same queries as `count` sequential hc_compress calls."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2408_17063_amd import hc
+    r = W.RINGS["ring-32768"]
+    ctx = hc.Context(log_n=15, p=r.p, L=r.L, q_bits=r.q_bits, K=r.K, p_bits=r.p_bits)
+    specs = W.batched_queries(count=count, seed=0, max_ct=32, n=ctx.n)
+    Nmax = 32 * ctx.n
+    rng = W.rng_for(0xBA7C, 1)
+    db = W.value_columns(rng, Nmax, 1, "u16", ctx.p)
+    sk, pk = ctx.keygen(W.seed32("sk", 4))
+    keys = set()
+    for N, t in specs:
+        keys.update(ctx.plan(N, 1, t)[0])
+    gk = ctx.galois_keygen(sk, sorted(keys), W.seed32("gk", 4))
+    dbh = ctx.db_upload(db)
+    qs = []
+    for qi, (N, t) in enumerate(specs):
+        v = W.index_vector(W.rng_for(0xBA7C, 2, qi), N, t)
+        qs.append((encrypt_query(ctx, pk, v, N // ctx.n, (0xBA7C, qi)), N, t, ctx.ct_tensor(1)[0]))
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    # sequential plain calls (after one warm-up pass of the largest query)
+    big = max(range(count), key=lambda i: specs[i][0])
+    ctx.compress(gk, dbh, qs[big][0], qs[big][1], qs[big][2])
+    lat = []
+    t0 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    evs = []
+    for (cts, N, t, out) in qs:
+        e = torch.cuda.Event(enable_timing=True)
+        ctx.compress(gk, dbh, cts, N, t, out=out)
+        e.record(stream)
+        evs.append(e)
+    torch.cuda.synchronize()
+    prev = t0
+    for e in evs:
+        lat.append(prev.elapsed_time(e))
+        prev = e
+    seq_ms = t0.elapsed_time(evs[-1])
+    singles = [out.clone() for (_, _, _, out) in qs]
+    # one batched call
+    ctx.compress_batch(gk, dbh, qs)
+    torch.cuda.synchronize()
+    b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b0.record(stream)
+    rc, stats, infos = ctx.compress_batch(gk, dbh, qs)
+    b1.record(stream)
+    torch.cuda.synchronize()
+    assert rc == hc.HC_OK
+    batch_ms = b0.elapsed_time(b1)
+    same = all(torch.equal(ctx.output(out, info), ctx.output(ref, info))
+               for (_, _, _, out), ref, info in zip(qs, singles, infos))
+    res = {"queries": count, "ring_degree": ctx.n, "records_min": min(N for N, _ in specs),
+           "records_max": max(N for N, _ in specs), "t_min": min(t for _, t in specs),
+           "t_max": max(t for _, t in specs),
+           "sequential_ms": round(seq_ms, 2), "batched_ms": round(batch_ms, 2),
+           "sequential_value": round(count / (seq_ms / 1e3), 3), "batched_value": round(count / (batch_ms / 1e3), 3),
+           "speedup": round(seq_ms / batch_ms, 3), "unit": "compressions/s",
+           "sequential_p50_ms": round(percentile(lat, 50), 2), "sequential_p99_ms": round(percentile(lat, 99), 2),
+           "batch_equals_sequential": bool(same)}
+    del qs, singles
+    ctx.close()
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -132,6 +269,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large-65536")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-queries", type=int, default=8,
+                    help="queries of the headline workload per batched call (0: skip)")
+    ap.add_argument("--mixed-batch", type=int, default=64,
+                    help="queries of the mixed 2^15-ring batch (0: skip)")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="launch one plain copy kernel of this many MiB (counter calibration)")
     ap.add_argument("--comp-level", type=int, default=0,
                     help="ciphertext primes kept for Comp (0: the library default; 24: no switching)")
     args = ap.parse_args()
@@ -153,17 +296,27 @@ def main():
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
+    step_ev = []
     for _ in range(args.steps):
         ctx.compress(st["gk"], st["db"], st["cts"], wl.N, wl.t, out=out, comp_level=args.comp_level)
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record(stream)
+        step_ev.append(ev)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = e0.elapsed_time(e1)
+    lat, prev = [], e0
+    for ev in step_ev:
+        lat.append(prev.elapsed_time(ev))
+        prev = ev
     ms_per_step = gpu_ms / args.steps
     value = args.steps / (gpu_ms / 1000.0)
     log("timed %d steps: %.1f ms/step (events), wall %.2fs" % (args.steps, ms_per_step, wall))
     rl = kernel_rooflines(ctx, hc)
     ctx.timing(False)
+    if args.copy_probe_mb:
+        ctx.probe_copy(args.copy_probe_mb << 20)
     for name, r in rl.items():
         log("  %-16s %8.1f ms %6d launches  %s %.3f of peak" % (name, r["ms"], r["launches"], r["bound"],
                                                                r["frac"]))
@@ -191,6 +344,15 @@ def main():
                    "ptct_per_step": st["info"]["n_ptct"],
                    "comp_level_primes": info["level"]},
     }
+    rec["latency_ms"] = {"p50": round(percentile(lat, 50), 2), "p99": round(percentile(lat, 99), 2),
+                         "kind": "plain, one query at a time"}
+    if args.batch_queries:
+        rec["batched"] = batched_large(st, args.batch_queries, max(1, args.steps // 2))
+        log("batched %d queries: %.1f ms per batch, %.3f compressions/s" % (
+            args.batch_queries, rec["batched"]["ms_per_batch"], rec["batched"]["value"]))
+    if args.mixed_batch:
+        rec["mixed_batch"] = mixed_batch(args.mixed_batch)
+        log("mixed batch:", rec["mixed_batch"])
     rec["roofline"] = dict(rl[dominant], kernel=dominant)
     if "keyswitch_inner" in rl:
         rec["roofline_keyswitch"] = dict(rl["keyswitch_inner"], kernel="keyswitch_inner")

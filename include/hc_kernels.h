@@ -113,6 +113,11 @@ hc_status hc_timing_read(hc_context* ctx, int kind, double* total_ms, uint64_t* 
  * the measured rate in multiply-adds per second (device-wide). */
 hc_status hc_probe_mul32_rate(hc_context* ctx, double ms, double* rate_out);
 
+/* Calibration probe for memory counters: one launch of a plain copy kernel
+ * (hc::probe_copy_kernel) that reads `bytes` and writes `bytes` of freshly
+ * allocated device memory (rounded down to 8-byte words). Synchronises. */
+hc_status hc_probe_copy(hc_context* ctx, uint64_t bytes);
+
 #ifdef __cplusplus
 }
 #endif

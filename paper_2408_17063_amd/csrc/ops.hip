@@ -730,6 +730,28 @@ __global__ void probe_mul32_kernel(uint64_t* sink, uint32_t iters) {
 
 }  // namespace hc
 
+namespace hc {
+__global__ void probe_copy_kernel(uint64_t* __restrict__ dst, const uint64_t* __restrict__ src, size_t words) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < words; i += stride) dst[i] = src[i];
+}
+}  // namespace hc
+
+extern "C" hc_status hc_probe_copy(hc_context* c, uint64_t bytes) {
+    if (!c || bytes < 8) return HC_EINVAL;
+    HC_CHECK(hipSetDevice(c->device));
+    const size_t words = bytes / 8;
+    uint64_t *a = nullptr, *b = nullptr;
+    HC_CHECK(hipMalloc((void**)&a, words * 8));
+    HC_CHECK(hipMalloc((void**)&b, words * 8));
+    hipLaunchKernelGGL(hc::probe_copy_kernel, dim3(4096), dim3(256), 0, 0, b, a, words);
+    HC_CHECK(hipDeviceSynchronize());
+    HC_CHECK(hipFree(a));
+    HC_CHECK(hipFree(b));
+    return HC_OK;
+}
+
 extern "C" hc_status hc_probe_mul32_rate(hc_context* c, double ms, double* rate_out) {
     if (!c || !rate_out || ms <= 0) return HC_EINVAL;
     HC_CHECK(hipSetDevice(c->device));

@@ -103,6 +103,7 @@ _sig("hc_timing_enable", _st, c_vp, ctypes.c_int)
 _sig("hc_timing_read", _st, c_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
      ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
 _sig("hc_probe_mul32_rate", _st, c_vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double))
+_sig("hc_probe_copy", _st, c_vp, ctypes.c_uint64)
 
 KT_NTT_FWD, KT_NTT_INV, KT_KS_INNER, KT_DIAG_MAC, KT_MODUP = 0, 1, 2, 3, 4
 KT_NAMES = {KT_NTT_FWD: "ntt_forward", KT_NTT_INV: "ntt_inverse", KT_KS_INNER: "keyswitch_inner",
@@ -114,7 +115,7 @@ EXPORTED = [
     "hc_db_upload", "hc_db_destroy", "hc_encrypt", "hc_compress", "hc_compress_batch",
     "hc_decrypt", "hc_decompress", "hc_ntt", "hc_rotate", "hc_rotate_hoisted", "hc_mul_plain",
     "hc_modup", "hc_moddown", "hc_sample", "hc_encode_diagonal", "hc_export_sk", "hc_export_pk",
-    "hc_export_gk", "hc_timing_enable", "hc_timing_read", "hc_probe_mul32_rate",
+    "hc_export_gk", "hc_timing_enable", "hc_timing_read", "hc_probe_mul32_rate", "hc_probe_copy",
 ]
 
 
@@ -320,6 +321,9 @@ class Context:
         r = ctypes.c_double()
         _check(_lib.hc_probe_mul32_rate(self.h, ms, ctypes.byref(r)), "hc_probe_mul32_rate")
         return r.value
+
+    def probe_copy(self, nbytes):
+        _check(_lib.hc_probe_copy(self.h, int(nbytes)), "hc_probe_copy")
 
     def export_sk(self, sk):
         out = np.zeros(self.n, dtype=np.int64)
