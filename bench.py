@@ -190,6 +190,31 @@ def batched_large(st, Q, steps):
             "unit": "compressions/s"}
 
 
+def on_the_fly(st, resident_out, steps, comp_level):
+    """The same compression with the resident tables released: every step encodes its
+    diagonals itself. Its output must equal the resident run's bit for bit."""
+    import torch
+    ctx, wl = st["ctx"], st["wl"]
+    ref = resident_out.clone()
+    ctx.diag_release()
+    out = ctx.ct_tensor(1)[0]
+    ctx.compress(st["gk"], st["db"], st["cts"], wl.N, wl.t, out=out, comp_level=comp_level)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        _, info = ctx.compress(st["gk"], st["db"], st["cts"], wl.N, wl.t, out=out, comp_level=comp_level)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    same = bool(torch.equal(out, ref))
+    del out, ref
+    torch.cuda.empty_cache()
+    return {"steps": steps, "ms_per_step": round(ms, 3), "value": round(1e3 / ms, 4),
+            "unit": "compressions/s", "n_diag_encoded_per_step": info["n_diag"], "equals_resident": same}
+
+
 def mixed_batch(count=64):
     """The batched configuration: `count` independent compressions over the 2^15 ring
     (14 x 55-bit + 2 x 60-bit primes), ciphertexts per query uniform in 1..32, t
@@ -248,6 +273,47 @@ def mixed_batch(count=64):
     batch_ms = b0.elapsed_time(b1)
     same = all(torch.equal(ctx.output(out, info), ctx.output(ref, info))
                for (_, _, _, out), ref, info in zip(qs, singles, infos))
+    # the same queries with every class's diagonals resident
+    t0p = time.perf_counter()
+    held = 0
+    for N, t in specs:
+        held = ctx.diag_prepare(N, 1, t)
+    prep_s = time.perf_counter() - t0p
+    ctx.compress(gk, dbh, qs[big][0], qs[big][1], qs[big][2])
+    torch.cuda.synchronize()
+    r0 = torch.cuda.Event(enable_timing=True)
+    r0.record(stream)
+    rlat, prev = [], r0
+    for (cts, N, t, out) in qs:
+        ctx.compress(gk, dbh, cts, N, t, out=out)
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        rlat.append(e)
+    torch.cuda.synchronize()
+    rseq_ms = r0.elapsed_time(rlat[-1])
+    rl_ms = []
+    for e in rlat:
+        rl_ms.append(prev.elapsed_time(e))
+        prev = e
+    same_r = all(torch.equal(ctx.output(out, info), ctx.output(ref, info))
+                 for (_, _, _, out), ref, info in zip(qs, singles, infos))
+    ctx.compress_batch(gk, dbh, qs)
+    torch.cuda.synchronize()
+    b0.record(stream)
+    rc, stats, infos = ctx.compress_batch(gk, dbh, qs)
+    b1.record(stream)
+    torch.cuda.synchronize()
+    assert rc == hc.HC_OK
+    rbatch_ms = b0.elapsed_time(b1)
+    same_rb = all(torch.equal(ctx.output(out, info), ctx.output(ref, info))
+                  for (_, _, _, out), ref, info in zip(qs, singles, infos))
+    resident = {"prepare_s": round(prep_s, 3), "bytes": held, "sequential_ms": round(rseq_ms, 2),
+                "batched_ms": round(rbatch_ms, 2), "sequential_value": round(count / (rseq_ms / 1e3), 3),
+                "batched_value": round(count / (rbatch_ms / 1e3), 3), "speedup": round(rseq_ms / rbatch_ms, 3),
+                "sequential_p50_ms": round(percentile(rl_ms, 50), 2),
+                "sequential_p99_ms": round(percentile(rl_ms, 99), 2),
+                "equals_on_the_fly": bool(same_r and same_rb)}
+    ctx.diag_release()
     res = {"queries": count, "ring_degree": ctx.n, "records_min": min(N for N, _ in specs),
            "records_max": max(N for N, _ in specs), "t_min": min(t for _, t in specs),
            "t_max": max(t for _, t in specs),
@@ -255,7 +321,7 @@ def mixed_batch(count=64):
            "sequential_value": round(count / (seq_ms / 1e3), 3), "batched_value": round(count / (batch_ms / 1e3), 3),
            "speedup": round(seq_ms / batch_ms, 3), "unit": "compressions/s",
            "sequential_p50_ms": round(percentile(lat, 50), 2), "sequential_p99_ms": round(percentile(lat, 99), 2),
-           "batch_equals_sequential": bool(same)}
+           "batch_equals_sequential": bool(same), "resident": resident}
     del qs, singles
     ctx.close()
     torch.cuda.empty_cache()
@@ -277,6 +343,11 @@ def main():
                     help="launch one plain copy kernel of this many MiB (counter calibration)")
     ap.add_argument("--comp-level", type=int, default=0,
                     help="ciphertext primes kept for Comp (0: the library default; 24: no switching)")
+    ap.add_argument("--diagonals", choices=["resident", "on-the-fly"], default="resident",
+                    help="resident: precompute the query-independent diagonals once (hc_diag_prepare) "
+                         "before timing; on-the-fly: encode them inside every compression")
+    ap.add_argument("--on-the-fly-steps", type=int, default=2,
+                    help="with resident diagonals, also time this many steps encoding them on the fly")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the compression path here is built and measured on a single "
@@ -289,6 +360,13 @@ def main():
     ctx, wl = st["ctx"], st["wl"]
     out = ctx.ct_tensor(1)[0]
     stream = torch.cuda.current_stream()
+    prep = None
+    if args.diagonals == "resident":
+        t0 = time.perf_counter()
+        held = ctx.diag_prepare(wl.N, wl.ncol, wl.t, args.comp_level)
+        prep = {"seconds": round(time.perf_counter() - t0, 3), "bytes": held}
+        log("resident diagonals: %.2f GB prepared in %.2fs" % (held / 1e9, prep["seconds"]))
+    info = st["info"]
     for _ in range(args.warmup):
         _, info = ctx.compress(st["gk"], st["db"], st["cts"], wl.N, wl.t, out=out, comp_level=args.comp_level)
     torch.cuda.synchronize()
@@ -346,17 +424,24 @@ def main():
     }
     rec["latency_ms"] = {"p50": round(percentile(lat, 50), 2), "p99": round(percentile(lat, 99), 2),
                          "kind": "plain, one query at a time"}
+    if prep is not None:
+        rec["config"]["diagonals"] = "resident (query-independent, prepared once before timing)"
+        rec["diag_prepare"] = prep
+    else:
+        rec["config"]["diagonals"] = "encoded on the fly inside every step"
     if args.batch_queries:
         rec["batched"] = batched_large(st, args.batch_queries, max(1, args.steps // 2))
         log("batched %d queries: %.1f ms per batch, %.3f compressions/s" % (
             args.batch_queries, rec["batched"]["ms_per_batch"], rec["batched"]["value"]))
+    if prep is not None and args.on_the_fly_steps:
+        rec["on_the_fly"] = on_the_fly(st, out, args.on_the_fly_steps, args.comp_level)
+        log("diagonals on the fly: %.1f ms/step; output equals resident: %s" % (
+            rec["on_the_fly"]["ms_per_step"], rec["on_the_fly"]["equals_resident"]))
     if args.mixed_batch:
         rec["mixed_batch"] = mixed_batch(args.mixed_batch)
         log("mixed batch:", rec["mixed_batch"])
     rec["roofline"] = dict(rl[dominant], kernel=dominant)
-    if "keyswitch_inner" in rl:
-        rec["roofline_keyswitch"] = dict(rl["keyswitch_inner"], kernel="keyswitch_inner")
-    rec["kernels"] = {k: {"ms": v["ms"], "frac": v["frac"], "bound": v["bound"]} for k, v in rl.items()}
+    rec["rooflines"] = rl
     rec["mul32_probe_T"] = round(probe, 3)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(st["info"])

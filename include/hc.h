@@ -81,8 +81,9 @@ typedef struct {
     uint32_t n_ct;         /* input ciphertexts ceil(N / n) */
     uint32_t n_keyswitch;  /* key switches performed */
     uint64_t n_ptct;       /* plaintext-ciphertext products performed */
-    uint64_t n_diag;       /* diagonal plaintexts encoded */
+    uint64_t n_diag;       /* diagonal plaintexts encoded during the call */
     uint32_t level;        /* ciphertext primes of the output (the Comp level) */
+    uint64_t n_diag_resident; /* diagonal plaintexts read from resident tables (hc_diag_prepare) */
 } hc_compress_info;
 
 /* ------------------------------------------------------------------ context */
@@ -185,6 +186,30 @@ typedef struct {
  * each query's own status in q[i].status). */
 hc_status hc_compress_batch(hc_context* ctx, const hc_gk* gk, const hc_db* db,
                             hc_query* q, uint32_t nq, hipStream_t stream);
+
+/* ------------------------------------------------------------------ resident diagonals (Sec. 5.2) */
+
+/* Server-side precomputation for the diagonal method of Sec. 5.2. The BSGS
+ * diagonals of C that a compression multiplies by depend only on the record
+ * groups (through N), on s and on the Comp level: never on the query or on the
+ * database. Encode every diagonal that compressions with (N, ncol, t_bound,
+ * comp_level) use and keep them resident on the device, one table per
+ * (s, B, level) class: [k][s/B][B][level][n] words, NTT domain, Montgomery
+ * form, k = the most u-blocks of a group. Later hc_compress and
+ * hc_compress_batch calls read a class from its table when it holds enough
+ * u-blocks, instead of encoding its diagonals on the fly; the results are
+ * bit-identical either way. A class already resident with at least k u-blocks
+ * is kept; one with fewer is rebuilt. The tables stay until hc_diag_release or
+ * hc_context_destroy. bytes_out (optional): device bytes then held by all
+ * tables. Synchronises the device.
+ * Errors: as hc_plan; HC_ENOMEM when a table does not fit in device memory
+ * (tables built before that one in the same call are kept). */
+hc_status hc_diag_prepare(hc_context* ctx, uint64_t N, uint32_t ncol, uint32_t t_bound,
+                          uint32_t comp_level, uint64_t* bytes_out);
+
+/* Free every resident diagonal table of ctx; later compressions encode their
+ * diagonals on the fly. Synchronises the device. */
+void hc_diag_release(hc_context* ctx);
 
 /* ------------------------------------------------------------------ client side (host CPU) */
 

@@ -147,12 +147,26 @@ static void fill_info(const Plan& pl, hc_compress_info* info) {
     info->n_ptct = pl.n_ptct;
     info->n_diag = pl.n_diag;
     info->level = (uint32_t)pl.level;
+    info->n_diag_resident = 0;
+}
+
+// Diagonal classes (s, B) of one plan with their largest u-block count.
+static std::map<uint32_t, uint32_t> plan_classes(const Plan& pl) {
+    std::map<uint32_t, uint32_t> kmax;  // B -> k
+    for (auto& g : pl.groups) kmax[g.B] = std::max(kmax[g.B], g.k);
+    return kmax;
 }
 
 static size_t rup(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Device-memory budget for the diagonal chunk buffer (plaintexts [Lc][n] u64).
 static const size_t kDiagBudgetBytes = (size_t)16 << 30;
+
+// The resident table of class (s, B) at level Lc if it holds at least kb u-blocks.
+static const Ctx::DiagTab* resident_table(const Ctx& c, uint32_t s, uint32_t B, int Lc, uint32_t kb) {
+    auto it = c.diag_tabs.find(std::make_tuple(s, B, Lc));
+    return (it != c.diag_tabs.end() && it->second.kb >= kb) ? &it->second : nullptr;
+}
 
 // One query of a batch and its device regions.
 struct QueryRun {
@@ -216,8 +230,16 @@ struct QueryRun {
         return HC_OK;
     }
     uint64_t* msconv = nullptr;
+    uint64_t n_diag = 0, n_diag_res = 0;  // diagonals encoded / read from resident tables
     const uint64_t* vec_ct(int vid, uint32_t i) const { return cts + ((size_t)vid * pl.n_ct + i) * CW; }
 };
+
+static void fill_info(const QueryRun& q, hc_compress_info* info) {
+    if (!info) return;
+    fill_info(q.pl, info);
+    info->n_diag = q.n_diag;
+    info->n_diag_resident = q.n_diag_res;
+}
 
 // A batch of compressions run as one sequence of batched phases: every phase
 // (Mask, switch, u-packing, baby steps, diagonal chunks, giant steps, each
@@ -231,7 +253,8 @@ hc_status compress_many(Ctx& c, const hc_gk* gk, const hc_db* db, std::vector<Qu
     const int Lc = qs[0].pl.level;
     size_t total = 64 * 256, max_jobs = 1;
     size_t diag_max = 1;
-    std::map<std::pair<uint32_t, uint32_t>, uint32_t> cls_k;  // (s, B) -> max k
+    std::map<std::pair<uint32_t, uint32_t>, uint32_t> cls_k;   // (s, B) -> max k
+    std::map<std::pair<uint32_t, uint32_t>, uint32_t> cls_np;  // (s, B) -> pairs
     for (auto& q : qs) {
         if (q.pl.level != Lc) return HC_EINVAL;
         for (uint32_t k : q.pl.keys)
@@ -243,6 +266,7 @@ hc_status compress_many(Ctx& c, const hc_gk* gk, const hc_db* db, std::vector<Qu
         for (auto& g : q.pl.groups) {
             auto key = std::make_pair(q.pl.s, g.B);
             cls_k[key] = std::max(cls_k[key], g.k);
+            cls_np[key] += (uint32_t)q.pl.streams.size();
         }
     }
     size_t jobs_all = 0;
@@ -250,14 +274,21 @@ hc_status compress_many(Ctx& c, const hc_gk* gk, const hc_db* db, std::vector<Qu
     max_jobs = std::max(max_jobs, jobs_all * qs.size());
     const size_t PW = (size_t)Lc * n;
     std::map<std::pair<uint32_t, uint32_t>, uint32_t> cls_gc;
+    std::map<std::pair<uint32_t, uint32_t>, const Ctx::DiagTab*> cls_res;
     for (auto& kv : cls_k) {
         const uint32_t s = kv.first.first, B = kv.first.second, kb = kv.second;
+        const Ctx::DiagTab* tab = resident_table(c, s, B, Lc, kb);
+        cls_res[kv.first] = tab;
+        if (tab) continue;
         const size_t per_g = (size_t)kb * B * PW * 8;
         const uint32_t Gc = (uint32_t)std::min<size_t>(s / B, std::max<size_t>(1, kDiagBudgetBytes / per_g));
         cls_gc[kv.first] = Gc;
         diag_max = std::max(diag_max, (size_t)kb * Gc * B);
     }
-    total += rup(PW * 8 * diag_max) + rup(n * 4 * diag_max) + ks_scratch_bytes(c, Lc, (int)max_jobs);
+    size_t rt_max = 1;  // gathered rotated ciphertexts of one class
+    for (auto& kv : cls_k) rt_max = std::max(rt_max, (size_t)cls_np[kv.first] * kv.second * kv.first.second * 2 * PW);
+    total += rup(PW * 8 * diag_max) + rup(n * 4 * diag_max) + rup(rt_max * 8) +
+             ks_scratch_bytes(c, Lc, (int)max_jobs);
 
     stage_reset(c, st);  // the workspace and staging area are reused call to call
     if (c.ws.reserve(total) != HC_OK) return HC_ENOMEM;
@@ -267,7 +298,13 @@ hc_status compress_many(Ctx& c, const hc_gk* gk, const hc_db* db, std::vector<Qu
         if (q.take(a) != HC_OK) return HC_ENOMEM;
     uint64_t* D = a.take<uint64_t>(PW * diag_max);
     uint32_t* Dp = a.take<uint32_t>(n * diag_max);
-    if (!D || !Dp) return HC_ENOMEM;
+    uint64_t* Rt = a.take<uint64_t>(rt_max);
+    if (!D || !Dp || !Rt) return HC_ENOMEM;
+    for (auto& q : qs) {
+        q.n_diag = q.n_diag_res = 0;
+        for (auto& kv : plan_classes(q.pl))
+            (cls_res[std::make_pair(q.pl.s, kv.first)] ? q.n_diag_res : q.n_diag) += (uint64_t)kv.second * q.pl.s;
+    }
     hc_status err = HC_OK;
 #define RUN(x) do { if ((err = (x)) != HC_OK) return err; } while (0)
     const uint32_t col_k = 2u * c.n - 1;
@@ -384,37 +421,54 @@ hc_status compress_many(Ctx& c, const hc_gk* gk, const hc_db* db, std::vector<Qu
             for (int pp = 0; pp < q.npairs; pp++)
                 if (q.pl.s == s && q.pl.groups[pp / q.pl.streams.size()].B == B) cls.push_back({&q, pp});
         const uint32_t G = s / B;
+        const size_t np = cls.size();
+        // the class's rotated ciphertexts, gathered once into the MAC's tiled layout
+        std::vector<const uint64_t*> hptr(np * kb * B + np * G, nullptr);
+        for (size_t ci = 0; ci < np; ci++) {
+            QueryRun& q = *cls[ci].first;
+            const int pp = cls[ci].second;
+            for (uint32_t beta = 0; beta < q.R[pp].size(); beta++)
+                for (uint32_t b = 0; b < B; b++) hptr[(ci * kb + beta) * B + b] = q.R[pp][beta][b];
+            for (uint32_t gi = 0; gi < G; gi++) hptr[np * kb * B + ci * G + gi] = q.A[pp][gi];
+        }
+        const uint64_t* const* rptr =
+            (const uint64_t* const*)stage_bytes(c, hptr.data(), sizeof(uint64_t*) * np * kb * B, st);
+        if (!rptr) return HC_ENOMEM;
+        k_diag_gather(c, Rt, rptr, (int)np, (int)(kb * B), Lc, st);
+        if (const Ctx::DiagTab* tab = cls_res[kv.first]) {
+            // resident diagonals: one pass over every giant index
+            uint64_t** aptr = (uint64_t**)stage_bytes(c, hptr.data() + np * kb * B, sizeof(uint64_t*) * np * G, st);
+            if (!aptr) return HC_ENOMEM;
+            k_diag_mac(c, aptr, Rt, tab->d, diag_layout_tiled(c, tab->kb * B, G), (int)np, (int)(kb * B), (int)G,
+                       false, Lc, st);
+            continue;
+        }
         std::vector<uint32_t> hprm;
-        std::vector<const uint64_t*> hptr;
+        std::vector<uint64_t*> haptr;
         for (uint32_t g0 = 0; g0 < G; g0 += Gc) {
             const uint32_t gc = std::min(Gc, G - g0);
             hprm.clear();
-            for (uint32_t beta = 0; beta < kb; beta++)
-                for (uint32_t gi = 0; gi < gc; gi++)
-                    for (uint32_t b = 0; b < B; b++) {
+            for (uint32_t beta = 0; beta < kb; beta++)  // chunk order (beta, b, g)
+                for (uint32_t b = 0; b < B; b++)
+                    for (uint32_t gi = 0; gi < gc; gi++) {
                         hprm.push_back(beta);
                         hprm.push_back(g0 + gi);
                         hprm.push_back(b);
                     }
             const int cnt = (int)(hprm.size() / 3);
-            // R pointers [cls][kb][B], then A pointers [cls][gc]
-            hptr.assign(cls.size() * kb * B + cls.size() * gc, nullptr);
-            for (size_t ci = 0; ci < cls.size(); ci++) {
-                QueryRun& q = *cls[ci].first;
-                const int pp = cls[ci].second;
-                for (uint32_t beta = 0; beta < q.R[pp].size(); beta++)
-                    for (uint32_t b = 0; b < B; b++) hptr[(ci * kb + beta) * B + b] = q.R[pp][beta][b];
-                for (uint32_t gi = 0; gi < gc; gi++) hptr[cls.size() * kb * B + ci * gc + gi] = q.A[pp][g0 + gi];
-            }
+            haptr.assign(np * gc, nullptr);  // A pointers [cls][gc]
+            for (size_t ci = 0; ci < np; ci++)
+                for (uint32_t gi = 0; gi < gc; gi++) haptr[ci * gc + gi] = cls[ci].first->A[cls[ci].second][g0 + gi];
             const uint32_t* dprm = (const uint32_t*)stage_bytes(c, hprm.data(), sizeof(uint32_t) * hprm.size(), st);
-            uint64_t** dptr = (uint64_t**)stage_bytes(c, hptr.data(), sizeof(uint64_t*) * hptr.size(), st);
-            if (!dprm || !dptr) return HC_ENOMEM;
+            uint64_t** aptr = (uint64_t**)stage_bytes(c, haptr.data(), sizeof(uint64_t*) * haptr.size(), st);
+            if (!dprm || !aptr) return HC_ENOMEM;
             k_diag_gen(c, Dp, dprm, cnt, s, B, st);
             ntt32(c, Dp, cnt, true, st);
             k_lift(c, D, Dp, cnt, true, Lc, st);
             ntt64(c, D, PW, cnt, 0, Lc, false, st);
-            k_diag_mac(c, dptr + cls.size() * kb * B, (const uint64_t* const*)dptr, D, (int)cls.size(), (int)kb,
-                       (int)gc, (int)B, false, Lc, st);
+            k_diag_split(c, D, (size_t)cnt * PW, Lc, st);
+            k_diag_mac(c, aptr, Rt, D, diag_layout_natural(c, Lc, gc), (int)np, (int)(kb * B), (int)gc, false, Lc,
+                       st);
         }
     }
 
@@ -510,6 +564,12 @@ extern "C" hc_status hc_plan(hc_context* cp, uint64_t N, uint32_t ncol, uint32_t
     hc_status s = make_plan(*cp, N, ncol, t_bound, comp_level, pl);
     if (s != HC_OK) return s;
     fill_info(pl, info);
+    if (info) {
+        info->n_diag = 0;
+        for (auto& kv : plan_classes(pl))
+            (resident_table(*cp, pl.s, kv.first, pl.level, kv.second) ? info->n_diag_resident : info->n_diag) +=
+                (uint64_t)kv.second * pl.s;
+    }
     uint32_t cap = *count;
     *count = (uint32_t)pl.keys.size();
     if (cap < pl.keys.size()) return HC_EINVAL;
@@ -529,7 +589,7 @@ extern "C" hc_status hc_compress(hc_context* cp, const hc_gk* gk, const hc_db* d
     qs[0].ct_v = ct_v;
     qs[0].ct_out = ct_out;
     s = compress_many(*cp, gk, db, qs, st);
-    if (s == HC_OK) fill_info(qs[0].pl, info);
+    if (s == HC_OK) fill_info(qs[0], info);
     return s;
 }
 
@@ -565,9 +625,89 @@ extern "C" hc_status hc_compress_batch(hc_context* cp, const hc_gk* gk, const hc
         auto& ids = idx[kv.first];
         for (size_t j = 0; j < ids.size(); j++) {
             q[ids[j]].status = s;
-            if (s == HC_OK) fill_info(kv.second[j].pl, q[ids[j]].info);
+            if (s == HC_OK) fill_info(kv.second[j], q[ids[j]].info);
         }
         if (s != HC_OK && first == HC_OK) first = s;
     }
     return first;
+}
+
+extern "C" hc_status hc_diag_prepare(hc_context* cp, uint64_t N, uint32_t ncol, uint32_t t_bound,
+                                     uint32_t comp_level, uint64_t* bytes_out) {
+    if (!cp) return HC_EINVAL;
+    Ctx& c = *cp;
+    HC_CHECK(hipSetDevice(c.device));
+    Plan pl;
+    hc_status s = make_plan(c, N, ncol, t_bound, comp_level, pl);
+    if (s != HC_OK) return s;
+    const int Lc = pl.level;
+    const size_t n = c.n, PW = (size_t)Lc * n;
+    const hipStream_t st = nullptr;
+    for (auto& kv : plan_classes(pl)) {
+        const uint32_t B = kv.first, kb = kv.second, G = pl.s / B;
+        if (resident_table(c, pl.s, B, Lc, kb)) continue;
+        const auto key = std::make_tuple(pl.s, B, Lc);
+        auto old = c.diag_tabs.find(key);
+        if (old != c.diag_tabs.end()) {
+            HC_CHECK(hipDeviceSynchronize());
+            HC_CHECK(hipFree(old->second.d));
+            c.diag_tabs.erase(old);
+        }
+        const size_t count = (size_t)kb * G * B;
+        Ctx::DiagTab tab;
+        tab.kb = kb;
+        tab.bytes = diag_table_words(c, Lc, kb * B, G) * 8;
+        if (hipMalloc((void**)&tab.d, tab.bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return HC_ENOMEM;
+        }
+        // encode in chunks: slot values (Sec. 5.2 diagonals of C), to R_p, lift, NTT per
+        // prime, then into the table's tiled layout
+        const size_t chunk = std::min<size_t>(count, 2048);
+        stage_reset(c, st);
+        if (c.ws.reserve(n * 4 * chunk + PW * 8 * chunk + 4096) != HC_OK) {
+            (void)hipFree(tab.d);
+            return HC_ENOMEM;
+        }
+        c.ws.reset();
+        uint32_t* Dp = c.ws.take<uint32_t>(n * chunk);
+        uint64_t* Dn = c.ws.take<uint64_t>(PW * chunk);
+        std::vector<uint32_t> hprm;
+        for (size_t i0 = 0; i0 < count; i0 += chunk) {
+            const size_t cnt = std::min(chunk, count - i0);
+            hprm.clear();
+            for (size_t i = i0; i < i0 + cnt; i++) {
+                hprm.push_back((uint32_t)(i / ((size_t)G * B)));  // beta
+                hprm.push_back((uint32_t)((i / B) % G));           // giant index
+                hprm.push_back((uint32_t)(i % B));                 // baby index
+            }
+            stage_reset(c, st);
+            const uint32_t* dprm = (const uint32_t*)stage_bytes(c, hprm.data(), sizeof(uint32_t) * hprm.size(), st);
+            if (!dprm) {
+                (void)hipFree(tab.d);
+                return HC_ENOMEM;
+            }
+            k_diag_gen(c, Dp, dprm, (int)cnt, pl.s, B, st);
+            ntt32(c, Dp, (int)cnt, true, st);
+            k_lift(c, Dn, Dp, (int)cnt, true, Lc, st);
+            ntt64(c, Dn, PW, (int)cnt, 0, Lc, false, st);
+            k_diag_tile(c, tab.d, Dn, i0, (int)cnt, kb, B, G, Lc, st);
+        }
+        HC_CHECK(hipDeviceSynchronize());
+        c.diag_tabs[key] = tab;
+    }
+    if (bytes_out) {
+        uint64_t t = 0;
+        for (auto& kv : c.diag_tabs) t += kv.second.bytes;
+        *bytes_out = t;
+    }
+    return HC_OK;
+}
+
+extern "C" void hc_diag_release(hc_context* cp) {
+    if (!cp) return;
+    (void)hipSetDevice(cp->device);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : cp->diag_tabs) (void)hipFree(kv.second.d);
+    cp->diag_tabs.clear();
 }

@@ -369,6 +369,7 @@ extern "C" void hc_context_destroy(hc_context* c) {
     for (void* p : c->owned) (void)hipFree(p);
     if (c->stage_host) (void)hipHostFree(c->stage_host);
     for (auto& kv : c->prefix_masks) (void)hipFree(kv.second);
+    for (auto& kv : c->diag_tabs) (void)hipFree(kv.second.d);
     c->ws.release();
     delete c;
 }

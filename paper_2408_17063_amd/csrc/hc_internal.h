@@ -6,6 +6,7 @@
 
 #include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/hc.h"
@@ -82,6 +83,11 @@ struct hc_context {
     // plaintext multipliers owned by the context (NTT domain, Montgomery form, [L][n])
     uint64_t* d_rowmask[2] = {nullptr, nullptr};
     std::map<uint32_t, uint64_t*> prefix_masks;  // keyed by s
+
+    // resident diagonal tables keyed by (s, B, level): [kb][s/B][B][level][n], NTT domain,
+    // Montgomery form
+    struct DiagTab { uint32_t kb = 0; uint64_t* d = nullptr; size_t bytes = 0; };
+    std::map<std::tuple<uint32_t, uint32_t, int>, DiagTab> diag_tabs;
 
     hc::Arena ws;      // per-call workspace
     // pinned host staging for per-call tables (job lists, pointer tables) and its device mirror
@@ -234,7 +240,30 @@ void k_enc_finish(const Ctx& c, uint64_t* ct, const uint64_t* e0, const uint64_t
 //   A[pp][g] (+)= sum_{beta < kb, b < B} D[beta][g][b] * R[pp][beta][b]
 // R, A given as device arrays of ciphertext pointers; D contiguous
 // [kb][G][B][L][n] (Montgomery). accumulate: add to the existing A.
-void k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* const* R, const uint64_t* D,
-                int npairs, int kb, int G, int B, bool accumulate, int Lc, hipStream_t st);
+// Giant indices per wave of the diagonal multiply-accumulate (and per chunk of the
+// resident tables' layout).
+constexpr int DIAG_GC = 8;
+// Word strides of a diagonal table (split words, see k_diag_split): D(beta, g, b) of
+// limb r at coefficient 64 tile + lane, term j = beta B + b, giant g = DIAG_GC c + i, is
+// D[r sr + tile st + c sgc + j sj + i sg + lane].
+struct DiagLayout { size_t sr, st, sgc, sj, sg; };
+// one [Lc][n] polynomial per diagonal, index (beta B + b) gc + g (gc giants per chunk)
+DiagLayout diag_layout_natural(const Ctx& c, int Lc, uint32_t gc);
+// resident tables: [Lc][n/64][ceil(dG/DIAG_GC)][Jt][DIAG_GC][64], Jt = kbt B terms
+DiagLayout diag_layout_tiled(const Ctx& c, uint32_t Jt, uint32_t dG);
+// words of a resident table of Jt terms and dG giants
+size_t diag_table_words(const Ctx& c, int Lc, uint32_t Jt, uint32_t dG);
+// natural order (beta dG + g) B + b -> tiled and split, for `count` diagonals from index i0
+void k_diag_tile(const Ctx& c, uint64_t* out, const uint64_t* in, size_t i0, int count, uint32_t kbt,
+                 uint32_t B, uint32_t dG, int Lc, hipStream_t st);
+// words v -> (v >> h) 2^32 + (v mod 2^h), h = ceil(bits of the largest of the first Lc primes / 2)
+void k_diag_split(const Ctx& c, uint64_t* d, size_t words, int Lc, hipStream_t st);
+// Rt[r][tile][pp][j][2][64] (split) from the pointer table R[pp][j] (j < J; nullptr: zeros)
+void k_diag_gather(const Ctx& c, uint64_t* Rt, const uint64_t* const* R, int npairs, int J, int Lc,
+                   hipStream_t st);
+// A[pp][g] (=|+=) sum_{j<J} D(j, g) R[pp][j], g < ga, for npairs pairs: A pointers
+// [npairs][ga], R gathered by k_diag_gather, D split and in Montgomery form.
+void k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* Rt, const uint64_t* D,
+                const DiagLayout& lay, int npairs, int J, int ga, bool accumulate, int Lc, hipStream_t st);
 
 }  // namespace hc

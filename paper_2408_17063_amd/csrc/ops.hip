@@ -6,7 +6,9 @@
 // along grid.y -- so all accesses are unit-stride across a wavefront, except
 // the automorphism gathers (a fixed permutation within a row).
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 #include "hc_internal.h"
 
@@ -619,62 +621,169 @@ hc_status upload_keccak_constants(const uint64_t rc[24], const uint32_t rho[25],
 
 // ------------------------------------------------------------------ diagonal multiply-accumulate
 
-// A[pp][g] = (A[pp][g] +) sum_{beta, b} D[beta][g][b] * R[pp][beta][b], per
-// (row, coefficient). Each thread keeps GC giant accumulators (both
-// ciphertext components) as 128-bit sums, folded through a Montgomery
-// reduction every `chunk` terms, and reads each R value once per GC giants.
-template <int GC>
-__global__ void diag_mac_kernel(uint64_t* const* __restrict__ A, const uint64_t* const* __restrict__ R,
-                                const uint64_t* __restrict__ D, const uint64_t* __restrict__ mods,
-                                const uint64_t* __restrict__ qinv, int n, int L, int kb, int G, int B,
-                                int g0, int chunk, int accumulate) {
-    int x = blockIdx.x * blockDim.x + threadIdx.x;
+// A[pp][g] = (A[pp][g] +) sum_{beta < kb, b < B} D(beta, g, b) * R[pp][beta][b], per
+// (row, coefficient): for every coefficient this is a small matrix product over
+// Z_q, (2 npairs x kb B) times (kb B x G), with D in Montgomery form.
+//
+// Arithmetic: both operands are stored split, v = v1 2^h + v0 with h = ceil(bits(q)/2),
+// as the word v1 2^32 + v0, so a product is four 32 x 32 -> 64-bit multiply-adds
+// (v_mad_u64_u32) into three 64-bit sums (low, middle, high) that cannot overflow for
+// `chunk` terms; every `chunk` terms they are recombined into one 128-bit value T below
+// q 2^64 and T mod q (= REDC(REDC(T) 2^128 mod q)) is carried on in the low sum. The
+// last fold is one REDC: with D in Montgomery form that is the plain sum of products.
+//
+// Work: one wave per (limb, 64 consecutive coefficients, ciphertext pair, GC = 8 giant
+// indices), lane = coefficient. The waves of a block are consecutive pairs with the
+// same giants: they read the same diagonal words together. Blocks are numbered so
+// that each XCD (blocks go to XCDs round robin) works through a contiguous range of
+// work items whose fastest index is the giant chunk: the blocks resident on one XCD
+// at a time share one tile of the rotated ciphertexts through that XCD's L2.
+//
+// Operands are tiled so that a block streams two contiguous regions: the rotated
+// ciphertexts Rt[r][tile][pp][j][2][64] (term j = beta B + b; written split by
+// diag_gather_kernel) and D, whose layout is given by word strides: the split word of
+// D(beta, g, b) for limb r at coefficient 64 tile + lane, g = GC c + i (giant chunk c,
+// i < GC), is D[r sr + tile st + c sgc + j sj + i sg + lane].
+struct DiagMacArgs {
+    int n, L, J, ga, npairs, wp, npg, ngc, ntiles;
+    uint32_t work, per_xcd;
+    size_t sr, st, sgc, sj, sg;
+    int chunk, h, accumulate;
+};
+
+__device__ __forceinline__ uint64_t split_word(uint64_t v, int h) {
+    return ((v >> h) << 32) | (v & ((1ull << h) - 1));
+}
+
+// Rt[r][tile][pp][j][k][64] = R[pp][j] component k at (r, 64 tile + lane), split;
+// nullptr -> 0.
+__global__ void diag_gather_kernel(uint64_t* __restrict__ Rt, const uint64_t* const* __restrict__ R, int n,
+                                   int L, int J, int npairs, int pj0, int h) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     const int r = blockIdx.y;
-    const int pp = blockIdx.z;
-    const uint64_t q = mods[r], qi = qinv[r];
+    const int pj = pj0 + (int)blockIdx.z;  // pp * J + j
+    const uint64_t* rp = R[pj];
     const size_t ln = (size_t)L * n;
-    const size_t off = (size_t)r * n + x;
-    const int gc = (G - g0) < GC ? (G - g0) : GC;
+    const size_t src = (size_t)r * n + x;
+    const uint64_t v0 = rp ? rp[src] : 0, v1 = rp ? rp[ln + src] : 0;
+    const size_t o = (((size_t)r * (n / 64) + (size_t)(x / 64)) * ((size_t)npairs * J) + pj) * 128 + (x & 63);
+    Rt[o] = split_word(v0, h);
+    Rt[o + 64] = split_word(v1, h);
+}
 
-    u128p acc0[GC], acc1[GC];
-    uint64_t sum0[GC], sum1[GC];
+// Loads run three terms ahead: the loads of term j + 2 are issued before the
+// products of term j, so every wave keeps two terms of loads in flight while it
+// computes. Loads past the last term re-read it (addresses stay in bounds; those
+// values are never used).
+template <int GC>
+__global__ __launch_bounds__(512) void diag_mac_kernel(uint64_t* const* __restrict__ A,
+                                                            const uint64_t* __restrict__ Rt,
+                                                            const uint64_t* __restrict__ D,
+                                                            const uint64_t* __restrict__ mods,
+                                                            const uint64_t* __restrict__ qinv,
+                                                            const uint64_t* __restrict__ r2, DiagMacArgs a) {
+    const uint32_t bid = blockIdx.x;
+    const uint32_t wk = (bid & 7u) * a.per_xcd + (bid >> 3);
+    if (wk >= a.work) return;
+    uint32_t t = wk;
+    const int gci = (int)(t % (uint32_t)a.ngc); t /= (uint32_t)a.ngc;
+    const int pg = (int)(t % (uint32_t)a.npg); t /= (uint32_t)a.npg;
+    const int tile = (int)(t % (uint32_t)a.ntiles);
+    const int r = (int)(t / (uint32_t)a.ntiles);
+    const int pp = pg * a.wp + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (pp >= a.npairs) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const uint64_t q = mods[r], qi = qinv[r], q2 = r2[r];
+    const int g0 = gci * GC;
+    const int gc = (a.ga - g0) < GC ? (a.ga - g0) : GC;
+    const int h = a.h;
+    const int J = a.J;
+
+    uint64_t lo[GC][2], mid[GC][2], hi[GC][2];
     #pragma unroll
-    for (int g = 0; g < GC; g++) { acc0[g] = u128p{0, 0}; acc1[g] = u128p{0, 0}; sum0[g] = 0; sum1[g] = 0; }
-    int terms = 0;
-    for (int beta = 0; beta < kb; beta++) {
-        for (int b = 0; b < B; b++) {
-            const uint64_t* rp = R[((size_t)pp * kb + beta) * B + b];
-            if (rp == nullptr) continue;
-            uint64_t r0 = rp[off], r1 = rp[ln + off];
-            const uint64_t* dp = D + (((size_t)beta * G + g0) * B + b) * ln + off;
+    for (int g = 0; g < GC; g++)
+        #pragma unroll
+        for (int k = 0; k < 2; k++) lo[g][k] = mid[g][k] = hi[g][k] = 0;
+
+    auto fold = [&](bool last) __attribute__((always_inline)) {
+        #pragma unroll
+        for (int g = 0; g < GC; g++)
             #pragma unroll
-            for (int g = 0; g < GC; g++) {
-                if (g < gc) {
-                    uint64_t d = dp[(size_t)g * B * ln];
-                    add128(acc0[g], mul128(r0, d));
-                    add128(acc1[g], mul128(r1, d));
-                }
+            for (int k = 0; k < 2; k++) {
+                u128p T{lo[g][k], 0};
+                add128(T, u128p{mid[g][k] << h, mid[g][k] >> (64 - h)});
+                add128(T, u128p{hi[g][k] << (2 * h), hi[g][k] >> (64 - 2 * h)});
+                const uint64_t v = redc(T, q, qi);
+                lo[g][k] = last ? v : mont_mul(v, q2, q, qi);
+                mid[g][k] = hi[g][k] = 0;
             }
-            if (++terms == chunk) {
-                #pragma unroll
-                for (int g = 0; g < GC; g++) {
-                    sum0[g] = add_mod(sum0[g], redc(acc0[g], q, qi), q);
-                    sum1[g] = add_mod(sum1[g], redc(acc1[g], q, qi), q);
-                    acc0[g] = u128p{0, 0};
-                    acc1[g] = u128p{0, 0};
-                }
-                terms = 0;
-            }
+    };
+
+    const uint64_t* Rb = Rt + (((size_t)r * a.ntiles + tile) * a.npairs + pp) * (size_t)J * 128 + lane;
+    const uint64_t* Db = D + (size_t)r * a.sr + (size_t)tile * a.st + (size_t)gci * a.sgc + lane;
+    size_t gofs[GC];
+    #pragma unroll
+    for (int g = 0; g < GC; g++) gofs[g] = (size_t)(g < gc ? g : gc - 1) * a.sg;
+
+    // the three slots are indexed only by compile-time constants (registers, never memory)
+    uint64_t rv[3][2], dv[3][GC];
+    auto load = [&](int j, auto slot_c) __attribute__((always_inline)) {
+        constexpr int slot = decltype(slot_c)::value;
+        const int jj = j < J ? j : J - 1;
+        const uint64_t* rp = Rb + (size_t)jj * 128;
+        rv[slot][0] = rp[0];
+        rv[slot][1] = rp[64];
+        const uint64_t* dp = Db + (size_t)jj * a.sj;
+        #pragma unroll
+        for (int g = 0; g < GC; g++) dv[slot][g] = dp[gofs[g]];
+    };
+    int terms = 0;
+    auto step = [&](auto slot_c) __attribute__((always_inline)) {
+        constexpr int slot = decltype(slot_c)::value;
+        const uint32_t r0l = (uint32_t)rv[slot][0], r0h = (uint32_t)(rv[slot][0] >> 32);
+        const uint32_t r1l = (uint32_t)rv[slot][1], r1h = (uint32_t)(rv[slot][1] >> 32);
+        #pragma unroll
+        for (int g = 0; g < GC; g++) {
+            const uint32_t dl = (uint32_t)dv[slot][g], dh = (uint32_t)(dv[slot][g] >> 32);
+            lo[g][0] += (uint64_t)r0l * dl;
+            mid[g][0] += (uint64_t)r0l * dh;
+            mid[g][0] += (uint64_t)r0h * dl;
+            hi[g][0] += (uint64_t)r0h * dh;
+            lo[g][1] += (uint64_t)r1l * dl;
+            mid[g][1] += (uint64_t)r1l * dh;
+            mid[g][1] += (uint64_t)r1h * dl;
+            hi[g][1] += (uint64_t)r1h * dh;
         }
+        if (++terms == a.chunk) {
+            fold(false);
+            terms = 0;
+        }
+    };
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, 1>;
+    using S2 = std::integral_constant<int, 2>;
+    load(0, S0{});
+    load(1, S1{});
+    for (int j = 0; j < J; j += 3) {
+        load(j + 2, S2{});
+        step(S0{});
+        if (j + 1 >= J) break;
+        load(j + 3, S0{});
+        step(S1{});
+        if (j + 2 >= J) break;
+        load(j + 4, S1{});
+        step(S2{});
     }
+    fold(true);
+    const size_t ln = (size_t)a.L * a.n;
+    const size_t off = (size_t)r * a.n + (size_t)tile * 64 + lane;
     #pragma unroll
     for (int g = 0; g < GC; g++) {
         if (g < gc) {
-            uint64_t v0 = add_mod(sum0[g], redc(acc0[g], q, qi), q);
-            uint64_t v1 = add_mod(sum1[g], redc(acc1[g], q, qi), q);
-            uint64_t* ap = A[(size_t)pp * G + g0 + g];
-            if (accumulate) {
+            uint64_t v0 = lo[g][0], v1 = lo[g][1];
+            uint64_t* ap = A[(size_t)pp * a.ga + g0 + g];
+            if (a.accumulate) {
                 v0 = add_mod(v0, ap[off], q);
                 v1 = add_mod(v1, ap[ln + off], q);
             }
@@ -684,27 +793,146 @@ __global__ void diag_mac_kernel(uint64_t* const* __restrict__ A, const uint64_t*
     }
 }
 
-void k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* const* R, const uint64_t* D,
-                int npairs, int kb, int G, int B, bool accumulate, int Lc, hipStream_t st) {
-    // terms per 128-bit accumulator before it must be folded: t q^2 < q 2^64
-    uint64_t qmax = 0;
-    for (int i = 0; i < c.L; i++) qmax = qmax > c.primes[i] ? qmax : c.primes[i];
-    uint64_t chunk = (~0ull) / qmax;
-    if (chunk > 1024) chunk = 1024;
-    if (chunk < 1) chunk = 1;
-    constexpr int GC = 4;
-    for (int g0 = 0; g0 < G; g0 += GC) {
-        const int gc = (G - g0) < GC ? (G - g0) : GC;
-        const double ln = (double)Lc * c.n;
-        // reads each R (both components) and each D once, writes each A once
-        TimeScope ts(c, HC_KT_DIAG_MAC, st,
-                     8.0 * ln * (2.0 * npairs * kb * B + (double)kb * gc * B +
-                                 (accumulate ? 4.0 : 2.0) * npairs * gc),
-                     2.0 * ln * npairs * kb * B * gc);
-        hipLaunchKernelGGL((diag_mac_kernel<GC>), ew_grid(c.n, Lc, npairs), dim3(EW_THREADS), 0, st,
-                           A, R, D, c.d_mods, c.d_qinv, c.n, Lc, kb, G, B, g0, (int)chunk,
-                           accumulate ? 1 : 0);
-    }
+// Largest number of terms the split sums of diag_mac_kernel take before a fold,
+// for residues below qmax < 2^bits split at h: the low sum starts from a residue
+// below qmax, every sum stays below 2^64, and the recombined value stays below
+// q 2^64 (qmax + terms (q-1)^2 < q 2^64 holds for terms < 2^64 / q).
+static int diag_chunk(int bits, int h, uint64_t qmax) {
+    const unsigned __int128 one = 1;
+    const unsigned __int128 top = (one << 64) - 1;
+    const unsigned __int128 m0 = (one << h) - 1, m1 = (one << (bits - h)) - 1;
+    unsigned __int128 ch = (top - qmax) / (m0 * m0);
+    if (top / (2 * m0 * m1) < ch) ch = top / (2 * m0 * m1);
+    if (top / (m1 * m1) < ch) ch = top / (m1 * m1);
+    const unsigned __int128 cq = (one << 64) / qmax - 1;
+    if (cq < ch) ch = cq;
+    if (ch > 4096) ch = 4096;
+    return (int)ch;
+}
+
+// The split position for the first Lc primes: h = ceil(bits(max q) / 2).
+static void diag_split_bits(const Ctx& c, int Lc, int* bits, int* h, uint64_t* qmax) {
+    uint64_t m = 0;
+    for (int i = 0; i < Lc; i++) m = m > c.primes[i] ? m : c.primes[i];
+    int b = 0;
+    while (b < 64 && (m >> b)) b++;
+    *bits = b;
+    *h = (b + 1) / 2;
+    *qmax = m;
+}
+
+int diag_split_h(const Ctx& c, int Lc) {
+    int bits, h;
+    uint64_t qmax;
+    diag_split_bits(c, Lc, &bits, &h, &qmax);
+    return h;
+}
+
+__global__ void diag_split_kernel(uint64_t* __restrict__ d, size_t words, int h) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < words) d[i] = split_word(d[i], h);
+}
+
+void k_diag_split(const Ctx& c, uint64_t* d, size_t words, int Lc, hipStream_t st) {
+    const size_t blocks = (words + 255) / 256;
+    hipLaunchKernelGGL(diag_split_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d, words, diag_split_h(c, Lc));
+}
+
+void k_diag_gather(const Ctx& c, uint64_t* Rt, const uint64_t* const* R, int npairs, int J, int Lc,
+                   hipStream_t st) {
+    const int total = npairs * J;
+    const int h = diag_split_h(c, Lc);
+    for (int pj0 = 0; pj0 < total; pj0 += 65535)
+        hipLaunchKernelGGL(diag_gather_kernel, ew_grid(c.n, Lc, std::min(65535, total - pj0)), dim3(EW_THREADS), 0,
+                           st, Rt, R, c.n, Lc, J, npairs, pj0, h);
+}
+
+void k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* Rt, const uint64_t* D,
+                const DiagLayout& lay, int npairs, int J, int ga, bool accumulate, int Lc, hipStream_t st) {
+    int bits, h;
+    uint64_t qmax;
+    diag_split_bits(c, Lc, &bits, &h, &qmax);
+    constexpr int GC = DIAG_GC;
+    DiagMacArgs a;
+    a.n = c.n;
+    a.L = Lc;
+    a.J = J;
+    a.ga = ga;
+    a.npairs = npairs;
+    a.wp = npairs < 8 ? npairs : 8;
+    a.npg = (npairs + a.wp - 1) / a.wp;
+    a.ngc = (ga + GC - 1) / GC;
+    a.ntiles = c.n / 64;
+    const uint64_t work = (uint64_t)Lc * a.ntiles * a.npg * a.ngc;
+    a.work = (uint32_t)work;
+    a.per_xcd = (uint32_t)((work + 7) / 8);
+    a.sr = lay.sr;
+    a.st = lay.st;
+    a.sgc = lay.sgc;
+    a.sj = lay.sj;
+    a.sg = lay.sg;
+    a.h = h;
+    a.chunk = diag_chunk(bits, h, qmax);
+    a.accumulate = accumulate ? 1 : 0;
+    const double ln = (double)Lc * c.n;
+    // reads each R (both components) and each D once, writes each A once
+    TimeScope ts(c, HC_KT_DIAG_MAC, st,
+                 8.0 * ln * (2.0 * npairs * J + (double)J * ga + (accumulate ? 4.0 : 2.0) * npairs * ga),
+                 2.0 * ln * npairs * J * ga);
+    hipLaunchKernelGGL((diag_mac_kernel<GC>), dim3(a.per_xcd * 8), dim3(64 * a.wp), 0, st, A, Rt, D, c.d_mods,
+                       c.d_qinv, c.d_r2, a);
+}
+
+// Natural layout (one [Lc][n] polynomial per diagonal, index (beta dG + g) B + b) ->
+// the tiled, split layout of resident tables, [Lc][n/64][ceil(dG/GC)][kbt B][GC][64]
+// (term j = beta B + b, giant g = GC c + i): the words one block (a 64-coefficient
+// tile and one chunk of GC giants) multiplies by form one contiguous run. `count`
+// diagonals starting at index i0.
+__global__ void diag_tile_kernel(uint64_t* __restrict__ out, const uint64_t* __restrict__ in, size_t i0,
+                                 int n, int L, uint32_t kbt, uint32_t B, uint32_t dG, int h) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int r = blockIdx.y;
+    const size_t i = i0 + blockIdx.z;
+    const uint32_t b = (uint32_t)(i % B);
+    const uint32_t g = (uint32_t)((i / B) % dG);
+    const uint32_t beta = (uint32_t)(i / ((size_t)B * dG));
+    const size_t Jt = (size_t)kbt * B, nch = (dG + DIAG_GC - 1) / DIAG_GC;
+    const size_t per_chunk = Jt * DIAG_GC * 64;
+    const size_t o = (((size_t)r * (n / 64) + (size_t)(x / 64)) * nch + g / DIAG_GC) * per_chunk +
+                     (((size_t)beta * B + b) * DIAG_GC + g % DIAG_GC) * 64 + (x & 63);
+    out[o] = split_word(in[((size_t)blockIdx.z * L + r) * n + x], h);
+}
+
+void k_diag_tile(const Ctx& c, uint64_t* out, const uint64_t* in, size_t i0, int count, uint32_t kbt,
+                 uint32_t B, uint32_t dG, int Lc, hipStream_t st) {
+    hipLaunchKernelGGL(diag_tile_kernel, ew_grid(c.n, Lc, count), dim3(EW_THREADS), 0, st, out, in, i0, c.n,
+                       Lc, kbt, B, dG, diag_split_h(c, Lc));
+}
+
+size_t diag_table_words(const Ctx& c, int Lc, uint32_t Jt, uint32_t dG) {
+    return (size_t)Lc * c.n * Jt * ((dG + DIAG_GC - 1) / DIAG_GC) * DIAG_GC;
+}
+
+DiagLayout diag_layout_natural(const Ctx& c, int Lc, uint32_t gc) {
+    const size_t ln = (size_t)Lc * c.n;
+    DiagLayout l;
+    l.sr = c.n;
+    l.st = 64;
+    l.sg = ln;
+    l.sgc = DIAG_GC * ln;
+    l.sj = (size_t)gc * ln;
+    return l;
+}
+
+DiagLayout diag_layout_tiled(const Ctx& c, uint32_t Jt, uint32_t dG) {
+    DiagLayout l;
+    l.sg = 64;
+    l.sj = (size_t)DIAG_GC * 64;
+    l.sgc = (size_t)Jt * DIAG_GC * 64;
+    l.st = ((dG + DIAG_GC - 1) / DIAG_GC) * l.sgc;
+    l.sr = (size_t)(c.n / 64) * l.st;
+    return l;
 }
 
 

@@ -46,7 +46,8 @@ class CompressInfo(ctypes.Structure):
     _fields_ = [("s", ctypes.c_uint32), ("groups", ctypes.c_uint32), ("streams", ctypes.c_uint32),
                 ("bands", ctypes.c_uint32), ("n_ct", ctypes.c_uint32),
                 ("n_keyswitch", ctypes.c_uint32), ("n_ptct", ctypes.c_uint64),
-                ("n_diag", ctypes.c_uint64), ("level", ctypes.c_uint32)]
+                ("n_diag", ctypes.c_uint64), ("level", ctypes.c_uint32),
+                ("n_diag_resident", ctypes.c_uint64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -104,6 +105,9 @@ _sig("hc_timing_read", _st, c_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
      ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
 _sig("hc_probe_mul32_rate", _st, c_vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double))
 _sig("hc_probe_copy", _st, c_vp, ctypes.c_uint64)
+_sig("hc_diag_prepare", _st, c_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+     ctypes.POINTER(ctypes.c_uint64))
+_sig("hc_diag_release", None, c_vp)
 
 KT_NTT_FWD, KT_NTT_INV, KT_KS_INNER, KT_DIAG_MAC, KT_MODUP = 0, 1, 2, 3, 4
 KT_NAMES = {KT_NTT_FWD: "ntt_forward", KT_NTT_INV: "ntt_inverse", KT_KS_INNER: "keyswitch_inner",
@@ -116,6 +120,7 @@ EXPORTED = [
     "hc_decrypt", "hc_decompress", "hc_ntt", "hc_rotate", "hc_rotate_hoisted", "hc_mul_plain",
     "hc_modup", "hc_moddown", "hc_sample", "hc_encode_diagonal", "hc_export_sk", "hc_export_pk",
     "hc_export_gk", "hc_timing_enable", "hc_timing_read", "hc_probe_mul32_rate", "hc_probe_copy",
+    "hc_diag_prepare", "hc_diag_release",
 ]
 
 
@@ -208,6 +213,16 @@ class Context:
         _check(_lib.hc_plan(self.h, N, ncol, t_bound, comp_level, _np_ptr(arr, ctypes.c_uint32),
                             ctypes.byref(cap), ctypes.byref(info)), "hc_plan")
         return [int(x) for x in arr[:cap.value]], info.as_dict()
+
+    def diag_prepare(self, N, ncol, t_bound, comp_level=0):
+        """Encode and keep resident the diagonals these compressions use; returns the
+        device bytes held by all resident tables."""
+        b = ctypes.c_uint64(0)
+        _check(_lib.hc_diag_prepare(self.h, N, ncol, t_bound, comp_level, ctypes.byref(b)), "hc_diag_prepare")
+        return int(b.value)
+
+    def diag_release(self):
+        _lib.hc_diag_release(self.h)
 
     def db_upload(self, cols):
         cols = np.ascontiguousarray(cols, dtype=np.uint32)

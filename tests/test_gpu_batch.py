@@ -81,3 +81,28 @@ def test_batch_uneven_queries_ring_32768():
         exp = C.expected_bands(sched, q["v"], db)
         for b in range(sched.bands):
             assert C.band_slots(sched, dec, b) == exp[b]
+
+
+def test_batch_with_resident_diagonals():
+    """A batch whose classes are read from resident tables equals each query's
+    compression alone with diagonals encoded on the fly."""
+    from paper_2408_17063_amd import hc
+    say("batch resident")
+    specs = [(3 * 2048, 5), (7 * 2048, 13), (1000, 1), (7 * 2048 - 100, 30), (2048, 2)]
+    ctx = context("ring-2048-p12289")
+    sk, pk, gk, dbh, db, qs = make_queries(ctx, "ring-2048-p12289", specs, 4, 23)
+    alone = []
+    for q in qs:
+        o, info = ctx.compress(gk, dbh, q["cts"], q["N"], q["t"])
+        alone.append((to_host(ctx.output(o, info)), info))
+    try:
+        for N, t in specs:
+            ctx.diag_prepare(N, 4, t)
+        outs = [ctx.ct_tensor(1)[0] for _ in qs]
+        st, statuses, infos = ctx.compress_batch(gk, dbh, [(q["cts"], q["N"], q["t"], o) for q, o in zip(qs, outs)])
+        assert st == hc.HC_OK and all(x == hc.HC_OK for x in statuses)
+        for o, info, (want, ainfo) in zip(outs, infos, alone):
+            assert info["n_diag"] == 0 and info["n_diag_resident"] == ainfo["n_diag"]
+            assert np.array_equal(to_host(ctx.output(o, info)), want)
+    finally:
+        ctx.diag_release()

@@ -65,7 +65,7 @@ def check_decrypts(run):
 
 
 @pytest.mark.parametrize("wl_name,comp_level", [("tiny-1024", 0), ("plain-4096", 0), ("multi-2048", 0),
-                                                ("multi-2048", 4)])
+                                                ("multi-2048", 4), ("fold-1024-q60", 0)])
 def test_compress_bit_identical_to_oracle(wl_name, comp_level):
     from oracle import bfv, compress as C, slots
     say("compress parity", wl_name, comp_level)
@@ -136,3 +136,76 @@ def test_mod_switch_and_full_level_agree_on_values():
     s = lo["info"]["s"]
     for band in range(lo["info"]["bands"]):
         assert np.array_equal(a[:, band * s:(band + 1) * s], b[:, band * s:(band + 1) * s])
+
+
+@pytest.mark.parametrize("wl_name,comp_level", [("multi-2048", 0), ("multi-2048", 4), ("plain-4096", 0),
+                                                ("fold-1024-q60", 0)])
+def test_resident_diagonals_bit_identical(wl_name, comp_level):
+    """Compressions that read the diagonals from resident tables (hc_diag_prepare)
+    produce the same bits as with diagonals encoded on the fly."""
+    say("resident diagonals", wl_name, comp_level)
+    run = lib_run(wl_name, comp_level=comp_level)
+    ctx, wl = run["ctx"], run["wl"]
+    assert run["info"]["n_diag"] > 0 and run["info"]["n_diag_resident"] == 0
+    try:
+        held = ctx.diag_prepare(run["N"], wl.ncol, run["t"], comp_level)
+        # one table per class, giants padded to whole chunks of 8
+        assert held >= run["info"]["n_diag"] * run["info"]["level"] * ctx.n * 8
+        _, pinfo = ctx.plan(run["N"], wl.ncol, run["t"], comp_level)
+        assert pinfo["n_diag"] == 0 and pinfo["n_diag_resident"] == run["info"]["n_diag"]
+        out, info = ctx.compress(run["gk"], run["db"], run["cts"], run["N"], run["t"], comp_level=comp_level)
+        assert info["n_diag"] == 0 and info["n_diag_resident"] == run["info"]["n_diag"]
+        assert np.array_equal(to_host(ctx.output(out, info)), to_host(run["out"]))
+        # preparing again keeps the table
+        assert ctx.diag_prepare(run["N"], wl.ncol, run["t"], comp_level) == held
+    finally:
+        ctx.diag_release()
+    out, info = ctx.compress(run["gk"], run["db"], run["cts"], run["N"], run["t"], comp_level=comp_level)
+    assert info["n_diag_resident"] == 0
+    assert np.array_equal(to_host(ctx.output(out, info)), to_host(run["out"]))
+
+
+def test_resident_table_grows_and_serves_smaller_groups():
+    """A table prepared for fewer u-blocks does not serve a query that needs more
+    (encoded on the fly instead); preparing for more rebuilds it, and the larger
+    table then serves every query of its class. Outputs never change."""
+    say("resident table growth")
+    wl = W.WORKLOADS["multi-2048"]
+    ctx = context(wl.ring)
+    small = lib_run("multi-2048", N=2 * 2048, t=7, t_bound=16)
+    big = lib_run("multi-2048", N=4 * 2048, t=7, t_bound=16)
+    _, ps = ctx.plan(small["N"], wl.ncol, 16)
+    _, pb = ctx.plan(big["N"], wl.ncol, 16)
+    try:
+        ctx.diag_prepare(small["N"], wl.ncol, 16)
+        _, p2 = ctx.plan(big["N"], wl.ncol, 16)
+        out, info = ctx.compress(big["gk"], big["db"], big["cts"], big["N"], 16)
+        assert np.array_equal(to_host(ctx.output(out, info)), to_host(big["out"]))
+        assert info["n_diag"] + info["n_diag_resident"] == pb["n_diag"]
+        assert (info["n_diag"], info["n_diag_resident"]) == (p2["n_diag"], p2["n_diag_resident"])
+        ctx.diag_prepare(big["N"], wl.ncol, 16)
+        for r, p in ((big, pb), (small, ps)):
+            out, info = ctx.compress(r["gk"], r["db"], r["cts"], r["N"], 16)
+            assert np.array_equal(to_host(ctx.output(out, info)), to_host(r["out"]))
+            assert info["n_diag_resident"] + info["n_diag"] == p["n_diag"]
+        _, pb2 = ctx.plan(big["N"], wl.ncol, 16)
+        assert pb2["n_diag"] == 0
+    finally:
+        ctx.diag_release()
+
+
+def test_resident_diagonals_full_size_ring_32768():
+    """Full-size single-ciphertext workload at ring 2^15 with resident diagonals:
+    decrypts to the Vandermonde products and decompresses exactly."""
+    say("resident full size")
+    run = lib_run("single-32768")
+    ctx, wl = run["ctx"], run["wl"]
+    try:
+        ctx.diag_prepare(run["N"], wl.ncol, run["t"])
+        out, info = ctx.compress(run["gk"], run["db"], run["cts"], run["N"], run["t"])
+        assert info["n_diag"] == 0 and info["n_diag_resident"] > 0
+        got = to_host(ctx.output(out, info))
+        assert np.array_equal(got, to_host(run["out"]))
+        check_decrypts(dict(run, out=ctx.output(out, info)))
+    finally:
+        ctx.diag_release()

@@ -42,6 +42,8 @@ RINGS = {
     # small rings for parity tests that exercise groups, streams and bands
     "ring-2048-p12289": Ring(2048, 12289, 4, 54, 2, 60),
     "ring-1024-p12289": Ring(1024, 12289, 2, 54, 1, 60),
+    # 60-bit ciphertext primes: the diagonal sums fold every 8 terms
+    "ring-1024-q60": Ring(1024, 12289, 2, 60, 1, 61),
 }
 
 
@@ -61,6 +63,8 @@ WORKLOADS = {
     "large-65536": Workload("large-65536", "ring-65536", 1 << 20, 1024, 4, "u16"),
     "multi-2048": Workload("multi-2048", "ring-2048-p12289", 7 * 2048, 13, 4, "zp"),
     "tiny-1024": Workload("tiny-1024", "ring-1024-p12289", 1024, 5, 1, "zp"),
+    # s = 64, B = 8, 2 u-blocks: 16 diagonal terms per sum, more than one fold at 60 bits
+    "fold-1024-q60": Workload("fold-1024-q60", "ring-1024-q60", 1024, 40, 1, "zp"),
 }
 
 
