@@ -328,6 +328,107 @@ def mixed_batch(count=64):
     return res
 
 
+def serving(st, rates, requests, lane_gb=40, lanes=2, max_batch=16):
+    """The serving configuration: a seeded Poisson stream of PDQ requests at the
+    headline parameters (ring 2^16, 24 + 3 primes). Each request draws its record
+    count from {2^15, 2^17, 2^20} (a prefix of the resident 2^20 x 4 database) and t
+    log-uniform in [16, 1024]. Galois keys for the whole mix, the database and the
+    diagonal tables of every class stay resident; the server admits requests by
+    workspace footprint and batches them continuously on two streams. Latency is
+    scheduled arrival -> result final on the device, as seen by the host. Each rate
+    is a fraction of the plain (one query at a time) capacity measured on the same
+    mix."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2408_17063_amd import hc
+    ctx, wl = st["ctx"], st["wl"]
+    sizes = [1 << 15, 1 << 17, 1 << 20]
+    st["gk"].close()
+    ctx.trim()
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    keys = set()
+    for N in sizes:
+        for sv in (16, 32, 64, 128, 256, 512, 1024):
+            keys.update(ctx.plan(N, wl.ncol, sv)[0])
+    gk = ctx.galois_keygen(st["sk"], sorted(keys), W.seed32("gk-serve", 0))
+    held = 0
+    for N in sizes:
+        for sv in (16, 32, 64, 128, 256, 512, 1024):
+            held = ctx.diag_prepare(N, wl.ncol, sv)
+    setup_s = time.perf_counter() - t0
+    log("serving setup %.1fs: %d Galois keys, %.1f GB resident diagonals" % (setup_s, len(keys), held / 1e9))
+    # a pool of encrypted index vectors per record count (16 matches: valid for every t >= 16)
+    pool = {}
+    for N in sizes:
+        pool[N] = []
+        for j in range(3):
+            v = W.index_vector(W.rng_for(0x5E7E, N, j), N, 16)
+            pool[N].append(encrypt_query(ctx, st["pk"], v, -(-N // ctx.n), (0x5E7E, N, j)))
+    rng = W.rng_for(0x5E7E, 1)
+
+    def draw(count):
+        Ns = rng.choice(sizes, size=count)
+        ts = np.rint(np.exp(rng.uniform(np.log(16), np.log(1024), size=count))).astype(int)
+        return [(int(N), int(t), pool[int(N)][i % 3]) for i, (N, t) in enumerate(zip(Ns, ts))]
+
+    # plain capacity on the same mix: one query at a time, back to back
+    mix = draw(30)
+    out = ctx.ct_tensor(1)[0]
+    for N, t, cts in mix[:3]:
+        ctx.compress(gk, st["db"], cts, N, t, out=out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for N, t, cts in mix:
+        ctx.compress(gk, st["db"], cts, N, t, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1) / len(mix)
+    capacity = 1e3 / plain_ms
+    log("plain capacity on the serving mix: %.2f ms per query, %.2f queries/s" % (plain_ms, capacity))
+    ctx.trim()
+    torch.cuda.empty_cache()
+    srv = hc.Server(ctx, gk, st["db"], lane_bytes=int(lane_gb) << 30, lanes=lanes, max_batch=max_batch)
+    res = {"plain_ms_per_query": round(plain_ms, 3), "plain_capacity": round(capacity, 3), "requests_per_rate": requests,
+           "lanes": lanes, "lane_gb": lane_gb, "max_batch": max_batch, "galois_keys": len(keys),
+           "resident_diagonal_gb": round(held / 1e9, 2), "setup_s": round(setup_s, 1), "rates": []}
+    try:
+        for frac in rates:
+            lam = frac * capacity
+            reqs = draw(requests)
+            gaps = rng.exponential(1.0 / lam, size=requests)
+            start = time.monotonic_ns() + 20_000_000
+            arrive = start + np.cumsum(gaps * 1e9).astype(np.int64)
+            arrival_of, lat, done_last, batch_sizes = {}, [], 0, []
+            i = 0
+            while len(lat) < requests:
+                now = time.monotonic_ns()
+                while i < requests and arrive[i] <= now:
+                    N, t, cts = reqs[i]
+                    rid = srv.submit(cts, N, t, ctx.ct_tensor(1)[0])
+                    arrival_of[rid] = int(arrive[i])
+                    i += 1
+                wait_ms = 5.0 if i >= requests else max(0.0, min(5.0, (arrive[i] - time.monotonic_ns()) / 1e6))
+                for r in srv.poll(cap=64, timeout_ms=wait_ms):
+                    assert r["status"] == hc.HC_OK
+                    lat.append((r["done_ns"] - arrival_of[r["id"]]) / 1e6)
+                    done_last = max(done_last, r["done_ns"])
+                    batch_sizes.append(r["batch_size"])
+            span = (done_last - int(arrive[0])) / 1e9
+            row = {"fraction_of_plain_capacity": frac, "offered_per_s": round(lam, 3),
+                   "throughput_per_s": round(requests / span, 3), "p50_ms": round(percentile(lat, 50), 2),
+                   "p99_ms": round(percentile(lat, 99), 2), "mean_batch": round(float(np.mean(batch_sizes)), 2)}
+            log("serving at %.2f x plain capacity: %s" % (frac, row))
+            res["rates"].append(row)
+        res["server_stats"] = srv.stats()
+    finally:
+        srv.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -346,6 +447,9 @@ def main():
     ap.add_argument("--diagonals", choices=["resident", "on-the-fly"], default="resident",
                     help="resident: precompute the query-independent diagonals once (hc_diag_prepare) "
                          "before timing; on-the-fly: encode them inside every compression")
+    ap.add_argument("--serve-rates", default="0.25,0.5,0.75,0.9,1.0,1.25",
+                    help="serving arrival rates as fractions of the plain capacity ('' to skip)")
+    ap.add_argument("--serve-requests", type=int, default=200, help="requests per serving rate")
     ap.add_argument("--on-the-fly-steps", type=int, default=2,
                     help="with resident diagonals, also time this many steps encoding them on the fly")
     args = ap.parse_args()
@@ -440,6 +544,8 @@ def main():
     if args.mixed_batch:
         rec["mixed_batch"] = mixed_batch(args.mixed_batch)
         log("mixed batch:", rec["mixed_batch"])
+    if args.serve_rates:
+        rec["serving"] = serving(st, [float(x) for x in args.serve_rates.split(",")], args.serve_requests)
     rec["roofline"] = dict(rl[dominant], kernel=dominant)
     rec["rooflines"] = rl
     rec["mul32_probe_T"] = round(probe, 3)

@@ -94,6 +94,10 @@ typedef struct {
 hc_status hc_context_create(const hc_params* params, int device, hc_context** out);
 void hc_context_destroy(hc_context* ctx);
 
+/* Free the context's per-call device workspace (it grows again on the next
+ * call that needs it). Synchronises the device. */
+void hc_context_trim(hc_context* ctx);
+
 /* Copy the derived primes: q_1..q_L then p_1..p_K (host array of L + K). */
 hc_status hc_context_primes(const hc_context* ctx, uint64_t* primes_out);
 
@@ -210,6 +214,62 @@ hc_status hc_diag_prepare(hc_context* ctx, uint64_t N, uint32_t ncol, uint32_t t
 /* Free every resident diagonal table of ctx; later compressions encode their
  * diagonals on the fly. Synchronises the device. */
 void hc_diag_release(hc_context* ctx);
+
+/* ------------------------------------------------------------------ serving loop (Sec. 3, Answer) */
+
+typedef struct hc_server hc_server;
+
+/* A request loop over one context, key set and database, all resident on the
+ * device: PDQ queries are submitted as they arrive and answered by continuous
+ * batching. A host thread admits waiting requests, oldest first, into a batch
+ * while the batch's device workspace fits one lane and the batch holds at most
+ * max_batch queries, and runs it (the batched phases of hc_compress_batch) on
+ * that lane's own stream. With lanes > 1 a new batch starts while earlier ones
+ * are still running, so requests arriving meanwhile share the device with them
+ * rather than waiting for them to finish. Every result is bit-identical to
+ * hc_compress of the same query.
+ *   comp_level: as in hc_compress, for every request.
+ *   lane_bytes: device workspace per lane, allocated at creation.
+ *   lanes: 1..4 concurrent batches; max_batch >= 1.
+ * ctx, gk and db must outlive the server. Resident diagonal tables
+ * (hc_diag_prepare) must not be prepared or released while it runs.
+ * Errors: HC_EINVAL, HC_ENOMEM (lanes do not fit), HC_EDEVICE. */
+hc_status hc_server_create(hc_context* ctx, const hc_gk* gk, const hc_db* db, uint32_t comp_level,
+                           uint64_t lane_bytes, uint32_t lanes, uint32_t max_batch, hc_server** out);
+
+/* Queue one query; returns at once. ct_v and ct_out are device buffers as for
+ * hc_compress and must stay valid and unchanged until the request completes.
+ * id_out (optional): the request id, increasing from 1. Errors: as hc_plan,
+ * HC_ENOKEY, and HC_ENOMEM when the query alone does not fit one lane. */
+hc_status hc_server_submit(hc_server* srv, const uint64_t* ct_v, uint64_t N, uint32_t t_bound,
+                           uint64_t* ct_out, uint64_t* id_out);
+
+/* One completed request. Times are CLOCK_MONOTONIC nanoseconds. */
+typedef struct {
+    uint64_t id;
+    hc_status status;
+    int64_t submit_ns;        /* hc_server_submit accepted it */
+    int64_t start_ns;         /* its batch was enqueued on the device */
+    int64_t done_ns;          /* the host saw its batch finish; ct_out is then final */
+    uint32_t batch_size;      /* queries in its batch */
+    hc_compress_info info;
+} hc_server_result;
+
+/* Move up to cap completed requests (in completion order) to out, waiting up to
+ * timeout_ms for the first if none is ready; *count may then be 0. */
+hc_status hc_server_poll(hc_server* srv, hc_server_result* out, uint32_t cap, uint32_t* count,
+                         double timeout_ms);
+
+typedef struct {
+    uint64_t submitted, completed, batches;
+    uint32_t max_batch_seen;  /* most queries in one batch */
+    uint32_t max_lanes_busy;  /* most batches on the device at once */
+} hc_server_stats;
+hc_status hc_server_stats_get(hc_server* srv, hc_server_stats* out);
+
+/* Finish every queued and running request, stop the loop and free the lanes.
+ * Results not yet polled are dropped. */
+void hc_server_destroy(hc_server* srv);
 
 /* ------------------------------------------------------------------ client side (host CPU) */
 

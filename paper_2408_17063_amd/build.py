@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhc.so")
 
-SOURCES = ["ntt.hip", "ops.hip", "context.cpp", "he.cpp", "compress.cpp", "decode.cpp"]
+SOURCES = ["ntt.hip", "ops.hip", "context.cpp", "he.cpp", "compress.cpp", "server.cpp", "decode.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("HC_OFFLOAD_ARCH", "gfx950")
@@ -58,7 +58,7 @@ def build(verbose=False):
     # for device memory and streams holds a single HIP/HSA runtime.
     hip_dir = hip_runtime_dir()
     cmd = ["g++", "-shared", "-fPIC", "-o", tmp] + objs + [
-        "-L" + hip_dir, "-l:libamdhip64.so", "-Wl,-rpath," + hip_dir, "-Wl,--no-undefined"]
+        "-L" + hip_dir, "-l:libamdhip64.so", "-pthread", "-Wl,-rpath," + hip_dir, "-Wl,--no-undefined"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

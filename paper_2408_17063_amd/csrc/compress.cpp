@@ -27,27 +27,10 @@
 #include <algorithm>
 #include <set>
 
-#include "he.h"
+#include "compress.h"
 
 namespace hc {
 
-struct PlanGroup {
-    uint32_t ct_start, ct_count;
-    uint64_t rec_start, n_rec;
-    uint32_t k, B;
-};
-
-struct Plan {
-    uint32_t s = 0, n_ct = 0, ncol = 0;
-    int level = 0;  // ciphertext primes kept for Comp (modulus switched after Mask)
-    uint64_t N = 0;
-    std::vector<PlanGroup> groups;
-    std::vector<std::pair<int, int>> streams;  // vector ids (0 = v, c = d_c), -1 = none
-    std::vector<uint32_t> keys;
-    uint32_t bands = 0;
-    uint32_t n_ks = 0;
-    uint64_t n_ptct = 0, n_diag = 0;
-};
 
 static uint32_t rot_elt(const Ctx& c, int64_t r) {
     int64_t nh = c.nh;
@@ -136,7 +119,7 @@ hc_status make_plan(const Ctx& c, uint64_t N, uint32_t ncol, uint32_t t_bound, u
     return HC_OK;
 }
 
-static void fill_info(const Plan& pl, hc_compress_info* info) {
+void fill_info(const Plan& pl, hc_compress_info* info) {
     if (!info) return;
     info->s = pl.s;
     info->groups = (uint32_t)pl.groups.size();
@@ -157,7 +140,6 @@ static std::map<uint32_t, uint32_t> plan_classes(const Plan& pl) {
     return kmax;
 }
 
-static size_t rup(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Device-memory budget for the diagonal chunk buffer (plaintexts [Lc][n] u64).
 static const size_t kDiagBudgetBytes = (size_t)16 << 30;
@@ -168,73 +150,8 @@ static const Ctx::DiagTab* resident_table(const Ctx& c, uint32_t s, uint32_t B, 
     return (it != c.diag_tabs.end() && it->second.kb >= kb) ? &it->second : nullptr;
 }
 
-// One query of a batch and its device regions.
-struct QueryRun {
-    const uint64_t* ct_v = nullptr;
-    uint64_t* ct_out = nullptr;
-    Plan pl;
-    size_t CW = 0, PW = 0, CWF = 0, ntot = 0, ub = 0, baby = 0, gi = 0;
-    int npairs = 0;
-    uint64_t *ctf = nullptr, *cts = nullptr, *ubuf = nullptr, *tbuf = nullptr, *rbuf = nullptr,
-             *wbuf = nullptr, *bbuf = nullptr, *gbuf = nullptr, *gout = nullptr, *ybuf = nullptr,
-             *ytmp = nullptr, *mbuf = nullptr, *mrot = nullptr, *outN = nullptr;
-    std::vector<std::vector<uint64_t*>> U, A;
-    std::vector<std::vector<std::vector<uint64_t*>>> R;
 
-    void sizes(const Ctx& c) {
-        const size_t n = c.n;
-        CW = 2 * (size_t)pl.level * n;
-        PW = (size_t)pl.level * n;
-        CWF = 2 * (size_t)c.L * n;
-        ntot = (size_t)pl.n_ct * (1 + pl.ncol);
-        npairs = (int)(pl.groups.size() * pl.streams.size());
-        ub = baby = gi = 0;
-        for (auto& g : pl.groups) {
-            ub += (size_t)g.k * pl.streams.size();
-            baby += (size_t)g.k * (g.B - 1) * pl.streams.size();
-            gi += (size_t)(pl.s / g.B) * pl.streams.size();
-        }
-    }
-    size_t bytes(const Ctx& c) const {
-        size_t t = rup(CWF * 8 * ntot);
-        if (pl.level < c.L) t += 2 * rup(CW * 8 * ntot);
-        t += 4 * rup(CW * 8 * std::max<size_t>(ub, 1)) + rup(CW * 8 * std::max<size_t>(baby, 1));
-        t += 2 * rup(CW * 8 * gi) + 2 * rup(CW * 8 * npairs) + 2 * rup(CW * 8 * pl.bands) + rup(CW * 8);
-        return t;
-    }
-    hc_status take(Arena& a) {
-        ctf = a.take<uint64_t>(CWF * ntot);
-        cts = ctf;
-        uint64_t* conv = nullptr;
-        if ((int)CW != (int)CWF) {
-            cts = a.take<uint64_t>(CW * ntot);
-            conv = a.take<uint64_t>(CW * ntot);
-            if (!conv) return HC_ENOMEM;
-        }
-        msconv = conv;
-        ubuf = a.take<uint64_t>(CW * std::max<size_t>(ub, 1));
-        tbuf = a.take<uint64_t>(CW * std::max<size_t>(ub, 1));
-        rbuf = a.take<uint64_t>(CW * std::max<size_t>(ub, 1));
-        wbuf = a.take<uint64_t>(CW * std::max<size_t>(ub, 1));
-        bbuf = a.take<uint64_t>(CW * std::max<size_t>(baby, 1));
-        gbuf = a.take<uint64_t>(CW * gi);
-        gout = a.take<uint64_t>(CW * gi);
-        ybuf = a.take<uint64_t>(CW * npairs);
-        ytmp = a.take<uint64_t>(CW * npairs);
-        mbuf = a.take<uint64_t>(CW * pl.bands);
-        mrot = a.take<uint64_t>(CW * pl.bands);
-        outN = a.take<uint64_t>(CW);
-        if (!ctf || !cts || !ubuf || !tbuf || !rbuf || !wbuf || !bbuf || !gbuf || !gout || !ybuf || !ytmp ||
-            !mbuf || !mrot || !outN)
-            return HC_ENOMEM;
-        return HC_OK;
-    }
-    uint64_t* msconv = nullptr;
-    uint64_t n_diag = 0, n_diag_res = 0;  // diagonals encoded / read from resident tables
-    const uint64_t* vec_ct(int vid, uint32_t i) const { return cts + ((size_t)vid * pl.n_ct + i) * CW; }
-};
-
-static void fill_info(const QueryRun& q, hc_compress_info* info) {
+void fill_info(const QueryRun& q, hc_compress_info* info) {
     if (!info) return;
     fill_info(q.pl, info);
     info->n_diag = q.n_diag;
@@ -247,14 +164,18 @@ static void fill_info(const QueryRun& q, hc_compress_info* info) {
 // same Galois element across queries go through the same key-switching pass and
 // pairs with the same (s, B) share each diagonal chunk. All queries must have
 // the same Comp level. Each query's result equals its single-query compression.
-hc_status compress_many(Ctx& c, const hc_gk* gk, const hc_db* db, std::vector<QueryRun>& qs, hipStream_t st) {
-    if (qs.empty()) return HC_OK;
+
+hc_status batch_shape(const Ctx& c, const hc_gk* gk, const hc_db* db, std::vector<QueryRun>& qs, BatchShape& b) {
+    if (qs.empty()) return HC_EINVAL;
     const size_t n = c.n;
     const int Lc = qs[0].pl.level;
-    size_t total = 64 * 256, max_jobs = 1;
-    size_t diag_max = 1;
-    std::map<std::pair<uint32_t, uint32_t>, uint32_t> cls_k;   // (s, B) -> max k
-    std::map<std::pair<uint32_t, uint32_t>, uint32_t> cls_np;  // (s, B) -> pairs
+    b = BatchShape();
+    b.Lc = Lc;
+    size_t total = 64 * 256, max_jobs = 1, diag_max = 1;
+    auto& cls_k = b.cls_k;
+    auto& cls_np = b.cls_np;
+    auto& cls_gc = b.cls_gc;
+    auto& cls_res = b.cls_res;
     for (auto& q : qs) {
         if (q.pl.level != Lc) return HC_EINVAL;
         for (uint32_t k : q.pl.keys)
@@ -273,8 +194,6 @@ hc_status compress_many(Ctx& c, const hc_gk* gk, const hc_db* db, std::vector<Qu
     for (auto& q : qs) jobs_all = std::max(jobs_all, q.ub + q.baby + q.gi);
     max_jobs = std::max(max_jobs, jobs_all * qs.size());
     const size_t PW = (size_t)Lc * n;
-    std::map<std::pair<uint32_t, uint32_t>, uint32_t> cls_gc;
-    std::map<std::pair<uint32_t, uint32_t>, const Ctx::DiagTab*> cls_res;
     for (auto& kv : cls_k) {
         const uint32_t s = kv.first.first, B = kv.first.second, kb = kv.second;
         const Ctx::DiagTab* tab = resident_table(c, s, B, Lc, kb);
@@ -290,9 +209,29 @@ hc_status compress_many(Ctx& c, const hc_gk* gk, const hc_db* db, std::vector<Qu
     total += rup(PW * 8 * diag_max) + rup(n * 4 * diag_max) + rup(rt_max * 8) +
              ks_scratch_bytes(c, Lc, (int)max_jobs);
 
-    stage_reset(c, st);  // the workspace and staging area are reused call to call
-    if (c.ws.reserve(total) != HC_OK) return HC_ENOMEM;
-    Arena& a = c.ws;
+    b.total = total;
+    b.max_jobs = max_jobs;
+    b.diag_max = diag_max;
+    b.rt_max = rt_max;
+    return HC_OK;
+}
+
+hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::vector<QueryRun>& qs,
+                        hipStream_t st) {
+    if (qs.empty()) return HC_OK;
+    BatchShape shape;
+    hc_status bs = batch_shape(c, gk, db, qs, shape);
+    if (bs != HC_OK) return bs;
+    const size_t n = c.n;
+    const int Lc = shape.Lc;
+    const size_t PW = (size_t)Lc * n;
+    const size_t total = shape.total, max_jobs = shape.max_jobs, diag_max = shape.diag_max, rt_max = shape.rt_max;
+    auto& cls_k = shape.cls_k;
+    auto& cls_gc = shape.cls_gc;
+    auto& cls_res = shape.cls_res;
+    stage_reset(l, st);  // the workspace and staging area are reused call to call
+    if (l.ws.reserve(total) != HC_OK) return HC_ENOMEM;
+    Arena& a = l.ws;
     KsScratch ks = ks_scratch(c, a, Lc, (int)max_jobs);
     for (auto& q : qs)
         if (q.take(a) != HC_OK) return HC_ENOMEM;
@@ -321,7 +260,7 @@ hc_status compress_many(Ctx& c, const hc_gk* gk, const hc_db* db, std::vector<Qu
                     mj.push_back(EwJob{q.ctf + ((size_t)(1 + col) * q.pl.n_ct + i) * q.CWF, q.ctf + i * q.CWF,
                                        db->d_pt + ((size_t)col * db->n_ct + i) * c.L * n});
         }
-        RUN(ew_run(c, mj, c.L, true, st));
+        RUN(ew_run(c, l, mj, c.L, true, st));
     }
     // 2. switch to the Comp level (Sec. 5.3's smaller parameters, as a modulus switch)
     if (Lc < c.L)
@@ -368,9 +307,9 @@ hc_status compress_many(Ctx& c, const hc_gk* gk, const hc_db* db, std::vector<Qu
                 }
             }
         }
-        RUN(ew_run(c, mul, Lc, true, st));
-        RUN(ks_run(c, ks, rot, nullptr, Lc, st));
-        RUN(ew_run(c, add, Lc, false, st));
+        RUN(ew_run(c, l, mul, Lc, true, st));
+        RUN(ks_run(c, l, ks, rot, nullptr, Lc, st));
+        RUN(ew_run(c, l, add, Lc, false, st));
     }
 
     // 4. hoisted baby steps Rot_row(u; b), b = 1..B-1, one raise per u-block
@@ -399,7 +338,7 @@ hc_status compress_many(Ctx& c, const hc_gk* gk, const hc_db* db, std::vector<Qu
                     }
                 }
         }
-        if (!jobs.empty()) RUN(ks_run(c, ks, jobs, &srcs, Lc, st));
+        if (!jobs.empty()) RUN(ks_run(c, l, ks, jobs, &srcs, Lc, st));
     }
 
     // 5. diagonals encoded on the fly, one chunk of giant indices at a time, accumulated
@@ -432,12 +371,12 @@ hc_status compress_many(Ctx& c, const hc_gk* gk, const hc_db* db, std::vector<Qu
             for (uint32_t gi = 0; gi < G; gi++) hptr[np * kb * B + ci * G + gi] = q.A[pp][gi];
         }
         const uint64_t* const* rptr =
-            (const uint64_t* const*)stage_bytes(c, hptr.data(), sizeof(uint64_t*) * np * kb * B, st);
+            (const uint64_t* const*)stage_bytes(l, hptr.data(), sizeof(uint64_t*) * np * kb * B, st);
         if (!rptr) return HC_ENOMEM;
         k_diag_gather(c, Rt, rptr, (int)np, (int)(kb * B), Lc, st);
         if (const Ctx::DiagTab* tab = cls_res[kv.first]) {
             // resident diagonals: one pass over every giant index
-            uint64_t** aptr = (uint64_t**)stage_bytes(c, hptr.data() + np * kb * B, sizeof(uint64_t*) * np * G, st);
+            uint64_t** aptr = (uint64_t**)stage_bytes(l, hptr.data() + np * kb * B, sizeof(uint64_t*) * np * G, st);
             if (!aptr) return HC_ENOMEM;
             k_diag_mac(c, aptr, Rt, tab->d, diag_layout_tiled(c, tab->kb * B, G), (int)np, (int)(kb * B), (int)G,
                        false, Lc, st);
@@ -459,8 +398,8 @@ hc_status compress_many(Ctx& c, const hc_gk* gk, const hc_db* db, std::vector<Qu
             haptr.assign(np * gc, nullptr);  // A pointers [cls][gc]
             for (size_t ci = 0; ci < np; ci++)
                 for (uint32_t gi = 0; gi < gc; gi++) haptr[ci * gc + gi] = cls[ci].first->A[cls[ci].second][g0 + gi];
-            const uint32_t* dprm = (const uint32_t*)stage_bytes(c, hprm.data(), sizeof(uint32_t) * hprm.size(), st);
-            uint64_t** aptr = (uint64_t**)stage_bytes(c, haptr.data(), sizeof(uint64_t*) * haptr.size(), st);
+            const uint32_t* dprm = (const uint32_t*)stage_bytes(l, hprm.data(), sizeof(uint32_t) * hprm.size(), st);
+            uint64_t** aptr = (uint64_t**)stage_bytes(l, haptr.data(), sizeof(uint64_t*) * haptr.size(), st);
             if (!dprm || !aptr) return HC_ENOMEM;
             k_diag_gen(c, Dp, dprm, cnt, s, B, st);
             ntt32(c, Dp, cnt, true, st);
@@ -490,7 +429,7 @@ hc_status compress_many(Ctx& c, const hc_gk* gk, const hc_db* db, std::vector<Qu
                     go += G;
                 }
         }
-        if (!jobs.empty()) RUN(ks_run(c, ks, jobs, nullptr, Lc, st));
+        if (!jobs.empty()) RUN(ks_run(c, l, ks, jobs, nullptr, Lc, st));
         for (auto& q : qs) {
             size_t go = 0;
             int pp = 0;
@@ -513,7 +452,7 @@ hc_status compress_many(Ctx& c, const hc_gk* gk, const hc_db* db, std::vector<Qu
                 for (int pp = 0; pp < q.npairs; pp++)
                     jobs.push_back(KsJob{q.ybuf + pp * q.CW, q.ytmp + pp * q.CW, find_key(gk, k), k, 0});
         if (jobs.empty()) continue;
-        RUN(ks_run(c, ks, jobs, nullptr, Lc, st));
+        RUN(ks_run(c, l, ks, jobs, nullptr, Lc, st));
         for (auto& q : qs)
             if (q.pl.s <= sh) k_add(c, q.ybuf, q.ybuf, q.ytmp, 0, Lc, 2 * q.npairs, q.PW, st);
     }
@@ -534,8 +473,8 @@ hc_status compress_many(Ctx& c, const hc_gk* gk, const hc_db* db, std::vector<Qu
                 }
             }
         }
-        RUN(ew_run(c, mul, Lc, true, st));
-        if (!jobs.empty()) RUN(ks_run(c, ks, jobs, nullptr, Lc, st));
+        RUN(ew_run(c, l, mul, Lc, true, st));
+        if (!jobs.empty()) RUN(ks_run(c, l, ks, jobs, nullptr, Lc, st));
     }
     // 9. outputs back to the coefficient domain
     for (auto& q : qs) {
@@ -588,7 +527,7 @@ extern "C" hc_status hc_compress(hc_context* cp, const hc_gk* gk, const hc_db* d
     if (s != HC_OK) return s;
     qs[0].ct_v = ct_v;
     qs[0].ct_out = ct_out;
-    s = compress_many(*cp, gk, db, qs, st);
+    s = compress_many(*cp, cp->lane, gk, db, qs, st);
     if (s == HC_OK) fill_info(qs[0], info);
     return s;
 }
@@ -621,7 +560,7 @@ extern "C" hc_status hc_compress_batch(hc_context* cp, const hc_gk* gk, const hc
         idx[r.pl.level].push_back(i);
     }
     for (auto& kv : by_level) {
-        hc_status s = compress_many(*cp, gk, db, kv.second, st);
+        hc_status s = compress_many(*cp, cp->lane, gk, db, kv.second, st);
         auto& ids = idx[kv.first];
         for (size_t j = 0; j < ids.size(); j++) {
             q[ids[j]].status = s;
@@ -664,14 +603,14 @@ extern "C" hc_status hc_diag_prepare(hc_context* cp, uint64_t N, uint32_t ncol, 
         // encode in chunks: slot values (Sec. 5.2 diagonals of C), to R_p, lift, NTT per
         // prime, then into the table's tiled layout
         const size_t chunk = std::min<size_t>(count, 2048);
-        stage_reset(c, st);
-        if (c.ws.reserve(n * 4 * chunk + PW * 8 * chunk + 4096) != HC_OK) {
+        stage_reset(c.lane, st);
+        if (c.lane.ws.reserve(n * 4 * chunk + PW * 8 * chunk + 4096) != HC_OK) {
             (void)hipFree(tab.d);
             return HC_ENOMEM;
         }
-        c.ws.reset();
-        uint32_t* Dp = c.ws.take<uint32_t>(n * chunk);
-        uint64_t* Dn = c.ws.take<uint64_t>(PW * chunk);
+        c.lane.ws.reset();
+        uint32_t* Dp = c.lane.ws.take<uint32_t>(n * chunk);
+        uint64_t* Dn = c.lane.ws.take<uint64_t>(PW * chunk);
         std::vector<uint32_t> hprm;
         for (size_t i0 = 0; i0 < count; i0 += chunk) {
             const size_t cnt = std::min(chunk, count - i0);
@@ -681,8 +620,8 @@ extern "C" hc_status hc_diag_prepare(hc_context* cp, uint64_t N, uint32_t ncol, 
                 hprm.push_back((uint32_t)((i / B) % G));           // giant index
                 hprm.push_back((uint32_t)(i % B));                 // baby index
             }
-            stage_reset(c, st);
-            const uint32_t* dprm = (const uint32_t*)stage_bytes(c, hprm.data(), sizeof(uint32_t) * hprm.size(), st);
+            stage_reset(c.lane, st);
+            const uint32_t* dprm = (const uint32_t*)stage_bytes(c.lane, hprm.data(), sizeof(uint32_t) * hprm.size(), st);
             if (!dprm) {
                 (void)hipFree(tab.d);
                 return HC_ENOMEM;

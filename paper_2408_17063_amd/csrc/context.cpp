@@ -37,6 +37,27 @@ void Arena::release() {
     used = 0;
 }
 
+hc_status Lane::init(size_t stage_bytes) {
+    stage_cap = stage_bytes;
+    if (hipHostMalloc((void**)&stage_host, stage_cap, hipHostMallocDefault) != hipSuccess) {
+        stage_host = nullptr;
+        return HC_ENOMEM;
+    }
+    if (hipMalloc((void**)&stage_dev, stage_cap) != hipSuccess) {
+        stage_dev = nullptr;
+        return HC_ENOMEM;
+    }
+    return HC_OK;
+}
+
+void Lane::release() {
+    if (stage_host) (void)hipHostFree(stage_host);
+    if (stage_dev) (void)hipFree(stage_dev);
+    stage_host = nullptr;
+    stage_dev = nullptr;
+    ws.release();
+}
+
 // ------------------------------------------------------------------ number theory (host)
 
 static bool is_prime_u64(uint64_t x) {
@@ -350,13 +371,10 @@ extern "C" hc_status hc_context_create(const hc_params* prm, int device, hc_cont
         return st;
     }
     // staging for per-call tables
-    c.stage_cap = (size_t)8 << 20;
-    if (hipHostMalloc((void**)&c.stage_host, c.stage_cap, hipHostMallocDefault) != hipSuccess ||
-        hipMalloc((void**)&c.stage_dev, c.stage_cap) != hipSuccess) {
+    if (c.lane.init((size_t)8 << 20) != HC_OK) {
         hc_context_destroy(cp);
         return HC_ENOMEM;
     }
-    c.owned.push_back(c.stage_dev);
     if (hipDeviceSynchronize() != hipSuccess) { hc_context_destroy(cp); return HC_EDEVICE; }
     *out = cp;
     return HC_OK;
@@ -367,11 +385,17 @@ extern "C" void hc_context_destroy(hc_context* c) {
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     for (void* p : c->owned) (void)hipFree(p);
-    if (c->stage_host) (void)hipHostFree(c->stage_host);
     for (auto& kv : c->prefix_masks) (void)hipFree(kv.second);
     for (auto& kv : c->diag_tabs) (void)hipFree(kv.second.d);
-    c->ws.release();
+    c->lane.release();
     delete c;
+}
+
+extern "C" void hc_context_trim(hc_context* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    c->lane.ws.release();
 }
 
 extern "C" hc_status hc_context_primes(const hc_context* c, uint64_t* out) {
@@ -398,6 +422,7 @@ extern "C" const char* hc_status_str(hc_status s) {
 namespace hc {
 
 static hipEvent_t pool_get(const hc_context& c) {
+    std::lock_guard<std::mutex> g(c.timing_mu);
     if (!c.event_pool.empty()) {
         hipEvent_t e = c.event_pool.back();
         c.event_pool.pop_back();
@@ -419,6 +444,7 @@ TimeScope::TimeScope(const hc_context& c_, int kind_, hipStream_t st_, double by
 TimeScope::~TimeScope() {
     if (!c.timing || !a || !b) return;
     (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> g(c.timing_mu);
     c.tlaunches.push_back({kind, a, b, bytes, ops});
 }
 

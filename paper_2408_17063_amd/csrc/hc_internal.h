@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -37,6 +38,18 @@ struct Arena {
         used += bytes;
         return p;
     }
+    void release();
+};
+
+// The per-call device workspace and pinned staging area of one stream of work. The
+// context owns one (for its entry points); a server owns one per concurrent batch.
+struct Lane {
+    Arena ws;
+    uint8_t* stage_host = nullptr;   // pinned host staging for per-call tables
+    uint8_t* stage_dev = nullptr;    // its device mirror
+    size_t stage_cap = 0, stage_used = 0;
+    hipStream_t stage_stream = nullptr;
+    hc_status init(size_t stage_bytes);
     void release();
 };
 
@@ -89,17 +102,14 @@ struct hc_context {
     struct DiagTab { uint32_t kb = 0; uint64_t* d = nullptr; size_t bytes = 0; };
     std::map<std::tuple<uint32_t, uint32_t, int>, DiagTab> diag_tabs;
 
-    hc::Arena ws;      // per-call workspace
-    // pinned host staging for per-call tables (job lists, pointer tables) and its device mirror
-    uint8_t* stage_host = nullptr;
-    uint8_t* stage_dev = nullptr;
-    size_t stage_cap = 0, stage_used = 0;
-    hipStream_t stage_stream = nullptr;
+    hc::Lane lane;     // workspace and staging of the context's own entry points
+    std::mutex lazy_mu;  // guards the lazily built tables (prefix masks, switch tables)
     std::vector<void*> owned;  // device allocations freed at destroy
 
     // kernel timing (measurement only)
     struct TimedLaunch { int kind; hipEvent_t a, b; double bytes, ops; };
     bool timing = false;
+    mutable std::mutex timing_mu;
     mutable std::vector<TimedLaunch> tlaunches;
     mutable std::vector<hipEvent_t> event_pool;
 };

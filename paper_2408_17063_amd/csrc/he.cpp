@@ -36,6 +36,7 @@ hc_status encode_plain(Ctx& c, uint64_t* out, const uint32_t* host_slots, int co
 }
 
 hc_status prefix_mask(Ctx& c, uint32_t s, const uint64_t** out) {
+    std::lock_guard<std::mutex> g(c.lazy_mu);
     auto it = c.prefix_masks.find(s);
     if (it != c.prefix_masks.end()) { *out = it->second; return HC_OK; }
     std::vector<uint32_t> sl((size_t)c.n, 0);
@@ -51,22 +52,22 @@ hc_status prefix_mask(Ctx& c, uint32_t s, const uint64_t** out) {
 
 // ------------------------------------------------------------------ staging
 
-void stage_reset(Ctx& c, hipStream_t st) {
+void stage_reset(Lane& l, hipStream_t st) {
     // the previous call's asynchronous copies out of the staging area must be done
-    if (c.stage_stream != st) (void)hipStreamSynchronize(c.stage_stream);
+    if (l.stage_stream != st) (void)hipStreamSynchronize(l.stage_stream);
     (void)hipStreamSynchronize(st);
-    c.stage_used = 0;
-    c.stage_stream = st;
+    l.stage_used = 0;
+    l.stage_stream = st;
 }
 
-void* stage_bytes(Ctx& c, const void* data, size_t bytes, hipStream_t st) {
-    size_t off = (c.stage_used + 255) & ~(size_t)255;
-    if (off + bytes > c.stage_cap) return nullptr;
-    memcpy(c.stage_host + off, data, bytes);
-    if (hipMemcpyAsync(c.stage_dev + off, c.stage_host + off, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+void* stage_bytes(Lane& l, const void* data, size_t bytes, hipStream_t st) {
+    size_t off = (l.stage_used + 255) & ~(size_t)255;
+    if (off + bytes > l.stage_cap) return nullptr;
+    memcpy(l.stage_host + off, data, bytes);
+    if (hipMemcpyAsync(l.stage_dev + off, l.stage_host + off, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
         return nullptr;
-    c.stage_used = off + bytes;
-    return c.stage_dev + off;
+    l.stage_used = off + bytes;
+    return l.stage_dev + off;
 }
 
 // ------------------------------------------------------------------ batched key switching
@@ -108,7 +109,7 @@ KsScratch ks_scratch(Ctx& c, Arena& a, int Lc, int max_jobs) {
 // Rotations at level Lc. Plain (srcs == nullptr): each job raises its own rotated c1.
 // Hoisted: srcs[u] are raised once (unrotated) and every job with xidx = u rotates
 // the raised digits instead. Jobs are processed in passes of at most maxM.
-hc_status ks_run(Ctx& c, KsScratch& s, const std::vector<KsJob>& jobs,
+hc_status ks_run(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
                  const std::vector<const uint64_t*>* srcs, int Lc, hipStream_t st) {
     if (!s.tmpC || !s.X || !s.T || !s.conv) return HC_ENOMEM;
     const size_t n = c.n;
@@ -132,7 +133,7 @@ hc_status ks_run(Ctx& c, KsScratch& s, const std::vector<KsJob>& jobs,
             const int M = (int)std::min<size_t>(s.maxM, jobs.size() - m0);
             std::vector<KsJob> jb(jobs.begin() + m0, jobs.begin() + m0 + M);
             for (int i = 0; i < M; i++) jb[i].xidx = (uint32_t)i;
-            const KsJob* d = (const KsJob*)stage_bytes(c, jb.data(), sizeof(KsJob) * M, st);
+            const KsJob* d = (const KsJob*)stage_bytes(l, jb.data(), sizeof(KsJob) * M, st);
             if (!d) return HC_ENOMEM;
             raise(d, M, true);
             finish(d, M, false);
@@ -144,7 +145,7 @@ hc_status ks_run(Ctx& c, KsScratch& s, const std::vector<KsJob>& jobs,
         const int Uc = (int)std::min<size_t>(s.maxU, U - u0);
         std::vector<KsJob> sj(Uc);
         for (int i = 0; i < Uc; i++) sj[i] = KsJob{(*srcs)[u0 + i], nullptr, nullptr, 1u, (uint32_t)i};
-        const KsJob* ds = (const KsJob*)stage_bytes(c, sj.data(), sizeof(KsJob) * Uc, st);
+        const KsJob* ds = (const KsJob*)stage_bytes(l, sj.data(), sizeof(KsJob) * Uc, st);
         if (!ds) return HC_ENOMEM;
         raise(ds, Uc, false);
         std::vector<KsJob> mine;
@@ -156,7 +157,7 @@ hc_status ks_run(Ctx& c, KsScratch& s, const std::vector<KsJob>& jobs,
             }
         for (size_t m0 = 0; m0 < mine.size(); m0 += s.maxM) {
             const int M = (int)std::min<size_t>(s.maxM, mine.size() - m0);
-            const KsJob* d = (const KsJob*)stage_bytes(c, mine.data() + m0, sizeof(KsJob) * M, st);
+            const KsJob* d = (const KsJob*)stage_bytes(l, mine.data() + m0, sizeof(KsJob) * M, st);
             if (!d) return HC_ENOMEM;
             finish(d, M, true);
         }
@@ -164,9 +165,9 @@ hc_status ks_run(Ctx& c, KsScratch& s, const std::vector<KsJob>& jobs,
     return HC_OK;
 }
 
-hc_status ew_run(Ctx& c, const std::vector<EwJob>& jobs, int Lc, bool mul, hipStream_t st) {
+hc_status ew_run(Ctx& c, Lane& l, const std::vector<EwJob>& jobs, int Lc, bool mul, hipStream_t st) {
     if (jobs.empty()) return HC_OK;
-    const EwJob* d = (const EwJob*)stage_bytes(c, jobs.data(), sizeof(EwJob) * jobs.size(), st);
+    const EwJob* d = (const EwJob*)stage_bytes(l, jobs.data(), sizeof(EwJob) * jobs.size(), st);
     if (!d) return HC_ENOMEM;
     k_ew_jobs(c, d, (int)jobs.size(), Lc, mul, st);
     return HC_OK;
@@ -174,6 +175,7 @@ hc_status ew_run(Ctx& c, const std::vector<EwJob>& jobs, int Lc, bool mul, hipSt
 
 // Constants for dropping the primes Lc..L-1 (product D), cached per level.
 static hc_status ms_tables(Ctx& c, int Lc, const Ctx::MsTab** out) {
+    std::lock_guard<std::mutex> g(c.lazy_mu);
     auto it = c.ms_tabs.find(Lc);
     if (it == c.ms_tabs.end()) {
         const int L = c.L, nd = L - Lc;
@@ -443,12 +445,12 @@ static hc_status rotate_common(hc_context* cp, const hc_gk* gk, const uint32_t* 
     HC_CHECK(hipSetDevice(c.device));
     const size_t Ln2 = 2 * (size_t)c.L * c.n;
     std::vector<KsJob> jobs(count);
-    stage_reset(c, st);
-    if (c.ws.reserve(ks_scratch_bytes(c, c.L, (int)count) + sizeof(uint64_t) * Ln2 * (count + 1) + 4096) != HC_OK)
+    stage_reset(c.lane, st);
+    if (c.lane.ws.reserve(ks_scratch_bytes(c, c.L, (int)count) + sizeof(uint64_t) * Ln2 * (count + 1) + 4096) != HC_OK)
         return HC_ENOMEM;
-    KsScratch s = ks_scratch(c, c.ws, c.L, (int)count);
-    uint64_t* inN = c.ws.take<uint64_t>(Ln2);
-    uint64_t* outN = c.ws.take<uint64_t>(Ln2 * count);
+    KsScratch s = ks_scratch(c, c.lane.ws, c.L, (int)count);
+    uint64_t* inN = c.lane.ws.take<uint64_t>(Ln2);
+    uint64_t* outN = c.lane.ws.take<uint64_t>(Ln2 * count);
     if (!inN || !outN) return HC_ENOMEM;
     for (uint32_t i = 0; i < count; i++) {
         const uint64_t* key = find_key(gk, elts[i]);
@@ -458,7 +460,7 @@ static hc_status rotate_common(hc_context* cp, const hc_gk* gk, const uint32_t* 
     HC_CHECK(hipMemcpyAsync(inN, ct_in, sizeof(uint64_t) * Ln2, hipMemcpyDeviceToDevice, st));
     ntt64(c, inN, (size_t)c.L * c.n, 2, 0, c.L, false, st);
     std::vector<const uint64_t*> srcs{inN};
-    hc_status stt = ks_run(c, s, jobs, hoisted ? &srcs : nullptr, c.L, st);
+    hc_status stt = ks_run(c, c.lane, s, jobs, hoisted ? &srcs : nullptr, c.L, st);
     if (stt != HC_OK) return stt;
     ntt64(c, outN, (size_t)c.L * c.n, 2 * (int)count, 0, c.L, true, st);
     HC_CHECK(hipMemcpyAsync(cts_out, outN, sizeof(uint64_t) * Ln2 * count, hipMemcpyDeviceToDevice, st));
@@ -485,9 +487,9 @@ extern "C" hc_status hc_mul_plain(hc_context* cp, const uint64_t* ct_in, const u
     HC_CHECK(hipSetDevice(c.device));
     const size_t Ln = (size_t)c.L * c.n;
     HC_CHECK(hipStreamSynchronize(st));
-    if (c.ws.reserve(sizeof(uint64_t) * Ln * 3 + 1024) != HC_OK) return HC_ENOMEM;
-    uint64_t* pt = c.ws.take<uint64_t>(Ln);
-    uint64_t* tmp = c.ws.take<uint64_t>(2 * Ln);
+    if (c.lane.ws.reserve(sizeof(uint64_t) * Ln * 3 + 1024) != HC_OK) return HC_ENOMEM;
+    uint64_t* pt = c.lane.ws.take<uint64_t>(Ln);
+    uint64_t* tmp = c.lane.ws.take<uint64_t>(2 * Ln);
     if (!pt || !tmp) return HC_ENOMEM;
     hc_status s = encode_plain(c, pt, slots, 1, true, st);
     if (s != HC_OK) return s;
@@ -507,8 +509,8 @@ extern "C" hc_status hc_modup(hc_context* cp, const uint64_t* x, uint32_t digit,
     HC_CHECK(hipSetDevice(c.device));
     const size_t n = c.n, R = (size_t)c.nq;
     HC_CHECK(hipStreamSynchronize(st));
-    if (c.ws.reserve(sizeof(uint64_t) * (size_t)c.dnum * R * n + 4096) != HC_OK) return HC_ENOMEM;
-    uint64_t* X = c.ws.take<uint64_t>((size_t)c.dnum * R * n);
+    if (c.lane.ws.reserve(sizeof(uint64_t) * (size_t)c.dnum * R * n + 4096) != HC_OK) return HC_ENOMEM;
+    uint64_t* X = c.lane.ws.take<uint64_t>((size_t)c.dnum * R * n);
     if (!X) return HC_ENOMEM;
     // x is [L][n], the compact layout of one source at the top level
     kb_modup(c, X, x, 1, c.L, st);
@@ -528,21 +530,21 @@ extern "C" hc_status hc_moddown(hc_context* cp, const uint64_t* T, uint64_t* out
     Ctx& c = *cp;
     HC_CHECK(hipSetDevice(c.device));
     const size_t n = c.n;
-    stage_reset(c, st);
-    if (c.ws.reserve(sizeof(uint64_t) * (2 * c.nq * n + 6 * c.L * n) + 4096) != HC_OK) return HC_ENOMEM;
+    stage_reset(c.lane, st);
+    if (c.lane.ws.reserve(sizeof(uint64_t) * (2 * c.nq * n + 6 * c.L * n) + 4096) != HC_OK) return HC_ENOMEM;
     // T as component 0 of one job's [2][L+K][n] (component 1 zero); the conversion and the
     // final combination are element-wise, so they apply in the coefficient domain too
-    uint64_t* TT = c.ws.take<uint64_t>(2 * c.nq * n);
-    uint64_t* conv = c.ws.take<uint64_t>(2 * c.L * n);
-    uint64_t* zero = c.ws.take<uint64_t>(2 * c.L * n);
-    uint64_t* o2 = c.ws.take<uint64_t>(2 * c.L * n);
+    uint64_t* TT = c.lane.ws.take<uint64_t>(2 * c.nq * n);
+    uint64_t* conv = c.lane.ws.take<uint64_t>(2 * c.L * n);
+    uint64_t* zero = c.lane.ws.take<uint64_t>(2 * c.L * n);
+    uint64_t* o2 = c.lane.ws.take<uint64_t>(2 * c.L * n);
     if (!TT || !conv || !zero || !o2) return HC_ENOMEM;
     const size_t zc = 2 * c.nq * n, zc2 = 2 * c.L * n;
     hipLaunchKernelGGL(zero_fill_kernel, dim3((zc + 255) / 256), dim3(256), 0, st, TT, zc);
     hipLaunchKernelGGL(zero_fill_kernel, dim3((zc2 + 255) / 256), dim3(256), 0, st, zero, zc2);
     HC_CHECK(hipMemcpyAsync(TT, T, sizeof(uint64_t) * c.nq * n, hipMemcpyDeviceToDevice, st));
     KsJob j{zero, o2, nullptr, 1u, 0u};
-    const KsJob* dj = (const KsJob*)stage_bytes(c, &j, sizeof(j), st);
+    const KsJob* dj = (const KsJob*)stage_bytes(c.lane, &j, sizeof(j), st);
     if (!dj) return HC_ENOMEM;
     kb_conv(c, conv, TT, 1, c.L, st);
     kb_final(c, dj, TT, conv, 1, c.L, st);

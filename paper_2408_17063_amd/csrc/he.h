@@ -18,14 +18,14 @@ hc_status encode_plain(Ctx& c, uint64_t* out, const uint32_t* host_slots, int co
                        hipStream_t st);
 hc_status prefix_mask(Ctx& c, uint32_t s, const uint64_t** out);
 // per-call staging of small tables (pinned host -> device, in stream order)
-void stage_reset(Ctx& c, hipStream_t st);
-void* stage_bytes(Ctx& c, const void* data, size_t bytes, hipStream_t st);
+void stage_reset(Lane& l, hipStream_t st);
+void* stage_bytes(Lane& l, const void* data, size_t bytes, hipStream_t st);
 // batched key switching at level Lc (see ks_run in he.cpp)
 size_t ks_scratch_bytes(const Ctx& c, int Lc, int max_jobs);
 KsScratch ks_scratch(Ctx& c, Arena& a, int Lc, int max_jobs);
-hc_status ks_run(Ctx& c, KsScratch& s, const std::vector<KsJob>& jobs,
+hc_status ks_run(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
                  const std::vector<const uint64_t*>* srcs, int Lc, hipStream_t st);
-hc_status ew_run(Ctx& c, const std::vector<EwJob>& jobs, int Lc, bool mul, hipStream_t st);
+hc_status ew_run(Ctx& c, Lane& l, const std::vector<EwJob>& jobs, int Lc, bool mul, hipStream_t st);
 // drop the primes Lc..L-1 of `count` contiguous top-level ciphertexts (NTT domain)
 hc_status mod_switch_batch(Ctx& c, uint64_t* out, uint64_t* in, int count, int Lc, uint64_t* conv,
                            hipStream_t st);

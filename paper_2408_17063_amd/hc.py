@@ -59,6 +59,17 @@ class Query(ctypes.Structure):
                 ("status", ctypes.c_int)]
 
 
+class ServerResult(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int), ("submit_ns", ctypes.c_int64),
+                ("start_ns", ctypes.c_int64), ("done_ns", ctypes.c_int64), ("batch_size", ctypes.c_uint32),
+                ("info", CompressInfo)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("max_batch_seen", ctypes.c_uint32), ("max_lanes_busy", ctypes.c_uint32)]
+
+
 def _sig(name, res, *args):
     f = getattr(_lib, name)
     f.restype = res
@@ -71,6 +82,7 @@ _sig("hc_status_str", ctypes.c_char_p, _st)
 _sig("hc_context_create", _st, ctypes.POINTER(Params), ctypes.c_int, ctypes.POINTER(c_vp))
 _sig("hc_context_destroy", None, c_vp)
 _sig("hc_context_primes", _st, c_vp, c_u64p)
+_sig("hc_context_trim", None, c_vp)
 _sig("hc_keygen", _st, c_vp, c_u8p, ctypes.POINTER(c_vp), ctypes.POINTER(c_vp))
 _sig("hc_sk_destroy", None, c_vp)
 _sig("hc_pk_destroy", None, c_vp)
@@ -108,19 +120,28 @@ _sig("hc_probe_copy", _st, c_vp, ctypes.c_uint64)
 _sig("hc_diag_prepare", _st, c_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
      ctypes.POINTER(ctypes.c_uint64))
 _sig("hc_diag_release", None, c_vp)
+_sig("hc_server_create", _st, c_vp, c_vp, c_vp, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+     ctypes.POINTER(c_vp))
+_sig("hc_server_submit", _st, c_vp, c_vp, ctypes.c_uint64, ctypes.c_uint32, c_vp, ctypes.POINTER(ctypes.c_uint64))
+_sig("hc_server_poll", _st, c_vp, ctypes.POINTER(ServerResult), ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
+     ctypes.c_double)
+_sig("hc_server_stats_get", _st, c_vp, ctypes.POINTER(ServerStats))
+_sig("hc_server_destroy", None, c_vp)
 
 KT_NTT_FWD, KT_NTT_INV, KT_KS_INNER, KT_DIAG_MAC, KT_MODUP = 0, 1, 2, 3, 4
 KT_NAMES = {KT_NTT_FWD: "ntt_forward", KT_NTT_INV: "ntt_inverse", KT_KS_INNER: "keyswitch_inner",
             KT_DIAG_MAC: "diag_mac", KT_MODUP: "modup"}
 
 EXPORTED = [
-    "hc_status_str", "hc_context_create", "hc_context_destroy", "hc_context_primes", "hc_keygen",
+    "hc_status_str", "hc_context_create", "hc_context_destroy", "hc_context_primes", "hc_context_trim",
+    "hc_keygen",
     "hc_sk_destroy", "hc_pk_destroy", "hc_galois_keygen", "hc_gk_destroy", "hc_plan",
     "hc_db_upload", "hc_db_destroy", "hc_encrypt", "hc_compress", "hc_compress_batch",
     "hc_decrypt", "hc_decompress", "hc_ntt", "hc_rotate", "hc_rotate_hoisted", "hc_mul_plain",
     "hc_modup", "hc_moddown", "hc_sample", "hc_encode_diagonal", "hc_export_sk", "hc_export_pk",
     "hc_export_gk", "hc_timing_enable", "hc_timing_read", "hc_probe_mul32_rate", "hc_probe_copy",
-    "hc_diag_prepare", "hc_diag_release",
+    "hc_diag_prepare", "hc_diag_release", "hc_server_create", "hc_server_submit", "hc_server_poll",
+    "hc_server_stats_get", "hc_server_destroy",
 ]
 
 
@@ -185,6 +206,10 @@ class Context:
             pass
 
     # ---- torch helpers
+    def trim(self):
+        """Free the per-call device workspace (it grows again on demand)."""
+        _lib.hc_context_trim(self.h)
+
     def ct_tensor(self, count=1):
         import torch
         return torch.empty((count, 2, self.L, self.n), dtype=torch.int64, device="cuda:%d" % self.device)
@@ -412,3 +437,53 @@ class Database(_Handle):
     def __init__(self, ctx, h, ncol, N):
         super().__init__(ctx, h)
         self.ncol, self.N = ncol, N
+
+
+class Server:
+    """Serving loop (hc_server_*): submit queries as they arrive, poll completions.
+    Keeps every submitted request's device tensors alive until it is polled."""
+
+    def __init__(self, ctx, gk, db, comp_level=0, lane_bytes=8 << 30, lanes=2, max_batch=16):
+        self.ctx, self.gk, self.db = ctx, gk, db
+        h = c_vp()
+        _check(_lib.hc_server_create(ctx.h, gk.h, db.h if db is not None else None, comp_level, lane_bytes, lanes,
+                                     max_batch, ctypes.byref(h)), "hc_server_create")
+        self.h = h
+        self._live = {}
+
+    def submit(self, ct_v, N, t_bound, out):
+        rid = ctypes.c_uint64(0)
+        _check(_lib.hc_server_submit(self.h, _dev(ct_v), N, t_bound, _dev(out), ctypes.byref(rid)),
+               "hc_server_submit")
+        self._live[rid.value] = (ct_v, out)
+        return rid.value
+
+    def poll(self, cap=64, timeout_ms=0.0):
+        arr = (ServerResult * cap)()
+        cnt = ctypes.c_uint32(0)
+        _check(_lib.hc_server_poll(self.h, arr, cap, ctypes.byref(cnt), float(timeout_ms)), "hc_server_poll")
+        res = []
+        for i in range(cnt.value):
+            r = arr[i]
+            self._live.pop(r.id, None)
+            res.append({"id": r.id, "status": r.status, "submit_ns": r.submit_ns, "start_ns": r.start_ns,
+                        "done_ns": r.done_ns, "batch_size": r.batch_size, "info": r.info.as_dict()})
+        return res
+
+    def stats(self):
+        st = ServerStats()
+        _check(_lib.hc_server_stats_get(self.h, ctypes.byref(st)), "hc_server_stats_get")
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def close(self):
+        if self.h:
+            _lib.hc_server_destroy(self.h)
+            self.h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
