@@ -254,6 +254,23 @@ def rotate(pr, ct, gk):
     return Ciphertext(c0 + moddown(pr, T0), moddown(pr, T1))
 
 
+def rotate_sum(pr, cts, gks):
+    """Sum of the non-hoisted rotations sigma_{k_g}(ct_g), g = 0.., with the key
+    products summed over PQ and brought down once: sum_g sigma(c0_g) +
+    ModDown(sum_g T0_g), ModDown(sum_g T1_g). Up to ModDown's rounding this is
+    sum_g rotate(ct_g); every modular sum is exact, so only the one ModDown rounds."""
+    C0 = T0s = T1s = None
+    for ct, gk in zip(cts, gks):
+        c1 = automorphism(ct.c1, gk.k)
+        xs = [modup(pr, c1, j) for j in range(pr.dnum)]
+        T0, T1 = _inner(pr, xs, gk)
+        c0 = automorphism(ct.c0, gk.k)
+        C0 = c0 if C0 is None else C0 + c0
+        T0s = T0 if T0s is None else T0s + T0
+        T1s = T1 if T1s is None else T1s + T1
+    return Ciphertext(C0 + moddown(pr, T0s), moddown(pr, T1s))
+
+
 def rotate_hoisted(pr, ct, gks):
     """Rotations of one ciphertext by several sigma_k sharing one ModUp."""
     xs = [modup(pr, ct.c1, j) for j in range(pr.dnum)]

@@ -27,7 +27,9 @@ determined by the inputs and the key seeds):
 * block products use baby step/giant step with B the power of two in [1, s]
   minimising k (B-1) + (s/B - 1) (k = blocks in the group), ties to the larger
   B. Baby-step rotations Rot_row(u; b), b < B, are hoisted (one ModUp per
-  block); giant-step, rotate-and-sum, Rot_col and merge rotations are not;
+  block); giant-step, rotate-and-sum, Rot_col and merge rotations are not. The
+  giant-step rotations of one block product are summed before ModDown: their
+  key products are added over PQ and brought down once (bfv.rotate_sum);
 * pre-rotated diagonal for block beta, giant index g, baby index b, slot m of
   either row: alpha(beta, (m + b) mod n/2) ^ (((m - g B) mod s) + 1) mod p with
   alpha(beta, c) = beta n/2 + c + 1;
@@ -256,7 +258,7 @@ def block_product(pr, sched, grp, us, keys):
         if B > 1:
             rs += bfv.rotate_hoisted(pr, u, [keys[rot(n, b)] for b in range(1, B)])
         baby.append(rs)
-    y = None
+    accs = []
     for gi in range(s // B):
         acc = None
         for beta in range(grp.k):
@@ -264,9 +266,11 @@ def block_product(pr, sched, grp, us, keys):
                 d = diagonal_slots(pr.p, pr.nh, s, B, beta, gi, b)
                 term = bfv.mul_plain(pr, baby[beta][b], bfv.plain_poly(pr, d))
                 acc = term if acc is None else acc + term
-        if gi > 0:
-            acc = bfv.rotate(pr, acc, keys[rot(n, gi * B)])
-        y = acc if y is None else y + acc
+        accs.append(acc)
+    # giant steps: y = A_0 + sum_{g >= 1} Rot_row(A_g; g B), one ModDown for the sum
+    y = accs[0]
+    if len(accs) > 1:
+        y = y + bfv.rotate_sum(pr, accs[1:], [keys[rot(n, gi * B)] for gi in range(1, len(accs))])
     return y
 
 

@@ -277,6 +277,42 @@ def test_rotation_forms_decrypt_alike(p4096, r_step):
     assert not (plain == hoisted)  # hoisting changes bits, not values
 
 
+def test_rotate_sum_is_rotations_up_to_one_rounding(p4096):
+    """A sum of rotations brought down once differs from the sum of separately
+    key-switched rotations only by ModDown's rounding: per coefficient, as an
+    integer mod Q, by a value in [-(K-1), G K - 1] (G rotations; each fast
+    ModDown returns floor(T/P) - u with 0 <= u < K), and decrypts to the sum of
+    the rotated slots."""
+    pr, sk, pk = p4096
+    steps = [1, 5, 2047]
+    cts, gks, want = [], [], np.zeros((2, pr.nh), dtype=np.int64)
+    for i, r in enumerate(steps):
+        sl = np.random.default_rng(40 + i).integers(0, pr.p, size=(2, pr.nh))
+        cts.append(bfv.encrypt(pr, pk, sl, bytes([50 + i] * 32)))
+        gks.append(bfv.galois_keygen(pr, sk, bfv.rot_row_element(pr, r), bytes([60 + i] * 32)))
+        want = (want + np.roll(sl, -r, axis=1)) % pr.p
+    lazy = bfv.rotate_sum(pr, cts, gks)
+    eager = None
+    for ct, gk in zip(cts, gks):
+        r = bfv.rotate(pr, ct, gk)
+        eager = r if eager is None else eager + r
+    assert np.array_equal(bfv.decrypt(pr, sk, lazy), want)
+    Q = math.prod(pr.q)
+    G, K = len(steps), pr.K
+    for a, b in ((lazy.c0, eager.c0), (lazy.c1, eager.c1)):
+        for x in range(0, pr.n, 97):
+            # CRT of the difference's residues, written out here
+            v = 0
+            for i, q in enumerate(pr.q):
+                d = (int(a.c[i][x]) - int(b.c[i][x])) % q
+                Mi = Q // q
+                v += d * Mi * pow(Mi % q, -1, q)
+            v %= Q
+            v = v - Q if v > Q // 2 else v
+            assert -(K - 1) <= v <= G * K - 1, (x, v)
+    assert not (lazy == eager)  # the rounding does show in the bits
+
+
 # --------------------------------------------------------------------------- decompression
 
 def test_newton_matches_direct_expansion():
