@@ -206,13 +206,17 @@ hc_status batch_shape(const Ctx& c, const hc_gk* gk, const hc_db* db, std::vecto
     }
     size_t rt_max = 1;  // gathered rotated ciphertexts of one class
     for (auto& kv : cls_k) rt_max = std::max(rt_max, (size_t)cls_np[kv.first] * kv.second * kv.first.second * 2 * PW);
+    size_t sum_groups = 0;  // giant-step sums (one per pair)
+    for (auto& q : qs) sum_groups += (size_t)q.npairs;
+    const size_t R = (size_t)Lc + c.K;
     total += rup(PW * 8 * diag_max) + rup(n * 4 * diag_max) + rup(rt_max * 8) +
-             ks_scratch_bytes(c, Lc, (int)max_jobs);
+             rup(sum_groups * 2 * R * n * 8) + rup(sum_groups * PW * 8) + ks_scratch_bytes(c, Lc, (int)max_jobs);
 
     b.total = total;
     b.max_jobs = max_jobs;
     b.diag_max = diag_max;
     b.rt_max = rt_max;
+    b.sum_groups = sum_groups;
     return HC_OK;
 }
 
@@ -238,7 +242,9 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
     uint64_t* D = a.take<uint64_t>(PW * diag_max);
     uint32_t* Dp = a.take<uint32_t>(n * diag_max);
     uint64_t* Rt = a.take<uint64_t>(rt_max);
-    if (!D || !Dp || !Rt) return HC_ENOMEM;
+    uint64_t* TA = a.take<uint64_t>(std::max<size_t>(1, shape.sum_groups) * 2 * ((size_t)Lc + c.K) * n);
+    uint64_t* C0A = a.take<uint64_t>(std::max<size_t>(1, shape.sum_groups) * PW);
+    if (!D || !Dp || !Rt || !TA || !C0A) return HC_ENOMEM;
     for (auto& q : qs) {
         q.n_diag = q.n_diag_res = 0;
         for (auto& kv : plan_classes(q.pl))
@@ -411,35 +417,35 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
         }
     }
 
-    // 6. giant steps: y = A_0 + sum_g Rot_row(A_g; g B)
+    // 6. giant steps: y = A_0 + sum_{g >= 1} Rot_row(A_g; g B); the giant rotations of
+    //    each pair are key-switched as one sum with a single ModDown
     {
         std::vector<KsJob> jobs;
+        std::vector<uint32_t> grp;
+        std::vector<uint64_t*> outs;
+        std::vector<EwJob> add;
         for (auto& q : qs) {
-            size_t go = 0;
             int pp = 0;
             for (auto& g : q.pl.groups)
                 for (size_t si = 0; si < q.pl.streams.size(); si++, pp++) {
                     const uint32_t G = q.pl.s / g.B;
-                    HC_CHECK(hipMemcpyAsync(q.gout + go * q.CW, q.A[pp][0], sizeof(uint64_t) * q.CW,
-                                            hipMemcpyDeviceToDevice, st));
+                    uint64_t* y = q.ybuf + (size_t)pp * q.CW;
+                    if (G == 1) {
+                        HC_CHECK(hipMemcpyAsync(y, q.A[pp][0], sizeof(uint64_t) * q.CW, hipMemcpyDeviceToDevice, st));
+                        continue;
+                    }
+                    uint64_t* o = q.gout + (size_t)pp * q.CW;
                     for (uint32_t gi = 1; gi < G; gi++) {
                         const uint32_t k = rot_elt(c, (int64_t)gi * g.B);
-                        jobs.push_back(KsJob{q.A[pp][gi], q.gout + (go + gi) * q.CW, find_key(gk, k), k, 0});
+                        jobs.push_back(KsJob{q.A[pp][gi], nullptr, find_key(gk, k), k, 0});
+                        grp.push_back((uint32_t)outs.size());
                     }
-                    go += G;
+                    outs.push_back(o);
+                    add.push_back(EwJob{y, q.A[pp][0], o});
                 }
         }
-        if (!jobs.empty()) RUN(ks_run(c, l, ks, jobs, nullptr, Lc, st));
-        for (auto& q : qs) {
-            size_t go = 0;
-            int pp = 0;
-            for (auto& g : q.pl.groups)
-                for (size_t si = 0; si < q.pl.streams.size(); si++, pp++) {
-                    const uint32_t G = q.pl.s / g.B;
-                    k_sum_cts(c, q.ybuf + (size_t)pp * q.CW, q.gout + go * q.CW, 1, (int)G, Lc, st);
-                    go += G;
-                }
-        }
+        if (!jobs.empty()) RUN(ks_run_sum(c, l, ks, jobs, grp, outs, TA, C0A, Lc, st));
+        RUN(ew_run(c, l, add, Lc, false, st));
     }
 
     // 7. rotate-and-sum, once after the block sums (Sec. 5.2): y += Rot_row(y; sh) for

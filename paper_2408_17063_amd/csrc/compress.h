@@ -59,7 +59,8 @@ struct QueryRun {
         size_t t = rup(CWF * 8 * ntot);
         if (pl.level < c.L) t += 2 * rup(CW * 8 * ntot);
         t += 4 * rup(CW * 8 * std::max<size_t>(ub, 1)) + rup(CW * 8 * std::max<size_t>(baby, 1));
-        t += 2 * rup(CW * 8 * gi) + 2 * rup(CW * 8 * npairs) + 2 * rup(CW * 8 * pl.bands) + rup(CW * 8);
+        t += rup(CW * 8 * gi) + rup(CW * 8 * npairs) + 2 * rup(CW * 8 * npairs) + 2 * rup(CW * 8 * pl.bands) +
+             rup(CW * 8);
         return t;
     }
     hc_status take(Arena& a) {
@@ -78,7 +79,7 @@ struct QueryRun {
         wbuf = a.take<uint64_t>(CW * std::max<size_t>(ub, 1));
         bbuf = a.take<uint64_t>(CW * std::max<size_t>(baby, 1));
         gbuf = a.take<uint64_t>(CW * gi);
-        gout = a.take<uint64_t>(CW * gi);
+        gout = a.take<uint64_t>(CW * npairs);  // each pair's key-switched giant-step sum
         ybuf = a.take<uint64_t>(CW * npairs);
         ytmp = a.take<uint64_t>(CW * npairs);
         mbuf = a.take<uint64_t>(CW * pl.bands);
@@ -99,7 +100,7 @@ struct QueryRun {
 // resident, the on-the-fly chunking, and the workspace bytes compress_many takes.
 struct BatchShape {
     int Lc = 0;
-    size_t total = 0, max_jobs = 1, diag_max = 1, rt_max = 1;
+    size_t total = 0, max_jobs = 1, diag_max = 1, rt_max = 1, sum_groups = 0;
     std::map<std::pair<uint32_t, uint32_t>, uint32_t> cls_k;   // (s, B) -> max k
     std::map<std::pair<uint32_t, uint32_t>, uint32_t> cls_np;  // (s, B) -> pairs
     std::map<std::pair<uint32_t, uint32_t>, uint32_t> cls_gc;  // (s, B) -> giants per chunk

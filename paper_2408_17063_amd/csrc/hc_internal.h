@@ -151,6 +151,9 @@ struct KsJob {
     uint32_t xidx;
 };
 
+// Jobs [j0, j1) of a key-switching pass that belong to sum group g.
+struct KsGroupRange { uint32_t g, j0, j1, pad; };
+
 // One element-wise job over a ciphertext [2][Lc][n]: out = a (*|+) b.
 struct EwJob {
     uint64_t* out;
@@ -196,7 +199,11 @@ void k_mul_plain(const Ctx& c, uint64_t* out, const uint64_t* ct, const uint64_t
 void kb_take_c1(const Ctx& c, uint64_t* tmpC, const KsJob* jobs, int M, int Lc, bool permute,
                 hipStream_t st);
 // X [U][dn][Lc+K][n] raised digits of the coefficient-domain tmpC [U][Lc][n]
-void kb_modup(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, hipStream_t st);
+// ModUp of U sources [Lc][n] (coefficient domain) into digits X[U][dn][Lc+K][n]; a
+// digit's own rows are written only if own_rows.
+void kb_modup(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, bool own_rows, hipStream_t st);
+// the digits' own rows of X from the NTT-domain sources
+void kb_own_rows(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, hipStream_t st);
 // T [M][2][Lc+K][n] = sum_j X[xidx_m][j] (rotated by k_m if hoisted) * key_m[j]
 void kb_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const KsJob* jobs, int M, int Lc, bool hoisted,
               hipStream_t st);
@@ -268,6 +275,11 @@ void k_diag_tile(const Ctx& c, uint64_t* out, const uint64_t* in, size_t i0, int
                  uint32_t B, uint32_t dG, int Lc, hipStream_t st);
 // words v -> (v >> h) 2^32 + (v mod 2^h), h = ceil(bits of the largest of the first Lc primes / 2)
 void k_diag_split(const Ctx& c, uint64_t* d, size_t words, int Lc, hipStream_t st);
+// TA[g] += sum of the jobs' key products T, C0A[g] += sum of their rotated c0, per range
+void kb_accum(const Ctx& c, uint64_t* TA, uint64_t* C0A, const uint64_t* T, const KsJob* jobs,
+              const KsGroupRange* ranges, int nranges, int Lc, hipStream_t st);
+// p[0..words) = 0 (a kernel, so it can sit in a captured graph)
+void k_zero(const Ctx& c, uint64_t* p, size_t words, hipStream_t st);
 // Rt[r][tile][pp][j][2][64] (split) from the pointer table R[pp][j] (j < J; nullptr: zeros)
 void k_diag_gather(const Ctx& c, uint64_t* Rt, const uint64_t* const* R, int npairs, int J, int Lc,
                    hipStream_t st);

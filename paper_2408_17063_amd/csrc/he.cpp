@@ -106,6 +106,26 @@ KsScratch ks_scratch(Ctx& c, Arena& a, int Lc, int max_jobs) {
     return s;
 }
 
+// Raise U sources for key switching at level Lc: c1 (rotated by the job's element
+// if permute), ModUp into dn digits over PQ, NTT domain. Each digit's own rows are
+// copied in the NTT domain before the inverse transform; only the rows ModUp
+// computes are transformed forward.
+static void ks_raise(Ctx& c, KsScratch& s, const KsJob* d, int U, int Lc, bool permute, hipStream_t st) {
+    const size_t n = c.n;
+    const int R = Lc + c.K, dn = Lc / c.alpha, a = c.alpha;
+    kb_take_c1(c, s.tmpC, d, U, Lc, permute, st);
+    kb_own_rows(c, s.X, s.tmpC, U, Lc, st);
+    ntt64(c, s.tmpC, (size_t)Lc * n, U, 0, Lc, true, st);
+    kb_modup(c, s.X, s.tmpC, U, Lc, false, st);
+    for (int j = 0; j < dn; j++) {
+        uint64_t* Xj = s.X + (size_t)j * R * n;
+        if (j > 0) ntt64(c, Xj, (size_t)dn * R * n, U, 0, j * a, false, st);
+        if ((j + 1) * a < Lc)
+            ntt64(c, Xj + (size_t)(j + 1) * a * n, (size_t)dn * R * n, U, (j + 1) * a, Lc - (j + 1) * a, false, st);
+    }
+    ntt64(c, s.X + (size_t)Lc * n, (size_t)R * n, U * dn, c.L, c.K, false, st);
+}
+
 // Rotations at level Lc. Plain (srcs == nullptr): each job raises its own rotated c1.
 // Hoisted: srcs[u] are raised once (unrotated) and every job with xidx = u rotates
 // the raised digits instead. Jobs are processed in passes of at most maxM.
@@ -114,13 +134,7 @@ hc_status ks_run(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
     if (!s.tmpC || !s.X || !s.T || !s.conv) return HC_ENOMEM;
     const size_t n = c.n;
     const int R = Lc + c.K, dn = Lc / c.alpha;
-    auto raise = [&](const KsJob* d, int U, bool permute) {
-        kb_take_c1(c, s.tmpC, d, U, Lc, permute, st);
-        ntt64(c, s.tmpC, (size_t)Lc * n, U, 0, Lc, true, st);
-        kb_modup(c, s.X, s.tmpC, U, Lc, st);
-        ntt64(c, s.X, (size_t)R * n, U * dn, 0, Lc, false, st);
-        ntt64(c, s.X + (size_t)Lc * n, (size_t)R * n, U * dn, c.L, c.K, false, st);
-    };
+    auto raise = [&](const KsJob* d, int U, bool permute) { ks_raise(c, s, d, U, Lc, permute, st); };
     auto finish = [&](const KsJob* d, int M, bool hoisted) {
         kb_inner(c, s.T, s.X, d, M, Lc, hoisted, st);
         ntt64(c, s.T + (size_t)Lc * n, (size_t)R * n, 2 * M, c.L, c.K, true, st);
@@ -161,6 +175,51 @@ hc_status ks_run(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
             if (!d) return HC_ENOMEM;
             finish(d, M, true);
         }
+    }
+    return HC_OK;
+}
+
+// Sums of plain rotations, one ModDown per sum: for each group g, outs[g] = sum of
+// Rot_k(in) over the jobs with group[i] == g, whose key products are added over PQ
+// (TA, groups x [2][Lc+K][n]) and whose rotated c0 are added (C0A, groups x [Lc][n])
+// before a single ModDown. Jobs must be ordered by group.
+hc_status ks_run_sum(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
+                     const std::vector<uint32_t>& group, const std::vector<uint64_t*>& outs, uint64_t* TA,
+                     uint64_t* C0A, int Lc, hipStream_t st) {
+    if (!s.tmpC || !s.X || !s.T || !s.conv || !TA || !C0A || group.size() != jobs.size()) return HC_ENOMEM;
+    const size_t n = c.n, G = outs.size();
+    const int R = Lc + c.K;
+    k_zero(c, TA, G * 2 * (size_t)R * n, st);
+    k_zero(c, C0A, G * (size_t)Lc * n, st);
+    for (size_t m0 = 0; m0 < jobs.size(); m0 += s.maxM) {
+        const int M = (int)std::min<size_t>(s.maxM, jobs.size() - m0);
+        std::vector<KsJob> jb(jobs.begin() + m0, jobs.begin() + m0 + M);
+        for (int i = 0; i < M; i++) jb[i].xidx = (uint32_t)i;
+        std::vector<KsGroupRange> rg;
+        for (int i = 0; i < M; i++) {
+            const uint32_t g = group[m0 + i];
+            if (rg.empty() || rg.back().g != g) rg.push_back(KsGroupRange{g, (uint32_t)i, (uint32_t)i + 1, 0});
+            else rg.back().j1 = (uint32_t)i + 1;
+        }
+        const KsJob* d = (const KsJob*)stage_bytes(l, jb.data(), sizeof(KsJob) * M, st);
+        const KsGroupRange* dr = (const KsGroupRange*)stage_bytes(l, rg.data(), sizeof(KsGroupRange) * rg.size(), st);
+        if (!d || !dr) return HC_ENOMEM;
+        ks_raise(c, s, d, M, Lc, true, st);
+        kb_inner(c, s.T, s.X, d, M, Lc, false, st);
+        kb_accum(c, TA, C0A, s.T, d, dr, (int)rg.size(), Lc, st);
+    }
+    // one ModDown per group (TA is consumed in place)
+    for (size_t g0 = 0; g0 < G; g0 += s.maxM) {
+        const int Mg = (int)std::min<size_t>(s.maxM, G - g0);
+        uint64_t* T = TA + g0 * 2 * (size_t)R * n;
+        std::vector<KsJob> fj(Mg);
+        for (int i = 0; i < Mg; i++) fj[i] = KsJob{C0A + (g0 + i) * (size_t)Lc * n, outs[g0 + i], nullptr, 1u, 0u};
+        const KsJob* df = (const KsJob*)stage_bytes(l, fj.data(), sizeof(KsJob) * Mg, st);
+        if (!df) return HC_ENOMEM;
+        ntt64(c, T + (size_t)Lc * n, (size_t)R * n, 2 * Mg, c.L, c.K, true, st);
+        kb_conv(c, s.conv, T, Mg, Lc, st);
+        ntt64(c, s.conv, (size_t)Lc * n, 2 * Mg, 0, Lc, false, st);
+        kb_final(c, df, T, s.conv, Mg, Lc, st);
     }
     return HC_OK;
 }
@@ -513,7 +572,7 @@ extern "C" hc_status hc_modup(hc_context* cp, const uint64_t* x, uint32_t digit,
     uint64_t* X = c.lane.ws.take<uint64_t>((size_t)c.dnum * R * n);
     if (!X) return HC_ENOMEM;
     // x is [L][n], the compact layout of one source at the top level
-    kb_modup(c, X, x, 1, c.L, st);
+    kb_modup(c, X, x, 1, c.L, true, st);
     HC_CHECK(hipMemcpyAsync(out, X + (size_t)digit * R * n, sizeof(uint64_t) * R * n,
                             hipMemcpyDeviceToDevice, st));
     HC_CHECK(hipStreamSynchronize(st));

@@ -25,6 +25,10 @@ size_t ks_scratch_bytes(const Ctx& c, int Lc, int max_jobs);
 KsScratch ks_scratch(Ctx& c, Arena& a, int Lc, int max_jobs);
 hc_status ks_run(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
                  const std::vector<const uint64_t*>* srcs, int Lc, hipStream_t st);
+// sums of rotations with one ModDown per sum (see ks_run_sum in he.cpp)
+hc_status ks_run_sum(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
+                     const std::vector<uint32_t>& group, const std::vector<uint64_t*>& outs, uint64_t* TA,
+                     uint64_t* C0A, int Lc, hipStream_t st);
 hc_status ew_run(Ctx& c, Lane& l, const std::vector<EwJob>& jobs, int Lc, bool mul, hipStream_t st);
 // drop the primes Lc..L-1 of `count` contiguous top-level ciphertexts (NTT domain)
 hc_status mod_switch_batch(Ctx& c, uint64_t* out, uint64_t* in, int count, int Lc, uint64_t* conv,

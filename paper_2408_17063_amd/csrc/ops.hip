@@ -147,7 +147,7 @@ void kb_take_c1(const Ctx& c, uint64_t* tmpC, const KsJob* jobs, int M, int Lc, 
 __global__ void kb_modup_kernel(uint64_t* __restrict__ X, const uint64_t* __restrict__ tmpC,
                                 const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv,
                                 const uint64_t* __restrict__ inv, const uint64_t* __restrict__ cst,
-                                int n, int nq, int alpha, int L, int Lc, int K, int dn) {
+                                int n, int nq, int alpha, int L, int Lc, int K, int dn, int own) {
     int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     const int j = blockIdx.y, u = blockIdx.z, R = Lc + K;
@@ -157,7 +157,7 @@ __global__ void kb_modup_kernel(uint64_t* __restrict__ X, const uint64_t* __rest
     for (int a = 0; a < alpha; a++) {
         const int r = j * alpha + a;
         const uint64_t v = src[(size_t)r * n + x];
-        out[(size_t)r * n + x] = v;
+        if (own) out[(size_t)r * n + x] = v;
         const uint64_t* iv = inv + ((size_t)j * alpha + a) * 2;
         y[a] = shoup(v, iv[0], iv[1], mods[r]);
     }
@@ -171,13 +171,30 @@ __global__ void kb_modup_kernel(uint64_t* __restrict__ X, const uint64_t* __rest
     }
 }
 
-void kb_modup(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, hipStream_t st) {
+void kb_modup(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, bool own_rows, hipStream_t st) {
     const int dn = Lc / c.alpha, R = Lc + c.K;
     const double n = c.n;
-    TimeScope ts(c, HC_KT_MODUP, st, 8.0 * n * U * ((double)Lc + (double)dn * R),
+    TimeScope ts(c, HC_KT_MODUP, st,
+                 8.0 * n * U * ((double)Lc + (double)dn * (R - (own_rows ? 0 : c.alpha))),
                  n * U * dn * (double)(R - c.alpha) * c.alpha);
     hipLaunchKernelGGL(kb_modup_kernel, ew_grid(c.n, dn, U), dim3(EW_THREADS), 0, st, X, tmpC, c.d_mods,
-                       c.d_qinv, c.d_modup_inv, c.d_modup_c, c.n, c.nq, c.alpha, c.L, Lc, c.K, dn);
+                       c.d_qinv, c.d_modup_inv, c.d_modup_c, c.n, c.nq, c.alpha, c.L, Lc, c.K, dn,
+                       own_rows ? 1 : 0);
+}
+
+// X[u][j][r] = tmpC[u][r] for the rows r of digit j = r / alpha (its own primes), in
+// the NTT domain: ModUp leaves a digit's own residues unchanged, so their transform
+// is the input's.
+__global__ void kb_own_rows_kernel(uint64_t* __restrict__ X, const uint64_t* __restrict__ tmpC, int n,
+                                   int alpha, int Lc, int R, int dn) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int r = blockIdx.y, u = blockIdx.z, j = r / alpha;
+    X[(((size_t)u * dn + j) * R + r) * n + x] = tmpC[((size_t)u * Lc + r) * n + x];
+}
+void kb_own_rows(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, hipStream_t st) {
+    hipLaunchKernelGGL(kb_own_rows_kernel, ew_grid(c.n, Lc, U), dim3(EW_THREADS), 0, st, X, tmpC, c.n, c.alpha,
+                       Lc, Lc + c.K, Lc / c.alpha);
 }
 
 // T[m][comp][row][x] = sum_j X[xidx][j][row][src(x)] * key_m[j][comp][prime(row)][x]; the key is
@@ -264,6 +281,55 @@ void kb_final(const Ctx& c, const KsJob* jobs, const uint64_t* T, const uint64_t
               hipStream_t st) {
     hipLaunchKernelGGL(kb_final_kernel, ew_grid(c.n, Lc, M), dim3(EW_THREADS), 0, st, jobs, T, conv,
                        c.d_mods, c.d_pinv, c.n, c.logn, Lc, c.K);
+}
+
+// Sums of key-switched rotations brought down once: the key products T of the jobs
+// [j0, j1) of each group are added into TA[g] ([2][Lc+K][n], mod each row's prime)
+// and their rotated c0 into C0A[g] ([Lc][n]). Rows 0..2R-1 are T's, then Lc rows of c0.
+__global__ void kb_accum_kernel(uint64_t* __restrict__ TA, uint64_t* __restrict__ C0A,
+                                const uint64_t* __restrict__ T, const KsJob* __restrict__ jobs,
+                                const KsGroupRange* __restrict__ ranges, const uint64_t* __restrict__ mods,
+                                int n, int logn, int L, int Lc, int K) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int row = blockIdx.y, R = Lc + K;
+    const KsGroupRange gr = ranges[blockIdx.z];
+    if (row < 2 * R) {
+        const int comp = row / R, rr = row - comp * R;
+        const uint64_t q = mods[row_prime(rr, Lc, L)];
+        uint64_t* ta = TA + (((size_t)gr.g * 2 + comp) * R + rr) * n + x;
+        uint64_t acc = *ta;
+        for (uint32_t m = gr.j0; m < gr.j1; m++) acc = add_mod(acc, T[(((size_t)m * 2 + comp) * R + rr) * n + x], q);
+        *ta = acc;
+    } else {
+        const int i = row - 2 * R;
+        const uint64_t q = mods[i];
+        uint64_t* ca = C0A + ((size_t)gr.g * Lc + i) * n + x;
+        uint64_t acc = *ca;
+        for (uint32_t m = gr.j0; m < gr.j1; m++) {
+            const KsJob jb = jobs[m];
+            const uint32_t src = (jb.k == 1) ? x : galois_src(x, jb.k, logn);
+            acc = add_mod(acc, jb.in[(size_t)i * n + src], q);
+        }
+        *ca = acc;
+    }
+}
+
+void kb_accum(const Ctx& c, uint64_t* TA, uint64_t* C0A, const uint64_t* T, const KsJob* jobs,
+              const KsGroupRange* ranges, int nranges, int Lc, hipStream_t st) {
+    const int R = Lc + c.K;
+    hipLaunchKernelGGL(kb_accum_kernel, ew_grid(c.n, 2 * R + Lc, nranges), dim3(EW_THREADS), 0, st, TA, C0A, T,
+                       jobs, ranges, c.d_mods, c.n, c.logn, c.L, Lc, c.K);
+}
+
+__global__ void zero_words_kernel(uint64_t* __restrict__ p, size_t words) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < words) p[i] = 0;
+}
+
+void k_zero(const Ctx& c, uint64_t* p, size_t words, hipStream_t st) {
+    (void)c;
+    if (words) hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st, p, words);
 }
 
 // y[g] = sum_{t < cnt} src[g][t] for `groups` groups of `cnt` ciphertexts (stride CW words
