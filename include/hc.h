@@ -61,7 +61,7 @@ typedef struct {
     uint32_t log_n;   /* ring degree n = 2^log_n, 10 <= log_n <= 16 */
     uint64_t p;       /* plaintext prime, p = 1 mod 2n, p < 2^30 */
     uint32_t L;       /* ciphertext primes */
-    uint32_t q_bits;  /* bit size bound of the ciphertext primes, <= 61 */
+    uint32_t q_bits;  /* bit size bound of the ciphertext primes, 30..60 */
     uint32_t K;       /* special primes (= primes per key-switching digit); L % K == 0 */
     uint32_t p_bits;  /* bit size bound of the special primes, <= 61 */
 } hc_params;

@@ -205,7 +205,9 @@ hc_status batch_shape(const Ctx& c, const hc_gk* gk, const hc_db* db, std::vecto
         diag_max = std::max(diag_max, (size_t)kb * Gc * B);
     }
     size_t rt_max = 1;  // gathered rotated ciphertexts of one class
-    for (auto& kv : cls_k) rt_max = std::max(rt_max, (size_t)cls_np[kv.first] * kv.second * kv.first.second * 2 * PW);
+    for (auto& kv : cls_k)
+        rt_max = std::max(rt_max, (size_t)cls_np[kv.first] * diag_terms_padded((int)(kv.second * kv.first.second)) *
+                                      2 * PW);
     size_t sum_groups = 0;  // giant-step sums (one per pair)
     for (auto& q : qs) sum_groups += (size_t)q.npairs;
     const size_t R = (size_t)Lc + c.K;

@@ -177,7 +177,7 @@ extern "C" hc_status hc_context_create(const hc_params* prm, int device, hc_cont
     *out = nullptr;
     if (prm->log_n < 10 || prm->log_n > 16) return HC_EINVAL;
     if (prm->K < 1 || prm->K > 4 || prm->L < 1 || prm->L % prm->K) return HC_EINVAL;
-    if (prm->q_bits < 30 || prm->q_bits > 61 || prm->p_bits < 30 || prm->p_bits > 61) return HC_EINVAL;
+    if (prm->q_bits < 30 || prm->q_bits > 60 || prm->p_bits < 30 || prm->p_bits > 61) return HC_EINVAL;
     const uint64_t n = 1ull << prm->log_n;
     if (prm->p >= (1ull << 26) || (prm->p - 1) % (2 * n) != 0 || !is_prime_u64(prm->p)) return HC_EINVAL;
     if (prm->L + prm->K > 64) return HC_EINVAL;

@@ -258,8 +258,9 @@ void k_enc_finish(const Ctx& c, uint64_t* ct, const uint64_t* e0, const uint64_t
 // R, A given as device arrays of ciphertext pointers; D contiguous
 // [kb][G][B][L][n] (Montgomery). accumulate: add to the existing A.
 // Giant indices per wave of the diagonal multiply-accumulate (and per chunk of the
-// resident tables' layout).
+// resident tables' layout), and terms per LDS stage.
 constexpr int DIAG_GC = 8;
+constexpr int DIAG_T = 4;
 // Word strides of a diagonal table (split words, see k_diag_split): D(beta, g, b) of
 // limb r at coefficient 64 tile + lane, term j = beta B + b, giant g = DIAG_GC c + i, is
 // D[r sr + tile st + c sgc + j sj + i sg + lane].
@@ -280,7 +281,11 @@ void kb_accum(const Ctx& c, uint64_t* TA, uint64_t* C0A, const uint64_t* T, cons
               const KsGroupRange* ranges, int nranges, int Lc, hipStream_t st);
 // p[0..words) = 0 (a kernel, so it can sit in a captured graph)
 void k_zero(const Ctx& c, uint64_t* p, size_t words, hipStream_t st);
-// Rt[r][tile][pp][j][2][64] (split) from the pointer table R[pp][j] (j < J; nullptr: zeros)
+// terms of the gathered rotated ciphertexts per pair: J rounded up to whole rounds of
+// the multiply-accumulate (two stages of DIAG_T terms)
+inline int diag_terms_padded(int J) { return (J + 2 * DIAG_T - 1) / (2 * DIAG_T) * (2 * DIAG_T); }
+// Rt[r][tile][pp][j][2][64] (split) from the pointer table R[pp][j] (j < J; nullptr and
+// J <= j < diag_terms_padded(J): zeros)
 void k_diag_gather(const Ctx& c, uint64_t* Rt, const uint64_t* const* R, int npairs, int J, int Lc,
                    hipStream_t st);
 // A[pp][g] (=|+=) sum_{j<J} D(j, g) R[pp][j], g < ga, for npairs pairs: A pointers

@@ -711,7 +711,7 @@ hc_status upload_keccak_constants(const uint64_t rc[24], const uint32_t rho[25],
 // D(beta, g, b) for limb r at coefficient 64 tile + lane, g = GC c + i (giant chunk c,
 // i < GC), is D[r sr + tile st + c sgc + j sj + i sg + lane].
 struct DiagMacArgs {
-    int n, L, J, ga, npairs, wp, npg, ngc, ntiles;
+    int n, L, J, Jp, ga, npairs, wp, npg, ngc, ntiles;
     uint32_t work, per_xcd;
     size_t sr, st, sgc, sj, sg;
     int chunk, h, accumulate;
@@ -721,50 +721,60 @@ __device__ __forceinline__ uint64_t split_word(uint64_t v, int h) {
     return ((v >> h) << 32) | (v & ((1ull << h) - 1));
 }
 
-// Rt[r][tile][pp][j][k][64] = R[pp][j] component k at (r, 64 tile + lane), split;
-// nullptr -> 0.
+// Rt[r][tile][pp][j][k][64] = R[pp][j] component k at (r, 64 tile + lane), split, for
+// j < Jp (a multiple of 3 >= J); nullptr and j >= J -> 0.
 __global__ void diag_gather_kernel(uint64_t* __restrict__ Rt, const uint64_t* const* __restrict__ R, int n,
-                                   int L, int J, int npairs, int pj0, int h) {
+                                   int L, int J, int Jp, int npairs, int pj0, int h) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     const int r = blockIdx.y;
-    const int pj = pj0 + (int)blockIdx.z;  // pp * J + j
-    const uint64_t* rp = R[pj];
+    const int pj = pj0 + (int)blockIdx.z;  // pp * Jp + j
+    const int pp = pj / Jp, j = pj - pp * Jp;
+    const uint64_t* rp = j < J ? R[(size_t)pp * J + j] : nullptr;
     const size_t ln = (size_t)L * n;
     const size_t src = (size_t)r * n + x;
     const uint64_t v0 = rp ? rp[src] : 0, v1 = rp ? rp[ln + src] : 0;
-    const size_t o = (((size_t)r * (n / 64) + (size_t)(x / 64)) * ((size_t)npairs * J) + pj) * 128 + (x & 63);
+    const size_t o = (((size_t)r * (n / 64) + (size_t)(x / 64)) * ((size_t)npairs * Jp) + pj) * 128 + (x & 63);
     Rt[o] = split_word(v0, h);
     Rt[o + 64] = split_word(v1, h);
 }
 
-// Loads run three terms ahead: the loads of term j + 2 are issued before the
-// products of term j, so every wave keeps two terms of loads in flight while it
-// computes. Loads past the last term re-read it (addresses stay in bounds; those
-// values are never used).
-template <int GC>
+// The diagonals of a block are read from device memory once and shared through LDS:
+// every wave of a block (the block's ciphertext pairs, plus helper waves up to 4)
+// loads 16-byte pieces of the next T terms' diagonal words into registers while the
+// pair waves multiply the current T terms out of LDS; the pieces then go to the other
+// LDS buffer and one barrier per stage flips the buffers. Each pair wave's rotated
+// ciphertexts for the next stage are loaded alongside into a second register set.
+// The loop covers Jp terms (a multiple of 2 T; terms past J have zero rotated
+// ciphertexts) in pairs of stages, with no exit in between.
+template <int GC, int T>
 __global__ __launch_bounds__(512) void diag_mac_kernel(uint64_t* const* __restrict__ A,
-                                                            const uint64_t* __restrict__ Rt,
-                                                            const uint64_t* __restrict__ D,
-                                                            const uint64_t* __restrict__ mods,
-                                                            const uint64_t* __restrict__ qinv,
-                                                            const uint64_t* __restrict__ r2, DiagMacArgs a) {
+                                                           const uint64_t* __restrict__ Rt,
+                                                           const uint64_t* __restrict__ D,
+                                                           const uint64_t* __restrict__ mods,
+                                                           const uint64_t* __restrict__ qinv,
+                                                           const uint64_t* __restrict__ r2, DiagMacArgs a) {
+    constexpr int CH = T * GC * 32;        // 16-byte pieces per stage
+    constexpr int MAXC = (CH + 255) / 256;  // per thread (blocks have >= 256 threads)
+    __shared__ uint64_t lds[2][T][GC][64];
     const uint32_t bid = blockIdx.x;
     const uint32_t wk = (bid & 7u) * a.per_xcd + (bid >> 3);
-    if (wk >= a.work) return;
+    if (wk >= a.work) return;  // uniform over the block
     uint32_t t = wk;
     const int gci = (int)(t % (uint32_t)a.ngc); t /= (uint32_t)a.ngc;
     const int pg = (int)(t % (uint32_t)a.npg); t /= (uint32_t)a.npg;
     const int tile = (int)(t % (uint32_t)a.ntiles);
     const int r = (int)(t / (uint32_t)a.ntiles);
-    const int pp = pg * a.wp + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    if (pp >= a.npairs) return;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int pp = pg * a.wp + w;
+    const bool active = w < a.wp && pp < a.npairs;  // wave-uniform
     const int lane = (int)(threadIdx.x & 63);
+    const int nthr = (int)blockDim.x;
     const uint64_t q = mods[r], qi = qinv[r], q2 = r2[r];
     const int g0 = gci * GC;
     const int gc = (a.ga - g0) < GC ? (a.ga - g0) : GC;
     const int h = a.h;
-    const int J = a.J;
+    const int J = a.J, Jp = a.Jp;
 
     uint64_t lo[GC][2], mid[GC][2], hi[GC][2];
     #pragma unroll
@@ -777,70 +787,104 @@ __global__ __launch_bounds__(512) void diag_mac_kernel(uint64_t* const* __restri
         for (int g = 0; g < GC; g++)
             #pragma unroll
             for (int k = 0; k < 2; k++) {
-                u128p T{lo[g][k], 0};
-                add128(T, u128p{mid[g][k] << h, mid[g][k] >> (64 - h)});
-                add128(T, u128p{hi[g][k] << (2 * h), hi[g][k] >> (64 - 2 * h)});
-                const uint64_t v = redc(T, q, qi);
+                u128p T2{lo[g][k], 0};
+                add128(T2, u128p{mid[g][k] << h, mid[g][k] >> (64 - h)});
+                add128(T2, u128p{hi[g][k] << (2 * h), hi[g][k] >> (64 - 2 * h)});
+                const uint64_t v = redc(T2, q, qi);
                 lo[g][k] = last ? v : mont_mul(v, q2, q, qi);
                 mid[g][k] = hi[g][k] = 0;
             }
     };
 
-    const uint64_t* Rb = Rt + (((size_t)r * a.ntiles + tile) * a.npairs + pp) * (size_t)J * 128 + lane;
-    const uint64_t* Db = D + (size_t)r * a.sr + (size_t)tile * a.st + (size_t)gci * a.sgc + lane;
-    size_t gofs[GC];
-    #pragma unroll
-    for (int g = 0; g < GC; g++) gofs[g] = (size_t)(g < gc ? g : gc - 1) * a.sg;
-
-    // the three slots are indexed only by compile-time constants (registers, never memory)
-    uint64_t rv[3][2], dv[3][GC];
-    auto load = [&](int j, auto slot_c) __attribute__((always_inline)) {
-        constexpr int slot = decltype(slot_c)::value;
-        const int jj = j < J ? j : J - 1;
-        const uint64_t* rp = Rb + (size_t)jj * 128;
-        rv[slot][0] = rp[0];
-        rv[slot][1] = rp[64];
-        const uint64_t* dp = Db + (size_t)jj * a.sj;
+    const uint64_t* Rb = Rt + (((size_t)r * a.ntiles + tile) * a.npairs + (active ? pp : 0)) * (size_t)Jp * 128 + lane;
+    const uint64_t* Db = D + (size_t)r * a.sr + (size_t)tile * a.st + (size_t)(g0 / DIAG_GC) * a.sgc +
+                          (size_t)(g0 % DIAG_GC) * a.sg;
+    // staging piece c: term c / (32 GC), giant (c / 32) % GC, words 2 (c % 32), +1 of the lane row
+    uint64_t dv[MAXC][2];
+    auto issue = [&](int j0) __attribute__((always_inline)) {
         #pragma unroll
-        for (int g = 0; g < GC; g++) dv[slot][g] = dp[gofs[g]];
+        for (int k = 0; k < MAXC; k++) {
+            const int c = (int)threadIdx.x + k * nthr;
+            const int tt = c / (32 * GC), g = (c / 32) % GC, qd = c % 32;
+            const int jd = (j0 + tt) < J ? (j0 + tt) : J - 1;
+            const int gg = g < gc ? g : gc - 1;
+            const uint64_t* src = Db + (size_t)jd * a.sj + (size_t)gg * a.sg + 2 * qd;
+            if (c < CH) {
+                dv[k][0] = src[0];
+                dv[k][1] = src[1];
+            }
+        }
+    };
+    auto commit = [&](int buf) __attribute__((always_inline)) {
+        #pragma unroll
+        for (int k = 0; k < MAXC; k++) {
+            const int c = (int)threadIdx.x + k * nthr;
+            const int tt = c / (32 * GC), g = (c / 32) % GC, qd = c % 32;
+            if (c < CH) {
+                lds[buf][tt][g][2 * qd] = dv[k][0];
+                lds[buf][tt][g][2 * qd + 1] = dv[k][1];
+            }
+        }
+    };
+    uint64_t rv[2][T][2];
+    auto loadR = [&](int j0, auto slot_c) __attribute__((always_inline)) {
+        constexpr int slot = decltype(slot_c)::value;
+        if (active) {
+            #pragma unroll
+            for (int u = 0; u < T; u++) {
+                const int jr = (j0 + u) < Jp ? (j0 + u) : Jp - 1;
+                rv[slot][u][0] = Rb[(size_t)jr * 128];
+                rv[slot][u][1] = Rb[(size_t)jr * 128 + 64];
+            }
+        }
     };
     int terms = 0;
-    auto step = [&](auto slot_c) __attribute__((always_inline)) {
+    auto compute = [&](int buf, auto slot_c) __attribute__((always_inline)) {
         constexpr int slot = decltype(slot_c)::value;
-        const uint32_t r0l = (uint32_t)rv[slot][0], r0h = (uint32_t)(rv[slot][0] >> 32);
-        const uint32_t r1l = (uint32_t)rv[slot][1], r1h = (uint32_t)(rv[slot][1] >> 32);
-        #pragma unroll
-        for (int g = 0; g < GC; g++) {
-            const uint32_t dl = (uint32_t)dv[slot][g], dh = (uint32_t)(dv[slot][g] >> 32);
-            lo[g][0] += (uint64_t)r0l * dl;
-            mid[g][0] += (uint64_t)r0l * dh;
-            mid[g][0] += (uint64_t)r0h * dl;
-            hi[g][0] += (uint64_t)r0h * dh;
-            lo[g][1] += (uint64_t)r1l * dl;
-            mid[g][1] += (uint64_t)r1l * dh;
-            mid[g][1] += (uint64_t)r1h * dl;
-            hi[g][1] += (uint64_t)r1h * dh;
-        }
-        if (++terms == a.chunk) {
+        if (!active) return;
+        if (terms + T > a.chunk) {
             fold(false);
             terms = 0;
         }
+        #pragma unroll
+        for (int u = 0; u < T; u++) {
+            const uint32_t r0l = (uint32_t)rv[slot][u][0], r0h = (uint32_t)(rv[slot][u][0] >> 32);
+            const uint32_t r1l = (uint32_t)rv[slot][u][1], r1h = (uint32_t)(rv[slot][u][1] >> 32);
+            #pragma unroll
+            for (int g = 0; g < GC; g++) {
+                const uint64_t d = lds[buf][u][g][lane];
+                const uint32_t dl = (uint32_t)d, dh = (uint32_t)(d >> 32);
+                lo[g][0] += (uint64_t)r0l * dl;
+                mid[g][0] += (uint64_t)r0l * dh;
+                mid[g][0] += (uint64_t)r0h * dl;
+                hi[g][0] += (uint64_t)r0h * dh;
+                lo[g][1] += (uint64_t)r1l * dl;
+                mid[g][1] += (uint64_t)r1l * dh;
+                mid[g][1] += (uint64_t)r1h * dl;
+                hi[g][1] += (uint64_t)r1h * dh;
+            }
+        }
+        terms += T;
     };
     using S0 = std::integral_constant<int, 0>;
     using S1 = std::integral_constant<int, 1>;
-    using S2 = std::integral_constant<int, 2>;
-    load(0, S0{});
-    load(1, S1{});
-    for (int j = 0; j < J; j += 3) {
-        load(j + 2, S2{});
-        step(S0{});
-        if (j + 1 >= J) break;
-        load(j + 3, S0{});
-        step(S1{});
-        if (j + 2 >= J) break;
-        load(j + 4, S1{});
-        step(S2{});
+    issue(0);
+    loadR(0, S0{});
+    commit(0);
+    __syncthreads();
+    for (int j0 = 0; j0 < Jp; j0 += 2 * T) {
+        issue(j0 + T);
+        loadR(j0 + T, S1{});
+        compute(0, S0{});
+        commit(1);
+        __syncthreads();
+        issue(j0 + 2 * T);
+        loadR(j0 + 2 * T, S0{});
+        compute(1, S1{});
+        commit(0);
+        __syncthreads();
     }
+    if (!active) return;
     fold(true);
     const size_t ln = (size_t)a.L * a.n;
     const size_t off = (size_t)r * a.n + (size_t)tile * 64 + lane;
@@ -906,11 +950,12 @@ void k_diag_split(const Ctx& c, uint64_t* d, size_t words, int Lc, hipStream_t s
 
 void k_diag_gather(const Ctx& c, uint64_t* Rt, const uint64_t* const* R, int npairs, int J, int Lc,
                    hipStream_t st) {
-    const int total = npairs * J;
+    const int Jp = diag_terms_padded(J);
+    const int total = npairs * Jp;
     const int h = diag_split_h(c, Lc);
     for (int pj0 = 0; pj0 < total; pj0 += 65535)
         hipLaunchKernelGGL(diag_gather_kernel, ew_grid(c.n, Lc, std::min(65535, total - pj0)), dim3(EW_THREADS), 0,
-                           st, Rt, R, c.n, Lc, J, npairs, pj0, h);
+                           st, Rt, R, c.n, Lc, J, Jp, npairs, pj0, h);
 }
 
 void k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* Rt, const uint64_t* D,
@@ -923,9 +968,10 @@ void k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* Rt, const uint
     a.n = c.n;
     a.L = Lc;
     a.J = J;
+    a.Jp = diag_terms_padded(J);
     a.ga = ga;
     a.npairs = npairs;
-    a.wp = npairs < 8 ? npairs : 8;
+    a.wp = npairs < 4 ? npairs : 4;  // pairs per block (4 waves; two blocks fit a CU)
     a.npg = (npairs + a.wp - 1) / a.wp;
     a.ngc = (ga + GC - 1) / GC;
     a.ntiles = c.n / 64;
@@ -938,14 +984,14 @@ void k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* Rt, const uint
     a.sj = lay.sj;
     a.sg = lay.sg;
     a.h = h;
-    a.chunk = diag_chunk(bits, h, qmax);
+    a.chunk = diag_chunk(bits, h, qmax);  // >= 8 for primes below 2^60 (folds come every DIAG_T terms)
     a.accumulate = accumulate ? 1 : 0;
     const double ln = (double)Lc * c.n;
     // reads each R (both components) and each D once, writes each A once
     TimeScope ts(c, HC_KT_DIAG_MAC, st,
                  8.0 * ln * (2.0 * npairs * J + (double)J * ga + (accumulate ? 4.0 : 2.0) * npairs * ga),
                  2.0 * ln * npairs * J * ga);
-    hipLaunchKernelGGL((diag_mac_kernel<GC>), dim3(a.per_xcd * 8), dim3(64 * a.wp), 0, st, A, Rt, D, c.d_mods,
+    hipLaunchKernelGGL((diag_mac_kernel<GC, DIAG_T>), dim3(a.per_xcd * 8), dim3(256), 0, st, A, Rt, D, c.d_mods,
                        c.d_qinv, c.d_r2, a);
 }
 
