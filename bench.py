@@ -90,6 +90,26 @@ def kernel_rooflines(ctx, hc):
     return rl
 
 
+def measured_traffic(workload):
+    """HBM bytes per launch from the committed counter summary of this workload
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), per kernel class;
+    empty when the summary is missing or the kernels' sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        log("traffic summary is stale (kernel sources changed): traffic reported as null")
+        return {}
+    return {k: v["traffic_bytes_per_launch"] for k, v in rec["kernels"].items()}
+
+
 def cpu_baseline(info):
     """The CPU oracle on a bounded sample of the same workload, scaled by the step's
     operation counts. The oracle runs the same schedule as the library: Mask at the
@@ -497,6 +517,9 @@ def main():
     log("timed %d steps: %.1f ms/step (events), wall %.2fs" % (args.steps, ms_per_step, wall))
     rl = kernel_rooflines(ctx, hc)
     ctx.timing(False)
+    for name, tb in measured_traffic(args.workload).items():
+        if name in rl:
+            rl[name]["traffic"] = tb
     if args.copy_probe_mb:
         ctx.probe_copy(args.copy_probe_mb << 20)
     for name, r in rl.items():
