@@ -356,8 +356,8 @@ def serving(st, rates, requests, lane_gb=40, lanes=2, max_batch=16):
     diagonal tables of every class stay resident; the server admits requests by
     workspace footprint and batches them continuously on two streams. Latency is
     scheduled arrival -> result final on the device, as seen by the host. Each rate
-    is a fraction of the plain (one query at a time) capacity measured on the same
-    mix."""
+    is a fraction of the plain (one query at a time, back to back) throughput of the
+    same request list, measured just before it is served."""
     import numpy as np
     import torch
     import workloads as W
@@ -393,32 +393,33 @@ def serving(st, rates, requests, lane_gb=40, lanes=2, max_batch=16):
         ts = np.rint(np.exp(rng.uniform(np.log(16), np.log(1024), size=count))).astype(int)
         return [(int(N), int(t), pool[int(N)][i % 3]) for i, (N, t) in enumerate(zip(Ns, ts))]
 
-    # plain capacity on the same mix: one query at a time, back to back
-    mix = draw(30)
     out = ctx.ct_tensor(1)[0]
-    for N, t, cts in mix[:3]:
-        ctx.compress(gk, st["db"], cts, N, t, out=out)
-    torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for N, t, cts in mix:
-        ctx.compress(gk, st["db"], cts, N, t, out=out)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    plain_ms = e0.elapsed_time(e1) / len(mix)
-    capacity = 1e3 / plain_ms
-    log("plain capacity on the serving mix: %.2f ms per query, %.2f queries/s" % (plain_ms, capacity))
+
+    def plain_ms(reqs):
+        """The same requests one at a time, back to back (GPU events)."""
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for N, t, cts in reqs:
+            ctx.compress(gk, st["db"], cts, N, t, out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    warm = draw(6)
+    plain_ms(warm)
     ctx.trim()
     torch.cuda.empty_cache()
     srv = hc.Server(ctx, gk, st["db"], lane_bytes=int(lane_gb) << 30, lanes=lanes, max_batch=max_batch)
-    res = {"plain_ms_per_query": round(plain_ms, 3), "plain_capacity": round(capacity, 3), "requests_per_rate": requests,
-           "lanes": lanes, "lane_gb": lane_gb, "max_batch": max_batch, "galois_keys": len(keys),
-           "resident_diagonal_gb": round(held / 1e9, 2), "setup_s": round(setup_s, 1), "rates": []}
+    res = {"requests_per_rate": requests, "lanes": lanes, "lane_gb": lane_gb, "max_batch": max_batch,
+           "galois_keys": len(keys), "resident_diagonal_gb": round(held / 1e9, 2), "setup_s": round(setup_s, 1),
+           "rates": []}
     try:
         for frac in rates:
-            lam = frac * capacity
             reqs = draw(requests)
+            pms = plain_ms(reqs)  # the same request list, plain, for the capacity and the comparison
+            capacity = requests / (pms / 1e3)
+            lam = frac * capacity
             gaps = rng.exponential(1.0 / lam, size=requests)
             start = time.monotonic_ns() + 20_000_000
             arrive = start + np.cumsum(gaps * 1e9).astype(np.int64)
@@ -438,7 +439,7 @@ def serving(st, rates, requests, lane_gb=40, lanes=2, max_batch=16):
                     done_last = max(done_last, r["done_ns"])
                     batch_sizes.append(r["batch_size"])
             span = (done_last - int(arrive[0])) / 1e9
-            row = {"fraction_of_plain_capacity": frac, "offered_per_s": round(lam, 3),
+            row = {"fraction_of_plain_capacity": frac, "plain_per_s": round(capacity, 3), "offered_per_s": round(lam, 3),
                    "throughput_per_s": round(requests / span, 3), "p50_ms": round(percentile(lat, 50), 2),
                    "p99_ms": round(percentile(lat, 99), 2), "mean_batch": round(float(np.mean(batch_sizes)), 2)}
             log("serving at %.2f x plain capacity: %s" % (frac, row))
@@ -470,6 +471,8 @@ def main():
     ap.add_argument("--serve-rates", default="0.25,0.5,0.75,0.9,1.0,1.25",
                     help="serving arrival rates as fractions of the plain capacity ('' to skip)")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests per serving rate")
+    ap.add_argument("--serve-lanes", type=int, default=2, help="concurrent batches of the server")
+    ap.add_argument("--serve-max-batch", type=int, default=16, help="queries per server batch")
     ap.add_argument("--on-the-fly-steps", type=int, default=2,
                     help="with resident diagonals, also time this many steps encoding them on the fly")
     args = ap.parse_args()
@@ -568,7 +571,8 @@ def main():
         rec["mixed_batch"] = mixed_batch(args.mixed_batch)
         log("mixed batch:", rec["mixed_batch"])
     if args.serve_rates:
-        rec["serving"] = serving(st, [float(x) for x in args.serve_rates.split(",")], args.serve_requests)
+        rec["serving"] = serving(st, [float(x) for x in args.serve_rates.split(",")], args.serve_requests,
+                                 lanes=args.serve_lanes, max_batch=args.serve_max_batch)
     rec["roofline"] = dict(rl[dominant], kernel=dominant)
     rec["rooflines"] = rl
     rec["mul32_probe_T"] = round(probe, 3)

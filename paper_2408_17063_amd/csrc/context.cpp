@@ -47,14 +47,20 @@ hc_status Lane::init(size_t stage_bytes) {
         stage_dev = nullptr;
         return HC_ENOMEM;
     }
+    if (hipEventCreateWithFlags(&copied, hipEventDisableTiming) != hipSuccess) {
+        copied = nullptr;
+        return HC_EDEVICE;
+    }
     return HC_OK;
 }
 
 void Lane::release() {
     if (stage_host) (void)hipHostFree(stage_host);
     if (stage_dev) (void)hipFree(stage_dev);
+    if (copied) (void)hipEventDestroy(copied);
     stage_host = nullptr;
     stage_dev = nullptr;
+    copied = nullptr;
     ws.release();
 }
 

@@ -49,6 +49,7 @@ struct Lane {
     uint8_t* stage_dev = nullptr;    // its device mirror
     size_t stage_cap = 0, stage_used = 0;
     hipStream_t stage_stream = nullptr;
+    hipEvent_t copied = nullptr;     // recorded after the last copy out of the staging area
     hc_status init(size_t stage_bytes);
     void release();
 };

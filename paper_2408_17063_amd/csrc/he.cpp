@@ -53,9 +53,11 @@ hc_status prefix_mask(Ctx& c, uint32_t s, const uint64_t** out) {
 // ------------------------------------------------------------------ staging
 
 void stage_reset(Lane& l, hipStream_t st) {
-    // the previous call's asynchronous copies out of the staging area must be done
+    // The workspace is reused in stream order; on another stream the previous call
+    // must be done. The staging area is free once its last copy has run, so on the
+    // same stream the host prepares the next call while the GPU finishes this one.
     if (l.stage_stream != st) (void)hipStreamSynchronize(l.stage_stream);
-    (void)hipStreamSynchronize(st);
+    if (l.copied) (void)hipEventSynchronize(l.copied);
     l.stage_used = 0;
     l.stage_stream = st;
 }
@@ -66,6 +68,7 @@ void* stage_bytes(Lane& l, const void* data, size_t bytes, hipStream_t st) {
     memcpy(l.stage_host + off, data, bytes);
     if (hipMemcpyAsync(l.stage_dev + off, l.stage_host + off, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
         return nullptr;
+    if (l.copied && hipEventRecord(l.copied, st) != hipSuccess) return nullptr;
     l.stage_used = off + bytes;
     return l.stage_dev + off;
 }
