@@ -196,6 +196,7 @@ def batched_large(st, Q, steps):
     ctx.compress_batch(st["gk"], st["db"], qs)  # warm-up (workspace)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
+    ctx.timing(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(steps):
@@ -204,6 +205,10 @@ def batched_large(st, Q, steps):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    for name, r in kernel_rooflines(ctx, hc).items():
+        log("  batched %-16s %8.1f ms per batch %6d launches  %s %.3f of peak" % (
+            name, r["ms"] / steps, r["launches"] // steps, r["bound"], r["frac"]))
+    ctx.timing(False)
     del qs
     torch.cuda.empty_cache()
     return {"queries": Q, "ms_per_batch": round(ms, 2), "value": round(Q / (ms / 1e3), 4),

@@ -152,8 +152,12 @@ struct KsJob {
     uint32_t xidx;
 };
 
-// Jobs [j0, j1) of a key-switching pass that belong to sum group g.
+// Jobs [j0, j1) of a key-switching pass that belong to sum group g (indices into a
+// member list).
 struct KsGroupRange { uint32_t g, j0, j1, pad; };
+// Jobs [j0, j0 + cnt) of a pass that share one key (cnt <= KS_RUN).
+constexpr int KS_RUN = 8;
+struct KsRun { uint32_t j0, cnt; };
 
 // One element-wise job over a ciphertext [2][Lc][n]: out = a (*|+) b.
 struct EwJob {
@@ -206,8 +210,8 @@ void kb_modup(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, bo
 // the digits' own rows of X from the NTT-domain sources
 void kb_own_rows(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, hipStream_t st);
 // T [M][2][Lc+K][n] = sum_j X[xidx_m][j] (rotated by k_m if hoisted) * key_m[j]
-void kb_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const KsJob* jobs, int M, int Lc, bool hoisted,
-              hipStream_t st);
+void kb_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const KsJob* jobs, const KsRun* runs, int nruns, int M,
+              int Lc, bool hoisted, hipStream_t st);
 // conv [M][2][Lc][n] = Conv_{P->Q} of the special rows of T (coefficient domain)
 void kb_conv(const Ctx& c, uint64_t* conv, const uint64_t* T, int M, int Lc, hipStream_t st);
 // out_m = (sigma_k(c0_m) + (T0 - conv0) P^-1, (T1 - conv1) P^-1), NTT domain
@@ -279,7 +283,7 @@ void k_diag_tile(const Ctx& c, uint64_t* out, const uint64_t* in, size_t i0, int
 void k_diag_split(const Ctx& c, uint64_t* d, size_t words, int Lc, hipStream_t st);
 // TA[g] += sum of the jobs' key products T, C0A[g] += sum of their rotated c0, per range
 void kb_accum(const Ctx& c, uint64_t* TA, uint64_t* C0A, const uint64_t* T, const KsJob* jobs,
-              const KsGroupRange* ranges, int nranges, int Lc, hipStream_t st);
+              const KsGroupRange* ranges, const uint32_t* members, int nranges, int Lc, hipStream_t st);
 // p[0..words) = 0 (a kernel, so it can sit in a captured graph)
 void k_zero(const Ctx& c, uint64_t* p, size_t words, hipStream_t st);
 // terms of the gathered rotated ciphertexts per pair: J rounded up to whole rounds of

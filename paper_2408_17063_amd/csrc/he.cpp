@@ -129,31 +129,56 @@ static void ks_raise(Ctx& c, KsScratch& s, const KsJob* d, int U, int Lc, bool p
     ntt64(c, s.X + (size_t)Lc * n, (size_t)R * n, U * dn, c.L, c.K, false, st);
 }
 
+// Jobs of a pass in key order (stable), so that jobs sharing a key are adjacent; the
+// order of jobs never changes a result.
+static void sort_by_key(std::vector<KsJob>& jb) {
+    std::stable_sort(jb.begin(), jb.end(),
+                     [](const KsJob& x, const KsJob& y) { return (uintptr_t)x.key < (uintptr_t)y.key; });
+}
+
+// Runs of up to KS_RUN adjacent jobs with the same key, staged for kb_inner.
+static const KsRun* stage_runs(Lane& l, const std::vector<KsJob>& jb, int* nruns, hipStream_t st) {
+    std::vector<KsRun> runs;
+    for (uint32_t i = 0; i < (uint32_t)jb.size(); i++) {
+        if (!runs.empty() && runs.back().cnt < (uint32_t)KS_RUN && jb[runs.back().j0].key == jb[i].key)
+            runs.back().cnt++;
+        else
+            runs.push_back(KsRun{i, 1});
+    }
+    *nruns = (int)runs.size();
+    return (const KsRun*)stage_bytes(l, runs.data(), sizeof(KsRun) * runs.size(), st);
+}
+
 // Rotations at level Lc. Plain (srcs == nullptr): each job raises its own rotated c1.
 // Hoisted: srcs[u] are raised once (unrotated) and every job with xidx = u rotates
-// the raised digits instead. Jobs are processed in passes of at most maxM.
+// the raised digits instead. Jobs are processed in passes of at most maxM, each pass
+// in key order so that jobs sharing a key read it once (kb_inner).
 hc_status ks_run(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
                  const std::vector<const uint64_t*>* srcs, int Lc, hipStream_t st) {
     if (!s.tmpC || !s.X || !s.T || !s.conv) return HC_ENOMEM;
     const size_t n = c.n;
-    const int R = Lc + c.K, dn = Lc / c.alpha;
+    const int R = Lc + c.K;
     auto raise = [&](const KsJob* d, int U, bool permute) { ks_raise(c, s, d, U, Lc, permute, st); };
-    auto finish = [&](const KsJob* d, int M, bool hoisted) {
-        kb_inner(c, s.T, s.X, d, M, Lc, hoisted, st);
+    auto finish = [&](const KsJob* d, const KsRun* runs, int nruns, int M, bool hoisted) {
+        kb_inner(c, s.T, s.X, d, runs, nruns, M, Lc, hoisted, st);
         ntt64(c, s.T + (size_t)Lc * n, (size_t)R * n, 2 * M, c.L, c.K, true, st);
         kb_conv(c, s.conv, s.T, M, Lc, st);
         ntt64(c, s.conv, (size_t)Lc * n, 2 * M, 0, Lc, false, st);
         kb_final(c, d, s.T, s.conv, M, Lc, st);
     };
     if (!srcs) {
-        for (size_t m0 = 0; m0 < jobs.size(); m0 += s.maxM) {
-            const int M = (int)std::min<size_t>(s.maxM, jobs.size() - m0);
-            std::vector<KsJob> jb(jobs.begin() + m0, jobs.begin() + m0 + M);
+        std::vector<KsJob> all(jobs);
+        sort_by_key(all);
+        for (size_t m0 = 0; m0 < all.size(); m0 += s.maxM) {
+            const int M = (int)std::min<size_t>(s.maxM, all.size() - m0);
+            std::vector<KsJob> jb(all.begin() + m0, all.begin() + m0 + M);
             for (int i = 0; i < M; i++) jb[i].xidx = (uint32_t)i;
             const KsJob* d = (const KsJob*)stage_bytes(l, jb.data(), sizeof(KsJob) * M, st);
-            if (!d) return HC_ENOMEM;
+            int nruns = 0;
+            const KsRun* dr = stage_runs(l, jb, &nruns, st);
+            if (!d || !dr) return HC_ENOMEM;
             raise(d, M, true);
-            finish(d, M, false);
+            finish(d, dr, nruns, M, false);
         }
         return HC_OK;
     }
@@ -172,11 +197,15 @@ hc_status ks_run(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
                 t.xidx = (uint32_t)(j.xidx - u0);
                 mine.push_back(t);
             }
+        sort_by_key(mine);
         for (size_t m0 = 0; m0 < mine.size(); m0 += s.maxM) {
             const int M = (int)std::min<size_t>(s.maxM, mine.size() - m0);
-            const KsJob* d = (const KsJob*)stage_bytes(l, mine.data() + m0, sizeof(KsJob) * M, st);
-            if (!d) return HC_ENOMEM;
-            finish(d, M, true);
+            std::vector<KsJob> jb(mine.begin() + m0, mine.begin() + m0 + M);
+            const KsJob* d = (const KsJob*)stage_bytes(l, jb.data(), sizeof(KsJob) * M, st);
+            int nruns = 0;
+            const KsRun* dr = stage_runs(l, jb, &nruns, st);
+            if (!d || !dr) return HC_ENOMEM;
+            finish(d, dr, nruns, M, true);
         }
     }
     return HC_OK;
@@ -185,7 +214,8 @@ hc_status ks_run(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
 // Sums of plain rotations, one ModDown per sum: for each group g, outs[g] = sum of
 // Rot_k(in) over the jobs with group[i] == g, whose key products are added over PQ
 // (TA, groups x [2][Lc+K][n]) and whose rotated c0 are added (C0A, groups x [Lc][n])
-// before a single ModDown. Jobs must be ordered by group.
+// before a single ModDown. Passes run in key order; every sum is exact, so the order
+// does not change a result.
 hc_status ks_run_sum(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
                      const std::vector<uint32_t>& group, const std::vector<uint64_t*>& outs, uint64_t* TA,
                      uint64_t* C0A, int Lc, hipStream_t st) {
@@ -194,22 +224,39 @@ hc_status ks_run_sum(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jo
     const int R = Lc + c.K;
     k_zero(c, TA, G * 2 * (size_t)R * n, st);
     k_zero(c, C0A, G * (size_t)Lc * n, st);
+    // job order by key, carrying each job's group
+    std::vector<uint32_t> order(jobs.size());
+    for (uint32_t i = 0; i < (uint32_t)jobs.size(); i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+        return (uintptr_t)jobs[x].key < (uintptr_t)jobs[y].key;
+    });
     for (size_t m0 = 0; m0 < jobs.size(); m0 += s.maxM) {
         const int M = (int)std::min<size_t>(s.maxM, jobs.size() - m0);
-        std::vector<KsJob> jb(jobs.begin() + m0, jobs.begin() + m0 + M);
-        for (int i = 0; i < M; i++) jb[i].xidx = (uint32_t)i;
+        std::vector<KsJob> jb(M);
+        for (int i = 0; i < M; i++) {
+            jb[i] = jobs[order[m0 + i]];
+            jb[i].xidx = (uint32_t)i;
+        }
+        // members of each group within the pass
+        std::vector<uint32_t> members(M);
+        for (int i = 0; i < M; i++) members[i] = (uint32_t)i;
+        std::stable_sort(members.begin(), members.end(),
+                         [&](uint32_t x, uint32_t y) { return group[order[m0 + x]] < group[order[m0 + y]]; });
         std::vector<KsGroupRange> rg;
         for (int i = 0; i < M; i++) {
-            const uint32_t g = group[m0 + i];
+            const uint32_t g = group[order[m0 + members[i]]];
             if (rg.empty() || rg.back().g != g) rg.push_back(KsGroupRange{g, (uint32_t)i, (uint32_t)i + 1, 0});
             else rg.back().j1 = (uint32_t)i + 1;
         }
         const KsJob* d = (const KsJob*)stage_bytes(l, jb.data(), sizeof(KsJob) * M, st);
-        const KsGroupRange* dr = (const KsGroupRange*)stage_bytes(l, rg.data(), sizeof(KsGroupRange) * rg.size(), st);
-        if (!d || !dr) return HC_ENOMEM;
+        const KsGroupRange* dg = (const KsGroupRange*)stage_bytes(l, rg.data(), sizeof(KsGroupRange) * rg.size(), st);
+        const uint32_t* dm = (const uint32_t*)stage_bytes(l, members.data(), sizeof(uint32_t) * M, st);
+        int nruns = 0;
+        const KsRun* dr = stage_runs(l, jb, &nruns, st);
+        if (!d || !dg || !dm || !dr) return HC_ENOMEM;
         ks_raise(c, s, d, M, Lc, true, st);
-        kb_inner(c, s.T, s.X, d, M, Lc, false, st);
-        kb_accum(c, TA, C0A, s.T, d, dr, (int)rg.size(), Lc, st);
+        kb_inner(c, s.T, s.X, d, dr, nruns, M, Lc, false, st);
+        kb_accum(c, TA, C0A, s.T, d, dg, dm, (int)rg.size(), Lc, st);
     }
     // one ModDown per group (TA is consumed in place)
     for (size_t g0 = 0; g0 < G; g0 += s.maxM) {

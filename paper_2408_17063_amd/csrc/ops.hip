@@ -199,40 +199,55 @@ void kb_own_rows(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc,
 
 // T[m][comp][row][x] = sum_j X[xidx][j][row][src(x)] * key_m[j][comp][prime(row)][x]; the key is
 // in Montgomery form, so one reduction of the 128-bit sum gives the plain sum (dnum q^2 < q 2^64).
+// Key inner product of a pass, one run of up to KS_RUN jobs that share one key per
+// block (jobs sorted by key): each key word is read once per run, and each job's
+// raised digit (rotated on the fly for hoisted jobs) is multiplied into its own
+// 128-bit sums, reduced once.
 __global__ void kb_inner_kernel(uint64_t* __restrict__ T, const uint64_t* __restrict__ X,
-                                const KsJob* __restrict__ jobs, const uint64_t* __restrict__ mods,
-                                const uint64_t* __restrict__ qinv, int n, int logn, int nq, int L, int Lc,
-                                int K, int dn, int hoisted) {
+                                const KsJob* __restrict__ jobs, const KsRun* __restrict__ runs,
+                                const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv, int n,
+                                int logn, int nq, int L, int Lc, int K, int dn, int hoisted) {
     int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
-    const int row = blockIdx.y, m = blockIdx.z, R = Lc + K;
-    const KsJob jb = jobs[m];
+    const int row = blockIdx.y, R = Lc + K;
+    const KsRun run = runs[blockIdx.z];
     const int pr = row_prime(row, Lc, L);
-    // plain jobs raised their already-rotated c1; hoisted jobs rotate the shared raised digits
-    const uint32_t src = (!hoisted || jb.k == 1) ? x : galois_src(x, jb.k, logn);
-    const uint64_t* xs = X + (size_t)jb.xidx * dn * R * n + (size_t)row * n + src;
     const size_t keyrow = (size_t)nq * n;
-    const uint64_t* kp = jb.key + (size_t)pr * n + x;
-    u128p a0{0, 0}, a1{0, 0};
+    const uint64_t* kp = jobs[run.j0].key + (size_t)pr * n + x;
+    u128p a0[KS_RUN], a1[KS_RUN];
+    #pragma unroll
+    for (int i = 0; i < KS_RUN; i++) { a0[i] = u128p{0, 0}; a1[i] = u128p{0, 0}; }
     for (int j = 0; j < dn; j++) {
-        const uint64_t xv = xs[(size_t)j * R * n];
-        const uint64_t* kj = kp + (size_t)j * 2 * keyrow;
-        add128(a0, mul128(xv, kj[0]));
-        add128(a1, mul128(xv, kj[keyrow]));
+        const uint64_t k0 = kp[(size_t)j * 2 * keyrow], k1 = kp[(size_t)j * 2 * keyrow + keyrow];
+        #pragma unroll
+        for (int i = 0; i < KS_RUN; i++) {
+            if (i < (int)run.cnt) {
+                const KsJob jb = jobs[run.j0 + i];
+                // plain jobs raised their already-rotated c1; hoisted jobs rotate the shared raised digits
+                const uint32_t src = (!hoisted || jb.k == 1) ? x : galois_src(x, jb.k, logn);
+                const uint64_t xv = X[((size_t)jb.xidx * dn + j) * R * n + (size_t)row * n + src];
+                add128(a0[i], mul128(xv, k0));
+                add128(a1[i], mul128(xv, k1));
+            }
+        }
     }
     const uint64_t q = mods[pr], qi = qinv[pr];
-    uint64_t* t = T + (size_t)m * 2 * R * n + (size_t)row * n + x;
-    t[0] = redc(a0, q, qi);
-    t[(size_t)R * n] = redc(a1, q, qi);
+    #pragma unroll
+    for (int i = 0; i < KS_RUN; i++) {
+        if (i < (int)run.cnt) {
+            uint64_t* t = T + (size_t)(run.j0 + i) * 2 * R * n + (size_t)row * n + x;
+            t[0] = redc(a0[i], q, qi);
+            t[(size_t)R * n] = redc(a1[i], q, qi);
+        }
+    }
 }
-
-void kb_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const KsJob* jobs, int M, int Lc, bool hoisted,
-              hipStream_t st) {
+void kb_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const KsJob* jobs, const KsRun* runs, int nruns, int M,
+              int Lc, bool hoisted, hipStream_t st) {
     const int dn = Lc / c.alpha, R = Lc + c.K;
-    // per job: reads the key (2 dn rows per prime) and the raised digits, writes T
-    const double rows = (double)R * c.n * M;
-    TimeScope ts(c, HC_KT_KS_INNER, st, 8.0 * rows * (2.0 * dn + dn + 2.0), 2.0 * dn * rows);
-    hipLaunchKernelGGL(kb_inner_kernel, ew_grid(c.n, R, M), dim3(EW_THREADS), 0, st, T, X, jobs, c.d_mods,
+    // per run and row: the key (2 dn words) once; per job: its raised digits and T
+    const double rows = (double)R * c.n;
+    TimeScope ts(c, HC_KT_KS_INNER, st, 8.0 * rows * (2.0 * dn * nruns + (dn + 2.0) * M), 2.0 * dn * rows * M);
+    hipLaunchKernelGGL(kb_inner_kernel, ew_grid(c.n, R, nruns), dim3(EW_THREADS), 0, st, T, X, jobs, runs, c.d_mods,
                        c.d_qinv, c.n, c.logn, c.nq, c.L, Lc, c.K, dn, hoisted ? 1 : 0);
 }
 
@@ -284,12 +299,12 @@ void kb_final(const Ctx& c, const KsJob* jobs, const uint64_t* T, const uint64_t
 }
 
 // Sums of key-switched rotations brought down once: the key products T of the jobs
-// [j0, j1) of each group are added into TA[g] ([2][Lc+K][n], mod each row's prime)
+// members[j0..j1) of each group are added into TA[g] ([2][Lc+K][n], mod each row's prime)
 // and their rotated c0 into C0A[g] ([Lc][n]). Rows 0..2R-1 are T's, then Lc rows of c0.
 __global__ void kb_accum_kernel(uint64_t* __restrict__ TA, uint64_t* __restrict__ C0A,
                                 const uint64_t* __restrict__ T, const KsJob* __restrict__ jobs,
-                                const KsGroupRange* __restrict__ ranges, const uint64_t* __restrict__ mods,
-                                int n, int logn, int L, int Lc, int K) {
+                                const KsGroupRange* __restrict__ ranges, const uint32_t* __restrict__ members,
+                                const uint64_t* __restrict__ mods, int n, int logn, int L, int Lc, int K) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     const int row = blockIdx.y, R = Lc + K;
@@ -299,15 +314,18 @@ __global__ void kb_accum_kernel(uint64_t* __restrict__ TA, uint64_t* __restrict_
         const uint64_t q = mods[row_prime(rr, Lc, L)];
         uint64_t* ta = TA + (((size_t)gr.g * 2 + comp) * R + rr) * n + x;
         uint64_t acc = *ta;
-        for (uint32_t m = gr.j0; m < gr.j1; m++) acc = add_mod(acc, T[(((size_t)m * 2 + comp) * R + rr) * n + x], q);
+        for (uint32_t u = gr.j0; u < gr.j1; u++) {
+            const uint32_t m = members[u];
+            acc = add_mod(acc, T[(((size_t)m * 2 + comp) * R + rr) * n + x], q);
+        }
         *ta = acc;
     } else {
         const int i = row - 2 * R;
         const uint64_t q = mods[i];
         uint64_t* ca = C0A + ((size_t)gr.g * Lc + i) * n + x;
         uint64_t acc = *ca;
-        for (uint32_t m = gr.j0; m < gr.j1; m++) {
-            const KsJob jb = jobs[m];
+        for (uint32_t u = gr.j0; u < gr.j1; u++) {
+            const KsJob jb = jobs[members[u]];
             const uint32_t src = (jb.k == 1) ? x : galois_src(x, jb.k, logn);
             acc = add_mod(acc, jb.in[(size_t)i * n + src], q);
         }
@@ -316,10 +334,10 @@ __global__ void kb_accum_kernel(uint64_t* __restrict__ TA, uint64_t* __restrict_
 }
 
 void kb_accum(const Ctx& c, uint64_t* TA, uint64_t* C0A, const uint64_t* T, const KsJob* jobs,
-              const KsGroupRange* ranges, int nranges, int Lc, hipStream_t st) {
+              const KsGroupRange* ranges, const uint32_t* members, int nranges, int Lc, hipStream_t st) {
     const int R = Lc + c.K;
     hipLaunchKernelGGL(kb_accum_kernel, ew_grid(c.n, 2 * R + Lc, nranges), dim3(EW_THREADS), 0, st, TA, C0A, T,
-                       jobs, ranges, c.d_mods, c.n, c.logn, c.L, Lc, c.K);
+                       jobs, ranges, members, c.d_mods, c.n, c.logn, c.L, Lc, c.K);
 }
 
 __global__ void zero_words_kernel(uint64_t* __restrict__ p, size_t words) {
