@@ -386,8 +386,9 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
             // resident diagonals: one pass over every giant index
             uint64_t** aptr = (uint64_t**)stage_bytes(l, hptr.data() + np * kb * B, sizeof(uint64_t*) * np * G, st);
             if (!aptr) return HC_ENOMEM;
-            k_diag_mac(c, aptr, Rt, tab->d, diag_layout_tiled(c, tab->kb * B, G), (int)np, (int)(kb * B), (int)G,
-                       false, Lc, st);
+            hc_status ms = k_diag_mac(c, aptr, Rt, tab->d, diag_layout_tiled(c, tab->kb * B, G), (int)np,
+                                      (int)(kb * B), (int)G, false, Lc, st);
+            if (ms != HC_OK) return ms;
             continue;
         }
         std::vector<uint32_t> hprm;
@@ -414,8 +415,9 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
             k_lift(c, D, Dp, cnt, true, Lc, st);
             ntt64(c, D, PW, cnt, 0, Lc, false, st);
             k_diag_split(c, D, (size_t)cnt * PW, Lc, st);
-            k_diag_mac(c, aptr, Rt, D, diag_layout_natural(c, Lc, gc), (int)np, (int)(kb * B), (int)gc, false, Lc,
-                       st);
+            hc_status ms = k_diag_mac(c, aptr, Rt, D, diag_layout_natural(c, Lc, gc), (int)np, (int)(kb * B),
+                                      (int)gc, false, Lc, st);
+            if (ms != HC_OK) return ms;
         }
     }
 

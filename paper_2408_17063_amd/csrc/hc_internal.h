@@ -287,15 +287,19 @@ void kb_accum(const Ctx& c, uint64_t* TA, uint64_t* C0A, const uint64_t* T, cons
 // p[0..words) = 0 (a kernel, so it can sit in a captured graph)
 void k_zero(const Ctx& c, uint64_t* p, size_t words, hipStream_t st);
 // terms of the gathered rotated ciphertexts per pair: J rounded up to whole rounds of
-// the multiply-accumulate (two stages of DIAG_T terms)
-inline int diag_terms_padded(int J) { return (J + 2 * DIAG_T - 1) / (2 * DIAG_T) * (2 * DIAG_T); }
+// the multiply-accumulate (DIAG_NS stages of DIAG_T terms: the stages in flight at once)
+constexpr int DIAG_NS = 4;
+inline int diag_terms_padded(int J) {
+    return (J + DIAG_NS * DIAG_T - 1) / (DIAG_NS * DIAG_T) * (DIAG_NS * DIAG_T);
+}
 // Rt[r][tile][pp][j][2][64] (split) from the pointer table R[pp][j] (j < J; nullptr and
 // J <= j < diag_terms_padded(J): zeros)
 void k_diag_gather(const Ctx& c, uint64_t* Rt, const uint64_t* const* R, int npairs, int J, int Lc,
                    hipStream_t st);
 // A[pp][g] (=|+=) sum_{j<J} D(j, g) R[pp][j], g < ga, for npairs pairs: A pointers
 // [npairs][ga], R gathered by k_diag_gather, D split and in Montgomery form.
-void k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* Rt, const uint64_t* D,
-                const DiagLayout& lay, int npairs, int J, int ga, bool accumulate, int Lc, hipStream_t st);
+// HC_EINVAL if one term's diagonal words for DIAG_GC giants span 2^31 bytes or more
+hc_status k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* Rt, const uint64_t* D,
+                     const DiagLayout& lay, int npairs, int J, int ga, bool accumulate, int Lc, hipStream_t st);
 
 }  // namespace hc

@@ -740,7 +740,7 @@ __device__ __forceinline__ uint64_t split_word(uint64_t v, int h) {
 }
 
 // Rt[r][tile][pp][j][k][64] = R[pp][j] component k at (r, 64 tile + lane), split, for
-// j < Jp (a multiple of 3 >= J); nullptr and j >= J -> 0.
+// j < Jp (J rounded up by diag_terms_padded); nullptr and j >= J -> 0.
 __global__ void diag_gather_kernel(uint64_t* __restrict__ Rt, const uint64_t* const* __restrict__ R, int n,
                                    int L, int J, int Jp, int npairs, int pj0, int h) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -757,24 +757,47 @@ __global__ void diag_gather_kernel(uint64_t* __restrict__ Rt, const uint64_t* co
     Rt[o + 64] = split_word(v1, h);
 }
 
-// The diagonals of a block are read from device memory once and shared through LDS:
-// every wave of a block (the block's ciphertext pairs, plus helper waves up to 4)
-// loads 16-byte pieces of the next T terms' diagonal words into registers while the
-// pair waves multiply the current T terms out of LDS; the pieces then go to the other
-// LDS buffer and one barrier per stage flips the buffers. Each pair wave's rotated
-// ciphertexts for the next stage are loaded alongside into a second register set.
-// The loop covers Jp terms (a multiple of 2 T; terms past J have zero rotated
-// ciphertexts) in pairs of stages, with no exit in between.
-template <int GC, int T>
-__global__ __launch_bounds__(512) void diag_mac_kernel(uint64_t* const* __restrict__ A,
-                                                           const uint64_t* __restrict__ Rt,
-                                                           const uint64_t* __restrict__ D,
-                                                           const uint64_t* __restrict__ mods,
-                                                           const uint64_t* __restrict__ qinv,
-                                                           const uint64_t* __restrict__ r2, DiagMacArgs a) {
-    constexpr int CH = T * GC * 32;        // 16-byte pieces per stage
-    constexpr int MAXC = (CH + 255) / 256;  // per thread (blocks have >= 256 threads)
-    __shared__ uint64_t lds[2][T][GC][64];
+// The diagonals of a block are read from device memory once and shared through LDS,
+// streamed by LDS DMA through a ring of NS stage buffers. A stage's diagonal words (T
+// terms x GC giants x 64 coefficients, 16 KB) are written by 16 buffer_load_dwordx4 ...
+// lds instructions (each puts 64 lanes x 16 bytes contiguously at the wave-uniform LDS
+// base in M0), four per wave of the block (the block's pair waves and helper waves up to
+// 4), issued NS - 1 stages before the stage is multiplied; each pair wave loads its
+// rotated ciphertexts into NS register slots at the same distance. Per stage a wave
+// waits until only the last NS - 2 stages' loads are outstanding (its own share of the
+// stage has landed) and the block synchronises on a bare s_barrier: a fenced barrier
+// would wait for every outstanding LDS DMA. The buffer a stage refills was multiplied in
+// the stage before; the barrier orders that. The buffer (MUBUF) form of the DMA is used
+// because the compiler's wait-count tracking treats a pending global (FLAT) LDS DMA as
+// both a memory and an LDS access and then waits for all loads at every use of loaded
+// registers. The loop covers Jp terms (a multiple of NS T; terms past J have zero
+// rotated ciphertexts) with no exit in between.
+#define HC_VMCNT(n) (((n) & 15) | (7 << 4) | (15 << 8) | (((n) >> 4) << 14))
+// buffer resource word 3 for raw (untyped) buffer access
+#define HC_RSRC_WORD3 0x00020000
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// a wave-uniform pointer, held in scalar registers
+__device__ __forceinline__ void* uniform_ptr(const void* p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (void*)(((uint64_t)hi << 32) | lo);
+}
+
+template <int GC, int T, int NS>
+__global__ __launch_bounds__(256) void diag_mac_kernel(uint64_t* const* __restrict__ A,
+                                                            const uint64_t* __restrict__ Rt,
+                                                            const uint64_t* __restrict__ D,
+                                                            const uint64_t* __restrict__ mods,
+                                                            const uint64_t* __restrict__ qinv,
+                                                            const uint64_t* __restrict__ r2, DiagMacArgs a) {
+    constexpr int PIECES = T * GC * 32;  // 16-byte pieces per stage
+    constexpr int INSTR = PIECES / 64;   // wave instructions per stage
+    constexpr int PER_WAVE = INSTR / 4;  // blocks are 4 waves
+    static_assert(INSTR % 4 == 0 && GC % 2 == 0, "stage size");
+    constexpr int RLOADS = 2 * T;        // a pair wave's rotated-ciphertext loads per stage
+    __shared__ __attribute__((aligned(1024))) uint64_t lds[NS][T][GC][64];
     const uint32_t bid = blockIdx.x;
     const uint32_t wk = (bid & 7u) * a.per_xcd + (bid >> 3);
     if (wk >= a.work) return;  // uniform over the block
@@ -787,12 +810,12 @@ __global__ __launch_bounds__(512) void diag_mac_kernel(uint64_t* const* __restri
     const int pp = pg * a.wp + w;
     const bool active = w < a.wp && pp < a.npairs;  // wave-uniform
     const int lane = (int)(threadIdx.x & 63);
-    const int nthr = (int)blockDim.x;
     const uint64_t q = mods[r], qi = qinv[r], q2 = r2[r];
     const int g0 = gci * GC;
     const int gc = (a.ga - g0) < GC ? (a.ga - g0) : GC;
     const int h = a.h;
     const int J = a.J, Jp = a.Jp;
+    const int nst = Jp / T;  // a multiple of NS
 
     uint64_t lo[GC][2], mid[GC][2], hi[GC][2];
     #pragma unroll
@@ -817,49 +840,37 @@ __global__ __launch_bounds__(512) void diag_mac_kernel(uint64_t* const* __restri
     const uint64_t* Rb = Rt + (((size_t)r * a.ntiles + tile) * a.npairs + (active ? pp : 0)) * (size_t)Jp * 128 + lane;
     const uint64_t* Db = D + (size_t)r * a.sr + (size_t)tile * a.st + (size_t)(g0 / DIAG_GC) * a.sgc +
                           (size_t)(g0 % DIAG_GC) * a.sg;
-    // staging piece c: term c / (32 GC), giant (c / 32) % GC, words 2 (c % 32), +1 of the lane row
-    uint64_t dv[MAXC][2];
-    auto issue = [&](int j0) __attribute__((always_inline)) {
+    // bytes a term's diagonal words span from their first word (giants g0..g0+gc-1)
+    const int nrec = __builtin_amdgcn_readfirstlane((int)(((size_t)(gc - 1) * a.sg + 64) * 8));
+    // piece c = 64 m + lane of a stage: term c / (32 GC) = m / (GC / 2), giant (c / 32) % GC,
+    // words 2 (c % 32), +1 of the 64-coefficient row; it lands at byte 16 c of the stage
+    // buffer. A term's words are addressed from a per-instruction buffer base.
+    auto issueD = [&](int s, int buf) __attribute__((always_inline)) {
         #pragma unroll
-        for (int k = 0; k < MAXC; k++) {
-            const int c = (int)threadIdx.x + k * nthr;
-            const int tt = c / (32 * GC), g = (c / 32) % GC, qd = c % 32;
-            const int jd = (j0 + tt) < J ? (j0 + tt) : J - 1;
+        for (int k = 0; k < PER_WAVE; k++) {
+            const int m = w * PER_WAVE + k;  // wave-uniform, so is the term
+            const int tt = m / (GC / 2), g = 2 * (m % (GC / 2)) + (lane >> 5), qd = lane & 31;
+            const int jd = (s * T + tt) < J ? (s * T + tt) : J - 1;
             const int gg = g < gc ? g : gc - 1;
-            const uint64_t* src = Db + (size_t)jd * a.sj + (size_t)gg * a.sg + 2 * qd;
-            if (c < CH) {
-                dv[k][0] = src[0];
-                dv[k][1] = src[1];
-            }
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(Db + (size_t)jd * a.sj), 0, nrec, HC_RSRC_WORD3);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)((char*)&lds[buf][0][0][0] + m * 1024), 16,
+                                                     (uint32_t)((size_t)gg * a.sg + 2 * qd) * 8u, 0, 0, 0);
         }
     };
-    auto commit = [&](int buf) __attribute__((always_inline)) {
-        #pragma unroll
-        for (int k = 0; k < MAXC; k++) {
-            const int c = (int)threadIdx.x + k * nthr;
-            const int tt = c / (32 * GC), g = (c / 32) % GC, qd = c % 32;
-            if (c < CH) {
-                lds[buf][tt][g][2 * qd] = dv[k][0];
-                lds[buf][tt][g][2 * qd + 1] = dv[k][1];
-            }
-        }
-    };
-    uint64_t rv[2][T][2];
-    auto loadR = [&](int j0, auto slot_c) __attribute__((always_inline)) {
+    uint64_t rv[NS][T][2];
+    auto loadR = [&](int s, auto slot_c) __attribute__((always_inline)) {
         constexpr int slot = decltype(slot_c)::value;
-        if (active) {
-            #pragma unroll
-            for (int u = 0; u < T; u++) {
-                const int jr = (j0 + u) < Jp ? (j0 + u) : Jp - 1;
-                rv[slot][u][0] = Rb[(size_t)jr * 128];
-                rv[slot][u][1] = Rb[(size_t)jr * 128 + 64];
-            }
+        #pragma unroll
+        for (int u = 0; u < T; u++) {
+            const int jr = (s * T + u) < Jp ? (s * T + u) : Jp - 1;
+            rv[slot][u][0] = Rb[(size_t)jr * 128];
+            rv[slot][u][1] = Rb[(size_t)jr * 128 + 64];
         }
     };
     int terms = 0;
     auto compute = [&](int buf, auto slot_c) __attribute__((always_inline)) {
         constexpr int slot = decltype(slot_c)::value;
-        if (!active) return;
         if (terms + T > a.chunk) {
             fold(false);
             terms = 0;
@@ -884,24 +895,54 @@ __global__ __launch_bounds__(512) void diag_mac_kernel(uint64_t* const* __restri
         }
         terms += T;
     };
-    using S0 = std::integral_constant<int, 0>;
-    using S1 = std::integral_constant<int, 1>;
-    issue(0);
-    loadR(0, S0{});
-    commit(0);
-    __syncthreads();
-    for (int j0 = 0; j0 < Jp; j0 += 2 * T) {
-        issue(j0 + T);
-        loadR(j0 + T, S1{});
-        compute(0, S0{});
-        commit(1);
-        __syncthreads();
-        issue(j0 + 2 * T);
-        loadR(j0 + 2 * T, S0{});
-        compute(1, S1{});
-        commit(0);
-        __syncthreads();
-    }
+    // Two copies of the stage loop: pair waves (loads, products) and helper waves (their
+    // share of the diagonal loads only), so neither carries a branch on the wave's role.
+    // A stage's loads: the wave's rotated ciphertexts first, then its diagonal share, so
+    // waiting for stage s leaves exactly the later stages' loads outstanding.
+    auto run = [&](auto act_c) __attribute__((always_inline)) {
+        constexpr bool ACT = decltype(act_c)::value;
+        auto stage_loads = [&](int s, auto slot_c) __attribute__((always_inline)) {
+            if constexpr (ACT) loadR(s, slot_c);
+            issueD(s, decltype(slot_c)::value);
+        };
+        auto wait_stage = [&]() __attribute__((always_inline)) {
+            __builtin_amdgcn_s_waitcnt(HC_VMCNT((NS - 2) * ((ACT ? RLOADS : 0) + PER_WAVE)));
+            __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_barrier();
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        auto mul = [&](int buf, auto slot_c) __attribute__((always_inline)) {
+            if constexpr (ACT) compute(buf, slot_c);
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        using S0 = std::integral_constant<int, 0>;
+        using S1 = std::integral_constant<int, 1>;
+        using S2 = std::integral_constant<int, 2>;
+        using S3 = std::integral_constant<int, 3>;
+        static_assert(NS == 4, "the stage loop below is written out for four slots");
+        stage_loads(0, S0{});
+        stage_loads(1, S1{});
+        stage_loads(2, S2{});
+        for (int s = 0; s < nst; s += NS) {
+            wait_stage();
+            stage_loads(s + 3, S3{});
+            mul(0, S0{});
+            wait_stage();
+            stage_loads(s + 4, S0{});
+            mul(1, S1{});
+            wait_stage();
+            stage_loads(s + 5, S1{});
+            mul(2, S2{});
+            wait_stage();
+            stage_loads(s + 6, S2{});
+            mul(3, S3{});
+        }
+    };
+    if (active) run(std::true_type{});
+    else run(std::false_type{});
+    // the last NS - 1 stages' loads (clamped to valid terms) land before the block's LDS
+    // can be handed to another block
+    __builtin_amdgcn_s_waitcnt(HC_VMCNT(0));
     if (!active) return;
     fold(true);
     const size_t ln = (size_t)a.L * a.n;
@@ -976,8 +1017,10 @@ void k_diag_gather(const Ctx& c, uint64_t* Rt, const uint64_t* const* R, int npa
                            st, Rt, R, c.n, Lc, J, Jp, npairs, pj0, h);
 }
 
-void k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* Rt, const uint64_t* D,
-                const DiagLayout& lay, int npairs, int J, int ga, bool accumulate, int Lc, hipStream_t st) {
+hc_status k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* Rt, const uint64_t* D,
+                     const DiagLayout& lay, int npairs, int J, int ga, bool accumulate, int Lc, hipStream_t st) {
+    // the kernel addresses one term's words (DIAG_GC giants) by 32-bit buffer offsets
+    if (((size_t)(DIAG_GC - 1) * lay.sg + 64) * 8 >= ((size_t)1 << 31)) return HC_EINVAL;
     int bits, h;
     uint64_t qmax;
     diag_split_bits(c, Lc, &bits, &h, &qmax);
@@ -1009,8 +1052,9 @@ void k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* Rt, const uint
     TimeScope ts(c, HC_KT_DIAG_MAC, st,
                  8.0 * ln * (2.0 * npairs * J + (double)J * ga + (accumulate ? 4.0 : 2.0) * npairs * ga),
                  2.0 * ln * npairs * J * ga);
-    hipLaunchKernelGGL((diag_mac_kernel<GC, DIAG_T>), dim3(a.per_xcd * 8), dim3(256), 0, st, A, Rt, D, c.d_mods,
-                       c.d_qinv, c.d_r2, a);
+    hipLaunchKernelGGL((diag_mac_kernel<GC, DIAG_T, DIAG_NS>), dim3(a.per_xcd * 8), dim3(256), 0, st, A, Rt, D,
+                       c.d_mods, c.d_qinv, c.d_r2, a);
+    return HC_OK;
 }
 
 // Natural layout (one [Lc][n] polynomial per diagonal, index (beta dG + g) B + b) ->
