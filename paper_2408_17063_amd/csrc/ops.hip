@@ -251,26 +251,32 @@ void kb_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const KsJob* jobs, c
                        c.d_qinv, c.n, c.logn, c.nq, c.L, Lc, c.K, dn, hoisted ? 1 : 0);
 }
 
-// conv[m][comp][i][x] = sum_k [T_{p_k}(x) (P/p_k)^-1]_{p_k} (P/p_k) mod q_i (coefficient domain)
+// conv[m][comp][i][x] = sum_k [T_{p_k}(x) (P/p_k)^-1]_{p_k} (P/p_k) mod q_i (coefficient domain).
+// A thread converts one coefficient to CONV_ROWS consecutive output primes, so each
+// [T_{p_k}(x) (P/p_k)^-1] is read and computed once for all of them.
+constexpr int CONV_ROWS = 8;
 __global__ void kb_conv_kernel(uint64_t* __restrict__ conv, const uint64_t* __restrict__ T,
                                const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv,
                                const uint64_t* __restrict__ inv, const uint64_t* __restrict__ cst,
                                int n, int L, int Lc, int K) {
     int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
-    const int i = blockIdx.y, mc = blockIdx.z, R = Lc + K;  // mc = m * 2 + comp
+    const int i0 = blockIdx.y * CONV_ROWS, mc = blockIdx.z, R = Lc + K;  // mc = m * 2 + comp
     const uint64_t* Tc = T + (size_t)mc * R * n;
     uint64_t y[4];
     for (int k = 0; k < K; k++)
         y[k] = shoup(Tc[(size_t)(Lc + k) * n + x], inv[2 * k], inv[2 * k + 1], mods[L + k]);
-    u128p acc{0, 0};
-    for (int k = 0; k < K; k++) add128(acc, mul128(y[k], cst[(size_t)k * L + i]));
-    conv[((size_t)mc * Lc + i) * n + x] = redc(acc, mods[i], qinv[i]);
+    const int i1 = (i0 + CONV_ROWS) < Lc ? (i0 + CONV_ROWS) : Lc;
+    for (int i = i0; i < i1; i++) {
+        u128p acc{0, 0};
+        for (int k = 0; k < K; k++) add128(acc, mul128(y[k], cst[(size_t)k * L + i]));
+        conv[((size_t)mc * Lc + i) * n + x] = redc(acc, mods[i], qinv[i]);
+    }
 }
 
 void kb_conv(const Ctx& c, uint64_t* conv, const uint64_t* T, int M, int Lc, hipStream_t st) {
-    hipLaunchKernelGGL(kb_conv_kernel, ew_grid(c.n, Lc, 2 * M), dim3(EW_THREADS), 0, st, conv, T, c.d_mods,
-                       c.d_qinv, c.d_moddown_inv, c.d_moddown_c, c.n, c.L, Lc, c.K);
+    hipLaunchKernelGGL(kb_conv_kernel, ew_grid(c.n, (Lc + CONV_ROWS - 1) / CONV_ROWS, 2 * M), dim3(EW_THREADS), 0,
+                       st, conv, T, c.d_mods, c.d_qinv, c.d_moddown_inv, c.d_moddown_c, c.n, c.L, Lc, c.K);
 }
 
 // out_m = (sigma_k(c0_m) + (T0 - conv0) P^-1, (T1 - conv1) P^-1)   (NTT domain, level Lc)
@@ -374,29 +380,46 @@ void k_sum_cts(const Ctx& c, uint64_t* y, const uint64_t* src, int groups, int c
 
 // conv[c][i][x] = sum_{j dropped} [ct_j(x) (D/q_j)^-1]_{q_j} (D/q_j) mod q_i  for kept i < Lc;
 // ct [count][2][L][n] with the dropped rows Lc..L-1 in the coefficient domain; blockIdx.z = t*2+comp.
+// A thread covers CONV_ROWS consecutive kept primes: each dropped residue is read and
+// scaled once.
 __global__ void ms_conv_kernel(uint64_t* __restrict__ conv, const uint64_t* __restrict__ ct,
                                const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv,
                                const uint64_t* __restrict__ inv, const uint64_t* __restrict__ cst,
                                int n, int L, int Lc, int fold) {
     int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
-    const int tc = blockIdx.z, i = blockIdx.y, nd = L - Lc;
-    const uint64_t qi = mods[i], qii = qinv[i];
+    const int tc = blockIdx.z, i0 = blockIdx.y * CONV_ROWS, nd = L - Lc;
+    const int ni = (Lc - i0) < CONV_ROWS ? (Lc - i0) : CONV_ROWS;
     const uint64_t* cc = ct + (size_t)tc * L * n;
-    u128p acc{0, 0};
-    uint64_t sum = 0;
+    u128p acc[CONV_ROWS];
+    uint64_t sum[CONV_ROWS];
+    #pragma unroll
+    for (int u = 0; u < CONV_ROWS; u++) { acc[u] = u128p{0, 0}; sum[u] = 0; }
     int terms = 0;
     for (int j = 0; j < nd; j++) {
         const int r = Lc + j;
-        uint64_t y = shoup(cc[(size_t)r * n + x], inv[2 * j], inv[2 * j + 1], mods[r]);
-        add128(acc, mul128(y, cst[(size_t)j * Lc + i]));
+        const uint64_t y = shoup(cc[(size_t)r * n + x], inv[2 * j], inv[2 * j + 1], mods[r]);
+        const uint64_t* cj = cst + (size_t)j * Lc + i0;
+        #pragma unroll
+        for (int u = 0; u < CONV_ROWS; u++)
+            if (u < ni) add128(acc[u], mul128(y, cj[u]));
         if (++terms == fold) {  // keep each 128-bit sum below q_i 2^64
-            sum = add_mod(sum, redc(acc, qi, qii), qi);
-            acc = u128p{0, 0};
+            #pragma unroll
+            for (int u = 0; u < CONV_ROWS; u++)
+                if (u < ni) {
+                    const uint64_t q = mods[i0 + u];
+                    sum[u] = add_mod(sum[u], redc(acc[u], q, qinv[i0 + u]), q);
+                    acc[u] = u128p{0, 0};
+                }
             terms = 0;
         }
     }
-    conv[((size_t)tc * Lc + i) * n + x] = add_mod(sum, redc(acc, qi, qii), qi);
+    #pragma unroll
+    for (int u = 0; u < CONV_ROWS; u++)
+        if (u < ni) {
+            const int i = i0 + u;
+            conv[((size_t)tc * Lc + i) * n + x] = add_mod(sum[u], redc(acc[u], mods[i], qinv[i]), mods[i]);
+        }
 }
 
 // out[t][c][i] = (ct[t][c][i] - conv[t][c][i]) D^-1 mod q_i (NTT domain), out at level Lc
@@ -416,7 +439,8 @@ void k_ms_conv(const Ctx& c, uint64_t* conv, const uint64_t* ct, const uint64_t*
     uint64_t qmax = 0;
     for (int i = 0; i < c.L; i++) qmax = qmax > c.primes[i] ? qmax : c.primes[i];
     int fold = (int)std::min<uint64_t>(1024, (~0ull) / qmax);
-    hipLaunchKernelGGL(ms_conv_kernel, ew_grid(c.n, Lc, 2 * count), dim3(EW_THREADS), 0, st, conv, ct,
+    hipLaunchKernelGGL(ms_conv_kernel, ew_grid(c.n, (Lc + CONV_ROWS - 1) / CONV_ROWS, 2 * count), dim3(EW_THREADS),
+                       0, st, conv, ct,
                        c.d_mods, c.d_qinv, inv, cst, c.n, c.L, Lc, fold < 1 ? 1 : fold);
 }
 
@@ -777,6 +801,15 @@ __global__ void diag_gather_kernel(uint64_t* __restrict__ Rt, const uint64_t* co
 #define HC_RSRC_WORD3 0x00020000
 typedef __attribute__((address_space(3))) void lds_void_t;
 
+// f(integral_constant<int, i>) for i = B..E-1, unrolled at compile time
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
 // a wave-uniform pointer, held in scalar registers
 __device__ __forceinline__ void* uniform_ptr(const void* p) {
     const uint64_t v = (uint64_t)p;
@@ -915,27 +948,14 @@ __global__ __launch_bounds__(256) void diag_mac_kernel(uint64_t* const* __restri
             if constexpr (ACT) compute(buf, slot_c);
             __builtin_amdgcn_sched_barrier(0);
         };
-        using S0 = std::integral_constant<int, 0>;
-        using S1 = std::integral_constant<int, 1>;
-        using S2 = std::integral_constant<int, 2>;
-        using S3 = std::integral_constant<int, 3>;
-        static_assert(NS == 4, "the stage loop below is written out for four slots");
-        stage_loads(0, S0{});
-        stage_loads(1, S1{});
-        stage_loads(2, S2{});
+        static_for<0, NS - 1>([&](auto i_c) __attribute__((always_inline)) { stage_loads(i_c.value, i_c); });
         for (int s = 0; s < nst; s += NS) {
-            wait_stage();
-            stage_loads(s + 3, S3{});
-            mul(0, S0{});
-            wait_stage();
-            stage_loads(s + 4, S0{});
-            mul(1, S1{});
-            wait_stage();
-            stage_loads(s + 5, S1{});
-            mul(2, S2{});
-            wait_stage();
-            stage_loads(s + 6, S2{});
-            mul(3, S3{});
+            static_for<0, NS>([&](auto i_c) __attribute__((always_inline)) {
+                constexpr int i = decltype(i_c)::value;
+                wait_stage();
+                stage_loads(s + i + NS - 1, std::integral_constant<int, (i + NS - 1) % NS>{});
+                mul(i, i_c);
+            });
         }
     };
     if (active) run(std::true_type{});
