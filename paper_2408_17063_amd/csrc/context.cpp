@@ -359,6 +359,7 @@ extern "C" hc_status hc_context_create(const hc_params* prm, int device, hc_cont
     UP(c.d_pmodq, pmodq);
     UP(c.d_delta, delta);
 #undef UP
+    if ((st = ntt_build_tw2(c)) != HC_OK) { hc_context_destroy(cp); return st; }
     if ((st = upload_keccak_constants(rc, rho, c.h_cdt.data())) != HC_OK) { hc_context_destroy(cp); return st; }
 
     // ---- row masks [1;0] and [0;1] as plaintext multipliers

@@ -74,6 +74,7 @@ struct hc_context {
     uint64_t* d_qinv = nullptr;     // [nq] -q^-1 mod 2^64
     uint64_t* d_r2 = nullptr;       // [nq] 2^128 mod q
     uint64_t* d_tw = nullptr;       // [nq][2][n][2]: (w, w') forward then inverse
+    uint64_t* d_tw2 = nullptr;      // low-bit NTT pass twiddles in thread order (rings above 2^12)
     uint64_t* d_ninv = nullptr;     // [nq][2]
     uint32_t* d_modp = nullptr;     // [1] p
     uint32_t* d_twp = nullptr;      // [2][n][2] mod p
@@ -184,6 +185,8 @@ void ntt64(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb
            bool inverse, hipStream_t stream);
 // mod-p transforms of `count` contiguous length-n rows.
 void ntt32(const Ctx& c, uint32_t* data, int count, bool inverse, hipStream_t stream);
+// builds d_tw2 from d_tw (context creation; synchronises the device)
+hc_status ntt_build_tw2(Ctx& c);
 
 // ------------------------------------------------------------------ kernels (ops.hip)
 // All arrays are [rows][n] per polynomial; "nl" rows starting at prime index lf.

@@ -60,10 +60,13 @@ template <typename T> struct NttTab {
     const T* base;  // [nprime][2][n][2]
     const T* ninv;  // [nprime][2]
     const T* mods;  // [nprime]
+    const T* tw2;   // low-bit pass twiddles in thread order (rings above one tile), or nullptr
 };
 
 constexpr int TILE_LOG = 12;
-constexpr int NTT_THREADS = 256;
+constexpr int NTT_EPT_LOG = 4;                          // elements per thread: 2^NTT_EPT_LOG
+constexpr int NTT_EPT = 1 << NTT_EPT_LOG;
+constexpr int NTT_THREADS = (1 << TILE_LOG) / NTT_EPT;  // block size for full tiles
 
 __device__ __forceinline__ uint32_t insert_bits(uint32_t g, uint32_t v, int pos, int width) {
     uint32_t lowmask = (1u << pos) - 1u;
@@ -77,6 +80,22 @@ struct Tile {
     static constexpr int LOGP = TLOG - S;
     static constexpr int P = 1 << LOGP;
     static constexpr int N = 1 << LOGN;
+    static constexpr int THREADS = TSIZE / NTT_EPT;
+    // The pass over the low index bits of a two-pass ring reads twiddles that differ
+    // from thread to thread (up to one per butterfly in the last stages). They come
+    // from a copy of the table laid out in the order the threads consume them,
+    // [tile][ord][thread], so each load instruction reads one contiguous run.
+    static constexpr bool TW2 = sizeof(T) == 8 && BLO == 0 && LOGN > TILE_LOG;
+    static constexpr int round_r(int done) { return (S - done) >= NTT_EPT_LOG ? NTT_EPT_LOG : (S - done); }
+    static constexpr int round_tw(int r) { return (NTT_EPT >> r) * ((1 << r) - 1); }
+    static constexpr int tw_before(int done) {
+        int o = 0;
+        for (int d = 0; d < done; d += round_r(d)) o += round_tw(round_r(d));
+        return o;
+    }
+    static constexpr int TW_PASS = tw_before(S);  // twiddle pairs per thread over the pass
+    // position of twiddle t of stage u in a round of r stages, within a group's run
+    static constexpr int tw_off(int r, int u) { return INV ? (1 << r) - (1 << (r - u)) : (1 << u) - 1; }
 
     // global index of tile element e = (k << LOGP) | spl, sub-problem base sp0
     static __device__ __forceinline__ uint32_t gidx(uint32_t e, uint32_t sp0) {
@@ -87,10 +106,10 @@ struct Tile {
 
     // one round of R stages; butterfly bits [KBIT, KBIT+R) of k; DONE stages before it
     template <int R, int KBIT, int DONE>
-    static __device__ __forceinline__ void round(T* lds, uint32_t sp0, const T* tw, T q) {
+    static __device__ __forceinline__ void round(T* lds, uint32_t sp0, const T* tw, const T* tw2, T q) {
         constexpr int POS = LOGP + KBIT;
         constexpr int GS = 1 << R;
-        constexpr int PER = 16 >> R;  // groups per thread
+        constexpr int PER = NTT_EPT >> R;  // groups per thread
         #pragma unroll
         for (int sub = 0; sub < PER; sub++) {
             const uint32_t g = threadIdx.x * PER + sub;
@@ -108,7 +127,14 @@ struct Tile {
                     const uint32_t base = (1u << st) + (j0 >> (LOGN - st));
                     T w[8], wp[8];
                     #pragma unroll
-                    for (int t = 0; t < (1 << u); t++) Ar<T>::load_pair(tw + 2 * (base + t), w[t], wp[t]);
+                    for (int t = 0; t < (1 << u); t++) {
+                        if constexpr (TW2)
+                            Ar<T>::load_pair(tw2 + 2 * ((size_t)(tw_before(DONE) + sub * ((1 << R) - 1) +
+                                                                 tw_off(R, u) + t) * THREADS + threadIdx.x),
+                                             w[t], wp[t]);
+                        else
+                            Ar<T>::load_pair(tw + 2 * (base + t), w[t], wp[t]);
+                    }
                     #pragma unroll
                     for (int v = 0; v < GS; v++) {
                         if (!(v & half)) {
@@ -125,8 +151,14 @@ struct Tile {
                     const uint32_t base = ((uint32_t)N >> (st + 1)) + (j0 >> (st + 1));
                     T w[8], wp[8];
                     #pragma unroll
-                    for (int t = 0; t < (1 << (R - 1 - u)); t++)
-                        Ar<T>::load_pair(tw + 2 * (base + t), w[t], wp[t]);
+                    for (int t = 0; t < (1 << (R - 1 - u)); t++) {
+                        if constexpr (TW2)
+                            Ar<T>::load_pair(tw2 + 2 * ((size_t)(tw_before(DONE) + sub * ((1 << R) - 1) +
+                                                                 tw_off(R, u) + t) * THREADS + threadIdx.x),
+                                             w[t], wp[t]);
+                        else
+                            Ar<T>::load_pair(tw + 2 * (base + t), w[t], wp[t]);
+                    }
                     #pragma unroll
                     for (int v = 0; v < GS; v++) {
                         if (!(v & half)) {
@@ -145,13 +177,42 @@ struct Tile {
 
     // rounds: forward processes k bits from the top down, inverse from the bottom up
     template <int DONE>
-    static __device__ __forceinline__ void rounds(T* lds, uint32_t sp0, const T* tw, T q) {
+    static __device__ __forceinline__ void rounds(T* lds, uint32_t sp0, const T* tw, const T* tw2, T q) {
         if constexpr (DONE < S) {
-            constexpr int R = (S - DONE) >= 4 ? 4 : (S - DONE);
+            constexpr int R = round_r(DONE);
             constexpr int KBIT = INV ? DONE : (S - DONE - R);
-            round<R, KBIT, DONE>(lds, sp0, tw, q);
+            round<R, KBIT, DONE>(lds, sp0, tw, tw2, q);
             __syncthreads();
-            rounds<DONE + R>(lds, sp0, tw, q);
+            rounds<DONE + R>(lds, sp0, tw, tw2, q);
+        }
+    }
+
+    // Writes this thread's twiddles of the pass, in consumption order, to
+    // out[ord][THREADS] (pairs): the same indices round() computes.
+    template <int DONE>
+    static __device__ __forceinline__ void emit(T* out, uint32_t sp0, const T* tw) {
+        if constexpr (DONE < S) {
+            constexpr int R = round_r(DONE);
+            constexpr int KBIT = INV ? DONE : (S - DONE - R);
+            constexpr int POS = LOGP + KBIT;
+            constexpr int PER = NTT_EPT >> R;
+            for (int sub = 0; sub < PER; sub++) {
+                const uint32_t g = threadIdx.x * PER + sub;
+                const uint32_t j0 = gidx(insert_bits(g, 0, POS, R), sp0);
+                for (int u = 0; u < R; u++) {
+                    const int st = ST0 + DONE + u;
+                    const uint32_t base = INV ? ((uint32_t)N >> (st + 1)) + (j0 >> (st + 1))
+                                              : (1u << st) + (j0 >> (LOGN - st));
+                    const int cnt = INV ? (1 << (R - 1 - u)) : (1 << u);
+                    for (int t = 0; t < cnt; t++) {
+                        const size_t o = 2 * ((size_t)(tw_before(DONE) + sub * ((1 << R) - 1) + tw_off(R, u) + t) *
+                                                  THREADS + threadIdx.x);
+                        out[o] = tw[2 * (base + t)];
+                        out[o + 1] = tw[2 * (base + t) + 1];
+                    }
+                }
+            }
+            emit<DONE + R>(out, sp0, tw);
         }
     }
 };
@@ -168,10 +229,10 @@ ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab
     T* a = data + (size_t)blockIdx.z * poly_stride + (size_t)row * TL::N;
     const uint32_t sp0 = blockIdx.x * TL::P;
 
-    constexpr int THREADS = TL::TSIZE / 16;  // the launch's block size
+    constexpr int THREADS = TL::TSIZE / NTT_EPT;  // the launch's block size
     // load in global-contiguous order
     #pragma unroll
-    for (int i = 0; i < 16; i++) {
+    for (int i = 0; i < NTT_EPT; i++) {
         const uint32_t f = threadIdx.x + i * THREADS;
         uint32_t k, spl;
         if (BLO == 0) { spl = f >> S; k = f & ((1u << S) - 1u); }
@@ -180,11 +241,15 @@ ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab
         lds[e] = a[TL::gidx(e, sp0)];
     }
     __syncthreads();
-    TL::template rounds<0>(lds, sp0, tw, q);
+    const T* tw2 = nullptr;
+    if constexpr (TL::TW2)
+        tw2 = tab.tw2 + (((size_t)prime * 2 + (INV ? 1 : 0)) * gridDim.x + blockIdx.x) * (size_t)TL::TW_PASS *
+                            TL::THREADS * 2;
+    TL::template rounds<0>(lds, sp0, tw, tw2, q);
 
     const T* ni = tab.ninv + 2 * prime;
     #pragma unroll
-    for (int i = 0; i < 16; i++) {
+    for (int i = 0; i < NTT_EPT; i++) {
         const uint32_t f = threadIdx.x + i * THREADS;
         uint32_t k, spl;
         if (BLO == 0) { spl = f >> S; k = f & ((1u << S) - 1u); }
@@ -204,7 +269,7 @@ template <typename T, bool INV, int LOGN, int S, int BLO, int ST0, bool LAST>
 static void pass(const Ctx& c, int kind, T* data, size_t stride, int count, int lf, int nl,
                  NttTab<T> tab, hipStream_t st) {
     constexpr int TLOG = LOGN < TILE_LOG ? LOGN : TILE_LOG;
-    constexpr int THREADS = (1 << TLOG) / 16;
+    constexpr int THREADS = (1 << TLOG) / NTT_EPT;
     static_assert(THREADS <= NTT_THREADS, "tile");
     dim3 grid(1 << (LOGN - TLOG), nl, count);
     const double bytes = 2.0 * sizeof(T) * (double)count * nl * (1 << LOGN);
@@ -251,17 +316,56 @@ static void run_ntt(const Ctx& c, int kind, T* data, size_t stride, int count, i
     }
 }
 
+// Thread-ordered twiddles of the low-bit pass of each direction (see Tile::TW2):
+// out[prime][dir][tile][TW_PASS][THREADS][2], one block per (tile, prime).
+template <bool INV, int LOGN>
+__global__ void __launch_bounds__(NTT_THREADS) ntt_tw2_kernel(uint64_t* __restrict__ out,
+                                                              const uint64_t* __restrict__ tw_all) {
+    typedef Tile<uint64_t, INV, LOGN, 8, 0, INV ? 0 : LOGN - 8> TL;
+    const int prime = blockIdx.y;
+    const uint64_t* tw = tw_all + ((size_t)prime * 2 + (INV ? 1 : 0)) * 2 * TL::N;
+    uint64_t* o = out + (((size_t)prime * 2 + (INV ? 1 : 0)) * gridDim.x + blockIdx.x) * (size_t)TL::TW_PASS *
+                            TL::THREADS * 2;
+    TL::template emit<0>(o, blockIdx.x * TL::P, tw);
+}
+
+template <int LOGN>
+static hc_status build_tw2_logn(Ctx& c) {
+    typedef Tile<uint64_t, false, LOGN, 8, 0, LOGN - 8> TF;
+    typedef Tile<uint64_t, true, LOGN, 8, 0, 0> TI;
+    static_assert(TF::TW2 && TI::TW2 && TF::TW_PASS == TI::TW_PASS, "low-bit passes");
+    const int tiles = 1 << (LOGN - TILE_LOG);
+    const size_t words = (size_t)c.nq * 2 * tiles * TF::TW_PASS * TF::THREADS * 2;
+    HC_CHECK(hipMalloc((void**)&c.d_tw2, sizeof(uint64_t) * words));
+    c.owned.push_back(c.d_tw2);
+    hipLaunchKernelGGL((ntt_tw2_kernel<false, LOGN>), dim3(tiles, c.nq), dim3(TF::THREADS), 0, 0, c.d_tw2, c.d_tw);
+    hipLaunchKernelGGL((ntt_tw2_kernel<true, LOGN>), dim3(tiles, c.nq), dim3(TI::THREADS), 0, 0, c.d_tw2, c.d_tw);
+    HC_CHECK(hipGetLastError());
+    HC_CHECK(hipDeviceSynchronize());
+    return HC_OK;
+}
+
+hc_status ntt_build_tw2(Ctx& c) {
+    switch (c.logn) {
+        case 13: return build_tw2_logn<13>(c);
+        case 14: return build_tw2_logn<14>(c);
+        case 15: return build_tw2_logn<15>(c);
+        case 16: return build_tw2_logn<16>(c);
+        default: return HC_OK;  // one-pass rings read the table directly
+    }
+}
+
 void ntt64(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb_first, int nlimbs,
            bool inverse, hipStream_t stream) {
     if (count <= 0 || nlimbs <= 0) return;
-    NttTab<uint64_t> tab{c.d_tw, c.d_ninv, c.d_mods};
+    NttTab<uint64_t> tab{c.d_tw, c.d_ninv, c.d_mods, c.d_tw2};
     if (inverse) run_ntt<uint64_t, true>(c, HC_KT_NTT_INV, data, poly_stride, count, limb_first, nlimbs, tab, stream);
     else run_ntt<uint64_t, false>(c, HC_KT_NTT_FWD, data, poly_stride, count, limb_first, nlimbs, tab, stream);
 }
 
 void ntt32(const Ctx& c, uint32_t* data, int count, bool inverse, hipStream_t stream) {
     if (count <= 0) return;
-    NttTab<uint32_t> tab{c.d_twp, c.d_ninvp, c.d_modp};
+    NttTab<uint32_t> tab{c.d_twp, c.d_ninvp, c.d_modp, nullptr};
     if (inverse) run_ntt<uint32_t, true>(c, -1, data, (size_t)c.n, count, 0, 1, tab, stream);
     else run_ntt<uint32_t, false>(c, -1, data, (size_t)c.n, count, 0, 1, tab, stream);
 }
