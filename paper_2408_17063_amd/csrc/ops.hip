@@ -918,10 +918,14 @@ __global__ __launch_bounds__(256) void diag_mac_kernel(uint64_t* const* __restri
                 const uint32_t dl = (uint32_t)d, dh = (uint32_t)(d >> 32);
                 lo[g][0] += (uint64_t)r0l * dl;
                 mid[g][0] += (uint64_t)r0l * dh;
+                // keeps the two middle products as two multiply-adds into the sum
+                // (the compiler would otherwise add them first and then add the pair)
+                asm("" : "+v"(mid[g][0]));
                 mid[g][0] += (uint64_t)r0h * dl;
                 hi[g][0] += (uint64_t)r0h * dh;
                 lo[g][1] += (uint64_t)r1l * dl;
                 mid[g][1] += (uint64_t)r1l * dh;
+                asm("" : "+v"(mid[g][1]));
                 mid[g][1] += (uint64_t)r1h * dl;
                 hi[g][1] += (uint64_t)r1h * dh;
             }
