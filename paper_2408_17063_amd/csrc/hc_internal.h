@@ -284,9 +284,12 @@ void k_diag_tile(const Ctx& c, uint64_t* out, const uint64_t* in, size_t i0, int
                  uint32_t B, uint32_t dG, int Lc, hipStream_t st);
 // words v -> (v >> h) 2^32 + (v mod 2^h), h = ceil(bits of the largest of the first Lc primes / 2)
 void k_diag_split(const Ctx& c, uint64_t* d, size_t words, int Lc, hipStream_t st);
-// TA[g] += sum of the jobs' key products T, C0A[g] += sum of their rotated c0, per range
-void kb_accum(const Ctx& c, uint64_t* TA, uint64_t* C0A, const uint64_t* T, const KsJob* jobs,
-              const KsGroupRange* ranges, const uint32_t* members, int nranges, int Lc, hipStream_t st);
+// TA[g] += sum of the jobs' key products (raised digits X times their keys, over PQ),
+// C0A[g] += sum of their rotated c0, per group range of a pass of M jobs with nkeys
+// distinct keys
+void kb_inner_sum(const Ctx& c, uint64_t* TA, uint64_t* C0A, const uint64_t* X, const KsJob* jobs,
+                  const KsGroupRange* ranges, const uint32_t* members, int nranges, int M, int nkeys, int Lc,
+                  hipStream_t st);
 // p[0..words) = 0 (a kernel, so it can sit in a captured graph)
 void k_zero(const Ctx& c, uint64_t* p, size_t words, hipStream_t st);
 // terms of the gathered rotated ciphertexts per pair: J rounded up to whole rounds of

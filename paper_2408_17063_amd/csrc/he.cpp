@@ -214,8 +214,8 @@ hc_status ks_run(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
 // Sums of plain rotations, one ModDown per sum: for each group g, outs[g] = sum of
 // Rot_k(in) over the jobs with group[i] == g, whose key products are added over PQ
 // (TA, groups x [2][Lc+K][n]) and whose rotated c0 are added (C0A, groups x [Lc][n])
-// before a single ModDown. Passes run in key order; every sum is exact, so the order
-// does not change a result.
+// before a single ModDown. Passes run in key order (jobs of one pass that share a key
+// read it together); every sum is exact, so the order does not change a result.
 hc_status ks_run_sum(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
                      const std::vector<uint32_t>& group, const std::vector<uint64_t*>& outs, uint64_t* TA,
                      uint64_t* C0A, int Lc, hipStream_t st) {
@@ -248,15 +248,14 @@ hc_status ks_run_sum(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jo
             if (rg.empty() || rg.back().g != g) rg.push_back(KsGroupRange{g, (uint32_t)i, (uint32_t)i + 1, 0});
             else rg.back().j1 = (uint32_t)i + 1;
         }
+        int nkeys = 0;
+        for (int i = 0; i < M; i++) nkeys += (i == 0 || jb[i].key != jb[i - 1].key) ? 1 : 0;
         const KsJob* d = (const KsJob*)stage_bytes(l, jb.data(), sizeof(KsJob) * M, st);
         const KsGroupRange* dg = (const KsGroupRange*)stage_bytes(l, rg.data(), sizeof(KsGroupRange) * rg.size(), st);
         const uint32_t* dm = (const uint32_t*)stage_bytes(l, members.data(), sizeof(uint32_t) * M, st);
-        int nruns = 0;
-        const KsRun* dr = stage_runs(l, jb, &nruns, st);
-        if (!d || !dg || !dm || !dr) return HC_ENOMEM;
+        if (!d || !dg || !dm) return HC_ENOMEM;
         ks_raise(c, s, d, M, Lc, true, st);
-        kb_inner(c, s.T, s.X, d, dr, nruns, M, Lc, false, st);
-        kb_accum(c, TA, C0A, s.T, d, dg, dm, (int)rg.size(), Lc, st);
+        kb_inner_sum(c, TA, C0A, s.X, d, dg, dm, (int)rg.size(), M, nkeys, Lc, st);
     }
     // one ModDown per group (TA is consumed in place)
     for (size_t g0 = 0; g0 < G; g0 += s.maxM) {

@@ -304,29 +304,55 @@ void kb_final(const Ctx& c, const KsJob* jobs, const uint64_t* T, const uint64_t
                        c.d_mods, c.d_pinv, c.n, c.logn, Lc, c.K);
 }
 
-// Sums of key-switched rotations brought down once: the key products T of the jobs
-// members[j0..j1) of each group are added into TA[g] ([2][Lc+K][n], mod each row's prime)
-// and their rotated c0 into C0A[g] ([Lc][n]). Rows 0..2R-1 are T's, then Lc rows of c0.
-__global__ void kb_accum_kernel(uint64_t* __restrict__ TA, uint64_t* __restrict__ C0A,
-                                const uint64_t* __restrict__ T, const KsJob* __restrict__ jobs,
-                                const KsGroupRange* __restrict__ ranges, const uint32_t* __restrict__ members,
-                                const uint64_t* __restrict__ mods, int n, int logn, int L, int Lc, int K) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+// Key products of rotations summed per group before the group's single ModDown:
+// TA[g][comp][row] += sum over the group's jobs m of X_m[row] * key_m[comp][row] (all
+// digits; X_m is job m's raised, already rotated c1) and C0A[g][i] += sum of the jobs'
+// rotated c0 (rows R..R+Lc-1 of the grid). Per-job products are never written out.
+// The group is the fastest grid index: blocks of all groups at one (tile, row) run
+// together, and the jobs of a pass that share a key (one rotation, different groups)
+// read its words through L2 at the same time. The key is in Montgomery form, so a
+// reduction of a 128-bit sum of at most `fold` products (fold q < 2^64) is the plain
+// sum of those products.
+__global__ void kb_inner_sum_kernel(uint64_t* __restrict__ TA, uint64_t* __restrict__ C0A,
+                                    const uint64_t* __restrict__ X, const KsJob* __restrict__ jobs,
+                                    const KsGroupRange* __restrict__ ranges, const uint32_t* __restrict__ members,
+                                    const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv, int n,
+                                    int logn, int nq, int L, int Lc, int K, int dn, int fold) {
+    const int x = blockIdx.y * blockDim.x + threadIdx.x;
     if (x >= n) return;
-    const int row = blockIdx.y, R = Lc + K;
-    const KsGroupRange gr = ranges[blockIdx.z];
-    if (row < 2 * R) {
-        const int comp = row / R, rr = row - comp * R;
-        const uint64_t q = mods[row_prime(rr, Lc, L)];
-        uint64_t* ta = TA + (((size_t)gr.g * 2 + comp) * R + rr) * n + x;
-        uint64_t acc = *ta;
+    const int row = blockIdx.z, R = Lc + K;
+    const KsGroupRange gr = ranges[blockIdx.x];
+    if (row < R) {
+        const int pr = row_prime(row, Lc, L);
+        const uint64_t q = mods[pr], qi = qinv[pr];
+        const size_t keyrow = (size_t)nq * n;
+        u128p a0{0, 0}, a1{0, 0};
+        uint64_t s0 = 0, s1 = 0;
+        int terms = 0;
         for (uint32_t u = gr.j0; u < gr.j1; u++) {
-            const uint32_t m = members[u];
-            acc = add_mod(acc, T[(((size_t)m * 2 + comp) * R + rr) * n + x], q);
+            const KsJob jb = jobs[members[u]];
+            const uint64_t* kp = jb.key + (size_t)pr * n + x;
+            const uint64_t* xp = X + ((size_t)jb.xidx * dn * R + row) * n + x;
+            for (int j = 0; j < dn; j++) {
+                const uint64_t xv = xp[(size_t)j * R * n];
+                add128(a0, mul128(xv, kp[(size_t)j * 2 * keyrow]));
+                add128(a1, mul128(xv, kp[(size_t)j * 2 * keyrow + keyrow]));
+                if (++terms == fold) {
+                    s0 = add_mod(s0, redc(a0, q, qi), q);
+                    s1 = add_mod(s1, redc(a1, q, qi), q);
+                    a0 = u128p{0, 0};
+                    a1 = u128p{0, 0};
+                    terms = 0;
+                }
+            }
         }
-        *ta = acc;
+        s0 = add_mod(s0, redc(a0, q, qi), q);
+        s1 = add_mod(s1, redc(a1, q, qi), q);
+        uint64_t* ta = TA + ((size_t)gr.g * 2 * R + row) * n + x;
+        ta[0] = add_mod(ta[0], s0, q);
+        ta[(size_t)R * n] = add_mod(ta[(size_t)R * n], s1, q);
     } else {
-        const int i = row - 2 * R;
+        const int i = row - R;
         const uint64_t q = mods[i];
         uint64_t* ca = C0A + ((size_t)gr.g * Lc + i) * n + x;
         uint64_t acc = *ca;
@@ -339,11 +365,21 @@ __global__ void kb_accum_kernel(uint64_t* __restrict__ TA, uint64_t* __restrict_
     }
 }
 
-void kb_accum(const Ctx& c, uint64_t* TA, uint64_t* C0A, const uint64_t* T, const KsJob* jobs,
-              const KsGroupRange* ranges, const uint32_t* members, int nranges, int Lc, hipStream_t st) {
-    const int R = Lc + c.K;
-    hipLaunchKernelGGL(kb_accum_kernel, ew_grid(c.n, 2 * R + Lc, nranges), dim3(EW_THREADS), 0, st, TA, C0A, T,
-                       jobs, ranges, members, c.d_mods, c.n, c.logn, c.L, Lc, c.K);
+void kb_inner_sum(const Ctx& c, uint64_t* TA, uint64_t* C0A, const uint64_t* X, const KsJob* jobs,
+                  const KsGroupRange* ranges, const uint32_t* members, int nranges, int M, int nkeys, int Lc,
+                  hipStream_t st) {
+    const int R = Lc + c.K, dn = Lc / c.alpha;
+    uint64_t qmax = 0;
+    for (int i = 0; i < c.nq; i++) qmax = qmax > c.primes[i] ? qmax : c.primes[i];
+    const int fold = (int)std::min<uint64_t>(1024, (~0ull) / qmax);
+    // the distinct keys once, each job's raised digits and rotated c0 once, the sums read and written
+    const double n = c.n;
+    TimeScope ts(c, HC_KT_KS_INNER, st,
+                 8.0 * n * ((double)nkeys * 2 * dn * R + (double)M * (dn * R + Lc) + (double)nranges * 2 * (2 * R + Lc)),
+                 2.0 * dn * R * n * M);
+    hipLaunchKernelGGL(kb_inner_sum_kernel, dim3(nranges, (c.n + EW_THREADS - 1) / EW_THREADS, R + Lc),
+                       dim3(EW_THREADS), 0, st, TA, C0A, X, jobs, ranges, members, c.d_mods, c.d_qinv, c.n, c.logn,
+                       c.nq, c.L, Lc, c.K, dn, fold < 1 ? 1 : fold);
 }
 
 __global__ void zero_words_kernel(uint64_t* __restrict__ p, size_t words) {
