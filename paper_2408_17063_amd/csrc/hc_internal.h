@@ -203,15 +203,13 @@ void k_mul_plain(const Ctx& c, uint64_t* out, const uint64_t* ct, const uint64_t
                  hipStream_t st);
 // ModUp of all digits: X [dnum][nq][n] (coefficient domain) from x [L][n] (coefficient domain).
 // ---- batched key switching (compact rows: Lc ciphertext primes, then K special primes)
-// tmpC[m] = c1 of job m's input (permuted by sigma_k unless k = 1), [M][Lc][n]
-void kb_take_c1(const Ctx& c, uint64_t* tmpC, const KsJob* jobs, int M, int Lc, bool permute,
-                hipStream_t st);
+// tmpC[m] = c1 of job m's input (permuted by sigma_k unless k = 1), [M][Lc][n], NTT
+// domain; the same rows also into the digits' own rows of X [M][dn][Lc+K][n]
+void kb_take_c1(const Ctx& c, uint64_t* tmpC, uint64_t* X, const KsJob* jobs, int M, int Lc, hipStream_t st);
 // X [U][dn][Lc+K][n] raised digits of the coefficient-domain tmpC [U][Lc][n]
 // ModUp of U sources [Lc][n] (coefficient domain) into digits X[U][dn][Lc+K][n]; a
 // digit's own rows are written only if own_rows.
 void kb_modup(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, bool own_rows, hipStream_t st);
-// the digits' own rows of X from the NTT-domain sources
-void kb_own_rows(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, hipStream_t st);
 // T [M][2][Lc+K][n] = sum_j X[xidx_m][j] (rotated by k_m if hoisted) * key_m[j]
 void kb_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const KsJob* jobs, const KsRun* runs, int nruns, int M,
               int Lc, bool hoisted, hipStream_t st);

@@ -116,8 +116,8 @@ KsScratch ks_scratch(Ctx& c, Arena& a, int Lc, int max_jobs) {
 static void ks_raise(Ctx& c, KsScratch& s, const KsJob* d, int U, int Lc, bool permute, hipStream_t st) {
     const size_t n = c.n;
     const int R = Lc + c.K, dn = Lc / c.alpha, a = c.alpha;
-    kb_take_c1(c, s.tmpC, d, U, Lc, permute, st);
-    kb_own_rows(c, s.X, s.tmpC, U, Lc, st);
+    (void)permute;  // jobs carry their element (k = 1: no rotation)
+    kb_take_c1(c, s.tmpC, s.X, d, U, Lc, st);
     ntt64(c, s.tmpC, (size_t)Lc * n, U, 0, Lc, true, st);
     kb_modup(c, s.X, s.tmpC, U, Lc, false, st);
     for (int j = 0; j < dn; j++) {

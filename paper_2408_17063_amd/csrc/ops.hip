@@ -125,21 +125,25 @@ void k_from_mont(const Ctx& c, uint64_t* x, int lf, int nl, int count, size_t st
 __device__ __forceinline__ int row_prime(int row, int Lc, int L) { return row < Lc ? row : L + row - Lc; }
 
 // tmpC[m] = c1 of job m's input, permuted by sigma_{k_m} (k = 1: plain copy)
-__global__ void kb_take_c1_kernel(uint64_t* __restrict__ tmpC, const KsJob* __restrict__ jobs, int n,
-                                  int logn, int Lc) {
+__global__ void kb_take_c1_kernel(uint64_t* __restrict__ tmpC, uint64_t* __restrict__ X,
+                                  const KsJob* __restrict__ jobs, int n, int logn, int Lc, int alpha, int R,
+                                  int dn) {
     int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     const KsJob jb = jobs[blockIdx.z];
     const uint32_t src = (jb.k == 1) ? x : galois_src(x, jb.k, logn);
-    const size_t r = blockIdx.y;
-    tmpC[((size_t)blockIdx.z * Lc + r) * n + x] = jb.in[((size_t)Lc + r) * n + src];
+    const int r = blockIdx.y, u = blockIdx.z;
+    const uint64_t v = jb.in[((size_t)Lc + r) * n + src];
+    tmpC[((size_t)u * Lc + r) * n + x] = v;
+    X[(((size_t)u * dn + r / alpha) * R + r) * n + x] = v;
 }
 
-void kb_take_c1(const Ctx& c, uint64_t* tmpC, const KsJob* jobs, int M, int Lc, bool permute,
-                hipStream_t st) {
-    (void)permute;
-    hipLaunchKernelGGL(kb_take_c1_kernel, ew_grid(c.n, Lc, M), dim3(EW_THREADS), 0, st, tmpC, jobs, c.n,
-                       c.logn, Lc);
+// tmpC[u] = c1 of job u (rotated by its element), NTT domain, and the same rows into
+// X[u][j] for the digit j they belong to: ModUp leaves a digit's own residues unchanged,
+// so their transform is the input's.
+void kb_take_c1(const Ctx& c, uint64_t* tmpC, uint64_t* X, const KsJob* jobs, int M, int Lc, hipStream_t st) {
+    hipLaunchKernelGGL(kb_take_c1_kernel, ew_grid(c.n, Lc, M), dim3(EW_THREADS), 0, st, tmpC, X, jobs, c.n,
+                       c.logn, Lc, c.alpha, Lc + c.K, Lc / c.alpha);
 }
 
 // X[u][j] (compact rows) from the coefficient-domain tmpC[u]: the digit's own rows
@@ -180,21 +184,6 @@ void kb_modup(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, bo
     hipLaunchKernelGGL(kb_modup_kernel, ew_grid(c.n, dn, U), dim3(EW_THREADS), 0, st, X, tmpC, c.d_mods,
                        c.d_qinv, c.d_modup_inv, c.d_modup_c, c.n, c.nq, c.alpha, c.L, Lc, c.K, dn,
                        own_rows ? 1 : 0);
-}
-
-// X[u][j][r] = tmpC[u][r] for the rows r of digit j = r / alpha (its own primes), in
-// the NTT domain: ModUp leaves a digit's own residues unchanged, so their transform
-// is the input's.
-__global__ void kb_own_rows_kernel(uint64_t* __restrict__ X, const uint64_t* __restrict__ tmpC, int n,
-                                   int alpha, int Lc, int R, int dn) {
-    int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= n) return;
-    const int r = blockIdx.y, u = blockIdx.z, j = r / alpha;
-    X[(((size_t)u * dn + j) * R + r) * n + x] = tmpC[((size_t)u * Lc + r) * n + x];
-}
-void kb_own_rows(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, hipStream_t st) {
-    hipLaunchKernelGGL(kb_own_rows_kernel, ew_grid(c.n, Lc, U), dim3(EW_THREADS), 0, st, X, tmpC, c.n, c.alpha,
-                       Lc, Lc + c.K, Lc / c.alpha);
 }
 
 // T[m][comp][row][x] = sum_j X[xidx][j][row][src(x)] * key_m[j][comp][prime(row)][x]; the key is
