@@ -204,20 +204,22 @@ hc_status batch_shape(const Ctx& c, const hc_gk* gk, const hc_db* db, std::vecto
         cls_gc[kv.first] = Gc;
         diag_max = std::max(diag_max, (size_t)kb * Gc * B);
     }
-    size_t rt_max = 1;  // gathered rotated ciphertexts of one class
-    for (auto& kv : cls_k)
-        rt_max = std::max(rt_max, (size_t)cls_np[kv.first] * diag_terms_padded((int)(kv.second * kv.first.second)) *
-                                      2 * PW);
+    size_t rt_words = 0;  // the rotated ciphertexts of every class in the MAC's layout
+    for (auto& kv : cls_k) {
+        b.cls_rt[kv.first] = rt_words;
+        rt_words += (size_t)cls_np[kv.first] * diag_terms_padded((int)(kv.second * kv.first.second)) * 2 * PW;
+    }
+    rt_words = std::max<size_t>(rt_words, 1);
     size_t sum_groups = 0;  // giant-step sums (one per pair)
     for (auto& q : qs) sum_groups += (size_t)q.npairs;
     const size_t R = (size_t)Lc + c.K;
-    total += rup(PW * 8 * diag_max) + rup(n * 4 * diag_max) + rup(rt_max * 8) +
+    total += rup(PW * 8 * diag_max) + rup(n * 4 * diag_max) + rup(rt_words * 8) +
              rup(sum_groups * 2 * R * n * 8) + rup(sum_groups * PW * 8) + ks_scratch_bytes(c, Lc, (int)max_jobs);
 
     b.total = total;
     b.max_jobs = max_jobs;
     b.diag_max = diag_max;
-    b.rt_max = rt_max;
+    b.rt_words = rt_words;
     b.sum_groups = sum_groups;
     return HC_OK;
 }
@@ -231,7 +233,7 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
     const size_t n = c.n;
     const int Lc = shape.Lc;
     const size_t PW = (size_t)Lc * n;
-    const size_t total = shape.total, max_jobs = shape.max_jobs, diag_max = shape.diag_max, rt_max = shape.rt_max;
+    const size_t total = shape.total, max_jobs = shape.max_jobs, diag_max = shape.diag_max;
     auto& cls_k = shape.cls_k;
     auto& cls_gc = shape.cls_gc;
     auto& cls_res = shape.cls_res;
@@ -243,7 +245,8 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
         if (q.take(a) != HC_OK) return HC_ENOMEM;
     uint64_t* D = a.take<uint64_t>(PW * diag_max);
     uint32_t* Dp = a.take<uint32_t>(n * diag_max);
-    uint64_t* Rt = a.take<uint64_t>(rt_max);
+    uint64_t* Rt = a.take<uint64_t>(shape.rt_words);
+    uint64_t* const Rt0 = Rt;
     uint64_t* TA = a.take<uint64_t>(std::max<size_t>(1, shape.sum_groups) * 2 * ((size_t)Lc + c.K) * n);
     uint64_t* C0A = a.take<uint64_t>(std::max<size_t>(1, shape.sum_groups) * PW);
     if (!D || !Dp || !Rt || !TA || !C0A) return HC_ENOMEM;
@@ -320,28 +323,43 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
         RUN(ew_run(c, l, add, Lc, false, st));
     }
 
-    // 4. hoisted baby steps Rot_row(u; b), b = 1..B-1, one raise per u-block
+    // Each class (s, B) gathers its pairs' rotated ciphertexts into one region of Rt, in
+    // the multiply-accumulate's layout [Lc][n/64][pair][Jp][2][64] (split words); pair
+    // ci of the class is its ci-th (query, pair) in query order.
+    std::map<std::pair<uint32_t, uint32_t>, uint32_t> cls_seen;
+    for (auto& q : qs) {
+        q.ci.assign(q.npairs, 0);
+        for (int pp = 0; pp < q.npairs; pp++)
+            q.ci[pp] = cls_seen[std::make_pair(q.pl.s, q.pl.groups[pp / q.pl.streams.size()].B)]++;
+    }
+
+    // 4. hoisted baby steps Rot_row(u; b), b = 1..B-1, one raise per u-block; each
+    //    result is written straight into its class's Rt region
     {
         std::vector<const uint64_t*> srcs;
         std::vector<KsJob> jobs;
         for (auto& q : qs) {
-            const size_t CW = q.CW;
             q.R.assign(q.npairs, {});
-            size_t bo = 0;
             int pp = 0;
             for (auto& g : q.pl.groups)
                 for (size_t si = 0; si < q.pl.streams.size(); si++, pp++) {
-                    q.R[pp].assign(g.k, std::vector<uint64_t*>(g.B, nullptr));
+                    const auto key = std::make_pair(q.pl.s, g.B);
+                    const size_t Jp = (size_t)diag_terms_padded((int)(cls_k[key] * g.B));
+                    const size_t np = shape.cls_np[key];
+                    uint64_t* Rc = Rt + shape.cls_rt[key];
+                    q.R[pp].assign(g.k, std::vector<const uint64_t*>(g.B, nullptr));
                     for (uint32_t beta = 0; beta < g.k; beta++) {
                         q.R[pp][beta][0] = q.U[pp][beta];
                         if (g.B == 1) continue;
                         const uint32_t xi = (uint32_t)srcs.size();
                         srcs.push_back(q.U[pp][beta]);
                         for (uint32_t b = 1; b < g.B; b++) {
-                            uint64_t* r = q.bbuf + (bo++) * CW;
                             const uint32_t k = rot_elt(c, b);
-                            jobs.push_back(KsJob{q.U[pp][beta], r, find_key(gk, k), k, xi});
-                            q.R[pp][beta][b] = r;
+                            KsJob jb{q.U[pp][beta], Rc + ((size_t)q.ci[pp] * Jp + beta * g.B + b) * 128,
+                                     find_key(gk, k), k, xi};
+                            jb.tstride = np * Jp * 128;
+                            jobs.push_back(jb);
+                            q.R[pp][beta][b] = kRtInPlace;
                         }
                     }
                 }
@@ -369,11 +387,14 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
                 if (q.pl.s == s && q.pl.groups[pp / q.pl.streams.size()].B == B) cls.push_back({&q, pp});
         const uint32_t G = s / B;
         const size_t np = cls.size();
-        // the class's rotated ciphertexts, gathered once into the MAC's tiled layout
+        uint64_t* Rt = Rt0 + shape.cls_rt[kv.first];
+        // the rest of the class's rotated ciphertexts (the unrotated u-blocks, zero
+        // padding), gathered into its region of the MAC's tiled layout
         std::vector<const uint64_t*> hptr(np * kb * B + np * G, nullptr);
         for (size_t ci = 0; ci < np; ci++) {
             QueryRun& q = *cls[ci].first;
             const int pp = cls[ci].second;
+            if (q.ci[pp] != ci) return HC_EINVAL;  // the pair order phase 4 wrote in
             for (uint32_t beta = 0; beta < q.R[pp].size(); beta++)
                 for (uint32_t b = 0; b < B; b++) hptr[(ci * kb + beta) * B + b] = q.R[pp][beta][b];
             for (uint32_t gi = 0; gi < G; gi++) hptr[np * kb * B + ci * G + gi] = q.A[pp][gi];

@@ -36,10 +36,11 @@ struct QueryRun {
     size_t CW = 0, PW = 0, CWF = 0, ntot = 0, ub = 0, baby = 0, gi = 0;
     int npairs = 0;
     uint64_t *ctf = nullptr, *cts = nullptr, *ubuf = nullptr, *tbuf = nullptr, *rbuf = nullptr,
-             *wbuf = nullptr, *bbuf = nullptr, *gbuf = nullptr, *gout = nullptr, *ybuf = nullptr,
+             *wbuf = nullptr, *gbuf = nullptr, *gout = nullptr, *ybuf = nullptr,
              *ytmp = nullptr, *mbuf = nullptr, *mrot = nullptr, *outN = nullptr;
     std::vector<std::vector<uint64_t*>> U, A;
-    std::vector<std::vector<std::vector<uint64_t*>>> R;
+    std::vector<std::vector<std::vector<const uint64_t*>>> R;  // [pair][u-block][b] (kRtInPlace: in Rt)
+    std::vector<uint32_t> ci;                                    // [pair] index within its (s, B) class
 
     void sizes(const Ctx& c) {
         const size_t n = c.n;
@@ -58,7 +59,7 @@ struct QueryRun {
     size_t bytes(const Ctx& c) const {
         size_t t = rup(CWF * 8 * ntot);
         if (pl.level < c.L) t += 2 * rup(CW * 8 * ntot);
-        t += 4 * rup(CW * 8 * std::max<size_t>(ub, 1)) + rup(CW * 8 * std::max<size_t>(baby, 1));
+        t += 4 * rup(CW * 8 * std::max<size_t>(ub, 1));
         t += rup(CW * 8 * gi) + rup(CW * 8 * npairs) + 2 * rup(CW * 8 * npairs) + 2 * rup(CW * 8 * pl.bands) +
              rup(CW * 8);
         return t;
@@ -77,7 +78,6 @@ struct QueryRun {
         tbuf = a.take<uint64_t>(CW * std::max<size_t>(ub, 1));
         rbuf = a.take<uint64_t>(CW * std::max<size_t>(ub, 1));
         wbuf = a.take<uint64_t>(CW * std::max<size_t>(ub, 1));
-        bbuf = a.take<uint64_t>(CW * std::max<size_t>(baby, 1));
         gbuf = a.take<uint64_t>(CW * gi);
         gout = a.take<uint64_t>(CW * npairs);  // each pair's key-switched giant-step sum
         ybuf = a.take<uint64_t>(CW * npairs);
@@ -85,7 +85,7 @@ struct QueryRun {
         mbuf = a.take<uint64_t>(CW * pl.bands);
         mrot = a.take<uint64_t>(CW * pl.bands);
         outN = a.take<uint64_t>(CW);
-        if (!ctf || !cts || !ubuf || !tbuf || !rbuf || !wbuf || !bbuf || !gbuf || !gout || !ybuf || !ytmp ||
+        if (!ctf || !cts || !ubuf || !tbuf || !rbuf || !wbuf || !gbuf || !gout || !ybuf || !ytmp ||
             !mbuf || !mrot || !outN)
             return HC_ENOMEM;
         return HC_OK;
@@ -100,7 +100,8 @@ struct QueryRun {
 // resident, the on-the-fly chunking, and the workspace bytes compress_many takes.
 struct BatchShape {
     int Lc = 0;
-    size_t total = 0, max_jobs = 1, diag_max = 1, rt_max = 1, sum_groups = 0;
+    size_t total = 0, max_jobs = 1, diag_max = 1, rt_words = 1, sum_groups = 0;
+    std::map<std::pair<uint32_t, uint32_t>, size_t> cls_rt;    // (s, B) -> word offset of its Rt
     std::map<std::pair<uint32_t, uint32_t>, uint32_t> cls_k;   // (s, B) -> max k
     std::map<std::pair<uint32_t, uint32_t>, uint32_t> cls_np;  // (s, B) -> pairs
     std::map<std::pair<uint32_t, uint32_t>, uint32_t> cls_gc;  // (s, B) -> giants per chunk

@@ -151,6 +151,9 @@ struct KsJob {
     const uint64_t* key;
     uint32_t k;
     uint32_t xidx;
+    // nonzero: out points into the multiply-accumulate's gathered layout (see
+    // kb_final), words between consecutive (prime, 64-coefficient tile) blocks
+    uint64_t tstride = 0;
 };
 
 // Jobs [j0, j1) of a key-switching pass that belong to sum group g (indices into a
@@ -293,11 +296,14 @@ void k_zero(const Ctx& c, uint64_t* p, size_t words, hipStream_t st);
 // terms of the gathered rotated ciphertexts per pair: J rounded up to whole rounds of
 // the multiply-accumulate (DIAG_NS stages of DIAG_T terms: the stages in flight at once)
 constexpr int DIAG_NS = 4;
+// split position h of the first Lc primes (ceil(bits of the largest / 2))
+int diag_split_h(const Ctx& c, int Lc);
 inline int diag_terms_padded(int J) {
     return (J + DIAG_NS * DIAG_T - 1) / (DIAG_NS * DIAG_T) * (DIAG_NS * DIAG_T);
 }
 // Rt[r][tile][pp][j][2][64] (split) from the pointer table R[pp][j] (j < J; nullptr and
-// J <= j < diag_terms_padded(J): zeros)
+// J <= j < diag_terms_padded(J): zeros; kRtInPlace: already written there, skipped)
+static const uint64_t* const kRtInPlace = reinterpret_cast<const uint64_t*>(uintptr_t(1));
 void k_diag_gather(const Ctx& c, uint64_t* Rt, const uint64_t* const* R, int npairs, int J, int Lc,
                    hipStream_t st);
 // A[pp][g] (=|+=) sum_{j<J} D(j, g) R[pp][j], g < ga, for npairs pairs: A pointers

@@ -20,6 +20,11 @@ static inline dim3 ew_grid(int n, int rows, int count = 1) {
     return dim3((n + EW_THREADS - 1) / EW_THREADS, rows, count);
 }
 
+// A residue v < 2^(2h) stored split for the multiply-accumulate: (v >> h) 2^32 + (v mod 2^h).
+__device__ __forceinline__ uint64_t split_word(uint64_t v, int h) {
+    return ((v >> h) << 32) | (v & ((1ull << h) - 1));
+}
+
 // NTT-domain index that sigma_k pulls from: entry i holds a(psi^(2 brv(i)+1)),
 // so sigma_k(a) at i equals a at the entry whose exponent is (2 brv(i)+1) k.
 __device__ __forceinline__ uint32_t galois_src(uint32_t i, uint32_t k, int logn) {
@@ -268,10 +273,12 @@ void kb_conv(const Ctx& c, uint64_t* conv, const uint64_t* T, int M, int Lc, hip
                        st, conv, T, c.d_mods, c.d_qinv, c.d_moddown_inv, c.d_moddown_c, c.n, c.L, Lc, c.K);
 }
 
-// out_m = (sigma_k(c0_m) + (T0 - conv0) P^-1, (T1 - conv1) P^-1)   (NTT domain, level Lc)
+// out_m = (sigma_k(c0_m) + (T0 - conv0) P^-1, (T1 - conv1) P^-1)   (NTT domain, level Lc).
+// A job with a tile stride writes into the multiply-accumulate's gathered layout
+// instead: word (comp, i, x) at out[(i (n/64) + x/64) tstride + 64 comp + x mod 64], split.
 __global__ void kb_final_kernel(const KsJob* __restrict__ jobs, const uint64_t* __restrict__ T,
                                 const uint64_t* __restrict__ conv, const uint64_t* __restrict__ mods,
-                                const uint64_t* __restrict__ pinv, int n, int logn, int Lc, int K) {
+                                const uint64_t* __restrict__ pinv, int n, int logn, int Lc, int K, int h) {
     int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     const int i = blockIdx.y, m = blockIdx.z, R = Lc + K;
@@ -283,14 +290,20 @@ __global__ void kb_final_kernel(const KsJob* __restrict__ jobs, const uint64_t* 
     uint64_t d1 = shoup(sub_mod(Tm[(size_t)R * n], Cm[(size_t)Lc * n], q), pi, pis, q);
     const uint32_t src = (jb.k == 1) ? x : galois_src(x, jb.k, logn);
     const uint64_t c0 = jb.in[(size_t)i * n + src];
-    jb.out[(size_t)i * n + x] = add_mod(d0, c0, q);
-    jb.out[((size_t)Lc + i) * n + x] = d1;
+    if (jb.tstride) {
+        const size_t o = ((size_t)i * (n >> 6) + (x >> 6)) * jb.tstride + (x & 63);
+        jb.out[o] = split_word(add_mod(d0, c0, q), h);
+        jb.out[o + 64] = split_word(d1, h);
+    } else {
+        jb.out[(size_t)i * n + x] = add_mod(d0, c0, q);
+        jb.out[((size_t)Lc + i) * n + x] = d1;
+    }
 }
 
 void kb_final(const Ctx& c, const KsJob* jobs, const uint64_t* T, const uint64_t* conv, int M, int Lc,
               hipStream_t st) {
     hipLaunchKernelGGL(kb_final_kernel, ew_grid(c.n, Lc, M), dim3(EW_THREADS), 0, st, jobs, T, conv,
-                       c.d_mods, c.d_pinv, c.n, c.logn, Lc, c.K);
+                       c.d_mods, c.d_pinv, c.n, c.logn, Lc, c.K, diag_split_h(c, Lc));
 }
 
 // Key products of rotations summed per group before the group's single ModDown:
@@ -784,12 +797,10 @@ struct DiagMacArgs {
     int chunk, h, accumulate;
 };
 
-__device__ __forceinline__ uint64_t split_word(uint64_t v, int h) {
-    return ((v >> h) << 32) | (v & ((1ull << h) - 1));
-}
 
 // Rt[r][tile][pp][j][k][64] = R[pp][j] component k at (r, 64 tile + lane), split, for
-// j < Jp (J rounded up by diag_terms_padded); nullptr and j >= J -> 0.
+// j < Jp (J rounded up by diag_terms_padded); nullptr and j >= J -> 0; entries equal to
+// kRtInPlace were written into Rt by their producer and are left alone.
 __global__ void diag_gather_kernel(uint64_t* __restrict__ Rt, const uint64_t* const* __restrict__ R, int n,
                                    int L, int J, int Jp, int npairs, int pj0, int h) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -798,6 +809,7 @@ __global__ void diag_gather_kernel(uint64_t* __restrict__ Rt, const uint64_t* co
     const int pj = pj0 + (int)blockIdx.z;  // pp * Jp + j
     const int pp = pj / Jp, j = pj - pp * Jp;
     const uint64_t* rp = j < J ? R[(size_t)pp * J + j] : nullptr;
+    if (rp == kRtInPlace) return;
     const size_t ln = (size_t)L * n;
     const size_t src = (size_t)r * n + x;
     const uint64_t v0 = rp ? rp[src] : 0, v1 = rp ? rp[ln + src] : 0;
