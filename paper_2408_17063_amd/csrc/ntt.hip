@@ -94,6 +94,13 @@ struct Tile {
         return o;
     }
     static constexpr int TW_PASS = tw_before(S);  // twiddle pairs per thread over the pass
+    // In the low-bit pass of a two-pass ring a thread's global-contiguous loads and
+    // stores step through the tile at a stride of P words in LDS, which puts a
+    // wavefront's lanes on the same banks. One pad word after every P words spreads
+    // them; the rounds' accesses stay (nearly) contiguous.
+    static constexpr bool PAD = BLO == 0 && LOGP > 0;
+    static constexpr int LDS_WORDS = TSIZE + (PAD ? TSIZE / P : 0);
+    static __device__ __forceinline__ uint32_t lpos(uint32_t e) { return PAD ? e + (e >> LOGP) : e; }
     // position of twiddle t of stage u in a round of r stages, within a group's run
     static constexpr int tw_off(int r, int u) { return INV ? (1 << r) - (1 << (r - u)) : (1 << u) - 1; }
 
@@ -110,12 +117,17 @@ struct Tile {
         constexpr int POS = LOGP + KBIT;
         constexpr int GS = 1 << R;
         constexpr int PER = NTT_EPT >> R;  // groups per thread
+        // element v of a group sits at lpos(insert_bits(g, 0, POS, R)) + v VSTEP: the
+        // group's own bits are disjoint from the others (and POS >= LOGP when padded)
+        static_assert(!PAD || POS >= LOGP, "pad step");
+        constexpr uint32_t VSTEP = (1u << POS) + (PAD ? (1u << (POS - LOGP)) : 0u);
         #pragma unroll
         for (int sub = 0; sub < PER; sub++) {
             const uint32_t g = threadIdx.x * PER + sub;
+            const uint32_t lb = lpos(insert_bits(g, 0, POS, R));
             T x[GS];
             #pragma unroll
-            for (int v = 0; v < GS; v++) x[v] = lds[insert_bits(g, v, POS, R)];
+            for (int v = 0; v < GS; v++) x[v] = lds[lb + v * VSTEP];
             const uint32_t j0 = gidx(insert_bits(g, 0, POS, R), sp0);
             const T twoq = q << 1;
             #pragma unroll
@@ -171,7 +183,7 @@ struct Tile {
                 }
             }
             #pragma unroll
-            for (int v = 0; v < GS; v++) lds[insert_bits(g, v, POS, R)] = x[v];
+            for (int v = 0; v < GS; v++) lds[lb + v * VSTEP] = x[v];
         }
     }
 
@@ -217,11 +229,13 @@ struct Tile {
     }
 };
 
-template <typename T, bool INV, int LOGN, int S, int BLO, int ST0, bool LAST>
-__global__ void __launch_bounds__(NTT_THREADS)
+// WPE: minimum waves per SIMD the registers must allow (1 = no constraint); the forward
+// low-bit pass fits four waves (128 registers) without spills, the other passes would spill.
+template <typename T, bool INV, int LOGN, int S, int BLO, int ST0, bool LAST, int WPE>
+__global__ void __launch_bounds__(NTT_THREADS) __attribute__((amdgpu_waves_per_eu(WPE)))
 ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab<T> tab) {
     typedef Tile<T, INV, LOGN, S, BLO, ST0> TL;
-    __shared__ T lds[TL::TSIZE];
+    __shared__ T lds[TL::LDS_WORDS];
     const int row = blockIdx.y;
     const int prime = limb_first + row;
     const T q = tab.mods[prime];
@@ -238,7 +252,7 @@ ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab
         if (BLO == 0) { spl = f >> S; k = f & ((1u << S) - 1u); }
         else { k = f >> TL::LOGP; spl = f & (TL::P - 1); }
         const uint32_t e = (k << TL::LOGP) | spl;
-        lds[e] = a[TL::gidx(e, sp0)];
+        lds[TL::lpos(e)] = a[TL::gidx(e, sp0)];
     }
     __syncthreads();
     const T* tw2 = nullptr;
@@ -255,7 +269,7 @@ ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab
         if (BLO == 0) { spl = f >> S; k = f & ((1u << S) - 1u); }
         else { k = f >> TL::LOGP; spl = f & (TL::P - 1); }
         const uint32_t e = (k << TL::LOGP) | spl;
-        T v = lds[e];
+        T v = lds[TL::lpos(e)];
         if (LAST) {
             if (INV) v = csubT<T>(Ar<T>::shoup_lazy(v, ni[0], ni[1], q), q);
             else { v = csubT<T>(v, q << 1); v = csubT<T>(v, q); }
@@ -274,13 +288,16 @@ static void pass(const Ctx& c, int kind, T* data, size_t stride, int count, int 
     dim3 grid(1 << (LOGN - TLOG), nl, count);
     const double bytes = 2.0 * sizeof(T) * (double)count * nl * (1 << LOGN);
     const double ops = (double)count * nl * (1 << (LOGN - 1)) * S;
+    constexpr int WPE = (sizeof(T) == 8 && !INV && BLO == 0 && LOGN > TILE_LOG) ? 4 : 1;
+    auto launch = [&]() {
+        hipLaunchKernelGGL((ntt_tile_kernel<T, INV, LOGN, S, BLO, ST0, LAST, WPE>), grid, dim3(THREADS), 0, st, data,
+                           stride, lf, tab);
+    };
     if (kind >= 0) {
         TimeScope ts(c, kind, st, bytes, ops);
-        hipLaunchKernelGGL((ntt_tile_kernel<T, INV, LOGN, S, BLO, ST0, LAST>), grid, dim3(THREADS), 0, st,
-                           data, stride, lf, tab);
+        launch();
     } else {
-        hipLaunchKernelGGL((ntt_tile_kernel<T, INV, LOGN, S, BLO, ST0, LAST>), grid, dim3(THREADS), 0, st,
-                           data, stride, lf, tab);
+        launch();
     }
 }
 
