@@ -236,11 +236,12 @@ __global__ void __launch_bounds__(NTT_THREADS) __attribute__((amdgpu_waves_per_e
 ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab<T> tab) {
     typedef Tile<T, INV, LOGN, S, BLO, ST0> TL;
     __shared__ T lds[TL::LDS_WORDS];
-    const int row = blockIdx.y;
+    const int row = blockIdx.z;  // limb; polynomials along y, so consecutive blocks of one
+                                 // XCD share a (prime, tile) and its twiddles stay in L2
     const int prime = limb_first + row;
     const T q = tab.mods[prime];
     const T* tw = tab.base + ((size_t)prime * 2 + (INV ? 1 : 0)) * 2 * TL::N;
-    T* a = data + (size_t)blockIdx.z * poly_stride + (size_t)row * TL::N;
+    T* a = data + (size_t)blockIdx.y * poly_stride + (size_t)row * TL::N;
     const uint32_t sp0 = blockIdx.x * TL::P;
 
     constexpr int THREADS = TL::TSIZE / NTT_EPT;  // the launch's block size
@@ -285,7 +286,7 @@ static void pass(const Ctx& c, int kind, T* data, size_t stride, int count, int 
     constexpr int TLOG = LOGN < TILE_LOG ? LOGN : TILE_LOG;
     constexpr int THREADS = (1 << TLOG) / NTT_EPT;
     static_assert(THREADS <= NTT_THREADS, "tile");
-    dim3 grid(1 << (LOGN - TLOG), nl, count);
+    dim3 grid(1 << (LOGN - TLOG), count, nl);
     const double bytes = 2.0 * sizeof(T) * (double)count * nl * (1 << LOGN);
     const double ops = (double)count * nl * (1 << (LOGN - 1)) * S;
     constexpr int WPE = (sizeof(T) == 8 && !INV && BLO == 0 && LOGN > TILE_LOG) ? 4 : 1;
