@@ -162,20 +162,27 @@ __global__ void kb_modup_kernel(uint64_t* __restrict__ X, const uint64_t* __rest
     const int j = blockIdx.y, u = blockIdx.z, R = Lc + K;
     const uint64_t* src = tmpC + (size_t)u * Lc * n;
     uint64_t* out = X + ((size_t)u * dn + j) * R * n;
-    uint64_t y[4];
-    for (int a = 0; a < alpha; a++) {
-        const int r = j * alpha + a;
-        const uint64_t v = src[(size_t)r * n + x];
-        if (own) out[(size_t)r * n + x] = v;
-        const uint64_t* iv = inv + ((size_t)j * alpha + a) * 2;
-        y[a] = shoup(v, iv[0], iv[1], mods[r]);
-    }
+    // alpha <= 4 (the context's limit): fixed-trip loops, so the loads issue together
+    uint64_t v[4], y[4];
+    #pragma unroll
+    for (int a = 0; a < 4; a++)
+        if (a < alpha) v[a] = src[(size_t)(j * alpha + a) * n + x];
+    #pragma unroll
+    for (int a = 0; a < 4; a++)
+        if (a < alpha) {
+            const int r = j * alpha + a;
+            if (own) out[(size_t)r * n + x] = v[a];
+            const uint64_t* iv = inv + ((size_t)j * alpha + a) * 2;
+            y[a] = shoup(v[a], iv[0], iv[1], mods[r]);
+        }
     const uint64_t* cj = cst + (size_t)j * alpha * nq;
     for (int row = 0; row < R; row++) {
         if (row >= j * alpha && row < (j + 1) * alpha) continue;
         const int pr = row_prime(row, Lc, L);
         u128p acc{0, 0};
-        for (int a = 0; a < alpha; a++) add128(acc, mul128(y[a], cj[(size_t)a * nq + pr]));
+        #pragma unroll
+        for (int a = 0; a < 4; a++)
+            if (a < alpha) add128(acc, mul128(y[a], cj[(size_t)a * nq + pr]));
         out[(size_t)row * n + x] = redc(acc, mods[pr], qinv[pr]);
     }
 }
@@ -257,13 +264,20 @@ __global__ void kb_conv_kernel(uint64_t* __restrict__ conv, const uint64_t* __re
     if (x >= n) return;
     const int i0 = blockIdx.y * CONV_ROWS, mc = blockIdx.z, R = Lc + K;  // mc = m * 2 + comp
     const uint64_t* Tc = T + (size_t)mc * R * n;
-    uint64_t y[4];
-    for (int k = 0; k < K; k++)
-        y[k] = shoup(Tc[(size_t)(Lc + k) * n + x], inv[2 * k], inv[2 * k + 1], mods[L + k]);
+    // K <= 4 (the context's limit): fixed-trip loops, so the loads issue together
+    uint64_t v[4], y[4];
+    #pragma unroll
+    for (int k = 0; k < 4; k++)
+        if (k < K) v[k] = Tc[(size_t)(Lc + k) * n + x];
+    #pragma unroll
+    for (int k = 0; k < 4; k++)
+        if (k < K) y[k] = shoup(v[k], inv[2 * k], inv[2 * k + 1], mods[L + k]);
     const int i1 = (i0 + CONV_ROWS) < Lc ? (i0 + CONV_ROWS) : Lc;
     for (int i = i0; i < i1; i++) {
         u128p acc{0, 0};
-        for (int k = 0; k < K; k++) add128(acc, mul128(y[k], cst[(size_t)k * L + i]));
+        #pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (k < K) add128(acc, mul128(y[k], cst[(size_t)k * L + i]));
         conv[((size_t)mc * Lc + i) * n + x] = redc(acc, mods[i], qinv[i]);
     }
 }
@@ -434,22 +448,32 @@ __global__ void ms_conv_kernel(uint64_t* __restrict__ conv, const uint64_t* __re
     #pragma unroll
     for (int u = 0; u < CONV_ROWS; u++) { acc[u] = u128p{0, 0}; sum[u] = 0; }
     int terms = 0;
-    for (int j = 0; j < nd; j++) {
-        const int r = Lc + j;
-        const uint64_t y = shoup(cc[(size_t)r * n + x], inv[2 * j], inv[2 * j + 1], mods[r]);
-        const uint64_t* cj = cst + (size_t)j * Lc + i0;
+    // the dropped residues in batches of 8, each batch's loads issued together
+    constexpr int MS_BATCH = 8;
+    for (int j0 = 0; j0 < nd; j0 += MS_BATCH) {
+        uint64_t v[MS_BATCH];
         #pragma unroll
-        for (int u = 0; u < CONV_ROWS; u++)
-            if (u < ni) add128(acc[u], mul128(y, cj[u]));
-        if (++terms == fold) {  // keep each 128-bit sum below q_i 2^64
+        for (int b = 0; b < MS_BATCH; b++)
+            if (j0 + b < nd) v[b] = cc[(size_t)(Lc + j0 + b) * n + x];
+        #pragma unroll
+        for (int b = 0; b < MS_BATCH; b++) {
+            const int j = j0 + b;
+            if (j >= nd) break;
+            const uint64_t y = shoup(v[b], inv[2 * j], inv[2 * j + 1], mods[Lc + j]);
+            const uint64_t* cj = cst + (size_t)j * Lc + i0;
             #pragma unroll
             for (int u = 0; u < CONV_ROWS; u++)
-                if (u < ni) {
-                    const uint64_t q = mods[i0 + u];
-                    sum[u] = add_mod(sum[u], redc(acc[u], q, qinv[i0 + u]), q);
-                    acc[u] = u128p{0, 0};
-                }
-            terms = 0;
+                if (u < ni) add128(acc[u], mul128(y, cj[u]));
+            if (++terms == fold) {  // keep each 128-bit sum below q_i 2^64
+                #pragma unroll
+                for (int u = 0; u < CONV_ROWS; u++)
+                    if (u < ni) {
+                        const uint64_t q = mods[i0 + u];
+                        sum[u] = add_mod(sum[u], redc(acc[u], q, qinv[i0 + u]), q);
+                        acc[u] = u128p{0, 0};
+                    }
+                terms = 0;
+            }
         }
     }
     #pragma unroll
