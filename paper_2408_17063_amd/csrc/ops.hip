@@ -434,21 +434,21 @@ void k_sum_cts(const Ctx& c, uint64_t* y, const uint64_t* src, int groups, int c
 // ct [count][2][L][n] with the dropped rows Lc..L-1 in the coefficient domain; blockIdx.z = t*2+comp.
 // A thread covers CONV_ROWS consecutive kept primes: each dropped residue is read and
 // scaled once.
+template <int NI>
 __global__ void ms_conv_kernel(uint64_t* __restrict__ conv, const uint64_t* __restrict__ ct,
                                const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv,
                                const uint64_t* __restrict__ inv, const uint64_t* __restrict__ cst,
-                               int n, int L, int Lc, int fold) {
+                               int n, int L, int Lc, int i0) {
     int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
-    const int tc = blockIdx.z, i0 = blockIdx.y * CONV_ROWS, nd = L - Lc;
-    const int ni = (Lc - i0) < CONV_ROWS ? (Lc - i0) : CONV_ROWS;
+    const int tc = blockIdx.z, nd = L - Lc;
     const uint64_t* cc = ct + (size_t)tc * L * n;
-    u128p acc[CONV_ROWS];
-    uint64_t sum[CONV_ROWS];
+    u128p acc[NI];
+    uint64_t sum[NI];
     #pragma unroll
-    for (int u = 0; u < CONV_ROWS; u++) { acc[u] = u128p{0, 0}; sum[u] = 0; }
-    int terms = 0;
-    // the dropped residues in batches of 8, each batch's loads issued together
+    for (int u = 0; u < NI; u++) sum[u] = 0;
+    // the dropped residues in batches of 8 whose loads issue together; each batch's
+    // 128-bit sums (8 products below 2^60 q_i) are reduced before the next
     constexpr int MS_BATCH = 8;
     for (int j0 = 0; j0 < nd; j0 += MS_BATCH) {
         uint64_t v[MS_BATCH];
@@ -456,32 +456,25 @@ __global__ void ms_conv_kernel(uint64_t* __restrict__ conv, const uint64_t* __re
         for (int b = 0; b < MS_BATCH; b++)
             if (j0 + b < nd) v[b] = cc[(size_t)(Lc + j0 + b) * n + x];
         #pragma unroll
+        for (int u = 0; u < NI; u++) acc[u] = u128p{0, 0};
+        #pragma unroll
         for (int b = 0; b < MS_BATCH; b++) {
             const int j = j0 + b;
-            if (j >= nd) break;
-            const uint64_t y = shoup(v[b], inv[2 * j], inv[2 * j + 1], mods[Lc + j]);
-            const uint64_t* cj = cst + (size_t)j * Lc + i0;
-            #pragma unroll
-            for (int u = 0; u < CONV_ROWS; u++)
-                if (u < ni) add128(acc[u], mul128(y, cj[u]));
-            if (++terms == fold) {  // keep each 128-bit sum below q_i 2^64
+            if (j < nd) {
+                const uint64_t y = shoup(v[b], inv[2 * j], inv[2 * j + 1], mods[Lc + j]);
+                const uint64_t* cj = cst + (size_t)j * Lc + i0;
                 #pragma unroll
-                for (int u = 0; u < CONV_ROWS; u++)
-                    if (u < ni) {
-                        const uint64_t q = mods[i0 + u];
-                        sum[u] = add_mod(sum[u], redc(acc[u], q, qinv[i0 + u]), q);
-                        acc[u] = u128p{0, 0};
-                    }
-                terms = 0;
+                for (int u = 0; u < NI; u++) add128(acc[u], mul128(y, cj[u]));
             }
+        }
+        #pragma unroll
+        for (int u = 0; u < NI; u++) {
+            const uint64_t q = mods[i0 + u];
+            sum[u] = add_mod(sum[u], redc(acc[u], q, qinv[i0 + u]), q);
         }
     }
     #pragma unroll
-    for (int u = 0; u < CONV_ROWS; u++)
-        if (u < ni) {
-            const int i = i0 + u;
-            conv[((size_t)tc * Lc + i) * n + x] = add_mod(sum[u], redc(acc[u], mods[i], qinv[i]), mods[i]);
-        }
+    for (int u = 0; u < NI; u++) conv[((size_t)tc * Lc + i0 + u) * n + x] = sum[u];
 }
 
 // out[t][c][i] = (ct[t][c][i] - conv[t][c][i]) D^-1 mod q_i (NTT domain), out at level Lc
@@ -496,14 +489,31 @@ __global__ void ms_final_kernel(uint64_t* __restrict__ out, const uint64_t* __re
     out[((size_t)tc * Lc + i) * n + x] = shoup(d, dinv[2 * i], dinv[2 * i + 1], q);
 }
 
+// Calls f(integral_constant<int, v>) for a runtime v in 1..8.
+template <typename F>
+static void with_rows(int v, F&& f) {
+    switch (v) {
+        case 1: f(std::integral_constant<int, 1>{}); break;
+        case 2: f(std::integral_constant<int, 2>{}); break;
+        case 3: f(std::integral_constant<int, 3>{}); break;
+        case 4: f(std::integral_constant<int, 4>{}); break;
+        case 5: f(std::integral_constant<int, 5>{}); break;
+        case 6: f(std::integral_constant<int, 6>{}); break;
+        case 7: f(std::integral_constant<int, 7>{}); break;
+        default: f(std::integral_constant<int, 8>{}); break;
+    }
+}
+
 void k_ms_conv(const Ctx& c, uint64_t* conv, const uint64_t* ct, const uint64_t* inv, const uint64_t* cst,
                int Lc, int count, hipStream_t st) {
-    uint64_t qmax = 0;
-    for (int i = 0; i < c.L; i++) qmax = qmax > c.primes[i] ? qmax : c.primes[i];
-    int fold = (int)std::min<uint64_t>(1024, (~0ull) / qmax);
-    hipLaunchKernelGGL(ms_conv_kernel, ew_grid(c.n, (Lc + CONV_ROWS - 1) / CONV_ROWS, 2 * count), dim3(EW_THREADS),
-                       0, st, conv, ct,
-                       c.d_mods, c.d_qinv, inv, cst, c.n, c.L, Lc, fold < 1 ? 1 : fold);
+    // the kept primes in chunks of up to CONV_ROWS per thread (primes below 2^60, so a
+    // batch of 8 products stays below q 2^64)
+    for (int i0 = 0; i0 < Lc; i0 += CONV_ROWS)
+        with_rows(std::min(CONV_ROWS, Lc - i0), [&](auto ni_c) {
+            constexpr int NI = decltype(ni_c)::value;
+            hipLaunchKernelGGL((ms_conv_kernel<NI>), ew_grid(c.n, 1, 2 * count), dim3(EW_THREADS), 0, st, conv, ct,
+                               c.d_mods, c.d_qinv, inv, cst, c.n, c.L, Lc, i0);
+        });
 }
 
 void k_ms_final(const Ctx& c, uint64_t* out, const uint64_t* ct, const uint64_t* conv, const uint64_t* dinv,
