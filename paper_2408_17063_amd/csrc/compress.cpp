@@ -324,7 +324,7 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
     }
 
     // Each class (s, B) gathers its pairs' rotated ciphertexts into one region of Rt, in
-    // the multiply-accumulate's layout [Lc][n/64][pair][Jp][2][64] (split words); pair
+    // the multiply-accumulate's layout [Lc][n/64][pair][Jp][64][2] (split words); pair
     // ci of the class is its ci-th (query, pair) in query order.
     std::map<std::pair<uint32_t, uint32_t>, uint32_t> cls_seen;
     for (auto& q : qs) {

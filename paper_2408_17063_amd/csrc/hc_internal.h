@@ -301,7 +301,7 @@ int diag_split_h(const Ctx& c, int Lc);
 inline int diag_terms_padded(int J) {
     return (J + DIAG_NS * DIAG_T - 1) / (DIAG_NS * DIAG_T) * (DIAG_NS * DIAG_T);
 }
-// Rt[r][tile][pp][j][2][64] (split) from the pointer table R[pp][j] (j < J; nullptr and
+// Rt[r][tile][pp][j][64][2] (split) from the pointer table R[pp][j] (j < J; nullptr and
 // J <= j < diag_terms_padded(J): zeros; kRtInPlace: already written there, skipped)
 static const uint64_t* const kRtInPlace = reinterpret_cast<const uint64_t*>(uintptr_t(1));
 void k_diag_gather(const Ctx& c, uint64_t* Rt, const uint64_t* const* R, int npairs, int J, int Lc,

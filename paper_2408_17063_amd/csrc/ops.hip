@@ -289,7 +289,7 @@ void kb_conv(const Ctx& c, uint64_t* conv, const uint64_t* T, int M, int Lc, hip
 
 // out_m = (sigma_k(c0_m) + (T0 - conv0) P^-1, (T1 - conv1) P^-1)   (NTT domain, level Lc).
 // A job with a tile stride writes into the multiply-accumulate's gathered layout
-// instead: word (comp, i, x) at out[(i (n/64) + x/64) tstride + 64 comp + x mod 64], split.
+// instead: word (comp, i, x) at out[(i (n/64) + x/64) tstride + 2 (x mod 64) + comp], split.
 __global__ void kb_final_kernel(const KsJob* __restrict__ jobs, const uint64_t* __restrict__ T,
                                 const uint64_t* __restrict__ conv, const uint64_t* __restrict__ mods,
                                 const uint64_t* __restrict__ pinv, int n, int logn, int Lc, int K, int h) {
@@ -305,9 +305,8 @@ __global__ void kb_final_kernel(const KsJob* __restrict__ jobs, const uint64_t* 
     const uint32_t src = (jb.k == 1) ? x : galois_src(x, jb.k, logn);
     const uint64_t c0 = jb.in[(size_t)i * n + src];
     if (jb.tstride) {
-        const size_t o = ((size_t)i * (n >> 6) + (x >> 6)) * jb.tstride + (x & 63);
-        jb.out[o] = split_word(add_mod(d0, c0, q), h);
-        jb.out[o + 64] = split_word(d1, h);
+        const size_t o = ((size_t)i * (n >> 6) + (x >> 6)) * jb.tstride + 2 * (x & 63);
+        *reinterpret_cast<ulonglong2*>(jb.out + o) = ulonglong2{split_word(add_mod(d0, c0, q), h), split_word(d1, h)};
     } else {
         jb.out[(size_t)i * n + x] = add_mod(d0, c0, q);
         jb.out[((size_t)Lc + i) * n + x] = d1;
@@ -820,7 +819,7 @@ hc_status upload_keccak_constants(const uint64_t rc[24], const uint32_t rho[25],
 // at a time share one tile of the rotated ciphertexts through that XCD's L2.
 //
 // Operands are tiled so that a block streams two contiguous regions: the rotated
-// ciphertexts Rt[r][tile][pp][j][2][64] (term j = beta B + b; written split by
+// ciphertexts Rt[r][tile][pp][j][64][2] (term j = beta B + b; written split by
 // diag_gather_kernel) and D, whose layout is given by word strides: the split word of
 // D(beta, g, b) for limb r at coefficient 64 tile + lane, g = GC c + i (giant chunk c,
 // i < GC), is D[r sr + tile st + c sgc + j sj + i sg + lane].
@@ -832,7 +831,7 @@ struct DiagMacArgs {
 };
 
 
-// Rt[r][tile][pp][j][k][64] = R[pp][j] component k at (r, 64 tile + lane), split, for
+// Rt[r][tile][pp][j][lane][k] = R[pp][j] component k at (r, 64 tile + lane), split, for
 // j < Jp (J rounded up by diag_terms_padded); nullptr and j >= J -> 0; entries equal to
 // kRtInPlace were written into Rt by their producer and are left alone.
 __global__ void diag_gather_kernel(uint64_t* __restrict__ Rt, const uint64_t* const* __restrict__ R, int n,
@@ -847,9 +846,8 @@ __global__ void diag_gather_kernel(uint64_t* __restrict__ Rt, const uint64_t* co
     const size_t ln = (size_t)L * n;
     const size_t src = (size_t)r * n + x;
     const uint64_t v0 = rp ? rp[src] : 0, v1 = rp ? rp[ln + src] : 0;
-    const size_t o = (((size_t)r * (n / 64) + (size_t)(x / 64)) * ((size_t)npairs * Jp) + pj) * 128 + (x & 63);
-    Rt[o] = split_word(v0, h);
-    Rt[o + 64] = split_word(v1, h);
+    const size_t o = (((size_t)r * (n / 64) + (size_t)(x / 64)) * ((size_t)npairs * Jp) + pj) * 128 + 2 * (x & 63);
+    *reinterpret_cast<ulonglong2*>(Rt + o) = ulonglong2{split_word(v0, h), split_word(v1, h)};
 }
 
 // The diagonals of a block are read from device memory once and shared through LDS,
@@ -900,7 +898,7 @@ __global__ __launch_bounds__(256) void diag_mac_kernel(uint64_t* const* __restri
     constexpr int INSTR = PIECES / 64;   // wave instructions per stage
     constexpr int PER_WAVE = INSTR / 4;  // blocks are 4 waves
     static_assert(INSTR % 4 == 0 && GC % 2 == 0, "stage size");
-    constexpr int RLOADS = 2 * T;        // a pair wave's rotated-ciphertext loads per stage
+    constexpr int RLOADS = T;            // a pair wave's rotated-ciphertext loads per stage (16 B each)
     __shared__ __attribute__((aligned(1024))) uint64_t lds[NS][T][GC][64];
     const uint32_t bid = blockIdx.x;
     const uint32_t wk = (bid & 7u) * a.per_xcd + (bid >> 3);
@@ -941,7 +939,7 @@ __global__ __launch_bounds__(256) void diag_mac_kernel(uint64_t* const* __restri
             }
     };
 
-    const uint64_t* Rb = Rt + (((size_t)r * a.ntiles + tile) * a.npairs + (active ? pp : 0)) * (size_t)Jp * 128 + lane;
+    const uint64_t* Rb = Rt + (((size_t)r * a.ntiles + tile) * a.npairs + (active ? pp : 0)) * (size_t)Jp * 128 + 2 * lane;
     const uint64_t* Db = D + (size_t)r * a.sr + (size_t)tile * a.st + (size_t)(g0 / DIAG_GC) * a.sgc +
                           (size_t)(g0 % DIAG_GC) * a.sg;
     // bytes a term's diagonal words span from their first word (giants g0..g0+gc-1)
@@ -968,8 +966,9 @@ __global__ __launch_bounds__(256) void diag_mac_kernel(uint64_t* const* __restri
         #pragma unroll
         for (int u = 0; u < T; u++) {
             const int jr = (s * T + u) < Jp ? (s * T + u) : Jp - 1;
-            rv[slot][u][0] = Rb[(size_t)jr * 128];
-            rv[slot][u][1] = Rb[(size_t)jr * 128 + 64];
+            const ulonglong2 w = *reinterpret_cast<const ulonglong2*>(Rb + (size_t)jr * 128);
+            rv[slot][u][0] = w.x;
+            rv[slot][u][1] = w.y;
         }
     };
     int terms = 0;
