@@ -101,6 +101,24 @@ struct Tile {
     static constexpr bool PAD = BLO == 0 && LOGP > 0;
     static constexpr int LDS_WORDS = TSIZE + (PAD ? TSIZE / P : 0);
     static __device__ __forceinline__ uint32_t lpos(uint32_t e) { return PAD ? e + (e >> LOGP) : e; }
+    // True if no index bit a thread's group supplies survives the twiddle-index shift
+    // of any stage of the round (butterfly bits [kbit, kbit + r) of k, `done` stages
+    // before it): the round's twiddles are then the same for the whole block.
+    static constexpr bool round_uniform(int kbit, int r, int done) {
+        int hi = -1;  // highest j0 bit a group supplies
+        for (int b = 0; b < S; b++)
+            if (b < kbit || b >= kbit + r) hi = hi > BLO + b ? hi : BLO + b;
+        for (int c = 0; c < LOGP; c++) {
+            const int pos = BLO == 0 ? S + c : c;
+            hi = hi > pos ? hi : pos;
+        }
+        for (int u = 0; u < r; u++) {
+            const int st = ST0 + done + u;
+            const int shift = INV ? st + 1 : LOGN - st;
+            if (hi >= shift) return false;
+        }
+        return true;
+    }
     // position of twiddle t of stage u in a round of r stages, within a group's run
     static constexpr int tw_off(int r, int u) { return INV ? (1 << r) - (1 << (r - u)) : (1 << u) - 1; }
 
@@ -136,7 +154,8 @@ struct Tile {
                 if (!INV) {
                     // partner bit R-1-u of v; twiddle 2^st + (j0 >> (LOGN-st)) + (v >> (R-u))
                     const int half = 1 << (R - 1 - u);
-                    const uint32_t base = (1u << st) + (j0 >> (LOGN - st));
+                    uint32_t base = (1u << st) + (j0 >> (LOGN - st));
+                    if constexpr (round_uniform(KBIT, R, DONE)) base = __builtin_amdgcn_readfirstlane(base);
                     T w[8], wp[8];
                     #pragma unroll
                     for (int t = 0; t < (1 << u); t++) {
@@ -160,7 +179,8 @@ struct Tile {
                 } else {
                     // partner bit u of v; twiddle n/2^(st+1) + (j0 >> (st+1)) + (v >> (u+1))
                     const int half = 1 << u;
-                    const uint32_t base = ((uint32_t)N >> (st + 1)) + (j0 >> (st + 1));
+                    uint32_t base = ((uint32_t)N >> (st + 1)) + (j0 >> (st + 1));
+                    if constexpr (round_uniform(KBIT, R, DONE)) base = __builtin_amdgcn_readfirstlane(base);
                     T w[8], wp[8];
                     #pragma unroll
                     for (int t = 0; t < (1 << (R - 1 - u)); t++) {
@@ -229,8 +249,9 @@ struct Tile {
     }
 };
 
-// WPE: minimum waves per SIMD the registers must allow (1 = no constraint); the forward
-// low-bit pass fits four waves (128 registers) without spills, the other passes would spill.
+// WPE: minimum waves per SIMD the registers must allow (1 = no constraint); the second
+// pass of each direction (forward low bits, inverse high bits) fits four waves (128
+// registers) without spills, the first passes would spill.
 template <typename T, bool INV, int LOGN, int S, int BLO, int ST0, bool LAST, int WPE>
 __global__ void __launch_bounds__(NTT_THREADS) __attribute__((amdgpu_waves_per_eu(WPE)))
 ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab<T> tab) {
@@ -289,7 +310,7 @@ static void pass(const Ctx& c, int kind, T* data, size_t stride, int count, int 
     dim3 grid(1 << (LOGN - TLOG), count, nl);
     const double bytes = 2.0 * sizeof(T) * (double)count * nl * (1 << LOGN);
     const double ops = (double)count * nl * (1 << (LOGN - 1)) * S;
-    constexpr int WPE = (sizeof(T) == 8 && !INV && BLO == 0 && LOGN > TILE_LOG) ? 4 : 1;
+    constexpr int WPE = (sizeof(T) == 8 && LOGN > TILE_LOG && (INV ? BLO != 0 : BLO == 0)) ? 4 : 1;
     auto launch = [&]() {
         hipLaunchKernelGGL((ntt_tile_kernel<T, INV, LOGN, S, BLO, ST0, LAST, WPE>), grid, dim3(THREADS), 0, st, data,
                            stride, lf, tab);
