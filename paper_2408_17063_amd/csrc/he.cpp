@@ -84,7 +84,7 @@ static size_t ks_job_words(const Ctx& c, int Lc) {
     return (size_t)c.n * (2 * (size_t)R + 2 * (size_t)Lc);
 }
 
-static const size_t kKsScratchBudget = (size_t)3 << 30;
+static const size_t kKsScratchBudget = (size_t)12 << 30;
 
 size_t ks_scratch_bytes(const Ctx& c, int Lc, int max_jobs) {
     const size_t per = 8 * (ks_src_words(c, Lc) + ks_job_words(c, Lc));
