@@ -399,14 +399,14 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
                 for (uint32_t b = 0; b < B; b++) hptr[(ci * kb + beta) * B + b] = q.R[pp][beta][b];
             for (uint32_t gi = 0; gi < G; gi++) hptr[np * kb * B + ci * G + gi] = q.A[pp][gi];
         }
+        // the rotated-ciphertext and giant-accumulator pointer tables, one copy
         const uint64_t* const* rptr =
-            (const uint64_t* const*)stage_bytes(l, hptr.data(), sizeof(uint64_t*) * np * kb * B, st);
+            (const uint64_t* const*)stage_bytes(l, hptr.data(), sizeof(uint64_t*) * hptr.size(), st);
         if (!rptr) return HC_ENOMEM;
         k_diag_gather(c, Rt, rptr, (int)np, (int)(kb * B), Lc, st);
         if (const Ctx::DiagTab* tab = cls_res[kv.first]) {
             // resident diagonals: one pass over every giant index
-            uint64_t** aptr = (uint64_t**)stage_bytes(l, hptr.data() + np * kb * B, sizeof(uint64_t*) * np * G, st);
-            if (!aptr) return HC_ENOMEM;
+            uint64_t** aptr = (uint64_t**)(rptr + np * kb * B);
             hc_status ms = k_diag_mac(c, aptr, Rt, tab->d, diag_layout_tiled(c, tab->kb * B, G), (int)np,
                                       (int)(kb * B), (int)G, false, Lc, st);
             if (ms != HC_OK) return ms;

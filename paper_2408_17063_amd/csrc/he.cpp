@@ -73,6 +73,26 @@ void* stage_bytes(Lane& l, const void* data, size_t bytes, hipStream_t st) {
     return l.stage_dev + off;
 }
 
+bool stage_many(Lane& l, std::initializer_list<StagePart> parts, hipStream_t st) {
+    const size_t first = (l.stage_used + 255) & ~(size_t)255;
+    size_t off = first;
+    for (const StagePart& p : parts) {
+        off = (off + 255) & ~(size_t)255;
+        if (off + p.bytes > l.stage_cap) return false;
+        memcpy(l.stage_host + off, p.data, p.bytes);
+        *p.dev = l.stage_dev + off;
+        off += p.bytes;
+    }
+    if (off > first) {
+        if (hipMemcpyAsync(l.stage_dev + first, l.stage_host + first, off - first, hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+            return false;
+        if (l.copied && hipEventRecord(l.copied, st) != hipSuccess) return false;
+    }
+    l.stage_used = off;
+    return true;
+}
+
 // ------------------------------------------------------------------ batched key switching
 
 static size_t ks_src_words(const Ctx& c, int Lc) {
@@ -136,8 +156,8 @@ static void sort_by_key(std::vector<KsJob>& jb) {
                      [](const KsJob& x, const KsJob& y) { return (uintptr_t)x.key < (uintptr_t)y.key; });
 }
 
-// Runs of up to KS_RUN adjacent jobs with the same key, staged for kb_inner.
-static const KsRun* stage_runs(Lane& l, const std::vector<KsJob>& jb, int* nruns, hipStream_t st) {
+// Runs of up to KS_RUN adjacent jobs with the same key, for kb_inner.
+static std::vector<KsRun> key_runs(const std::vector<KsJob>& jb) {
     std::vector<KsRun> runs;
     for (uint32_t i = 0; i < (uint32_t)jb.size(); i++) {
         if (!runs.empty() && runs.back().cnt < (uint32_t)KS_RUN && jb[runs.back().j0].key == jb[i].key)
@@ -145,14 +165,15 @@ static const KsRun* stage_runs(Lane& l, const std::vector<KsJob>& jb, int* nruns
         else
             runs.push_back(KsRun{i, 1});
     }
-    *nruns = (int)runs.size();
-    return (const KsRun*)stage_bytes(l, runs.data(), sizeof(KsRun) * runs.size(), st);
+    return runs;
 }
 
 // Rotations at level Lc. Plain (srcs == nullptr): each job raises its own rotated c1.
 // Hoisted: srcs[u] are raised once (unrotated) and every job with xidx = u rotates
 // the raised digits instead. Jobs are processed in passes of at most maxM, each pass
-// in key order so that jobs sharing a key read it once (kb_inner).
+// in key order so that jobs sharing a key read it once (kb_inner). A pass's tables
+// (jobs, key runs, and the raised sources when they start a chunk) go to the device
+// in one copy.
 hc_status ks_run(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
                  const std::vector<const uint64_t*>* srcs, int Lc, hipStream_t st) {
     if (!s.tmpC || !s.X || !s.T || !s.conv) return HC_ENOMEM;
@@ -173,12 +194,13 @@ hc_status ks_run(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
             const int M = (int)std::min<size_t>(s.maxM, all.size() - m0);
             std::vector<KsJob> jb(all.begin() + m0, all.begin() + m0 + M);
             for (int i = 0; i < M; i++) jb[i].xidx = (uint32_t)i;
-            const KsJob* d = (const KsJob*)stage_bytes(l, jb.data(), sizeof(KsJob) * M, st);
-            int nruns = 0;
-            const KsRun* dr = stage_runs(l, jb, &nruns, st);
-            if (!d || !dr) return HC_ENOMEM;
-            raise(d, M, true);
-            finish(d, dr, nruns, M, false);
+            const std::vector<KsRun> runs = key_runs(jb);
+            void *d = nullptr, *dr = nullptr;
+            if (!stage_many(l, {{jb.data(), sizeof(KsJob) * M, &d}, {runs.data(), sizeof(KsRun) * runs.size(), &dr}},
+                            st))
+                return HC_ENOMEM;
+            raise((const KsJob*)d, M, true);
+            finish((const KsJob*)d, (const KsRun*)dr, (int)runs.size(), M, false);
         }
         return HC_OK;
     }
@@ -187,9 +209,6 @@ hc_status ks_run(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
         const int Uc = (int)std::min<size_t>(s.maxU, U - u0);
         std::vector<KsJob> sj(Uc);
         for (int i = 0; i < Uc; i++) sj[i] = KsJob{(*srcs)[u0 + i], nullptr, nullptr, 1u, (uint32_t)i};
-        const KsJob* ds = (const KsJob*)stage_bytes(l, sj.data(), sizeof(KsJob) * Uc, st);
-        if (!ds) return HC_ENOMEM;
-        raise(ds, Uc, false);
         std::vector<KsJob> mine;
         for (const KsJob& j : jobs)
             if (j.xidx >= u0 && j.xidx < u0 + Uc) {
@@ -198,14 +217,19 @@ hc_status ks_run(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
                 mine.push_back(t);
             }
         sort_by_key(mine);
-        for (size_t m0 = 0; m0 < mine.size(); m0 += s.maxM) {
-            const int M = (int)std::min<size_t>(s.maxM, mine.size() - m0);
+        for (size_t m0 = 0; m0 < std::max<size_t>(mine.size(), 1); m0 += s.maxM) {
+            const int M = (int)std::min<size_t>(s.maxM, mine.size() - std::min(m0, mine.size()));
             std::vector<KsJob> jb(mine.begin() + m0, mine.begin() + m0 + M);
-            const KsJob* d = (const KsJob*)stage_bytes(l, jb.data(), sizeof(KsJob) * M, st);
-            int nruns = 0;
-            const KsRun* dr = stage_runs(l, jb, &nruns, st);
-            if (!d || !dr) return HC_ENOMEM;
-            finish(d, dr, nruns, M, true);
+            const std::vector<KsRun> runs = key_runs(jb);
+            void *ds = nullptr, *d = nullptr, *dr = nullptr;
+            const bool first = m0 == 0;
+            if (!stage_many(l, {{sj.data(), first ? sizeof(KsJob) * Uc : 0, &ds},
+                                {jb.data(), sizeof(KsJob) * M, &d},
+                                {runs.data(), sizeof(KsRun) * runs.size(), &dr}},
+                            st))
+                return HC_ENOMEM;
+            if (first) raise((const KsJob*)ds, Uc, false);
+            if (M > 0) finish((const KsJob*)d, (const KsRun*)dr, (int)runs.size(), M, true);
         }
     }
     return HC_OK;
@@ -250,12 +274,15 @@ hc_status ks_run_sum(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jo
         }
         int nkeys = 0;
         for (int i = 0; i < M; i++) nkeys += (i == 0 || jb[i].key != jb[i - 1].key) ? 1 : 0;
-        const KsJob* d = (const KsJob*)stage_bytes(l, jb.data(), sizeof(KsJob) * M, st);
-        const KsGroupRange* dg = (const KsGroupRange*)stage_bytes(l, rg.data(), sizeof(KsGroupRange) * rg.size(), st);
-        const uint32_t* dm = (const uint32_t*)stage_bytes(l, members.data(), sizeof(uint32_t) * M, st);
-        if (!d || !dg || !dm) return HC_ENOMEM;
+        void *dv = nullptr, *dgv = nullptr, *dmv = nullptr;
+        if (!stage_many(l, {{jb.data(), sizeof(KsJob) * M, &dv}, {rg.data(), sizeof(KsGroupRange) * rg.size(), &dgv},
+                            {members.data(), sizeof(uint32_t) * M, &dmv}},
+                        st))
+            return HC_ENOMEM;
+        const KsJob* d = (const KsJob*)dv;
         ks_raise(c, s, d, M, Lc, true, st);
-        kb_inner_sum(c, TA, C0A, s.X, d, dg, dm, (int)rg.size(), M, nkeys, Lc, st);
+        kb_inner_sum(c, TA, C0A, s.X, d, (const KsGroupRange*)dgv, (const uint32_t*)dmv, (int)rg.size(), M, nkeys,
+                     Lc, st);
     }
     // one ModDown per group (TA is consumed in place)
     for (size_t g0 = 0; g0 < G; g0 += s.maxM) {

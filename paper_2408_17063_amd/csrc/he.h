@@ -1,5 +1,7 @@
 // Declarations shared by the host orchestration files (he.cpp, compress.cpp).
 #pragma once
+#include <initializer_list>
+
 #include "hc_internal.h"
 
 namespace hc {
@@ -20,6 +22,13 @@ hc_status prefix_mask(Ctx& c, uint32_t s, const uint64_t** out);
 // per-call staging of small tables (pinned host -> device, in stream order)
 void stage_reset(Lane& l, hipStream_t st);
 void* stage_bytes(Lane& l, const void* data, size_t bytes, hipStream_t st);
+// Several host arrays staged with one copy: each part's device address goes to *dev.
+struct StagePart {
+    const void* data;
+    size_t bytes;
+    void** dev;
+};
+bool stage_many(Lane& l, std::initializer_list<StagePart> parts, hipStream_t st);
 // batched key switching at level Lc (see ks_run in he.cpp)
 size_t ks_scratch_bytes(const Ctx& c, int Lc, int max_jobs);
 KsScratch ks_scratch(Ctx& c, Arena& a, int Lc, int max_jobs);
