@@ -192,10 +192,13 @@ extern "C" hc_status hc_context_create(const hc_params* prm, int device, hc_cont
     HC_CHECK(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return HC_EINVAL;
     HC_CHECK(hipSetDevice(device));
+    int cus = 0;
+    HC_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
 
     Ctx* cp = new Ctx();
     Ctx& c = *cp;
     c.device = device;
+    c.cus = cus;
     c.logn = prm->log_n;
     c.n = (int)n;
     c.nh = c.n / 2;

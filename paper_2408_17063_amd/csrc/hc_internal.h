@@ -58,6 +58,7 @@ struct Lane {
 
 struct hc_context {
     int device = 0;
+    int cus = 0;  // compute units of the device
     int logn = 0, n = 0, nh = 0;
     int L = 0, K = 0, dnum = 0, alpha = 0, nq = 0;
     uint64_t p = 0;

@@ -17,21 +17,75 @@
 // constant, so rounds are fully unrolled. Within a round the twiddles of stage
 // u are the 2^u (forward) or 2^(R-1-u) (inverse) consecutive table entries the
 // thread's group needs, each one 16-byte load of (w, w') from the interleaved
-// table. Rings up to 2^12 take one launch per transform; larger rings take two
-// (high bits then the low 8 bits forward, the reverse order inverse).
+// table (from LDS in the high-bit pass of a two-pass ring, whose entries all lie
+// below 256; from a thread-ordered copy in the low-bit pass). Rings up to 2^12
+// take one launch per transform; larger rings take two (high bits then the low 8
+// bits forward, the reverse order inverse).
 //
-// Butterflies are lazy (Harvey): forward values stay in [0, 4q), inverse
-// values in [0, 2q); the last launch reduces to [0, q) (and scales by n^-1).
+// The 64-bit butterflies keep the carry flag out of their arithmetic: the product's
+// reduction adds qt*(2^64 - q) instead of subtracting qt*q, and the conditional
+// subtractions pick their result by the sign bit of x - r (csub_neg), so chains of
+// dependent carry and compare results, which stall the SIMD between instructions,
+// are rare.
+//
+// Butterflies are lazy (Harvey). With 32-bit primes the twiddle products are exact
+// Shoup products in [0, 2q): forward values stay in [0, 4q), inverse values in
+// [0, 2q). With 64-bit primes (q < 2^61) the quotient of a twiddle product is
+// taken from the three partial products that reach the high word of x*w' and
+// drops their carries, which saves half the multiplies of the exact high word and
+// leaves the product in [0, 4q): forward values then stay in [0, 8q), inverse values
+// in [0, 4q). The last launch reduces to [0, q) (and scales by n^-1 with an exact
+// Shoup product).
+#include <type_traits>
+
 #include "hc_internal.h"
 
 namespace hc {
+
+template <typename T>
+__device__ __forceinline__ T csubT(T x, T q) { return x >= q ? x - q : x; }
+
+// x - r if x >= r else x, for 64-bit x < 2^63 + r and r < 2^63, given nr = 2^64 - r:
+// the sign of x - r picks the result through a bit mask, which keeps the carry flag
+// and compare results out of it.
+__device__ __forceinline__ uint64_t csub_neg(uint64_t x, uint64_t nr) {
+    const uint64_t t = x + nr;
+    uint32_t m = (uint32_t)((int32_t)(uint32_t)(t >> 32) >> 31);
+    asm("" : "+v"(m));
+    const uint64_t mm = ((uint64_t)m << 32) | m;
+    return (x & mm) | (t & ~mm);
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
+           __builtin_amdgcn_readfirstlane((uint32_t)v);
+}
+
+__device__ __forceinline__ uint64_t uniformT(uint64_t v) { return uniform64(v); }
+__device__ __forceinline__ uint32_t uniformT(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 template <typename T> struct Ar;
 
 template <> struct Ar<uint64_t> {
     typedef ulonglong2 Pair;
+    static constexpr int LAZY = 2;  // butterfly values are reduced below 4q (forward: 8q)
     static __device__ __forceinline__ uint64_t shoup_lazy(uint64_t x, uint64_t w, uint64_t wp, uint64_t q) {
         return x * w - __umul64hi(x, wp) * q;
+    }
+    // x*w - qt*q with qt = xh*wh' + hi(xh*wl') + hi(xl*wh') for w' = wh'*2^32 + wl':
+    // x*w'/2^64 exceeds qt by the dropped low words, less than 3, so qt is at most 2
+    // below the exact Shoup quotient and the result lies in [0, 4q) for any 64-bit
+    // x. nq = 2^64 - q.
+    static __device__ __forceinline__ uint64_t mul(uint64_t x, uint64_t w, uint64_t wp, uint64_t q, uint64_t nq) {
+        (void)q;
+        const uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32);
+        const uint32_t wl = (uint32_t)wp, wh = (uint32_t)(wp >> 32);
+        const uint64_t qt = (uint64_t)xh * wh + __umulhi(xh, wl) + __umulhi(xl, wh);
+        return x * w + qt * nq;
+    }
+    static __device__ __forceinline__ uint64_t red(uint64_t x, uint64_t r, uint64_t nr) {
+        (void)r;
+        return csub_neg(x, nr);
     }
     static __device__ __forceinline__ void load_pair(const uint64_t* p, uint64_t& w, uint64_t& wp) {
         ulonglong2 v = *reinterpret_cast<const ulonglong2*>(p);
@@ -41,9 +95,14 @@ template <> struct Ar<uint64_t> {
 };
 
 template <> struct Ar<uint32_t> {
+    static constexpr int LAZY = 1;  // butterfly values are reduced below 2q (forward: 4q)
     static __device__ __forceinline__ uint32_t shoup_lazy(uint32_t x, uint32_t w, uint32_t wp, uint32_t q) {
         return x * w - __umulhi(x, wp) * q;
     }
+    static __device__ __forceinline__ uint32_t mul(uint32_t x, uint32_t w, uint32_t wp, uint32_t q, uint32_t) {
+        return shoup_lazy(x, w, wp, q);
+    }
+    static __device__ __forceinline__ uint32_t red(uint32_t x, uint32_t r, uint32_t) { return x >= r ? x - r : x; }
     static __device__ __forceinline__ void load_pair(const uint32_t* p, uint32_t& w, uint32_t& wp) {
         uint2 v = *reinterpret_cast<const uint2*>(p);
         w = v.x;
@@ -51,8 +110,6 @@ template <> struct Ar<uint32_t> {
     }
 };
 
-template <typename T>
-__device__ __forceinline__ T csubT(T x, T q) { return x >= q ? x - q : x; }
 
 // Tables for one prime: [2 directions][n][2] = (w, w') pairs, forward then
 // inverse; plus n^-1 and its Shoup constant.
@@ -94,6 +151,10 @@ struct Tile {
         return o;
     }
     static constexpr int TW_PASS = tw_before(S);  // twiddle pairs per thread over the pass
+    // The pass over the high index bits of a two-pass ring only uses table entries
+    // below 2^S <= THREADS: a block keeps them in LDS, one pair per thread, and its
+    // rounds read no twiddles from global memory.
+    static constexpr bool LTW = BLO != 0 && LOGN > TILE_LOG;
     // In the low-bit pass of a two-pass ring a thread's global-contiguous loads and
     // stores step through the tile at a stride of P words in LDS, which puts a
     // wavefront's lanes on the same banks. One pad word after every P words spreads
@@ -131,7 +192,7 @@ struct Tile {
 
     // one round of R stages; butterfly bits [KBIT, KBIT+R) of k; DONE stages before it
     template <int R, int KBIT, int DONE>
-    static __device__ __forceinline__ void round(T* lds, uint32_t sp0, const T* tw, const T* tw2, T q) {
+    static __device__ __forceinline__ void round(T* lds, uint32_t sp0, const T* tw, const T* tw2, const T* ltw, T q) {
         constexpr int POS = LOGP + KBIT;
         constexpr int GS = 1 << R;
         constexpr int PER = NTT_EPT >> R;  // groups per thread
@@ -147,57 +208,58 @@ struct Tile {
             #pragma unroll
             for (int v = 0; v < GS; v++) x[v] = lds[lb + v * VSTEP];
             const uint32_t j0 = gidx(insert_bits(g, 0, POS, R), sp0);
-            const T twoq = q << 1;
+            const T rq = q << Ar<T>::LAZY;
+            T nq = (T)0 - q, nrq = (T)0 - rq;
+            // opaque to the compiler, so x*w + qt*nq is not turned back into a
+            // subtraction with its carry chain
+            if constexpr (sizeof(T) == 8) {
+                nq = uniform64(nq);
+                nrq = uniform64(nrq);
+                asm("" : "+s"(nq), "+s"(nrq));
+            }
             #pragma unroll
             for (int u = 0; u < R; u++) {
                 const int st = ST0 + DONE + u;
+                // stage u's twiddles: 2^u (forward) or 2^(R-1-u) (inverse) pairs from
+                // base on
+                const int cnt = INV ? (1 << (R - 1 - u)) : (1 << u);
+                uint32_t base = INV ? ((uint32_t)N >> (st + 1)) + (j0 >> (st + 1)) : (1u << st) + (j0 >> (LOGN - st));
+                if constexpr (round_uniform(KBIT, R, DONE)) base = __builtin_amdgcn_readfirstlane(base);
+                T w[8], wp[8];
+                #pragma unroll
+                for (int t = 0; t < cnt; t++) {
+                    if constexpr (TW2)
+                        Ar<T>::load_pair(tw2 + 2 * ((size_t)(tw_before(DONE) + sub * ((1 << R) - 1) + tw_off(R, u) + t) *
+                                                        THREADS + threadIdx.x),
+                                         w[t], wp[t]);
+                    else if constexpr (LTW)
+                        Ar<T>::load_pair(ltw + 2 * (base + t), w[t], wp[t]);
+                    else
+                        Ar<T>::load_pair(tw + 2 * (base + t), w[t], wp[t]);
+                }
                 if (!INV) {
-                    // partner bit R-1-u of v; twiddle 2^st + (j0 >> (LOGN-st)) + (v >> (R-u))
+                    // partner bit R-1-u of v; twiddle base + (v >> (R-u))
                     const int half = 1 << (R - 1 - u);
-                    uint32_t base = (1u << st) + (j0 >> (LOGN - st));
-                    if constexpr (round_uniform(KBIT, R, DONE)) base = __builtin_amdgcn_readfirstlane(base);
-                    T w[8], wp[8];
-                    #pragma unroll
-                    for (int t = 0; t < (1 << u); t++) {
-                        if constexpr (TW2)
-                            Ar<T>::load_pair(tw2 + 2 * ((size_t)(tw_before(DONE) + sub * ((1 << R) - 1) +
-                                                                 tw_off(R, u) + t) * THREADS + threadIdx.x),
-                                             w[t], wp[t]);
-                        else
-                            Ar<T>::load_pair(tw + 2 * (base + t), w[t], wp[t]);
-                    }
                     #pragma unroll
                     for (int v = 0; v < GS; v++) {
                         if (!(v & half)) {
                             const int t = v >> (R - u);
-                            T X = csubT<T>(x[v], twoq);
-                            T y = Ar<T>::shoup_lazy(x[v | half], w[t], wp[t], q);
+                            T X = Ar<T>::red(x[v], rq, nrq);
+                            T y = Ar<T>::mul(x[v | half], w[t], wp[t], q, nq);
                             x[v] = X + y;
-                            x[v | half] = X - y + twoq;
+                            x[v | half] = X - y + rq;
                         }
                     }
                 } else {
-                    // partner bit u of v; twiddle n/2^(st+1) + (j0 >> (st+1)) + (v >> (u+1))
+                    // partner bit u of v; twiddle base + (v >> (u+1))
                     const int half = 1 << u;
-                    uint32_t base = ((uint32_t)N >> (st + 1)) + (j0 >> (st + 1));
-                    if constexpr (round_uniform(KBIT, R, DONE)) base = __builtin_amdgcn_readfirstlane(base);
-                    T w[8], wp[8];
-                    #pragma unroll
-                    for (int t = 0; t < (1 << (R - 1 - u)); t++) {
-                        if constexpr (TW2)
-                            Ar<T>::load_pair(tw2 + 2 * ((size_t)(tw_before(DONE) + sub * ((1 << R) - 1) +
-                                                                 tw_off(R, u) + t) * THREADS + threadIdx.x),
-                                             w[t], wp[t]);
-                        else
-                            Ar<T>::load_pair(tw + 2 * (base + t), w[t], wp[t]);
-                    }
                     #pragma unroll
                     for (int v = 0; v < GS; v++) {
                         if (!(v & half)) {
                             const int t = v >> (u + 1);
                             T X = x[v], Y = x[v | half];
-                            x[v] = csubT<T>(X + Y, twoq);
-                            x[v | half] = Ar<T>::shoup_lazy(X + twoq - Y, w[t], wp[t], q);
+                            x[v] = Ar<T>::red(X + Y, rq, nrq);
+                            x[v | half] = Ar<T>::mul(X + rq - Y, w[t], wp[t], q, nq);
                         }
                     }
                 }
@@ -209,13 +271,13 @@ struct Tile {
 
     // rounds: forward processes k bits from the top down, inverse from the bottom up
     template <int DONE>
-    static __device__ __forceinline__ void rounds(T* lds, uint32_t sp0, const T* tw, const T* tw2, T q) {
+    static __device__ __forceinline__ void rounds(T* lds, uint32_t sp0, const T* tw, const T* tw2, const T* ltw, T q) {
         if constexpr (DONE < S) {
             constexpr int R = round_r(DONE);
             constexpr int KBIT = INV ? DONE : (S - DONE - R);
-            round<R, KBIT, DONE>(lds, sp0, tw, tw2, q);
+            round<R, KBIT, DONE>(lds, sp0, tw, tw2, ltw, q);
             __syncthreads();
-            rounds<DONE + R>(lds, sp0, tw, tw2, q);
+            rounds<DONE + R>(lds, sp0, tw, tw2, ltw, q);
         }
     }
 
@@ -249,55 +311,97 @@ struct Tile {
     }
 };
 
-// WPE: minimum waves per SIMD the registers must allow (1 = no constraint); the second
-// pass of each direction (forward low bits, inverse high bits) fits four waves (128
-// registers) without spills, the first passes would spill.
+// Tiles per block: the high-bit pass of a two-pass ring gives each block two adjacent
+// tiles of one row. Both are loaded up front; the second one's loads are in flight
+// while the first is transformed (its rounds read LDS only), and they were issued
+// before the first tile's stores, so waiting for them never waits for those stores.
+template <typename T, bool INV, int LOGN, int S, int BLO>
+struct Tpb {
+    static constexpr int value = (INV && BLO != 0 && LOGN > TILE_LOG) ? 2 : 1;
+};
+
+// Grid: (tiles of a row / TPB, polynomials, rows). WPE: minimum waves per SIMD the
+// registers must allow (1 = no constraint).
 template <typename T, bool INV, int LOGN, int S, int BLO, int ST0, bool LAST, int WPE>
 __global__ void __launch_bounds__(NTT_THREADS) __attribute__((amdgpu_waves_per_eu(WPE)))
 ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab<T> tab) {
     typedef Tile<T, INV, LOGN, S, BLO, ST0> TL;
+    constexpr int TPB = Tpb<T, INV, LOGN, S, BLO>::value;
+    constexpr int THREADS = TL::THREADS;  // the launch's block size
     __shared__ T lds[TL::LDS_WORDS];
+    __shared__ T ltw[TL::LTW ? 2 * THREADS : 2];
+    const uint32_t tid = threadIdx.x;
     const int row = blockIdx.z;  // limb; polynomials along y, so consecutive blocks of one
                                  // XCD share a (prime, tile) and its twiddles stay in L2
     const int prime = limb_first + row;
     const T q = tab.mods[prime];
     const T* tw = tab.base + ((size_t)prime * 2 + (INV ? 1 : 0)) * 2 * TL::N;
     T* a = data + (size_t)blockIdx.y * poly_stride + (size_t)row * TL::N;
-    const uint32_t sp0 = blockIdx.x * TL::P;
 
-    constexpr int THREADS = TL::TSIZE / NTT_EPT;  // the launch's block size
-    // load in global-contiguous order
-    #pragma unroll
-    for (int i = 0; i < NTT_EPT; i++) {
-        const uint32_t f = threadIdx.x + i * THREADS;
+    // element i of this thread in global-contiguous order: tile element e
+    auto elem = [&](int i) -> uint32_t {
+        const uint32_t f = tid + i * THREADS;
         uint32_t k, spl;
         if (BLO == 0) { spl = f >> S; k = f & ((1u << S) - 1u); }
         else { k = f >> TL::LOGP; spl = f & (TL::P - 1); }
-        const uint32_t e = (k << TL::LOGP) | spl;
-        lds[TL::lpos(e)] = a[TL::gidx(e, sp0)];
-    }
-    __syncthreads();
-    const T* tw2 = nullptr;
-    if constexpr (TL::TW2)
-        tw2 = tab.tw2 + (((size_t)prime * 2 + (INV ? 1 : 0)) * gridDim.x + blockIdx.x) * (size_t)TL::TW_PASS *
-                            TL::THREADS * 2;
-    TL::template rounds<0>(lds, sp0, tw, tw2, q);
+        return (k << TL::LOGP) | spl;
+    };
 
+    T pw0 = 0, pw1 = 0;
+    if constexpr (TL::LTW) {
+        pw0 = tw[2 * tid];
+        pw1 = tw[2 * tid + 1];
+    }
+    static_assert(TPB <= 2, "tiles per block");
+    T x[TPB][NTT_EPT];
+    #pragma unroll
+    for (int k = 0; k < TPB; k++) {
+        const uint32_t sp0 = (blockIdx.x * TPB + k) * TL::P;
+        #pragma unroll
+        for (int i = 0; i < NTT_EPT; i++) x[k][i] = a[TL::gidx(elem(i), sp0)];
+    }
     const T* ni = tab.ninv + 2 * prime;
-    #pragma unroll
-    for (int i = 0; i < NTT_EPT; i++) {
-        const uint32_t f = threadIdx.x + i * THREADS;
-        uint32_t k, spl;
-        if (BLO == 0) { spl = f >> S; k = f & ((1u << S) - 1u); }
-        else { k = f >> TL::LOGP; spl = f & (TL::P - 1); }
-        const uint32_t e = (k << TL::LOGP) | spl;
-        T v = lds[TL::lpos(e)];
-        if (LAST) {
-            if (INV) v = csubT<T>(Ar<T>::shoup_lazy(v, ni[0], ni[1], q), q);
-            else { v = csubT<T>(v, q << 1); v = csubT<T>(v, q); }
-        }
-        a[TL::gidx(e, sp0)] = v;
+    T n0 = 0, n1 = 0;
+    if constexpr (LAST && INV) {
+        n0 = ni[0];
+        n1 = ni[1];
     }
+
+    // one tile through LDS; K is a constant so x[K] stays in registers
+    auto process = [&](auto kc) {
+        constexpr int K = decltype(kc)::value;
+        const uint32_t tile = blockIdx.x * TPB + K;
+        const uint32_t sp0 = tile * TL::P;
+        if constexpr (K > 0) __syncthreads();
+        #pragma unroll
+        for (int i = 0; i < NTT_EPT; i++) lds[TL::lpos(elem(i))] = x[K][i];
+        if constexpr (TL::LTW && K == 0) {
+            ltw[2 * tid] = pw0;
+            ltw[2 * tid + 1] = pw1;
+        }
+        __syncthreads();
+        const T* tw2 = nullptr;
+        if constexpr (TL::TW2)
+            tw2 = tab.tw2 + (((size_t)prime * 2 + (INV ? 1 : 0)) * (gridDim.x * TPB) + tile) * (size_t)TL::TW_PASS *
+                                THREADS * 2;
+        TL::template rounds<0>(lds, sp0, tw, tw2, ltw, q);
+        #pragma unroll
+        for (int i = 0; i < NTT_EPT; i++) {
+            const uint32_t e = elem(i);
+            T v = lds[TL::lpos(e)];
+            if (LAST) {
+                if (INV) v = csubT<T>(Ar<T>::shoup_lazy(v, n0, n1, q), q);
+                else {
+                    if (Ar<T>::LAZY == 2) v = csubT<T>(v, q << 2);
+                    v = csubT<T>(v, q << 1);
+                    v = csubT<T>(v, q);
+                }
+            }
+            a[TL::gidx(e, sp0)] = v;
+        }
+    };
+    process(std::integral_constant<int, 0>());
+    if constexpr (TPB > 1) process(std::integral_constant<int, 1>());
 }
 
 // Launch one pass; `ops` butterflies and `bytes` moved for the timing record.
@@ -306,11 +410,15 @@ static void pass(const Ctx& c, int kind, T* data, size_t stride, int count, int 
                  NttTab<T> tab, hipStream_t st) {
     constexpr int TLOG = LOGN < TILE_LOG ? LOGN : TILE_LOG;
     constexpr int THREADS = (1 << TLOG) / NTT_EPT;
+    constexpr int TPB = Tpb<T, INV, LOGN, S, BLO>::value;
     static_assert(THREADS <= NTT_THREADS, "tile");
-    dim3 grid(1 << (LOGN - TLOG), count, nl);
+    static_assert((1 << (LOGN - TLOG)) % TPB == 0, "tiles per block");
+    // the second pass of each direction (forward low bits, inverse high bits) fits four
+    // waves per SIMD (128 registers) with one tile per block
+    constexpr int WPE = (sizeof(T) == 8 && LOGN > TILE_LOG && (INV ? BLO != 0 : true) && TPB == 1) ? 4 : 1;
+    dim3 grid((1 << (LOGN - TLOG)) / TPB, count, nl);
     const double bytes = 2.0 * sizeof(T) * (double)count * nl * (1 << LOGN);
     const double ops = (double)count * nl * (1 << (LOGN - 1)) * S;
-    constexpr int WPE = (sizeof(T) == 8 && LOGN > TILE_LOG && (INV ? BLO != 0 : BLO == 0)) ? 4 : 1;
     auto launch = [&]() {
         hipLaunchKernelGGL((ntt_tile_kernel<T, INV, LOGN, S, BLO, ST0, LAST, WPE>), grid, dim3(THREADS), 0, st, data,
                            stride, lf, tab);

@@ -43,6 +43,36 @@ def test_ntt_roundtrip_and_ring_product(ring):
     assert np.array_equal(to_host(da), a)
 
 
+@pytest.mark.parametrize("log_n", [10, 13, 14])
+def test_ntt_top_of_range_and_short_high_pass(log_n):
+    """The lazy butterflies' bounds at their limits: a 61-bit special prime (the
+    largest the 64-bit transform takes), every input q - 1, and the two-pass rings
+    whose high-bit pass has fewer than 8 stages (2^13, 2^14)."""
+    from paper_2408_17063_amd import hc
+    from oracle.ring import negacyclic_mul_limb
+    say("ntt extremes", log_n)
+    ctx = hc.Context(log_n=log_n, p=786433, L=2, q_bits=60, K=1, p_bits=61)
+    n, nq = ctx.n, ctx.nq
+    assert max(ctx.primes) >> 60 == 1
+    r = np.random.default_rng(log_n)
+    a = np.stack([np.full(n, q - 1, dtype=np.uint64) for q in ctx.primes])
+    b = np.stack([r.integers(q - 4096, q, n, dtype=np.uint64) for q in ctx.primes])
+    da, db = to_dev(a), to_dev(b)
+    ctx.ntt(da, 0, nq)
+    ctx.ntt(db, 0, nq)
+    fa, fb = to_host(da), to_host(db)
+    assert all((fa[i] < q).all() and (fb[i] < q).all() for i, q in enumerate(ctx.primes))
+    prod = np.stack([((fa[i].astype(object) * fb[i].astype(object)) % q).astype(np.uint64)
+                     for i, q in enumerate(ctx.primes)])
+    dp = to_dev(prod)
+    ctx.ntt(dp, 0, nq, inverse=True)
+    got = to_host(dp)
+    for i in range(nq):
+        assert np.array_equal(got[i], negacyclic_mul_limb(a[i], b[i], ctx.primes[i])), i
+    ctx.ntt(db, 0, nq, inverse=True)
+    assert np.array_equal(to_host(db), b)
+
+
 @pytest.mark.parametrize("ring", ["ring-4096", "ring-65536"])
 def test_samplers_match_oracle(ring):
     import torch
