@@ -17,10 +17,11 @@
 // constant, so rounds are fully unrolled. Within a round the twiddles of stage
 // u are the 2^u (forward) or 2^(R-1-u) (inverse) consecutive table entries the
 // thread's group needs, each one 16-byte load of (w, w') from the interleaved
-// table (from LDS in the high-bit pass of a two-pass ring, whose entries all lie
-// below 256; from a thread-ordered copy in the low-bit pass). Rings up to 2^12
-// take one launch per transform; larger rings take two (high bits then the low 8
-// bits forward, the reverse order inverse).
+// table (from a thread-ordered copy in the low-bit pass of a two-pass ring). Rings
+// up to 2^12 take one launch per transform; larger rings take two (high bits then
+// the low 8 bits forward, the reverse order inverse). The 8-stage high-bit pass
+// keeps its first and last rounds' groups in registers between global memory and
+// the rounds (see Tile::DIRECT).
 //
 // The 64-bit butterflies keep the carry flag out of their arithmetic: the product's
 // reduction adds qt*(2^64 - q) instead of subtracting qt*q, and the conditional
@@ -36,8 +37,6 @@
 // leaves the product in [0, 4q): forward values then stay in [0, 8q), inverse values
 // in [0, 4q). The last launch reduces to [0, q) (and scales by n^-1 with an exact
 // Shoup product).
-#include <type_traits>
-
 #include "hc_internal.h"
 
 namespace hc {
@@ -151,10 +150,12 @@ struct Tile {
         return o;
     }
     static constexpr int TW_PASS = tw_before(S);  // twiddle pairs per thread over the pass
-    // The pass over the high index bits of a two-pass ring only uses table entries
-    // below 2^S <= THREADS: a block keeps them in LDS, one pair per thread, and its
-    // rounds read no twiddles from global memory.
-    static constexpr bool LTW = BLO != 0 && LOGN > TILE_LOG;
+    // The 8-stage pass over the high index bits of a two-pass ring is two rounds of
+    // one group per thread whose elements are 128-byte runs in global memory (16
+    // consecutive sub-problems) in both rounds' layouts: a thread loads its first
+    // round's group straight from global memory and stores its second round's group
+    // straight back, so the tile passes through LDS once.
+    static constexpr bool DIRECT = BLO != 0 && LOGN > TILE_LOG && S == 2 * NTT_EPT_LOG;  // (no LDS padding)
     // In the low-bit pass of a two-pass ring a thread's global-contiguous loads and
     // stores step through the tile at a stride of P words in LDS, which puts a
     // wavefront's lanes on the same banks. One pad word after every P words spreads
@@ -190,9 +191,73 @@ struct Tile {
         return ((sp >> BLO) << (BLO + S)) | (k << BLO) | (sp & ((1u << BLO) - 1u));
     }
 
-    // one round of R stages; butterfly bits [KBIT, KBIT+R) of k; DONE stages before it
+    // The R stages of one round on one group held in registers: x[v] is tile element
+    // insert_bits(g, v, LOGP + KBIT, R); butterfly bits [KBIT, KBIT+R) of k; DONE
+    // stages before it; sub: the group's index among the thread's groups.
     template <int R, int KBIT, int DONE>
-    static __device__ __forceinline__ void round(T* lds, uint32_t sp0, const T* tw, const T* tw2, const T* ltw, T q) {
+    static __device__ __forceinline__ void butterflies(T (&x)[1 << R], uint32_t g, int sub, uint32_t sp0, const T* tw,
+                                                       const T* tw2, T q) {
+        constexpr int POS = LOGP + KBIT;
+        constexpr int GS = 1 << R;
+        const uint32_t j0 = gidx(insert_bits(g, 0, POS, R), sp0);
+        const T rq = q << Ar<T>::LAZY;
+        T nq = (T)0 - q, nrq = (T)0 - rq;
+        // opaque to the compiler, so x*w + qt*nq is not turned back into a
+        // subtraction with its carry chain
+        if constexpr (sizeof(T) == 8) {
+            nq = uniform64(nq);
+            nrq = uniform64(nrq);
+            asm("" : "+s"(nq), "+s"(nrq));
+        }
+        #pragma unroll
+        for (int u = 0; u < R; u++) {
+            const int st = ST0 + DONE + u;
+            // stage u's twiddles: 2^u (forward) or 2^(R-1-u) (inverse) pairs from base on
+            const int cnt = INV ? (1 << (R - 1 - u)) : (1 << u);
+            uint32_t base = INV ? ((uint32_t)N >> (st + 1)) + (j0 >> (st + 1)) : (1u << st) + (j0 >> (LOGN - st));
+            if constexpr (round_uniform(KBIT, R, DONE)) base = __builtin_amdgcn_readfirstlane(base);
+            T w[8], wp[8];
+            #pragma unroll
+            for (int t = 0; t < cnt; t++) {
+                if constexpr (TW2)
+                    Ar<T>::load_pair(tw2 + 2 * ((size_t)(tw_before(DONE) + sub * ((1 << R) - 1) + tw_off(R, u) + t) *
+                                                    THREADS + threadIdx.x),
+                                     w[t], wp[t]);
+                else
+                    Ar<T>::load_pair(tw + 2 * (base + t), w[t], wp[t]);
+            }
+            if (!INV) {
+                // partner bit R-1-u of v; twiddle base + (v >> (R-u))
+                const int half = 1 << (R - 1 - u);
+                #pragma unroll
+                for (int v = 0; v < GS; v++) {
+                    if (!(v & half)) {
+                        const int t = v >> (R - u);
+                        T X = Ar<T>::red(x[v], rq, nrq);
+                        T y = Ar<T>::mul(x[v | half], w[t], wp[t], q, nq);
+                        x[v] = X + y;
+                        x[v | half] = X - y + rq;
+                    }
+                }
+            } else {
+                // partner bit u of v; twiddle base + (v >> (u+1))
+                const int half = 1 << u;
+                #pragma unroll
+                for (int v = 0; v < GS; v++) {
+                    if (!(v & half)) {
+                        const int t = v >> (u + 1);
+                        T X = x[v], Y = x[v | half];
+                        x[v] = Ar<T>::red(X + Y, rq, nrq);
+                        x[v | half] = Ar<T>::mul(X + rq - Y, w[t], wp[t], q, nq);
+                    }
+                }
+            }
+        }
+    }
+
+    // one round of R stages on the tile in LDS
+    template <int R, int KBIT, int DONE>
+    static __device__ __forceinline__ void round(T* lds, uint32_t sp0, const T* tw, const T* tw2, T q) {
         constexpr int POS = LOGP + KBIT;
         constexpr int GS = 1 << R;
         constexpr int PER = NTT_EPT >> R;  // groups per thread
@@ -207,63 +272,7 @@ struct Tile {
             T x[GS];
             #pragma unroll
             for (int v = 0; v < GS; v++) x[v] = lds[lb + v * VSTEP];
-            const uint32_t j0 = gidx(insert_bits(g, 0, POS, R), sp0);
-            const T rq = q << Ar<T>::LAZY;
-            T nq = (T)0 - q, nrq = (T)0 - rq;
-            // opaque to the compiler, so x*w + qt*nq is not turned back into a
-            // subtraction with its carry chain
-            if constexpr (sizeof(T) == 8) {
-                nq = uniform64(nq);
-                nrq = uniform64(nrq);
-                asm("" : "+s"(nq), "+s"(nrq));
-            }
-            #pragma unroll
-            for (int u = 0; u < R; u++) {
-                const int st = ST0 + DONE + u;
-                // stage u's twiddles: 2^u (forward) or 2^(R-1-u) (inverse) pairs from
-                // base on
-                const int cnt = INV ? (1 << (R - 1 - u)) : (1 << u);
-                uint32_t base = INV ? ((uint32_t)N >> (st + 1)) + (j0 >> (st + 1)) : (1u << st) + (j0 >> (LOGN - st));
-                if constexpr (round_uniform(KBIT, R, DONE)) base = __builtin_amdgcn_readfirstlane(base);
-                T w[8], wp[8];
-                #pragma unroll
-                for (int t = 0; t < cnt; t++) {
-                    if constexpr (TW2)
-                        Ar<T>::load_pair(tw2 + 2 * ((size_t)(tw_before(DONE) + sub * ((1 << R) - 1) + tw_off(R, u) + t) *
-                                                        THREADS + threadIdx.x),
-                                         w[t], wp[t]);
-                    else if constexpr (LTW)
-                        Ar<T>::load_pair(ltw + 2 * (base + t), w[t], wp[t]);
-                    else
-                        Ar<T>::load_pair(tw + 2 * (base + t), w[t], wp[t]);
-                }
-                if (!INV) {
-                    // partner bit R-1-u of v; twiddle base + (v >> (R-u))
-                    const int half = 1 << (R - 1 - u);
-                    #pragma unroll
-                    for (int v = 0; v < GS; v++) {
-                        if (!(v & half)) {
-                            const int t = v >> (R - u);
-                            T X = Ar<T>::red(x[v], rq, nrq);
-                            T y = Ar<T>::mul(x[v | half], w[t], wp[t], q, nq);
-                            x[v] = X + y;
-                            x[v | half] = X - y + rq;
-                        }
-                    }
-                } else {
-                    // partner bit u of v; twiddle base + (v >> (u+1))
-                    const int half = 1 << u;
-                    #pragma unroll
-                    for (int v = 0; v < GS; v++) {
-                        if (!(v & half)) {
-                            const int t = v >> (u + 1);
-                            T X = x[v], Y = x[v | half];
-                            x[v] = Ar<T>::red(X + Y, rq, nrq);
-                            x[v | half] = Ar<T>::mul(X + rq - Y, w[t], wp[t], q, nq);
-                        }
-                    }
-                }
-            }
+            butterflies<R, KBIT, DONE>(x, g, sub, sp0, tw, tw2, q);
             #pragma unroll
             for (int v = 0; v < GS; v++) lds[lb + v * VSTEP] = x[v];
         }
@@ -271,13 +280,13 @@ struct Tile {
 
     // rounds: forward processes k bits from the top down, inverse from the bottom up
     template <int DONE>
-    static __device__ __forceinline__ void rounds(T* lds, uint32_t sp0, const T* tw, const T* tw2, const T* ltw, T q) {
+    static __device__ __forceinline__ void rounds(T* lds, uint32_t sp0, const T* tw, const T* tw2, T q) {
         if constexpr (DONE < S) {
             constexpr int R = round_r(DONE);
             constexpr int KBIT = INV ? DONE : (S - DONE - R);
-            round<R, KBIT, DONE>(lds, sp0, tw, tw2, ltw, q);
+            round<R, KBIT, DONE>(lds, sp0, tw, tw2, q);
             __syncthreads();
-            rounds<DONE + R>(lds, sp0, tw, tw2, ltw, q);
+            rounds<DONE + R>(lds, sp0, tw, tw2, q);
         }
     }
 
@@ -311,25 +320,14 @@ struct Tile {
     }
 };
 
-// Tiles per block: the high-bit pass of a two-pass ring gives each block two adjacent
-// tiles of one row. Both are loaded up front; the second one's loads are in flight
-// while the first is transformed (its rounds read LDS only), and they were issued
-// before the first tile's stores, so waiting for them never waits for those stores.
-template <typename T, bool INV, int LOGN, int S, int BLO>
-struct Tpb {
-    static constexpr int value = (INV && BLO != 0 && LOGN > TILE_LOG) ? 2 : 1;
-};
-
-// Grid: (tiles of a row / TPB, polynomials, rows). WPE: minimum waves per SIMD the
+// Grid: (tiles of a row, polynomials, rows). WPE: minimum waves per SIMD the
 // registers must allow (1 = no constraint).
 template <typename T, bool INV, int LOGN, int S, int BLO, int ST0, bool LAST, int WPE>
 __global__ void __launch_bounds__(NTT_THREADS) __attribute__((amdgpu_waves_per_eu(WPE)))
 ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab<T> tab) {
     typedef Tile<T, INV, LOGN, S, BLO, ST0> TL;
-    constexpr int TPB = Tpb<T, INV, LOGN, S, BLO>::value;
     constexpr int THREADS = TL::THREADS;  // the launch's block size
     __shared__ T lds[TL::LDS_WORDS];
-    __shared__ T ltw[TL::LTW ? 2 * THREADS : 2];
     const uint32_t tid = threadIdx.x;
     const int row = blockIdx.z;  // limb; polynomials along y, so consecutive blocks of one
                                  // XCD share a (prime, tile) and its twiddles stay in L2
@@ -337,71 +335,65 @@ ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab
     const T q = tab.mods[prime];
     const T* tw = tab.base + ((size_t)prime * 2 + (INV ? 1 : 0)) * 2 * TL::N;
     T* a = data + (size_t)blockIdx.y * poly_stride + (size_t)row * TL::N;
+    const uint32_t sp0 = blockIdx.x * TL::P;
+    const T* ni = tab.ninv + 2 * prime;
+    auto finish = [&](T v) -> T {
+        if (LAST) {
+            if (INV) v = csubT<T>(Ar<T>::shoup_lazy(v, ni[0], ni[1], q), q);
+            else {
+                if (Ar<T>::LAZY == 2) v = csubT<T>(v, q << 2);
+                v = csubT<T>(v, q << 1);
+                v = csubT<T>(v, q);
+            }
+        }
+        return v;
+    };
 
-    // element i of this thread in global-contiguous order: tile element e
-    auto elem = [&](int i) -> uint32_t {
+    if constexpr (TL::DIRECT) {
+        constexpr int R = NTT_EPT_LOG;
+        constexpr int P1 = TL::LOGP + (INV ? 0 : R);  // first round: group bits of k
+        constexpr int P2 = TL::LOGP + (INV ? R : 0);  // second round
+        T x[NTT_EPT];
+        #pragma unroll
+        for (int v = 0; v < NTT_EPT; v++) x[v] = a[TL::gidx(insert_bits(tid, v, P1, R), sp0)];
+        TL::template butterflies<R, P1 - TL::LOGP, 0>(x, tid, 0, sp0, tw, nullptr, q);
+        #pragma unroll
+        for (int v = 0; v < NTT_EPT; v++) lds[insert_bits(tid, v, P1, R)] = x[v];
+        __syncthreads();
+        #pragma unroll
+        for (int v = 0; v < NTT_EPT; v++) x[v] = lds[insert_bits(tid, v, P2, R)];
+        TL::template butterflies<R, P2 - TL::LOGP, R>(x, tid, 0, sp0, tw, nullptr, q);
+        #pragma unroll
+        for (int v = 0; v < NTT_EPT; v++) a[TL::gidx(insert_bits(tid, v, P2, R), sp0)] = finish(x[v]);
+        return;
+    }
+
+    // load in global-contiguous order
+    #pragma unroll
+    for (int i = 0; i < NTT_EPT; i++) {
         const uint32_t f = tid + i * THREADS;
         uint32_t k, spl;
         if (BLO == 0) { spl = f >> S; k = f & ((1u << S) - 1u); }
         else { k = f >> TL::LOGP; spl = f & (TL::P - 1); }
-        return (k << TL::LOGP) | spl;
-    };
-
-    T pw0 = 0, pw1 = 0;
-    if constexpr (TL::LTW) {
-        pw0 = tw[2 * tid];
-        pw1 = tw[2 * tid + 1];
+        const uint32_t e = (k << TL::LOGP) | spl;
+        lds[TL::lpos(e)] = a[TL::gidx(e, sp0)];
     }
-    static_assert(TPB <= 2, "tiles per block");
-    T x[TPB][NTT_EPT];
+    __syncthreads();
+    const T* tw2 = nullptr;
+    if constexpr (TL::TW2)
+        tw2 = tab.tw2 + (((size_t)prime * 2 + (INV ? 1 : 0)) * gridDim.x + blockIdx.x) * (size_t)TL::TW_PASS *
+                            THREADS * 2;
+    TL::template rounds<0>(lds, sp0, tw, tw2, q);
+
     #pragma unroll
-    for (int k = 0; k < TPB; k++) {
-        const uint32_t sp0 = (blockIdx.x * TPB + k) * TL::P;
-        #pragma unroll
-        for (int i = 0; i < NTT_EPT; i++) x[k][i] = a[TL::gidx(elem(i), sp0)];
+    for (int i = 0; i < NTT_EPT; i++) {
+        const uint32_t f = tid + i * THREADS;
+        uint32_t k, spl;
+        if (BLO == 0) { spl = f >> S; k = f & ((1u << S) - 1u); }
+        else { k = f >> TL::LOGP; spl = f & (TL::P - 1); }
+        const uint32_t e = (k << TL::LOGP) | spl;
+        a[TL::gidx(e, sp0)] = finish(lds[TL::lpos(e)]);
     }
-    const T* ni = tab.ninv + 2 * prime;
-    T n0 = 0, n1 = 0;
-    if constexpr (LAST && INV) {
-        n0 = ni[0];
-        n1 = ni[1];
-    }
-
-    // one tile through LDS; K is a constant so x[K] stays in registers
-    auto process = [&](auto kc) {
-        constexpr int K = decltype(kc)::value;
-        const uint32_t tile = blockIdx.x * TPB + K;
-        const uint32_t sp0 = tile * TL::P;
-        if constexpr (K > 0) __syncthreads();
-        #pragma unroll
-        for (int i = 0; i < NTT_EPT; i++) lds[TL::lpos(elem(i))] = x[K][i];
-        if constexpr (TL::LTW && K == 0) {
-            ltw[2 * tid] = pw0;
-            ltw[2 * tid + 1] = pw1;
-        }
-        __syncthreads();
-        const T* tw2 = nullptr;
-        if constexpr (TL::TW2)
-            tw2 = tab.tw2 + (((size_t)prime * 2 + (INV ? 1 : 0)) * (gridDim.x * TPB) + tile) * (size_t)TL::TW_PASS *
-                                THREADS * 2;
-        TL::template rounds<0>(lds, sp0, tw, tw2, ltw, q);
-        #pragma unroll
-        for (int i = 0; i < NTT_EPT; i++) {
-            const uint32_t e = elem(i);
-            T v = lds[TL::lpos(e)];
-            if (LAST) {
-                if (INV) v = csubT<T>(Ar<T>::shoup_lazy(v, n0, n1, q), q);
-                else {
-                    if (Ar<T>::LAZY == 2) v = csubT<T>(v, q << 2);
-                    v = csubT<T>(v, q << 1);
-                    v = csubT<T>(v, q);
-                }
-            }
-            a[TL::gidx(e, sp0)] = v;
-        }
-    };
-    process(std::integral_constant<int, 0>());
-    if constexpr (TPB > 1) process(std::integral_constant<int, 1>());
 }
 
 // Launch one pass; `ops` butterflies and `bytes` moved for the timing record.
@@ -410,13 +402,11 @@ static void pass(const Ctx& c, int kind, T* data, size_t stride, int count, int 
                  NttTab<T> tab, hipStream_t st) {
     constexpr int TLOG = LOGN < TILE_LOG ? LOGN : TILE_LOG;
     constexpr int THREADS = (1 << TLOG) / NTT_EPT;
-    constexpr int TPB = Tpb<T, INV, LOGN, S, BLO>::value;
     static_assert(THREADS <= NTT_THREADS, "tile");
-    static_assert((1 << (LOGN - TLOG)) % TPB == 0, "tiles per block");
-    // the second pass of each direction (forward low bits, inverse high bits) fits four
-    // waves per SIMD (128 registers) with one tile per block
-    constexpr int WPE = (sizeof(T) == 8 && LOGN > TILE_LOG && (INV ? BLO != 0 : true) && TPB == 1) ? 4 : 1;
-    dim3 grid((1 << (LOGN - TLOG)) / TPB, count, nl);
+    // 64-bit passes of two-pass rings: four waves per SIMD (128 registers), which the
+    // twiddle-heavy passes reach with a few spilled words
+    constexpr int WPE = (sizeof(T) == 8 && LOGN > TILE_LOG) ? 4 : 1;
+    dim3 grid(1 << (LOGN - TLOG), count, nl);
     const double bytes = 2.0 * sizeof(T) * (double)count * nl * (1 << LOGN);
     const double ops = (double)count * nl * (1 << (LOGN - 1)) * S;
     auto launch = [&]() {
