@@ -137,16 +137,21 @@ struct Tile {
     static constexpr int P = 1 << LOGP;
     static constexpr int N = 1 << LOGN;
     static constexpr int THREADS = TSIZE / NTT_EPT;
-    // The pass over the low index bits of a two-pass ring reads twiddles that differ
-    // from thread to thread (up to one per butterfly in the last stages). They come
-    // from a copy of the table laid out in the order the threads consume them,
-    // [tile][ord][thread], so each load instruction reads one contiguous run.
+    // The pass over the low index bits of a two-pass ring has one round whose
+    // twiddles differ from thread to thread (up to one per butterfly in the last
+    // forward stages, the first inverse ones). They come from a copy of the table
+    // laid out in the order the threads consume them, [tile][ord][thread], so each
+    // load instruction reads one contiguous run. In its other round a thread's
+    // twiddles depend on its sub-problem only: 16 consecutive table entries serve a
+    // block, and they are read from the table itself.
     static constexpr bool TW2 = sizeof(T) == 8 && BLO == 0 && LOGN > TILE_LOG;
     static constexpr int round_r(int done) { return (S - done) >= NTT_EPT_LOG ? NTT_EPT_LOG : (S - done); }
+    static constexpr bool tw2_round(int done) { return TW2 && (INV ? done == 0 : done != 0); }
     static constexpr int round_tw(int r) { return (NTT_EPT >> r) * ((1 << r) - 1); }
     static constexpr int tw_before(int done) {
         int o = 0;
-        for (int d = 0; d < done; d += round_r(d)) o += round_tw(round_r(d));
+        for (int d = 0; d < done; d += round_r(d))
+            if (tw2_round(d)) o += round_tw(round_r(d));
         return o;
     }
     static constexpr int TW_PASS = tw_before(S);  // twiddle pairs per thread over the pass
@@ -219,7 +224,7 @@ struct Tile {
             T w[8], wp[8];
             #pragma unroll
             for (int t = 0; t < cnt; t++) {
-                if constexpr (TW2)
+                if constexpr (tw2_round(DONE))
                     Ar<T>::load_pair(tw2 + 2 * ((size_t)(tw_before(DONE) + sub * ((1 << R) - 1) + tw_off(R, u) + t) *
                                                     THREADS + threadIdx.x),
                                      w[t], wp[t]);
@@ -299,7 +304,7 @@ struct Tile {
             constexpr int KBIT = INV ? DONE : (S - DONE - R);
             constexpr int POS = LOGP + KBIT;
             constexpr int PER = NTT_EPT >> R;
-            for (int sub = 0; sub < PER; sub++) {
+            for (int sub = 0; sub < (tw2_round(DONE) ? PER : 0); sub++) {
                 const uint32_t g = threadIdx.x * PER + sub;
                 const uint32_t j0 = gidx(insert_bits(g, 0, POS, R), sp0);
                 for (int u = 0; u < R; u++) {
@@ -337,14 +342,20 @@ ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab
     T* a = data + (size_t)blockIdx.y * poly_stride + (size_t)row * TL::N;
     const uint32_t sp0 = blockIdx.x * TL::P;
     const T* ni = tab.ninv + 2 * prime;
+    // the last launch: [0, 8q) or [0, 4q) forward, times n^-1 inverse, down to [0, q)
     auto finish = [&](T v) -> T {
-        if (LAST) {
-            if (INV) v = csubT<T>(Ar<T>::shoup_lazy(v, ni[0], ni[1], q), q);
-            else {
-                if (Ar<T>::LAZY == 2) v = csubT<T>(v, q << 2);
-                v = csubT<T>(v, q << 1);
-                v = csubT<T>(v, q);
+        if constexpr (LAST) {
+            T nq1 = (T)0 - q, nq2 = (T)0 - (q << 1), nq4 = (T)0 - (q << 2);
+            if constexpr (sizeof(T) == 8) {
+                nq1 = uniform64(nq1);
+                nq2 = uniform64(nq2);
+                nq4 = uniform64(nq4);
+                asm("" : "+s"(nq1), "+s"(nq2), "+s"(nq4));
             }
+            if constexpr (INV) v = Ar<T>::mul(v, ni[0], ni[1], q, nq1);  // [0, 4q) (64-bit), [0, 2q)
+            if constexpr (Ar<T>::LAZY == 2 && !INV) v = Ar<T>::red(v, q << 2, nq4);
+            if constexpr (Ar<T>::LAZY == 2 || !INV) v = Ar<T>::red(v, q << 1, nq2);
+            v = Ar<T>::red(v, q, nq1);
         }
         return v;
     };
