@@ -161,6 +161,13 @@ struct Tile {
     // round's group straight from global memory and stores its second round's group
     // straight back, so the tile passes through LDS once.
     static constexpr bool DIRECT = BLO != 0 && LOGN > TILE_LOG && S == 2 * NTT_EPT_LOG;  // (no LDS padding)
+    // In the 8-stage low-bit pass the round over k's high 4 bits (the forward pass's
+    // first, the inverse pass's second) has groups of stride 16 within a sub-problem:
+    // with the group index's nibbles swapped (lanes take consecutive k low bits) its
+    // elements are 128-byte runs, so the forward pass loads that round's groups
+    // straight from global memory and the inverse pass stores them straight back.
+    static constexpr bool DIRECT_LO = BLO == 0 && LOGN > TILE_LOG && S == 2 * NTT_EPT_LOG && THREADS == 256;
+    static __device__ __forceinline__ uint32_t swap_nibbles(uint32_t t) { return ((t & 15u) << 4) | (t >> 4); }
     // In the low-bit pass of a two-pass ring a thread's global-contiguous loads and
     // stores step through the tile at a stride of P words in LDS, which puts a
     // wavefront's lanes on the same banks. One pad word after every P words spreads
@@ -379,22 +386,56 @@ ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab
         return;
     }
 
-    // load in global-contiguous order
-    #pragma unroll
-    for (int i = 0; i < NTT_EPT; i++) {
-        const uint32_t f = tid + i * THREADS;
-        uint32_t k, spl;
-        if (BLO == 0) { spl = f >> S; k = f & ((1u << S) - 1u); }
-        else { k = f >> TL::LOGP; spl = f & (TL::P - 1); }
-        const uint32_t e = (k << TL::LOGP) | spl;
-        lds[TL::lpos(e)] = a[TL::gidx(e, sp0)];
-    }
-    __syncthreads();
     const T* tw2 = nullptr;
     if constexpr (TL::TW2)
         tw2 = tab.tw2 + (((size_t)prime * 2 + (INV ? 1 : 0)) * gridDim.x + blockIdx.x) * (size_t)TL::TW_PASS *
                             THREADS * 2;
-    TL::template rounds<0>(lds, sp0, tw, tw2, q);
+
+    if constexpr (TL::DIRECT_LO) {
+        constexpr int R = NTT_EPT_LOG;
+        constexpr int PH = TL::LOGP + R;  // groups over k's high 4 bits
+        const uint32_t gh = TL::swap_nibbles(tid);
+        T x[NTT_EPT];
+        if constexpr (!INV) {
+            #pragma unroll
+            for (int v = 0; v < NTT_EPT; v++) x[v] = a[TL::gidx(insert_bits(gh, v, PH, R), sp0)];
+            TL::template butterflies<R, R, 0>(x, gh, 0, sp0, tw, tw2, q);
+            #pragma unroll
+            for (int v = 0; v < NTT_EPT; v++) lds[TL::lpos(insert_bits(gh, v, PH, R))] = x[v];
+            __syncthreads();
+            TL::template round<R, 0, R>(lds, sp0, tw, tw2, q);
+            __syncthreads();
+        } else {
+            #pragma unroll
+            for (int i = 0; i < NTT_EPT; i++) {
+                const uint32_t f = tid + i * THREADS;
+                const uint32_t e = ((f & ((1u << S) - 1u)) << TL::LOGP) | (f >> S);
+                lds[TL::lpos(e)] = a[TL::gidx(e, sp0)];
+            }
+            __syncthreads();
+            TL::template round<R, 0, 0>(lds, sp0, tw, tw2, q);
+            __syncthreads();
+            #pragma unroll
+            for (int v = 0; v < NTT_EPT; v++) x[v] = lds[TL::lpos(insert_bits(gh, v, PH, R))];
+            TL::template butterflies<R, R, R>(x, gh, 0, sp0, tw, tw2, q);
+            #pragma unroll
+            for (int v = 0; v < NTT_EPT; v++) a[TL::gidx(insert_bits(gh, v, PH, R), sp0)] = finish(x[v]);
+            return;
+        }
+    } else {
+        // load in global-contiguous order
+        #pragma unroll
+        for (int i = 0; i < NTT_EPT; i++) {
+            const uint32_t f = tid + i * THREADS;
+            uint32_t k, spl;
+            if (BLO == 0) { spl = f >> S; k = f & ((1u << S) - 1u); }
+            else { k = f >> TL::LOGP; spl = f & (TL::P - 1); }
+            const uint32_t e = (k << TL::LOGP) | spl;
+            lds[TL::lpos(e)] = a[TL::gidx(e, sp0)];
+        }
+        __syncthreads();
+        TL::template rounds<0>(lds, sp0, tw, tw2, q);
+    }
 
     #pragma unroll
     for (int i = 0; i < NTT_EPT; i++) {
