@@ -35,8 +35,11 @@
 // taken from the three partial products that reach the high word of x*w' and
 // drops their carries, which saves half the multiplies of the exact high word and
 // leaves the product in [0, 4q): forward values then stay in [0, 8q), inverse values
-// in [0, 4q). The last launch reduces to [0, q) (and scales by n^-1 with an exact
-// Shoup product).
+// in [0, 4q). For primes below 2^57 (a block checks its row's prime) the forward
+// transform makes no conditional subtractions at all: a stage adds at most 4q to
+// the bound, so 16 stages from below 8q stay below 72q < 2^64, and the last launch
+// reduces with one truncated product by 1. The last launch reduces to [0, q) (and
+// scales by n^-1).
 #include "hc_internal.h"
 
 namespace hc {
@@ -206,7 +209,10 @@ struct Tile {
     // The R stages of one round on one group held in registers: x[v] is tile element
     // insert_bits(g, v, LOGP + KBIT, R); butterfly bits [KBIT, KBIT+R) of k; DONE
     // stages before it; sub: the group's index among the thread's groups.
-    template <int R, int KBIT, int DONE>
+    // NR (forward, 64-bit primes below 2^57): no conditional subtraction; a forward
+    // stage then adds at most 4q to the bound, and 16 stages from below 8q stay below
+    // 72q < 2^64.
+    template <int R, int KBIT, int DONE, bool NR = false>
     static __device__ __forceinline__ void butterflies(T (&x)[1 << R], uint32_t g, int sub, uint32_t sp0, const T* tw,
                                                        const T* tw2, T q) {
         constexpr int POS = LOGP + KBIT;
@@ -245,7 +251,7 @@ struct Tile {
                 for (int v = 0; v < GS; v++) {
                     if (!(v & half)) {
                         const int t = v >> (R - u);
-                        T X = Ar<T>::red(x[v], rq, nrq);
+                        T X = NR ? x[v] : Ar<T>::red(x[v], rq, nrq);
                         T y = Ar<T>::mul(x[v | half], w[t], wp[t], q, nq);
                         x[v] = X + y;
                         x[v | half] = X - y + rq;
@@ -268,7 +274,7 @@ struct Tile {
     }
 
     // one round of R stages on the tile in LDS
-    template <int R, int KBIT, int DONE>
+    template <int R, int KBIT, int DONE, bool NR = false>
     static __device__ __forceinline__ void round(T* lds, uint32_t sp0, const T* tw, const T* tw2, T q) {
         constexpr int POS = LOGP + KBIT;
         constexpr int GS = 1 << R;
@@ -284,21 +290,21 @@ struct Tile {
             T x[GS];
             #pragma unroll
             for (int v = 0; v < GS; v++) x[v] = lds[lb + v * VSTEP];
-            butterflies<R, KBIT, DONE>(x, g, sub, sp0, tw, tw2, q);
+            butterflies<R, KBIT, DONE, NR>(x, g, sub, sp0, tw, tw2, q);
             #pragma unroll
             for (int v = 0; v < GS; v++) lds[lb + v * VSTEP] = x[v];
         }
     }
 
     // rounds: forward processes k bits from the top down, inverse from the bottom up
-    template <int DONE>
+    template <int DONE, bool NR = false>
     static __device__ __forceinline__ void rounds(T* lds, uint32_t sp0, const T* tw, const T* tw2, T q) {
         if constexpr (DONE < S) {
             constexpr int R = round_r(DONE);
             constexpr int KBIT = INV ? DONE : (S - DONE - R);
-            round<R, KBIT, DONE>(lds, sp0, tw, tw2, q);
+            round<R, KBIT, DONE, NR>(lds, sp0, tw, tw2, q);
             __syncthreads();
-            rounds<DONE + R>(lds, sp0, tw, tw2, q);
+            rounds<DONE + R, NR>(lds, sp0, tw, tw2, q);
         }
     }
 
@@ -349,81 +355,99 @@ ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab
     T* a = data + (size_t)blockIdx.y * poly_stride + (size_t)row * TL::N;
     const uint32_t sp0 = blockIdx.x * TL::P;
     const T* ni = tab.ninv + 2 * prime;
-    // the last launch: [0, 8q) or [0, 4q) forward, times n^-1 inverse, down to [0, q)
-    auto finish = [&](T v) -> T {
-        if constexpr (LAST) {
-            T nq1 = (T)0 - q, nq2 = (T)0 - (q << 1), nq4 = (T)0 - (q << 2);
-            if constexpr (sizeof(T) == 8) {
-                nq1 = uniform64(nq1);
-                nq2 = uniform64(nq2);
-                nq4 = uniform64(nq4);
-                asm("" : "+s"(nq1), "+s"(nq2), "+s"(nq4));
+    // NR: forward transform of a 64-bit prime below 2^57 without conditional subtractions
+    auto body = [&](auto nr_c) __attribute__((always_inline)) {
+        constexpr bool NR = decltype(nr_c)::value;
+        // the last launch: forward values below 8q (4q with 32-bit primes; 72q without
+        // conditional subtractions), inverse values times n^-1, down to [0, q)
+        auto finish = [&](T v) -> T {
+            if constexpr (LAST) {
+                T nq1 = (T)0 - q, nq2 = (T)0 - (q << 1), nq4 = (T)0 - (q << 2);
+                if constexpr (sizeof(T) == 8) {
+                    nq1 = uniform64(nq1);
+                    nq2 = uniform64(nq2);
+                    nq4 = uniform64(nq4);
+                    asm("" : "+s"(nq1), "+s"(nq2), "+s"(nq4));
+                }
+                if constexpr (INV) v = Ar<T>::mul(v, ni[0], ni[1], q, nq1);  // [0, 4q) (64-bit), [0, 2q)
+                else if constexpr (NR) v = Ar<T>::mul(v, tw[0], tw[1], q, nq1);  // entry 0 is (1, 2^64 / q): [0, 4q)
+                else if constexpr (Ar<T>::LAZY == 2) v = Ar<T>::red(v, q << 2, nq4);
+                if constexpr (Ar<T>::LAZY == 2 || !INV) v = Ar<T>::red(v, q << 1, nq2);
+                v = Ar<T>::red(v, q, nq1);
             }
-            if constexpr (INV) v = Ar<T>::mul(v, ni[0], ni[1], q, nq1);  // [0, 4q) (64-bit), [0, 2q)
-            if constexpr (Ar<T>::LAZY == 2 && !INV) v = Ar<T>::red(v, q << 2, nq4);
-            if constexpr (Ar<T>::LAZY == 2 || !INV) v = Ar<T>::red(v, q << 1, nq2);
-            v = Ar<T>::red(v, q, nq1);
+            return v;
+        };
+
+        if constexpr (TL::DIRECT) {
+            constexpr int R = NTT_EPT_LOG;
+            constexpr int P1 = TL::LOGP + (INV ? 0 : R);  // first round: group bits of k
+            constexpr int P2 = TL::LOGP + (INV ? R : 0);  // second round
+            T x[NTT_EPT];
+            #pragma unroll
+            for (int v = 0; v < NTT_EPT; v++) x[v] = a[TL::gidx(insert_bits(tid, v, P1, R), sp0)];
+            TL::template butterflies<R, P1 - TL::LOGP, 0, NR>(x, tid, 0, sp0, tw, nullptr, q);
+            #pragma unroll
+            for (int v = 0; v < NTT_EPT; v++) lds[insert_bits(tid, v, P1, R)] = x[v];
+            __syncthreads();
+            #pragma unroll
+            for (int v = 0; v < NTT_EPT; v++) x[v] = lds[insert_bits(tid, v, P2, R)];
+            TL::template butterflies<R, P2 - TL::LOGP, R, NR>(x, tid, 0, sp0, tw, nullptr, q);
+            #pragma unroll
+            for (int v = 0; v < NTT_EPT; v++) a[TL::gidx(insert_bits(tid, v, P2, R), sp0)] = finish(x[v]);
+            return;
         }
-        return v;
-    };
 
-    if constexpr (TL::DIRECT) {
-        constexpr int R = NTT_EPT_LOG;
-        constexpr int P1 = TL::LOGP + (INV ? 0 : R);  // first round: group bits of k
-        constexpr int P2 = TL::LOGP + (INV ? R : 0);  // second round
-        T x[NTT_EPT];
-        #pragma unroll
-        for (int v = 0; v < NTT_EPT; v++) x[v] = a[TL::gidx(insert_bits(tid, v, P1, R), sp0)];
-        TL::template butterflies<R, P1 - TL::LOGP, 0>(x, tid, 0, sp0, tw, nullptr, q);
-        #pragma unroll
-        for (int v = 0; v < NTT_EPT; v++) lds[insert_bits(tid, v, P1, R)] = x[v];
-        __syncthreads();
-        #pragma unroll
-        for (int v = 0; v < NTT_EPT; v++) x[v] = lds[insert_bits(tid, v, P2, R)];
-        TL::template butterflies<R, P2 - TL::LOGP, R>(x, tid, 0, sp0, tw, nullptr, q);
-        #pragma unroll
-        for (int v = 0; v < NTT_EPT; v++) a[TL::gidx(insert_bits(tid, v, P2, R), sp0)] = finish(x[v]);
-        return;
-    }
+        const T* tw2 = nullptr;
+        if constexpr (TL::TW2)
+            tw2 = tab.tw2 + (((size_t)prime * 2 + (INV ? 1 : 0)) * gridDim.x + blockIdx.x) * (size_t)TL::TW_PASS *
+                                THREADS * 2;
 
-    const T* tw2 = nullptr;
-    if constexpr (TL::TW2)
-        tw2 = tab.tw2 + (((size_t)prime * 2 + (INV ? 1 : 0)) * gridDim.x + blockIdx.x) * (size_t)TL::TW_PASS *
-                            THREADS * 2;
-
-    if constexpr (TL::DIRECT_LO) {
-        constexpr int R = NTT_EPT_LOG;
-        constexpr int PH = TL::LOGP + R;  // groups over k's high 4 bits
-        const uint32_t gh = TL::swap_nibbles(tid);
-        T x[NTT_EPT];
-        if constexpr (!INV) {
-            #pragma unroll
-            for (int v = 0; v < NTT_EPT; v++) x[v] = a[TL::gidx(insert_bits(gh, v, PH, R), sp0)];
-            TL::template butterflies<R, R, 0>(x, gh, 0, sp0, tw, tw2, q);
-            #pragma unroll
-            for (int v = 0; v < NTT_EPT; v++) lds[TL::lpos(insert_bits(gh, v, PH, R))] = x[v];
-            __syncthreads();
-            TL::template round<R, 0, R>(lds, sp0, tw, tw2, q);
-            __syncthreads();
+        if constexpr (TL::DIRECT_LO) {
+            constexpr int R = NTT_EPT_LOG;
+            constexpr int PH = TL::LOGP + R;  // groups over k's high 4 bits
+            const uint32_t gh = TL::swap_nibbles(tid);
+            T x[NTT_EPT];
+            if constexpr (!INV) {
+                #pragma unroll
+                for (int v = 0; v < NTT_EPT; v++) x[v] = a[TL::gidx(insert_bits(gh, v, PH, R), sp0)];
+                TL::template butterflies<R, R, 0, NR>(x, gh, 0, sp0, tw, tw2, q);
+                #pragma unroll
+                for (int v = 0; v < NTT_EPT; v++) lds[TL::lpos(insert_bits(gh, v, PH, R))] = x[v];
+                __syncthreads();
+                TL::template round<R, 0, R, NR>(lds, sp0, tw, tw2, q);
+                __syncthreads();
+            } else {
+                #pragma unroll
+                for (int i = 0; i < NTT_EPT; i++) {
+                    const uint32_t f = tid + i * THREADS;
+                    const uint32_t e = ((f & ((1u << S) - 1u)) << TL::LOGP) | (f >> S);
+                    lds[TL::lpos(e)] = a[TL::gidx(e, sp0)];
+                }
+                __syncthreads();
+                TL::template round<R, 0, 0>(lds, sp0, tw, tw2, q);
+                __syncthreads();
+                #pragma unroll
+                for (int v = 0; v < NTT_EPT; v++) x[v] = lds[TL::lpos(insert_bits(gh, v, PH, R))];
+                TL::template butterflies<R, R, R>(x, gh, 0, sp0, tw, tw2, q);
+                #pragma unroll
+                for (int v = 0; v < NTT_EPT; v++) a[TL::gidx(insert_bits(gh, v, PH, R), sp0)] = finish(x[v]);
+                return;
+            }
         } else {
+            // load in global-contiguous order
             #pragma unroll
             for (int i = 0; i < NTT_EPT; i++) {
                 const uint32_t f = tid + i * THREADS;
-                const uint32_t e = ((f & ((1u << S) - 1u)) << TL::LOGP) | (f >> S);
+                uint32_t k, spl;
+                if (BLO == 0) { spl = f >> S; k = f & ((1u << S) - 1u); }
+                else { k = f >> TL::LOGP; spl = f & (TL::P - 1); }
+                const uint32_t e = (k << TL::LOGP) | spl;
                 lds[TL::lpos(e)] = a[TL::gidx(e, sp0)];
             }
             __syncthreads();
-            TL::template round<R, 0, 0>(lds, sp0, tw, tw2, q);
-            __syncthreads();
-            #pragma unroll
-            for (int v = 0; v < NTT_EPT; v++) x[v] = lds[TL::lpos(insert_bits(gh, v, PH, R))];
-            TL::template butterflies<R, R, R>(x, gh, 0, sp0, tw, tw2, q);
-            #pragma unroll
-            for (int v = 0; v < NTT_EPT; v++) a[TL::gidx(insert_bits(gh, v, PH, R), sp0)] = finish(x[v]);
-            return;
+            TL::template rounds<0, NR>(lds, sp0, tw, tw2, q);
         }
-    } else {
-        // load in global-contiguous order
+
         #pragma unroll
         for (int i = 0; i < NTT_EPT; i++) {
             const uint32_t f = tid + i * THREADS;
@@ -431,20 +455,14 @@ ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab
             if (BLO == 0) { spl = f >> S; k = f & ((1u << S) - 1u); }
             else { k = f >> TL::LOGP; spl = f & (TL::P - 1); }
             const uint32_t e = (k << TL::LOGP) | spl;
-            lds[TL::lpos(e)] = a[TL::gidx(e, sp0)];
+            a[TL::gidx(e, sp0)] = finish(lds[TL::lpos(e)]);
         }
-        __syncthreads();
-        TL::template rounds<0>(lds, sp0, tw, tw2, q);
-    }
-
-    #pragma unroll
-    for (int i = 0; i < NTT_EPT; i++) {
-        const uint32_t f = tid + i * THREADS;
-        uint32_t k, spl;
-        if (BLO == 0) { spl = f >> S; k = f & ((1u << S) - 1u); }
-        else { k = f >> TL::LOGP; spl = f & (TL::P - 1); }
-        const uint32_t e = (k << TL::LOGP) | spl;
-        a[TL::gidx(e, sp0)] = finish(lds[TL::lpos(e)]);
+    };
+    if constexpr (!INV && sizeof(T) == 8) {
+        if (q < ((T)1 << 57)) body(std::true_type{});
+        else body(std::false_type{});
+    } else {
+        body(std::false_type{});
     }
 }
 

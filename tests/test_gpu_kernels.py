@@ -43,17 +43,18 @@ def test_ntt_roundtrip_and_ring_product(ring):
     assert np.array_equal(to_host(da), a)
 
 
-@pytest.mark.parametrize("log_n", [10, 13, 14])
-def test_ntt_top_of_range_and_short_high_pass(log_n):
+@pytest.mark.parametrize("log_n,q_bits", [(10, 60), (13, 60), (14, 60), (16, 56), (13, 56)])
+def test_ntt_top_of_range_and_short_high_pass(log_n, q_bits):
     """The lazy butterflies' bounds at their limits: a 61-bit special prime (the
-    largest the 64-bit transform takes), every input q - 1, and the two-pass rings
-    whose high-bit pass has fewer than 8 stages (2^13, 2^14)."""
+    largest the 64-bit transform takes), primes just below 2^56 (the forward transform
+    without conditional subtractions, whose values reach 72q), every input q - 1 or
+    near it, and the two-pass rings whose high-bit pass has fewer than 8 stages."""
     from paper_2408_17063_amd import hc
     from oracle.ring import negacyclic_mul_limb
-    say("ntt extremes", log_n)
-    ctx = hc.Context(log_n=log_n, p=786433, L=2, q_bits=60, K=1, p_bits=61)
+    say("ntt extremes", log_n, q_bits)
+    ctx = hc.Context(log_n=log_n, p=786433, L=2, q_bits=q_bits, K=1, p_bits=61)
     n, nq = ctx.n, ctx.nq
-    assert max(ctx.primes) >> 60 == 1
+    assert max(ctx.primes) >> 60 == 1 and min(ctx.primes) >> (q_bits - 1) == 1
     r = np.random.default_rng(log_n)
     a = np.stack([np.full(n, q - 1, dtype=np.uint64) for q in ctx.primes])
     b = np.stack([r.integers(q - 4096, q, n, dtype=np.uint64) for q in ctx.primes])
