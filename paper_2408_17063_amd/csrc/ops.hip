@@ -438,42 +438,49 @@ __global__ void ms_conv_kernel(uint64_t* __restrict__ conv, const uint64_t* __re
                                const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv,
                                const uint64_t* __restrict__ inv, const uint64_t* __restrict__ cst,
                                int n, int L, int Lc, int i0) {
-    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    // two adjacent coefficients per thread: each row is read in 16-byte pieces
+    const int x = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
     if (x >= n) return;
     const int tc = blockIdx.z, nd = L - Lc;
     const uint64_t* cc = ct + (size_t)tc * L * n;
-    u128p acc[NI];
-    uint64_t sum[NI];
+    u128p acc[NI][2];
+    uint64_t sum[NI][2];
     #pragma unroll
-    for (int u = 0; u < NI; u++) sum[u] = 0;
+    for (int u = 0; u < NI; u++) sum[u][0] = sum[u][1] = 0;
     // the dropped residues in batches of 8 whose loads issue together; each batch's
     // 128-bit sums (8 products below 2^60 q_i) are reduced before the next
     constexpr int MS_BATCH = 8;
     for (int j0 = 0; j0 < nd; j0 += MS_BATCH) {
-        uint64_t v[MS_BATCH];
+        ulonglong2 v[MS_BATCH];
         #pragma unroll
         for (int b = 0; b < MS_BATCH; b++)
-            if (j0 + b < nd) v[b] = cc[(size_t)(Lc + j0 + b) * n + x];
+            if (j0 + b < nd) v[b] = *reinterpret_cast<const ulonglong2*>(cc + (size_t)(Lc + j0 + b) * n + x);
         #pragma unroll
-        for (int u = 0; u < NI; u++) acc[u] = u128p{0, 0};
+        for (int u = 0; u < NI; u++) acc[u][0] = acc[u][1] = u128p{0, 0};
         #pragma unroll
         for (int b = 0; b < MS_BATCH; b++) {
             const int j = j0 + b;
             if (j < nd) {
-                const uint64_t y = shoup(v[b], inv[2 * j], inv[2 * j + 1], mods[Lc + j]);
+                const uint64_t qj = mods[Lc + j], w = inv[2 * j], wp = inv[2 * j + 1];
+                const uint64_t y0 = shoup(v[b].x, w, wp, qj), y1 = shoup(v[b].y, w, wp, qj);
                 const uint64_t* cj = cst + (size_t)j * Lc + i0;
                 #pragma unroll
-                for (int u = 0; u < NI; u++) add128(acc[u], mul128(y, cj[u]));
+                for (int u = 0; u < NI; u++) {
+                    add128(acc[u][0], mul128(y0, cj[u]));
+                    add128(acc[u][1], mul128(y1, cj[u]));
+                }
             }
         }
         #pragma unroll
         for (int u = 0; u < NI; u++) {
-            const uint64_t q = mods[i0 + u];
-            sum[u] = add_mod(sum[u], redc(acc[u], q, qinv[i0 + u]), q);
+            const uint64_t q = mods[i0 + u], qi = qinv[i0 + u];
+            sum[u][0] = add_mod(sum[u][0], redc(acc[u][0], q, qi), q);
+            sum[u][1] = add_mod(sum[u][1], redc(acc[u][1], q, qi), q);
         }
     }
     #pragma unroll
-    for (int u = 0; u < NI; u++) conv[((size_t)tc * Lc + i0 + u) * n + x] = sum[u];
+    for (int u = 0; u < NI; u++)
+        *reinterpret_cast<ulonglong2*>(conv + ((size_t)tc * Lc + i0 + u) * n + x) = ulonglong2{sum[u][0], sum[u][1]};
 }
 
 // out[t][c][i] = (ct[t][c][i] - conv[t][c][i]) D^-1 mod q_i (NTT domain), out at level Lc
@@ -510,7 +517,7 @@ void k_ms_conv(const Ctx& c, uint64_t* conv, const uint64_t* ct, const uint64_t*
     for (int i0 = 0; i0 < Lc; i0 += CONV_ROWS)
         with_rows(std::min(CONV_ROWS, Lc - i0), [&](auto ni_c) {
             constexpr int NI = decltype(ni_c)::value;
-            hipLaunchKernelGGL((ms_conv_kernel<NI>), ew_grid(c.n, 1, 2 * count), dim3(EW_THREADS), 0, st, conv, ct,
+            hipLaunchKernelGGL((ms_conv_kernel<NI>), ew_grid(c.n / 2, 1, 2 * count), dim3(EW_THREADS), 0, st, conv, ct,
                                c.d_mods, c.d_qinv, inv, cst, c.n, c.L, Lc, i0);
         });
 }
