@@ -399,11 +399,16 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
                 for (uint32_t b = 0; b < B; b++) hptr[(ci * kb + beta) * B + b] = q.R[pp][beta][b];
             for (uint32_t gi = 0; gi < G; gi++) hptr[np * kb * B + ci * G + gi] = q.A[pp][gi];
         }
-        // the rotated-ciphertext and giant-accumulator pointer tables, one copy
-        const uint64_t* const* rptr =
-            (const uint64_t* const*)stage_bytes(l, hptr.data(), sizeof(uint64_t*) * hptr.size(), st);
-        if (!rptr) return HC_ENOMEM;
-        k_diag_gather(c, Rt, rptr, (int)np, (int)(kb * B), Lc, st);
+        // the rotated-ciphertext and giant-accumulator pointer tables and the list of
+        // entries the gather writes, one copy
+        const std::vector<uint32_t> work = diag_gather_list(hptr, (int)np, (int)(kb * B));
+        void *drp = nullptr, *dwk = nullptr;
+        if (!stage_many(l, {{hptr.data(), sizeof(uint64_t*) * hptr.size(), &drp},
+                            {work.data(), sizeof(uint32_t) * work.size(), &dwk}},
+                        st))
+            return HC_ENOMEM;
+        const uint64_t* const* rptr = (const uint64_t* const*)drp;
+        k_diag_gather(c, Rt, rptr, (const uint32_t*)dwk, (int)work.size(), (int)np, (int)(kb * B), Lc, st);
         if (const Ctx::DiagTab* tab = cls_res[kv.first]) {
             // resident diagonals: one pass over every giant index
             uint64_t** aptr = (uint64_t**)(rptr + np * kb * B);

@@ -220,7 +220,7 @@ extern "C" hc_status hc_context_create(const hc_params* prm, int device, hc_cont
 
     // ---- NTT tables for every prime
     c.h_tw.assign((size_t)nq * 4 * n, 0);
-    std::vector<uint64_t> ninv(2 * nq), qinv(nq), r2(nq);
+    std::vector<uint64_t> ninv(4 * nq), qinv(nq), r2(nq);
     for (int i = 0; i < nq; i++) {
         uint64_t q = c.primes[i];
         uint64_t psi = root_2n(q, n), psii = h_invmod(psi, q);
@@ -239,8 +239,11 @@ extern "C" hc_status hc_context_create(const hc_params* prm, int device, hc_cont
             t[2 * n + 2 * k] = pwi[e];
             t[2 * n + 2 * k + 1] = h_shoup_const(pwi[e], q);
         }
-        ninv[2 * i] = h_invmod(n % q, q);
-        ninv[2 * i + 1] = h_shoup_const(ninv[2 * i], q);
+        // n^-1 and, for the inverse transform's last stage, its one twiddle times n^-1
+        ninv[4 * i] = h_invmod(n % q, q);
+        ninv[4 * i + 1] = h_shoup_const(ninv[4 * i], q);
+        ninv[4 * i + 2] = h_mulmod(t[2 * n + 2], ninv[4 * i], q);
+        ninv[4 * i + 3] = h_shoup_const(ninv[4 * i + 2], q);
         qinv[i] = h_mont_qinv(q);
         r2[i] = h_mulmod(h_to_mont(1, q), h_to_mont(1, q), q);  // 2^128 mod q
     }
@@ -269,7 +272,9 @@ extern "C" hc_status hc_context_create(const hc_params* prm, int device, hc_cont
         c.h_twp[2 * n + 2 * k + 1] = (uint32_t)(((uint64_t)wi << 32) / p);
     }
     uint32_t ninvp = (uint32_t)h_invmod(n % p, p);
-    std::vector<uint32_t> ninvp_v = {ninvp, (uint32_t)(((uint64_t)ninvp << 32) / p)};
+    const uint32_t w1ninv = (uint32_t)(((uint64_t)c.h_twp[2 * n + 2] * ninvp) % p);
+    std::vector<uint32_t> ninvp_v = {ninvp, (uint32_t)(((uint64_t)ninvp << 32) / p), w1ninv,
+                                     (uint32_t)(((uint64_t)w1ninv << 32) / p)};
     // slot (r, c) <-> evaluation at zeta^e, e = (-1)^r 3^c mod 2n; forward NTT entry i
     // holds the evaluation at zeta^(2 brv(i) + 1)
     c.h_slotpos.assign(n, 0);

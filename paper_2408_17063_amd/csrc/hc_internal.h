@@ -76,10 +76,10 @@ struct hc_context {
     uint64_t* d_r2 = nullptr;       // [nq] 2^128 mod q
     uint64_t* d_tw = nullptr;       // [nq][2][n][2]: (w, w') forward then inverse
     uint64_t* d_tw2 = nullptr;      // low-bit NTT pass twiddles in thread order (rings above 2^12)
-    uint64_t* d_ninv = nullptr;     // [nq][2]
+    uint64_t* d_ninv = nullptr;     // [nq][4]: n^-1, Shoup; W^-1[1] n^-1, Shoup
     uint32_t* d_modp = nullptr;     // [1] p
     uint32_t* d_twp = nullptr;      // [2][n][2] mod p
-    uint32_t* d_ninvp = nullptr;    // [2]
+    uint32_t* d_ninvp = nullptr;    // [4]: as d_ninv, mod p
     uint32_t* d_slotpos = nullptr;  // [n]
     uint32_t* d_posslot = nullptr;  // [n] inverse of slotpos
     uint64_t* d_modup_inv = nullptr;  // [dnum][alpha][2]  (D_j/q_i)^-1 mod q_i and Shoup
@@ -303,10 +303,13 @@ inline int diag_terms_padded(int J) {
     return (J + DIAG_NS * DIAG_T - 1) / (DIAG_NS * DIAG_T) * (DIAG_NS * DIAG_T);
 }
 // Rt[r][tile][pp][j][64][2] (split) from the pointer table R[pp][j] (j < J; nullptr and
-// J <= j < diag_terms_padded(J): zeros; kRtInPlace: already written there, skipped)
+// J <= j < diag_terms_padded(J): zeros; kRtInPlace: already written there). Only the
+// entries pp * diag_terms_padded(J) + j listed in work[0..nwork) are written; the
+// list holds every entry that is not kRtInPlace (diag_gather_list builds it).
 static const uint64_t* const kRtInPlace = reinterpret_cast<const uint64_t*>(uintptr_t(1));
-void k_diag_gather(const Ctx& c, uint64_t* Rt, const uint64_t* const* R, int npairs, int J, int Lc,
-                   hipStream_t st);
+std::vector<uint32_t> diag_gather_list(const std::vector<const uint64_t*>& R, int npairs, int J);
+void k_diag_gather(const Ctx& c, uint64_t* Rt, const uint64_t* const* R, const uint32_t* work, int nwork, int npairs,
+                   int J, int Lc, hipStream_t st);
 // A[pp][g] (=|+=) sum_{j<J} D(j, g) R[pp][j], g < ga, for npairs pairs: A pointers
 // [npairs][ga], R gathered by k_diag_gather, D split and in Montgomery form.
 // HC_EINVAL if one term's diagonal words for DIAG_GC giants span 2^31 bytes or more

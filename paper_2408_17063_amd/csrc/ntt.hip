@@ -6,7 +6,8 @@
 // W[k] = psi^brv(k). Output entry i = a(psi^(2 brv(i) + 1)).
 // Inverse (Gentleman-Sande): stage u = 0..logn-1 pairs j with j + 2^u,
 // twiddle Winv[n/2^(u+1) + (j >> (u+1))], Winv[k] = psi^-brv(k), then a
-// final multiplication by n^-1.
+// final multiplication by n^-1 (folded into the last stage, whose one twiddle is
+// Winv[1]).
 //
 // A launch runs S consecutive stages on tiles of 4096 elements (the whole
 // ring below 2^12) held in LDS. The stages touch the index bits [BLO, BLO+S);
@@ -38,14 +39,11 @@
 // in [0, 4q). For primes below 2^57 (a block checks its row's prime) the forward
 // transform makes no conditional subtractions at all: a stage adds at most 4q to
 // the bound, so 16 stages from below 8q stay below 72q < 2^64, and the last launch
-// reduces with one truncated product by 1. The last launch reduces to [0, q) (and
-// scales by n^-1).
+// reduces with one truncated product by 1. The last launch brings every value to
+// [0, q).
 #include "hc_internal.h"
 
 namespace hc {
-
-template <typename T>
-__device__ __forceinline__ T csubT(T x, T q) { return x >= q ? x - q : x; }
 
 // x - r if x >= r else x, for 64-bit x < 2^63 + r and r < 2^63, given nr = 2^64 - r:
 // the sign of x - r picks the result through a bit mask, which keeps the carry flag
@@ -63,17 +61,10 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
            __builtin_amdgcn_readfirstlane((uint32_t)v);
 }
 
-__device__ __forceinline__ uint64_t uniformT(uint64_t v) { return uniform64(v); }
-__device__ __forceinline__ uint32_t uniformT(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-
 template <typename T> struct Ar;
 
 template <> struct Ar<uint64_t> {
-    typedef ulonglong2 Pair;
     static constexpr int LAZY = 2;  // butterfly values are reduced below 4q (forward: 8q)
-    static __device__ __forceinline__ uint64_t shoup_lazy(uint64_t x, uint64_t w, uint64_t wp, uint64_t q) {
-        return x * w - __umul64hi(x, wp) * q;
-    }
     // x*w - qt*q with qt = xh*wh' + hi(xh*wl') + hi(xl*wh') for w' = wh'*2^32 + wl':
     // x*w'/2^64 exceeds qt by the dropped low words, less than 3, so qt is at most 2
     // below the exact Shoup quotient and the result lies in [0, 4q) for any 64-bit
@@ -114,10 +105,10 @@ template <> struct Ar<uint32_t> {
 
 
 // Tables for one prime: [2 directions][n][2] = (w, w') pairs, forward then
-// inverse; plus n^-1 and its Shoup constant.
+// inverse; plus n^-1 and Winv[1] n^-1 with their Shoup constants.
 template <typename T> struct NttTab {
     const T* base;  // [nprime][2][n][2]
-    const T* ninv;  // [nprime][2]
+    const T* ninv;  // [nprime][4]: n^-1 and its Shoup constant, W^-1[1] n^-1 and its Shoup constant
     const T* mods;  // [nprime]
     const T* tw2;   // low-bit pass twiddles in thread order (rings above one tile), or nullptr
 };
@@ -212,9 +203,12 @@ struct Tile {
     // NR (forward, 64-bit primes below 2^57): no conditional subtraction; a forward
     // stage then adds at most 4q to the bound, and 16 stages from below 8q stay below
     // 72q < 2^64.
-    template <int R, int KBIT, int DONE, bool NR = false>
+    // FOLD (the inverse transform's last launch): the last stage, whose one twiddle is
+    // W^-1[1], also scales by n^-1: its sums are multiplied by n^-1 and its differences
+    // by W^-1[1] n^-1 (ni: the prime's [4] entry of the n^-1 table).
+    template <int R, int KBIT, int DONE, bool NR = false, bool FOLD = false>
     static __device__ __forceinline__ void butterflies(T (&x)[1 << R], uint32_t g, int sub, uint32_t sp0, const T* tw,
-                                                       const T* tw2, T q) {
+                                                       const T* tw2, T q, const T* ni = nullptr) {
         constexpr int POS = LOGP + KBIT;
         constexpr int GS = 1 << R;
         const uint32_t j0 = gidx(insert_bits(g, 0, POS, R), sp0);
@@ -227,8 +221,10 @@ struct Tile {
             nrq = uniform64(nrq);
             asm("" : "+s"(nq), "+s"(nrq));
         }
+        // this round holds the transform's last stage (u = R - 1)
+        constexpr bool FOLD_HERE = FOLD && INV && ST0 + DONE + R == LOGN;
         #pragma unroll
-        for (int u = 0; u < R; u++) {
+        for (int u = 0; u < (FOLD_HERE ? R - 1 : R); u++) {
             const int st = ST0 + DONE + u;
             // stage u's twiddles: 2^u (forward) or 2^(R-1-u) (inverse) pairs from base on
             const int cnt = INV ? (1 << (R - 1 - u)) : (1 << u);
@@ -271,11 +267,22 @@ struct Tile {
                 }
             }
         }
+        if constexpr (FOLD_HERE) {
+            constexpr int half = 1 << (R - 1);
+            const T n0 = ni[0], n1 = ni[1], m0 = ni[2], m1 = ni[3];
+            #pragma unroll
+            for (int v = 0; v < half; v++) {
+                const T X = x[v], Y = x[v | half];
+                x[v] = Ar<T>::mul(X + Y, n0, n1, q, nq);
+                x[v | half] = Ar<T>::mul(X + rq - Y, m0, m1, q, nq);
+            }
+        }
     }
 
     // one round of R stages on the tile in LDS
-    template <int R, int KBIT, int DONE, bool NR = false>
-    static __device__ __forceinline__ void round(T* lds, uint32_t sp0, const T* tw, const T* tw2, T q) {
+    template <int R, int KBIT, int DONE, bool NR = false, bool FOLD = false>
+    static __device__ __forceinline__ void round(T* lds, uint32_t sp0, const T* tw, const T* tw2, T q,
+                                                 const T* ni = nullptr) {
         constexpr int POS = LOGP + KBIT;
         constexpr int GS = 1 << R;
         constexpr int PER = NTT_EPT >> R;  // groups per thread
@@ -290,21 +297,22 @@ struct Tile {
             T x[GS];
             #pragma unroll
             for (int v = 0; v < GS; v++) x[v] = lds[lb + v * VSTEP];
-            butterflies<R, KBIT, DONE, NR>(x, g, sub, sp0, tw, tw2, q);
+            butterflies<R, KBIT, DONE, NR, FOLD>(x, g, sub, sp0, tw, tw2, q, ni);
             #pragma unroll
             for (int v = 0; v < GS; v++) lds[lb + v * VSTEP] = x[v];
         }
     }
 
     // rounds: forward processes k bits from the top down, inverse from the bottom up
-    template <int DONE, bool NR = false>
-    static __device__ __forceinline__ void rounds(T* lds, uint32_t sp0, const T* tw, const T* tw2, T q) {
+    template <int DONE, bool NR = false, bool FOLD = false>
+    static __device__ __forceinline__ void rounds(T* lds, uint32_t sp0, const T* tw, const T* tw2, T q,
+                                                  const T* ni = nullptr) {
         if constexpr (DONE < S) {
             constexpr int R = round_r(DONE);
             constexpr int KBIT = INV ? DONE : (S - DONE - R);
-            round<R, KBIT, DONE, NR>(lds, sp0, tw, tw2, q);
+            round<R, KBIT, DONE, NR, FOLD>(lds, sp0, tw, tw2, q, ni);
             __syncthreads();
-            rounds<DONE + R, NR>(lds, sp0, tw, tw2, q);
+            rounds<DONE + R, NR, FOLD>(lds, sp0, tw, tw2, q, ni);
         }
     }
 
@@ -354,7 +362,8 @@ ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab
     const T* tw = tab.base + ((size_t)prime * 2 + (INV ? 1 : 0)) * 2 * TL::N;
     T* a = data + (size_t)blockIdx.y * poly_stride + (size_t)row * TL::N;
     const uint32_t sp0 = blockIdx.x * TL::P;
-    const T* ni = tab.ninv + 2 * prime;
+    const T* ni = tab.ninv + 4 * prime;
+    constexpr bool FOLD = INV && LAST;
     // NR: forward transform of a 64-bit prime below 2^57 without conditional subtractions
     auto body = [&](auto nr_c) __attribute__((always_inline)) {
         constexpr bool NR = decltype(nr_c)::value;
@@ -369,8 +378,9 @@ ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab
                     nq4 = uniform64(nq4);
                     asm("" : "+s"(nq1), "+s"(nq2), "+s"(nq4));
                 }
-                if constexpr (INV) v = Ar<T>::mul(v, ni[0], ni[1], q, nq1);  // [0, 4q) (64-bit), [0, 2q)
-                else if constexpr (NR) v = Ar<T>::mul(v, tw[0], tw[1], q, nq1);  // entry 0 is (1, 2^64 / q): [0, 4q)
+                if constexpr (INV) {
+                    // scaled by n^-1 in the last stage: [0, 4q) (64-bit), [0, 2q)
+                } else if constexpr (NR) v = Ar<T>::mul(v, tw[0], tw[1], q, nq1);  // entry 0 is (1, 2^64 / q): [0, 4q)
                 else if constexpr (Ar<T>::LAZY == 2) v = Ar<T>::red(v, q << 2, nq4);
                 if constexpr (Ar<T>::LAZY == 2 || !INV) v = Ar<T>::red(v, q << 1, nq2);
                 v = Ar<T>::red(v, q, nq1);
@@ -391,7 +401,7 @@ ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab
             __syncthreads();
             #pragma unroll
             for (int v = 0; v < NTT_EPT; v++) x[v] = lds[insert_bits(tid, v, P2, R)];
-            TL::template butterflies<R, P2 - TL::LOGP, R, NR>(x, tid, 0, sp0, tw, nullptr, q);
+            TL::template butterflies<R, P2 - TL::LOGP, R, NR, FOLD>(x, tid, 0, sp0, tw, nullptr, q, ni);
             #pragma unroll
             for (int v = 0; v < NTT_EPT; v++) a[TL::gidx(insert_bits(tid, v, P2, R), sp0)] = finish(x[v]);
             return;
@@ -445,7 +455,7 @@ ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab
                 lds[TL::lpos(e)] = a[TL::gidx(e, sp0)];
             }
             __syncthreads();
-            TL::template rounds<0, NR>(lds, sp0, tw, tw2, q);
+            TL::template rounds<0, NR, FOLD>(lds, sp0, tw, tw2, q, ni);
         }
 
         #pragma unroll

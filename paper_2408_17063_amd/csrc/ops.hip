@@ -841,12 +841,13 @@ struct DiagMacArgs {
 // Rt[r][tile][pp][j][lane][k] = R[pp][j] component k at (r, 64 tile + lane), split, for
 // j < Jp (J rounded up by diag_terms_padded); nullptr and j >= J -> 0; entries equal to
 // kRtInPlace were written into Rt by their producer and are left alone.
-__global__ void diag_gather_kernel(uint64_t* __restrict__ Rt, const uint64_t* const* __restrict__ R, int n,
-                                   int L, int J, int Jp, int npairs, int pj0, int h) {
+__global__ void diag_gather_kernel(uint64_t* __restrict__ Rt, const uint64_t* const* __restrict__ R,
+                                   const uint32_t* __restrict__ work, int n, int L, int J, int Jp, int npairs,
+                                   int w0, int h) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     const int r = blockIdx.y;
-    const int pj = pj0 + (int)blockIdx.z;  // pp * Jp + j
+    const int pj = (int)work[w0 + (int)blockIdx.z];  // pp * Jp + j
     const int pp = pj / Jp, j = pj - pp * Jp;
     const uint64_t* rp = j < J ? R[(size_t)pp * J + j] : nullptr;
     if (rp == kRtInPlace) return;
@@ -1108,14 +1109,22 @@ void k_diag_split(const Ctx& c, uint64_t* d, size_t words, int Lc, hipStream_t s
     hipLaunchKernelGGL(diag_split_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d, words, diag_split_h(c, Lc));
 }
 
-void k_diag_gather(const Ctx& c, uint64_t* Rt, const uint64_t* const* R, int npairs, int J, int Lc,
-                   hipStream_t st) {
+std::vector<uint32_t> diag_gather_list(const std::vector<const uint64_t*>& R, int npairs, int J) {
     const int Jp = diag_terms_padded(J);
-    const int total = npairs * Jp;
+    std::vector<uint32_t> w;
+    for (int pp = 0; pp < npairs; pp++)
+        for (int j = 0; j < Jp; j++)
+            if (j >= J || R[(size_t)pp * J + j] != kRtInPlace) w.push_back((uint32_t)(pp * Jp + j));
+    return w;
+}
+
+void k_diag_gather(const Ctx& c, uint64_t* Rt, const uint64_t* const* R, const uint32_t* work, int nwork, int npairs,
+                   int J, int Lc, hipStream_t st) {
+    const int Jp = diag_terms_padded(J);
     const int h = diag_split_h(c, Lc);
-    for (int pj0 = 0; pj0 < total; pj0 += 65535)
-        hipLaunchKernelGGL(diag_gather_kernel, ew_grid(c.n, Lc, std::min(65535, total - pj0)), dim3(EW_THREADS), 0,
-                           st, Rt, R, c.n, Lc, J, Jp, npairs, pj0, h);
+    for (int w0 = 0; w0 < nwork; w0 += 65535)
+        hipLaunchKernelGGL(diag_gather_kernel, ew_grid(c.n, Lc, std::min(65535, nwork - w0)), dim3(EW_THREADS), 0,
+                           st, Rt, R, work, c.n, Lc, J, Jp, npairs, w0, h);
 }
 
 hc_status k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* Rt, const uint64_t* D,
