@@ -273,9 +273,11 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
         }
         RUN(ew_run(c, l, mj, c.L, true, st));
     }
-    // 2. switch to the Comp level (Sec. 5.3's smaller parameters, as a modulus switch)
+    // 2. switch to the Comp level (Sec. 5.3's smaller parameters, as a modulus switch);
+    // the input ciphertexts' dropped rows are read from the query (coefficient form)
     if (Lc < c.L)
-        for (auto& q : qs) RUN(mod_switch_batch(c, q.cts, q.ctf, (int)q.ntot, Lc, q.msconv, st));
+        for (auto& q : qs)
+            RUN(mod_switch_batch(c, q.cts, q.ctf, (int)q.ntot, Lc, q.msconv, st, q.ct_v, (int)q.pl.n_ct));
 
     // 3. u-blocks (Sec. 5.2 remark): row 0: A*[1;0] + Rot_col(B*[1;0]); row 1: Rot_col(A*[0;1]) + B*[0;1]
     {

@@ -357,13 +357,18 @@ static hc_status ms_tables(Ctx& c, int Lc, const Ctx::MsTab** out) {
 // in and out). The dropped rows of `in` are left in the coefficient domain. conv: 2 Lc n
 // words per ciphertext.
 hc_status mod_switch_batch(Ctx& c, uint64_t* out, uint64_t* in, int count, int Lc, uint64_t* conv,
-                           hipStream_t st) {
+                           hipStream_t st, const uint64_t* coef, int ncoef) {
     const Ctx::MsTab* t = nullptr;
     hc_status s = ms_tables(c, Lc, &t);
     if (s != HC_OK) return s;
-    const size_t n = c.n, Ln = (size_t)c.L * n;
-    ntt64(c, in + (size_t)Lc * n, Ln, 2 * count, Lc, c.L - Lc, true, st);
-    k_ms_conv(c, conv, in, t->inv, t->cst, Lc, count, st);
+    if (!coef || ncoef < 0) ncoef = 0;
+    if (ncoef > count) return HC_EINVAL;
+    const size_t n = c.n, Ln = (size_t)c.L * n, skip = 2 * (size_t)ncoef;
+    // the dropped rows in coefficient form: given for the first ncoef, transformed back
+    // for the rest
+    ntt64(c, in + skip * Ln + (size_t)Lc * n, Ln, 2 * (count - ncoef), Lc, c.L - Lc, true, st);
+    if (ncoef > 0) k_ms_conv(c, conv, coef, t->inv, t->cst, Lc, ncoef, st);
+    k_ms_conv(c, conv + skip * Lc * n, in + skip * Ln, t->inv, t->cst, Lc, count - ncoef, st);
     ntt64(c, conv, (size_t)Lc * n, 2 * count, 0, Lc, false, st);
     k_ms_final(c, out, in, conv, t->dinv, Lc, count, st);
     return HC_OK;

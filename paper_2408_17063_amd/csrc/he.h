@@ -39,9 +39,11 @@ hc_status ks_run_sum(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jo
                      const std::vector<uint32_t>& group, const std::vector<uint64_t*>& outs, uint64_t* TA,
                      uint64_t* C0A, int Lc, hipStream_t st);
 hc_status ew_run(Ctx& c, Lane& l, const std::vector<EwJob>& jobs, int Lc, bool mul, hipStream_t st);
-// drop the primes Lc..L-1 of `count` contiguous top-level ciphertexts (NTT domain)
+// drop the primes Lc..L-1 of `count` contiguous top-level ciphertexts (NTT domain). The
+// first ncoef of them may also be given in coefficient form (coef, same layout): their
+// dropped rows are then read from there instead of being transformed back.
 hc_status mod_switch_batch(Ctx& c, uint64_t* out, uint64_t* in, int count, int Lc, uint64_t* conv,
-                           hipStream_t st);
+                           hipStream_t st, const uint64_t* coef = nullptr, int ncoef = 0);
 const uint64_t* find_key(const hc_gk* gk, uint32_t k);
 
 }  // namespace hc

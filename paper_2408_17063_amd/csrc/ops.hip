@@ -512,6 +512,7 @@ static void with_rows(int v, F&& f) {
 
 void k_ms_conv(const Ctx& c, uint64_t* conv, const uint64_t* ct, const uint64_t* inv, const uint64_t* cst,
                int Lc, int count, hipStream_t st) {
+    if (count <= 0) return;
     // the kept primes in chunks of up to CONV_ROWS per thread (primes below 2^60, so a
     // batch of 8 products stays below q 2^64)
     for (int i0 = 0; i0 < Lc; i0 += CONV_ROWS)
