@@ -262,16 +262,22 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
 
     // 1. inputs to the NTT domain; Mask at the top level (Alg. 7 step 2)
     {
-        std::vector<EwJob> mj;
+        // ciphertext i times every column's plaintext i, into slot (1 + col) n_ct + i
+        std::vector<MaskJob> mj;
         for (auto& q : qs) {
             HC_CHECK(hipMemcpyAsync(q.ctf, q.ct_v, sizeof(uint64_t) * q.CWF * q.pl.n_ct, hipMemcpyDeviceToDevice, st));
             ntt64(c, q.ctf, (size_t)c.L * n, 2 * (int)q.pl.n_ct, 0, c.L, false, st);
-            for (uint32_t col = 0; col < q.pl.ncol; col++)
+            if (q.pl.ncol > 0)
                 for (uint32_t i = 0; i < q.pl.n_ct; i++)
-                    mj.push_back(EwJob{q.ctf + ((size_t)(1 + col) * q.pl.n_ct + i) * q.CWF, q.ctf + i * q.CWF,
-                                       db->d_pt + ((size_t)col * db->n_ct + i) * c.L * n});
+                    mj.push_back(MaskJob{q.ctf + i * q.CWF, q.ctf + ((size_t)q.pl.n_ct + i) * q.CWF,
+                                         db->d_pt + (size_t)i * c.L * n, (uint64_t)q.pl.n_ct * q.CWF,
+                                         (uint64_t)db->n_ct * c.L * n, q.pl.ncol, 0u});
         }
-        RUN(ew_run(c, l, mj, c.L, true, st));
+        if (!mj.empty()) {
+            const MaskJob* dm = (const MaskJob*)stage_bytes(l, mj.data(), sizeof(MaskJob) * mj.size(), st);
+            if (!dm) return HC_ENOMEM;
+            k_mask_jobs(c, dm, (int)mj.size(), c.L, st);
+        }
     }
     // 2. switch to the Comp level (Sec. 5.3's smaller parameters, as a modulus switch);
     // the input ciphertexts' dropped rows are read from the query (coefficient form)

@@ -171,6 +171,16 @@ struct EwJob {
     const uint64_t* b;
 };
 
+// Products of one ciphertext a ([2][L][n]) with ncol plaintexts ([L][n] each, Montgomery
+// form): out + c out_step = a * (b + c b_step), c < ncol.
+struct MaskJob {
+    const uint64_t* a;
+    uint64_t* out;
+    const uint64_t* b;
+    uint64_t out_step, b_step;
+    uint32_t ncol, pad;
+};
+
 // Brackets one kernel launch with events when timing is enabled.
 struct TimeScope {
     const hc_context& c;
@@ -226,6 +236,9 @@ void kb_final(const Ctx& c, const KsJob* jobs, const uint64_t* T, const uint64_t
 void k_sum_cts(const Ctx& c, uint64_t* y, const uint64_t* src, int groups, int cnt, int Lc, hipStream_t st);
 // element-wise jobs at level Lc: out = a * b (b a Montgomery plaintext [Lc rows]) or out = a + b
 void k_ew_jobs(const Ctx& c, const EwJob* jobs, int M, int Lc, bool mul, hipStream_t st);
+// MaskJob products at L rows: a thread reads its coefficient of both components once
+// and each plaintext once
+void k_mask_jobs(const Ctx& c, const MaskJob* jobs, int M, int L, hipStream_t st);
 // modulus switching of `count` contiguous ciphertexts from L to Lc primes:
 // conv [count][2][Lc][n] from the dropped rows of ct [count][2][L][n] (coefficient domain);
 // out [count][2][Lc][n] = (ct - conv) D^-1 (NTT domain)

@@ -542,6 +542,30 @@ __global__ void ew_jobs_kernel(const EwJob* __restrict__ jobs, const uint64_t* _
     else jb.out[o] = add_mod(jb.a[o], jb.b[o], q);
 }
 
+__global__ void mask_jobs_kernel(const MaskJob* __restrict__ jobs, const uint64_t* __restrict__ mods,
+                                 const uint64_t* __restrict__ qinv, int n, int L) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const MaskJob jb = jobs[blockIdx.z];
+    const int row = blockIdx.y;
+    const uint64_t q = mods[row], qi = qinv[row];
+    const size_t o0 = (size_t)row * n + x, o1 = ((size_t)L + row) * n + x;
+    const uint64_t a0 = jb.a[o0], a1 = jb.a[o1];
+    #pragma unroll 4
+    for (uint32_t col = 0; col < jb.ncol; col++) {
+        const uint64_t p = jb.b[col * jb.b_step + o0];
+        uint64_t* out = jb.out + col * jb.out_step;
+        out[o0] = mont_mul(a0, p, q, qi);
+        out[o1] = mont_mul(a1, p, q, qi);
+    }
+}
+
+void k_mask_jobs(const Ctx& c, const MaskJob* jobs, int M, int L, hipStream_t st) {
+    if (M <= 0) return;
+    hipLaunchKernelGGL(mask_jobs_kernel, ew_grid(c.n, L, M), dim3(EW_THREADS), 0, st, jobs, c.d_mods, c.d_qinv, c.n,
+                       L);
+}
+
 void k_ew_jobs(const Ctx& c, const EwJob* jobs, int M, int Lc, bool mul, hipStream_t st) {
     if (M <= 0) return;
     hipLaunchKernelGGL(ew_jobs_kernel, ew_grid(c.n, 2 * Lc, M), dim3(EW_THREADS), 0, st, jobs, c.d_mods,
