@@ -59,12 +59,16 @@ typedef enum {
 
 typedef struct {
     uint32_t log_n;   /* ring degree n = 2^log_n, 10 <= log_n <= 16 */
-    uint64_t p;       /* plaintext prime, p = 1 mod 2n, p < 2^30 */
+    uint64_t p;       /* plaintext prime, p = 1 mod 2n, p < 2^26 */
     uint32_t L;       /* ciphertext primes */
     uint32_t q_bits;  /* bit size bound of the ciphertext primes, 30..60 */
-    uint32_t K;       /* special primes (= primes per key-switching digit); L % K == 0 */
+    uint32_t K;       /* special primes (= primes per key-switching digit), 1..4; L % K == 0 */
     uint32_t p_bits;  /* bit size bound of the special primes, <= 61 */
 } hc_params;
+/* The key inner product sums the dnum = L / K digit products of a row in one
+ * 128-bit accumulator before a single Montgomery reduction, so every prime q of
+ * the basis must satisfy dnum * q < 2^64 (at most 15 digits of 60-bit primes, 7
+ * of 61-bit ones); hc_context_create rejects parameters that break it. */
 
 typedef struct hc_context hc_context;
 typedef struct hc_sk hc_sk;
@@ -82,15 +86,17 @@ typedef struct {
     uint32_t n_keyswitch;  /* key switches performed */
     uint64_t n_ptct;       /* plaintext-ciphertext products performed */
     uint64_t n_diag;       /* diagonal plaintexts encoded during the call */
-    uint32_t level;        /* ciphertext primes of the output (the Comp level) */
+    uint32_t level;        /* ciphertext primes of the output (out_level, else the Comp level) */
     uint64_t n_diag_resident; /* diagonal plaintexts read from resident tables (hc_diag_prepare) */
+    uint32_t comp_level;   /* ciphertext primes Comp ran at */
 } hc_compress_info;
 
 /* ------------------------------------------------------------------ context */
 
 /* Derive primes and tables for `params` on HIP device `device` and upload
  * them. Errors: HC_EINVAL (n not a power of two in range, p not prime or
- * p != 1 mod 2n, L % K != 0, not enough primes), HC_EDEVICE, HC_ENOMEM. */
+ * p != 1 mod 2n, L % K != 0, not enough primes, dnum * q >= 2^64 for a prime q),
+ * HC_EDEVICE, HC_ENOMEM. */
 hc_status hc_context_create(const hc_params* params, int device, hc_context** out);
 void hc_context_destroy(hc_context* ctx);
 
@@ -121,12 +127,12 @@ void hc_gk_destroy(hc_gk* gk);
 
 /* The Galois elements a compression of N records, ncol value columns and
  * sparsity bound t_bound needs (the schedule's key set, ascending), and the
- * plan's counts. comp_level as in hc_compress.
+ * plan's counts. comp_level and out_level as in hc_compress.
  * *count is the capacity of elements_out on entry and the number written on
  * exit. Errors: HC_EINVAL (the bands do not fit in n/2 slots, s > n/2, N = 0,
  * bad comp_level, capacity too small -- *count then holds the size needed). */
 hc_status hc_plan(hc_context* ctx, uint64_t N, uint32_t ncol, uint32_t t_bound, uint32_t comp_level,
-                  uint32_t* elements_out, uint32_t* count, hc_compress_info* info);
+                  uint32_t out_level, uint32_t* elements_out, uint32_t* count, hc_compress_info* info);
 
 /* ------------------------------------------------------------------ database */
 
@@ -154,6 +160,10 @@ hc_status hc_encrypt(hc_context* ctx, const hc_pk* pk, const uint32_t* slots,
  * and the rest of the map runs there with the same Galois keys restricted to
  * those primes. comp_level: 0 = the smallest multiple of K that is >= 2
  * (at most L); L = no switching; otherwise a multiple of K up to L.
+ * out_level: 0 = the answer stays at the Comp level; 1..Comp level = the merged
+ * answer is modulus-switched once more to its first out_level primes before it
+ * is written (the answer the paper sends is one ciphertext modulo one prime,
+ * Sec. 6.2; out_level = 1 gives that form). The output decrypts to the same slots.
  *   ct_v: device, n_ct = ceil(N/n) ciphertexts [n_ct][2][L][n] of the index
  *         vector; record r sits in ciphertext r / n, row (r % n) / (n/2),
  *         column r % (n/2).
@@ -168,8 +178,8 @@ hc_status hc_encrypt(hc_context* ctx, const hc_pk* pk, const uint32_t* slots,
  * Errors: HC_EINVAL (shapes, bands do not fit), HC_ENOKEY (gk lacks a needed
  * element), HC_ENOMEM (workspace), HC_EDEVICE. */
 hc_status hc_compress(hc_context* ctx, const hc_gk* gk, const hc_db* db, const uint64_t* ct_v,
-                      uint64_t N, uint32_t t_bound, uint32_t comp_level, uint64_t* ct_out,
-                      hc_compress_info* info, hipStream_t stream);
+                      uint64_t N, uint32_t t_bound, uint32_t comp_level, uint32_t out_level,
+                      uint64_t* ct_out, hc_compress_info* info, hipStream_t stream);
 
 /* One entry of a batch for hc_compress_batch. */
 typedef struct {
@@ -177,6 +187,7 @@ typedef struct {
     uint64_t N;
     uint32_t t_bound;
     uint32_t comp_level;    /* as in hc_compress */
+    uint32_t out_level;     /* as in hc_compress */
     uint64_t* ct_out;       /* device, room for [2][L][n] */
     hc_compress_info* info; /* optional */
     hc_status status;       /* per-query result */
@@ -228,21 +239,25 @@ typedef struct hc_server hc_server;
  * are still running, so requests arriving meanwhile share the device with them
  * rather than waiting for them to finish. Every result is bit-identical to
  * hc_compress of the same query.
- *   comp_level: as in hc_compress, for every request.
+ *   comp_level, out_level: as in hc_compress, for every request.
  *   lane_bytes: device workspace per lane, allocated at creation.
  *   lanes: 1..4 concurrent batches; max_batch >= 1.
  * ctx, gk and db must outlive the server. Resident diagonal tables
  * (hc_diag_prepare) must not be prepared or released while it runs.
  * Errors: HC_EINVAL, HC_ENOMEM (lanes do not fit), HC_EDEVICE. */
 hc_status hc_server_create(hc_context* ctx, const hc_gk* gk, const hc_db* db, uint32_t comp_level,
-                           uint64_t lane_bytes, uint32_t lanes, uint32_t max_batch, hc_server** out);
+                           uint32_t out_level, uint64_t lane_bytes, uint32_t lanes, uint32_t max_batch,
+                           hc_server** out);
 
 /* Queue one query; returns at once. ct_v and ct_out are device buffers as for
  * hc_compress and must stay valid and unchanged until the request completes.
+ * `stream` is the stream the caller produced ct_v on: submit records an event
+ * there, and the batch that takes the request waits for it before reading
+ * ct_v (so ct_v may still be in flight on that stream at submission).
  * id_out (optional): the request id, increasing from 1. Errors: as hc_plan,
- * HC_ENOKEY, and HC_ENOMEM when the query alone does not fit one lane. */
+ * HC_ENOKEY, HC_EDEVICE, and HC_ENOMEM when the query alone does not fit one lane. */
 hc_status hc_server_submit(hc_server* srv, const uint64_t* ct_v, uint64_t N, uint32_t t_bound,
-                           uint64_t* ct_out, uint64_t* id_out);
+                           uint64_t* ct_out, hipStream_t stream, uint64_t* id_out);
 
 /* One completed request. Times are CLOCK_MONOTONIC nanoseconds. */
 typedef struct {

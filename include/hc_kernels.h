@@ -40,6 +40,28 @@ hc_status hc_ntt(hc_context* ctx, uint64_t* data, uint32_t count, uint32_t limb_
 hc_status hc_rotate(hc_context* ctx, const hc_gk* gk, uint32_t element, const uint64_t* ct_in,
                     uint64_t* ct_out, hipStream_t stream);
 
+/* hc_rotate at a lower level: ct_in / ct_out device [2][level][n] (coefficient
+ * domain, may not alias) over the first `level` ciphertext primes, key-switched
+ * with the Galois key restricted to those primes, the special primes and the
+ * digits inside them (still a valid key for the smaller modulus; this is how the
+ * compression rotates after its modulus switch, Sec. 5.3). level: a multiple of
+ * K in [K, L]. Errors: HC_EINVAL, HC_ENOKEY, HC_ENOMEM. Synchronises. */
+hc_status hc_rotate_level(hc_context* ctx, const hc_gk* gk, uint32_t element, uint32_t level,
+                          const uint64_t* ct_in, uint64_t* ct_out, hipStream_t stream);
+
+/* Modulus switching (the BFV form of the paper's move to smaller parameters,
+ * Sec. 5.3, and of its single-prime answer, Sec. 6.2): drop the primes
+ * level_out..level_in-1 of `count` ciphertexts. With D the product of the dropped
+ * primes each component c becomes (c - Conv_{D->Q'}([c]_D)) D^-1 mod Q', Conv the
+ * fast basis conversion of the dropped residues; this divides c by D (up to a
+ * conversion overflow of fewer than level_in - level_out multiples of Q'), so the
+ * result decrypts under Q' = q_1..q_level_out to the same slots.
+ * ct_in: device [count][2][level_in][n], ct_out: device [count][2][level_out][n],
+ * both coefficient domain (may not alias). 1 <= level_out < level_in <= L.
+ * Errors: HC_EINVAL, HC_ENOMEM. Enqueued on `stream`; returns without waiting. */
+hc_status hc_mod_switch(hc_context* ctx, const uint64_t* ct_in, uint32_t count, uint32_t level_in,
+                        uint32_t level_out, uint64_t* ct_out, hipStream_t stream);
+
 /* Hoisted rotations of one ciphertext by `count` elements: one ModUp of c1,
  * then per element sigma_k applied to the raised digits, inner product and
  * ModDown. cts_out: device [count][2][L][n]. Decrypts like hc_rotate but

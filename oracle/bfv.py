@@ -284,12 +284,14 @@ def rotate_hoisted(pr, ct, gks):
 # ---------------------------------------------------------------------------
 # modulus switching (the BFV form of switching to smaller parameters, Sec. 5.3)
 
-def at_level(pr, level):
-    """Parameters of the ring restricted to the first `level` ciphertext primes
-    (a multiple of the digit size): Q' = q_1 ... q_level, same special primes."""
+def at_level(pr, level, keyswitch=True):
+    """Parameters of the ring restricted to the first `level` ciphertext primes:
+    Q' = q_1 ... q_level, same special primes. Key switching needs whole digits,
+    so `level` must be a multiple of the digit size unless keyswitch is False (a
+    ciphertext that is only decrypted, such as a mod-switched output)."""
     import copy
-    if level % pr.alpha or not 0 < level <= pr.L:
-        raise ValueError("level must be a positive multiple of the digit size")
+    if not 0 < level <= pr.L or (keyswitch and level % pr.alpha):
+        raise ValueError("level must be in [1, L] (a multiple of the digit size for key switching)")
     lo = copy.copy(pr)
     lo.L = level
     lo.q = pr.q[:level]

@@ -38,6 +38,10 @@ determined by the inputs and the key seeds):
   the output is that band as is; otherwise every band is multiplied by the
   mask of slots [0, s) and band beta' is rotated by -beta' s before summing;
   the bands must fit: bands * s <= n/2;
+* smaller parameters for the answer (Sec. 5.3; Sec. 6.2 counts the answer as
+  one ciphertext modulo a single 54-bit prime): after the merge the output may
+  be modulus-switched once more, to its first `out_level` primes, by the same
+  division by the dropped primes (out_level in compress; default: no switch);
 * smaller parameters for Comp (Sec. 5.3 switches to a smaller ring after
   Mask): here the modulus is switched instead. After Mask, the index-vector
   and masked ciphertexts drop to the first `level` ciphertext primes, and
@@ -288,12 +292,24 @@ def default_level(pr):
     return min(lvl, pr.L)
 
 
-def compress(pr, sched, cts_v, db, gks, level=None):
+def compress(pr, sched, cts_v, db, gks, level=None, out_level=None):
     """Comp of Alg. 7 step 3 on ciphertexts of v (and Mask, step 2).
 
     cts_v: n_ct ciphertexts of the index vector; db: ncol value columns of
     length N; gks: Galois keys by element; level: ciphertext primes kept for
-    Comp (None: default_level). Returns one ciphertext at that level."""
+    Comp (None: default_level); out_level: primes of the answer (None: the Comp
+    level; fewer: the merged output is modulus-switched down to them). Returns
+    one ciphertext at out_level."""
+    out = _compress(pr, sched, cts_v, db, gks, level)
+    lvl = len(out.c0.mods)
+    if out_level is None or out_level == lvl:
+        return out
+    if not 0 < out_level < lvl:
+        raise ScheduleError("out_level must be in [1, Comp level]")
+    return bfv.mod_switch(bfv.at_level(pr, lvl), out, out_level)
+
+
+def _compress(pr, sched, cts_v, db, gks, level):
     if len(cts_v) != sched.n_ct or len(db) != sched.ncol or any(len(col) < sched.N for col in db):
         raise ScheduleError("inputs do not match the schedule")
     level = default_level(pr) if level is None else level
@@ -342,6 +358,21 @@ def vandermonde_product(p, s, vec):
     return out
 
 
+def vandermonde_product_sparse(p, s, vec):
+    """vandermonde_product restricted to the nonzero entries of vec (the zero
+    entries add nothing to any sum): for long, sparse vectors."""
+    x = np.asarray(vec, dtype=np.int64) % p
+    nz = np.nonzero(x)[0]
+    idx = (nz + 1) % p
+    xv = x[nz]
+    out = []
+    powv = idx.copy()
+    for _ in range(s):
+        out.append(int((powv * xv % p).sum() % p))
+        powv = powv * idx % p
+    return out
+
+
 def expected_bands(sched, v, db):
     """For each band, (row0, row1): the first s slots it must decrypt to."""
     p, s = sched.p, sched.s
@@ -352,8 +383,8 @@ def expected_bands(sched, v, db):
     for grp in sched.groups:
         sl = slice(grp.rec_start, grp.rec_start + grp.n_rec)
         for a, b in sched.streams:
-            r0 = vandermonde_product(p, s, vecs[a][sl])
-            r1 = vandermonde_product(p, s, vecs[b][sl]) if b is not None else [0] * s
+            r0 = vandermonde_product_sparse(p, s, vecs[a][sl])
+            r1 = vandermonde_product_sparse(p, s, vecs[b][sl]) if b is not None else [0] * s
             out.append((r0, r1))
     return out
 

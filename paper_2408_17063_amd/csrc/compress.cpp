@@ -55,11 +55,13 @@ static int default_level(const Ctx& c) {
 }
 
 hc_status make_plan(const Ctx& c, uint64_t N, uint32_t ncol, uint32_t t_bound, uint32_t comp_level,
-                    Plan& pl) {
+                    uint32_t out_level, Plan& pl) {
     if (N == 0 || t_bound == 0) return HC_EINVAL;
     if (comp_level == 0) pl.level = default_level(c);
     else if ((int)comp_level > c.L || comp_level % c.alpha) return HC_EINVAL;
     else pl.level = (int)comp_level;
+    if ((int)out_level > pl.level) return HC_EINVAL;
+    pl.out_level = out_level ? (int)out_level : pl.level;
     uint32_t s = 1;
     while (s < t_bound) s *= 2;
     if (s > (uint32_t)c.nh) return HC_EINVAL;
@@ -129,7 +131,8 @@ void fill_info(const Plan& pl, hc_compress_info* info) {
     info->n_keyswitch = pl.n_ks;
     info->n_ptct = pl.n_ptct;
     info->n_diag = pl.n_diag;
-    info->level = (uint32_t)pl.level;
+    info->level = (uint32_t)pl.out_level;
+    info->comp_level = (uint32_t)pl.level;
     info->n_diag_resident = 0;
 }
 
@@ -520,7 +523,8 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
         RUN(ew_run(c, l, mul, Lc, true, st));
         if (!jobs.empty()) RUN(ks_run(c, l, ks, jobs, nullptr, Lc, st));
     }
-    // 9. outputs back to the coefficient domain
+    // 9. outputs back to the coefficient domain, then (out_level < Lc) the answer's own
+    //    modulus switch, element-wise in the coefficient domain (Sec. 6.2's one-prime answer)
     for (auto& q : qs) {
         uint64_t* res = q.ybuf;
         if (q.pl.bands > 1) {
@@ -528,7 +532,10 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
             res = q.outN;
         }
         ntt64(c, res, q.PW, 2, 0, Lc, true, st);
-        HC_CHECK(hipMemcpyAsync(q.ct_out, res, sizeof(uint64_t) * q.CW, hipMemcpyDeviceToDevice, st));
+        if (q.pl.out_level < Lc)
+            RUN(mod_switch_coef(c, q.ct_out, res, 1, Lc, q.pl.out_level, q.ytmp, st));
+        else
+            HC_CHECK(hipMemcpyAsync(q.ct_out, res, sizeof(uint64_t) * q.CW, hipMemcpyDeviceToDevice, st));
     }
 #undef RUN
     HC_CHECK(hipGetLastError());
@@ -540,11 +547,11 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
 using namespace hc;
 
 extern "C" hc_status hc_plan(hc_context* cp, uint64_t N, uint32_t ncol, uint32_t t_bound,
-                             uint32_t comp_level, uint32_t* elements_out, uint32_t* count,
+                             uint32_t comp_level, uint32_t out_level, uint32_t* elements_out, uint32_t* count,
                              hc_compress_info* info) {
     if (!cp || !count) return HC_EINVAL;
     Plan pl;
-    hc_status s = make_plan(*cp, N, ncol, t_bound, comp_level, pl);
+    hc_status s = make_plan(*cp, N, ncol, t_bound, comp_level, out_level, pl);
     if (s != HC_OK) return s;
     fill_info(pl, info);
     if (info) {
@@ -562,12 +569,12 @@ extern "C" hc_status hc_plan(hc_context* cp, uint64_t N, uint32_t ncol, uint32_t
 }
 
 extern "C" hc_status hc_compress(hc_context* cp, const hc_gk* gk, const hc_db* db, const uint64_t* ct_v,
-                                 uint64_t N, uint32_t t_bound, uint32_t comp_level, uint64_t* ct_out,
-                                 hc_compress_info* info, hipStream_t st) {
+                                 uint64_t N, uint32_t t_bound, uint32_t comp_level, uint32_t out_level,
+                                 uint64_t* ct_out, hc_compress_info* info, hipStream_t st) {
     if (!cp || !gk || !ct_v || !ct_out) return HC_EINVAL;
     HC_CHECK(hipSetDevice(cp->device));
     std::vector<QueryRun> qs(1);
-    hc_status s = make_plan(*cp, N, db ? db->ncol : 0, t_bound, comp_level, qs[0].pl);
+    hc_status s = make_plan(*cp, N, db ? db->ncol : 0, t_bound, comp_level, out_level, qs[0].pl);
     if (s != HC_OK) return s;
     qs[0].ct_v = ct_v;
     qs[0].ct_out = ct_out;
@@ -588,7 +595,8 @@ extern "C" hc_status hc_compress_batch(hc_context* cp, const hc_gk* gk, const hc
         QueryRun r;
         q[i].status = (!q[i].ct_v || !q[i].ct_out)
                           ? HC_EINVAL
-                          : make_plan(*cp, q[i].N, db ? db->ncol : 0, q[i].t_bound, q[i].comp_level, r.pl);
+                          : make_plan(*cp, q[i].N, db ? db->ncol : 0, q[i].t_bound, q[i].comp_level,
+                                      q[i].out_level, r.pl);
         if (q[i].status == HC_OK) {
             for (uint32_t k : r.pl.keys)
                 if (!find_key(gk, k)) q[i].status = HC_ENOKEY;
@@ -621,7 +629,7 @@ extern "C" hc_status hc_diag_prepare(hc_context* cp, uint64_t N, uint32_t ncol, 
     Ctx& c = *cp;
     HC_CHECK(hipSetDevice(c.device));
     Plan pl;
-    hc_status s = make_plan(c, N, ncol, t_bound, comp_level, pl);
+    hc_status s = make_plan(c, N, ncol, t_bound, comp_level, 0, pl);
     if (s != HC_OK) return s;
     const int Lc = pl.level;
     const size_t n = c.n, PW = (size_t)Lc * n;

@@ -16,7 +16,8 @@ struct PlanGroup {
 
 struct Plan {
     uint32_t s = 0, n_ct = 0, ncol = 0;
-    int level = 0;  // ciphertext primes kept for Comp (modulus switched after Mask)
+    int level = 0;      // ciphertext primes kept for Comp (modulus switched after Mask)
+    int out_level = 0;  // ciphertext primes of the answer (<= level; switched after the merge)
     uint64_t N = 0;
     std::vector<PlanGroup> groups;
     std::vector<std::pair<int, int>> streams;  // vector ids (0 = v, c = d_c), -1 = none
@@ -108,8 +109,9 @@ struct BatchShape {
     std::map<std::pair<uint32_t, uint32_t>, const Ctx::DiagTab*> cls_res;
 };
 
-// Plan one compression (validates N, ncol, t_bound and comp_level).
-hc_status make_plan(const Ctx& c, uint64_t N, uint32_t ncol, uint32_t t_bound, uint32_t comp_level, Plan& pl);
+// Plan one compression (validates N, ncol, t_bound, comp_level and out_level).
+hc_status make_plan(const Ctx& c, uint64_t N, uint32_t ncol, uint32_t t_bound, uint32_t comp_level,
+                    uint32_t out_level, Plan& pl);
 void fill_info(const Plan& pl, hc_compress_info* info);
 void fill_info(const QueryRun& q, hc_compress_info* info);
 // Shape and workspace bytes of a batch; also sizes each QueryRun.

@@ -173,6 +173,7 @@ static hc_status upload(Ctx& c, T** dst, const std::vector<T>& src) {
 
 hc_status encode_plain(Ctx& c, uint64_t* out, const uint32_t* host_slots, int count, bool mont,
                        hipStream_t st);
+hc_status build_ms_tables(Ctx& c);
 
 }  // namespace hc
 
@@ -216,6 +217,13 @@ extern "C" hc_status hc_context_create(const hc_params* prm, int device, hc_cont
     }
     c.primes = qs;
     c.primes.insert(c.primes.end(), sps.begin(), sps.end());
+    // the key inner product reduces a sum of dnum products below q^2 with one
+    // Montgomery reduction, which needs dnum q < 2^64
+    for (uint64_t q : c.primes)
+        if ((unsigned __int128)c.dnum * q >= ((unsigned __int128)1 << 64)) {
+            delete cp;
+            return HC_EINVAL;
+        }
     const int nq = c.nq, L = c.L, K = c.K, logn = c.logn;
 
     // ---- NTT tables for every prime
@@ -368,6 +376,7 @@ extern "C" hc_status hc_context_create(const hc_params* prm, int device, hc_cont
     UP(c.d_delta, delta);
 #undef UP
     if ((st = ntt_build_tw2(c)) != HC_OK) { hc_context_destroy(cp); return st; }
+    if ((st = build_ms_tables(c)) != HC_OK) { hc_context_destroy(cp); return st; }
     if ((st = upload_keccak_constants(rc, rho, c.h_cdt.data())) != HC_OK) { hc_context_destroy(cp); return st; }
 
     // ---- row masks [1;0] and [0;1] as plaintext multipliers

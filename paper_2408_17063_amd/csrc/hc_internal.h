@@ -92,7 +92,9 @@ struct hc_context {
     uint32_t* d_cdt = nullptr;          // [20]
     uint64_t* d_keccak_rc = nullptr;    // [24]
 
-    // modulus-switching constants per target level: inv [L-Lc][2], cst [L-Lc][Lc], dinv [Lc][2]
+    // modulus-switching constants for dropping the primes Lc..Lin-1 of a ciphertext at
+    // level Lin, for every 1 <= Lc < Lin <= L (built at creation, so no call allocates
+    // them): inv [Lin-Lc][2], cst [Lin-Lc][Lc], dinv [Lc][2]; keyed by Lin * 256 + Lc
     struct MsTab { uint64_t* inv; uint64_t* cst; uint64_t* dinv; };
     std::map<int, MsTab> ms_tabs;
 
@@ -239,13 +241,13 @@ void k_ew_jobs(const Ctx& c, const EwJob* jobs, int M, int Lc, bool mul, hipStre
 // MaskJob products at L rows: a thread reads its coefficient of both components once
 // and each plaintext once
 void k_mask_jobs(const Ctx& c, const MaskJob* jobs, int M, int L, hipStream_t st);
-// modulus switching of `count` contiguous ciphertexts from L to Lc primes:
-// conv [count][2][Lc][n] from the dropped rows of ct [count][2][L][n] (coefficient domain);
-// out [count][2][Lc][n] = (ct - conv) D^-1 (NTT domain)
+// modulus switching of `count` contiguous ciphertexts from Lin to Lc primes:
+// conv [count][2][Lc][n] from the dropped rows of ct [count][2][Lin][n] (coefficient domain);
+// out [count][2][Lc][n] = (ct - conv) D^-1 (element-wise: conv in ct's domain)
 void k_ms_conv(const Ctx& c, uint64_t* conv, const uint64_t* ct, const uint64_t* inv, const uint64_t* cst,
-               int Lc, int count, hipStream_t st);
+               int Lin, int Lc, int count, hipStream_t st);
 void k_ms_final(const Ctx& c, uint64_t* out, const uint64_t* ct, const uint64_t* conv, const uint64_t* dinv,
-                int Lc, int count, hipStream_t st);
+                int Lin, int Lc, int count, hipStream_t st);
 // slots (device u32 [count][2][nh]) -> NTT-mod-p positions [count][n]
 void k_slots_to_eval(const Ctx& c, uint32_t* out, const uint32_t* slots, int count, hipStream_t st);
 // centred lift of mod-p coefficients [count][n] into [count][L][n]; Montgomery form if mont

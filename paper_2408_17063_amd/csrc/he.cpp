@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <tuple>
 
 #include "he.h"
 
@@ -308,49 +309,54 @@ hc_status ew_run(Ctx& c, Lane& l, const std::vector<EwJob>& jobs, int Lc, bool m
     return HC_OK;
 }
 
-// Constants for dropping the primes Lc..L-1 (product D), cached per level.
-static hc_status ms_tables(Ctx& c, int Lc, const Ctx::MsTab** out) {
-    std::lock_guard<std::mutex> g(c.lazy_mu);
-    auto it = c.ms_tabs.find(Lc);
-    if (it == c.ms_tabs.end()) {
-        const int L = c.L, nd = L - Lc;
-        std::vector<uint64_t> inv(2 * (size_t)nd), cst((size_t)nd * Lc), dinv(2 * (size_t)Lc);
-        for (int j = 0; j < nd; j++) {
-            const uint64_t qj = c.primes[Lc + j];
-            uint64_t h = 1;  // (D / q_j) mod q_j
-            for (int j2 = 0; j2 < nd; j2++)
-                if (j2 != j) h = h_mulmod(h, c.primes[Lc + j2] % qj, qj);
-            inv[2 * j] = h_invmod(h, qj);
-            inv[2 * j + 1] = h_shoup_const(inv[2 * j], qj);
+// Constants for dropping the primes Lc..Lin-1 (product D) of a ciphertext at level Lin,
+// for every 1 <= Lc < Lin <= L, packed in one device buffer (context creation).
+hc_status build_ms_tables(Ctx& c) {
+    const int L = c.L;
+    std::vector<uint64_t> all;
+    std::vector<std::tuple<int, size_t, size_t, size_t>> offs;  // key, inv, cst, dinv
+    for (int Lin = 2; Lin <= L; Lin++)
+        for (int Lc = 1; Lc < Lin; Lc++) {
+            const int nd = Lin - Lc;
+            const size_t oi = all.size(), oc = oi + 2 * (size_t)nd, od = oc + (size_t)nd * Lc;
+            all.resize(od + 2 * (size_t)Lc);
+            for (int j = 0; j < nd; j++) {
+                const uint64_t qj = c.primes[Lc + j];
+                uint64_t h = 1;  // (D / q_j) mod q_j
+                for (int j2 = 0; j2 < nd; j2++)
+                    if (j2 != j) h = h_mulmod(h, c.primes[Lc + j2] % qj, qj);
+                all[oi + 2 * j] = h_invmod(h, qj);
+                all[oi + 2 * j + 1] = h_shoup_const(all[oi + 2 * j], qj);
+                for (int i = 0; i < Lc; i++) {
+                    const uint64_t qi = c.primes[i];
+                    uint64_t hi = 1;
+                    for (int j2 = 0; j2 < nd; j2++)
+                        if (j2 != j) hi = h_mulmod(hi, c.primes[Lc + j2] % qi, qi);
+                    all[oc + (size_t)j * Lc + i] = h_to_mont(hi, qi);
+                }
+            }
             for (int i = 0; i < Lc; i++) {
                 const uint64_t qi = c.primes[i];
-                uint64_t hi = 1;
-                for (int j2 = 0; j2 < nd; j2++)
-                    if (j2 != j) hi = h_mulmod(hi, c.primes[Lc + j2] % qi, qi);
-                cst[(size_t)j * Lc + i] = h_to_mont(hi, qi);
+                uint64_t D = 1;
+                for (int j = 0; j < nd; j++) D = h_mulmod(D, c.primes[Lc + j] % qi, qi);
+                all[od + 2 * i] = h_invmod(D, qi);
+                all[od + 2 * i + 1] = h_shoup_const(all[od + 2 * i], qi);
             }
+            offs.emplace_back(Lin * 256 + Lc, oi, oc, od);
         }
-        for (int i = 0; i < Lc; i++) {
-            const uint64_t qi = c.primes[i];
-            uint64_t D = 1;
-            for (int j = 0; j < nd; j++) D = h_mulmod(D, c.primes[Lc + j] % qi, qi);
-            dinv[2 * i] = h_invmod(D, qi);
-            dinv[2 * i + 1] = h_shoup_const(dinv[2 * i], qi);
-        }
-        Ctx::MsTab t{};
-        HC_CHECK(hipMalloc((void**)&t.inv, sizeof(uint64_t) * std::max<size_t>(inv.size(), 1)));
-        HC_CHECK(hipMalloc((void**)&t.cst, sizeof(uint64_t) * std::max<size_t>(cst.size(), 1)));
-        HC_CHECK(hipMalloc((void**)&t.dinv, sizeof(uint64_t) * dinv.size()));
-        c.owned.push_back(t.inv);
-        c.owned.push_back(t.cst);
-        c.owned.push_back(t.dinv);
-        HC_CHECK(hipMemcpy(t.inv, inv.data(), sizeof(uint64_t) * inv.size(), hipMemcpyHostToDevice));
-        HC_CHECK(hipMemcpy(t.cst, cst.data(), sizeof(uint64_t) * cst.size(), hipMemcpyHostToDevice));
-        HC_CHECK(hipMemcpy(t.dinv, dinv.data(), sizeof(uint64_t) * dinv.size(), hipMemcpyHostToDevice));
-        it = c.ms_tabs.emplace(Lc, t).first;
-    }
-    *out = &it->second;
+    if (all.empty()) return HC_OK;
+    uint64_t* d = nullptr;
+    HC_CHECK(hipMalloc((void**)&d, sizeof(uint64_t) * all.size()));
+    c.owned.push_back(d);
+    HC_CHECK(hipMemcpy(d, all.data(), sizeof(uint64_t) * all.size(), hipMemcpyHostToDevice));
+    for (auto& o : offs)
+        c.ms_tabs[std::get<0>(o)] = Ctx::MsTab{d + std::get<1>(o), d + std::get<2>(o), d + std::get<3>(o)};
     return HC_OK;
+}
+
+static const Ctx::MsTab* ms_table(const Ctx& c, int Lin, int Lc) {
+    auto it = c.ms_tabs.find(Lin * 256 + Lc);
+    return it == c.ms_tabs.end() ? nullptr : &it->second;
 }
 
 // out [count][2][Lc][n] = in [count][2][L][n] with the primes Lc..L-1 dropped (NTT domain
@@ -358,19 +364,30 @@ static hc_status ms_tables(Ctx& c, int Lc, const Ctx::MsTab** out) {
 // words per ciphertext.
 hc_status mod_switch_batch(Ctx& c, uint64_t* out, uint64_t* in, int count, int Lc, uint64_t* conv,
                            hipStream_t st, const uint64_t* coef, int ncoef) {
-    const Ctx::MsTab* t = nullptr;
-    hc_status s = ms_tables(c, Lc, &t);
-    if (s != HC_OK) return s;
+    const Ctx::MsTab* t = ms_table(c, c.L, Lc);
+    if (!t) return HC_EINVAL;
     if (!coef || ncoef < 0) ncoef = 0;
     if (ncoef > count) return HC_EINVAL;
     const size_t n = c.n, Ln = (size_t)c.L * n, skip = 2 * (size_t)ncoef;
     // the dropped rows in coefficient form: given for the first ncoef, transformed back
     // for the rest
     ntt64(c, in + skip * Ln + (size_t)Lc * n, Ln, 2 * (count - ncoef), Lc, c.L - Lc, true, st);
-    if (ncoef > 0) k_ms_conv(c, conv, coef, t->inv, t->cst, Lc, ncoef, st);
-    k_ms_conv(c, conv + skip * Lc * n, in + skip * Ln, t->inv, t->cst, Lc, count - ncoef, st);
+    if (ncoef > 0) k_ms_conv(c, conv, coef, t->inv, t->cst, c.L, Lc, ncoef, st);
+    k_ms_conv(c, conv + skip * Lc * n, in + skip * Ln, t->inv, t->cst, c.L, Lc, count - ncoef, st);
     ntt64(c, conv, (size_t)Lc * n, 2 * count, 0, Lc, false, st);
-    k_ms_final(c, out, in, conv, t->dinv, Lc, count, st);
+    k_ms_final(c, out, in, conv, t->dinv, c.L, Lc, count, st);
+    return HC_OK;
+}
+
+// out [count][2][Lo][n] = in [count][2][Lin][n] with the primes Lo..Lin-1 dropped, both in the
+// coefficient domain (no transform: the conversion and the division are element-wise).
+// conv: 2 Lo n words per ciphertext.
+hc_status mod_switch_coef(const Ctx& c, uint64_t* out, const uint64_t* in, int count, int Lin, int Lo,
+                          uint64_t* conv, hipStream_t st) {
+    const Ctx::MsTab* t = ms_table(c, Lin, Lo);
+    if (!t || count < 1) return HC_EINVAL;
+    k_ms_conv(c, conv, in, t->inv, t->cst, Lin, Lo, count, st);
+    k_ms_final(c, out, in, conv, t->dinv, Lin, Lo, count, st);
     return HC_OK;
 }
 
@@ -579,16 +596,17 @@ extern "C" hc_status hc_ntt(hc_context* cp, uint64_t* data, uint32_t count, uint
 }
 
 static hc_status rotate_common(hc_context* cp, const hc_gk* gk, const uint32_t* elts, uint32_t count,
-                               const uint64_t* ct_in, uint64_t* cts_out, bool hoisted, hipStream_t st) {
+                               const uint64_t* ct_in, uint64_t* cts_out, bool hoisted, int Lc, hipStream_t st) {
     if (!cp || !gk || !elts || !ct_in || !cts_out || count == 0) return HC_EINVAL;
     Ctx& c = *cp;
+    if (Lc < c.alpha || Lc > c.L || Lc % c.alpha) return HC_EINVAL;
     HC_CHECK(hipSetDevice(c.device));
-    const size_t Ln2 = 2 * (size_t)c.L * c.n;
+    const size_t Ln2 = 2 * (size_t)Lc * c.n;
     std::vector<KsJob> jobs(count);
     stage_reset(c.lane, st);
-    if (c.lane.ws.reserve(ks_scratch_bytes(c, c.L, (int)count) + sizeof(uint64_t) * Ln2 * (count + 1) + 4096) != HC_OK)
+    if (c.lane.ws.reserve(ks_scratch_bytes(c, Lc, (int)count) + sizeof(uint64_t) * Ln2 * (count + 1) + 4096) != HC_OK)
         return HC_ENOMEM;
-    KsScratch s = ks_scratch(c, c.lane.ws, c.L, (int)count);
+    KsScratch s = ks_scratch(c, c.lane.ws, Lc, (int)count);
     uint64_t* inN = c.lane.ws.take<uint64_t>(Ln2);
     uint64_t* outN = c.lane.ws.take<uint64_t>(Ln2 * count);
     if (!inN || !outN) return HC_ENOMEM;
@@ -598,11 +616,11 @@ static hc_status rotate_common(hc_context* cp, const hc_gk* gk, const uint32_t* 
         jobs[i] = KsJob{inN, outN + i * Ln2, key, elts[i], 0};
     }
     HC_CHECK(hipMemcpyAsync(inN, ct_in, sizeof(uint64_t) * Ln2, hipMemcpyDeviceToDevice, st));
-    ntt64(c, inN, (size_t)c.L * c.n, 2, 0, c.L, false, st);
+    ntt64(c, inN, (size_t)Lc * c.n, 2, 0, Lc, false, st);
     std::vector<const uint64_t*> srcs{inN};
-    hc_status stt = ks_run(c, c.lane, s, jobs, hoisted ? &srcs : nullptr, c.L, st);
+    hc_status stt = ks_run(c, c.lane, s, jobs, hoisted ? &srcs : nullptr, Lc, st);
     if (stt != HC_OK) return stt;
-    ntt64(c, outN, (size_t)c.L * c.n, 2 * (int)count, 0, c.L, true, st);
+    ntt64(c, outN, (size_t)Lc * c.n, 2 * (int)count, 0, Lc, true, st);
     HC_CHECK(hipMemcpyAsync(cts_out, outN, sizeof(uint64_t) * Ln2 * count, hipMemcpyDeviceToDevice, st));
     HC_CHECK(hipGetLastError());
     HC_CHECK(hipStreamSynchronize(st));
@@ -611,13 +629,40 @@ static hc_status rotate_common(hc_context* cp, const hc_gk* gk, const uint32_t* 
 
 extern "C" hc_status hc_rotate(hc_context* cp, const hc_gk* gk, uint32_t element, const uint64_t* ct_in,
                                uint64_t* ct_out, hipStream_t st) {
-    return rotate_common(cp, gk, &element, 1, ct_in, ct_out, false, st);
+    if (!cp) return HC_EINVAL;
+    return rotate_common(cp, gk, &element, 1, ct_in, ct_out, false, cp->L, st);
+}
+
+extern "C" hc_status hc_rotate_level(hc_context* cp, const hc_gk* gk, uint32_t element, uint32_t level,
+                                     const uint64_t* ct_in, uint64_t* ct_out, hipStream_t st) {
+    if (!cp) return HC_EINVAL;
+    return rotate_common(cp, gk, &element, 1, ct_in, ct_out, false, (int)level, st);
 }
 
 extern "C" hc_status hc_rotate_hoisted(hc_context* cp, const hc_gk* gk, const uint32_t* elements,
                                        uint32_t count, const uint64_t* ct_in, uint64_t* cts_out,
                                        hipStream_t st) {
-    return rotate_common(cp, gk, elements, count, ct_in, cts_out, true, st);
+    if (!cp) return HC_EINVAL;
+    return rotate_common(cp, gk, elements, count, ct_in, cts_out, true, cp->L, st);
+}
+
+extern "C" hc_status hc_mod_switch(hc_context* cp, const uint64_t* ct_in, uint32_t count, uint32_t level_in,
+                                   uint32_t level_out, uint64_t* ct_out, hipStream_t st) {
+    if (!cp || !ct_in || !ct_out || count == 0 || level_out < 1 || level_out >= level_in ||
+        level_in > (uint32_t)cp->L)
+        return HC_EINVAL;
+    Ctx& c = *cp;
+    HC_CHECK(hipSetDevice(c.device));
+    // the workspace is reused in stream order; wait for another stream's last use
+    stage_reset(c.lane, st);
+    const size_t cw = 2 * (size_t)level_out * c.n * count;
+    if (c.lane.ws.reserve(sizeof(uint64_t) * cw + 4096) != HC_OK) return HC_ENOMEM;
+    uint64_t* conv = c.lane.ws.take<uint64_t>(cw);
+    if (!conv) return HC_ENOMEM;
+    hc_status s = mod_switch_coef(c, ct_out, ct_in, (int)count, (int)level_in, (int)level_out, conv, st);
+    if (s != HC_OK) return s;
+    HC_CHECK(hipGetLastError());
+    return HC_OK;
 }
 
 extern "C" hc_status hc_mul_plain(hc_context* cp, const uint64_t* ct_in, const uint32_t* slots,

@@ -44,6 +44,12 @@ hc_status ew_run(Ctx& c, Lane& l, const std::vector<EwJob>& jobs, int Lc, bool m
 // dropped rows are then read from there instead of being transformed back.
 hc_status mod_switch_batch(Ctx& c, uint64_t* out, uint64_t* in, int count, int Lc, uint64_t* conv,
                            hipStream_t st, const uint64_t* coef = nullptr, int ncoef = 0);
+// dropping primes from coefficient-domain ciphertexts at level Lin down to Lo
+// (count contiguous ciphertexts; conv: 2 Lo n words each)
+hc_status mod_switch_coef(const Ctx& c, uint64_t* out, const uint64_t* in, int count, int Lin, int Lo,
+                          uint64_t* conv, hipStream_t st);
+// the switching constants of every level pair (context creation)
+hc_status build_ms_tables(Ctx& c);
 const uint64_t* find_key(const hc_gk* gk, uint32_t k);
 
 }  // namespace hc

@@ -430,7 +430,8 @@ void k_sum_cts(const Ctx& c, uint64_t* y, const uint64_t* src, int groups, int c
 // ------------------------------------------------------------------ modulus switching
 
 // conv[c][i][x] = sum_{j dropped} [ct_j(x) (D/q_j)^-1]_{q_j} (D/q_j) mod q_i  for kept i < Lc;
-// ct [count][2][L][n] with the dropped rows Lc..L-1 in the coefficient domain; blockIdx.z = t*2+comp.
+// ct [count][2][L][n] (L = the source level) with the dropped rows Lc..L-1 in the
+// coefficient domain; blockIdx.z = t*2+comp.
 // A thread covers CONV_ROWS consecutive kept primes: each dropped residue is read and
 // scaled once.
 template <int NI>
@@ -483,7 +484,8 @@ __global__ void ms_conv_kernel(uint64_t* __restrict__ conv, const uint64_t* __re
         *reinterpret_cast<ulonglong2*>(conv + ((size_t)tc * Lc + i0 + u) * n + x) = ulonglong2{sum[u][0], sum[u][1]};
 }
 
-// out[t][c][i] = (ct[t][c][i] - conv[t][c][i]) D^-1 mod q_i (NTT domain), out at level Lc
+// out[t][c][i] = (ct[t][c][i] - conv[t][c][i]) D^-1 mod q_i, out at level Lc (element-wise:
+// ct and conv in the same domain, NTT or coefficient)
 __global__ void ms_final_kernel(uint64_t* __restrict__ out, const uint64_t* __restrict__ ct,
                                 const uint64_t* __restrict__ conv, const uint64_t* __restrict__ mods,
                                 const uint64_t* __restrict__ dinv, int n, int L, int Lc) {
@@ -511,7 +513,7 @@ static void with_rows(int v, F&& f) {
 }
 
 void k_ms_conv(const Ctx& c, uint64_t* conv, const uint64_t* ct, const uint64_t* inv, const uint64_t* cst,
-               int Lc, int count, hipStream_t st) {
+               int Lin, int Lc, int count, hipStream_t st) {
     if (count <= 0) return;
     // the kept primes in chunks of up to CONV_ROWS per thread (primes below 2^60, so a
     // batch of 8 products stays below q 2^64)
@@ -519,14 +521,14 @@ void k_ms_conv(const Ctx& c, uint64_t* conv, const uint64_t* ct, const uint64_t*
         with_rows(std::min(CONV_ROWS, Lc - i0), [&](auto ni_c) {
             constexpr int NI = decltype(ni_c)::value;
             hipLaunchKernelGGL((ms_conv_kernel<NI>), ew_grid(c.n / 2, 1, 2 * count), dim3(EW_THREADS), 0, st, conv, ct,
-                               c.d_mods, c.d_qinv, inv, cst, c.n, c.L, Lc, i0);
+                               c.d_mods, c.d_qinv, inv, cst, c.n, Lin, Lc, i0);
         });
 }
 
 void k_ms_final(const Ctx& c, uint64_t* out, const uint64_t* ct, const uint64_t* conv, const uint64_t* dinv,
-                int Lc, int count, hipStream_t st) {
+                int Lin, int Lc, int count, hipStream_t st) {
     hipLaunchKernelGGL(ms_final_kernel, ew_grid(c.n, Lc, 2 * count), dim3(EW_THREADS), 0, st, out, ct, conv,
-                       c.d_mods, dinv, c.n, c.L, Lc);
+                       c.d_mods, dinv, c.n, Lin, Lc);
 }
 
 // element-wise jobs over ciphertexts at level Lc; blockIdx.y = comp * Lc + row

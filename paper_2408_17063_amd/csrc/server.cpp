@@ -30,6 +30,10 @@ struct ServerReq {
     uint64_t id = 0;
     QueryRun run;
     hc_server_result res{};
+    hipEvent_t ready = nullptr;  // recorded on the submitter's stream after ct_v was produced
+    ~ServerReq() {
+        if (ready) (void)hipEventDestroy(ready);
+    }
 };
 
 struct ServerLane {
@@ -47,7 +51,7 @@ struct hc_server {
     hc_context* c = nullptr;
     const hc_gk* gk = nullptr;
     const hc_db* db = nullptr;
-    uint32_t comp_level = 0;
+    uint32_t comp_level = 0, out_level = 0;
     size_t lane_bytes = 0;
     uint32_t max_batch = 1;
     std::vector<std::unique_ptr<hc::ServerLane>> lanes;
@@ -70,7 +74,11 @@ hc_status hc_server::launch(ServerLane& ln, std::vector<ServerReq*>& batch) {
     runs.reserve(batch.size());
     for (ServerReq* r : batch) runs.push_back(r->run);
     const int64_t t = now_ns();
-    hc_status s = compress_many(*c, ln.lane, gk, db, runs, ln.stream);
+    // the batch reads each ct_v only after the work its submitter queued before it
+    hc_status s = HC_OK;
+    for (ServerReq* r : batch)
+        if (r->ready && hipStreamWaitEvent(ln.stream, r->ready, 0) != hipSuccess) s = HC_EDEVICE;
+    if (s == HC_OK) s = compress_many(*c, ln.lane, gk, db, runs, ln.stream);
     for (size_t i = 0; i < batch.size(); i++) {
         batch[i]->res.start_ns = t;
         batch[i]->res.batch_size = (uint32_t)batch.size();
@@ -161,7 +169,8 @@ void hc_server::loop() {
 }
 
 extern "C" hc_status hc_server_create(hc_context* cp, const hc_gk* gk, const hc_db* db, uint32_t comp_level,
-                                      uint64_t lane_bytes, uint32_t lanes, uint32_t max_batch, hc_server** out) {
+                                      uint32_t out_level, uint64_t lane_bytes, uint32_t lanes, uint32_t max_batch,
+                                      hc_server** out) {
     if (!cp || !gk || !out || lanes < 1 || lanes > 4 || max_batch < 1 || lane_bytes < (1u << 20))
         return HC_EINVAL;
     *out = nullptr;
@@ -172,6 +181,7 @@ extern "C" hc_status hc_server_create(hc_context* cp, const hc_gk* gk, const hc_
     s->gk = gk;
     s->db = db;
     s->comp_level = comp_level;
+    s->out_level = out_level;
     s->lane_bytes = lane_bytes;
     s->max_batch = max_batch;
     // tables that compressions build on first use, built now (their construction
@@ -202,10 +212,11 @@ extern "C" hc_status hc_server_create(hc_context* cp, const hc_gk* gk, const hc_
 }
 
 extern "C" hc_status hc_server_submit(hc_server* s, const uint64_t* ct_v, uint64_t N, uint32_t t_bound,
-                                      uint64_t* ct_out, uint64_t* id_out) {
+                                      uint64_t* ct_out, hipStream_t stream, uint64_t* id_out) {
     if (!s || !ct_v || !ct_out) return HC_EINVAL;
     std::unique_ptr<ServerReq> r(new ServerReq());
-    hc_status st = make_plan(*s->c, N, s->db ? s->db->ncol : 0, t_bound, s->comp_level, r->run.pl);
+    hc_status st =
+        make_plan(*s->c, N, s->db ? s->db->ncol : 0, t_bound, s->comp_level, s->out_level, r->run.pl);
     if (st != HC_OK) return st;
     r->run.ct_v = ct_v;
     r->run.ct_out = ct_out;
@@ -216,6 +227,9 @@ extern "C" hc_status hc_server_submit(hc_server* s, const uint64_t* ct_v, uint64
         if (st != HC_OK) return st;
         if (shape.total > s->lane_bytes) return HC_ENOMEM;
     }
+    HC_CHECK(hipSetDevice(s->c->device));
+    HC_CHECK(hipEventCreateWithFlags(&r->ready, hipEventDisableTiming));
+    HC_CHECK(hipEventRecord(r->ready, stream));
     std::lock_guard<std::mutex> g(s->mu);
     if (s->stop) return HC_EINVAL;
     r->id = s->next_id++;

@@ -47,7 +47,7 @@ class CompressInfo(ctypes.Structure):
                 ("bands", ctypes.c_uint32), ("n_ct", ctypes.c_uint32),
                 ("n_keyswitch", ctypes.c_uint32), ("n_ptct", ctypes.c_uint64),
                 ("n_diag", ctypes.c_uint64), ("level", ctypes.c_uint32),
-                ("n_diag_resident", ctypes.c_uint64)]
+                ("n_diag_resident", ctypes.c_uint64), ("comp_level", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -55,8 +55,8 @@ class CompressInfo(ctypes.Structure):
 
 class Query(ctypes.Structure):
     _fields_ = [("ct_v", c_vp), ("N", ctypes.c_uint64), ("t_bound", ctypes.c_uint32),
-                ("comp_level", ctypes.c_uint32), ("ct_out", c_vp), ("info", ctypes.POINTER(CompressInfo)),
-                ("status", ctypes.c_int)]
+                ("comp_level", ctypes.c_uint32), ("out_level", ctypes.c_uint32), ("ct_out", c_vp),
+                ("info", ctypes.POINTER(CompressInfo)), ("status", ctypes.c_int)]
 
 
 class ServerResult(ctypes.Structure):
@@ -88,19 +88,21 @@ _sig("hc_sk_destroy", None, c_vp)
 _sig("hc_pk_destroy", None, c_vp)
 _sig("hc_galois_keygen", _st, c_vp, c_vp, c_u32p, ctypes.c_uint32, c_u8p, ctypes.POINTER(c_vp))
 _sig("hc_gk_destroy", None, c_vp)
-_sig("hc_plan", _st, c_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, c_u32p,
-     ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(CompressInfo))
+_sig("hc_plan", _st, c_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+     c_u32p, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(CompressInfo))
 _sig("hc_db_upload", _st, c_vp, c_u32p, ctypes.c_uint32, ctypes.c_uint64, ctypes.POINTER(c_vp))
 _sig("hc_db_destroy", None, c_vp)
 _sig("hc_encrypt", _st, c_vp, c_vp, c_u32p, c_u8p, c_vp, c_vp)
-_sig("hc_compress", _st, c_vp, c_vp, c_vp, c_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, c_vp,
-     ctypes.POINTER(CompressInfo), c_vp)
+_sig("hc_compress", _st, c_vp, c_vp, c_vp, c_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+     c_vp, ctypes.POINTER(CompressInfo), c_vp)
 _sig("hc_compress_batch", _st, c_vp, c_vp, c_vp, ctypes.POINTER(Query), ctypes.c_uint32, c_vp)
 _sig("hc_decrypt", _st, c_vp, c_vp, c_u64p, ctypes.c_uint32, c_u32p)
 _sig("hc_decompress", _st, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
      c_u32p, c_u32p, c_u64p, c_u32p, c_u32p)
 _sig("hc_ntt", _st, c_vp, c_vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, c_vp)
 _sig("hc_rotate", _st, c_vp, c_vp, ctypes.c_uint32, c_vp, c_vp, c_vp)
+_sig("hc_rotate_level", _st, c_vp, c_vp, ctypes.c_uint32, ctypes.c_uint32, c_vp, c_vp, c_vp)
+_sig("hc_mod_switch", _st, c_vp, c_vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, c_vp, c_vp)
 _sig("hc_rotate_hoisted", _st, c_vp, c_vp, c_u32p, ctypes.c_uint32, c_vp, c_vp, c_vp)
 _sig("hc_mul_plain", _st, c_vp, c_vp, c_u32p, c_vp, c_vp)
 _sig("hc_modup", _st, c_vp, c_vp, ctypes.c_uint32, c_vp, c_vp)
@@ -120,9 +122,10 @@ _sig("hc_probe_copy", _st, c_vp, ctypes.c_uint64)
 _sig("hc_diag_prepare", _st, c_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
      ctypes.POINTER(ctypes.c_uint64))
 _sig("hc_diag_release", None, c_vp)
-_sig("hc_server_create", _st, c_vp, c_vp, c_vp, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
-     ctypes.POINTER(c_vp))
-_sig("hc_server_submit", _st, c_vp, c_vp, ctypes.c_uint64, ctypes.c_uint32, c_vp, ctypes.POINTER(ctypes.c_uint64))
+_sig("hc_server_create", _st, c_vp, c_vp, c_vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32,
+     ctypes.c_uint32, ctypes.POINTER(c_vp))
+_sig("hc_server_submit", _st, c_vp, c_vp, ctypes.c_uint64, ctypes.c_uint32, c_vp, c_vp,
+     ctypes.POINTER(ctypes.c_uint64))
 _sig("hc_server_poll", _st, c_vp, ctypes.POINTER(ServerResult), ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
      ctypes.c_double)
 _sig("hc_server_stats_get", _st, c_vp, ctypes.POINTER(ServerStats))
@@ -137,7 +140,8 @@ EXPORTED = [
     "hc_keygen",
     "hc_sk_destroy", "hc_pk_destroy", "hc_galois_keygen", "hc_gk_destroy", "hc_plan",
     "hc_db_upload", "hc_db_destroy", "hc_encrypt", "hc_compress", "hc_compress_batch",
-    "hc_decrypt", "hc_decompress", "hc_ntt", "hc_rotate", "hc_rotate_hoisted", "hc_mul_plain",
+    "hc_decrypt", "hc_decompress", "hc_ntt", "hc_rotate", "hc_rotate_level", "hc_mod_switch",
+    "hc_rotate_hoisted", "hc_mul_plain",
     "hc_modup", "hc_moddown", "hc_sample", "hc_encode_diagonal", "hc_export_sk", "hc_export_pk",
     "hc_export_gk", "hc_timing_enable", "hc_timing_read", "hc_probe_mul32_rate", "hc_probe_copy",
     "hc_diag_prepare", "hc_diag_release", "hc_server_create", "hc_server_submit", "hc_server_poll",
@@ -163,9 +167,13 @@ def _np_ptr(a, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
 
 
-def _dev(t):
+def _dev(t, words=None, what="buffer"):
+    """Device address of an int64 CUDA tensor; with `words`, the tensor must hold at
+    least that many 64-bit words (else HC_EINVAL is raised before any library call)."""
     import torch
     assert t.is_cuda and t.dtype == torch.int64 and t.is_contiguous()
+    if words is not None and t.numel() < words:
+        raise HcError(HC_EINVAL, "%s holds %d words, %d needed" % (what, t.numel(), words))
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -227,15 +235,16 @@ class Context:
                                      ctypes.byref(gk)), "hc_galois_keygen")
         return GaloisKeys(self, gk, [int(x) for x in arr])
 
-    def plan(self, N, ncol, t_bound, comp_level=0):
+    def plan(self, N, ncol, t_bound, comp_level=0, out_level=0):
         cnt = ctypes.c_uint32(0)
         info = CompressInfo()
-        st = _lib.hc_plan(self.h, N, ncol, t_bound, comp_level, None, ctypes.byref(cnt), ctypes.byref(info))
+        st = _lib.hc_plan(self.h, N, ncol, t_bound, comp_level, out_level, None, ctypes.byref(cnt),
+                          ctypes.byref(info))
         if st not in (HC_OK, HC_EINVAL) or (st == HC_EINVAL and cnt.value == 0):
             _check(st, "hc_plan")
         arr = np.zeros(max(cnt.value, 1), dtype=np.uint32)
         cap = ctypes.c_uint32(len(arr))
-        _check(_lib.hc_plan(self.h, N, ncol, t_bound, comp_level, _np_ptr(arr, ctypes.c_uint32),
+        _check(_lib.hc_plan(self.h, N, ncol, t_bound, comp_level, out_level, _np_ptr(arr, ctypes.c_uint32),
                             ctypes.byref(cap), ctypes.byref(info)), "hc_plan")
         return [int(x) for x in arr[:cap.value]], info.as_dict()
 
@@ -270,12 +279,18 @@ class Context:
                                _stream(stream)), "hc_encrypt")
         return out
 
-    def compress(self, gk, db, ct_v, N, t_bound, out=None, stream=None, comp_level=0):
+    def ct_words(self, N):
+        """64-bit words of the index-vector ciphertexts of N records, [ceil(N/n)][2][L][n]."""
+        return -(-int(N) // self.n) * 2 * self.L * self.n
+
+    def compress(self, gk, db, ct_v, N, t_bound, out=None, stream=None, comp_level=0, out_level=0):
         """Returns (out buffer, info); output() extracts the [2][level][n] ciphertext."""
         out = self.ct_tensor(1)[0] if out is None else out
         info = CompressInfo()
-        _check(_lib.hc_compress(self.h, gk.h, db.h if db is not None else None, _dev(ct_v), N, t_bound,
-                                comp_level, _dev(out), ctypes.byref(info), _stream(stream)), "hc_compress")
+        _check(_lib.hc_compress(self.h, gk.h, db.h if db is not None else None,
+                                _dev(ct_v, self.ct_words(N), "ct_v"), N, t_bound, comp_level, out_level,
+                                _dev(out, 2 * self.L * self.n, "out"), ctypes.byref(info), _stream(stream)),
+               "hc_compress")
         return out, info.as_dict()
 
     def output(self, out, info):
@@ -283,16 +298,17 @@ class Context:
         lvl = info["level"]
         return out.reshape(-1)[:2 * lvl * self.n].reshape(2, lvl, self.n)
 
-    def compress_batch(self, gk, db, queries, stream=None, comp_level=0):
+    def compress_batch(self, gk, db, queries, stream=None, comp_level=0, out_level=0):
         """queries: list of (ct_v tensor, N, t_bound, out tensor)."""
         arr = (Query * len(queries))()
         infos = [CompressInfo() for _ in queries]
         for i, (ctv, N, t, out) in enumerate(queries):
-            arr[i].ct_v = _dev(ctv).value
+            arr[i].ct_v = _dev(ctv, self.ct_words(N), "ct_v").value
             arr[i].N = N
             arr[i].t_bound = t
             arr[i].comp_level = comp_level
-            arr[i].ct_out = _dev(out).value
+            arr[i].out_level = out_level
+            arr[i].ct_out = _dev(out, 2 * self.L * self.n, "out").value
             arr[i].info = ctypes.pointer(infos[i])
         st = _lib.hc_compress_batch(self.h, gk.h, db.h if db is not None else None, arr, len(queries),
                                     _stream(stream))
@@ -316,7 +332,27 @@ class Context:
 
     def rotate(self, gk, element, ct_in, out=None, stream=None):
         out = self.ct_tensor(1)[0] if out is None else out
-        _check(_lib.hc_rotate(self.h, gk.h, element, _dev(ct_in), _dev(out), _stream(stream)), "hc_rotate")
+        w = 2 * self.L * self.n
+        _check(_lib.hc_rotate(self.h, gk.h, element, _dev(ct_in, w, "ct_in"), _dev(out, w, "out"),
+                              _stream(stream)), "hc_rotate")
+        return out
+
+    def rotate_level(self, gk, element, level, ct_in, out=None, stream=None):
+        """Rotation of a [2][level][n] ciphertext with the key restricted to level primes."""
+        import torch
+        w = 2 * level * self.n
+        out = torch.empty(w, dtype=torch.int64, device=ct_in.device) if out is None else out
+        _check(_lib.hc_rotate_level(self.h, gk.h, element, level, _dev(ct_in, w, "ct_in"), _dev(out, w, "out"),
+                                    _stream(stream)), "hc_rotate_level")
+        return out
+
+    def mod_switch(self, ct_in, level_in, level_out, count=1, out=None, stream=None):
+        """Drop primes level_out..level_in-1 of `count` coefficient-domain ciphertexts."""
+        import torch
+        wo = count * 2 * level_out * self.n
+        out = torch.empty(wo, dtype=torch.int64, device=ct_in.device) if out is None else out
+        _check(_lib.hc_mod_switch(self.h, _dev(ct_in, count * 2 * level_in * self.n, "ct_in"), count, level_in,
+                                  level_out, _dev(out, wo, "out"), _stream(stream)), "hc_mod_switch")
         return out
 
     def rotate_hoisted(self, gk, elements, ct_in, stream=None):
@@ -443,17 +479,20 @@ class Server:
     """Serving loop (hc_server_*): submit queries as they arrive, poll completions.
     Keeps every submitted request's device tensors alive until it is polled."""
 
-    def __init__(self, ctx, gk, db, comp_level=0, lane_bytes=8 << 30, lanes=2, max_batch=16):
+    def __init__(self, ctx, gk, db, comp_level=0, lane_bytes=8 << 30, lanes=2, max_batch=16, out_level=0):
         self.ctx, self.gk, self.db = ctx, gk, db
         h = c_vp()
-        _check(_lib.hc_server_create(ctx.h, gk.h, db.h if db is not None else None, comp_level, lane_bytes, lanes,
-                                     max_batch, ctypes.byref(h)), "hc_server_create")
+        _check(_lib.hc_server_create(ctx.h, gk.h, db.h if db is not None else None, comp_level, out_level,
+                                     lane_bytes, lanes, max_batch, ctypes.byref(h)), "hc_server_create")
         self.h = h
         self._live = {}
 
-    def submit(self, ct_v, N, t_bound, out):
+    def submit(self, ct_v, N, t_bound, out, stream=None):
+        """ct_v may still be in flight on `stream` (torch's current stream by default)."""
         rid = ctypes.c_uint64(0)
-        _check(_lib.hc_server_submit(self.h, _dev(ct_v), N, t_bound, _dev(out), ctypes.byref(rid)),
+        c = self.ctx
+        _check(_lib.hc_server_submit(self.h, _dev(ct_v, c.ct_words(N), "ct_v"), N, t_bound,
+                                     _dev(out, 2 * c.L * c.n, "out"), _stream(stream), ctypes.byref(rid)),
                "hc_server_submit")
         self._live[rid.value] = (ct_v, out)
         return rid.value

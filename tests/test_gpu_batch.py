@@ -48,23 +48,31 @@ def run_batch_vs_single(ring_name, specs, ncol, seed, values="zp"):
 
 
 def test_batch_equals_single_and_oracle_small_ring():
-    from oracle import bfv, compress as C, slots
+    """Every query of an uneven batch equals its compression alone and the oracle's."""
+    from tests.oracle_runs import oracle_outputs
     say("batch small ring")
     specs = [(3 * 2048, 5), (7 * 2048, 13), (1000, 1), (7 * 2048 - 100, 30), (2048, 0 + 2)]
     ctx, sk, gk, dbh, db, qs, outs, infos = run_batch_vs_single("ring-2048-p12289", specs, 4, 21)
-    pr = oracle_params("ring-2048-p12289")
-    osk, opk = bfv.keygen(pr, W.seed32("sk", 21))
-    keys = set()
-    for N, t in specs:
-        keys.update(C.make_schedule(pr.n, pr.p, N, 4, t).keys)
-    gks = {k: bfv.galois_keygen(pr, osk, k, W.seed32("gk", 21)) for k in keys}
-    for qi in (0, 2):
-        q = qs[qi]
-        sched = C.make_schedule(pr.n, pr.p, q["N"], 4, q["t"])
-        vm = slots.vector_to_slot_matrices(q["v"], pr.n, sched.n_ct)
-        octs = [bfv.encrypt(pr, opk, vm[i], W.seed32("enc", 21, qi, i)) for i in range(sched.n_ct)]
-        want = C.compress(pr, sched, octs, db, gks, level=infos[qi]["level"])
-        assert np.array_equal(to_host(ctx.output(outs[qi], infos[qi])), want.stack()), qi
+    want = oracle_outputs("ring-2048-p12289", specs, 4, 21, db)
+    for qi in range(len(specs)):
+        assert np.array_equal(to_host(ctx.output(outs[qi], infos[qi])), want[qi]), qi
+
+
+def test_batch_one_prime_answers_match_oracle():
+    """A batch whose answers are switched to one prime (Sec. 6.2's answer form)."""
+    from paper_2408_17063_amd import hc
+    from tests.oracle_runs import oracle_outputs
+    say("batch one-prime answers")
+    specs = [(2 * 2048, 4), (7 * 2048, 9), (1500, 2)]
+    ctx = context("ring-2048-p12289")
+    sk, pk, gk, dbh, db, qs = make_queries(ctx, "ring-2048-p12289", specs, 4, 24)
+    outs = [ctx.ct_tensor(1)[0] for _ in qs]
+    st, statuses, infos = ctx.compress_batch(gk, dbh, [(q["cts"], q["N"], q["t"], o) for q, o in zip(qs, outs)],
+                                             out_level=1)
+    assert st == hc.HC_OK and all(i["level"] == 1 for i in infos)
+    want = oracle_outputs("ring-2048-p12289", specs, 4, 24, db, out_level=1)
+    for qi in range(len(specs)):
+        assert np.array_equal(to_host(ctx.output(outs[qi], infos[qi])), want[qi]), qi
 
 
 def test_batch_uneven_queries_ring_32768():

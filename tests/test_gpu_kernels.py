@@ -201,3 +201,58 @@ def test_diagonal_encoding_matches_oracle(ring, s, B, beta, gi, b):
     m = bfv.plain_poly(pr, C.diagonal_slots(pr.p, pr.nh, s, B, beta, gi, b))
     from oracle.ring import Poly
     assert np.array_equal(to_host(out), Poly.from_ints(pr.q, m).c)
+
+
+@pytest.mark.parametrize("ring", ["ring-2048-p12289", "ring-4096"])
+def test_mod_switch_and_rotate_level_match_oracle(ring):
+    """hc_mod_switch for every level pair (each kept-prime count, several ciphertexts
+    in one call) and hc_rotate_level at every digit-aligned level below the top, element
+    by element against the oracle; each switched ciphertext still decrypts to the slots."""
+    from oracle import bfv
+    ctx = context(ring)
+    pr = oracle_params(ring)
+    say("switch and level rotation", ring)
+    r = np.random.default_rng(11)
+    sk_seed, gk_seed = W.seed32("sk", 3), W.seed32("gk", 3)
+    k = pow(3, 5, 2 * pr.n)
+    osk, opk, ogk = oracle_keys(pr, sk_seed, gk_seed, [k])
+    sk, pk = ctx.keygen(sk_seed)
+    gk = ctx.galois_keygen(sk, [k], gk_seed)
+    slots = [r.integers(0, pr.p, size=(2, pr.nh)) for _ in range(2)]
+    cts = ctx.ct_tensor(2)
+    octs = []
+    for i in range(2):
+        ctx.encrypt(pk, slots[i], W.seed32("enc", 30, i), out=cts[i])
+        octs.append(bfv.encrypt(pr, opk, slots[i], W.seed32("enc", 30, i)))
+    for lin in range(2, pr.L + 1):
+        src = cts[:, :, :lin, :].contiguous() if lin < pr.L else cts
+        pin = bfv.at_level(pr, lin, keyswitch=False)
+        osrc = [o if lin == pr.L else bfv.mod_switch(pr, o, lin) for o in octs]
+        if lin < pr.L:
+            # the oracle's own switch to lin is the input: feed the library the same words
+            import torch
+            src = torch.from_numpy(np.stack([o.stack() for o in osrc]).view(np.int64)).cuda()
+        for lo in range(1, lin):
+            got = to_host(ctx.mod_switch(src, lin, lo, count=2)).reshape(2, 2, lo, pr.n)
+            for i in range(2):
+                want = bfv.mod_switch(pin, osrc[i], lo)
+                assert np.array_equal(got[i], want.stack()), (lin, lo, i)
+                assert np.array_equal(ctx.decrypt(sk, got[i]), slots[i]), (lin, lo, i)
+    for lvl in range(pr.alpha, pr.L, pr.alpha):
+        lo_ct = bfv.mod_switch(pr, octs[0], lvl)
+        plo = bfv.at_level(pr, lvl)
+        want = bfv.rotate(plo, lo_ct, bfv.key_at_level(pr, ogk[k], lvl))
+        got = to_host(ctx.rotate_level(gk, k, lvl, to_dev(lo_ct.stack())))
+        assert np.array_equal(got.reshape(2, lvl, pr.n), want.stack()), lvl
+        assert np.array_equal(ctx.decrypt(sk, got), np.roll(slots[0], -5, axis=1)), lvl
+
+
+def test_mod_switch_rejects_bad_levels():
+    from paper_2408_17063_amd import hc
+    ctx = context("ring-2048-p12289")
+    say("switch errors")
+    ct = ctx.ct_tensor(1)
+    for lin, lo in ((4, 4), (4, 0), (5, 2), (2, 3)):
+        with pytest.raises(hc.HcError) as e:
+            ctx.mod_switch(ct, lin, lo, out=ctx.ct_tensor(1))
+        assert e.value.status == hc.HC_EINVAL, (lin, lo)

@@ -1,6 +1,6 @@
 """The serving loop (hc_server_*): requests submitted as they arrive are answered by
 continuous batching, and every result is bit-identical to the same query
-compressed alone."""
+compressed alone and to the oracle's compression of that query."""
 import time
 
 import numpy as np
@@ -13,18 +13,22 @@ from tests.test_gpu_batch import make_queries
 pytestmark = pytest.mark.gpu
 
 
-def run_server(ring, specs, ncol, seed, values, delays_ms, lanes=2, max_batch=4, prepare=True):
+def run_server(ring, specs, ncol, seed, values, delays_ms, lanes=2, max_batch=4, prepare=True, out_level=0):
     from paper_2408_17063_amd import hc
+    from tests.oracle_runs import oracle_outputs
     ctx = context(ring)
     sk, pk, gk, dbh, db, qs = make_queries(ctx, ring, specs, ncol, seed, values)
+    oracle = oracle_outputs(ring, specs, ncol, seed, db, out_level=out_level or None)
     alone = []
     for q in qs:
-        o, info = ctx.compress(gk, dbh, q["cts"], q["N"], q["t"])
+        o, info = ctx.compress(gk, dbh, q["cts"], q["N"], q["t"], out_level=out_level)
         alone.append((to_host(ctx.output(o, info)), info))
+    for (want, _), ow in zip(alone, oracle):
+        assert np.array_equal(want, ow)
     if prepare:
         for N, t in specs:
             ctx.diag_prepare(N, ncol, t)
-    srv = hc.Server(ctx, gk, dbh, lane_bytes=2 << 30, lanes=lanes, max_batch=max_batch)
+    srv = hc.Server(ctx, gk, dbh, lane_bytes=2 << 30, lanes=lanes, max_batch=max_batch, out_level=out_level)
     try:
         outs = [ctx.ct_tensor(1)[0] for _ in qs]
         ids = []
@@ -42,12 +46,14 @@ def run_server(ring, specs, ncol, seed, values, delays_ms, lanes=2, max_batch=4,
         srv.close()
         ctx.diag_release()
     assert len(results) == len(ids)
-    for rid, o, (want, ainfo) in zip(ids, outs, alone):
+    for qi, (rid, o, (want, ainfo)) in enumerate(zip(ids, outs, alone)):
         r = results[rid]
         assert r["status"] == hc.HC_OK
         assert r["submit_ns"] <= r["start_ns"] <= r["done_ns"]
         assert r["info"]["level"] == ainfo["level"] and r["info"]["s"] == ainfo["s"]
-        assert np.array_equal(to_host(ctx.output(o, r["info"])), want), rid
+        got = to_host(ctx.output(o, r["info"]))
+        assert np.array_equal(got, want), rid
+        assert np.array_equal(got, oracle[qi]), rid
     return stats, results
 
 
@@ -72,6 +78,14 @@ def test_server_on_the_fly_diagonals_and_one_lane():
     stats, _ = run_server("ring-2048-p12289", specs, 4, 32, "zp", [0, 0, 1.0, 0], lanes=1, max_batch=3,
                           prepare=False)
     assert stats["completed"] == len(specs) and stats["max_lanes_busy"] == 1
+
+
+def test_server_one_prime_answers():
+    """Answers switched to one prime after the merge, served in a mix."""
+    say("server one-prime answers")
+    specs = [(3 * 2048, 5), (7 * 2048, 13), (2048, 2), (5 * 2048, 9), (6 * 2048, 3)]
+    stats, _ = run_server("ring-2048-p12289", specs, 4, 33, "zp", [0, 0, 0, 2.0, 0], out_level=1)
+    assert stats["completed"] == len(specs)
 
 
 def test_server_rejects_bad_requests():

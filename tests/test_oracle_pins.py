@@ -363,6 +363,12 @@ def test_vandermonde_product_definition():
     x = [3, 0, 7, 1, 0, 96]
     want = [sum((i + 1) ** j * x[i] for i in range(len(x))) % p for j in range(1, s + 1)]
     assert C.vandermonde_product(p, s, x) == want
+    assert C.vandermonde_product_sparse(p, s, x) == want
+    # a long sparse vector: the sparse form equals the dense definition
+    r = np.random.default_rng(12)
+    v = np.zeros(5000, dtype=np.int64)
+    v[r.choice(5000, 40, replace=False)] = r.integers(1, 786433, 40)
+    assert C.vandermonde_product_sparse(786433, 64, v) == C.vandermonde_product(786433, 64, v)
 
 
 # --------------------------------------------------------------------------- schedule
@@ -472,6 +478,45 @@ def test_mod_switch_divides_by_dropped_primes(p4096):
             got = exact_crt(comp_lo.c[:, coef], plo.q)
             want = c // D
             assert any(got == (want - u) % plo.Q for u in range(2))
+
+
+def test_answer_switch_to_one_prime(p4096):
+    """The answer's switch to one prime (Sec. 6.2 counts the answer as one ciphertext
+    modulo one prime): from a Comp-level ciphertext at 2 primes down to 1, the result
+    is floor(c / q_2) up to a conversion overflow in [0, 1), i.e. exactly the floor,
+    and decrypts under q_1 alone to the same slots; a whole compression switched this
+    way decrypts to the Vandermonde products."""
+    pr = make_params(4096, 65537, 4, 54, 2, 60)
+    sk, pk = bfv.keygen(pr, bytes(32))
+    sl = np.random.default_rng(10).integers(0, pr.p, size=(2, pr.nh))
+    ct = bfv.mod_switch(pr, bfv.encrypt(pr, pk, sl, bytes([5] * 32)), 2)
+    p2 = bfv.at_level(pr, 2)
+    one = bfv.mod_switch(p2, ct, 1)
+    p1 = bfv.at_level(pr, 1, keyswitch=False)
+    assert np.array_equal(bfv.decrypt(p1, sk, one), sl)
+    for comp, comp1 in ((ct.c0, one.c0), (ct.c1, one.c1)):
+        for coef in range(0, pr.n, 131):
+            c = exact_crt(comp.c[:, coef], p2.q)
+            assert int(comp1.c[0, coef]) == (c // pr.q[1]) % pr.q[0]
+    # end to end with out_level = 1
+    import workloads as W
+    wl = W.WORKLOADS["multi-2048"]
+    ring = W.RINGS[wl.ring]
+    pr = make_params(ring.n, ring.p, ring.L, ring.q_bits, ring.K, ring.p_bits)
+    v, db = W.query_inputs(wl)
+    sc = C.make_schedule(pr.n, pr.p, wl.N, wl.ncol, wl.t)
+    sk, pk = bfv.keygen(pr, W.seed32("sk", 0))
+    gks = {k: bfv.galois_keygen(pr, sk, k, W.seed32("gk", k)) for k in sc.keys}
+    vm = slots.vector_to_slot_matrices(v, pr.n, sc.n_ct)
+    cts = [bfv.encrypt(pr, pk, vm[i], W.seed32("enc", i)) for i in range(sc.n_ct)]
+    out = C.compress(pr, sc, cts, db, gks, out_level=1)
+    assert len(out.c0.mods) == 1
+    p1 = bfv.at_level(pr, 1, keyswitch=False)
+    assert bfv.noise_bits(p1, sk, out) < bfv.noise_budget_bits(p1) - 8
+    dec = bfv.decrypt(p1, sk, out)
+    exp = C.expected_bands(sc, v, db)
+    for b in range(sc.bands):
+        assert C.band_slots(sc, dec, b) == exp[b]
 
 
 def test_restricted_key_switches_at_lower_level():

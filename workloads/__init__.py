@@ -65,6 +65,9 @@ WORKLOADS = {
     "tiny-1024": Workload("tiny-1024", "ring-1024-p12289", 1024, 5, 1, "zp"),
     # s = 64, B = 8, 2 u-blocks: 16 diagonal terms per sum, more than one fold at 60 bits
     "fold-1024-q60": Workload("fold-1024-q60", "ring-1024-q60", 1024, 40, 1, "zp"),
+    # the large workload's ring and moduli with one ciphertext of records and t = 16:
+    # small enough for a whole compression on the CPU
+    "reduced-65536": Workload("reduced-65536", "ring-65536", 1 << 16, 16, 4, "u16"),
 }
 
 
