@@ -455,6 +455,33 @@ def serving(st, rates, requests, lane_gb=40, lanes=2, max_batch=16):
     return res
 
 
+def ntt_probe(wl_name, reps):
+    """Forward and inverse transforms of [64][3][n] (the Comp level's key-switching
+    batches) on random canonical residues; prints the mean time per launch pair."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2408_17063_amd import hc
+    r = W.RINGS[W.WORKLOADS[wl_name].ring]
+    ctx = hc.Context(log_n=int(math.log2(r.n)), p=r.p, L=r.L, q_bits=r.q_bits, K=r.K, p_bits=r.p_bits)
+    rng = np.random.default_rng(0)
+    host = np.stack([rng.integers(0, q, size=(64, ctx.n), dtype=np.uint64) for q in ctx.primes[:3]], axis=1)
+    x = torch.from_numpy(host.view(np.int64)).cuda()
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    for _ in range(reps):
+        ctx.ntt(x, 0, 3)
+        ctx.ntt(x, 0, 3, inverse=True)
+    torch.cuda.synchronize()
+    ok = bool(np.array_equal(x.cpu().numpy().view(np.uint64), host))
+    f, i = ctx.timing_read(hc.KT_NTT_FWD), ctx.timing_read(hc.KT_NTT_INV)
+    ctx.timing(False)
+    print(json.dumps({"ntt_probe": {"shape": [64, 3, ctx.n], "reps": reps, "roundtrip_exact": ok,
+                                    "forward_us": round(f["ms"] * 1e3 / reps, 2),
+                                    "inverse_us": round(i["ms"] * 1e3 / reps, 2),
+                                    "butterflies_per_transform": f["ops"] / reps}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -480,6 +507,10 @@ def main():
     ap.add_argument("--serve-max-batch", type=int, default=16, help="queries per server batch")
     ap.add_argument("--on-the-fly-steps", type=int, default=2,
                     help="with resident diagonals, also time this many steps encoding them on the fly")
+    ap.add_argument("--ntt-probe", type=int, default=0,
+                    help="only run this many forward + inverse transforms of the compression's most common "
+                         "NTT shape (64 polynomials x 3 primes at the workload's ring) and exit: a short "
+                         "program for counter collection")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the compression path here is built and measured on a single "
@@ -488,6 +519,9 @@ def main():
 
     import torch
     from paper_2408_17063_amd import hc
+    if args.ntt_probe:
+        ntt_probe(args.workload, args.ntt_probe)
+        return
     st = setup(args.workload)
     ctx, wl = st["ctx"], st["wl"]
     out = ctx.ct_tensor(1)[0]
