@@ -54,7 +54,8 @@ typedef enum {
     HC_EDEVICE = -3,  /* a HIP call failed */
     HC_ENOKEY = -4,   /* a rotation needs a Galois key that the key set lacks */
     HC_EDECODE = -5,  /* decompression failed: more than s matches or an inconsistent input */
-    HC_ENOISE = -6    /* decryption rounding is ambiguous (noise at the budget) */
+    HC_ENOISE = -6,   /* decryption rounding is ambiguous (noise at the budget) */
+    HC_ESCRATCH = -7  /* an allocation-free call needs more than its fixed device scratch */
 } hc_status;
 
 typedef struct {

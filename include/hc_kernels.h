@@ -49,6 +49,25 @@ hc_status hc_rotate(hc_context* ctx, const hc_gk* gk, uint32_t element, const ui
 hc_status hc_rotate_level(hc_context* ctx, const hc_gk* gk, uint32_t element, uint32_t level,
                           const uint64_t* ct_in, uint64_t* ct_out, hipStream_t stream);
 
+/* hc_rotate_level without any allocation, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and bit-identical results, but every temporary
+ * lives in one fixed device array of HC_NOALLOC_SCRATCH_BYTES that the library
+ * holds on each GPU it runs on until the process ends (found at hc_context_create).
+ * The caller passes the input and output as for hc_rotate_level; the call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine) and
+ * synchronises `stream` before returning. A rotation at `level` needs
+ * 8 n (7 level + (level / K) (level + K) + 2 K) bytes plus alignment; larger
+ * calls fail with HC_ESCRATCH (ring 2^16 with 3 special primes: levels up to 9,
+ * which covers the compression's Comp level; ring 2^15 with 2: every level up to
+ * 14). Every call on one GPU shares that GPU's array, so calls that overlap on
+ * one GPU (other streams, threads or contexts) race; serialise them. No word of
+ * the array needs to start at zero: a call reads only what it wrote first.
+ * Errors: as hc_rotate_level, HC_ESCRATCH, HC_EDEVICE (no scratch on the device). */
+#define HC_NOALLOC_SCRATCH_BYTES (64ull << 20)
+hc_status hc_rotate_level_noalloc(hc_context* ctx, const hc_gk* gk, uint32_t element, uint32_t level,
+                                  const uint64_t* ct_in, uint64_t* ct_out, hipStream_t stream);
+
 /* Modulus switching (the BFV form of the paper's move to smaller parameters,
  * Sec. 5.3, and of its single-prime answer, Sec. 6.2): drop the primes
  * level_out..level_in-1 of `count` ciphertexts. With D the product of the dropped

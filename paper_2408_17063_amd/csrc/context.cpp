@@ -16,6 +16,12 @@ hc_status fail_hip(hipError_t e, const char* what, const char* file, int line) {
     return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? HC_ENOMEM : HC_EDEVICE;
 }
 
+// Device scratch of the allocation-free entry points (hc_rotate_level_noalloc): one
+// copy per GPU, loaded with the code object and held until the process ends. Host
+// code reaches it only through the address hipGetSymbolAddress returns for the
+// current device (kept per context); the symbol itself is not a device address.
+static __device__ __align__(256) uint64_t scratch[HC_NOALLOC_SCRATCH_BYTES / sizeof(uint64_t)];
+
 hc_status Arena::reserve(size_t bytes) {
     if (bytes <= cap) { used = 0; return HC_OK; }
     release();
@@ -375,6 +381,17 @@ extern "C" hc_status hc_context_create(const hc_params* prm, int device, hc_cont
     UP(c.d_pmodq, pmodq);
     UP(c.d_delta, delta);
 #undef UP
+    // the allocation-free scratch of this device (the device is current here)
+    {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fprintf(stderr, "libhc: no allocation-free scratch on device %d: %s\n", device, hipGetErrorString(e));
+            ptr = nullptr;
+        }
+        c.d_scratch = (uint64_t*)ptr;
+    }
     if ((st = ntt_build_tw2(c)) != HC_OK) { hc_context_destroy(cp); return st; }
     if ((st = build_ms_tables(c)) != HC_OK) { hc_context_destroy(cp); return st; }
     if ((st = upload_keccak_constants(rc, rho, c.h_cdt.data())) != HC_OK) { hc_context_destroy(cp); return st; }
@@ -437,6 +454,7 @@ extern "C" const char* hc_status_str(hc_status s) {
         case HC_ENOKEY: return "missing Galois key";
         case HC_EDECODE: return "decoding failed";
         case HC_ENOISE: return "noise at the decryption budget";
+        case HC_ESCRATCH: return "call exceeds the fixed allocation-free scratch";
     }
     return "unknown status";
 }

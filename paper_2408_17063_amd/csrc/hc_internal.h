@@ -107,6 +107,8 @@ struct hc_context {
     struct DiagTab { uint32_t kb = 0; uint64_t* d = nullptr; size_t bytes = 0; };
     std::map<std::tuple<uint32_t, uint32_t, int>, DiagTab> diag_tabs;
 
+    uint64_t* d_scratch = nullptr;  // this device's fixed allocation-free scratch (context.cpp)
+
     hc::Lane lane;     // workspace and staging of the context's own entry points
     std::mutex lazy_mu;  // guards the lazily built tables (prefix masks, switch tables)
     std::vector<void*> owned;  // device allocations freed at destroy

@@ -639,6 +639,39 @@ extern "C" hc_status hc_rotate_level(hc_context* cp, const hc_gk* gk, uint32_t e
     return rotate_common(cp, gk, &element, 1, ct_in, ct_out, false, (int)level, st);
 }
 
+extern "C" hc_status hc_rotate_level_noalloc(hc_context* cp, const hc_gk* gk, uint32_t element, uint32_t level,
+                                             const uint64_t* ct_in, uint64_t* ct_out, hipStream_t st) {
+    if (!cp || !gk || !ct_in || !ct_out || ct_in == ct_out) return HC_EINVAL;
+    Ctx& c = *cp;
+    const int Lc = (int)level;
+    if (Lc < c.alpha || Lc > c.L || Lc % c.alpha) return HC_EINVAL;
+    const uint64_t* key = find_key(gk, element);
+    if (!key) return HC_ENOKEY;
+    if (!c.d_scratch) return HC_EDEVICE;
+    HC_CHECK(hipSetDevice(c.device));
+    const size_t Ln2 = 2 * (size_t)Lc * c.n;
+    // the input in the NTT domain, then one job's key-switching scratch, all carved
+    // from the fixed array (an arena over it: take() only hands out offsets)
+    Arena a;
+    a.base = reinterpret_cast<char*>(c.d_scratch);
+    a.cap = HC_NOALLOC_SCRATCH_BYTES;
+    if (ks_scratch_bytes(c, Lc, 1) + sizeof(uint64_t) * Ln2 + 256 > a.cap) return HC_ESCRATCH;
+    uint64_t* inN = a.take<uint64_t>(Ln2);
+    KsScratch s = ks_scratch(c, a, Lc, 1);
+    if (!inN || !s.tmpC || !s.X || !s.T || !s.conv) return HC_ESCRATCH;
+    stage_reset(c.lane, st);  // job tables go through the context's pinned staging area
+    HC_CHECK(hipMemcpyAsync(inN, ct_in, sizeof(uint64_t) * Ln2, hipMemcpyDeviceToDevice, st));
+    ntt64(c, inN, (size_t)Lc * c.n, 2, 0, Lc, false, st);
+    // the result goes to the caller's output in the NTT domain and is transformed there
+    std::vector<KsJob> jobs{KsJob{inN, ct_out, key, element, 0}};
+    hc_status stt = ks_run(c, c.lane, s, jobs, nullptr, Lc, st);
+    if (stt != HC_OK) return stt;
+    ntt64(c, ct_out, (size_t)Lc * c.n, 2, 0, Lc, true, st);
+    HC_CHECK(hipGetLastError());
+    HC_CHECK(hipStreamSynchronize(st));
+    return HC_OK;
+}
+
 extern "C" hc_status hc_rotate_hoisted(hc_context* cp, const hc_gk* gk, const uint32_t* elements,
                                        uint32_t count, const uint64_t* ct_in, uint64_t* cts_out,
                                        hipStream_t st) {

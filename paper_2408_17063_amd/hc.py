@@ -27,7 +27,8 @@ c_u64p = ctypes.POINTER(ctypes.c_uint64)
 c_i64p = ctypes.POINTER(ctypes.c_int64)
 c_vp = ctypes.c_void_p
 
-HC_OK, HC_EINVAL, HC_ENOMEM, HC_EDEVICE, HC_ENOKEY, HC_EDECODE, HC_ENOISE = 0, -1, -2, -3, -4, -5, -6
+HC_OK, HC_EINVAL, HC_ENOMEM, HC_EDEVICE, HC_ENOKEY, HC_EDECODE, HC_ENOISE, HC_ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class HcError(RuntimeError):
@@ -102,6 +103,7 @@ _sig("hc_decompress", _st, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ct
 _sig("hc_ntt", _st, c_vp, c_vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, c_vp)
 _sig("hc_rotate", _st, c_vp, c_vp, ctypes.c_uint32, c_vp, c_vp, c_vp)
 _sig("hc_rotate_level", _st, c_vp, c_vp, ctypes.c_uint32, ctypes.c_uint32, c_vp, c_vp, c_vp)
+_sig("hc_rotate_level_noalloc", _st, c_vp, c_vp, ctypes.c_uint32, ctypes.c_uint32, c_vp, c_vp, c_vp)
 _sig("hc_mod_switch", _st, c_vp, c_vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, c_vp, c_vp)
 _sig("hc_rotate_hoisted", _st, c_vp, c_vp, c_u32p, ctypes.c_uint32, c_vp, c_vp, c_vp)
 _sig("hc_mul_plain", _st, c_vp, c_vp, c_u32p, c_vp, c_vp)
@@ -140,7 +142,7 @@ EXPORTED = [
     "hc_keygen",
     "hc_sk_destroy", "hc_pk_destroy", "hc_galois_keygen", "hc_gk_destroy", "hc_plan",
     "hc_db_upload", "hc_db_destroy", "hc_encrypt", "hc_compress", "hc_compress_batch",
-    "hc_decrypt", "hc_decompress", "hc_ntt", "hc_rotate", "hc_rotate_level", "hc_mod_switch",
+    "hc_decrypt", "hc_decompress", "hc_ntt", "hc_rotate", "hc_rotate_level", "hc_rotate_level_noalloc", "hc_mod_switch",
     "hc_rotate_hoisted", "hc_mul_plain",
     "hc_modup", "hc_moddown", "hc_sample", "hc_encode_diagonal", "hc_export_sk", "hc_export_pk",
     "hc_export_gk", "hc_timing_enable", "hc_timing_read", "hc_probe_mul32_rate", "hc_probe_copy",
@@ -344,6 +346,14 @@ class Context:
         out = torch.empty(w, dtype=torch.int64, device=ct_in.device) if out is None else out
         _check(_lib.hc_rotate_level(self.h, gk.h, element, level, _dev(ct_in, w, "ct_in"), _dev(out, w, "out"),
                                     _stream(stream)), "hc_rotate_level")
+        return out
+
+    def rotate_level_noalloc(self, gk, element, level, ct_in, out, stream=None):
+        """hc_rotate_level through the allocation-free entry point (out is required:
+        the call allocates nothing, so neither does this wrapper)."""
+        w = 2 * level * self.n
+        _check(_lib.hc_rotate_level_noalloc(self.h, gk.h, element, level, _dev(ct_in, w, "ct_in"),
+                                            _dev(out, w, "out"), _stream(stream)), "hc_rotate_level_noalloc")
         return out
 
     def mod_switch(self, ct_in, level_in, level_out, count=1, out=None, stream=None):
