@@ -54,14 +54,11 @@ def setup(wl_name):
     return dict(ctx=ctx, sk=sk, pk=pk, gk=gk, db=dbh, cts=cts, v=v, dbv=db, wl=wl, info=info, keys=keys)
 
 
-# 32-bit integer multiply peak derived from the chip: 256 CUs x 4 SIMDs x 16 lanes
-# at 2.4 GHz = 39.3 T lane-operations/s for full-rate VALU work. On gfx950 the
-# 32 x 32 -> 64-bit multiply-add (v_mad_u64_u32) issues at full rate: the
-# library's register-only probe (hc_probe_mul32_rate) measures ~35.5 T/s.
-MUL32_PEAK_T = 256 * 64 * 2.4e9 / 1e12
-# One lazy Shoup butterfly multiplies two 64-bit words: the high half of x*w'
-# needs 4 32x32 partial products, the low halves of x*w and qhat*q 3 each.
-MUL32_PER_BUTTERFLY = 10
+# VALU issue peak derived from the chip: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz =
+# 39.3 T lane-instructions/s (a 64-wide VALU instruction occupies a 16-lane SIMD for 4
+# cycles). The integer multiply-add the kernels use (v_mad_u64_u32) issues at that
+# rate: the library's register-only probe (hc_probe_mul32_rate) measures ~35.5 T/s.
+VALU_PEAK_T = 256 * 64 * 2.4e9 / 1e12
 
 
 def kernel_rooflines(ctx, hc):
@@ -74,11 +71,17 @@ def kernel_rooflines(ctx, hc):
         sec = t["ms"] / 1e3
         out[name] = dict(t, sec=sec)
     rl = {}
+    valu = ntt_valu_per_butterfly()
     for name, t in out.items():
         if name.startswith("ntt"):
-            ach = t["ops"] * MUL32_PER_BUTTERFLY / t["sec"] / 1e12
-            rl[name] = {"bound": "alu", "achieved": round(ach, 3), "peak": round(MUL32_PEAK_T, 3),
-                        "unit": "Tmul32/s", "frac": round(ach / MUL32_PEAK_T, 4), "traffic": None,
+            # VALU lane-instructions per butterfly counted by rocprofv3 (SQ_INSTS_VALU x 64
+            # over the transform's butterflies) for this direction, times the live rate
+            ipb = valu.get(name)
+            ach = ipb * t["ops"] / t["sec"] / 1e12 if ipb else None
+            rl[name] = {"bound": "alu", "achieved": round(ach, 3) if ach else None, "peak": round(VALU_PEAK_T, 3),
+                        "unit": "T VALU lane-instr/s", "frac": round(ach / VALU_PEAK_T, 4) if ach else None,
+                        "traffic": None, "valu_lane_instr_per_butterfly": ipb,
+                        "butterflies_per_s_T": round(t["ops"] / t["sec"] / 1e12, 4),
                         "avg_launch_us": round(t["ms"] * 1e3 / t["launches"], 2),
                         "launches": t["launches"], "ms": round(t["ms"], 2)}
         else:
@@ -88,6 +91,31 @@ def kernel_rooflines(ctx, hc):
                         "avg_launch_us": round(t["ms"] * 1e3 / t["launches"], 2),
                         "launches": t["launches"], "ms": round(t["ms"], 2)}
     return rl
+
+
+def sources_current(rec):
+    import hashlib
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest() == rec["sources_sha256"]
+
+
+def ntt_valu_per_butterfly():
+    """VALU lane-instructions per butterfly of each NTT direction, from the committed
+    rocprofv3 counter summary (SQ_INSTS_VALU of the NTT probe); empty when missing or
+    when ntt.hip changed since."""
+    path = os.path.join(ROOT, "profiles", "ntt_valu_large-65536.json")
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        rec = json.load(f)
+    if not sources_current(rec):
+        log("NTT counter summary is stale (ntt.hip changed): NTT roofline reported as null")
+        return {}
+    return {"ntt_forward": rec["forward"]["valu_lane_instr_per_butterfly"],
+            "ntt_inverse": rec["inverse"]["valu_lane_instr_per_butterfly"]}
 
 
 def measured_traffic(workload):
@@ -110,24 +138,20 @@ def measured_traffic(workload):
     return {k: v["traffic_bytes_per_launch"] for k, v in rec["kernels"].items()}
 
 
-def cpu_baseline(info):
-    """The CPU oracle on a bounded sample of the same workload, scaled by the step's
-    operation counts. The oracle runs the same schedule as the library: Mask at the
-    full modulus, a modulus switch of each ciphertext, then the rest at the Comp
-    level. Sample: one Mask product and one modulus switch at the full modulus; one
-    rotation (key switch), one diagonal encoding and one diagonal product at the Comp
-    level; all at ring 2^16."""
+def _cpu_sample(args):
+    """One worker of the CPU baseline: the oracle's keys and one ciphertext at ring
+    2^16, then one timed run of each sampled operation (single thread)."""
+    level, seed = args
     import numpy as np
     import workloads as W
     from oracle import bfv, compress as C
     from oracle.params import make_params
     r = W.RINGS["ring-65536"]
     pr = make_params(r.n, r.p, r.L, r.q_bits, r.K, r.p_bits)
-    level = info["level"]
-    sk, pk = bfv.keygen(pr, W.seed32("sk", 0))
+    sk, pk = bfv.keygen(pr, W.seed32("sk", seed))
     k = bfv.rot_row_element(pr, 8)
-    gk = bfv.galois_keygen(pr, sk, k, W.seed32("gk", 0))
-    ct = bfv.encrypt(pr, pk, np.zeros((2, pr.nh), dtype=np.uint64), W.seed32("enc", 0, 0))
+    gk = bfv.galois_keygen(pr, sk, k, W.seed32("gk", seed))
+    ct = bfv.encrypt(pr, pk, np.zeros((2, pr.nh), dtype=np.uint64), W.seed32("enc", seed, 0))
     dbm = bfv.plain_poly(pr, C.db_slots(np.arange(pr.n, dtype=np.uint32) % 65536, pr.n, 0))
     t = {}
     t0 = time.perf_counter()
@@ -147,19 +171,62 @@ def cpu_baseline(info):
     t0 = time.perf_counter()
     bfv.mul_plain(plo, lo, m)
     t["ptct"] = time.perf_counter() - t0
+    return t
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
+def cpu_baseline(info):
+    """The CPU oracle on a bounded sample of the same workload, run on the host's cores.
+
+    The oracle runs the same schedule as the library: Mask at the full modulus, a
+    modulus switch of each ciphertext, then the rest at the Comp level. Sample: one
+    Mask product and one modulus switch at the full modulus; one rotation (key switch),
+    one diagonal encoding and one diagonal product at the Comp level; all at ring 2^16.
+    The compression's operations are independent across ciphertexts, limbs and
+    rotations of one phase, so the oracle parallelises over them: P worker processes
+    (one per usable core, at most 16) each run the sample at once, and the host's rate
+    is P compressions per the sample-scaled time of one (the workers' mean, measured
+    while all run). Labelled extrapolated: no whole compression is run."""
+    from multiprocessing import get_context
+    model, ncpu, usable = host_cpu()
+    P = max(1, min(16, usable))
+    level = info["comp_level"]
+    t_wall = time.perf_counter()
+    with get_context("spawn").Pool(P) as pool:
+        samples = pool.map(_cpu_sample, [(level, 1000 + i) for i in range(P)])
+    wall = time.perf_counter() - t_wall
+    t = {k: sum(x[k] for x in samples) / P for k in samples[0]}
     n_mask = 4 * 16                      # value columns x input ciphertexts
     n_switch = 16 * (1 + 4)
     per_query = (n_mask * t["mask"] + n_switch * t["switch"] + info["n_keyswitch"] * t["keyswitch"] +
                  info["n_diag"] * t["encode"] + (info["n_ptct"] - n_mask) * t["ptct"])
-    log("cpu oracle sample: %s -> %.0f s per compression" % ({a: round(b, 3) for a, b in t.items()}, per_query))
-    return {"value": 1.0 / per_query, "unit": "compressions/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle (single thread) timed at ring 2^16 on one Mask product and one modulus switch "
-                      "at 24 primes, and one rotation, one diagonal encoding and one diagonal product at "
-                      "%d primes (%s s), scaled by the step's %d Mask products, %d switches, %d key switches, "
-                      "%d diagonal encodings and %d other plaintext products"
-                      % (level, ", ".join("%s %.3f" % kv for kv in t.items()), n_mask, n_switch,
-                         info["n_keyswitch"], info["n_diag"], info["n_ptct"] - n_mask),
-            "extrapolated": True}
+    log("cpu oracle sample (%d workers, %.0fs): %s -> %.0f s per compression per core" % (
+        P, wall, {a: round(b, 3) for a, b in t.items()}, per_query))
+    return {"value": P / per_query, "unit": "compressions/s", "cores": P, "kind": "oracle",
+            "host_cpus": ncpu, "usable_cpus": usable, "cpu_model": model,
+            "sample": "oracle at ring 2^16 in %d parallel worker processes: one Mask product and one modulus "
+                      "switch at 24 primes, one rotation, one diagonal encoding and one diagonal product at %d "
+                      "primes per worker (mean %s s), scaled by the step's %d Mask products, %d switches, %d key "
+                      "switches, %d diagonal encodings and %d other plaintext products, times %d workers"
+                      % (P, level, ", ".join("%s %.3f" % kv for kv in t.items()), n_mask, n_switch,
+                         info["n_keyswitch"], info["n_diag"], info["n_ptct"] - n_mask, P),
+            "extrapolated": True, "wall_s": round(wall, 1)}
 
 
 def percentile(xs, q):
@@ -182,7 +249,7 @@ def encrypt_query(ctx, pk, v, n_ct, seed_ints):
     return cts
 
 
-def batched_large(st, Q, steps):
+def batched_large(st, Q, steps, out_level=0):
     """Q queries of the headline workload (own index vectors) in one hc_compress_batch."""
     import torch
     import workloads as W
@@ -193,20 +260,20 @@ def batched_large(st, Q, steps):
     for qi in range(Q):
         v, _ = W.query_inputs(wl, query=100 + qi)
         qs.append((encrypt_query(ctx, pk, v, st["cts"].shape[0], (100 + qi,)), wl.N, wl.t, ctx.ct_tensor(1)[0]))
-    ctx.compress_batch(st["gk"], st["db"], qs)  # warm-up (workspace)
+    ctx.compress_batch(st["gk"], st["db"], qs, out_level=out_level)  # warm-up (workspace)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ctx.timing(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(steps):
-        rc, stats, _ = ctx.compress_batch(st["gk"], st["db"], qs)
+        rc, stats, _ = ctx.compress_batch(st["gk"], st["db"], qs, out_level=out_level)
         assert rc == hc.HC_OK
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     for name, r in kernel_rooflines(ctx, hc).items():
-        log("  batched %-16s %8.1f ms per batch %6d launches  %s %.3f of peak" % (
+        log("  batched %-16s %8.1f ms per batch %6d launches  %s %s of peak" % (
             name, r["ms"] / steps, r["launches"] // steps, r["bound"], r["frac"]))
     ctx.timing(False)
     del qs
@@ -215,7 +282,34 @@ def batched_large(st, Q, steps):
             "unit": "compressions/s"}
 
 
-def on_the_fly(st, resident_out, steps, comp_level):
+def graph_leg(st, eager_out, steps, comp_level, out_level):
+    """The headline compression captured once into a HIP graph (hc_graph_create) and
+    replayed: same inputs, its output must equal the eager run's bit for bit."""
+    import torch
+    ctx, wl = st["ctx"], st["wl"]
+    gout = ctx.ct_tensor(1)[0]
+    t0 = time.perf_counter()
+    g = ctx.graph(st["gk"], st["db"], [(st["cts"], wl.N, wl.t, gout)], comp_level=comp_level, out_level=out_level)
+    cap_s = time.perf_counter() - t0
+    g.launch()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        g.launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    same = bool(torch.equal(gout, eager_out))
+    res = {"steps": steps, "ms_per_step": round(ms, 3), "value": round(1e3 / ms, 4), "unit": "compressions/s",
+           "nodes": g.nodes(), "capture_s": round(cap_s, 2), "equals_eager": same}
+    g.close()
+    del gout
+    return res
+
+
+def on_the_fly(st, resident_out, steps, comp_level, out_level=0):
     """The same compression with the resident tables released: every step encodes its
     diagonals itself. Its output must equal the resident run's bit for bit."""
     import torch
@@ -223,13 +317,14 @@ def on_the_fly(st, resident_out, steps, comp_level):
     ref = resident_out.clone()
     ctx.diag_release()
     out = ctx.ct_tensor(1)[0]
-    ctx.compress(st["gk"], st["db"], st["cts"], wl.N, wl.t, out=out, comp_level=comp_level)
+    ctx.compress(st["gk"], st["db"], st["cts"], wl.N, wl.t, out=out, comp_level=comp_level, out_level=out_level)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(steps):
-        _, info = ctx.compress(st["gk"], st["db"], st["cts"], wl.N, wl.t, out=out, comp_level=comp_level)
+        _, info = ctx.compress(st["gk"], st["db"], st["cts"], wl.N, wl.t, out=out, comp_level=comp_level,
+                               out_level=out_level)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
@@ -298,6 +393,21 @@ def mixed_batch(count=64):
     batch_ms = b0.elapsed_time(b1)
     same = all(torch.equal(ctx.output(out, info), ctx.output(ref, info))
                for (_, _, _, out), ref, info in zip(qs, singles, infos))
+    # the same batch captured once into a graph and replayed
+    gouts = [ctx.ct_tensor(1)[0] for _ in qs]
+    g = ctx.graph(gk, dbh, [(cts, N, t, o) for (cts, N, t, _), o in zip(qs, gouts)])
+    g.launch()
+    torch.cuda.synchronize()
+    b0.record(stream)
+    g.launch()
+    b1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = b0.elapsed_time(b1)
+    same_g = all(torch.equal(ctx.output(o, info), ctx.output(ref, info))
+                 for o, ref, info in zip(gouts, singles, g.infos))
+    graph_nodes = g.nodes()
+    g.close()
+    del gouts
     # the same queries with every class's diagonals resident
     t0p = time.perf_counter()
     held = 0
@@ -345,6 +455,9 @@ def mixed_batch(count=64):
            "sequential_ms": round(seq_ms, 2), "batched_ms": round(batch_ms, 2),
            "sequential_value": round(count / (seq_ms / 1e3), 3), "batched_value": round(count / (batch_ms / 1e3), 3),
            "speedup": round(seq_ms / batch_ms, 3), "unit": "compressions/s",
+           "graph_ms": round(graph_ms, 2), "graph_value": round(count / (graph_ms / 1e3), 3),
+           "graph_speedup": round(seq_ms / graph_ms, 3), "graph_nodes": graph_nodes,
+           "graph_equals_sequential": bool(same_g),
            "sequential_p50_ms": round(percentile(lat, 50), 2), "sequential_p99_ms": round(percentile(lat, 99), 2),
            "batch_equals_sequential": bool(same), "resident": resident}
     del qs, singles
@@ -353,7 +466,7 @@ def mixed_batch(count=64):
     return res
 
 
-def serving(st, rates, requests, lane_gb=40, lanes=2, max_batch=16):
+def serving(st, rates, requests, lane_gb=40, lanes=2, max_batch=16, out_level=0):
     """The serving configuration: a seeded Poisson stream of PDQ requests at the
     headline parameters (ring 2^16, 24 + 3 primes). Each request draws its record
     count from {2^15, 2^17, 2^20} (a prefix of the resident 2^20 x 4 database) and t
@@ -406,7 +519,7 @@ def serving(st, rates, requests, lane_gb=40, lanes=2, max_batch=16):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for N, t, cts in reqs:
-            ctx.compress(gk, st["db"], cts, N, t, out=out)
+            ctx.compress(gk, st["db"], cts, N, t, out=out, out_level=out_level)
         e1.record(stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1)
@@ -415,7 +528,8 @@ def serving(st, rates, requests, lane_gb=40, lanes=2, max_batch=16):
     plain_ms(warm)
     ctx.trim()
     torch.cuda.empty_cache()
-    srv = hc.Server(ctx, gk, st["db"], lane_bytes=int(lane_gb) << 30, lanes=lanes, max_batch=max_batch)
+    srv = hc.Server(ctx, gk, st["db"], lane_bytes=int(lane_gb) << 30, lanes=lanes, max_batch=max_batch,
+                    out_level=out_level)
     res = {"requests_per_rate": requests, "lanes": lanes, "lane_gb": lane_gb, "max_batch": max_batch,
            "galois_keys": len(keys), "resident_diagonal_gb": round(held / 1e9, 2), "setup_s": round(setup_s, 1),
            "rates": []}
@@ -452,6 +566,65 @@ def serving(st, rates, requests, lane_gb=40, lanes=2, max_batch=16):
         res["server_stats"] = srv.stats()
     finally:
         srv.close()
+    return res
+
+
+def small_config_latency(wl_name, reps=20, config=None):
+    """Latency of one compression of a smaller benchmark configuration (ring 4096:
+    configuration 1; ring 2^15: configuration 2), plain calls and graph replays, with
+    the answer decrypted to the Vandermonde products (Eq. (1)) once."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from oracle import compress as C
+    from paper_2408_17063_amd import hc
+    wl = W.WORKLOADS[wl_name]
+    r = W.RINGS[wl.ring]
+    ctx = hc.Context(log_n=int(math.log2(r.n)), p=r.p, L=r.L, q_bits=r.q_bits, K=r.K, p_bits=r.p_bits)
+    v, db = W.query_inputs(wl)
+    keys, info = ctx.plan(wl.N, wl.ncol, wl.t)
+    sk, pk = ctx.keygen(W.seed32("sk", 0))
+    gk = ctx.galois_keygen(sk, keys, W.seed32("gk", 0))
+    dbh = ctx.db_upload(db)
+    n_ct = -(-wl.N // ctx.n)
+    cts = encrypt_query(ctx, pk, v, n_ct, (0,))
+    out = ctx.ct_tensor(1)[0]
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        lat = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            lat.append(e0.elapsed_time(e1))
+        return lat
+
+    res = {"workload": wl_name, "config": config, "ring_degree": ctx.n, "records": wl.N, "t": wl.t}
+    try:
+        plain = timed(lambda: ctx.compress(gk, dbh, cts, wl.N, wl.t, out=out))
+        ref = out.clone()
+        _, info = ctx.compress(gk, dbh, cts, wl.N, wl.t, out=out)
+        sched = C.make_schedule(ctx.n, ctx.p, wl.N, wl.ncol, wl.t)
+        dec = ctx.decrypt(sk, ctx.output(out, info).cpu().numpy().view(np.uint64))
+        exp = C.expected_bands(sched, v, db)
+        ok = all(C.band_slots(sched, dec, b) == exp[b] for b in range(sched.bands))
+        gout = ctx.ct_tensor(1)[0]
+        g = ctx.graph(gk, dbh, [(cts, wl.N, wl.t, gout)])
+        graph = timed(lambda: g.launch())
+        same = bool(torch.equal(gout, ref))
+        res.update({"plain_p50_ms": round(percentile(plain, 50), 3), "plain_p99_ms": round(percentile(plain, 99), 3),
+                    "graph_p50_ms": round(percentile(graph, 50), 3), "graph_p99_ms": round(percentile(graph, 99), 3),
+                    "reps": reps, "key_switches": info["n_keyswitch"], "decrypts_to_vandermonde": bool(ok),
+                    "graph_equals_plain": same, "graph_nodes": g.nodes()})
+        g.close()
+    finally:
+        ctx.close()
+        torch.cuda.empty_cache()
     return res
 
 
@@ -507,6 +680,13 @@ def main():
     ap.add_argument("--serve-max-batch", type=int, default=16, help="queries per server batch")
     ap.add_argument("--on-the-fly-steps", type=int, default=2,
                     help="with resident diagonals, also time this many steps encoding them on the fly")
+    ap.add_argument("--out-level", type=int, default=1,
+                    help="primes of the answer (1: one prime, the answer form of Sec. 6.2; 0: the Comp level)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel variants")
+    ap.add_argument("--graph-steps", type=int, default=5,
+                    help="also time this many replays of the headline compression captured in a graph (0: skip)")
+    ap.add_argument("--small-configs", type=int, default=20,
+                    help="latency repetitions of the ring-4096 and ring-2^15 configurations (0: skip)")
     ap.add_argument("--ntt-probe", type=int, default=0,
                     help="only run this many forward + inverse transforms of the compression's most common "
                          "NTT shape (64 polynomials x 3 primes at the workload's ring) and exit: a short "
@@ -533,8 +713,16 @@ def main():
         prep = {"seconds": round(time.perf_counter() - t0, 3), "bytes": held}
         log("resident diagonals: %.2f GB prepared in %.2fs" % (held / 1e9, prep["seconds"]))
     info = st["info"]
+    ol = args.out_level
+    tune = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        tune = ctx.autotune(st["gk"], st["db"], st["cts"], wl.N, wl.t, args.comp_level)
+        tune["seconds"] = round(time.perf_counter() - t0, 2)
+        log("autotune:", tune)
     for _ in range(args.warmup):
-        _, info = ctx.compress(st["gk"], st["db"], st["cts"], wl.N, wl.t, out=out, comp_level=args.comp_level)
+        _, info = ctx.compress(st["gk"], st["db"], st["cts"], wl.N, wl.t, out=out, comp_level=args.comp_level,
+                               out_level=ol)
     torch.cuda.synchronize()
     ctx.timing(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -542,7 +730,7 @@ def main():
     e0.record(stream)
     step_ev = []
     for _ in range(args.steps):
-        ctx.compress(st["gk"], st["db"], st["cts"], wl.N, wl.t, out=out, comp_level=args.comp_level)
+        ctx.compress(st["gk"], st["db"], st["cts"], wl.N, wl.t, out=out, comp_level=args.comp_level, out_level=ol)
         ev = torch.cuda.Event(enable_timing=True)
         ev.record(stream)
         step_ev.append(ev)
@@ -565,8 +753,8 @@ def main():
     if args.copy_probe_mb:
         ctx.probe_copy(args.copy_probe_mb << 20)
     for name, r in rl.items():
-        log("  %-16s %8.1f ms %6d launches  %s %.3f of peak" % (name, r["ms"], r["launches"], r["bound"],
-                                                               r["frac"]))
+        log("  %-16s %8.1f ms %6d launches  %s %s of peak" % (name, r["ms"], r["launches"], r["bound"],
+                                                              r["frac"]))
     dominant = max(rl, key=lambda k: rl[k]["ms"])
     probe = ctx.probe_mul32_rate(50.0) / 1e12
     log("  32-bit multiply-add probe: %.2f T/s (derived peak %.2f T/s)" % (probe, MUL32_PEAK_T))
@@ -589,8 +777,11 @@ def main():
                    "records": wl.N, "t": wl.t, "ring_degree": ctx.n, "value_columns": wl.ncol,
                    "key_switches_per_step": st["info"]["n_keyswitch"],
                    "ptct_per_step": st["info"]["n_ptct"],
-                   "comp_level_primes": info["level"]},
+                   "comp_level_primes": info["comp_level"], "answer_primes": info["level"],
+                   "answer_bytes": 2 * info["level"] * ctx.n * 8},
     }
+    if tune is not None:
+        rec["autotune"] = tune
     rec["latency_ms"] = {"p50": round(percentile(lat, 50), 2), "p99": round(percentile(lat, 99), 2),
                          "kind": "plain, one query at a time"}
     if prep is not None:
@@ -598,20 +789,27 @@ def main():
         rec["diag_prepare"] = prep
     else:
         rec["config"]["diagonals"] = "encoded on the fly inside every step"
+    if args.graph_steps:
+        rec["graph"] = graph_leg(st, out, args.graph_steps, args.comp_level, ol)
+        log("graph replay: %s" % rec["graph"])
     if args.batch_queries:
-        rec["batched"] = batched_large(st, args.batch_queries, max(1, args.steps // 2))
+        rec["batched"] = batched_large(st, args.batch_queries, max(1, args.steps // 2), ol)
         log("batched %d queries: %.1f ms per batch, %.3f compressions/s" % (
             args.batch_queries, rec["batched"]["ms_per_batch"], rec["batched"]["value"]))
     if prep is not None and args.on_the_fly_steps:
-        rec["on_the_fly"] = on_the_fly(st, out, args.on_the_fly_steps, args.comp_level)
+        rec["on_the_fly"] = on_the_fly(st, out, args.on_the_fly_steps, args.comp_level, ol)
         log("diagonals on the fly: %.1f ms/step; output equals resident: %s" % (
             rec["on_the_fly"]["ms_per_step"], rec["on_the_fly"]["equals_resident"]))
+    if args.small_configs:
+        rec["small_configs"] = [small_config_latency("plain-4096", args.small_configs, 1),
+                                small_config_latency("single-32768", args.small_configs, 2)]
+        log("smaller configurations:", rec["small_configs"])
     if args.mixed_batch:
         rec["mixed_batch"] = mixed_batch(args.mixed_batch)
         log("mixed batch:", rec["mixed_batch"])
     if args.serve_rates:
         rec["serving"] = serving(st, [float(x) for x in args.serve_rates.split(",")], args.serve_requests,
-                                 lanes=args.serve_lanes, max_batch=args.serve_max_batch)
+                                 lanes=args.serve_lanes, max_batch=args.serve_max_batch, out_level=ol)
     rec["roofline"] = dict(rl[dominant], kernel=dominant)
     rec["rooflines"] = rl
     rec["mul32_probe_T"] = round(probe, 3)

@@ -203,6 +203,64 @@ typedef struct {
 hc_status hc_compress_batch(hc_context* ctx, const hc_gk* gk, const hc_db* db,
                             hc_query* q, uint32_t nq, hipStream_t stream);
 
+/* ------------------------------------------------------------------ captured compressions */
+
+typedef struct hc_graph hc_graph;
+
+/* Record the whole device work of hc_compress_batch(ctx, gk, db, q, nq) -- every
+ * phase of Mask and Comp for every query -- into one HIP graph, without running it.
+ * The schedule of a batch depends only on its queries' shapes (N, t_bound, levels),
+ * so the host-side planning is done once here: the graph owns its workspace and its
+ * tables, and reads each q[i].ct_v and writes each q[i].ct_out, whose addresses
+ * are fixed at creation. Each hc_graph_launch then recomputes the answers of
+ * whatever ciphertexts those buffers hold at that moment, bit-identical to
+ * hc_compress_batch on them. q[i].info and q[i].status are filled here. gk, db and
+ * resident diagonal tables (hc_diag_prepare) must stay unchanged while the graph
+ * exists. All queries must share one Comp level. Synchronises the device.
+ * Errors: as hc_compress_batch; HC_ENOMEM (the graph's workspace), HC_EDEVICE. */
+hc_status hc_graph_create(hc_context* ctx, const hc_gk* gk, const hc_db* db, hc_query* q, uint32_t nq,
+                          hc_graph** out);
+
+/* Enqueue one replay of the graph on `stream` and return. Launches of one graph use
+ * one workspace: order them (one stream, or synchronise in between). */
+hc_status hc_graph_launch(hc_graph* g, hipStream_t stream);
+
+/* Number of nodes (kernels and device copies) the graph holds. */
+hc_status hc_graph_nodes(const hc_graph* g, uint64_t* nodes);
+
+/* Wait for the device, then free the graph and its workspace. */
+void hc_graph_destroy(hc_graph* g);
+
+/* ------------------------------------------------------------------ kernel autotuning */
+
+/* Bit-neutral kernel variants (every variant computes the same words):
+ *   multiply-accumulate: 0 = 4 terms per LDS stage x 4 stages in flight (default),
+ *                        1 = 2 x 8, 2 = 8 x 2;
+ *   64-bit NTT passes of rings above 2^12: 0 = register budget of 4 waves per SIMD
+ *                        (default), 1 = 3 waves, 2 = 5 waves, 3 = a persistent grid over
+ *                        the pass's (tile, polynomial, prime) work queue.
+ * The compression's schedule itself (rotations, key switches, B) is never tuned. */
+#define HC_TUNE_MAC_VARIANTS 3
+#define HC_TUNE_NTT_VARIANTS 4
+typedef struct {
+    uint32_t mac_variant, ntt_variant;     /* chosen, now set in the context */
+    double mac_ms[HC_TUNE_MAC_VARIANTS];   /* multiply-accumulate device ms per compression */
+    double ntt_ms[HC_TUNE_NTT_VARIANTS];   /* forward + inverse NTT device ms per compression */
+} hc_tune_report;
+
+/* Time every variant of each tuned kernel on the caller's own compression
+ * (hc_compress of ct_v with N, t_bound, comp_level into ct_out, run a few times
+ * per variant with kernel timing on, which clears earlier hc_timing totals), keep
+ * the fastest in the context and report the times. Synchronises. Errors: as
+ * hc_compress. */
+hc_status hc_autotune(hc_context* ctx, const hc_gk* gk, const hc_db* db, const uint64_t* ct_v, uint64_t N,
+                      uint32_t t_bound, uint32_t comp_level, uint64_t* ct_out, hc_tune_report* report,
+                      hipStream_t stream);
+
+/* Set or read the context's variants (HC_EINVAL for an unknown variant). */
+hc_status hc_tune_set(hc_context* ctx, uint32_t mac_variant, uint32_t ntt_variant);
+hc_status hc_tune_get(const hc_context* ctx, uint32_t* mac_variant, uint32_t* ntt_variant);
+
 /* ------------------------------------------------------------------ resident diagonals (Sec. 5.2) */
 
 /* Server-side precomputation for the diagonal method of Sec. 5.2. The BSGS

@@ -50,6 +50,10 @@ struct Lane {
     size_t stage_cap = 0, stage_used = 0;
     hipStream_t stage_stream = nullptr;
     hipEvent_t copied = nullptr;     // recorded after the last copy out of the staging area
+    // set while a graph's device work is being captured with this lane (which the graph
+    // owns): the staging area then only grows during the call and is never reused, so the
+    // graph's host-to-device copies of its tables re-read unchanged memory at every launch
+    bool capture = false;
     hc_status init(size_t stage_bytes);
     void release();
 };
@@ -108,6 +112,11 @@ struct hc_context {
     std::map<std::tuple<uint32_t, uint32_t, int>, DiagTab> diag_tabs;
 
     uint64_t* d_scratch = nullptr;  // this device's fixed allocation-free scratch (context.cpp)
+
+    // kernel variants picked by hc_autotune / hc_tune_set (bit-neutral): the diagonal
+    // multiply-accumulate's (terms per stage, stages in flight) and the 64-bit NTT
+    // passes' occupancy or persistent grid
+    int tune_mac = 0, tune_ntt = 0;
 
     hc::Lane lane;     // workspace and staging of the context's own entry points
     std::mutex lazy_mu;  // guards the lazily built tables (prefix masks, switch tables)

@@ -57,6 +57,12 @@ void stage_reset(Lane& l, hipStream_t st) {
     // The workspace is reused in stream order; on another stream the previous call
     // must be done. The staging area is free once its last copy has run, so on the
     // same stream the host prepares the next call while the GPU finishes this one.
+    // A lane being captured into a graph is fresh and the graph's own: nothing to wait for.
+    if (l.capture) {
+        l.stage_used = 0;
+        l.stage_stream = st;
+        return;
+    }
     if (l.stage_stream != st) (void)hipStreamSynchronize(l.stage_stream);
     if (l.copied) (void)hipEventSynchronize(l.copied);
     l.stage_used = 0;
@@ -69,7 +75,7 @@ void* stage_bytes(Lane& l, const void* data, size_t bytes, hipStream_t st) {
     memcpy(l.stage_host + off, data, bytes);
     if (hipMemcpyAsync(l.stage_dev + off, l.stage_host + off, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
         return nullptr;
-    if (l.copied && hipEventRecord(l.copied, st) != hipSuccess) return nullptr;
+    if (!l.capture && l.copied && hipEventRecord(l.copied, st) != hipSuccess) return nullptr;
     l.stage_used = off + bytes;
     return l.stage_dev + off;
 }
@@ -88,7 +94,7 @@ bool stage_many(Lane& l, std::initializer_list<StagePart> parts, hipStream_t st)
         if (hipMemcpyAsync(l.stage_dev + first, l.stage_host + first, off - first, hipMemcpyHostToDevice, st) !=
             hipSuccess)
             return false;
-        if (l.copied && hipEventRecord(l.copied, st) != hipSuccess) return false;
+        if (!l.capture && l.copied && hipEventRecord(l.copied, st) != hipSuccess) return false;
     }
     l.stage_used = off;
     return true;

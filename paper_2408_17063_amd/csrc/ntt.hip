@@ -346,22 +346,21 @@ struct Tile {
     }
 };
 
-// Grid: (tiles of a row, polynomials, rows). WPE: minimum waves per SIMD the
-// registers must allow (1 = no constraint).
-template <typename T, bool INV, int LOGN, int S, int BLO, int ST0, bool LAST, int WPE>
-__global__ void __launch_bounds__(NTT_THREADS) __attribute__((amdgpu_waves_per_eu(WPE)))
-ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab<T> tab) {
+// One tile of one pass: tile bx of polynomial by, row (limb) bz; ntiles tiles per row.
+template <typename T, bool INV, int LOGN, int S, int BLO, int ST0, bool LAST>
+__device__ __forceinline__ void ntt_tile(T* __restrict__ data, size_t poly_stride, int limb_first,
+                                         const NttTab<T>& tab, T* lds, uint32_t bx, uint32_t by, uint32_t bz,
+                                         uint32_t ntiles) {
     typedef Tile<T, INV, LOGN, S, BLO, ST0> TL;
     constexpr int THREADS = TL::THREADS;  // the launch's block size
-    __shared__ T lds[TL::LDS_WORDS];
     const uint32_t tid = threadIdx.x;
-    const int row = blockIdx.z;  // limb; polynomials along y, so consecutive blocks of one
-                                 // XCD share a (prime, tile) and its twiddles stay in L2
+    const int row = (int)bz;  // limb; polynomials along y, so consecutive blocks of one
+                              // XCD share a (prime, tile) and its twiddles stay in L2
     const int prime = limb_first + row;
     const T q = tab.mods[prime];
     const T* tw = tab.base + ((size_t)prime * 2 + (INV ? 1 : 0)) * 2 * TL::N;
-    T* a = data + (size_t)blockIdx.y * poly_stride + (size_t)row * TL::N;
-    const uint32_t sp0 = blockIdx.x * TL::P;
+    T* a = data + (size_t)by * poly_stride + (size_t)row * TL::N;
+    const uint32_t sp0 = bx * TL::P;
     const T* ni = tab.ninv + 4 * prime;
     constexpr bool FOLD = INV && LAST;
     // NR: forward transform of a 64-bit prime below 2^57 without conditional subtractions
@@ -409,7 +408,7 @@ ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab
 
         const T* tw2 = nullptr;
         if constexpr (TL::TW2)
-            tw2 = tab.tw2 + (((size_t)prime * 2 + (INV ? 1 : 0)) * gridDim.x + blockIdx.x) * (size_t)TL::TW_PASS *
+            tw2 = tab.tw2 + (((size_t)prime * 2 + (INV ? 1 : 0)) * ntiles + bx) * (size_t)TL::TW_PASS *
                                 THREADS * 2;
 
         if constexpr (TL::DIRECT_LO) {
@@ -476,6 +475,38 @@ ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab
     }
 }
 
+// Grid: (tiles of a row, polynomials, rows). WPE: minimum waves per SIMD the
+// registers must allow (1 = no constraint).
+template <typename T, bool INV, int LOGN, int S, int BLO, int ST0, bool LAST, int WPE>
+__global__ void __launch_bounds__(NTT_THREADS) __attribute__((amdgpu_waves_per_eu(WPE)))
+ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab<T> tab) {
+    typedef Tile<T, INV, LOGN, S, BLO, ST0> TL;
+    __shared__ T lds[TL::LDS_WORDS];
+    ntt_tile<T, INV, LOGN, S, BLO, ST0, LAST>(data, poly_stride, limb_first, tab, lds, blockIdx.x, blockIdx.y,
+                                              blockIdx.z, gridDim.x);
+}
+
+// The same pass as a persistent grid: a fixed number of blocks (the device's resident
+// capacity) walks the pass's work queue of (tile, polynomial, row) items, item i =
+// (row count + polynomial) ntiles + tile in the regular grid's block order, each block
+// taking items blockIdx.x, blockIdx.x + gridDim.x, ... until the queue is exhausted.
+// Every item costs the same, so the static order balances like a dynamic one. The
+// block's LDS tile is reused item after item (a barrier separates them); every block
+// leaves the loop after its last item.
+template <typename T, bool INV, int LOGN, int S, int BLO, int ST0, bool LAST, int WPE>
+__global__ void __launch_bounds__(NTT_THREADS) __attribute__((amdgpu_waves_per_eu(WPE)))
+ntt_tile_persistent_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab<T> tab,
+                           uint32_t ntiles, uint32_t count, uint32_t items) {
+    typedef Tile<T, INV, LOGN, S, BLO, ST0> TL;
+    __shared__ T lds[TL::LDS_WORDS];
+    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
+        if (it != blockIdx.x) __syncthreads();  // the previous item's LDS reads are done
+        const uint32_t bx = it % ntiles, rest = it / ntiles;
+        ntt_tile<T, INV, LOGN, S, BLO, ST0, LAST>(data, poly_stride, limb_first, tab, lds, bx, rest % count,
+                                                  rest / count, ntiles);
+    }
+}
+
 // Launch one pass; `ops` butterflies and `bytes` moved for the timing record.
 template <typename T, bool INV, int LOGN, int S, int BLO, int ST0, bool LAST>
 static void pass(const Ctx& c, int kind, T* data, size_t stride, int count, int lf, int nl,
@@ -483,15 +514,38 @@ static void pass(const Ctx& c, int kind, T* data, size_t stride, int count, int 
     constexpr int TLOG = LOGN < TILE_LOG ? LOGN : TILE_LOG;
     constexpr int THREADS = (1 << TLOG) / NTT_EPT;
     static_assert(THREADS <= NTT_THREADS, "tile");
-    // 64-bit passes of two-pass rings: four waves per SIMD (128 registers), which the
-    // twiddle-heavy passes reach with a few spilled words
-    constexpr int WPE = (sizeof(T) == 8 && LOGN > TILE_LOG) ? 4 : 1;
+    // 64-bit passes of two-pass rings: by default four waves per SIMD (128 registers),
+    // which the twiddle-heavy passes reach with a few spilled words; the context's tuned
+    // variant (hc_autotune) may pick three or five, or the persistent grid. Every
+    // variant computes the same words.
+    constexpr bool TUNED = sizeof(T) == 8 && LOGN > TILE_LOG;
+    const int var = TUNED ? c.tune_ntt : 0;
     dim3 grid(1 << (LOGN - TLOG), count, nl);
     const double bytes = 2.0 * sizeof(T) * (double)count * nl * (1 << LOGN);
     const double ops = (double)count * nl * (1 << (LOGN - 1)) * S;
     auto launch = [&]() {
-        hipLaunchKernelGGL((ntt_tile_kernel<T, INV, LOGN, S, BLO, ST0, LAST, WPE>), grid, dim3(THREADS), 0, st, data,
-                           stride, lf, tab);
+        if constexpr (TUNED) {
+            if (var == 1) {
+                hipLaunchKernelGGL((ntt_tile_kernel<T, INV, LOGN, S, BLO, ST0, LAST, 3>), grid, dim3(THREADS), 0, st,
+                                   data, stride, lf, tab);
+                return;
+            }
+            if (var == 2) {
+                hipLaunchKernelGGL((ntt_tile_kernel<T, INV, LOGN, S, BLO, ST0, LAST, 5>), grid, dim3(THREADS), 0, st,
+                                   data, stride, lf, tab);
+                return;
+            }
+            if (var == 3) {
+                const uint32_t items = grid.x * grid.y * grid.z;
+                const uint32_t cap = (uint32_t)c.cus * 4;  // four 4-wave blocks per CU (4 waves per SIMD)
+                hipLaunchKernelGGL((ntt_tile_persistent_kernel<T, INV, LOGN, S, BLO, ST0, LAST, 4>),
+                                   dim3(items < cap ? items : cap), dim3(THREADS), 0, st, data, stride, lf, tab,
+                                   grid.x, (uint32_t)count, items);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((ntt_tile_kernel<T, INV, LOGN, S, BLO, ST0, LAST, TUNED ? 4 : 1>), grid, dim3(THREADS), 0,
+                           st, data, stride, lf, tab);
     };
     if (kind >= 0) {
         TimeScope ts(c, kind, st, bytes, ops);

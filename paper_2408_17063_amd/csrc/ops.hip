@@ -1189,8 +1189,23 @@ hc_status k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* Rt, const
     TimeScope ts(c, HC_KT_DIAG_MAC, st,
                  8.0 * ln * (2.0 * npairs * J + (double)J * ga + (accumulate ? 4.0 : 2.0) * npairs * ga),
                  2.0 * ln * npairs * J * ga);
-    hipLaunchKernelGGL((diag_mac_kernel<GC, DIAG_T, DIAG_NS>), dim3(a.per_xcd * 8), dim3(256), 0, st, A, Rt, D,
-                       c.d_mods, c.d_qinv, c.d_r2, a);
+    // the tuned variant (hc_autotune): terms per LDS stage x stages in flight, always
+    // DIAG_NS DIAG_T terms per round of the ring, so the rotated ciphertexts' padding and
+    // every result word are the same for all of them
+    static_assert(DIAG_T * DIAG_NS == 16, "variants below assume 16 terms per round");
+    switch (c.tune_mac) {
+        case 1:
+            hipLaunchKernelGGL((diag_mac_kernel<GC, 2, 8>), dim3(a.per_xcd * 8), dim3(256), 0, st, A, Rt, D, c.d_mods,
+                               c.d_qinv, c.d_r2, a);
+            break;
+        case 2:
+            hipLaunchKernelGGL((diag_mac_kernel<GC, 8, 2>), dim3(a.per_xcd * 8), dim3(256), 0, st, A, Rt, D, c.d_mods,
+                               c.d_qinv, c.d_r2, a);
+            break;
+        default:
+            hipLaunchKernelGGL((diag_mac_kernel<GC, DIAG_T, DIAG_NS>), dim3(a.per_xcd * 8), dim3(256), 0, st, A, Rt,
+                               D, c.d_mods, c.d_qinv, c.d_r2, a);
+    }
     return HC_OK;
 }
 

@@ -54,6 +54,18 @@ class CompressInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+TUNE_MAC_VARIANTS, TUNE_NTT_VARIANTS = 3, 4
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("mac_variant", ctypes.c_uint32), ("ntt_variant", ctypes.c_uint32),
+                ("mac_ms", ctypes.c_double * TUNE_MAC_VARIANTS), ("ntt_ms", ctypes.c_double * TUNE_NTT_VARIANTS)]
+
+    def as_dict(self):
+        return {"mac_variant": self.mac_variant, "ntt_variant": self.ntt_variant,
+                "mac_ms": [round(x, 4) for x in self.mac_ms], "ntt_ms": [round(x, 4) for x in self.ntt_ms]}
+
+
 class Query(ctypes.Structure):
     _fields_ = [("ct_v", c_vp), ("N", ctypes.c_uint64), ("t_bound", ctypes.c_uint32),
                 ("comp_level", ctypes.c_uint32), ("out_level", ctypes.c_uint32), ("ct_out", c_vp),
@@ -97,6 +109,14 @@ _sig("hc_encrypt", _st, c_vp, c_vp, c_u32p, c_u8p, c_vp, c_vp)
 _sig("hc_compress", _st, c_vp, c_vp, c_vp, c_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
      c_vp, ctypes.POINTER(CompressInfo), c_vp)
 _sig("hc_compress_batch", _st, c_vp, c_vp, c_vp, ctypes.POINTER(Query), ctypes.c_uint32, c_vp)
+_sig("hc_graph_create", _st, c_vp, c_vp, c_vp, ctypes.POINTER(Query), ctypes.c_uint32, ctypes.POINTER(c_vp))
+_sig("hc_graph_launch", _st, c_vp, c_vp)
+_sig("hc_graph_nodes", _st, c_vp, ctypes.POINTER(ctypes.c_uint64))
+_sig("hc_graph_destroy", None, c_vp)
+_sig("hc_autotune", _st, c_vp, c_vp, c_vp, c_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, c_vp,
+     ctypes.POINTER(TuneReport), c_vp)
+_sig("hc_tune_set", _st, c_vp, ctypes.c_uint32, ctypes.c_uint32)
+_sig("hc_tune_get", _st, c_vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32))
 _sig("hc_decrypt", _st, c_vp, c_vp, c_u64p, ctypes.c_uint32, c_u32p)
 _sig("hc_decompress", _st, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
      c_u32p, c_u32p, c_u64p, c_u32p, c_u32p)
@@ -146,6 +166,8 @@ EXPORTED = [
     "hc_rotate_hoisted", "hc_mul_plain",
     "hc_modup", "hc_moddown", "hc_sample", "hc_encode_diagonal", "hc_export_sk", "hc_export_pk",
     "hc_export_gk", "hc_timing_enable", "hc_timing_read", "hc_probe_mul32_rate", "hc_probe_copy",
+    "hc_graph_create", "hc_graph_launch", "hc_graph_nodes", "hc_graph_destroy",
+    "hc_autotune", "hc_tune_set", "hc_tune_get",
     "hc_diag_prepare", "hc_diag_release", "hc_server_create", "hc_server_submit", "hc_server_poll",
     "hc_server_stats_get", "hc_server_destroy",
 ]
@@ -316,6 +338,42 @@ class Context:
                                     _stream(stream))
         return st, [arr[i].status for i in range(len(queries))], [x.as_dict() for x in infos]
 
+    def autotune(self, gk, db, ct_v, N, t_bound, comp_level=0, stream=None):
+        """Pick the fastest bit-neutral kernel variants on this compression; returns the report."""
+        rep = TuneReport()
+        out = self.ct_tensor(1)[0]
+        _check(_lib.hc_autotune(self.h, gk.h, db.h if db is not None else None, _dev(ct_v, self.ct_words(N), "ct_v"),
+                                N, t_bound, comp_level, _dev(out), ctypes.byref(rep), _stream(stream)), "hc_autotune")
+        return rep.as_dict()
+
+    def tune_set(self, mac_variant, ntt_variant):
+        _check(_lib.hc_tune_set(self.h, mac_variant, ntt_variant), "hc_tune_set")
+
+    def tune_get(self):
+        a, b = ctypes.c_uint32(0), ctypes.c_uint32(0)
+        _check(_lib.hc_tune_get(self.h, ctypes.byref(a), ctypes.byref(b)), "hc_tune_get")
+        return int(a.value), int(b.value)
+
+    def graph(self, gk, db, queries, comp_level=0, out_level=0):
+        """Capture hc_compress_batch over queries [(ct_v, N, t_bound, out)] into a Graph;
+        each launch recomputes the answers of whatever the ct_v buffers hold."""
+        arr = (Query * len(queries))()
+        infos = [CompressInfo() for _ in queries]
+        keep = []
+        for i, (ctv, N, t, out) in enumerate(queries):
+            arr[i].ct_v = _dev(ctv, self.ct_words(N), "ct_v").value
+            arr[i].N = N
+            arr[i].t_bound = t
+            arr[i].comp_level = comp_level
+            arr[i].out_level = out_level
+            arr[i].ct_out = _dev(out, 2 * self.L * self.n, "out").value
+            arr[i].info = ctypes.pointer(infos[i])
+            keep.append((ctv, out))
+        h = c_vp()
+        _check(_lib.hc_graph_create(self.h, gk.h, db.h if db is not None else None, arr, len(queries),
+                                    ctypes.byref(h)), "hc_graph_create")
+        return Graph(self, h, keep, [x.as_dict() for x in infos])
+
     def decrypt(self, sk, ct_host):
         """ct_host: [2][level][n] (level inferred from the size)."""
         ct = np.ascontiguousarray(ct_host, dtype=np.uint64)
@@ -483,6 +541,23 @@ class Database(_Handle):
     def __init__(self, ctx, h, ncol, N):
         super().__init__(ctx, h)
         self.ncol, self.N = ncol, N
+
+
+class Graph(_Handle):
+    """A captured batch of compressions (hc_graph_*); keeps its buffers alive."""
+    _destroy = "hc_graph_destroy"
+
+    def __init__(self, ctx, h, buffers, infos):
+        super().__init__(ctx, h)
+        self.buffers, self.infos = buffers, infos
+
+    def launch(self, stream=None):
+        _check(_lib.hc_graph_launch(self.h, _stream(stream)), "hc_graph_launch")
+
+    def nodes(self):
+        n = ctypes.c_uint64(0)
+        _check(_lib.hc_graph_nodes(self.h, ctypes.byref(n)), "hc_graph_nodes")
+        return int(n.value)
 
 
 class Server:
