@@ -344,6 +344,134 @@ def _compress(pr, sched, cts_v, db, gks, level):
 
 
 # ---------------------------------------------------------------------------
+# the unencrypted-database form (Sec. 5.2, remark on an unencrypted database)
+#
+# With the database in the clear, C (DB * v) = (C diag(DB)) v, so the server can
+# fold the values into the matrix, D_c = C diag(DB_c), and compute [C; D_1; ...] v
+# directly on the index vector: no Mask, and no per-stream packing. Reading used here
+# (the remark gives no slot layout): the stream pairs are the same as above, (C, D_1),
+# (D_2, D_3), ..., and band g * (#streams) + sigma again holds group g's products,
+# row 0 = M_a v and row 1 = M_b v, so the answer decrypts exactly like the
+# encrypted-database form. Each input ciphertext X_i = [x_(2i); x_(2i+1)] (its two
+# slot rows hold the group-local record blocks 2i and 2i+1) gives two u-blocks, X_i and
+# Y_i = Rot_col(X_i) = [x_(2i+1); x_(2i)], shared by every stream; a diagonal now
+# differs between the rows: in row r of a u-block holding record block beta_r it
+# carries M_r's entries for that block,
+#   alpha(beta_r, c)^(((m - g B) mod s) + 1) * DB_(col_r)[record(beta_r, c)] mod p,
+#   c = (m + b) mod n/2,
+# with the DB factor 1 for the matrix C. Records past the database's end count as 0.
+# k = 2 (ciphertexts in the group) u-blocks per group, B by the same rule; baby steps
+# are hoisted once per u-block for all streams; the block products, giant steps,
+# rotate-and-sum, merge and the answer's switch follow the encrypted form. The inputs
+# are switched to the Comp level first (no Mask runs at the top level).
+
+def plain_db_blocks(grp):
+    """(beta_0, beta_1) of the u-blocks of a group: X_i, then Y_i, per ciphertext i."""
+    out = []
+    for i in range(grp.ct_count):
+        out.append((2 * i, 2 * i + 1))
+        out.append((2 * i + 1, 2 * i))
+    return out
+
+
+def plain_db_schedule(sched):
+    """The schedule of the unencrypted-database form: same groups, streams and s, with
+    k = 2 (ciphertexts in the group) and B chosen for that k."""
+    import copy
+    s2 = copy.deepcopy(sched)
+    for g in s2.groups:
+        g.k = 2 * g.ct_count
+        g.B = choose_B(s2.s, g.k)
+    s2.keys = sorted(required_keys(s2) | {2 * s2.n - 1})
+    return s2
+
+
+def diagonal_slots_db(p, nh, s, B, blocks, gi, b, cols, db, rec_start):
+    """Slots of the unencrypted-database diagonal: row r for record block blocks[r]
+    and matrix cols[r] (0: C; c >= 1: C diag(DB_c)), giant gi, baby b."""
+    m = np.arange(nh, dtype=np.int64)
+    c = (m + b) % nh
+    expo = (m - gi * B) % s + 1
+    rows = []
+    for r in range(2):
+        beta = blocks[r]
+        alpha = (beta * nh + c + 1) % p
+        val = powmod_vec(alpha, expo, p)
+        col = cols[r]
+        if col is not None and col > 0:
+            col_vals = np.asarray(db[col - 1], dtype=np.int64)
+            rec = rec_start + beta * nh + c
+            fac = np.where(rec < len(col_vals), col_vals[np.minimum(rec, len(col_vals) - 1)] % p, 0)
+            val = val * fac % p
+        elif col is None:
+            val = np.zeros_like(val)
+        rows.append(val.astype(np.uint64))
+    return np.stack(rows)
+
+
+def compress_plain_db(pr, sched, cts_v, db, gks, level=None, out_level=None):
+    """Comp in the unencrypted-database form (see above): the same answer layout as
+    compress, computed as [C; D_1; ...] v without Mask. sched: make_schedule's
+    schedule of the query (its groups, streams and s; k and B follow
+    plain_db_schedule)."""
+    if len(cts_v) != sched.n_ct or len(db) != sched.ncol or any(len(col) < sched.N for col in db):
+        raise ScheduleError("inputs do not match the schedule")
+    sc = plain_db_schedule(sched)
+    level = default_level(pr) if level is None else level
+    top = pr
+    if level < pr.L:
+        cts_v = [bfv.mod_switch(pr, ct, level) for ct in cts_v]
+        gks = {k: bfv.key_at_level(pr, gk, level) for k, gk in gks.items()}
+        pr = bfv.at_level(pr, level)
+    keys = KeySet(gks)
+    n, s = pr.n, sc.s
+    bands = []
+    for grp in sc.groups:
+        blocks = plain_db_blocks(grp)
+        us = []
+        for i in range(grp.ct_count):
+            X = cts_v[grp.ct_start + i]
+            us.append(X)
+            us.append(bfv.rotate(pr, X, keys[2 * n - 1]))
+        B = grp.B
+        baby = []
+        for u in us:
+            rs = [u]
+            if B > 1:
+                rs += bfv.rotate_hoisted(pr, u, [keys[rot(n, b)] for b in range(1, B)])
+            baby.append(rs)
+        for a, bcol in sc.streams:
+            accs = []
+            for gi in range(s // B):
+                acc = None
+                for beta in range(grp.k):
+                    for b in range(B):
+                        d = diagonal_slots_db(pr.p, pr.nh, s, B, blocks[beta], gi, b, (a, bcol), db,
+                                              grp.rec_start)
+                        term = bfv.mul_plain(pr, baby[beta][b], bfv.plain_poly(pr, d))
+                        acc = term if acc is None else acc + term
+                accs.append(acc)
+            y = accs[0]
+            if len(accs) > 1:
+                y = y + bfv.rotate_sum(pr, accs[1:], [keys[rot(n, gi * B)] for gi in range(1, len(accs))])
+            bands.append(rotate_and_sum(pr, sc, y, keys))
+    if len(bands) == 1:
+        out = bands[0]
+    else:
+        ms = bfv.plain_poly(pr, prefix_mask(pr.nh, s))
+        out = bfv.mul_plain(pr, bands[0], ms)
+        for beta in range(1, len(bands)):
+            t = bfv.mul_plain(pr, bands[beta], ms)
+            out = out + bfv.rotate(pr, t, keys[rot(pr.n, -beta * s)])
+    lvl = len(out.c0.mods)
+    if out_level is None or out_level == lvl:
+        return out
+    if not 0 < out_level < lvl:
+        raise ScheduleError("out_level must be in [1, Comp level]")
+    return bfv.mod_switch(bfv.at_level(top, lvl), out, out_level)
+
+
+# ---------------------------------------------------------------------------
 # plain definition of what the compressed ciphertext decrypts to
 
 def vandermonde_product(p, s, vec):

@@ -528,3 +528,56 @@ def test_restricted_key_switches_at_lower_level():
     k = bfv.rot_row_element(pr, 3)
     gk = bfv.key_at_level(pr, bfv.galois_keygen(pr, sk, k, bytes([7] * 32)), 2)
     assert np.array_equal(bfv.decrypt(plo, sk, bfv.rotate(plo, ct, gk)), np.roll(sl, -3, axis=1))
+
+
+# --------------------------------------------------------------------------- unencrypted database
+
+@pytest.mark.parametrize("wl_name,out_level", [("tiny-1024", None), ("multi-2048", None), ("multi-2048", 1)])
+def test_plain_db_form_decrypts_to_vandermonde(wl_name, out_level):
+    """Sec. 5.2's remark on an unencrypted database: [C; C diag(DB)] v computed on the
+    index vector alone decrypts to the same products as Mask + Comp (Eq. (1)) in every
+    band, and decompresses (Alg. 6) to the matched records and values."""
+    import workloads as W
+    wl = W.WORKLOADS[wl_name]
+    ring = W.RINGS[wl.ring]
+    pr = make_params(ring.n, ring.p, ring.L, ring.q_bits, ring.K, ring.p_bits)
+    v, db = W.query_inputs(wl)
+    sc = C.make_schedule(pr.n, pr.p, wl.N, wl.ncol, wl.t)
+    sc2 = C.plain_db_schedule(sc)
+    sk, pk = bfv.keygen(pr, W.seed32("sk", 0))
+    gks = {k: bfv.galois_keygen(pr, sk, k, W.seed32("gk", k)) for k in sc2.keys}
+    vm = slots.vector_to_slot_matrices(v, pr.n, sc.n_ct)
+    cts = [bfv.encrypt(pr, pk, vm[i], W.seed32("enc", i)) for i in range(sc.n_ct)]
+    out = C.compress_plain_db(pr, sc, cts, db, gks, out_level=out_level)
+    p_out = bfv.at_level(pr, len(out.c0.mods), keyswitch=False)
+    assert bfv.noise_bits(p_out, sk, out) < bfv.noise_budget_bits(p_out) - 8
+    dec = bfv.decrypt(p_out, sk, out)
+    exp = C.expected_bands(sc, v, db)
+    for b in range(sc.bands):
+        assert C.band_slots(sc, dec, b) == exp[b], b
+    S = len(sc.streams)
+    for gi, grp in enumerate(sc.groups):
+        rows = []
+        for st in range(S):
+            rows += list(C.band_slots(sc, dec, gi * S + st))
+        idx, vals = D.decompress_group(pr.p, grp.n_rec, rows[0], rows[1:1 + sc.ncol])
+        seg = v[grp.rec_start:grp.rec_start + grp.n_rec]
+        assert idx == [int(i) + 1 for i in np.nonzero(seg)[0]]
+
+
+def test_plain_db_diagonal_rows():
+    """The diagonal of the unencrypted-database form, entry by entry from its definition:
+    row r holds alpha^e times the value of the record the slot multiplies (C: times 1)."""
+    p, nh, s, B = 12289, 16, 8, 2
+    db = [np.arange(100, 140) % p, np.arange(7, 47) * 3 % p]
+    rec0 = 5
+    d = C.diagonal_slots_db(p, nh, s, B, (1, 0), 2, 1, (0, 2), db, rec0)
+    for m in range(nh):
+        c = (m + 1) % nh
+        e = (m - 2 * B) % s + 1
+        assert d[0, m] == pow(1 * nh + c + 1, e, p)                      # C, block 1
+        rec = rec0 + 0 * nh + c
+        assert d[1, m] == pow(c + 1, e, p) * int(db[1][rec]) % p         # C diag(DB_2), block 0
+    z = C.diagonal_slots_db(p, nh, s, B, (0, 1), 0, 0, (1, None), db, 30)
+    assert not z[1].any()                                                # a missing second vector
+    assert z[0, 15] == 0                                                 # record 30 + 15 is past the end
