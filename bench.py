@@ -282,6 +282,40 @@ def batched_large(st, Q, steps, out_level=0):
             "unit": "compressions/s"}
 
 
+def plain_db_leg(st, eager_out, steps, comp_level, out_level):
+    """The unencrypted-database form (hc_compress_plain_db) on the headline query: no
+    Mask, [C; C diag(DB)] v with its diagonals encoded on the fly (they depend on the
+    database); its answer must decrypt like the Mask + Comp answer."""
+    import numpy as np
+    import torch
+    ctx, wl = st["ctx"], st["wl"]
+    keys, plan = ctx.plan_plain_db(wl.N, wl.ncol, wl.t, comp_level, out_level)
+    if not set(keys) <= set(st["keys"]):
+        return {"skipped": "key set differs"}
+    out = ctx.ct_tensor(1)[0]
+    ctx.compress_plain_db(st["gk"], st["db"], st["cts"], wl.N, wl.t, out=out, comp_level=comp_level,
+                          out_level=out_level)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        _, info = ctx.compress_plain_db(st["gk"], st["db"], st["cts"], wl.N, wl.t, out=out, comp_level=comp_level,
+                                        out_level=out_level)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    a = ctx.decrypt(st["sk"], ctx.output(out, info).cpu().numpy().view(np.uint64))
+    b = ctx.decrypt(st["sk"], ctx.output(eager_out, info).cpu().numpy().view(np.uint64))
+    s = info["s"]
+    same = all(np.array_equal(a[:, k * s:(k + 1) * s], b[:, k * s:(k + 1) * s]) for k in range(info["bands"]))
+    del out
+    torch.cuda.empty_cache()
+    return {"steps": steps, "ms_per_step": round(ms, 3), "value": round(1e3 / ms, 4), "unit": "compressions/s",
+            "key_switches": info["n_keyswitch"], "diagonals_encoded": info["n_diag"],
+            "decrypts_like_mask_and_comp": bool(same)}
+
+
 def graph_leg(st, eager_out, steps, comp_level, out_level):
     """The headline compression captured once into a HIP graph (hc_graph_create) and
     replayed: same inputs, its output must equal the eager run's bit for bit."""
@@ -686,6 +720,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel variants")
     ap.add_argument("--graph-steps", type=int, default=5,
                     help="also time this many replays of the headline compression captured in a graph (0: skip)")
+    ap.add_argument("--plain-db-steps", type=int, default=2,
+                    help="also time the unencrypted-database form on the headline query (0: skip)")
     ap.add_argument("--small-configs", type=int, default=20,
                     help="latency repetitions of the ring-4096 and ring-2^15 configurations (0: skip)")
     ap.add_argument("--ntt-probe", type=int, default=0,
@@ -793,6 +829,9 @@ def main():
     if args.graph_steps:
         rec["graph"] = graph_leg(st, out, args.graph_steps, args.comp_level, ol)
         log("graph replay: %s" % rec["graph"])
+    if args.plain_db_steps:
+        rec["plain_db"] = plain_db_leg(st, out, args.plain_db_steps, args.comp_level, ol)
+        log("unencrypted-database form: %s" % rec["plain_db"])
     if args.batch_queries:
         rec["batched"] = batched_large(st, args.batch_queries, max(1, args.steps // 2), ol)
         log("batched %d queries: %.1f ms per batch, %.3f compressions/s" % (

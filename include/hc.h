@@ -182,6 +182,25 @@ hc_status hc_compress(hc_context* ctx, const hc_gk* gk, const hc_db* db, const u
                       uint64_t N, uint32_t t_bound, uint32_t comp_level, uint32_t out_level,
                       uint64_t* ct_out, hc_compress_info* info, hipStream_t stream);
 
+/* The unencrypted-database form (Sec. 5.2, remark on an unencrypted database): the
+ * server knows DB in the clear, so C (DB * v) = (C diag(DB)) v and the answer is
+ * [C; C diag(DB_1); ...; C diag(DB_ncol)] v computed directly on the index-vector
+ * ciphertexts -- no Mask and no per-stream packing. The inputs are switched to the
+ * Comp level first; each input ciphertext and its row swap Rot_col serve as the
+ * u-blocks of every stream, and the diagonals carry, row by row, the entries of the
+ * matrix for the record block that row holds (times the records' values, read from
+ * the database db keeps since hc_db_upload; records past its end count as 0). The
+ * answer has hc_compress's layout and decrypts to the same slots (its bits differ).
+ * Arguments as hc_compress; the key set is hc_plan_plain_db's (hc_plan's plus
+ * Rot_col's element 2n - 1 in every case). */
+hc_status hc_compress_plain_db(hc_context* ctx, const hc_gk* gk, const hc_db* db, const uint64_t* ct_v,
+                               uint64_t N, uint32_t t_bound, uint32_t comp_level, uint32_t out_level,
+                               uint64_t* ct_out, hc_compress_info* info, hipStream_t stream);
+
+/* hc_plan for hc_compress_plain_db (its key set and counts). */
+hc_status hc_plan_plain_db(hc_context* ctx, uint64_t N, uint32_t ncol, uint32_t t_bound, uint32_t comp_level,
+                           uint32_t out_level, uint32_t* elements_out, uint32_t* count, hc_compress_info* info);
+
 /* One entry of a batch for hc_compress_batch. */
 typedef struct {
     const uint64_t* ct_v;   /* device, ceil(N/n) ciphertexts */

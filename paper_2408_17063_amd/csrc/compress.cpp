@@ -32,13 +32,13 @@
 namespace hc {
 
 
-static uint32_t rot_elt(const Ctx& c, int64_t r) {
+uint32_t rot_elt(const Ctx& c, int64_t r) {
     int64_t nh = c.nh;
     int64_t rr = ((r % nh) + nh) % nh;
     return (uint32_t)h_powmod(3, (uint64_t)rr, 2ull * c.n);
 }
 
-static uint32_t choose_B(uint32_t s, uint32_t k) {
+uint32_t choose_B(uint32_t s, uint32_t k) {
     uint64_t best = ~0ull;
     uint32_t bestB = 1;
     for (uint32_t B = 1; B <= s; B *= 2) {

@@ -109,6 +109,10 @@ struct BatchShape {
     std::map<std::pair<uint32_t, uint32_t>, const Ctx::DiagTab*> cls_res;
 };
 
+// Galois element of Rot_row(.; r) (k = 3^r mod 2n, r taken mod n/2)
+uint32_t rot_elt(const Ctx& c, int64_t r);
+// baby steps: the power of two B in [1, s] minimising k (B - 1) + (s / B - 1), ties to the larger
+uint32_t choose_B(uint32_t s, uint32_t k);
 // Plan one compression (validates N, ncol, t_bound, comp_level and out_level).
 hc_status make_plan(const Ctx& c, uint64_t N, uint32_t ncol, uint32_t t_bound, uint32_t comp_level,
                     uint32_t out_level, Plan& pl);

@@ -150,6 +150,7 @@ struct hc_db {
     uint64_t N = 0;
     uint32_t n_ct = 0;
     uint64_t* d_pt = nullptr;  // [ncol][n_ct][L][n] NTT domain, Montgomery form
+    uint32_t* d_raw = nullptr; // [ncol][N] the values mod p (the unencrypted-database form)
 };
 
 namespace hc {
@@ -265,6 +266,11 @@ void k_slots_to_eval(const Ctx& c, uint32_t* out, const uint32_t* slots, int cou
 void k_lift(const Ctx& c, uint64_t* out, const uint32_t* in, int count, bool mont, int Lc,
             hipStream_t st);
 // compression diagonals in NTT-mod-p positions: out [count][n], params [count][3] (beta, gi, b)
+// diagonals of the unencrypted-database form in NTT-mod-p positions: out [count][n], params
+// [count][7] (beta_0, beta_1, gi, b, col_0, col_1, rec_start): row r for record block beta_r
+// of matrix col_r (0: C; c >= 1: C diag(DB_c) with raw [ncol][Ndb]; 0xffffffff: zero row)
+void k_diag_gen_db(const Ctx& c, uint32_t* out, const uint32_t* params, int count, uint32_t s, uint32_t B,
+                   const uint32_t* raw, uint64_t Ndb, hipStream_t st);
 void k_diag_gen(const Ctx& c, uint32_t* out, const uint32_t* params, int count, uint32_t s,
                 uint32_t B, hipStream_t st);
 // samplers: uniform residues for rows lf..lf+nl-1 (stream limb index = row prime index)

@@ -534,15 +534,18 @@ extern "C" hc_status hc_db_upload(hc_context* cp, const uint32_t* cols, uint32_t
     db->n_ct = (uint32_t)((N + n - 1) / n);
     if (ncol) {
         HC_CHECK(hipMalloc((void**)&db->d_pt, sizeof(uint64_t) * ncol * db->n_ct * c.L * n));
-        std::vector<uint32_t> sl(n * db->n_ct);
+        std::vector<uint32_t> sl(n * db->n_ct), raw((size_t)ncol * N);
         for (uint32_t col = 0; col < ncol; col++) {
             std::fill(sl.begin(), sl.end(), 0u);
-            for (uint64_t r = 0; r < N; r++) sl[r] = cols[(size_t)col * N + r] % (uint32_t)c.p;
+            for (uint64_t r = 0; r < N; r++) sl[r] = raw[(size_t)col * N + r] = cols[(size_t)col * N + r] % (uint32_t)c.p;
             // record r: ciphertext r / n, row (r % n) / nh, column r % nh = flat r % n
             hc_status s = encode_plain(c, db->d_pt + (size_t)col * db->n_ct * c.L * n, sl.data(),
                                        (int)db->n_ct, true, 0);
             if (s != HC_OK) { hc_db_destroy(db); return s; }
         }
+        // the values themselves, for the unencrypted-database form's diagonals
+        HC_CHECK(hipMalloc((void**)&db->d_raw, sizeof(uint32_t) * raw.size()));
+        HC_CHECK(hipMemcpy(db->d_raw, raw.data(), sizeof(uint32_t) * raw.size(), hipMemcpyHostToDevice));
     }
     *out = db;
     return HC_OK;
@@ -551,6 +554,7 @@ extern "C" hc_status hc_db_upload(hc_context* cp, const uint32_t* cols, uint32_t
 extern "C" void hc_db_destroy(hc_db* db) {
     if (!db) return;
     (void)hipFree(db->d_pt);
+    (void)hipFree(db->d_raw);
     delete db;
 }
 

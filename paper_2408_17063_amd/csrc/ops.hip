@@ -645,6 +645,47 @@ void k_diag_gen(const Ctx& c, uint32_t* out, const uint32_t* params, int count, 
                        c.d_posslot, c.n, c.nh, (uint32_t)c.p, s, B);
 }
 
+// The unencrypted-database form's diagonals: slot (row r, m) of the diagonal for the
+// u-block whose row r holds record block beta_r, giant gi, baby b: alpha^e times, for
+// the matrix C diag(DB_c), the value of that record (0 past the database's end), with
+// alpha = beta_r nh + ((m + b) mod nh) + 1 and e = ((m - gi B) mod s) + 1.
+__global__ void diag_gen_db_kernel(uint32_t* out, const uint32_t* params, const uint32_t* posslot,
+                                   const uint32_t* raw, uint64_t Ndb, int n, int nh, uint32_t p, uint32_t s,
+                                   uint32_t B) {
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const uint32_t* pr = params + 7 * blockIdx.z;
+    const uint32_t slot = posslot[x];
+    const uint32_t row = slot / (uint32_t)nh, m = slot % (uint32_t)nh;
+    const uint32_t beta = pr[row], gi = pr[2], b = pr[3], col = pr[4 + row], rec0 = pr[6];
+    uint32_t acc = 0;
+    if (col != 0xffffffffu) {
+        const uint32_t cc = (m + b) % (uint32_t)nh;
+        const uint64_t alpha = ((uint64_t)beta * nh + cc + 1) % p;
+        uint32_t e = ((m + s * (uint32_t)nh - (gi * B) % s) % s) + 1;
+        const double pinv = 1.0 / (double)p;
+        uint32_t base = (uint32_t)alpha;
+        acc = 1;
+        while (e) {
+            if (e & 1) acc = mulmod_p(acc, base, p, pinv);
+            base = mulmod_p(base, base, p, pinv);
+            e >>= 1;
+        }
+        if (col > 0) {
+            const uint64_t rec = (uint64_t)rec0 + (uint64_t)beta * nh + cc;
+            const uint32_t v = rec < Ndb ? raw[(uint64_t)(col - 1) * Ndb + rec] : 0u;
+            acc = mulmod_p(acc, v, p, pinv);
+        }
+    }
+    out[(size_t)blockIdx.z * n + x] = acc;
+}
+
+void k_diag_gen_db(const Ctx& c, uint32_t* out, const uint32_t* params, int count, uint32_t s, uint32_t B,
+                   const uint32_t* raw, uint64_t Ndb, hipStream_t st) {
+    hipLaunchKernelGGL(diag_gen_db_kernel, ew_grid(c.n, 1, count), dim3(EW_THREADS), 0, st, out, params,
+                       c.d_posslot, raw, Ndb, c.n, c.nh, (uint32_t)c.p, s, B);
+}
+
 // ------------------------------------------------------------------ encryption helpers
 
 __global__ void enc_finish_kernel(uint64_t* ct, const uint64_t* e0, const uint64_t* e1,

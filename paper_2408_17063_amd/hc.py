@@ -108,6 +108,10 @@ _sig("hc_db_destroy", None, c_vp)
 _sig("hc_encrypt", _st, c_vp, c_vp, c_u32p, c_u8p, c_vp, c_vp)
 _sig("hc_compress", _st, c_vp, c_vp, c_vp, c_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
      c_vp, ctypes.POINTER(CompressInfo), c_vp)
+_sig("hc_compress_plain_db", _st, c_vp, c_vp, c_vp, c_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+     ctypes.c_uint32, c_vp, ctypes.POINTER(CompressInfo), c_vp)
+_sig("hc_plan_plain_db", _st, c_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+     ctypes.c_uint32, c_u32p, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(CompressInfo))
 _sig("hc_compress_batch", _st, c_vp, c_vp, c_vp, ctypes.POINTER(Query), ctypes.c_uint32, c_vp)
 _sig("hc_graph_create", _st, c_vp, c_vp, c_vp, ctypes.POINTER(Query), ctypes.c_uint32, ctypes.POINTER(c_vp))
 _sig("hc_graph_launch", _st, c_vp, c_vp)
@@ -162,6 +166,7 @@ EXPORTED = [
     "hc_keygen",
     "hc_sk_destroy", "hc_pk_destroy", "hc_galois_keygen", "hc_gk_destroy", "hc_plan",
     "hc_db_upload", "hc_db_destroy", "hc_encrypt", "hc_compress", "hc_compress_batch",
+    "hc_compress_plain_db", "hc_plan_plain_db",
     "hc_decrypt", "hc_decompress", "hc_ntt", "hc_rotate", "hc_rotate_level", "hc_rotate_level_noalloc", "hc_mod_switch",
     "hc_rotate_hoisted", "hc_mul_plain",
     "hc_modup", "hc_moddown", "hc_sample", "hc_encode_diagonal", "hc_export_sk", "hc_export_pk",
@@ -271,6 +276,31 @@ class Context:
         _check(_lib.hc_plan(self.h, N, ncol, t_bound, comp_level, out_level, _np_ptr(arr, ctypes.c_uint32),
                             ctypes.byref(cap), ctypes.byref(info)), "hc_plan")
         return [int(x) for x in arr[:cap.value]], info.as_dict()
+
+    def plan_plain_db(self, N, ncol, t_bound, comp_level=0, out_level=0):
+        """Key set and counts of the unencrypted-database form."""
+        cnt = ctypes.c_uint32(0)
+        info = CompressInfo()
+        st = _lib.hc_plan_plain_db(self.h, N, ncol, t_bound, comp_level, out_level, None, ctypes.byref(cnt),
+                                   ctypes.byref(info))
+        if st not in (HC_OK, HC_EINVAL) or (st == HC_EINVAL and cnt.value == 0):
+            _check(st, "hc_plan_plain_db")
+        arr = np.zeros(max(cnt.value, 1), dtype=np.uint32)
+        cap = ctypes.c_uint32(len(arr))
+        _check(_lib.hc_plan_plain_db(self.h, N, ncol, t_bound, comp_level, out_level,
+                                     _np_ptr(arr, ctypes.c_uint32), ctypes.byref(cap), ctypes.byref(info)),
+               "hc_plan_plain_db")
+        return [int(x) for x in arr[:cap.value]], info.as_dict()
+
+    def compress_plain_db(self, gk, db, ct_v, N, t_bound, out=None, stream=None, comp_level=0, out_level=0):
+        """The unencrypted-database form: (out buffer, info), like compress()."""
+        out = self.ct_tensor(1)[0] if out is None else out
+        info = CompressInfo()
+        _check(_lib.hc_compress_plain_db(self.h, gk.h, db.h if db is not None else None,
+                                         _dev(ct_v, self.ct_words(N), "ct_v"), N, t_bound, comp_level, out_level,
+                                         _dev(out, 2 * self.L * self.n, "out"), ctypes.byref(info),
+                                         _stream(stream)), "hc_compress_plain_db")
+        return out, info.as_dict()
 
     def diag_prepare(self, N, ncol, t_bound, comp_level=0):
         """Encode and keep resident the diagonals these compressions use; returns the
