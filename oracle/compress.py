@@ -292,15 +292,16 @@ def default_level(pr):
     return min(lvl, pr.L)
 
 
-def compress(pr, sched, cts_v, db, gks, level=None, out_level=None):
+def compress(pr, sched, cts_v, db, gks, level=None, out_level=None, given=None):
     """Comp of Alg. 7 step 3 on ciphertexts of v (and Mask, step 2).
 
     cts_v: n_ct ciphertexts of the index vector; db: ncol value columns of
     length N; gks: Galois keys by element; level: ciphertext primes kept for
     Comp (None: default_level); out_level: primes of the answer (None: the Comp
     level; fewer: the merged output is modulus-switched down to them). Returns
-    one ciphertext at out_level."""
-    out = _compress(pr, sched, cts_v, db, gks, level)
+    one ciphertext at out_level. given: instead of masking db, the ciphertexts of
+    every value vector d_c directly ([ncol][n_ct], at the full modulus; Alg. 5)."""
+    out = _compress(pr, sched, cts_v, db, gks, level, given)
     lvl = len(out.c0.mods)
     if out_level is None or out_level == lvl:
         return out
@@ -309,12 +310,17 @@ def compress(pr, sched, cts_v, db, gks, level=None, out_level=None):
     return bfv.mod_switch(bfv.at_level(pr, lvl), out, out_level)
 
 
-def _compress(pr, sched, cts_v, db, gks, level):
-    if len(cts_v) != sched.n_ct or len(db) != sched.ncol or any(len(col) < sched.N for col in db):
-        raise ScheduleError("inputs do not match the schedule")
+def _compress(pr, sched, cts_v, db, gks, level, given=None):
+    if given is not None:
+        if len(cts_v) != sched.n_ct or len(given) != sched.ncol or any(len(g) != sched.n_ct for g in given):
+            raise ScheduleError("inputs do not match the schedule")
+        masked = [list(g) for g in given]
+    else:
+        if len(cts_v) != sched.n_ct or len(db) != sched.ncol or any(len(col) < sched.N for col in db):
+            raise ScheduleError("inputs do not match the schedule")
+        masked = [[mask(pr, cts_v[i], db[c], i) for i in range(sched.n_ct)]
+                  for c in range(sched.ncol)]
     level = default_level(pr) if level is None else level
-    masked = [[mask(pr, cts_v[i], db[c], i) for i in range(sched.n_ct)]
-              for c in range(sched.ncol)]
     if level < pr.L:
         cts_v = [bfv.mod_switch(pr, ct, level) for ct in cts_v]
         masked = [[bfv.mod_switch(pr, ct, level) for ct in row] for row in masked]

@@ -581,3 +581,131 @@ def test_plain_db_diagonal_rows():
     z = C.diagonal_slots_db(p, nh, s, B, (0, 1), 0, 0, (1, None), db, 30)
     assert not z[1].any()                                                # a missing second vector
     assert z[0, 15] == 0                                                 # record 30 + 15 is past the end
+
+
+# --------------------------------------------------------------------------- ciphertext products
+
+def int_negacyclic(a, b):
+    n = len(a)
+    out = [0] * n
+    for i in range(n):
+        for j in range(n):
+            if i + j < n:
+                out[i + j] += a[i] * b[j]
+            else:
+                out[i + j - n] -= a[i] * b[j]
+    return out
+
+
+def test_exact_negacyclic_is_the_integer_product():
+    from oracle import mult
+    r = np.random.default_rng(20)
+    for n, bits in ((8, 70), (16, 300), (32, 1000)):
+        a = [int(x) - (1 << (bits - 1)) for x in r.integers(0, 1 << 62, n)]
+        a = [x * (1 << (bits - 62)) + int(y) for x, y in zip(a, r.integers(0, 1 << 30, n))]
+        b = [int(x) * (1 << (bits - 62)) - int(y) for x, y in zip(r.integers(-(1 << 61), 1 << 61, n),
+                                                                   r.integers(0, 1 << 40, n))]
+        assert mult.exact_negacyclic(a, b) == int_negacyclic(a, b)
+
+
+@pytest.fixture(scope="module")
+def deep():
+    import workloads as W
+    r = W.RINGS["ring-1024-deep"]
+    pr = make_params(r.n, r.p, r.L, r.q_bits, r.K, r.p_bits)
+    from oracle import mult
+    sk, pk = bfv.keygen(pr, bytes([1] * 32))
+    rk = mult.relin_keygen(pr, sk, bytes([2] * 32))
+    return pr, sk, pk, rk
+
+
+def phase_three(pr, sk, z):
+    """[z0 + z1 s + z2 s^2]_Q, decoded (the tensor's decryption)."""
+    s = sk.on(pr.q)
+    v = z[0] + z[1] * s + z[2] * (s * s)
+    x = [bfv.crt(v.c[:, i], pr.q) for i in range(pr.n)]
+    return slots.decode([((2 * pr.p * xi + pr.Q) // (2 * pr.Q)) % pr.p for xi in x], pr)
+
+
+def test_tensor_and_product_decrypt_to_slotwise_product(deep):
+    from oracle import mult
+    pr, sk, pk, rk = deep
+    r = np.random.default_rng(21)
+    a = r.integers(0, pr.p, size=(2, pr.nh))
+    b = r.integers(0, pr.p, size=(2, pr.nh))
+    ca = bfv.encrypt(pr, pk, a, bytes([3] * 32))
+    cb = bfv.encrypt(pr, pk, b, bytes([4] * 32))
+    want = a * b % pr.p
+    assert np.array_equal(phase_three(pr, sk, mult.tensor(pr, ca, cb)), want)
+    prod = mult.mul(pr, ca, cb, rk)
+    assert np.array_equal(bfv.decrypt(pr, sk, prod), want)
+    assert bfv.noise_bits(pr, sk, prod) < bfv.noise_budget_bits(pr) - 200
+
+
+def test_relin_key_encrypts_gadget_times_s_squared(deep):
+    """b_j + a_j s = e_j + P (Q/D_j) [(Q/D_j)^-1]_{D_j} s^2 over PQ with e_j small."""
+    pr, sk, pk, rk = deep
+    s = sk.on(pr.qp)
+    s2 = s * s
+    for j, (b, a) in enumerate(rk.digits):
+        e = b + a * s - s2.scale([bfv.gadget_constant(pr, j, m) for m in pr.qp])
+        for i, m in enumerate(pr.qp):
+            cen = np.where(e.c[i] > m // 2, e.c[i].astype(object) - m, e.c[i].astype(object))
+            assert max(abs(int(x)) for x in cen) <= 19
+
+
+def test_power_and_fermat_index_vector(deep):
+    """Power_e slot-wise for small e, and Power_{p-1} = the index vector (Fermat)."""
+    from oracle import mult
+    pr, sk, pk, rk = deep
+    r = np.random.default_rng(22)
+    x = r.integers(0, pr.p, size=(2, pr.nh))
+    x[0, :40] = 0
+    cx = bfv.encrypt(pr, pk, x, bytes([5] * 32))
+    for e in (2, 3, 5):
+        assert np.array_equal(bfv.decrypt(pr, sk, mult.power(pr, cx, e, rk)),
+                              np.array([[pow(int(v), e, pr.p) for v in row] for row in x]))
+    v = mult.power(pr, cx, pr.p - 1, rk)
+    assert np.array_equal(bfv.decrypt(pr, sk, v), (x != 0).astype(np.int64))
+    assert bfv.noise_bits(pr, sk, v) < bfv.noise_budget_bits(pr) - 8
+
+
+def test_match_is_the_exact_match_predicate(deep):
+    """Match (Alg. 7 step 1) for keys with N not a multiple of n: 1 exactly where the
+    record's key equals the query, 0 elsewhere and past the last record."""
+    import workloads as W
+    from oracle import mult
+    pr, sk, pk, rk = deep
+    N = pr.n + 300
+    keys, x, v = W.match_inputs(N, 9, pr.p)
+    cx = bfv.encrypt(pr, pk, np.full((2, pr.nh), x), bytes([6] * 32))
+    out = mult.match(pr, cx, keys, rk)
+    got = np.concatenate([bfv.decrypt(pr, sk, c).reshape(-1) for c in out])
+    want = np.zeros(2 * pr.n, dtype=np.int64)
+    want[:N] = v
+    assert np.array_equal(got, want)
+
+
+def test_generic_comp_recovers_sparse_vector(deep):
+    """Alg. 5 on ciphertexts of d alone: v = Power_{p-1}(d), Comp of (v, d); the answer
+    decrypts to (C v, C d) (Eq. (1)) and decompresses to d's support and values."""
+    from oracle import mult
+    pr, sk, pk, rk = deep
+    N, t = pr.n, 6
+    r = np.random.default_rng(23)
+    d = np.zeros(N, dtype=np.int64)
+    pos = r.choice(N, t, replace=False)
+    d[pos] = r.integers(1, pr.p, t)
+    sc = C.make_schedule(pr.n, pr.p, N, 1, t)
+    gks = {k: bfv.galois_keygen(pr, sk, k, bytes([7] * 32)) for k in sc.keys}
+    cd = [bfv.encrypt(pr, pk, slots.vector_to_slot_matrices(d, pr.n, 1)[0], bytes([8] * 32))]
+    out = mult.compress_generic(pr, sc, cd, gks, rk, out_level=1)
+    p1 = bfv.at_level(pr, 1, keyswitch=False)
+    dec = bfv.decrypt(p1, sk, out)
+    v = (d != 0).astype(np.int64)
+    exp = C.expected_bands(sc, v, [d])
+    assert C.band_slots(sc, dec, 0) == exp[0]
+    idx, vals = D.decompress_group(pr.p, N, *[list(x) for x in C.band_slots(sc, dec, 0)][:1],
+                                   [C.band_slots(sc, dec, 0)[1]])
+    assert idx == sorted(int(i) + 1 for i in pos)
+    assert vals[0] == [int(d[i - 1]) for i in idx]

@@ -44,6 +44,8 @@ RINGS = {
     "ring-1024-p12289": Ring(1024, 12289, 2, 54, 1, 60),
     # 60-bit ciphertext primes: the diagonal sums fold every 8 terms
     "ring-1024-q60": Ring(1024, 12289, 2, 60, 1, 61),
+    # ten 60-bit primes: room for Power_{p-1} (x^3, then twelve squarings at p = 12289)
+    "ring-1024-deep": Ring(1024, 12289, 10, 60, 2, 61),
 }
 
 
@@ -106,6 +108,18 @@ def query_inputs(wl: Workload, query=0, t=None, N=None):
     v = index_vector(rng, N, t)
     db = value_columns(rng, N, wl.ncol, wl.values, ring.p)
     return v, db
+
+
+def match_inputs(N, t, p, seed=0):
+    """Exact-match workload: N record keys uniform in Z_p \\ {x}, t of them set to the
+    query key x (distinct positions); returns (keys, x, index vector)."""
+    rng = rng_for(0x3A7C, seed)
+    x = int(rng.integers(1, p))
+    keys = rng.integers(0, p - 1, size=N, dtype=np.int64)
+    keys = np.where(keys >= x, keys + 1, keys)  # every value but x
+    v = index_vector(rng, N, t)
+    keys = np.where(v == 1, x, keys).astype(np.uint32)
+    return keys, x, v
 
 
 def zlib_id(name):
