@@ -222,6 +222,52 @@ typedef struct {
 hc_status hc_compress_batch(hc_context* ctx, const hc_gk* gk, const hc_db* db,
                             hc_query* q, uint32_t nq, hipStream_t stream);
 
+/* ------------------------------------------------------------------ ciphertext products (Alg. 5, Alg. 7 step 1) */
+
+/* Relinearisation key: the key-switching key from s^2 to s, built like a Galois key
+ * with s^2 in place of sigma_k(s) (digit j: b_j = [-a_j s + e_j + P (Q/D_j)
+ * [(Q/D_j)^-1]_{D_j} s^2]_{PQ}, a_j uniform; stream tags "rk_a" / "rk_e", object
+ * = digit). Returned as a key set holding one key, under element 1; free it with
+ * hc_gk_destroy. Synchronises. */
+hc_status hc_relin_keygen(hc_context* ctx, const hc_sk* sk, const uint8_t seed[32], hc_gk** rk);
+
+/* Product of two ciphertexts at the full level L (device [2][L][n] each, coefficient
+ * domain; ct_out may alias an input): the exact rounding round(p/Q e) mod Q of the
+ * integer tensor e = (a0 b0, a0 b1 + a1 b0, a1 b1) of the centred lifts, computed
+ * exactly in RNS over Q and an auxiliary basis of L + 1 primes, then relinearised
+ * with rk (the key switch of the s^2 component, added in). Decrypts to the
+ * slot-wise product while the noise stays inside the budget (BFV multiplication
+ * grows it by about log2(2 p n) bits plus the inputs' noise). Synchronises.
+ * Errors: HC_ENOKEY (rk is not a relinearisation key), HC_EINVAL, HC_ENOMEM. */
+hc_status hc_mul(hc_context* ctx, const hc_gk* rk, const uint64_t* ct_a, const uint64_t* ct_b, uint64_t* ct_out,
+                 hipStream_t stream);
+
+/* ct_in^exponent slot-wise (exponent >= 1) by left-to-right binary exponentiation of
+ * hc_mul products (after the leading bit: square, then multiply by the input for every
+ * set bit). With exponent p - 1 this is the paper's Power_{p-1}: 1 in every nonzero slot,
+ * 0 elsewhere (Fermat). Synchronises. Errors: as hc_mul. */
+hc_status hc_power(hc_context* ctx, const hc_gk* rk, const uint64_t* ct_in, uint32_t exponent, uint64_t* ct_out,
+                   hipStream_t stream);
+
+/* Match (Alg. 7 step 1) for the exact-match predicate P(x, (k_i, v_i)) = [k_i = x] of
+ * the paper's key-value example: from ct_x, a ciphertext of the query key x in every
+ * slot ([2][L][n]), and the record keys (column 0 of `keys`, uploaded with
+ * hc_db_upload), the index-vector ciphertexts ct_v [ceil(N/n)][2][L][n] with
+ * v_r = 1 - (x - k_r)^(p-1): the query minus the keys' plaintext, Power_{p-1}, one minus
+ * the result; in the last ciphertext the slots past record N are multiplied by 0.
+ * Their output feeds hc_compress as ct_v. Synchronises. Errors: as hc_mul. */
+hc_status hc_match(hc_context* ctx, const hc_gk* rk, const hc_db* keys, const uint64_t* ct_x, uint64_t N,
+                   uint64_t* ct_v, hipStream_t stream);
+
+/* Comp of Alg. 5 on ciphertexts of a sparse vector d alone (no index vector given):
+ * v = Power_{p-1}(d) ciphertext by ciphertext at the full level, then the compression
+ * of the pair (v, d) exactly as hc_compress with one value column whose masked
+ * ciphertexts are d's own. ct_d: device [ceil(N/n)][2][L][n]. Other arguments as
+ * hc_compress (gk: hc_plan's key set for ncol = 1). Synchronises. */
+hc_status hc_compress_generic(hc_context* ctx, const hc_gk* gk, const hc_gk* rk, const uint64_t* ct_d, uint64_t N,
+                              uint32_t t_bound, uint32_t comp_level, uint32_t out_level, uint64_t* ct_out,
+                              hc_compress_info* info, hipStream_t stream);
+
 /* ------------------------------------------------------------------ captured compressions */
 
 typedef struct hc_graph hc_graph;

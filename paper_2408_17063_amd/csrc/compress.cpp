@@ -183,7 +183,8 @@ hc_status batch_shape(const Ctx& c, const hc_gk* gk, const hc_db* db, std::vecto
         if (q.pl.level != Lc) return HC_EINVAL;
         for (uint32_t k : q.pl.keys)
             if (!find_key(gk, k)) return HC_ENOKEY;
-        if (q.pl.ncol && (!db || db->ncol != q.pl.ncol || db->N < q.pl.N)) return HC_EINVAL;
+        if (q.ct_d ? q.pl.ncol != 1 : (q.pl.ncol && (!db || db->ncol != q.pl.ncol || db->N < q.pl.N)))
+            return HC_EINVAL;
         q.sizes(c);
         total += q.bytes(c);
         max_jobs = std::max<size_t>({max_jobs, q.ub, q.baby, q.gi, (size_t)q.pl.bands});
@@ -270,6 +271,13 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
         for (auto& q : qs) {
             HC_CHECK(hipMemcpyAsync(q.ctf, q.ct_v, sizeof(uint64_t) * q.CWF * q.pl.n_ct, hipMemcpyDeviceToDevice, st));
             ntt64(c, q.ctf, (size_t)c.L * n, 2 * (int)q.pl.n_ct, 0, c.L, false, st);
+            if (q.ct_d) {  // the value vector given (generic Comp): no Mask
+                uint64_t* dst = q.ctf + (size_t)q.pl.n_ct * q.CWF;
+                HC_CHECK(hipMemcpyAsync(dst, q.ct_d, sizeof(uint64_t) * q.CWF * q.pl.n_ct, hipMemcpyDeviceToDevice,
+                                        st));
+                ntt64(c, dst, (size_t)c.L * n, 2 * (int)q.pl.n_ct, 0, c.L, false, st);
+                continue;
+            }
             if (q.pl.ncol > 0)
                 for (uint32_t i = 0; i < q.pl.n_ct; i++)
                     mj.push_back(MaskJob{q.ctf + i * q.CWF, q.ctf + ((size_t)q.pl.n_ct + i) * q.CWF,

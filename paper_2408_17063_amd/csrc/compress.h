@@ -32,6 +32,9 @@ inline size_t rup(size_t b) { return (b + 255) & ~(size_t)255; }
 // One query of a batch and its device regions.
 struct QueryRun {
     const uint64_t* ct_v = nullptr;
+    // the value vector's ciphertexts themselves (generic Comp, Alg. 5: one column, no
+    // database to mask), [n_ct][2][L][n] coefficient domain; nullptr: Mask the database
+    const uint64_t* ct_d = nullptr;
     uint64_t* ct_out = nullptr;
     Plan pl;
     size_t CW = 0, PW = 0, CWF = 0, ntot = 0, ub = 0, baby = 0, gi = 0;

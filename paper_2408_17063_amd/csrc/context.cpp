@@ -180,6 +180,7 @@ static hc_status upload(Ctx& c, T** dst, const std::vector<T>& src) {
 hc_status encode_plain(Ctx& c, uint64_t* out, const uint32_t* host_slots, int count, bool mont,
                        hipStream_t st);
 hc_status build_ms_tables(Ctx& c);
+hc_status build_mult_tables(Ctx& c);
 
 }  // namespace hc
 
@@ -230,12 +231,24 @@ extern "C" hc_status hc_context_create(const hc_params* prm, int device, hc_cont
             delete cp;
             return HC_EINVAL;
         }
-    const int nq = c.nq, L = c.L, K = c.K, logn = c.logn;
+    // the auxiliary basis B of ciphertext products (L + 1 primes below 2^61, distinct from
+    // every q_i and p_k): the tensor of two centred ciphertexts is exact over Q and B
+    {
+        std::vector<uint64_t> skip = c.primes, bs;
+        if (!ntt_primes(61, c.L + 1, 2 * n, skip, bs)) {
+            delete cp;
+            return HC_EINVAL;
+        }
+        c.nb = (int)bs.size();
+        c.primes.insert(c.primes.end(), bs.begin(), bs.end());
+    }
+    c.ntab = c.nq + c.nb;
+    const int nq = c.nq, L = c.L, K = c.K, logn = c.logn, ntab = c.ntab;
 
-    // ---- NTT tables for every prime
-    c.h_tw.assign((size_t)nq * 4 * n, 0);
-    std::vector<uint64_t> ninv(4 * nq), qinv(nq), r2(nq);
-    for (int i = 0; i < nq; i++) {
+    // ---- NTT tables for every prime (Q, P and B)
+    c.h_tw.assign((size_t)ntab * 4 * n, 0);
+    std::vector<uint64_t> ninv(4 * ntab), qinv(ntab), r2(ntab);
+    for (int i = 0; i < ntab; i++) {
         uint64_t q = c.primes[i];
         uint64_t psi = root_2n(q, n), psii = h_invmod(psi, q);
         uint64_t* t = c.h_tw.data() + (size_t)i * 4 * n;
@@ -394,6 +407,7 @@ extern "C" hc_status hc_context_create(const hc_params* prm, int device, hc_cont
     }
     if ((st = ntt_build_tw2(c)) != HC_OK) { hc_context_destroy(cp); return st; }
     if ((st = build_ms_tables(c)) != HC_OK) { hc_context_destroy(cp); return st; }
+    if ((st = build_mult_tables(c)) != HC_OK) { hc_context_destroy(cp); return st; }
     if ((st = upload_keccak_constants(rc, rho, c.h_cdt.data())) != HC_OK) { hc_context_destroy(cp); return st; }
 
     // ---- row masks [1;0] and [0;1] as plaintext multipliers
@@ -441,7 +455,7 @@ extern "C" void hc_context_trim(hc_context* c) {
 
 extern "C" hc_status hc_context_primes(const hc_context* c, uint64_t* out) {
     if (!c || !out) return HC_EINVAL;
-    for (size_t i = 0; i < c->primes.size(); i++) out[i] = c->primes[i];
+    for (int i = 0; i < c->nq; i++) out[i] = c->primes[i];
     return HC_OK;
 }
 

@@ -65,9 +65,11 @@ struct hc_context {
     int cus = 0;  // compute units of the device
     int logn = 0, n = 0, nh = 0;
     int L = 0, K = 0, dnum = 0, alpha = 0, nq = 0;
+    int nb = 0;    // primes of the auxiliary basis B of ciphertext products (prime indices nq..nq+nb-1)
+    int ntab = 0;  // primes with NTT tables: nq + nb
     uint64_t p = 0;
     uint32_t zeta = 0;
-    std::vector<uint64_t> primes;          // q_1..q_L, p_1..p_K
+    std::vector<uint64_t> primes;          // q_1..q_L, p_1..p_K, then the product basis b_1..b_nb
     std::vector<uint64_t> h_qinv, h_r2;    // Montgomery constants per prime
     std::vector<uint64_t> h_tw;            // host copy of the NTT tables [nq][2][n][2]
     std::vector<uint32_t> h_twp;           // mod-p tables [2][n][2]
@@ -112,6 +114,10 @@ struct hc_context {
     std::map<std::tuple<uint32_t, uint32_t, int>, DiagTab> diag_tabs;
 
     uint64_t* d_scratch = nullptr;  // this device's fixed allocation-free scratch (context.cpp)
+
+    // exact base conversion constants of ciphertext products (mult.hip), device, one block:
+    // see MultTab there
+    uint64_t* d_mult = nullptr;
 
     // kernel variants picked by hc_autotune / hc_tune_set (bit-neutral): the diagonal
     // multiply-accumulate's (terms per stage, stages in flight) and the 64-bit NTT

@@ -458,10 +458,14 @@ extern "C" void hc_pk_destroy(hc_pk* pk) {
     delete pk;
 }
 
-extern "C" hc_status hc_galois_keygen(hc_context* cp, const hc_sk* sk, const uint32_t* elements,
-                                      uint32_t count, const uint8_t seed[32], hc_gk** out) {
-    if (!cp || !sk || !seed || !out || (count && !elements)) return HC_EINVAL;
-    Ctx& c = *cp;
+namespace hc {
+
+// Key-switching keys to s from sigma_k(s) (Galois keys, one per element; tags gk_a /
+// gk_e, object (k << 16) | digit) or from s^2 (relin: one key stored under element 1;
+// tags rk_a / rk_e, object = digit). Digit j of the key for target t:
+// b_j = [-a_j s + e_j + P (Q/D_j) [(Q/D_j)^-1]_{D_j} t]_{PQ}.
+hc_status ks_keygen(Ctx& c, const hc_sk* sk, const uint32_t* elements, uint32_t count, const uint8_t seed[32],
+                    bool relin, hc_gk** out) {
     for (uint32_t i = 0; i < count; i++)
         if ((elements[i] & 1) == 0 || elements[i] >= 2u * c.n) return HC_EINVAL;
     HC_CHECK(hipSetDevice(c.device));
@@ -483,8 +487,10 @@ extern "C" hc_status hc_galois_keygen(hc_context* cp, const hc_sk* sk, const uin
         for (int a = 0; a < c.alpha; a++) g[(size_t)j * nq + j * c.alpha + a] = hmod[j * c.alpha + a];
     HC_CHECK(hipMemcpy(d_g, g.data(), sizeof(uint64_t) * g.size(), hipMemcpyHostToDevice));
     std::vector<uint32_t> uniq(elements, elements + count);
+    if (relin) uniq.assign(1, 1u);
     std::sort(uniq.begin(), uniq.end());
     uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+    const uint64_t tag_a = tag_u64(relin ? "rk_a" : "gk_a"), tag_e = tag_u64(relin ? "rk_e" : "gk_e");
     for (uint32_t k : uniq) {
         uint64_t* key = nullptr;
         if (hipMalloc((void**)&key, sizeof(uint64_t) * c.dnum * 2 * nq * n) != hipSuccess) {
@@ -493,14 +499,17 @@ extern "C" hc_status hc_galois_keygen(hc_context* cp, const hc_sk* sk, const uin
             return HC_ENOMEM;
         }
         gk->keys[k] = key;
-        k_permute(c, d_rs, sk->d_s_mont, (int)nq, k, 1, 0, st);  // sigma_k(s), NTT domain
+        if (relin)  // s^2 in Montgomery form: (s R)(s R) R^-1
+            k_mul_mont(c, d_rs, sk->d_s_mont, sk->d_s_mont, 0, (int)nq, st);
+        else
+            k_permute(c, d_rs, sk->d_s_mont, (int)nq, k, 1, 0, st);  // sigma_k(s), NTT domain
         for (int j = 0; j < c.dnum; j++) {
-            uint64_t obj = ((uint64_t)k << 16) | (uint64_t)j;
+            uint64_t obj = relin ? (uint64_t)j : (((uint64_t)k << 16) | (uint64_t)j);
             uint64_t* b = key + (size_t)j * 2 * nq * n;
             uint64_t* a = b + nq * n;
-            k_sample_uniform(c, a, seed, tag_u64("gk_a"), obj, 0, (int)nq, st);
+            k_sample_uniform(c, a, seed, tag_a, obj, 0, (int)nq, st);
             ntt64(c, a, nq * n, 1, 0, (int)nq, false, st);
-            k_sample_small(c, d_e, nullptr, seed, tag_u64("gk_e"), obj, 2, 0, (int)nq, st);
+            k_sample_small(c, d_e, nullptr, seed, tag_e, obj, 2, 0, (int)nq, st);
             ntt64(c, d_e, nq * n, 1, 0, (int)nq, false, st);
             k_keyrow(c, b, d_e, a, sk->d_s_mont, d_rs, d_g + (size_t)j * nq, 0, (int)nq, st);
         }
@@ -512,6 +521,16 @@ extern "C" hc_status hc_galois_keygen(hc_context* cp, const hc_sk* sk, const uin
     HC_CHECK(hipFree(d_g));
     *out = gk;
     return HC_OK;
+}
+
+}  // namespace hc
+
+using namespace hc;
+
+extern "C" hc_status hc_galois_keygen(hc_context* cp, const hc_sk* sk, const uint32_t* elements,
+                                      uint32_t count, const uint8_t seed[32], hc_gk** out) {
+    if (!cp || !sk || !seed || !out || (count && !elements)) return HC_EINVAL;
+    return ks_keygen(*cp, sk, elements, count, seed, false, out);
 }
 
 extern "C" void hc_gk_destroy(hc_gk* gk) {

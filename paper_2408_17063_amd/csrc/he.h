@@ -51,5 +51,11 @@ hc_status mod_switch_coef(const Ctx& c, uint64_t* out, const uint64_t* in, int c
 // the switching constants of every level pair (context creation)
 hc_status build_ms_tables(Ctx& c);
 const uint64_t* find_key(const hc_gk* gk, uint32_t k);
+// key-switching keys from sigma_k(s) for each element, or (relin) from s^2 under element 1
+hc_status ks_keygen(Ctx& c, const hc_sk* sk, const uint32_t* elements, uint32_t count, const uint8_t seed[32],
+                    bool relin, hc_gk** out);
+// Power_e of n_ct ciphertexts at the full level (coefficient domain; out may alias in)
+hc_status power_many(Ctx& c, const hc_gk* rk, const uint64_t* in, uint32_t n_ct, uint32_t e, uint64_t* out,
+                     hipStream_t st);
 
 }  // namespace hc

@@ -1,0 +1,520 @@
+// Ciphertext products and what is built on them: Power (Alg. 5's Power_{p-1}), Match
+// (Alg. 7 step 1, exact-match predicate) and the generic Comp of Alg. 5.
+//
+// A product of (a0, a1) and (b0, b1) at the full modulus Q is the exact rounding
+// z = round(p/Q e) mod Q of the integer tensor e = (a0 b0, a0 b1 + a1 b0, a1 b1) of
+// the centred lifts (representatives in (-Q/2, Q/2)), followed by relinearisation
+// of z2. Everything is exact integer arithmetic in RNS:
+//  1. each centred lift is extended from Q to an auxiliary basis B of L + 1 primes
+//     below 2^61 (prod B > n Q, so |e| < Q prod B / 2 and e is determined by its
+//     residues over Q and B) by mixed-radix conversion (MRC): the digits y_i of the
+//     lift in radix (q_0, q_0 q_1, ...) are exact, their comparison with the digits of
+//     (Q - 1)/2 decides the sign, and the value is re-evaluated mod each b_j;
+//  2. forward NTTs over Q and B, the three pointwise products, inverse NTTs;
+//  3. scale and round per coefficient: r = (p e + (Q-1)/2) mod Q is recovered exactly by
+//     MRC over Q, z = (p e + (Q-1)/2 - r) / Q is then an exact division mod each b_j,
+//     and z (|z| < prod B / 2) is brought back to Q by MRC over B with its sign;
+//  4. relinearisation: (z0, z2) is key-switched like a rotation with k = 1 by the key
+//     for s^2 (ModUp, inner product over PQ, ModDown) and z1 is added to the second
+//     component.
+// One thread handles one coefficient of every polynomial of a step, so the digits
+// stay in registers.
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "compress.h"
+
+namespace hc {
+
+// Device constants of the exact conversions (one allocation, word offsets below).
+// Multipliers are stored in Montgomery form mod the prime they multiply under.
+struct MultTab {
+    const uint64_t* invq;   // [L][L]   q_k^-1 mod q_i (k < i), Montgomery mod q_i
+    const uint64_t* hq;     // [L]      digits of (Q-1)/2 in the radix of Q
+    const uint64_t* mqb;    // [nb][L]  prod_{k<i} q_k mod b_j, Montgomery mod b_j
+    const uint64_t* qmodb;  // [nb]     Q mod b_j
+    const uint64_t* qinvb;  // [nb]     Q^-1 mod b_j, Montgomery mod b_j
+    const uint64_t* hmod;   // [L + nb] (Q-1)/2 mod q_i, then mod b_j
+    const uint64_t* pmont;  // [L + nb] p in Montgomery form mod q_i, then mod b_j
+    const uint64_t* invb;   // [nb][nb] b_k^-1 mod b_j (k < j), Montgomery mod b_j
+    const uint64_t* hb;     // [nb]     digits of (prod B - 1)/2 in the radix of B
+    const uint64_t* mbq;    // [L][nb]  prod_{k<j} b_k mod q_i, Montgomery mod q_i
+    const uint64_t* bmodq;  // [L]      prod B mod q_i
+};
+constexpr int MAX_DIG = 48;  // limit on L + 1 (context creation keeps L + K <= 64; products need L <= 47)
+
+static MultTab mult_tab(const Ctx& c) {
+    const int L = c.L, nb = c.nb;
+    const uint64_t* d = c.d_mult;
+    MultTab t;
+    size_t o = 0;
+    t.invq = d + o; o += (size_t)L * L;
+    t.hq = d + o; o += L;
+    t.mqb = d + o; o += (size_t)nb * L;
+    t.qmodb = d + o; o += nb;
+    t.qinvb = d + o; o += nb;
+    t.hmod = d + o; o += L + nb;
+    t.pmont = d + o; o += L + nb;
+    t.invb = d + o; o += (size_t)nb * nb;
+    t.hb = d + o; o += nb;
+    t.mbq = d + o; o += (size_t)L * nb;
+    t.bmodq = d + o;
+    return t;
+}
+
+// host: mixed-radix digits of the integer with residues `res` over `mods`
+static std::vector<uint64_t> h_mrc(const std::vector<uint64_t>& res, const std::vector<uint64_t>& mods) {
+    const size_t m = mods.size();
+    std::vector<uint64_t> y(m);
+    for (size_t i = 0; i < m; i++) {
+        uint64_t t = res[i] % mods[i];
+        for (size_t k = 0; k < i; k++) {
+            const uint64_t yk = y[k] % mods[i];
+            t = (t + mods[i] - yk) % mods[i];
+            t = h_mulmod(t, h_invmod(mods[k] % mods[i], mods[i]), mods[i]);
+        }
+        y[i] = t;
+    }
+    return y;
+}
+
+hc_status build_mult_tables(Ctx& c) {
+    const int L = c.L, nb = c.nb, nq = c.nq;
+    if (L + 1 > MAX_DIG || nb != L + 1) return HC_OK;  // products unavailable (context limit)
+    std::vector<uint64_t> Qp(c.primes.begin(), c.primes.begin() + L),
+        Bp(c.primes.begin() + nq, c.primes.begin() + nq + nb);
+    std::vector<uint64_t> all;
+    // invq
+    for (int i = 0; i < L; i++)
+        for (int k = 0; k < L; k++)
+            all.push_back(k < i ? h_to_mont(h_invmod(Qp[k] % Qp[i], Qp[i]), Qp[i]) : 0);
+    // hq: (Q-1)/2 = (q_i - 1)/2 mod q_i
+    std::vector<uint64_t> hres(L);
+    for (int i = 0; i < L; i++) hres[i] = (Qp[i] - 1) / 2;
+    for (uint64_t x : h_mrc(hres, Qp)) all.push_back(x);
+    // mqb
+    for (int j = 0; j < nb; j++) {
+        uint64_t pr = 1;
+        for (int i = 0; i < L; i++) {
+            all.push_back(h_to_mont(pr, Bp[j]));
+            pr = h_mulmod(pr, Qp[i] % Bp[j], Bp[j]);
+        }
+    }
+    // qmodb, qinvb
+    std::vector<uint64_t> qmb(nb);
+    for (int j = 0; j < nb; j++) {
+        uint64_t pr = 1;
+        for (int i = 0; i < L; i++) pr = h_mulmod(pr, Qp[i] % Bp[j], Bp[j]);
+        qmb[j] = pr;
+        all.push_back(pr);
+    }
+    for (int j = 0; j < nb; j++) all.push_back(h_to_mont(h_invmod(qmb[j], Bp[j]), Bp[j]));
+    // hmod: (Q-1)/2 mod q_i and mod b_j = (Q mod b - 1) 2^-1 mod b
+    for (int i = 0; i < L; i++) all.push_back((Qp[i] - 1) / 2);
+    for (int j = 0; j < nb; j++)
+        all.push_back(h_mulmod((qmb[j] + Bp[j] - 1) % Bp[j], h_invmod(2, Bp[j]), Bp[j]));
+    // pmont
+    for (int i = 0; i < L; i++) all.push_back(h_to_mont(c.p % Qp[i], Qp[i]));
+    for (int j = 0; j < nb; j++) all.push_back(h_to_mont(c.p % Bp[j], Bp[j]));
+    // invb
+    for (int j = 0; j < nb; j++)
+        for (int k = 0; k < nb; k++)
+            all.push_back(k < j ? h_to_mont(h_invmod(Bp[k] % Bp[j], Bp[j]), Bp[j]) : 0);
+    // hb: (prod B - 1)/2 = (b_j - 1)/2 mod b_j
+    std::vector<uint64_t> hbres(nb);
+    for (int j = 0; j < nb; j++) hbres[j] = (Bp[j] - 1) / 2;
+    for (uint64_t x : h_mrc(hbres, Bp)) all.push_back(x);
+    // mbq, bmodq
+    for (int i = 0; i < L; i++) {
+        uint64_t pr = 1;
+        for (int j = 0; j < nb; j++) {
+            all.push_back(h_to_mont(pr, Qp[i]));
+            pr = h_mulmod(pr, Bp[j] % Qp[i], Qp[i]);
+        }
+    }
+    for (int i = 0; i < L; i++) {
+        uint64_t pr = 1;
+        for (int j = 0; j < nb; j++) pr = h_mulmod(pr, Bp[j] % Qp[i], Qp[i]);
+        all.push_back(pr);
+    }
+    HC_CHECK(hipMalloc((void**)&c.d_mult, sizeof(uint64_t) * all.size()));
+    c.owned.push_back(c.d_mult);
+    HC_CHECK(hipMemcpy(c.d_mult, all.data(), sizeof(uint64_t) * all.size(), hipMemcpyHostToDevice));
+    return HC_OK;
+}
+
+// MRC digits of x (residues over m primes starting at prime index p0): y_i < m_i.
+// Digit k is below its own prime; every prime of a basis lies in [2^(t-1), 2^t) for
+// one t, so y_k mod m_i is y_k or y_k - m_i.
+template <int MAXM>
+__device__ __forceinline__ void mrc(uint64_t* y, const uint64_t* x, int m, const uint64_t* mods,
+                                    const uint64_t* qinv, const uint64_t* inv, int p0) {
+    for (int i = 0; i < m; i++) {
+        const uint64_t q = mods[p0 + i], qi = qinv[p0 + i];
+        uint64_t t = x[i];
+        for (int k = 0; k < i; k++) {
+            const uint64_t yk = csub(y[k], q);
+            t = sub_mod(t, yk, q);
+            t = mont_mul(t, inv[(size_t)i * m + k], q, qi);
+        }
+        y[i] = t;
+    }
+}
+
+// x > h for digit vectors (most significant digit last)
+__device__ __forceinline__ bool digits_gt(const uint64_t* y, const uint64_t* h, int m) {
+    for (int i = m - 1; i >= 0; i--) {
+        if (y[i] != h[i]) return y[i] > h[i];
+    }
+    return false;
+}
+
+// out[t][j] = centred lift of in[t] (over Q, coefficient domain) mod b_j, t < count
+__global__ void bext_kernel(uint64_t* __restrict__ out, const uint64_t* __restrict__ in, MultTab tb,
+                            const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv, int n, int L,
+                            int nq, int nb) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int t = blockIdx.z;
+    const uint64_t* a = in + (size_t)t * L * n + x;
+    uint64_t r[MAX_DIG], y[MAX_DIG];
+    for (int i = 0; i < L; i++) r[i] = a[(size_t)i * n];
+    mrc<MAX_DIG>(y, r, L, mods, qinv, tb.invq, 0);
+    const bool neg = digits_gt(y, tb.hq, L);
+    uint64_t* o = out + (size_t)t * nb * n + x;
+    for (int j = 0; j < nb; j++) {
+        const int pj = nq + j;
+        const uint64_t b = mods[pj], bi = qinv[pj];
+        uint64_t v = 0;
+        for (int i = 0; i < L; i++) v = add_mod(v, mont_mul(y[i], tb.mqb[(size_t)j * L + i], b, bi), b);
+        if (neg) v = sub_mod(v, tb.qmodb[j], b);
+        o[(size_t)j * n] = v;
+    }
+}
+
+// e = (a0 b0, a0 b1 + a1 b0, a1 b1) pointwise (NTT domain) on R rows of prime indices
+// prime0 + row; a, b: [2][R][n]; e: [3][R][n]
+__global__ void tensor_kernel(uint64_t* __restrict__ e, const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
+                              const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv,
+                              const uint64_t* __restrict__ r2, int n, int R, int prime0) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int row = blockIdx.y, pi = prime0 + row;
+    const uint64_t q = mods[pi], qi = qinv[pi], rr = r2[pi];
+    const size_t o = (size_t)row * n + x, P = (size_t)R * n;
+    // b to Montgomery form: mont_mul(b, 2^128 mod q) = b 2^64 mod q
+    const uint64_t b0 = mont_mul(b[o], rr, q, qi), b1 = mont_mul(b[P + o], rr, q, qi);
+    const uint64_t a0 = a[o], a1 = a[P + o];
+    e[o] = mont_mul(a0, b0, q, qi);
+    e[P + o] = add_mod(mont_mul(a0, b1, q, qi), mont_mul(a1, b0, q, qi), q);
+    e[2 * P + o] = mont_mul(a1, b1, q, qi);
+}
+
+// z[slot[t]] (over Q, coefficient domain) = round(p e_t / Q) mod Q from e_t over Q (eq)
+// and over B (eb), coefficient domain, t < 3
+__global__ void scale_round_kernel(uint64_t* __restrict__ z, const uint64_t* __restrict__ eq,
+                                   const uint64_t* __restrict__ eb, MultTab tb, const uint64_t* __restrict__ mods,
+                                   const uint64_t* __restrict__ qinv, int n, int L, int nq, int nb, int s0, int s1,
+                                   int s2) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int t = blockIdx.z;
+    const int slot = t == 0 ? s0 : (t == 1 ? s1 : s2);
+    uint64_t r[MAX_DIG], y[MAX_DIG];
+    // r = (p e + H) mod Q, exactly, as MRC digits over Q
+    for (int i = 0; i < L; i++) {
+        const uint64_t q = mods[i], qi = qinv[i];
+        const uint64_t ev = eq[((size_t)t * L + i) * n + x];
+        r[i] = add_mod(mont_mul(ev, tb.pmont[i], q, qi), tb.hmod[i], q);
+    }
+    mrc<MAX_DIG>(y, r, L, mods, qinv, tb.invq, 0);
+    // z mod b_j = (p e + H - r) Q^-1 mod b_j (the division is exact)
+    for (int j = 0; j < nb; j++) {
+        const int pj = nq + j;
+        const uint64_t b = mods[pj], bi = qinv[pj];
+        uint64_t rv = 0;
+        for (int i = 0; i < L; i++) rv = add_mod(rv, mont_mul(y[i], tb.mqb[(size_t)j * L + i], b, bi), b);
+        const uint64_t ev = eb[((size_t)t * nb + j) * n + x];
+        uint64_t v = add_mod(mont_mul(ev, tb.pmont[L + j], b, bi), tb.hmod[L + j], b);
+        v = sub_mod(v, rv, b);
+        r[j] = mont_mul(v, tb.qinvb[j], b, bi);
+    }
+    // z (|z| < prod B / 2) from its residues over B, back to Q
+    mrc<MAX_DIG>(y, r, nb, mods, qinv, tb.invb, nq);
+    const bool neg = digits_gt(y, tb.hb, nb);
+    for (int i = 0; i < L; i++) {
+        const uint64_t q = mods[i], qi = qinv[i];
+        uint64_t v = 0;
+        for (int j = 0; j < nb; j++) v = add_mod(v, mont_mul(y[j], tb.mbq[(size_t)i * nb + j], q, qi), q);
+        if (neg) v = sub_mod(v, tb.bmodq[i], q);
+        z[((size_t)slot * L + i) * n + x] = v;
+    }
+}
+
+// c0 = c0 - Delta m over the first L primes (coefficient domain; m canonical in [0, p))
+__global__ void sub_delta_m_kernel(uint64_t* ct, const uint32_t* m, const uint64_t* mods, const uint64_t* delta,
+                                   int n) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int r = blockIdx.y;
+    const uint64_t q = mods[r];
+    const size_t o = (size_t)r * n + x;
+    ct[o] = sub_mod(ct[o], shoup((uint64_t)m[x], delta[2 * r], delta[2 * r + 1], q), q);
+}
+
+// ct = 1 - ct: (Delta - c0, -c1), Delta on the constant coefficient (coefficient domain)
+__global__ void one_minus_kernel(uint64_t* ct, const uint64_t* mods, const uint64_t* delta, int n, int L) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int r = blockIdx.y, comp = blockIdx.z;
+    const uint64_t q = mods[r];
+    const size_t o = ((size_t)comp * L + r) * n + x;
+    const uint64_t d = (comp == 0 && x == 0) ? delta[2 * r] : 0;
+    ct[o] = sub_mod(d, ct[o], q);
+}
+
+// One product at the full level: out = relin(round(p/Q (a x b))). a, b, out: [2][L][n]
+// coefficient domain (out may alias a or b). Workspace from the arena a_ (reset by the caller).
+static hc_status mul_ct(Ctx& c, Lane& l, KsScratch& ks, const uint64_t* rk, const uint64_t* a, const uint64_t* b,
+                        uint64_t* out, uint64_t* const* buf, hipStream_t st) {
+    const size_t n = c.n;
+    const int L = c.L, nb = c.nb, nq = c.nq;
+    const size_t QW = (size_t)L * n, BW = (size_t)nb * n;
+    uint64_t *aN = buf[0], *bN = buf[1], *aB = buf[2], *bB = buf[3], *eQ = buf[4], *eB = buf[5], *z = buf[6],
+             *ko = buf[7];
+    const MultTab tb = mult_tab(c);
+    const bool sq = a == b;
+    // 1. the centred lifts over B
+    hipLaunchKernelGGL(bext_kernel, dim3((unsigned)((n + 255) / 256), 1, 2), dim3(256), 0, st, aB, a, tb, c.d_mods,
+                       c.d_qinv, (int)n, L, nq, nb);
+    if (!sq)
+        hipLaunchKernelGGL(bext_kernel, dim3((unsigned)((n + 255) / 256), 1, 2), dim3(256), 0, st, bB, b, tb,
+                           c.d_mods, c.d_qinv, (int)n, L, nq, nb);
+    // 2. NTT domain over Q and B, the tensor, back
+    HC_CHECK(hipMemcpyAsync(aN, a, sizeof(uint64_t) * 2 * QW, hipMemcpyDeviceToDevice, st));
+    ntt64(c, aN, QW, 2, 0, L, false, st);
+    ntt64(c, aB, BW, 2, nq, nb, false, st);
+    if (!sq) {
+        HC_CHECK(hipMemcpyAsync(bN, b, sizeof(uint64_t) * 2 * QW, hipMemcpyDeviceToDevice, st));
+        ntt64(c, bN, QW, 2, 0, L, false, st);
+        ntt64(c, bB, BW, 2, nq, nb, false, st);
+    }
+    hipLaunchKernelGGL(tensor_kernel, dim3((unsigned)((n + 255) / 256), L), dim3(256), 0, st, eQ, aN, sq ? aN : bN,
+                       c.d_mods, c.d_qinv, c.d_r2, (int)n, L, 0);
+    hipLaunchKernelGGL(tensor_kernel, dim3((unsigned)((n + 255) / 256), nb), dim3(256), 0, st, eB, aB, sq ? aB : bB,
+                       c.d_mods, c.d_qinv, c.d_r2, (int)n, nb, nq);
+    ntt64(c, eQ, QW, 3, 0, L, true, st);
+    ntt64(c, eB, BW, 3, nq, nb, true, st);
+    // 3. z = round(p e / Q), stored (z0, z2, z1) so that (z0, z2) is a ciphertext to key-switch
+    hipLaunchKernelGGL(scale_round_kernel, dim3((unsigned)((n + 255) / 256), 1, 3), dim3(256), 0, st, z, eQ, eB, tb,
+                       c.d_mods, c.d_qinv, (int)n, L, nq, nb, 0, 2, 1);
+    // 4. relinearisation: (z0 + KS(z2)_0, z1 + KS(z2)_1)
+    ntt64(c, z, QW, 3, 0, L, false, st);
+    std::vector<KsJob> jobs{KsJob{z, ko, rk, 1u, 0}};
+    hc_status s = ks_run(c, l, ks, jobs, nullptr, L, st);
+    if (s != HC_OK) return s;
+    k_add(c, ko + QW, ko + QW, z + 2 * QW, 0, L, 1, QW, st);
+    ntt64(c, ko, QW, 2, 0, L, true, st);
+    HC_CHECK(hipMemcpyAsync(out, ko, sizeof(uint64_t) * 2 * QW, hipMemcpyDeviceToDevice, st));
+    return HC_OK;
+}
+
+// Workspace of products: 8 buffers + key-switching scratch for one job at level L.
+struct MulWs {
+    KsScratch ks;
+    uint64_t* buf[8];
+    uint64_t* t0;  // [2][L][n] spare ciphertexts
+    uint64_t* t1;
+};
+
+static size_t mul_ws_bytes(const Ctx& c) {
+    const size_t QW = (size_t)c.L * c.n, BW = (size_t)c.nb * c.n;
+    return 8 * (2 * QW + 2 * QW + 2 * BW + 2 * BW + 3 * QW + 3 * BW + 3 * QW + 2 * QW + 2 * QW + 2 * QW) +
+           ks_scratch_bytes(c, c.L, 1) + 16 * 256;
+}
+
+static hc_status mul_ws(Ctx& c, Arena& a, MulWs& w) {
+    const size_t QW = (size_t)c.L * c.n, BW = (size_t)c.nb * c.n;
+    w.ks = ks_scratch(c, a, c.L, 1);
+    const size_t sizes[8] = {2 * QW, 2 * QW, 2 * BW, 2 * BW, 3 * QW, 3 * BW, 3 * QW, 2 * QW};
+    for (int i = 0; i < 8; i++) {
+        w.buf[i] = a.take<uint64_t>(sizes[i]);
+        if (!w.buf[i]) return HC_ENOMEM;
+    }
+    w.t0 = a.take<uint64_t>(2 * QW);
+    w.t1 = a.take<uint64_t>(2 * QW);
+    if (!w.t0 || !w.t1 || !w.ks.tmpC) return HC_ENOMEM;
+    return HC_OK;
+}
+
+// out = in^e by left-to-right binary exponentiation (coefficient domain, may alias)
+static hc_status power_ct(Ctx& c, Lane& l, MulWs& w, const uint64_t* rk, const uint64_t* in, uint32_t e,
+                          uint64_t* out, hipStream_t st) {
+    const size_t CW = 2 * (size_t)c.L * c.n;
+    int top = 31;
+    while (top > 0 && !((e >> top) & 1u)) top--;
+    // acc in t0, the input kept in t1 (out may alias in)
+    HC_CHECK(hipMemcpyAsync(w.t1, in, sizeof(uint64_t) * CW, hipMemcpyDeviceToDevice, st));
+    HC_CHECK(hipMemcpyAsync(w.t0, in, sizeof(uint64_t) * CW, hipMemcpyDeviceToDevice, st));
+    for (int bit = top - 1; bit >= 0; bit--) {
+        hc_status s = mul_ct(c, l, w.ks, rk, w.t0, w.t0, w.t0, w.buf, st);
+        if (s != HC_OK) return s;
+        if ((e >> bit) & 1u) {
+            s = mul_ct(c, l, w.ks, rk, w.t0, w.t1, w.t0, w.buf, st);
+            if (s != HC_OK) return s;
+        }
+    }
+    HC_CHECK(hipMemcpyAsync(out, w.t0, sizeof(uint64_t) * CW, hipMemcpyDeviceToDevice, st));
+    return HC_OK;
+}
+
+static hc_status rk_of(const hc_gk* rk, const uint64_t** key) {
+    *key = rk ? find_key(rk, 1u) : nullptr;
+    return *key ? HC_OK : HC_ENOKEY;
+}
+
+// Power_{p-1} of n_ct ciphertexts (device [n_ct][2][L][n]) into out (same layout)
+hc_status power_many(Ctx& c, const hc_gk* rk, const uint64_t* in, uint32_t n_ct, uint32_t e, uint64_t* out,
+                     hipStream_t st) {
+    const uint64_t* key = nullptr;
+    hc_status s = rk_of(rk, &key);
+    if (s != HC_OK) return s;
+    if (!c.d_mult) return HC_EINVAL;
+    stage_reset(c.lane, st);
+    if (c.lane.ws.reserve(mul_ws_bytes(c)) != HC_OK) return HC_ENOMEM;
+    MulWs w;
+    if ((s = mul_ws(c, c.lane.ws, w)) != HC_OK) return s;
+    const size_t CW = 2 * (size_t)c.L * c.n;
+    for (uint32_t i = 0; i < n_ct; i++)
+        if ((s = power_ct(c, c.lane, w, key, in + i * CW, e, out + i * CW, st)) != HC_OK) return s;
+    return HC_OK;
+}
+
+}  // namespace hc
+
+using namespace hc;
+
+extern "C" hc_status hc_relin_keygen(hc_context* cp, const hc_sk* sk, const uint8_t seed[32], hc_gk** rk) {
+    if (!cp || !sk || !seed || !rk) return HC_EINVAL;
+    return ks_keygen(*cp, sk, nullptr, 0, seed, true, rk);
+}
+
+extern "C" hc_status hc_mul(hc_context* cp, const hc_gk* rk, const uint64_t* ct_a, const uint64_t* ct_b,
+                            uint64_t* ct_out, hipStream_t st) {
+    if (!cp || !ct_a || !ct_b || !ct_out) return HC_EINVAL;
+    Ctx& c = *cp;
+    HC_CHECK(hipSetDevice(c.device));
+    const uint64_t* key = nullptr;
+    hc_status s = rk_of(rk, &key);
+    if (s != HC_OK) return s;
+    if (!c.d_mult) return HC_EINVAL;
+    stage_reset(c.lane, st);
+    if (c.lane.ws.reserve(mul_ws_bytes(c)) != HC_OK) return HC_ENOMEM;
+    MulWs w;
+    if ((s = mul_ws(c, c.lane.ws, w)) != HC_OK) return s;
+    if ((s = mul_ct(c, c.lane, w.ks, key, ct_a, ct_b, ct_out, w.buf, st)) != HC_OK) return s;
+    HC_CHECK(hipGetLastError());
+    HC_CHECK(hipStreamSynchronize(st));
+    return HC_OK;
+}
+
+extern "C" hc_status hc_power(hc_context* cp, const hc_gk* rk, const uint64_t* ct_in, uint32_t exponent,
+                              uint64_t* ct_out, hipStream_t st) {
+    if (!cp || !ct_in || !ct_out || exponent == 0) return HC_EINVAL;
+    HC_CHECK(hipSetDevice(cp->device));
+    hc_status s = power_many(*cp, rk, ct_in, 1, exponent, ct_out, st);
+    if (s != HC_OK) return s;
+    HC_CHECK(hipGetLastError());
+    HC_CHECK(hipStreamSynchronize(st));
+    return HC_OK;
+}
+
+extern "C" hc_status hc_match(hc_context* cp, const hc_gk* rk, const hc_db* keys, const uint64_t* ct_x, uint64_t N,
+                              uint64_t* ct_v, hipStream_t st) {
+    if (!cp || !keys || !ct_x || !ct_v || N == 0 || keys->ncol < 1 || keys->N < N || !keys->d_raw) return HC_EINVAL;
+    Ctx& c = *cp;
+    HC_CHECK(hipSetDevice(c.device));
+    const uint64_t* key = nullptr;
+    hc_status s = rk_of(rk, &key);
+    if (s != HC_OK) return s;
+    if (!c.d_mult) return HC_EINVAL;
+    const size_t n = c.n, L = c.L, CW = 2 * L * n;
+    const uint32_t n_ct = (uint32_t)((N + n - 1) / n);
+    // per ciphertext: the keys' plaintext m (coefficients mod p), the query minus it
+    uint32_t *slots = nullptr, *m = nullptr;
+    HC_CHECK(hipMalloc((void**)&slots, sizeof(uint32_t) * n));
+    HC_CHECK(hipMalloc((void**)&m, sizeof(uint32_t) * n));
+    for (uint32_t i = 0; i < n_ct; i++) {
+        const uint64_t r0 = (uint64_t)i * n, cnt = std::min<uint64_t>(n, N - r0);
+        k_zero(c, reinterpret_cast<uint64_t*>(slots), n / 2, st);
+        HC_CHECK(hipMemcpyAsync(slots, keys->d_raw + r0, sizeof(uint32_t) * cnt, hipMemcpyDeviceToDevice, st));
+        k_slots_to_eval(c, m, slots, 1, st);
+        ntt32(c, m, 1, true, st);
+        uint64_t* v = ct_v + i * CW;
+        HC_CHECK(hipMemcpyAsync(v, ct_x, sizeof(uint64_t) * CW, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(sub_delta_m_kernel, dim3((unsigned)((n + 255) / 256), L), dim3(256), 0, st, v, m, c.d_mods,
+                           c.d_delta, (int)n);
+    }
+    // Power_{p-1}, then 1 - v
+    s = power_many(c, rk, ct_v, n_ct, (uint32_t)(c.p - 1), ct_v, st);
+    if (s == HC_OK)
+        for (uint32_t i = 0; i < n_ct; i++)
+            hipLaunchKernelGGL(one_minus_kernel, dim3((unsigned)((n + 255) / 256), L, 2), dim3(256), 0, st,
+                               ct_v + i * CW, c.d_mods, c.d_delta, (int)n, (int)L);
+    // slots past the last record: multiplied by the 0/1 mask of the records present
+    if (s == HC_OK && N % n) {
+        std::vector<uint32_t> valid(n, 0);
+        for (uint64_t r = 0; r < N % n; r++) valid[r] = 1;
+        uint64_t *pt = nullptr, *tmp = nullptr;
+        HC_CHECK(hipMalloc((void**)&pt, sizeof(uint64_t) * L * n));
+        HC_CHECK(hipMalloc((void**)&tmp, sizeof(uint64_t) * CW));
+        s = encode_plain(c, pt, valid.data(), 1, true, st);
+        if (s == HC_OK) {
+            uint64_t* last = ct_v + (size_t)(n_ct - 1) * CW;
+            HC_CHECK(hipMemcpyAsync(tmp, last, sizeof(uint64_t) * CW, hipMemcpyDeviceToDevice, st));
+            ntt64(c, tmp, L * n, 2, 0, (int)L, false, st);
+            k_mul_plain(c, tmp, tmp, pt, (int)L, st);
+            ntt64(c, tmp, L * n, 2, 0, (int)L, true, st);
+            HC_CHECK(hipMemcpyAsync(last, tmp, sizeof(uint64_t) * CW, hipMemcpyDeviceToDevice, st));
+        }
+        HC_CHECK(hipStreamSynchronize(st));
+        HC_CHECK(hipFree(pt));
+        HC_CHECK(hipFree(tmp));
+    }
+    HC_CHECK(hipStreamSynchronize(st));
+    HC_CHECK(hipFree(slots));
+    HC_CHECK(hipFree(m));
+    if (s != HC_OK) return s;
+    HC_CHECK(hipGetLastError());
+    return HC_OK;
+}
+
+extern "C" hc_status hc_compress_generic(hc_context* cp, const hc_gk* gk, const hc_gk* rk, const uint64_t* ct_d,
+                                         uint64_t N, uint32_t t_bound, uint32_t comp_level, uint32_t out_level,
+                                         uint64_t* ct_out, hc_compress_info* info, hipStream_t st) {
+    if (!cp || !gk || !ct_d || !ct_out) return HC_EINVAL;
+    Ctx& c = *cp;
+    HC_CHECK(hipSetDevice(c.device));
+    std::vector<QueryRun> qs(1);
+    hc_status s = make_plan(c, N, 1, t_bound, comp_level, out_level, qs[0].pl);
+    if (s != HC_OK) return s;
+    // v = Power_{p-1}(d), ciphertext by ciphertext at the full level
+    const size_t CW = 2 * (size_t)c.L * c.n;
+    uint64_t* v = nullptr;
+    HC_CHECK(hipMalloc((void**)&v, sizeof(uint64_t) * CW * qs[0].pl.n_ct));
+    s = power_many(c, rk, ct_d, qs[0].pl.n_ct, (uint32_t)(c.p - 1), v, st);
+    if (s == HC_OK) {
+        qs[0].ct_v = v;
+        qs[0].ct_d = ct_d;
+        qs[0].ct_out = ct_out;
+        s = compress_many(c, c.lane, gk, nullptr, qs, st);
+    }
+    const hipError_t e = hipStreamSynchronize(st);
+    (void)hipFree(v);
+    if (s != HC_OK) return s;
+    if (e != hipSuccess) return fail_hip(e, "hc_compress_generic", __FILE__, __LINE__);
+    fill_info(qs[0], info);
+    return HC_OK;
+}

@@ -606,11 +606,11 @@ static hc_status build_tw2_logn(Ctx& c) {
     typedef Tile<uint64_t, true, LOGN, 8, 0, 0> TI;
     static_assert(TF::TW2 && TI::TW2 && TF::TW_PASS == TI::TW_PASS, "low-bit passes");
     const int tiles = 1 << (LOGN - TILE_LOG);
-    const size_t words = (size_t)c.nq * 2 * tiles * TF::TW_PASS * TF::THREADS * 2;
+    const size_t words = (size_t)c.ntab * 2 * tiles * TF::TW_PASS * TF::THREADS * 2;
     HC_CHECK(hipMalloc((void**)&c.d_tw2, sizeof(uint64_t) * words));
     c.owned.push_back(c.d_tw2);
-    hipLaunchKernelGGL((ntt_tw2_kernel<false, LOGN>), dim3(tiles, c.nq), dim3(TF::THREADS), 0, 0, c.d_tw2, c.d_tw);
-    hipLaunchKernelGGL((ntt_tw2_kernel<true, LOGN>), dim3(tiles, c.nq), dim3(TI::THREADS), 0, 0, c.d_tw2, c.d_tw);
+    hipLaunchKernelGGL((ntt_tw2_kernel<false, LOGN>), dim3(tiles, c.ntab), dim3(TF::THREADS), 0, 0, c.d_tw2, c.d_tw);
+    hipLaunchKernelGGL((ntt_tw2_kernel<true, LOGN>), dim3(tiles, c.ntab), dim3(TI::THREADS), 0, 0, c.d_tw2, c.d_tw);
     HC_CHECK(hipGetLastError());
     HC_CHECK(hipDeviceSynchronize());
     return HC_OK;

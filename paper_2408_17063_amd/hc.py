@@ -121,6 +121,12 @@ _sig("hc_autotune", _st, c_vp, c_vp, c_vp, c_vp, ctypes.c_uint64, ctypes.c_uint3
      ctypes.POINTER(TuneReport), c_vp)
 _sig("hc_tune_set", _st, c_vp, ctypes.c_uint32, ctypes.c_uint32)
 _sig("hc_tune_get", _st, c_vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32))
+_sig("hc_relin_keygen", _st, c_vp, c_vp, c_u8p, ctypes.POINTER(c_vp))
+_sig("hc_mul", _st, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp)
+_sig("hc_power", _st, c_vp, c_vp, c_vp, ctypes.c_uint32, c_vp, c_vp)
+_sig("hc_match", _st, c_vp, c_vp, c_vp, c_vp, ctypes.c_uint64, c_vp, c_vp)
+_sig("hc_compress_generic", _st, c_vp, c_vp, c_vp, c_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+     ctypes.c_uint32, c_vp, ctypes.POINTER(CompressInfo), c_vp)
 _sig("hc_decrypt", _st, c_vp, c_vp, c_u64p, ctypes.c_uint32, c_u32p)
 _sig("hc_decompress", _st, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
      c_u32p, c_u32p, c_u64p, c_u32p, c_u32p)
@@ -173,6 +179,7 @@ EXPORTED = [
     "hc_export_gk", "hc_timing_enable", "hc_timing_read", "hc_probe_mul32_rate", "hc_probe_copy",
     "hc_graph_create", "hc_graph_launch", "hc_graph_nodes", "hc_graph_destroy",
     "hc_autotune", "hc_tune_set", "hc_tune_get",
+    "hc_relin_keygen", "hc_mul", "hc_power", "hc_match", "hc_compress_generic",
     "hc_diag_prepare", "hc_diag_release", "hc_server_create", "hc_server_submit", "hc_server_poll",
     "hc_server_stats_get", "hc_server_destroy",
 ]
@@ -263,6 +270,41 @@ class Context:
         _check(_lib.hc_galois_keygen(self.h, sk.h, _np_ptr(arr, ctypes.c_uint32), len(arr), _u8(seed),
                                      ctypes.byref(gk)), "hc_galois_keygen")
         return GaloisKeys(self, gk, [int(x) for x in arr])
+
+    def relin_keygen(self, sk, seed):
+        rk = c_vp()
+        _check(_lib.hc_relin_keygen(self.h, sk.h, _u8(seed), ctypes.byref(rk)), "hc_relin_keygen")
+        return GaloisKeys(self, rk, [1])
+
+    def mul(self, rk, a, b, out=None, stream=None):
+        out = self.ct_tensor(1)[0] if out is None else out
+        w = 2 * self.L * self.n
+        _check(_lib.hc_mul(self.h, rk.h, _dev(a, w, "ct_a"), _dev(b, w, "ct_b"), _dev(out, w, "out"),
+                           _stream(stream)), "hc_mul")
+        return out
+
+    def power(self, rk, ct, exponent, out=None, stream=None):
+        out = self.ct_tensor(1)[0] if out is None else out
+        w = 2 * self.L * self.n
+        _check(_lib.hc_power(self.h, rk.h, _dev(ct, w, "ct_in"), exponent, _dev(out, w, "out"), _stream(stream)),
+               "hc_power")
+        return out
+
+    def match(self, rk, keys_db, ct_x, N, out=None, stream=None):
+        """Index-vector ciphertexts [ceil(N/n)][2][L][n] of [k_r = x] (keys: column 0 of keys_db)."""
+        out = self.ct_tensor(-(-int(N) // self.n)) if out is None else out
+        _check(_lib.hc_match(self.h, rk.h, keys_db.h, _dev(ct_x, 2 * self.L * self.n, "ct_x"), N,
+                             _dev(out, self.ct_words(N), "ct_v"), _stream(stream)), "hc_match")
+        return out
+
+    def compress_generic(self, gk, rk, ct_d, N, t_bound, out=None, stream=None, comp_level=0, out_level=0):
+        """Alg. 5: Power_{p-1} of d, then Comp of (v, d); returns (out, info)."""
+        out = self.ct_tensor(1)[0] if out is None else out
+        info = CompressInfo()
+        _check(_lib.hc_compress_generic(self.h, gk.h, rk.h, _dev(ct_d, self.ct_words(N), "ct_d"), N, t_bound,
+                                        comp_level, out_level, _dev(out, 2 * self.L * self.n, "out"),
+                                        ctypes.byref(info), _stream(stream)), "hc_compress_generic")
+        return out, info.as_dict()
 
     def plan(self, N, ncol, t_bound, comp_level=0, out_level=0):
         cnt = ctypes.c_uint32(0)
