@@ -316,6 +316,68 @@ def plain_db_leg(st, eager_out, steps, comp_level, out_level):
             "decrypts_like_mask_and_comp": bool(same)}
 
 
+def products_leg(st, reps, out_level):
+    """Ciphertext products at the headline parameters (ring 2^16, 24 primes): one
+    hc_mul, one Power_{p-1} (x^3 then 18 squarings at p = 786433), and a whole PDQ
+    Answer with Match (Alg. 7): hc_match of a query key against 2^20 record keys (16
+    ciphertexts, one Power_{p-1} each), then Mask + Comp of its index vector with the
+    headline database; the answer must decompress to the matching records."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from oracle import compress as C
+    from paper_2408_17063_amd import hc
+    ctx, wl = st["ctx"], st["wl"]
+    t0 = time.perf_counter()
+    rk = ctx.relin_keygen(st["sk"], W.seed32("rk", 0))
+    keygen_s = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    a, b = st["cts"][0], st["cts"][1]
+    out = ctx.ct_tensor(1)[0]
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(k):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    mul_ms = timed(lambda: ctx.mul(rk, a, b, out=out), reps)
+    pow_ms = timed(lambda: ctx.power(rk, a, ctx.p - 1, out=out), 1)
+    keys, x, v = W.match_inputs(wl.N, wl.t, ctx.p, seed=5)
+    kdb = ctx.db_upload(keys.reshape(1, -1))
+    cx = ctx.encrypt(st["pk"], np.full((2, ctx.nh), x), W.seed32("enc-match", 0))
+    ctv = ctx.ct_tensor(st["cts"].shape[0])
+    match_ms = timed(lambda: ctx.match(rk, kdb, cx, wl.N, out=ctv), 1)
+    ans = ctx.ct_tensor(1)[0]
+    comp_ms = timed(lambda: ctx.compress(st["gk"], st["db"], ctv, wl.N, wl.t, out=ans, out_level=out_level), 1)
+    _, info = ctx.compress(st["gk"], st["db"], ctv, wl.N, wl.t, out=ans, out_level=out_level)
+    dec = ctx.decrypt(st["sk"], ctx.output(ans, info).cpu().numpy().view(np.uint64))
+    sched = C.make_schedule(ctx.n, ctx.p, wl.N, wl.ncol, wl.t)
+    S = len(sched.streams)
+    ok = True
+    for gi, grp in enumerate(sched.groups):
+        rows = []
+        for sv in range(S):
+            rows += list(C.band_slots(sched, dec, gi * S + sv))
+        idx, vals = hc.decompress(ctx.p, grp.n_rec, sched.s, rows[0], rows[1:1 + wl.ncol])
+        seg = v[grp.rec_start:grp.rec_start + grp.n_rec]
+        want = [int(i) + 1 for i in np.nonzero(seg)[0]]
+        ok = ok and idx == want and all(
+            vals[c] == [int(st["dbv"][c][grp.rec_start + i - 1]) % ctx.p for i in want] for c in range(wl.ncol))
+    rk.close()
+    kdb.close()
+    del ctv, ans
+    torch.cuda.empty_cache()
+    return {"relin_keygen_s": round(keygen_s, 2), "mul_ms": round(mul_ms, 3), "power_p_minus_1_ms": round(pow_ms, 2),
+            "match_ms": round(match_ms, 1), "match_records": wl.N, "answer_after_match_ms": round(comp_ms, 2),
+            "pdq_answer_with_match_per_s": round(1e3 / (match_ms + comp_ms), 4), "recovers_matches": bool(ok)}
+
+
 def graph_leg(st, eager_out, steps, comp_level, out_level):
     """The headline compression captured once into a HIP graph (hc_graph_create) and
     replayed: same inputs, its output must equal the eager run's bit for bit."""
@@ -722,6 +784,8 @@ def main():
                     help="also time this many replays of the headline compression captured in a graph (0: skip)")
     ap.add_argument("--plain-db-steps", type=int, default=2,
                     help="also time the unencrypted-database form on the headline query (0: skip)")
+    ap.add_argument("--products", type=int, default=1,
+                    help="also time ciphertext products, Power_{p-1} and a PDQ Answer with Match (0: skip)")
     ap.add_argument("--small-configs", type=int, default=20,
                     help="latency repetitions of the ring-4096 and ring-2^15 configurations (0: skip)")
     ap.add_argument("--ntt-probe", type=int, default=0,
@@ -829,6 +893,9 @@ def main():
     if args.graph_steps:
         rec["graph"] = graph_leg(st, out, args.graph_steps, args.comp_level, ol)
         log("graph replay: %s" % rec["graph"])
+    if args.products:
+        rec["products"] = products_leg(st, 5, ol)
+        log("products, Power and Match: %s" % rec["products"])
     if args.plain_db_steps:
         rec["plain_db"] = plain_db_leg(st, out, args.plain_db_steps, args.comp_level, ol)
         log("unencrypted-database form: %s" % rec["plain_db"])
@@ -840,6 +907,9 @@ def main():
         rec["on_the_fly"] = on_the_fly(st, out, args.on_the_fly_steps, args.comp_level, ol)
         log("diagonals on the fly: %.1f ms/step; output equals resident: %s" % (
             rec["on_the_fly"]["ms_per_step"], rec["on_the_fly"]["equals_resident"]))
+    if prep is not None and not args.on_the_fly_steps:
+        st["ctx"].diag_release()  # the legs below hold their own tables and batch workspaces
+    torch.cuda.empty_cache()
     if args.small_configs:
         rec["small_configs"] = [small_config_latency("plain-4096", args.small_configs, 1),
                                 small_config_latency("single-32768", args.small_configs, 2)]
