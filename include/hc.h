@@ -333,8 +333,10 @@ hc_status hc_tune_get(const hc_context* ctx, uint32_t* mac_variant, uint32_t* nt
  * groups (through N), on s and on the Comp level: never on the query or on the
  * database. Encode every diagonal that compressions with (N, ncol, t_bound,
  * comp_level) use and keep them resident on the device, one table per
- * (s, B, level) class: [k][s/B][B][level][n] words, NTT domain, Montgomery
- * form, k = the most u-blocks of a group. Later hc_compress and
+ * (s, B, level) class, NTT domain, k = the most u-blocks of a group, in one of two
+ * layouts (see hc_diag_layout): the seven balanced base-256 digits of each centred
+ * residue, tiled for the int8 matrix-core multiply-accumulate (7 bytes per residue),
+ * or split words in Montgomery form for the vector one (8 bytes). Later hc_compress and
  * hc_compress_batch calls read a class from its table when it holds enough
  * u-blocks, instead of encoding its diagonals on the fly; the results are
  * bit-identical either way. A class already resident with at least k u-blocks
@@ -349,6 +351,16 @@ hc_status hc_diag_prepare(hc_context* ctx, uint64_t N, uint32_t ncol, uint32_t t
 /* Free every resident diagonal table of ctx; later compressions encode their
  * diagonals on the fly. Synchronises the device. */
 void hc_diag_release(hc_context* ctx);
+
+/* Layout of the tables later hc_diag_prepare calls build (tables already resident
+ * keep theirs; release them to rebuild). HC_DIAG_LAYOUT_AUTO (the default): the
+ * matrix-core digit layout for every class it fits -- all Comp-level primes below
+ * 2^55, k B <= 128 terms, padding to 16 giants x 64 terms at most doubling the
+ * bytes -- else split words. HC_DIAG_LAYOUT_SPLIT: split words for every class.
+ * Either way the compressions' results are the same words.
+ * Errors: HC_EINVAL (unknown layout). */
+enum { HC_DIAG_LAYOUT_AUTO = 0, HC_DIAG_LAYOUT_SPLIT = 1 };
+hc_status hc_diag_layout(hc_context* ctx, int layout);
 
 /* ------------------------------------------------------------------ serving loop (Sec. 3, Answer) */
 

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhc.so")
 
-SOURCES = ["ntt.hip", "ops.hip", "context.cpp", "he.cpp", "compress.cpp", "server.cpp", "decode.cpp", "graph.cpp", "tune.cpp", "plain_db.cpp", "mult.hip"]
+SOURCES = ["ntt.hip", "ops.hip", "context.cpp", "he.cpp", "compress.cpp", "server.cpp", "decode.cpp", "graph.cpp", "tune.cpp", "plain_db.cpp", "mult.hip", "mfma_mac.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("HC_OFFLOAD_ARCH", "gfx950")

@@ -431,8 +431,10 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
         if (const Ctx::DiagTab* tab = cls_res[kv.first]) {
             // resident diagonals: one pass over every giant index
             uint64_t** aptr = (uint64_t**)(rptr + np * kb * B);
-            hc_status ms = k_diag_mac(c, aptr, Rt, tab->d, diag_layout_tiled(c, tab->kb * B, G), (int)np,
-                                      (int)(kb * B), (int)G, false, Lc, st);
+            hc_status ms = tab->mfma ? k_diag_mac_mfma(c, aptr, Rt, tab->d, tab->kb * B, (int)np, (int)(kb * B),
+                                                       (int)G, Lc, st)
+                                     : k_diag_mac(c, aptr, Rt, tab->d, diag_layout_tiled(c, tab->kb * B, G), (int)np,
+                                                  (int)(kb * B), (int)G, false, Lc, st);
             if (ms != HC_OK) return ms;
             continue;
         }
@@ -653,12 +655,56 @@ extern "C" hc_status hc_diag_prepare(hc_context* cp, uint64_t N, uint32_t ncol, 
             c.diag_tabs.erase(old);
         }
         const size_t count = (size_t)kb * G * B;
+        const uint32_t Jt = kb * B;
         Ctx::DiagTab tab;
         tab.kb = kb;
-        tab.bytes = diag_table_words(c, Lc, kb * B, G) * 8;
+        tab.mfma = c.diag_layout == HC_DIAG_LAYOUT_AUTO && diag_mfma_fits(c, Lc, Jt, G);
+        tab.bytes = tab.mfma ? diag_mfma_table_bytes(c, Lc, Jt, G) : diag_table_words(c, Lc, Jt, G) * 8;
         if (hipMalloc((void**)&tab.d, tab.bytes) != hipSuccess) {
             (void)hipGetLastError();
             return HC_ENOMEM;
+        }
+        if (tab.mfma) {
+            // digit layout: one (16-giant tile, 64-term block) of diagonals at a time,
+            // encoded as below but lifted as plain residues
+            const size_t cmax = 16 * 64;
+            stage_reset(c.lane, st);
+            if (c.lane.ws.reserve(n * 4 * cmax + PW * 8 * cmax + 4096) != HC_OK) {
+                (void)hipFree(tab.d);
+                return HC_ENOMEM;
+            }
+            c.lane.ws.reset();
+            uint32_t* Dp = c.lane.ws.take<uint32_t>(n * cmax);
+            uint64_t* Dn = c.lane.ws.take<uint64_t>(PW * cmax);
+            std::vector<uint32_t> hprm;
+            for (uint32_t t = 0; t * 16 < G; t++)
+                for (uint32_t jb = 0; jb * 64 < Jt; jb++) {
+                    const uint32_t ng = std::min<uint32_t>(16, G - 16 * t), nj = std::min<uint32_t>(64, Jt - 64 * jb);
+                    hprm.clear();
+                    for (uint32_t gl = 0; gl < ng; gl++)
+                        for (uint32_t jl = 0; jl < nj; jl++) {
+                            const uint32_t j = 64 * jb + jl;
+                            hprm.push_back(j / B);        // beta
+                            hprm.push_back(16 * t + gl);  // giant index
+                            hprm.push_back(j % B);        // baby index
+                        }
+                    const int cnt = (int)(ng * nj);
+                    stage_reset(c.lane, st);
+                    const uint32_t* dprm =
+                        (const uint32_t*)stage_bytes(c.lane, hprm.data(), sizeof(uint32_t) * hprm.size(), st);
+                    if (!dprm) {
+                        (void)hipFree(tab.d);
+                        return HC_ENOMEM;
+                    }
+                    k_diag_gen(c, Dp, dprm, cnt, pl.s, B, st);
+                    ntt32(c, Dp, cnt, true, st);
+                    k_lift(c, Dn, Dp, cnt, false, Lc, st);
+                    ntt64(c, Dn, PW, cnt, 0, Lc, false, st);
+                    k_diag_digits(c, tab.d, Dn, Jt, G, t, jb, Lc, st);
+                }
+            HC_CHECK(hipDeviceSynchronize());
+            c.diag_tabs[key] = tab;
+            continue;
         }
         // encode in chunks: slot values (Sec. 5.2 diagonals of C), to R_p, lift, NTT per
         // prime, then into the table's tiled layout
@@ -700,6 +746,12 @@ extern "C" hc_status hc_diag_prepare(hc_context* cp, uint64_t N, uint32_t ncol, 
         for (auto& kv : c.diag_tabs) t += kv.second.bytes;
         *bytes_out = t;
     }
+    return HC_OK;
+}
+
+extern "C" hc_status hc_diag_layout(hc_context* cp, int layout) {
+    if (!cp || (layout != HC_DIAG_LAYOUT_AUTO && layout != HC_DIAG_LAYOUT_SPLIT)) return HC_EINVAL;
+    cp->diag_layout = layout;
     return HC_OK;
 }
 

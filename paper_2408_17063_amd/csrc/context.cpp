@@ -393,6 +393,13 @@ extern "C" hc_status hc_context_create(const hc_params* prm, int device, hc_cont
     UP(c.d_pinv, pinv);
     UP(c.d_pmodq, pmodq);
     UP(c.d_delta, delta);
+    {
+        // digit weights of the matrix-core multiply-accumulate: 256^s 2^64 mod q_i
+        std::vector<uint64_t> mfw((size_t)L * 16, 0);
+        for (int i = 0; i < L; i++)
+            for (int s = 0; s < 13; s++) mfw[(size_t)i * 16 + s] = h_to_mont(h_powmod(256, (uint64_t)s, c.primes[i]), c.primes[i]);
+        UP(c.d_mfw, mfw);
+    }
 #undef UP
     // the allocation-free scratch of this device (the device is current here)
     {

@@ -110,8 +110,15 @@ struct hc_context {
 
     // resident diagonal tables keyed by (s, B, level): [kb][s/B][B][level][n], NTT domain,
     // Montgomery form
-    struct DiagTab { uint32_t kb = 0; uint64_t* d = nullptr; size_t bytes = 0; };
+    // mfma: the table is in the digit layout of the int8 matrix-core multiply-accumulate
+    // (mfma_mac.hip) instead of the split-word layout
+    struct DiagTab { uint32_t kb = 0; uint64_t* d = nullptr; size_t bytes = 0; bool mfma = false; };
     std::map<std::tuple<uint32_t, uint32_t, int>, DiagTab> diag_tabs;
+    int diag_layout = HC_DIAG_LAYOUT_AUTO;  // layout of tables built next (hc_diag_layout)
+
+    // digit weights of the int8 matrix-core multiply-accumulate: 256^s 2^64 mod q_i,
+    // [L][16] (s < 13)
+    uint64_t* d_mfw = nullptr;
 
     uint64_t* d_scratch = nullptr;  // this device's fixed allocation-free scratch (context.cpp)
 
@@ -353,5 +360,18 @@ void k_diag_gather(const Ctx& c, uint64_t* Rt, const uint64_t* const* R, const u
 // HC_EINVAL if one term's diagonal words for DIAG_GC giants span 2^31 bytes or more
 hc_status k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* Rt, const uint64_t* D,
                      const DiagLayout& lay, int npairs, int J, int ga, bool accumulate, int Lc, hipStream_t st);
+// The same product (A written, not accumulated) on the matrix cores (int8 MFMA over
+// balanced base-256 digits) from a resident table in the digit layout, Jt terms
+// (J <= Jt <= 128 used: J) by ga giants:
+// diag_mfma_fits says whether a table of Jt terms and G giants at level Lc takes that
+// layout (every prime below 2^55, Jt <= 128, padding at most doubling the bytes),
+// k_diag_digits writes its giant tile t / term block jb from ng x nj natural-layout
+// diagonals [(gl nj + jl)][Lc][n] (plain residues, NTT domain). HC_EINVAL outside.
+bool diag_mfma_fits(const Ctx& c, int Lc, uint32_t Jt, uint32_t G);
+size_t diag_mfma_table_bytes(const Ctx& c, int Lc, uint32_t Jt, uint32_t G);
+void k_diag_digits(const Ctx& c, void* table, const uint64_t* in, uint32_t Jt, uint32_t G, uint32_t t, uint32_t jb,
+                   int Lc, hipStream_t st);
+hc_status k_diag_mac_mfma(const Ctx& c, uint64_t* const* A, const uint64_t* Rt, const void* D, uint32_t Jt, int npairs,
+                          int J, int ga, int Lc, hipStream_t st);
 
 }  // namespace hc

@@ -28,6 +28,7 @@ c_i64p = ctypes.POINTER(ctypes.c_int64)
 c_vp = ctypes.c_void_p
 
 HC_OK, HC_EINVAL, HC_ENOMEM, HC_EDEVICE, HC_ENOKEY, HC_EDECODE, HC_ENOISE, HC_ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7
+DIAG_LAYOUT_AUTO, DIAG_LAYOUT_SPLIT = 0, 1
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
@@ -154,6 +155,7 @@ _sig("hc_probe_copy", _st, c_vp, ctypes.c_uint64)
 _sig("hc_diag_prepare", _st, c_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
      ctypes.POINTER(ctypes.c_uint64))
 _sig("hc_diag_release", None, c_vp)
+_sig("hc_diag_layout", _st, c_vp, ctypes.c_int)
 _sig("hc_server_create", _st, c_vp, c_vp, c_vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32,
      ctypes.c_uint32, ctypes.POINTER(c_vp))
 _sig("hc_server_submit", _st, c_vp, c_vp, ctypes.c_uint64, ctypes.c_uint32, c_vp, c_vp,
@@ -180,7 +182,7 @@ EXPORTED = [
     "hc_graph_create", "hc_graph_launch", "hc_graph_nodes", "hc_graph_destroy",
     "hc_autotune", "hc_tune_set", "hc_tune_get",
     "hc_relin_keygen", "hc_mul", "hc_power", "hc_match", "hc_compress_generic",
-    "hc_diag_prepare", "hc_diag_release", "hc_server_create", "hc_server_submit", "hc_server_poll",
+    "hc_diag_prepare", "hc_diag_release", "hc_diag_layout", "hc_server_create", "hc_server_submit", "hc_server_poll",
     "hc_server_stats_get", "hc_server_destroy",
 ]
 
@@ -353,6 +355,11 @@ class Context:
 
     def diag_release(self):
         _lib.hc_diag_release(self.h)
+
+    def diag_layout(self, layout):
+        """Layout of the tables later diag_prepare calls build: DIAG_LAYOUT_AUTO (matrix-core
+        digits where a class fits them) or DIAG_LAYOUT_SPLIT (split words everywhere)."""
+        _check(_lib.hc_diag_layout(self.h, int(layout)), "hc_diag_layout")
 
     def db_upload(self, cols):
         cols = np.ascontiguousarray(cols, dtype=np.uint32)
