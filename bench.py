@@ -210,6 +210,8 @@ def cpu_baseline(info):
     t_wall = time.perf_counter()
     with get_context("spawn").Pool(P) as pool:
         samples = pool.map(_cpu_sample, [(level, 1000 + i) for i in range(P)])
+        pool.close()
+        pool.join()  # every worker has exited before the result line is printed
     wall = time.perf_counter() - t_wall
     t = {k: sum(x[k] for x in samples) / P for k in samples[0]}
     n_mask = 4 * 16                      # value columns x input ciphertexts
