@@ -323,20 +323,27 @@ void kb_final(const Ctx& c, const KsJob* jobs, const uint64_t* T, const uint64_t
 // TA[g][comp][row] += sum over the group's jobs m of X_m[row] * key_m[comp][row] (all
 // digits; X_m is job m's raised, already rotated c1) and C0A[g][i] += sum of the jobs'
 // rotated c0 (rows R..R+Lc-1 of the grid). Per-job products are never written out.
-// The group is the fastest grid index: blocks of all groups at one (tile, row) run
-// together, and the jobs of a pass that share a key (one rotation, different groups)
-// read its words through L2 at the same time. The key is in Montgomery form, so a
+// Work item (range, tile, row) with the range fastest. Blocks go to the XCDs round robin,
+// so block b takes item (b mod 8) per_xcd + b / 8: consecutive items run on one XCD, the
+// blocks of all groups at one (tile, row) run together there, and the
+// jobs of a pass that share a key (one rotation, different groups) read its words
+// through that XCD's L2 at the same time. The key is in Montgomery form, so a
 // reduction of a 128-bit sum of at most `fold` products (fold q < 2^64) is the plain
 // sum of those products.
 __global__ void kb_inner_sum_kernel(uint64_t* __restrict__ TA, uint64_t* __restrict__ C0A,
                                     const uint64_t* __restrict__ X, const KsJob* __restrict__ jobs,
                                     const KsGroupRange* __restrict__ ranges, const uint32_t* __restrict__ members,
                                     const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv, int n,
-                                    int logn, int nq, int L, int Lc, int K, int dn, int fold) {
-    const int x = blockIdx.y * blockDim.x + threadIdx.x;
+                                    int logn, int nq, int L, int Lc, int K, int dn, int fold, uint32_t nranges,
+                                    uint32_t ntiles, uint32_t work, uint32_t per_xcd) {
+    const uint32_t bid = blockIdx.x;
+    const uint32_t wk = (bid & 7u) * per_xcd + (bid >> 3);
+    if (wk >= work) return;  // uniform over the block
+    const uint32_t tr = wk / nranges;
+    const int x = (int)(tr % ntiles) * blockDim.x + threadIdx.x;
     if (x >= n) return;
-    const int row = blockIdx.z, R = Lc + K;
-    const KsGroupRange gr = ranges[blockIdx.x];
+    const int row = (int)(tr / ntiles), R = Lc + K;
+    const KsGroupRange gr = ranges[wk % nranges];
     if (row < R) {
         const int pr = row_prime(row, Lc, L);
         const uint64_t q = mods[pr], qi = qinv[pr];
@@ -392,9 +399,12 @@ void kb_inner_sum(const Ctx& c, uint64_t* TA, uint64_t* C0A, const uint64_t* X, 
     TimeScope ts(c, HC_KT_KS_INNER, st,
                  8.0 * n * ((double)nkeys * 2 * dn * R + (double)M * (dn * R + Lc) + (double)nranges * 2 * (2 * R + Lc)),
                  2.0 * dn * R * n * M);
-    hipLaunchKernelGGL(kb_inner_sum_kernel, dim3(nranges, (c.n + EW_THREADS - 1) / EW_THREADS, R + Lc),
-                       dim3(EW_THREADS), 0, st, TA, C0A, X, jobs, ranges, members, c.d_mods, c.d_qinv, c.n, c.logn,
-                       c.nq, c.L, Lc, c.K, dn, fold < 1 ? 1 : fold);
+    const uint32_t ntiles = (uint32_t)((c.n + EW_THREADS - 1) / EW_THREADS);
+    const uint64_t work = (uint64_t)nranges * ntiles * (uint32_t)(R + Lc);
+    const uint32_t per_xcd = (uint32_t)((work + 7) / 8);
+    hipLaunchKernelGGL(kb_inner_sum_kernel, dim3(per_xcd * 8), dim3(EW_THREADS), 0, st, TA, C0A, X, jobs, ranges,
+                       members, c.d_mods, c.d_qinv, c.n, c.logn, c.nq, c.L, Lc, c.K, dn, fold < 1 ? 1 : fold,
+                       (uint32_t)nranges, ntiles, (uint32_t)work, per_xcd);
 }
 
 __global__ void zero_words_kernel(uint64_t* __restrict__ p, size_t words) {
