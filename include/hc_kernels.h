@@ -136,7 +136,8 @@ enum {
     HC_KT_KS_INNER = 2,  /* key-switch inner product with the Galois key */
     HC_KT_DIAG_MAC = 3,  /* diagonal multiply-accumulate */
     HC_KT_MODUP = 4,     /* ModUp basis conversion */
-    HC_KT_COUNT = 5
+    HC_KT_CONV_FUSED = 5, /* key switching's conversions fused with the NTTs' high-bit passes */
+    HC_KT_COUNT = 6
 };
 
 /* Start (enable = 1) or stop timing; starting clears the totals. */

@@ -228,6 +228,19 @@ void ntt64(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb
 void ntt32(const Ctx& c, uint32_t* data, int count, bool inverse, hipStream_t stream);
 // builds d_tw2 from d_tw (context creation; synchronises the device)
 hc_status ntt_build_tw2(Ctx& c);
+// Ring 2^16 (two NTT passes of 8 stages): key switching's conversions run fused with the
+// forward transform's high-bit pass (k_modup_fused, k_moddown_fused); its low-bit pass
+// alone runs through ntt64_low_pass (inverse: the first pass; forward: the last).
+bool conv_fused_ring(const Ctx& c);
+void ntt64_low_pass(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb_first, int nlimbs,
+                    bool inverse, hipStream_t stream);
+// ModUp of U sources at level Lc: tmpC [U][Lc][n] (coefficient domain) -> every row of
+// X[U][dn][R][n] outside each digit, after the forward high-bit pass (its low-bit pass
+// follows); the words equal kb_modup's followed by the full transform.
+void k_modup_fused(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, hipStream_t st);
+// ModDown's P -> Q conversion of M jobs at level Lc: T [M][2][R][n] special rows
+// (coefficient domain) -> conv [M][2][Lc][n] after the forward high-bit pass.
+void k_moddown_fused(const Ctx& c, uint64_t* conv, const uint64_t* T, int M, int Lc, hipStream_t st);
 
 // ------------------------------------------------------------------ kernels (ops.hip)
 // All arrays are [rows][n] per polynomial; "nl" rows starting at prime index lf.

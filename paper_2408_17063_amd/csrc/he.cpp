@@ -140,11 +140,43 @@ KsScratch ks_scratch(Ctx& c, Arena& a, int Lc, int max_jobs) {
 // if permute), ModUp into dn digits over PQ, NTT domain. Each digit's own rows are
 // copied in the NTT domain before the inverse transform; only the rows ModUp
 // computes are transformed forward.
+// ModDown's middle for M jobs at level Lc: the special rows of T [M][2][R][n] back to
+// coefficients, converted to the ciphertext primes, and forward into conv [M][2][Lc][n]
+// (NTT domain). At ring 2^16 the conversion is fused with the forward high-bit pass.
+static void moddown_conv(Ctx& c, uint64_t* conv, uint64_t* T, int M, int Lc, hipStream_t st) {
+    const size_t n = c.n;
+    const int R = Lc + c.K;
+    if (conv_fused_ring(c)) {
+        ntt64(c, T + (size_t)Lc * n, (size_t)R * n, 2 * M, c.L, c.K, true, st);
+        k_moddown_fused(c, conv, T, M, Lc, st);
+        ntt64_low_pass(c, conv, (size_t)Lc * n, 2 * M, 0, Lc, false, st);
+        return;
+    }
+    ntt64(c, T + (size_t)Lc * n, (size_t)R * n, 2 * M, c.L, c.K, true, st);
+    kb_conv(c, conv, T, M, Lc, st);
+    ntt64(c, conv, (size_t)Lc * n, 2 * M, 0, Lc, false, st);
+}
+
 static void ks_raise(Ctx& c, KsScratch& s, const KsJob* d, int U, int Lc, bool permute, hipStream_t st) {
     const size_t n = c.n;
     const int R = Lc + c.K, dn = Lc / c.alpha, a = c.alpha;
     (void)permute;  // jobs carry their element (k = 1: no rotation)
     kb_take_c1(c, s.tmpC, s.X, d, U, Lc, st);
+    if (conv_fused_ring(c)) {
+        // the inverse transform, then the conversion fused with the forward high-bit pass,
+        // then the forward low-bit pass of every converted row
+        ntt64(c, s.tmpC, (size_t)Lc * n, U, 0, Lc, true, st);
+        k_modup_fused(c, s.X, s.tmpC, U, Lc, st);
+        for (int j = 0; j < dn; j++) {
+            uint64_t* Xj = s.X + (size_t)j * R * n;
+            if (j > 0) ntt64_low_pass(c, Xj, (size_t)dn * R * n, U, 0, j * a, false, st);
+            if ((j + 1) * a < Lc)
+                ntt64_low_pass(c, Xj + (size_t)(j + 1) * a * n, (size_t)dn * R * n, U, (j + 1) * a,
+                               Lc - (j + 1) * a, false, st);
+        }
+        ntt64_low_pass(c, s.X + (size_t)Lc * n, (size_t)R * n, U * dn, c.L, c.K, false, st);
+        return;
+    }
     ntt64(c, s.tmpC, (size_t)Lc * n, U, 0, Lc, true, st);
     kb_modup(c, s.X, s.tmpC, U, Lc, false, st);
     for (int j = 0; j < dn; j++) {
@@ -189,9 +221,7 @@ hc_status ks_run(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
     auto raise = [&](const KsJob* d, int U, bool permute) { ks_raise(c, s, d, U, Lc, permute, st); };
     auto finish = [&](const KsJob* d, const KsRun* runs, int nruns, int M, bool hoisted) {
         kb_inner(c, s.T, s.X, d, runs, nruns, M, Lc, hoisted, st);
-        ntt64(c, s.T + (size_t)Lc * n, (size_t)R * n, 2 * M, c.L, c.K, true, st);
-        kb_conv(c, s.conv, s.T, M, Lc, st);
-        ntt64(c, s.conv, (size_t)Lc * n, 2 * M, 0, Lc, false, st);
+        moddown_conv(c, s.conv, s.T, M, Lc, st);
         kb_final(c, d, s.T, s.conv, M, Lc, st);
     };
     if (!srcs) {
@@ -299,9 +329,7 @@ hc_status ks_run_sum(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jo
         for (int i = 0; i < Mg; i++) fj[i] = KsJob{C0A + (g0 + i) * (size_t)Lc * n, outs[g0 + i], nullptr, 1u, 0u};
         const KsJob* df = (const KsJob*)stage_bytes(l, fj.data(), sizeof(KsJob) * Mg, st);
         if (!df) return HC_ENOMEM;
-        ntt64(c, T + (size_t)Lc * n, (size_t)R * n, 2 * Mg, c.L, c.K, true, st);
-        kb_conv(c, s.conv, T, Mg, Lc, st);
-        ntt64(c, s.conv, (size_t)Lc * n, 2 * Mg, 0, Lc, false, st);
+        moddown_conv(c, s.conv, T, Mg, Lc, st);
         kb_final(c, df, T, s.conv, Mg, Lc, st);
     }
     return HC_OK;

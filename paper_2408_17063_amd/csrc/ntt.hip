@@ -475,6 +475,167 @@ __device__ __forceinline__ void ntt_tile(T* __restrict__ data, size_t poly_strid
     }
 }
 
+// ---------------------------------------------------------------- fused base conversion
+// The fast base conversions of key switching sit between two transforms: ModUp takes a
+// digit's rows back to coefficients, converts them to every other row of PQ and
+// transforms those forward; ModDown does the same from the special rows to the
+// ciphertext rows. At ring 2^16 the forward transform's first pass (8 stages over the
+// high index bits) loads each thread's 16 elements straight from device memory (the
+// DIRECT layout), so the conversion can produce them there instead: per tile and
+// output row, the kernel reads the input rows' coefficients at those 16 positions,
+// computes y_a = [x_a (D/q_a)^-1]_{q_a} and out = sum_a y_a (D/q_a) mod r (the words
+// kb_modup / kb_conv write), and runs the pass on them. The converted rows never go
+// through device memory; the input rows are read once per output row, from L2 after
+// the first.
+struct ConvFused {
+    const uint64_t* in;          // input polynomials (coefficient domain, canonical)
+    uint64_t* out;               // output polynomials
+    size_t in_stride, out_stride;  // words between consecutive input / output polynomials
+    int in_row0, in_prime0;      // first input row of digit 0 (row r starts r n words in) and its prime
+    int digits, alpha;           // grid y = u digits + j: source u, digit j (inputs from row in_row0 + alpha j)
+    int out_rows, skip_n;        // output rows 0..out_rows-1 of polynomial y, except skip_n rows from alpha j
+    int Lc, L;                   // output row r has prime r < Lc ? r : L + r - Lc
+    const uint64_t* inv;         // [digit][a][2]: (D/q_a)^-1 mod q_a and its Shoup constant
+    const uint64_t* cst;         // cst[(alpha j + a) cst_stride + prime]: (D/q_a) mod prime, Montgomery form
+    size_t cst_stride;
+    const uint64_t* qinv;        // Montgomery constants of the primes
+};
+
+// One block per (output row, tile, polynomial), numbered so that the blocks of one
+// (tile, polynomial) -- which read the same input words -- run consecutively on one XCD
+// (blocks go to the XCDs round robin: block b takes item (b mod 8) per_xcd + b / 8).
+template <int A, int LOGN>
+__global__ void __launch_bounds__(NTT_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+conv_fused_kernel(ConvFused f, NttTab<uint64_t> tab, uint32_t nout, uint32_t work, uint32_t per_xcd) {
+    static_assert(A >= 1 && A <= 4, "digit size");
+    constexpr int R = NTT_EPT_LOG;
+    typedef Tile<uint64_t, false, LOGN, LOGN - 8, 8, 0> TF;  // forward transform, first pass
+    static_assert(TF::DIRECT, "ring 2^16");
+    constexpr int P_LO = TF::LOGP, P_HI = TF::LOGP + R;
+    constexpr size_t N = (size_t)1 << LOGN;
+    constexpr uint32_t NTILES = 1u << (LOGN - TILE_LOG);
+    __shared__ uint64_t lds[TF::LDS_WORDS];
+    const uint32_t bid = blockIdx.x;
+    const uint32_t wk = (bid & 7u) * per_xcd + (bid >> 3);
+    if (wk >= work) return;  // uniform over the block
+    const uint32_t ro = wk % nout, rest = wk / nout;
+    const uint32_t tid = threadIdx.x, sp0 = (rest % NTILES) * TF::P;
+    const int y = (int)(rest / NTILES), u = y / f.digits, j = y % f.digits;
+    const int row = (int)ro < f.alpha * j ? (int)ro : (int)ro + f.skip_n;  // past the digit's own rows
+    const int prime = row < f.Lc ? row : f.L + row - f.Lc;
+    const uint64_t q = tab.mods[prime], qi = f.qinv[prime];
+    const uint64_t* src = f.in + (size_t)u * f.in_stride + (size_t)(f.in_row0 + f.alpha * j) * N;
+    const uint64_t* cst0 = f.cst + (size_t)(f.alpha * j) * f.cst_stride + prime;
+    uint64_t x[NTT_EPT];
+    {
+        uint64_t qa[A], wa[A], wpa[A], c[A];
+        #pragma unroll
+        for (int a = 0; a < A; a++) {
+            qa[a] = tab.mods[f.in_prime0 + f.alpha * j + a];
+            wa[a] = f.inv[2 * (size_t)(f.alpha * j + a)];
+            wpa[a] = f.inv[2 * (size_t)(f.alpha * j + a) + 1];
+            c[a] = cst0[(size_t)a * f.cst_stride];
+        }
+        #pragma unroll
+        for (int v = 0; v < NTT_EPT; v++) {
+            const uint32_t e = TF::gidx(insert_bits(tid, v, P_HI, R), sp0);
+            u128p acc{0, 0};
+            #pragma unroll
+            for (int a = 0; a < A; a++) add128(acc, mul128(shoup(src[(size_t)a * N + e], wa[a], wpa[a], qa[a]), c[a]));
+            x[v] = redc(acc, q, qi);
+        }
+    }
+    const uint64_t* tw = tab.base + ((size_t)prime * 2) * 2 * N;
+    uint64_t* dst = f.out + (size_t)y * f.out_stride + (size_t)row * N;
+    // the same per-prime choice as the forward transform (no conditional subtractions
+    // below 2^57), so its low-bit pass finds the bounds it expects
+    auto pass = [&](auto nr_c) __attribute__((always_inline)) {
+        constexpr bool NR = decltype(nr_c)::value;
+        TF::template butterflies<R, R, 0, NR>(x, tid, 0, sp0, tw, nullptr, q);
+        #pragma unroll
+        for (int v = 0; v < NTT_EPT; v++) lds[insert_bits(tid, v, P_HI, R)] = x[v];
+        __syncthreads();
+        #pragma unroll
+        for (int v = 0; v < NTT_EPT; v++) x[v] = lds[insert_bits(tid, v, P_LO, R)];
+        TF::template butterflies<R, 0, R, NR>(x, tid, 0, sp0, tw, nullptr, q);
+        #pragma unroll
+        for (int v = 0; v < NTT_EPT; v++) dst[TF::gidx(insert_bits(tid, v, P_LO, R), sp0)] = x[v];
+    };
+    if (q < ((uint64_t)1 << 57)) pass(std::true_type{});
+    else pass(std::false_type{});
+}
+
+template <int LOGN>
+static void conv_fused_logn(const Ctx& c, const ConvFused& f, int polys, hipStream_t st) {
+    NttTab<uint64_t> tab{c.d_tw, c.d_ninv, c.d_mods, c.d_tw2};
+    const uint32_t nout = (uint32_t)(f.out_rows - f.skip_n);
+    const uint64_t work = (uint64_t)nout * (1u << (LOGN - TILE_LOG)) * (uint32_t)polys;
+    const uint32_t per_xcd = (uint32_t)((work + 7) / 8);
+    const dim3 grid(per_xcd * 8);
+    switch (f.alpha) {
+        case 1: hipLaunchKernelGGL((conv_fused_kernel<1, LOGN>), grid, dim3(NTT_THREADS), 0, st, f, tab, nout, (uint32_t)work, per_xcd); break;
+        case 2: hipLaunchKernelGGL((conv_fused_kernel<2, LOGN>), grid, dim3(NTT_THREADS), 0, st, f, tab, nout, (uint32_t)work, per_xcd); break;
+        case 3: hipLaunchKernelGGL((conv_fused_kernel<3, LOGN>), grid, dim3(NTT_THREADS), 0, st, f, tab, nout, (uint32_t)work, per_xcd); break;
+        default: hipLaunchKernelGGL((conv_fused_kernel<4, LOGN>), grid, dim3(NTT_THREADS), 0, st, f, tab, nout, (uint32_t)work, per_xcd); break;
+    }
+}
+
+bool conv_fused_ring(const Ctx& c) { return c.logn == 16; }
+
+// ModUp of U sources at level Lc: tmpC [U][Lc][n] (coefficient domain) -> X[U][dn][R][n],
+// every row outside each digit through the forward high-bit pass.
+void k_modup_fused(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, hipStream_t st) {
+    const int dn = Lc / c.alpha, R = Lc + c.K;
+    ConvFused f;
+    f.in = tmpC;
+    f.out = X;
+    f.in_stride = (size_t)Lc * c.n;
+    f.out_stride = (size_t)R * c.n;
+    f.in_row0 = 0;
+    f.in_prime0 = 0;
+    f.digits = dn;
+    f.alpha = c.alpha;
+    f.out_rows = R;
+    f.skip_n = c.alpha;
+    f.Lc = Lc;
+    f.L = c.L;
+    f.inv = c.d_modup_inv;
+    f.cst = c.d_modup_c;
+    f.cst_stride = (size_t)c.nq;
+    f.qinv = c.d_qinv;
+    const double n = c.n, polys = (double)U * dn;
+    // reads the digit's rows once, writes every converted row once; butterflies of the pass
+    TimeScope ts(c, HC_KT_CONV_FUSED, st, 8.0 * n * polys * R, polys * (n / 2) * 8 * (R - c.alpha));
+    conv_fused_logn<16>(c, f, U * dn, st);
+}
+
+// ModDown's conversion of M jobs (2 components each) at level Lc: the special rows of
+// T [M][2][R][n] (coefficient domain) -> conv [M][2][Lc][n] through the forward
+// high-bit pass.
+void k_moddown_fused(const Ctx& c, uint64_t* conv, const uint64_t* T, int M, int Lc, hipStream_t st) {
+    const int R = Lc + c.K;
+    ConvFused f;
+    f.in = T;
+    f.out = conv;
+    f.in_stride = (size_t)R * c.n;
+    f.out_stride = (size_t)Lc * c.n;
+    f.in_row0 = Lc;
+    f.in_prime0 = c.L;
+    f.digits = 1;
+    f.alpha = c.K;
+    f.out_rows = Lc;
+    f.skip_n = 0;
+    f.Lc = Lc;
+    f.L = c.L;
+    f.inv = c.d_moddown_inv;
+    f.cst = c.d_moddown_c;
+    f.cst_stride = (size_t)c.L;
+    f.qinv = c.d_qinv;
+    const double n = c.n, polys = 2.0 * M;
+    TimeScope ts(c, HC_KT_CONV_FUSED, st, 8.0 * n * polys * (c.K + Lc), polys * (n / 2) * 8 * Lc);
+    conv_fused_logn<16>(c, f, 2 * M, st);
+}
+
 // Grid: (tiles of a row, polynomials, rows). WPE: minimum waves per SIMD the
 // registers must allow (1 = no constraint).
 template <typename T, bool INV, int LOGN, int S, int BLO, int ST0, bool LAST, int WPE>
@@ -632,6 +793,23 @@ void ntt64(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb
     NttTab<uint64_t> tab{c.d_tw, c.d_ninv, c.d_mods, c.d_tw2};
     if (inverse) run_ntt<uint64_t, true>(c, HC_KT_NTT_INV, data, poly_stride, count, limb_first, nlimbs, tab, stream);
     else run_ntt<uint64_t, false>(c, HC_KT_NTT_FWD, data, poly_stride, count, limb_first, nlimbs, tab, stream);
+}
+
+// Only the low-bit pass of a two-pass ring: the inverse transform's first pass or the
+// forward transform's last (the other pass runs inside k_modup_fused / k_moddown_fused).
+template <int LOGN>
+static void low_pass_logn(const Ctx& c, uint64_t* data, size_t stride, int count, int lf, int nl, bool inverse,
+                          hipStream_t st) {
+    NttTab<uint64_t> tab{c.d_tw, c.d_ninv, c.d_mods, c.d_tw2};
+    constexpr int SL = 8, SH = LOGN - 8;
+    if (inverse) pass<uint64_t, true, LOGN, SL, 0, 0, false>(c, HC_KT_NTT_INV, data, stride, count, lf, nl, tab, st);
+    else pass<uint64_t, false, LOGN, SL, 0, SH, true>(c, HC_KT_NTT_FWD, data, stride, count, lf, nl, tab, st);
+}
+
+void ntt64_low_pass(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb_first, int nlimbs,
+                    bool inverse, hipStream_t stream) {
+    if (count <= 0 || nlimbs <= 0 || c.logn != 16) return;
+    low_pass_logn<16>(c, data, poly_stride, count, limb_first, nlimbs, inverse, stream);
 }
 
 void ntt32(const Ctx& c, uint32_t* data, int count, bool inverse, hipStream_t stream) {

@@ -165,9 +165,9 @@ _sig("hc_server_poll", _st, c_vp, ctypes.POINTER(ServerResult), ctypes.c_uint32,
 _sig("hc_server_stats_get", _st, c_vp, ctypes.POINTER(ServerStats))
 _sig("hc_server_destroy", None, c_vp)
 
-KT_NTT_FWD, KT_NTT_INV, KT_KS_INNER, KT_DIAG_MAC, KT_MODUP = 0, 1, 2, 3, 4
+KT_NTT_FWD, KT_NTT_INV, KT_KS_INNER, KT_DIAG_MAC, KT_MODUP, KT_CONV_FUSED = 0, 1, 2, 3, 4, 5
 KT_NAMES = {KT_NTT_FWD: "ntt_forward", KT_NTT_INV: "ntt_inverse", KT_KS_INNER: "keyswitch_inner",
-            KT_DIAG_MAC: "diag_mac", KT_MODUP: "modup"}
+            KT_DIAG_MAC: "diag_mac", KT_MODUP: "modup", KT_CONV_FUSED: "conv_fused"}
 
 EXPORTED = [
     "hc_status_str", "hc_context_create", "hc_context_destroy", "hc_context_primes", "hc_context_trim",
