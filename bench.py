@@ -71,16 +71,20 @@ def kernel_rooflines(ctx, hc):
         sec = t["ms"] / 1e3
         out[name] = dict(t, sec=sec)
     rl = {}
-    valu = ntt_valu_per_butterfly()
+    # the counts of the NTT pass variant in use (each variant is its own code object)
+    rec = valu_per_launch()
+    valu = {k: v["valu_lane_instr_per_launch"]
+            for k, v in rec.get("variants", {}).get(str(ctx.tune_get()[1]), {}).items()}
     for name, t in out.items():
-        if name.startswith("ntt"):
-            # VALU lane-instructions per butterfly counted by rocprofv3 (SQ_INSTS_VALU x 64
-            # over the transform's butterflies) for this direction, times the live rate
-            ipb = valu.get(name)
-            ach = ipb * t["ops"] / t["sec"] / 1e12 if ipb else None
+        if name.startswith("ntt") or name == "conv_fused":
+            # VALU lane-instructions per launch counted by rocprofv3 on this same workload
+            # (SQ_INSTS_VALU x 64, mean over the class's launches of a compression), times
+            # the launches, over the live device time
+            vpl = valu.get(name)
+            ach = vpl * t["launches"] / t["sec"] / 1e12 if vpl else None
             rl[name] = {"bound": "alu", "achieved": round(ach, 3) if ach else None, "peak": round(VALU_PEAK_T, 3),
                         "unit": "T VALU lane-instr/s", "frac": round(ach / VALU_PEAK_T, 4) if ach else None,
-                        "traffic": None, "valu_lane_instr_per_butterfly": ipb,
+                        "traffic": None, "valu_lane_instr_per_launch": vpl,
                         "butterflies_per_s_T": round(t["ops"] / t["sec"] / 1e12, 4),
                         "avg_launch_us": round(t["ms"] * 1e3 / t["launches"], 2),
                         "launches": t["launches"], "ms": round(t["ms"], 2)}
@@ -102,20 +106,19 @@ def sources_current(rec):
     return h.hexdigest() == rec["sources_sha256"]
 
 
-def ntt_valu_per_butterfly():
-    """VALU lane-instructions per butterfly of each NTT direction, from the committed
-    rocprofv3 counter summary (SQ_INSTS_VALU of the NTT probe); empty when missing or
-    when ntt.hip changed since."""
-    path = os.path.join(ROOT, "profiles", "ntt_valu_large-65536.json")
+def valu_per_launch():
+    """The committed rocprofv3 counter summary of this benchmark's own compressions:
+    VALU lane-instructions per launch of each transform class, per NTT pass variant;
+    empty when missing or when the kernels' sources changed since."""
+    path = os.path.join(ROOT, "profiles", "valu_large-65536.json")
     if not os.path.exists(path):
         return {}
     with open(path) as f:
         rec = json.load(f)
     if not sources_current(rec):
-        log("NTT counter summary is stale (ntt.hip changed): NTT roofline reported as null")
+        log("VALU counter summary is stale (kernel sources changed): transform rooflines reported as null")
         return {}
-    return {"ntt_forward": rec["forward"]["valu_lane_instr_per_butterfly"],
-            "ntt_inverse": rec["inverse"]["valu_lane_instr_per_butterfly"]}
+    return rec
 
 
 def measured_traffic(workload):
@@ -751,33 +754,6 @@ def small_config_latency(wl_name, reps=20, config=None):
     return res
 
 
-def ntt_probe(wl_name, reps):
-    """Forward and inverse transforms of [64][3][n] (the Comp level's key-switching
-    batches) on random canonical residues; prints the mean time per launch pair."""
-    import numpy as np
-    import torch
-    import workloads as W
-    from paper_2408_17063_amd import hc
-    r = W.RINGS[W.WORKLOADS[wl_name].ring]
-    ctx = hc.Context(log_n=int(math.log2(r.n)), p=r.p, L=r.L, q_bits=r.q_bits, K=r.K, p_bits=r.p_bits)
-    rng = np.random.default_rng(0)
-    host = np.stack([rng.integers(0, q, size=(64, ctx.n), dtype=np.uint64) for q in ctx.primes[:3]], axis=1)
-    x = torch.from_numpy(host.view(np.int64)).cuda()
-    torch.cuda.synchronize()
-    ctx.timing(True)
-    for _ in range(reps):
-        ctx.ntt(x, 0, 3)
-        ctx.ntt(x, 0, 3, inverse=True)
-    torch.cuda.synchronize()
-    ok = bool(np.array_equal(x.cpu().numpy().view(np.uint64), host))
-    f, i = ctx.timing_read(hc.KT_NTT_FWD), ctx.timing_read(hc.KT_NTT_INV)
-    ctx.timing(False)
-    print(json.dumps({"ntt_probe": {"shape": [64, 3, ctx.n], "reps": reps, "roundtrip_exact": ok,
-                                    "forward_us": round(f["ms"] * 1e3 / reps, 2),
-                                    "inverse_us": round(i["ms"] * 1e3 / reps, 2),
-                                    "butterflies_per_transform": f["ops"] / reps}}), flush=True)
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -806,6 +782,8 @@ def main():
     ap.add_argument("--out-level", type=int, default=1,
                     help="primes of the answer (1: one prime, the answer form of Sec. 6.2; 0: the Comp level)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel variants")
+    ap.add_argument("--ntt-variant", type=int, default=-1,
+                    help="set this NTT pass variant after tuning (counter collection per variant)")
     ap.add_argument("--graph-steps", type=int, default=5,
                     help="also time this many replays of the headline compression captured in a graph (0: skip)")
     ap.add_argument("--plain-db-steps", type=int, default=2,
@@ -814,10 +792,6 @@ def main():
                     help="also time ciphertext products, Power_{p-1} and a PDQ Answer with Match (0: skip)")
     ap.add_argument("--small-configs", type=int, default=20,
                     help="latency repetitions of the ring-4096 and ring-2^15 configurations (0: skip)")
-    ap.add_argument("--ntt-probe", type=int, default=0,
-                    help="only run this many forward + inverse transforms of the compression's most common "
-                         "NTT shape (64 polynomials x 3 primes at the workload's ring) and exit: a short "
-                         "program for counter collection")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the compression path here is built and measured on a single "
@@ -826,9 +800,6 @@ def main():
 
     import torch
     from paper_2408_17063_amd import hc
-    if args.ntt_probe:
-        ntt_probe(args.workload, args.ntt_probe)
-        return
     st = setup(args.workload)
     ctx, wl = st["ctx"], st["wl"]
     out = ctx.ct_tensor(1)[0]
@@ -847,6 +818,8 @@ def main():
         tune = ctx.autotune(st["gk"], st["db"], st["cts"], wl.N, wl.t, args.comp_level)
         tune["seconds"] = round(time.perf_counter() - t0, 2)
         log("autotune:", tune)
+    if args.ntt_variant >= 0:
+        ctx.tune_set(ctx.tune_get()[0], args.ntt_variant)
     for _ in range(args.warmup):
         _, info = ctx.compress(st["gk"], st["db"], st["cts"], wl.N, wl.t, out=out, comp_level=args.comp_level,
                                out_level=ol)
