@@ -394,6 +394,22 @@ extern "C" hc_status hc_context_create(const hc_params* prm, int device, hc_cont
     UP(c.d_pmodq, pmodq);
     UP(c.d_delta, delta);
     {
+        // n^-1 (and W^-1[1] n^-1) times the factor the base conversion of key switching
+        // multiplies a coefficient by before its sum, (D_j/q_i)^-1 mod q_i for a ciphertext
+        // prime of digit j and (P/p_k)^-1 mod p_k for a special prime: an inverse transform
+        // with these final constants yields the factored residues directly
+        std::vector<uint64_t> nconv(4 * (size_t)nq);
+        for (int i = 0; i < nq; i++) {
+            const uint64_t q = c.primes[i];
+            const uint64_t f = i < L ? modup_inv[2 * (size_t)i] : moddown_inv[2 * (size_t)(i - L)];
+            nconv[4 * i] = h_mulmod(ninv[4 * i], f, q);
+            nconv[4 * i + 1] = h_shoup_const(nconv[4 * i], q);
+            nconv[4 * i + 2] = h_mulmod(ninv[4 * i + 2], f, q);
+            nconv[4 * i + 3] = h_shoup_const(nconv[4 * i + 2], q);
+        }
+        UP(c.d_ninv_conv, nconv);
+    }
+    {
         // digit weights of the matrix-core multiply-accumulate: 256^s 2^64 mod q_i
         std::vector<uint64_t> mfw((size_t)L * 16, 0);
         for (int i = 0; i < L; i++)

@@ -83,6 +83,7 @@ struct hc_context {
     uint64_t* d_tw = nullptr;       // [nq][2][n][2]: (w, w') forward then inverse
     uint64_t* d_tw2 = nullptr;      // low-bit NTT pass twiddles in thread order (rings above 2^12)
     uint64_t* d_ninv = nullptr;     // [nq][4]: n^-1, Shoup; W^-1[1] n^-1, Shoup
+    uint64_t* d_ninv_conv = nullptr;  // [nq][4]: as d_ninv, times the key-switching conversion factor
     uint32_t* d_modp = nullptr;     // [1] p
     uint32_t* d_twp = nullptr;      // [2][n][2] mod p
     uint32_t* d_ninvp = nullptr;    // [4]: as d_ninv, mod p
@@ -234,12 +235,17 @@ hc_status ntt_build_tw2(Ctx& c);
 bool conv_fused_ring(const Ctx& c);
 void ntt64_low_pass(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb_first, int nlimbs,
                     bool inverse, hipStream_t stream);
-// ModUp of U sources at level Lc: tmpC [U][Lc][n] (coefficient domain) -> every row of
-// X[U][dn][R][n] outside each digit, after the forward high-bit pass (its low-bit pass
+// The inverse transform of rows limb_first.. (ciphertext primes of whole digits, or special
+// primes) scaled by the base conversion's factor: [x (D_j/q_i)^-1]_{q_i} or
+// [x (P/p_k)^-1]_{p_k} per coefficient, canonical (one multiplication folded into n^-1).
+void ntt64_inverse_conv(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb_first, int nlimbs,
+                        hipStream_t stream);
+// ModUp of U sources at level Lc: tmpC [U][Lc][n] (from ntt64_inverse_conv) -> every row
+// of X[U][dn][R][n] outside each digit, after the forward high-bit pass (its low-bit pass
 // follows); the words equal kb_modup's followed by the full transform.
 void k_modup_fused(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, hipStream_t st);
-// ModDown's P -> Q conversion of M jobs at level Lc: T [M][2][R][n] special rows
-// (coefficient domain) -> conv [M][2][Lc][n] after the forward high-bit pass.
+// ModDown's P -> Q conversion of M jobs at level Lc: T [M][2][R][n] special rows (from
+// ntt64_inverse_conv) -> conv [M][2][Lc][n] after the forward high-bit pass.
 void k_moddown_fused(const Ctx& c, uint64_t* conv, const uint64_t* T, int M, int Lc, hipStream_t st);
 
 // ------------------------------------------------------------------ kernels (ops.hip)

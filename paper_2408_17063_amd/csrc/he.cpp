@@ -147,7 +147,7 @@ static void moddown_conv(Ctx& c, uint64_t* conv, uint64_t* T, int M, int Lc, hip
     const size_t n = c.n;
     const int R = Lc + c.K;
     if (conv_fused_ring(c)) {
-        ntt64(c, T + (size_t)Lc * n, (size_t)R * n, 2 * M, c.L, c.K, true, st);
+        ntt64_inverse_conv(c, T + (size_t)Lc * n, (size_t)R * n, 2 * M, c.L, c.K, st);
         k_moddown_fused(c, conv, T, M, Lc, st);
         ntt64_low_pass(c, conv, (size_t)Lc * n, 2 * M, 0, Lc, false, st);
         return;
@@ -163,9 +163,10 @@ static void ks_raise(Ctx& c, KsScratch& s, const KsJob* d, int U, int Lc, bool p
     (void)permute;  // jobs carry their element (k = 1: no rotation)
     kb_take_c1(c, s.tmpC, s.X, d, U, Lc, st);
     if (conv_fused_ring(c)) {
-        // the inverse transform, then the conversion fused with the forward high-bit pass,
-        // then the forward low-bit pass of every converted row
-        ntt64(c, s.tmpC, (size_t)Lc * n, U, 0, Lc, true, st);
+        // the inverse transform (scaled by the conversion's factor), then the conversion
+        // fused with the forward high-bit pass, then the forward low-bit pass of every
+        // converted row
+        ntt64_inverse_conv(c, s.tmpC, (size_t)Lc * n, U, 0, Lc, st);
         k_modup_fused(c, s.X, s.tmpC, U, Lc, st);
         for (int j = 0; j < dn; j++) {
             uint64_t* Xj = s.X + (size_t)j * R * n;

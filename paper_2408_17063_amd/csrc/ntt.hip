@@ -482,20 +482,19 @@ __device__ __forceinline__ void ntt_tile(T* __restrict__ data, size_t poly_strid
 // ciphertext rows. At ring 2^16 the forward transform's first pass (8 stages over the
 // high index bits) loads each thread's 16 elements straight from device memory (the
 // DIRECT layout), so the conversion can produce them there instead: per tile and
-// output row, the kernel reads the input rows' coefficients at those 16 positions,
-// computes y_a = [x_a (D/q_a)^-1]_{q_a} and out = sum_a y_a (D/q_a) mod r (the words
-// kb_modup / kb_conv write), and runs the pass on them. The converted rows never go
-// through device memory; the input rows are read once per output row, from L2 after
-// the first.
+// output row, the kernel reads the input rows at those 16 positions -- already
+// y_a = [x_a (D/q_a)^-1]_{q_a}, the inverse transform having folded the factor into its
+// n^-1 -- computes out = sum_a y_a (D/q_a) mod r (the words kb_modup / kb_conv write),
+// and runs the pass on them. The converted rows never go through device memory; the
+// input rows are read once per output row, from L2 after the first.
 struct ConvFused {
-    const uint64_t* in;          // input polynomials (coefficient domain, canonical)
+    const uint64_t* in;          // input rows: y_a = [x_a (D/q_a)^-1]_{q_a}, canonical (ntt64_inverse_conv)
     uint64_t* out;               // output polynomials
     size_t in_stride, out_stride;  // words between consecutive input / output polynomials
     int in_row0, in_prime0;      // first input row of digit 0 (row r starts r n words in) and its prime
     int digits, alpha;           // grid y = u digits + j: source u, digit j (inputs from row in_row0 + alpha j)
     int out_rows, skip_n;        // output rows 0..out_rows-1 of polynomial y, except skip_n rows from alpha j
     int Lc, L;                   // output row r has prime r < Lc ? r : L + r - Lc
-    const uint64_t* inv;         // [digit][a][2]: (D/q_a)^-1 mod q_a and its Shoup constant
     const uint64_t* cst;         // cst[(alpha j + a) cst_stride + prime]: (D/q_a) mod prime, Montgomery form
     size_t cst_stride;
     const uint64_t* qinv;        // Montgomery constants of the primes
@@ -528,20 +527,15 @@ conv_fused_kernel(ConvFused f, NttTab<uint64_t> tab, uint32_t nout, uint32_t wor
     const uint64_t* cst0 = f.cst + (size_t)(f.alpha * j) * f.cst_stride + prime;
     uint64_t x[NTT_EPT];
     {
-        uint64_t qa[A], wa[A], wpa[A], c[A];
+        uint64_t c[A];
         #pragma unroll
-        for (int a = 0; a < A; a++) {
-            qa[a] = tab.mods[f.in_prime0 + f.alpha * j + a];
-            wa[a] = f.inv[2 * (size_t)(f.alpha * j + a)];
-            wpa[a] = f.inv[2 * (size_t)(f.alpha * j + a) + 1];
-            c[a] = cst0[(size_t)a * f.cst_stride];
-        }
+        for (int a = 0; a < A; a++) c[a] = cst0[(size_t)a * f.cst_stride];
         #pragma unroll
         for (int v = 0; v < NTT_EPT; v++) {
             const uint32_t e = TF::gidx(insert_bits(tid, v, P_HI, R), sp0);
             u128p acc{0, 0};
             #pragma unroll
-            for (int a = 0; a < A; a++) add128(acc, mul128(shoup(src[(size_t)a * N + e], wa[a], wpa[a], qa[a]), c[a]));
+            for (int a = 0; a < A; a++) add128(acc, mul128(src[(size_t)a * N + e], c[a]));
             x[v] = redc(acc, q, qi);
         }
     }
@@ -599,7 +593,6 @@ void k_modup_fused(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int L
     f.skip_n = c.alpha;
     f.Lc = Lc;
     f.L = c.L;
-    f.inv = c.d_modup_inv;
     f.cst = c.d_modup_c;
     f.cst_stride = (size_t)c.nq;
     f.qinv = c.d_qinv;
@@ -627,7 +620,6 @@ void k_moddown_fused(const Ctx& c, uint64_t* conv, const uint64_t* T, int M, int
     f.skip_n = 0;
     f.Lc = Lc;
     f.L = c.L;
-    f.inv = c.d_moddown_inv;
     f.cst = c.d_moddown_c;
     f.cst_stride = (size_t)c.L;
     f.qinv = c.d_qinv;
@@ -810,6 +802,13 @@ void ntt64_low_pass(const Ctx& c, uint64_t* data, size_t poly_stride, int count,
                     bool inverse, hipStream_t stream) {
     if (count <= 0 || nlimbs <= 0 || c.logn != 16) return;
     low_pass_logn<16>(c, data, poly_stride, count, limb_first, nlimbs, inverse, stream);
+}
+
+void ntt64_inverse_conv(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb_first, int nlimbs,
+                        hipStream_t stream) {
+    if (count <= 0 || nlimbs <= 0) return;
+    NttTab<uint64_t> tab{c.d_tw, c.d_ninv_conv, c.d_mods, c.d_tw2};
+    run_ntt<uint64_t, true>(c, HC_KT_NTT_INV, data, poly_stride, count, limb_first, nlimbs, tab, stream);
 }
 
 void ntt32(const Ctx& c, uint32_t* data, int count, bool inverse, hipStream_t stream) {
