@@ -270,9 +270,13 @@ void kb_take_c1(const Ctx& c, uint64_t* tmpC, uint64_t* X, const KsJob* jobs, in
 // ModUp of U sources [Lc][n] (coefficient domain) into digits X[U][dn][Lc+K][n]; a
 // digit's own rows are written only if own_rows.
 void kb_modup(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, bool own_rows, hipStream_t st);
-// T [M][2][Lc+K][n] = sum_j X[xidx_m][j] (rotated by k_m if hoisted) * key_m[j]
+// T [M][2][Lc+K][n] = sum_j X[xidx_m][j] (rotated by k_m if hoisted) * key_m[j], rows row0..
 void kb_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const KsJob* jobs, const KsRun* runs, int nruns, int M,
-              int Lc, bool hoisted, hipStream_t st);
+              int Lc, bool hoisted, hipStream_t st, int row0 = 0);
+// kb_final for the jobs of a pass in key runs, the ciphertext rows of T computed in place
+// from X and the keys (kb_inner need only have computed the special rows)
+void kb_final_inner(const Ctx& c, const KsJob* jobs, const KsRun* runs, int nruns, const uint64_t* X,
+                    const uint64_t* conv, int M, int Lc, bool hoisted, hipStream_t st);
 // conv [M][2][Lc][n] = Conv_{P->Q} of the special rows of T (coefficient domain)
 void kb_conv(const Ctx& c, uint64_t* conv, const uint64_t* T, int M, int Lc, hipStream_t st);
 // out_m = (sigma_k(c0_m) + (T0 - conv0) P^-1, (T1 - conv1) P^-1), NTT domain

@@ -221,9 +221,10 @@ hc_status ks_run(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
     const int R = Lc + c.K;
     auto raise = [&](const KsJob* d, int U, bool permute) { ks_raise(c, s, d, U, Lc, permute, st); };
     auto finish = [&](const KsJob* d, const KsRun* runs, int nruns, int M, bool hoisted) {
-        kb_inner(c, s.T, s.X, d, runs, nruns, M, Lc, hoisted, st);
+        // the special rows of the key products here, their ciphertext rows inside the final step
+        kb_inner(c, s.T, s.X, d, runs, nruns, M, Lc, hoisted, st, Lc);
         moddown_conv(c, s.conv, s.T, M, Lc, st);
-        kb_final(c, d, s.T, s.conv, M, Lc, st);
+        kb_final_inner(c, d, runs, nruns, s.X, s.conv, M, Lc, hoisted, st);
     };
     if (!srcs) {
         std::vector<KsJob> all(jobs);

@@ -207,10 +207,10 @@ void kb_modup(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, bo
 __global__ void kb_inner_kernel(uint64_t* __restrict__ T, const uint64_t* __restrict__ X,
                                 const KsJob* __restrict__ jobs, const KsRun* __restrict__ runs,
                                 const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv, int n,
-                                int logn, int nq, int L, int Lc, int K, int dn, int hoisted) {
+                                int logn, int nq, int L, int Lc, int K, int dn, int hoisted, int row0) {
     int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
-    const int row = blockIdx.y, R = Lc + K;
+    const int row = row0 + (int)blockIdx.y, R = Lc + K;
     const KsRun run = runs[blockIdx.z];
     const int pr = row_prime(row, Lc, L);
     const size_t keyrow = (size_t)nq * n;
@@ -243,13 +243,79 @@ __global__ void kb_inner_kernel(uint64_t* __restrict__ T, const uint64_t* __rest
     }
 }
 void kb_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const KsJob* jobs, const KsRun* runs, int nruns, int M,
-              int Lc, bool hoisted, hipStream_t st) {
+              int Lc, bool hoisted, hipStream_t st, int row0) {
     const int dn = Lc / c.alpha, R = Lc + c.K;
     // per run and row: the key (2 dn words) once; per job: its raised digits and T
-    const double rows = (double)R * c.n;
+    const double rows = (double)(R - row0) * c.n;
     TimeScope ts(c, HC_KT_KS_INNER, st, 8.0 * rows * (2.0 * dn * nruns + (dn + 2.0) * M), 2.0 * dn * rows * M);
-    hipLaunchKernelGGL(kb_inner_kernel, ew_grid(c.n, R, nruns), dim3(EW_THREADS), 0, st, T, X, jobs, runs, c.d_mods,
-                       c.d_qinv, c.n, c.logn, c.nq, c.L, Lc, c.K, dn, hoisted ? 1 : 0);
+    hipLaunchKernelGGL(kb_inner_kernel, ew_grid(c.n, R - row0, nruns), dim3(EW_THREADS), 0, st, T, X, jobs, runs,
+                       c.d_mods, c.d_qinv, c.n, c.logn, c.nq, c.L, Lc, c.K, dn, hoisted ? 1 : 0, row0);
+}
+
+// kb_final with the ciphertext rows of T computed in place, for the jobs of a pass in key
+// runs (as kb_inner): T0, T1 = sum_j X[xidx][j] (rotated if hoisted) * key[j] (one REDC of
+// the 128-bit sums, the words kb_inner writes), then out as kb_final. kb_inner then only
+// computes the special rows, so the ciphertext rows of T never go through device memory.
+__global__ void kb_final_inner_kernel(const KsJob* __restrict__ jobs, const KsRun* __restrict__ runs,
+                                      const uint64_t* __restrict__ X, const uint64_t* __restrict__ conv,
+                                      const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv,
+                                      const uint64_t* __restrict__ pinv, int n, int logn, int nq, int Lc, int K,
+                                      int dn, int hoisted, int h) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int i = blockIdx.y, R = Lc + K;
+    const KsRun run = runs[blockIdx.z];
+    const size_t keyrow = (size_t)nq * n;
+    const uint64_t* kp = jobs[run.j0].key + (size_t)i * n + x;
+    u128p a0[KS_RUN], a1[KS_RUN];
+    #pragma unroll
+    for (int u = 0; u < KS_RUN; u++) { a0[u] = u128p{0, 0}; a1[u] = u128p{0, 0}; }
+    for (int j = 0; j < dn; j++) {
+        const uint64_t k0 = kp[(size_t)j * 2 * keyrow], k1 = kp[(size_t)j * 2 * keyrow + keyrow];
+        #pragma unroll
+        for (int u = 0; u < KS_RUN; u++) {
+            if (u < (int)run.cnt) {
+                const KsJob jb = jobs[run.j0 + u];
+                const uint32_t src = (!hoisted || jb.k == 1) ? x : galois_src(x, jb.k, logn);
+                const uint64_t xv = X[((size_t)jb.xidx * dn + j) * R * n + (size_t)i * n + src];
+                add128(a0[u], mul128(xv, k0));
+                add128(a1[u], mul128(xv, k1));
+            }
+        }
+    }
+    const uint64_t q = mods[i], qi = qinv[i], pi = pinv[2 * i], pis = pinv[2 * i + 1];
+    #pragma unroll
+    for (int u = 0; u < KS_RUN; u++) {
+        if (u < (int)run.cnt) {
+            const int m = (int)run.j0 + u;
+            const KsJob jb = jobs[m];
+            const uint64_t* Cm = conv + (size_t)m * 2 * Lc * n + (size_t)i * n + x;
+            const uint64_t d0 = shoup(sub_mod(redc(a0[u], q, qi), Cm[0], q), pi, pis, q);
+            const uint64_t d1 = shoup(sub_mod(redc(a1[u], q, qi), Cm[(size_t)Lc * n], q), pi, pis, q);
+            const uint32_t src = (jb.k == 1) ? x : galois_src(x, jb.k, logn);
+            const uint64_t c0 = jb.in[(size_t)i * n + src];
+            if (jb.tstride) {
+                const size_t o = ((size_t)i * (n >> 6) + (x >> 6)) * jb.tstride + 2 * (x & 63);
+                *reinterpret_cast<ulonglong2*>(jb.out + o) =
+                    ulonglong2{split_word(add_mod(d0, c0, q), h), split_word(d1, h)};
+            } else {
+                jb.out[(size_t)i * n + x] = add_mod(d0, c0, q);
+                jb.out[((size_t)Lc + i) * n + x] = d1;
+            }
+        }
+    }
+}
+
+void kb_final_inner(const Ctx& c, const KsJob* jobs, const KsRun* runs, int nruns, const uint64_t* X,
+                    const uint64_t* conv, int M, int Lc, bool hoisted, hipStream_t st) {
+    const int dn = Lc / c.alpha;
+    // per run and row the key (2 dn words) once; per job its digits (dn), the two
+    // conversions, the rotated c0 and the two outputs
+    const double rows = (double)Lc * c.n;
+    TimeScope ts(c, HC_KT_KS_INNER, st, 8.0 * rows * (2.0 * dn * nruns + (dn + 5.0) * M), 2.0 * dn * rows * M);
+    hipLaunchKernelGGL(kb_final_inner_kernel, ew_grid(c.n, Lc, nruns), dim3(EW_THREADS), 0, st, jobs, runs, X, conv,
+                       c.d_mods, c.d_qinv, c.d_pinv, c.n, c.logn, c.nq, Lc, c.K, dn, hoisted ? 1 : 0,
+                       diag_split_h(c, Lc));
 }
 
 // conv[m][comp][i][x] = sum_k [T_{p_k}(x) (P/p_k)^-1]_{p_k} (P/p_k) mod q_i (coefficient domain).
