@@ -240,6 +240,14 @@ void ntt64_low_pass(const Ctx& c, uint64_t* data, size_t poly_stride, int count,
 // [x (P/p_k)^-1]_{p_k} per coefficient, canonical (one multiplication folded into n^-1).
 void ntt64_inverse_conv(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb_first, int nlimbs,
                         hipStream_t stream);
+// ModUp's inputs at ring 2^16 straight from the jobs' ciphertexts: row r of tmpC[u] gets c1
+// (row Lc + r) of jobs[u].in rotated by sigma_{k_u}, through the inverse transform's first
+// pass, and the rotated words also go to the digit's own row of X (ModUp leaves those
+// unchanged); then ntt64_inverse_high_conv finishes the transform. Together: kb_take_c1
+// followed by ntt64_inverse_conv.
+void ntt_take_c1_low(const Ctx& c, const KsJob* jobs, uint64_t* tmpC, uint64_t* X, int U, int Lc, hipStream_t st);
+void ntt64_inverse_high_conv(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb_first, int nlimbs,
+                             hipStream_t stream);
 // ModUp of U sources at level Lc: tmpC [U][Lc][n] (from ntt64_inverse_conv) -> every row
 // of X[U][dn][R][n] outside each digit, after the forward high-bit pass (its low-bit pass
 // follows); the words equal kb_modup's followed by the full transform.
@@ -331,6 +339,13 @@ void k_mul_mont(const Ctx& c, uint64_t* out, const uint64_t* a, const uint64_t* 
 // encryption finish (coefficient domain): c0 += e0 + Delta m ; c1 += e1
 void k_enc_finish(const Ctx& c, uint64_t* ct, const uint64_t* e0, const uint64_t* e1,
                   const uint32_t* m, hipStream_t st);
+// NTT-domain index that sigma_k pulls from: entry i holds a(psi^(2 brv(i)+1)),
+// so sigma_k(a) at i equals a at the entry whose exponent is (2 brv(i)+1) k.
+__device__ __forceinline__ uint32_t galois_src(uint32_t i, uint32_t k, int logn) {
+    uint32_t e = (__brev(i) >> (32 - logn)) * 2u + 1u;
+    uint32_t e2 = (e * k) & ((2u << logn) - 1u);
+    return __brev((e2 - 1u) >> 1) >> (32 - logn);
+}
 // diagonal multiply-accumulate:
 //   A[pp][g] (+)= sum_{beta < kb, b < B} D[beta][g][b] * R[pp][beta][b]
 // R, A given as device arrays of ciphertext pointers; D contiguous

@@ -161,12 +161,12 @@ static void ks_raise(Ctx& c, KsScratch& s, const KsJob* d, int U, int Lc, bool p
     const size_t n = c.n;
     const int R = Lc + c.K, dn = Lc / c.alpha, a = c.alpha;
     (void)permute;  // jobs carry their element (k = 1: no rotation)
-    kb_take_c1(c, s.tmpC, s.X, d, U, Lc, st);
     if (conv_fused_ring(c)) {
-        // the inverse transform (scaled by the conversion's factor), then the conversion
-        // fused with the forward high-bit pass, then the forward low-bit pass of every
-        // converted row
-        ntt64_inverse_conv(c, s.tmpC, (size_t)Lc * n, U, 0, Lc, st);
+        // the rotated c1 taken inside the inverse transform's first pass, its last pass
+        // scaled by the conversion's factor, then the conversion fused with the forward
+        // high-bit pass, then the forward low-bit pass of every converted row
+        ntt_take_c1_low(c, d, s.tmpC, s.X, U, Lc, st);
+        ntt64_inverse_high_conv(c, s.tmpC, (size_t)Lc * n, U, 0, Lc, st);
         k_modup_fused(c, s.X, s.tmpC, U, Lc, st);
         for (int j = 0; j < dn; j++) {
             uint64_t* Xj = s.X + (size_t)j * R * n;
@@ -178,6 +178,7 @@ static void ks_raise(Ctx& c, KsScratch& s, const KsJob* d, int U, int Lc, bool p
         ntt64_low_pass(c, s.X + (size_t)Lc * n, (size_t)R * n, U * dn, c.L, c.K, false, st);
         return;
     }
+    kb_take_c1(c, s.tmpC, s.X, d, U, Lc, st);
     ntt64(c, s.tmpC, (size_t)Lc * n, U, 0, Lc, true, st);
     kb_modup(c, s.X, s.tmpC, U, Lc, false, st);
     for (int j = 0; j < dn; j++) {

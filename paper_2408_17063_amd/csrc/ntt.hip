@@ -804,6 +804,67 @@ void ntt64_low_pass(const Ctx& c, uint64_t* data, size_t poly_stride, int count,
     low_pass_logn<16>(c, data, poly_stride, count, limb_first, nlimbs, inverse, stream);
 }
 
+// The inverse transform's first pass (the low index bits, ring 2^16) of ModUp's inputs,
+// loading them from the jobs' ciphertexts: word g of row r of polynomial u is c1 of
+// jobs[u].in at sigma_{k_u}'s source of g, and it is also stored to the digit's own row
+// of X. Otherwise the pass of ntt_tile (DIRECT_LO, inverse).
+__global__ void __launch_bounds__(NTT_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+ntt_take_c1_low_kernel(const KsJob* __restrict__ jobs, uint64_t* __restrict__ tmpC, uint64_t* __restrict__ X,
+                       NttTab<uint64_t> tab, int Lc, int alpha, int R, int dn) {
+    constexpr int LOGN = 16, S = 8, RR = NTT_EPT_LOG;
+    typedef Tile<uint64_t, true, LOGN, S, 0, 0> TL;
+    static_assert(TL::DIRECT_LO && TL::TW2 && TL::THREADS == NTT_THREADS, "ring 2^16 low-bit pass");
+    constexpr int PH = TL::LOGP + RR;
+    constexpr size_t N = (size_t)1 << LOGN;
+    __shared__ uint64_t lds[TL::LDS_WORDS];
+    const uint32_t tid = threadIdx.x, bx = blockIdx.x, u = blockIdx.y, r = blockIdx.z;
+    const int prime = (int)r;
+    const uint64_t q = tab.mods[prime];
+    const uint64_t* tw = tab.base + ((size_t)prime * 2 + 1) * 2 * N;
+    const uint64_t* tw2 = tab.tw2 + (((size_t)prime * 2 + 1) * gridDim.x + bx) * (size_t)TL::TW_PASS * TL::THREADS * 2;
+    const uint32_t sp0 = bx * TL::P;
+    const KsJob jb = jobs[u];
+    const uint64_t* in = jb.in + (size_t)(Lc + (int)r) * N;
+    uint64_t* own = X + (((size_t)u * dn + r / alpha) * R + r) * N;
+    #pragma unroll
+    for (int i = 0; i < NTT_EPT; i++) {
+        const uint32_t f = tid + i * TL::THREADS;
+        const uint32_t e = ((f & ((1u << S) - 1u)) << TL::LOGP) | (f >> S);
+        const uint32_t g = TL::gidx(e, sp0);
+        const uint64_t v = in[jb.k == 1 ? g : galois_src(g, jb.k, LOGN)];
+        own[g] = v;
+        lds[TL::lpos(e)] = v;
+    }
+    __syncthreads();
+    TL::template round<RR, 0, 0>(lds, sp0, tw, tw2, q);
+    __syncthreads();
+    const uint32_t gh = TL::swap_nibbles(tid);
+    uint64_t x[NTT_EPT];
+    #pragma unroll
+    for (int v = 0; v < NTT_EPT; v++) x[v] = lds[TL::lpos(insert_bits(gh, v, PH, RR))];
+    TL::template butterflies<RR, RR, RR>(x, gh, 0, sp0, tw, tw2, q);
+    uint64_t* a = tmpC + ((size_t)u * Lc + r) * N;
+    #pragma unroll
+    for (int v = 0; v < NTT_EPT; v++) a[TL::gidx(insert_bits(gh, v, PH, RR), sp0)] = x[v];
+}
+
+void ntt_take_c1_low(const Ctx& c, const KsJob* jobs, uint64_t* tmpC, uint64_t* X, int U, int Lc, hipStream_t st) {
+    if (U <= 0 || c.logn != 16) return;
+    NttTab<uint64_t> tab{c.d_tw, c.d_ninv, c.d_mods, c.d_tw2};
+    const double n = c.n;
+    // reads the rotated c1 rows, writes them to X and the pass's output: 24 bytes per word
+    TimeScope ts(c, HC_KT_NTT_INV, st, 24.0 * n * U * Lc, (double)U * Lc * (n / 2) * 8);
+    hipLaunchKernelGGL(ntt_take_c1_low_kernel, dim3(1u << (16 - TILE_LOG), (unsigned)U, (unsigned)Lc),
+                       dim3(NTT_THREADS), 0, st, jobs, tmpC, X, tab, Lc, c.alpha, Lc + c.K, Lc / c.alpha);
+}
+
+void ntt64_inverse_high_conv(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb_first, int nlimbs,
+                             hipStream_t stream) {
+    if (count <= 0 || nlimbs <= 0 || c.logn != 16) return;
+    NttTab<uint64_t> tab{c.d_tw, c.d_ninv_conv, c.d_mods, c.d_tw2};
+    pass<uint64_t, true, 16, 8, 8, 8, true>(c, HC_KT_NTT_INV, data, poly_stride, count, limb_first, nlimbs, tab, stream);
+}
+
 void ntt64_inverse_conv(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb_first, int nlimbs,
                         hipStream_t stream) {
     if (count <= 0 || nlimbs <= 0) return;

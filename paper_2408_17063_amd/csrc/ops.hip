@@ -25,13 +25,6 @@ __device__ __forceinline__ uint64_t split_word(uint64_t v, int h) {
     return ((v >> h) << 32) | (v & ((1ull << h) - 1));
 }
 
-// NTT-domain index that sigma_k pulls from: entry i holds a(psi^(2 brv(i)+1)),
-// so sigma_k(a) at i equals a at the entry whose exponent is (2 brv(i)+1) k.
-__device__ __forceinline__ uint32_t galois_src(uint32_t i, uint32_t k, int logn) {
-    uint32_t e = (__brev(i) >> (32 - logn)) * 2u + 1u;
-    uint32_t e2 = (e * k) & ((2u << logn) - 1u);
-    return __brev((e2 - 1u) >> 1) >> (32 - logn);
-}
 
 // ------------------------------------------------------------------ basic element-wise
 
