@@ -248,6 +248,11 @@ void ntt64_inverse_conv(const Ctx& c, uint64_t* data, size_t poly_stride, int co
 void ntt_take_c1_low(const Ctx& c, const KsJob* jobs, uint64_t* tmpC, uint64_t* X, int U, int Lc, hipStream_t st);
 void ntt64_inverse_high_conv(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb_first, int nlimbs,
                              hipStream_t stream);
+// ModDown of the M jobs of a pass at ring 2^16: the special rows of their key products
+// T[m][comp][Lc..R-1] computed inside the inverse transform's first pass (the words
+// kb_inner writes there); ntt64_inverse_high_conv then finishes the transform.
+void ntt_inner_low(const Ctx& c, const KsJob* jobs, const uint64_t* X, uint64_t* T, int M, int Lc, bool hoisted,
+                   hipStream_t st);
 // ModUp of U sources at level Lc: tmpC [U][Lc][n] (from ntt64_inverse_conv) -> every row
 // of X[U][dn][R][n] outside each digit, after the forward high-bit pass (its low-bit pass
 // follows); the words equal kb_modup's followed by the full transform.

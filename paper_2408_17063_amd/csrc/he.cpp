@@ -222,9 +222,17 @@ hc_status ks_run(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
     const int R = Lc + c.K;
     auto raise = [&](const KsJob* d, int U, bool permute) { ks_raise(c, s, d, U, Lc, permute, st); };
     auto finish = [&](const KsJob* d, const KsRun* runs, int nruns, int M, bool hoisted) {
-        // the special rows of the key products here, their ciphertext rows inside the final step
-        kb_inner(c, s.T, s.X, d, runs, nruns, M, Lc, hoisted, st, Lc);
-        moddown_conv(c, s.conv, s.T, M, Lc, st);
+        // the key products' special rows inside the inverse transform's first pass (ring
+        // 2^16) or by kb_inner, their ciphertext rows inside the final step
+        if (conv_fused_ring(c)) {
+            ntt_inner_low(c, d, s.X, s.T, M, Lc, hoisted, st);
+            ntt64_inverse_high_conv(c, s.T + (size_t)Lc * n, (size_t)R * n, 2 * M, c.L, c.K, st);
+            k_moddown_fused(c, s.conv, s.T, M, Lc, st);
+            ntt64_low_pass(c, s.conv, (size_t)Lc * n, 2 * M, 0, Lc, false, st);
+        } else {
+            kb_inner(c, s.T, s.X, d, runs, nruns, M, Lc, hoisted, st, Lc);
+            moddown_conv(c, s.conv, s.T, M, Lc, st);
+        }
         kb_final_inner(c, d, runs, nruns, s.X, s.conv, M, Lc, hoisted, st);
     };
     if (!srcs) {

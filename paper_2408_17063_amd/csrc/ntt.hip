@@ -848,6 +848,69 @@ ntt_take_c1_low_kernel(const KsJob* __restrict__ jobs, uint64_t* __restrict__ tm
     for (int v = 0; v < NTT_EPT; v++) a[TL::gidx(insert_bits(gh, v, PH, RR), sp0)] = x[v];
 }
 
+// ModDown's inverse transform, first pass (ring 2^16), of the special rows of the key
+// products, computing them while loading: word g of row Lc + k of T[m][comp] is
+// sum_j X[xidx_m][j][Lc + k][src(g)] key_m[j][comp][L + k][g] (src: sigma_{k_m}'s source
+// if hoisted), one REDC of the 128-bit sum -- the words kb_inner writes. Blocks of
+// consecutive jobs at one tile run on one XCD (the grid's x is the 16 tiles), so jobs
+// sharing a key read it through that XCD's L2.
+__global__ void __launch_bounds__(NTT_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+ntt_inner_low_kernel(const KsJob* __restrict__ jobs, const uint64_t* __restrict__ X, uint64_t* __restrict__ T,
+                     NttTab<uint64_t> tab, const uint64_t* __restrict__ qinv, int Lc, int K, int L, int nq, int dn,
+                     int hoisted) {
+    constexpr int LOGN = 16, S = 8, RR = NTT_EPT_LOG;
+    typedef Tile<uint64_t, true, LOGN, S, 0, 0> TL;
+    static_assert(TL::DIRECT_LO && TL::TW2 && TL::THREADS == NTT_THREADS, "ring 2^16 low-bit pass");
+    constexpr int PH = TL::LOGP + RR;
+    constexpr size_t N = (size_t)1 << LOGN;
+    __shared__ uint64_t lds[TL::LDS_WORDS];
+    const uint32_t tid = threadIdx.x, bx = blockIdx.x, mc = blockIdx.y, k = blockIdx.z;
+    const int m = (int)(mc >> 1), comp = (int)(mc & 1), R = Lc + K;
+    const int prime = L + (int)k;
+    const uint64_t q = tab.mods[prime], qi = qinv[prime];
+    const uint64_t* tw = tab.base + ((size_t)prime * 2 + 1) * 2 * N;
+    const uint64_t* tw2 = tab.tw2 + (((size_t)prime * 2 + 1) * gridDim.x + bx) * (size_t)TL::TW_PASS * TL::THREADS * 2;
+    const uint32_t sp0 = bx * TL::P;
+    const KsJob jb = jobs[m];
+    const size_t keyrow = (size_t)nq * N;
+    const uint64_t* kp = jb.key + (size_t)comp * keyrow + (size_t)prime * N;
+    const uint64_t* xp = X + ((size_t)jb.xidx * dn * R + Lc + k) * N;
+    const bool rot = hoisted && jb.k != 1;
+    #pragma unroll
+    for (int i = 0; i < NTT_EPT; i++) {
+        const uint32_t f = tid + i * TL::THREADS;
+        const uint32_t e = ((f & ((1u << S) - 1u)) << TL::LOGP) | (f >> S);
+        const uint32_t g = TL::gidx(e, sp0);
+        const uint32_t src = rot ? galois_src(g, jb.k, LOGN) : g;
+        u128p acc{0, 0};
+        for (int j = 0; j < dn; j++) add128(acc, mul128(xp[(size_t)j * R * N + src], kp[(size_t)j * 2 * keyrow + g]));
+        lds[TL::lpos(e)] = redc(acc, q, qi);
+    }
+    __syncthreads();
+    TL::template round<RR, 0, 0>(lds, sp0, tw, tw2, q);
+    __syncthreads();
+    const uint32_t gh = TL::swap_nibbles(tid);
+    uint64_t x[NTT_EPT];
+    #pragma unroll
+    for (int v = 0; v < NTT_EPT; v++) x[v] = lds[TL::lpos(insert_bits(gh, v, PH, RR))];
+    TL::template butterflies<RR, RR, RR>(x, gh, 0, sp0, tw, tw2, q);
+    uint64_t* a = T + ((size_t)mc * R + Lc + k) * N;
+    #pragma unroll
+    for (int v = 0; v < NTT_EPT; v++) a[TL::gidx(insert_bits(gh, v, PH, RR), sp0)] = x[v];
+}
+
+void ntt_inner_low(const Ctx& c, const KsJob* jobs, const uint64_t* X, uint64_t* T, int M, int Lc, bool hoisted,
+                   hipStream_t st) {
+    if (M <= 0 || c.logn != 16) return;
+    NttTab<uint64_t> tab{c.d_tw, c.d_ninv, c.d_mods, c.d_tw2};
+    const int dn = Lc / c.alpha;
+    const double n = c.n;
+    // per job and special row: its digits and the key words of both components, the pass's output
+    TimeScope ts(c, HC_KT_NTT_INV, st, 8.0 * n * M * c.K * (dn + 2.0 * dn + 2.0), 2.0 * M * c.K * (n / 2) * 8);
+    hipLaunchKernelGGL(ntt_inner_low_kernel, dim3(1u << (16 - TILE_LOG), (unsigned)(2 * M), (unsigned)c.K),
+                       dim3(NTT_THREADS), 0, st, jobs, X, T, tab, c.d_qinv, Lc, c.K, c.L, c.nq, dn, hoisted ? 1 : 0);
+}
+
 void ntt_take_c1_low(const Ctx& c, const KsJob* jobs, uint64_t* tmpC, uint64_t* X, int U, int Lc, hipStream_t st) {
     if (U <= 0 || c.logn != 16) return;
     NttTab<uint64_t> tab{c.d_tw, c.d_ninv, c.d_mods, c.d_tw2};
