@@ -97,6 +97,50 @@ def kernel_rooflines(ctx, hc):
     return rl
 
 
+def choose_baby(s, k):
+    """The planner's baby-step count: the power of two B in [1, s] minimising
+    k (B - 1) + (s / B - 1), ties to the larger B."""
+    best, bb, B = None, 1, 1
+    while B <= s:
+        cost = k * (B - 1) + (s // B - 1)
+        if best is None or cost <= best:
+            best, bb = cost, B
+        B *= 2
+    return bb
+
+
+def mac_stream_ceiling(ctx, t, info):
+    """The diagonal multiply-accumulate's read and write bytes per launch (digit layout,
+    one B class) replayed by the library's stream probe: contiguous reads with the same
+    share of contiguous writes mixed in, an upper bound for the kernel's own pattern
+    (its writes are 64-byte runs into every (pair, giant) output). t: the kernel class's
+    timing record over the timed steps."""
+    if t["launches"] == 0:
+        return None
+    s = info["s"]
+    nd = info["n_diag_resident"] or info["n_diag"]
+    if nd == 0 or nd % s:
+        return None
+    k = nd // s
+    B = choose_baby(s, k)
+    J, ga = k * B, s // B
+    npairs = info["groups"] * info["streams"]
+    ln = info["comp_level"] * ctx.n
+    per_launch = t["bytes"] / t["launches"]
+    expect = ln * (7.0 * J * ga + 16.0 * npairs * J + 16.0 * npairs * ga)
+    if abs(per_launch - expect) > 1e-9 * expect:
+        log("MAC stream probe skipped: the launches are not all of the digit-layout headline shape")
+        return None
+    write = ln * 16.0 * npairs * ga
+    read = expect - write
+    ms = ctx.probe_stream(int(read), int(write), 3)
+    ceil_gbs = (read + write) / ms * 1e-6
+    mac_gbs = per_launch * t["launches"] / t["ms"] * 1e-6
+    return {"read_bytes": int(read), "write_bytes": int(write), "probe_ms": round(ms, 4),
+            "ceiling_GBps": round(ceil_gbs, 1), "mac_GBps": round(mac_gbs, 1),
+            "mac_frac_of_ceiling": round(mac_gbs / ceil_gbs, 4)}
+
+
 def sources_current(rec):
     import hashlib
     h = hashlib.sha256()
@@ -765,6 +809,8 @@ def main():
                     help="queries of the headline workload per batched call (0: skip)")
     ap.add_argument("--mixed-batch", type=int, default=64,
                     help="queries of the mixed 2^15-ring batch (0: skip)")
+    ap.add_argument("--no-stream-probe", action="store_true",
+                    help="skip the read/write stream probe run beside the multiply-accumulate's roofline")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="launch one plain copy kernel of this many MiB (counter calibration)")
     ap.add_argument("--comp-level", type=int, default=0,
@@ -851,12 +897,18 @@ def main():
     recovered = answer_recovers(hc, ctx, dec, wl.N, wl.ncol, info["s"], st["v"], st["dbv"])
     log("timed answer decrypts and decompresses to the query's %d matches: %s" % (wl.t, recovered))
     rl = kernel_rooflines(ctx, hc)
+    mac_timing = ctx.timing_read(hc.KT_DIAG_MAC)
     ctx.timing(False)
     for name, tb in measured_traffic(args.workload).items():
         if name in rl:
             rl[name]["traffic"] = tb
     if args.copy_probe_mb:
         ctx.probe_copy(args.copy_probe_mb << 20)
+    if "diag_mac" in rl and not args.no_stream_probe:
+        sp = mac_stream_ceiling(ctx, mac_timing, info)
+        if sp:
+            rl["diag_mac"]["stream_probe"] = sp
+            log("  MAC vs a contiguous stream of the same read/write mix: %s" % sp)
     for name, r in rl.items():
         log("  %-16s %8.1f ms %6d launches  %s %s of peak" % (name, r["ms"], r["launches"], r["bound"],
                                                               r["frac"]))

@@ -160,6 +160,15 @@ hc_status hc_probe_mul32_rate(hc_context* ctx, double ms, double* rate_out);
  * allocated device memory (rounded down to 8-byte words). Synchronises. */
 hc_status hc_probe_copy(hc_context* ctx, uint64_t bytes);
 
+/* Ceiling probe for a kernel that streams reads with a share of writes mixed in (the
+ * diagonal multiply-accumulate's traffic): allocates `read_bytes` and `write_bytes`
+ * of device memory, then times `reps` launches (after one untimed) of
+ * hc::probe_stream_kernel, in which each block reads a contiguous 896 KiB of the
+ * first buffer and, spread over its reads, writes its contiguous share of the second.
+ * *ms_out = mean milliseconds per launch. Frees both buffers; synchronises.
+ * Errors: HC_EINVAL (read_bytes < 16, reps < 1), HC_ENOMEM, HC_EDEVICE. */
+hc_status hc_probe_stream(hc_context* ctx, uint64_t read_bytes, uint64_t write_bytes, int reps, double* ms_out);
+
 #ifdef __cplusplus
 }
 #endif

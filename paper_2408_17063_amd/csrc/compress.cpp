@@ -264,7 +264,10 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
     const uint32_t col_k = 2u * c.n - 1;
     const uint64_t* col_key = find_key(gk, col_k);
 
-    // 1. inputs to the NTT domain; Mask at the top level (Alg. 7 step 2)
+    // 1. inputs to the NTT domain; Mask at the top level (Alg. 7 step 2). At ring 2^16 with
+    //    a switch to follow, the products at the primes it drops are formed inside the
+    //    first pass of their inverse transform (ntt_mask_low), which the switch needs anyway.
+    const bool mask_fused = Lc < c.L && c.logn == 16;
     {
         // ciphertext i times every column's plaintext i, into slot (1 + col) n_ct + i
         std::vector<MaskJob> mj;
@@ -287,14 +290,23 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
         if (!mj.empty()) {
             const MaskJob* dm = (const MaskJob*)stage_bytes(l, mj.data(), sizeof(MaskJob) * mj.size(), st);
             if (!dm) return HC_ENOMEM;
-            k_mask_jobs(c, dm, (int)mj.size(), c.L, st);
+            k_mask_jobs(c, dm, (int)mj.size(), mask_fused ? Lc : c.L, c.L, st);
+            if (mask_fused) {
+                int nprod = 0, cmax = 0;
+                for (auto& j : mj) {
+                    nprod += (int)j.ncol;
+                    cmax = std::max(cmax, (int)j.ncol);
+                }
+                ntt_mask_low(c, dm, (int)mj.size(), cmax, nprod, Lc, st);
+            }
         }
     }
     // 2. switch to the Comp level (Sec. 5.3's smaller parameters, as a modulus switch);
     // the input ciphertexts' dropped rows are read from the query (coefficient form)
     if (Lc < c.L)
         for (auto& q : qs)
-            RUN(mod_switch_batch(c, q.cts, q.ctf, (int)q.ntot, Lc, q.msconv, st, q.ct_v, (int)q.pl.n_ct));
+            RUN(mod_switch_batch(c, q.cts, q.ctf, (int)q.ntot, Lc, q.msconv, st, q.ct_v, (int)q.pl.n_ct,
+                                 mask_fused && !q.ct_d && q.pl.ncol > 0));
 
     // 3. u-blocks (Sec. 5.2 remark): row 0: A*[1;0] + Rot_col(B*[1;0]); row 1: Rot_col(A*[0;1]) + B*[0;1]
     {

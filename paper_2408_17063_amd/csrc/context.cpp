@@ -512,17 +512,36 @@ static hipEvent_t pool_get(const hc_context& c) {
     return e;
 }
 
+TimeScope*& TimeScope::current() {
+    static thread_local TimeScope* cur = nullptr;
+    return cur;
+}
+
 TimeScope::TimeScope(const hc_context& c_, int kind_, hipStream_t st_, double bytes_, double ops_)
     : c(c_), kind(kind_), st(st_), bytes(bytes_), ops(ops_) {
     if (!c.timing) return;
     a = pool_get(c);
     b = pool_get(c);
-    if (a && b) (void)hipEventRecord(a, st);
+    if (!a || !b) {
+        std::lock_guard<std::mutex> g(c.timing_mu);
+        if (a) c.event_pool.push_back(a);
+        if (b) c.event_pool.push_back(b);
+        a = b = nullptr;
+        return;
+    }
+    prev = current();
+    current() = this;
 }
 
 TimeScope::~TimeScope() {
     if (!c.timing || !a || !b) return;
-    (void)hipEventRecord(b, st);
+    current() = prev;
+    if (!used) {  // no kernel launched through hc_launch: nothing to time
+        std::lock_guard<std::mutex> g(c.timing_mu);
+        c.event_pool.push_back(a);
+        c.event_pool.push_back(b);
+        return;
+    }
     std::lock_guard<std::mutex> g(c.timing_mu);
     c.tlaunches.push_back({kind, a, b, bytes, ops});
 }

@@ -1,8 +1,11 @@
 // Internal declarations of libhc: the context, key and database objects and
 // the device launchers the host orchestration calls.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <utility>
 
 #include <map>
 #include <mutex>
@@ -101,8 +104,11 @@ struct hc_context {
 
     // modulus-switching constants for dropping the primes Lc..Lin-1 of a ciphertext at
     // level Lin, for every 1 <= Lc < Lin <= L (built at creation, so no call allocates
-    // them): inv [Lin-Lc][2], cst [Lin-Lc][Lc], dinv [Lc][2]; keyed by Lin * 256 + Lc
-    struct MsTab { uint64_t* inv; uint64_t* cst; uint64_t* dinv; };
+    // them): inv [Lin-Lc][2], cst [Lin-Lc][Lc], dinv [Lc][2]; keyed by Lin * 256 + Lc.
+    // For Lin = L also ninv [L][4]: an inverse transform's final constants (as d_ninv)
+    // times inv's factor on the dropped rows, so that the transform yields the
+    // multiplied residues [x (D/q_j)^-1]_{q_j} directly (nullptr for Lin < L).
+    struct MsTab { uint64_t* inv; uint64_t* cst; uint64_t* dinv; uint64_t* ninv; };
     std::map<int, MsTab> ms_tabs;
 
     // plaintext multipliers owned by the context (NTT domain, Montgomery form, [L][n])
@@ -209,16 +215,45 @@ struct MaskJob {
     uint32_t ncol, pad;
 };
 
-// Brackets one kernel launch with events when timing is enabled.
+// Times the kernel launches made through hc_launch on stream st while it lives, when
+// timing is enabled: the first such launch carries the start event and every one the stop
+// event (hipExtLaunchKernel takes them from the dispatch itself, with no marker packets
+// between the kernels).
 struct TimeScope {
     const hc_context& c;
     int kind;
     hipStream_t st;
     double bytes, ops;
     hipEvent_t a = nullptr, b = nullptr;
+    bool used = false;
+    TimeScope* prev = nullptr;
     TimeScope(const hc_context& c_, int kind_, hipStream_t st_, double bytes_, double ops_);
     ~TimeScope();
+    static TimeScope*& current();  // the calling thread's innermost active scope
 };
+
+template <typename... F, typename... A, size_t... I>
+inline void launch_args(std::tuple<F...>& f, void** args, std::index_sequence<I...>) {
+    ((args[I] = (void*)&std::get<I>(f)), ...);
+}
+
+// Launches kernel(actuals...) like hipLaunchKernelGGL; inside a TimeScope of this stream,
+// with that scope's events.
+template <typename... Formals, typename... Actuals>
+inline void hc_launch(void (*kernel)(Formals...), dim3 grid, dim3 block, uint32_t shm, hipStream_t st,
+                      Actuals... actuals) {
+    static_assert(sizeof...(Formals) == sizeof...(Actuals) && sizeof...(Formals) > 0, "kernel arguments");
+    std::tuple<Formals...> f{std::tuple<Actuals...>{actuals...}};
+    void* args[sizeof...(Formals)];
+    launch_args(f, args, std::index_sequence_for<Formals...>{});
+    TimeScope* ts = TimeScope::current();
+    if (ts && ts->st == st) {
+        (void)hipExtLaunchKernel((const void*)kernel, grid, block, args, shm, st, ts->used ? nullptr : ts->a, ts->b, 0);
+        ts->used = true;
+    } else {
+        (void)hipLaunchKernel((const void*)kernel, grid, block, args, shm, st);
+    }
+}
 
 // ------------------------------------------------------------------ NTT (ntt.hip)
 // data: `count` polynomials spaced poly_stride elements apart; data points at
@@ -299,11 +334,21 @@ void kb_final(const Ctx& c, const KsJob* jobs, const uint64_t* T, const uint64_t
 void k_sum_cts(const Ctx& c, uint64_t* y, const uint64_t* src, int groups, int cnt, int Lc, hipStream_t st);
 // element-wise jobs at level Lc: out = a * b (b a Montgomery plaintext [Lc rows]) or out = a + b
 void k_ew_jobs(const Ctx& c, const EwJob* jobs, int M, int Lc, bool mul, hipStream_t st);
-// MaskJob products at L rows: a thread reads its coefficient of both components once
-// and each plaintext once
-void k_mask_jobs(const Ctx& c, const MaskJob* jobs, int M, int L, hipStream_t st);
+// MaskJob products at rows 0..rows-1 of ciphertexts with L rows: a thread reads its
+// coefficient of both components once and each plaintext once
+void k_mask_jobs(const Ctx& c, const MaskJob* jobs, int M, int rows, int L, hipStream_t st);
+// The MaskJob products at the rows Lc..L-1 (ring 2^16), computed while loading the inverse
+// transform's first pass: every column's output rows hold the pass's result there (the
+// words k_mask_jobs writes, after ntt64_low_pass(inverse)). cmax: the most columns of a
+// job; nprod: the jobs' columns in all.
+void ntt_mask_low(const Ctx& c, const MaskJob* jobs, int M, int cmax, int nprod, int Lc, hipStream_t st);
+// The inverse transform's second pass (ring 2^16) with the final constants `ninv`
+// ([prime][4], the layout of d_ninv) in place of n^-1.
+void ntt64_inverse_high_tab(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb_first, int nlimbs,
+                            const uint64_t* ninv, hipStream_t stream);
 // modulus switching of `count` contiguous ciphertexts from Lin to Lc primes:
-// conv [count][2][Lc][n] from the dropped rows of ct [count][2][Lin][n] (coefficient domain);
+// conv [count][2][Lc][n] from the dropped rows of ct [count][2][Lin][n] (coefficient domain;
+// with inv == nullptr already multiplied by their factors (D/q_j)^-1);
 // out [count][2][Lc][n] = (ct - conv) D^-1 (element-wise: conv in ct's domain)
 void k_ms_conv(const Ctx& c, uint64_t* conv, const uint64_t* ct, const uint64_t* inv, const uint64_t* cst,
                int Lin, int Lc, int count, hipStream_t st);

@@ -359,12 +359,14 @@ hc_status ew_run(Ctx& c, Lane& l, const std::vector<EwJob>& jobs, int Lc, bool m
 hc_status build_ms_tables(Ctx& c) {
     const int L = c.L;
     std::vector<uint64_t> all;
-    std::vector<std::tuple<int, size_t, size_t, size_t>> offs;  // key, inv, cst, dinv
+    std::vector<std::tuple<int, size_t, size_t, size_t, size_t>> offs;  // key, inv, cst, dinv, ninv
+    const size_t n = c.n;
     for (int Lin = 2; Lin <= L; Lin++)
         for (int Lc = 1; Lc < Lin; Lc++) {
             const int nd = Lin - Lc;
             const size_t oi = all.size(), oc = oi + 2 * (size_t)nd, od = oc + (size_t)nd * Lc;
-            all.resize(od + 2 * (size_t)Lc);
+            const size_t on = od + 2 * (size_t)Lc;
+            all.resize(on + (Lin == L ? 4 * (size_t)L : 0));
             for (int j = 0; j < nd; j++) {
                 const uint64_t qj = c.primes[Lc + j];
                 uint64_t h = 1;  // (D / q_j) mod q_j
@@ -387,7 +389,20 @@ hc_status build_ms_tables(Ctx& c) {
                 all[od + 2 * i] = h_invmod(D, qi);
                 all[od + 2 * i + 1] = h_shoup_const(all[od + 2 * i], qi);
             }
-            offs.emplace_back(Lin * 256 + Lc, oi, oc, od);
+            // from the top level: n^-1 and W^-1[1] n^-1 (W^-1[1] the inverse table's word
+            // of index 1), times (D/q_j)^-1 on the dropped rows
+            if (Lin == L)
+                for (int i = 0; i < L; i++) {
+                    const uint64_t q = c.primes[i];
+                    const uint64_t f = i < Lc ? 1 : all[oi + 2 * (size_t)(i - Lc)];
+                    const uint64_t ni = h_mulmod(h_invmod(n % q, q), f, q);
+                    const uint64_t w1 = c.h_tw[(size_t)i * 4 * n + 2 * n + 2];
+                    all[on + 4 * i] = ni;
+                    all[on + 4 * i + 1] = h_shoup_const(ni, q);
+                    all[on + 4 * i + 2] = h_mulmod(w1, ni, q);
+                    all[on + 4 * i + 3] = h_shoup_const(all[on + 4 * i + 2], q);
+                }
+            offs.emplace_back(Lin * 256 + Lc, oi, oc, od, Lin == L ? on : SIZE_MAX);
         }
     if (all.empty()) return HC_OK;
     uint64_t* d = nullptr;
@@ -395,7 +410,8 @@ hc_status build_ms_tables(Ctx& c) {
     c.owned.push_back(d);
     HC_CHECK(hipMemcpy(d, all.data(), sizeof(uint64_t) * all.size(), hipMemcpyHostToDevice));
     for (auto& o : offs)
-        c.ms_tabs[std::get<0>(o)] = Ctx::MsTab{d + std::get<1>(o), d + std::get<2>(o), d + std::get<3>(o)};
+        c.ms_tabs[std::get<0>(o)] = Ctx::MsTab{d + std::get<1>(o), d + std::get<2>(o), d + std::get<3>(o),
+                                               std::get<4>(o) == SIZE_MAX ? nullptr : d + std::get<4>(o)};
     return HC_OK;
 }
 
@@ -408,17 +424,28 @@ static const Ctx::MsTab* ms_table(const Ctx& c, int Lin, int Lc) {
 // in and out). The dropped rows of `in` are left in the coefficient domain. conv: 2 Lc n
 // words per ciphertext.
 hc_status mod_switch_batch(Ctx& c, uint64_t* out, uint64_t* in, int count, int Lc, uint64_t* conv,
-                           hipStream_t st, const uint64_t* coef, int ncoef) {
+                           hipStream_t st, const uint64_t* coef, int ncoef, bool low_done) {
     const Ctx::MsTab* t = ms_table(c, c.L, Lc);
     if (!t) return HC_EINVAL;
     if (!coef || ncoef < 0) ncoef = 0;
     if (ncoef > count) return HC_EINVAL;
+    const bool two_pass = c.logn == 16 && t->ninv;
+    if (low_done && !two_pass) return HC_EINVAL;
     const size_t n = c.n, Ln = (size_t)c.L * n, skip = 2 * (size_t)ncoef;
     // the dropped rows in coefficient form: given for the first ncoef, transformed back
-    // for the rest
-    ntt64(c, in + skip * Ln + (size_t)Lc * n, Ln, 2 * (count - ncoef), Lc, c.L - Lc, true, st);
+    // for the rest (at ring 2^16 already multiplied by their factors (D/q_j)^-1, which the
+    // transform's final constants carry)
+    const int nt = 2 * (count - ncoef);
+    uint64_t* tin = in + skip * Ln + (size_t)Lc * n;
+    if (two_pass) {
+        if (!low_done) ntt64_low_pass(c, tin, Ln, nt, Lc, c.L - Lc, true, st);
+        ntt64_inverse_high_tab(c, tin, Ln, nt, Lc, c.L - Lc, t->ninv, st);
+    } else {
+        ntt64(c, tin, Ln, nt, Lc, c.L - Lc, true, st);
+    }
     if (ncoef > 0) k_ms_conv(c, conv, coef, t->inv, t->cst, c.L, Lc, ncoef, st);
-    k_ms_conv(c, conv + skip * Lc * n, in + skip * Ln, t->inv, t->cst, c.L, Lc, count - ncoef, st);
+    k_ms_conv(c, conv + skip * Lc * n, in + skip * Ln, two_pass ? nullptr : t->inv, t->cst, c.L, Lc, count - ncoef,
+              st);
     ntt64(c, conv, (size_t)Lc * n, 2 * count, 0, Lc, false, st);
     k_ms_final(c, out, in, conv, t->dinv, c.L, Lc, count, st);
     return HC_OK;

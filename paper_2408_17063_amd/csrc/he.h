@@ -41,9 +41,11 @@ hc_status ks_run_sum(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jo
 hc_status ew_run(Ctx& c, Lane& l, const std::vector<EwJob>& jobs, int Lc, bool mul, hipStream_t st);
 // drop the primes Lc..L-1 of `count` contiguous top-level ciphertexts (NTT domain). The
 // first ncoef of them may also be given in coefficient form (coef, same layout): their
-// dropped rows are then read from there instead of being transformed back.
+// dropped rows are then read from there instead of being transformed back. low_done (ring
+// 2^16): the dropped rows of the other count - ncoef already hold the inverse transform's
+// first pass (ntt_mask_low).
 hc_status mod_switch_batch(Ctx& c, uint64_t* out, uint64_t* in, int count, int Lc, uint64_t* conv,
-                           hipStream_t st, const uint64_t* coef = nullptr, int ncoef = 0);
+                           hipStream_t st, const uint64_t* coef = nullptr, int ncoef = 0, bool low_done = false);
 // dropping primes from coefficient-domain ciphertexts at level Lin down to Lo
 // (count contiguous ciphertexts; conv: 2 Lo n words each)
 hc_status mod_switch_coef(const Ctx& c, uint64_t* out, const uint64_t* in, int count, int Lin, int Lo,

@@ -342,10 +342,10 @@ hc_status k_diag_mac_mfma(const Ctx& c, uint64_t* const* A, const uint64_t* Rt, 
                  2.0 * ln * npairs * J * ga);
     const int JB = (J + MF_K - 1) / MF_K;
     if (JB == 1)
-        hipLaunchKernelGGL((diag_mac_mfma_kernel<1>), dim3(a.per_xcd * 8), dim3(512), 0, st, A, Rt, (const mf_v4i*)D,
+        hc_launch((diag_mac_mfma_kernel<1>), dim3(a.per_xcd * 8), dim3(512), 0, st, A, Rt, (const mf_v4i*)D,
                            c.d_mods, c.d_qinv, c.d_mfw, a);
     else
-        hipLaunchKernelGGL((diag_mac_mfma_kernel<2>), dim3(a.per_xcd * 8), dim3(512), 0, st, A, Rt, (const mf_v4i*)D,
+        hc_launch((diag_mac_mfma_kernel<2>), dim3(a.per_xcd * 8), dim3(512), 0, st, A, Rt, (const mf_v4i*)D,
                            c.d_mods, c.d_qinv, c.d_mfw, a);
     return HC_OK;
 }

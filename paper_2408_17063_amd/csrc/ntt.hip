@@ -567,10 +567,10 @@ static void conv_fused_logn(const Ctx& c, const ConvFused& f, int polys, hipStre
     const uint32_t per_xcd = (uint32_t)((work + 7) / 8);
     const dim3 grid(per_xcd * 8);
     switch (f.alpha) {
-        case 1: hipLaunchKernelGGL((conv_fused_kernel<1, LOGN>), grid, dim3(NTT_THREADS), 0, st, f, tab, nout, (uint32_t)work, per_xcd); break;
-        case 2: hipLaunchKernelGGL((conv_fused_kernel<2, LOGN>), grid, dim3(NTT_THREADS), 0, st, f, tab, nout, (uint32_t)work, per_xcd); break;
-        case 3: hipLaunchKernelGGL((conv_fused_kernel<3, LOGN>), grid, dim3(NTT_THREADS), 0, st, f, tab, nout, (uint32_t)work, per_xcd); break;
-        default: hipLaunchKernelGGL((conv_fused_kernel<4, LOGN>), grid, dim3(NTT_THREADS), 0, st, f, tab, nout, (uint32_t)work, per_xcd); break;
+        case 1: hc_launch((conv_fused_kernel<1, LOGN>), grid, dim3(NTT_THREADS), 0, st, f, tab, nout, (uint32_t)work, per_xcd); break;
+        case 2: hc_launch((conv_fused_kernel<2, LOGN>), grid, dim3(NTT_THREADS), 0, st, f, tab, nout, (uint32_t)work, per_xcd); break;
+        case 3: hc_launch((conv_fused_kernel<3, LOGN>), grid, dim3(NTT_THREADS), 0, st, f, tab, nout, (uint32_t)work, per_xcd); break;
+        default: hc_launch((conv_fused_kernel<4, LOGN>), grid, dim3(NTT_THREADS), 0, st, f, tab, nout, (uint32_t)work, per_xcd); break;
     }
 }
 
@@ -679,25 +679,25 @@ static void pass(const Ctx& c, int kind, T* data, size_t stride, int count, int 
     auto launch = [&]() {
         if constexpr (TUNED) {
             if (var == 1) {
-                hipLaunchKernelGGL((ntt_tile_kernel<T, INV, LOGN, S, BLO, ST0, LAST, 3>), grid, dim3(THREADS), 0, st,
+                hc_launch((ntt_tile_kernel<T, INV, LOGN, S, BLO, ST0, LAST, 3>), grid, dim3(THREADS), 0, st,
                                    data, stride, lf, tab);
                 return;
             }
             if (var == 2) {
-                hipLaunchKernelGGL((ntt_tile_kernel<T, INV, LOGN, S, BLO, ST0, LAST, 5>), grid, dim3(THREADS), 0, st,
+                hc_launch((ntt_tile_kernel<T, INV, LOGN, S, BLO, ST0, LAST, 5>), grid, dim3(THREADS), 0, st,
                                    data, stride, lf, tab);
                 return;
             }
             if (var == 3) {
                 const uint32_t items = grid.x * grid.y * grid.z;
                 const uint32_t cap = (uint32_t)c.cus * 4;  // four 4-wave blocks per CU (4 waves per SIMD)
-                hipLaunchKernelGGL((ntt_tile_persistent_kernel<T, INV, LOGN, S, BLO, ST0, LAST, 4>),
+                hc_launch((ntt_tile_persistent_kernel<T, INV, LOGN, S, BLO, ST0, LAST, 4>),
                                    dim3(items < cap ? items : cap), dim3(THREADS), 0, st, data, stride, lf, tab,
                                    grid.x, (uint32_t)count, items);
                 return;
             }
         }
-        hipLaunchKernelGGL((ntt_tile_kernel<T, INV, LOGN, S, BLO, ST0, LAST, TUNED ? 4 : 1>), grid, dim3(THREADS), 0,
+        hc_launch((ntt_tile_kernel<T, INV, LOGN, S, BLO, ST0, LAST, TUNED ? 4 : 1>), grid, dim3(THREADS), 0,
                            st, data, stride, lf, tab);
     };
     if (kind >= 0) {
@@ -848,6 +848,72 @@ ntt_take_c1_low_kernel(const KsJob* __restrict__ jobs, uint64_t* __restrict__ tm
     for (int v = 0; v < NTT_EPT; v++) a[TL::gidx(insert_bits(gh, v, PH, RR), sp0)] = x[v];
 }
 
+// The inverse transform's first pass (ring 2^16) of Mask's products at the dropped rows
+// Lc..L-1, computed while loading: block (tile, (job m, component, column), row Lc + k)
+// takes its words of jobs[m].a times the column's plaintext row (Montgomery), runs the
+// pass and stores it to the column's output row -- the words mask_jobs writes there,
+// after the pass. The blocks of one tile go to one XCD (16 tiles: the block number's
+// residue mod 8 is the tile's), so the columns of a row reread its words from that L2.
+__global__ void __launch_bounds__(NTT_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+ntt_mask_low_kernel(const MaskJob* __restrict__ jobs, NttTab<uint64_t> tab, const uint64_t* __restrict__ qinv, int L,
+                    int Lc, int cmax) {
+    constexpr int LOGN = 16, S = 8, RR = NTT_EPT_LOG;
+    typedef Tile<uint64_t, true, LOGN, S, 0, 0> TL;
+    static_assert(TL::DIRECT_LO && TL::TW2 && TL::THREADS == NTT_THREADS, "ring 2^16 low-bit pass");
+    constexpr int PH = TL::LOGP + RR;
+    constexpr size_t N = (size_t)1 << LOGN;
+    __shared__ uint64_t lds[TL::LDS_WORDS];
+    const uint32_t tid = threadIdx.x, bx = blockIdx.x, k = blockIdx.z;
+    const uint32_t mc = blockIdx.y / (uint32_t)cmax, col = blockIdx.y % (uint32_t)cmax;
+    const int m = (int)(mc >> 1), comp = (int)(mc & 1);
+    const MaskJob jb = jobs[m];
+    if (col >= jb.ncol) return;  // uniform over the block
+    const int prime = Lc + (int)k;
+    const uint64_t q = tab.mods[prime], qi = qinv[prime];
+    const uint64_t* tw = tab.base + ((size_t)prime * 2 + 1) * 2 * N;
+    const uint64_t* tw2 = tab.tw2 + (((size_t)prime * 2 + 1) * gridDim.x + bx) * (size_t)TL::TW_PASS * TL::THREADS * 2;
+    const uint32_t sp0 = bx * TL::P;
+    const size_t row = ((size_t)comp * L + prime) * N;
+    const uint64_t* av = jb.a + row;
+    const uint64_t* pt = jb.b + (size_t)col * jb.b_step + (size_t)prime * N;
+    #pragma unroll
+    for (int i = 0; i < NTT_EPT; i++) {
+        const uint32_t f = tid + i * TL::THREADS;
+        const uint32_t e = ((f & ((1u << S) - 1u)) << TL::LOGP) | (f >> S);
+        const uint32_t g = TL::gidx(e, sp0);
+        lds[TL::lpos(e)] = mont_mul(av[g], pt[g], q, qi);
+    }
+    __syncthreads();
+    TL::template round<RR, 0, 0>(lds, sp0, tw, tw2, q);
+    __syncthreads();
+    const uint32_t gh = TL::swap_nibbles(tid);
+    uint64_t x[NTT_EPT];
+    #pragma unroll
+    for (int v = 0; v < NTT_EPT; v++) x[v] = lds[TL::lpos(insert_bits(gh, v, PH, RR))];
+    TL::template butterflies<RR, RR, RR>(x, gh, 0, sp0, tw, tw2, q);
+    uint64_t* o = jb.out + (size_t)col * jb.out_step + row;
+    #pragma unroll
+    for (int v = 0; v < NTT_EPT; v++) o[TL::gidx(insert_bits(gh, v, PH, RR), sp0)] = x[v];
+}
+
+void ntt_mask_low(const Ctx& c, const MaskJob* jobs, int M, int cmax, int nprod, int Lc, hipStream_t st) {
+    if (M <= 0 || cmax <= 0 || nprod <= 0 || Lc >= c.L || c.logn != 16) return;
+    NttTab<uint64_t> tab{c.d_tw, c.d_ninv, c.d_mods, c.d_tw2};
+    const double n = c.n, nd = c.L - Lc;
+    // per job row its words once; per product row the plaintext row and the pass's output
+    TimeScope ts(c, HC_KT_NTT_INV, st, 8.0 * n * 2.0 * nd * (M + 2.0 * nprod), 2.0 * nd * nprod * (n / 2) * 8);
+    static_assert((1u << (16 - TILE_LOG)) % 8 == 0, "tiles per row a multiple of the XCD count");
+    hc_launch(ntt_mask_low_kernel, dim3(1u << (16 - TILE_LOG), (unsigned)(2 * M * cmax), (unsigned)(c.L - Lc)),
+                       dim3(NTT_THREADS), 0, st, jobs, tab, c.d_qinv, c.L, Lc, cmax);
+}
+
+void ntt64_inverse_high_tab(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb_first, int nlimbs,
+                            const uint64_t* ninv, hipStream_t stream) {
+    if (count <= 0 || nlimbs <= 0 || c.logn != 16) return;
+    NttTab<uint64_t> tab{c.d_tw, ninv, c.d_mods, c.d_tw2};
+    pass<uint64_t, true, 16, 8, 8, 8, true>(c, HC_KT_NTT_INV, data, poly_stride, count, limb_first, nlimbs, tab, stream);
+}
+
 // ModDown's inverse transform, first pass (ring 2^16), of the special rows of the key
 // products, computing them while loading: word g of row Lc + k of T[m][comp] is
 // sum_j X[xidx_m][j][Lc + k][src(g)] key_m[j][comp][L + k][g] (src: sigma_{k_m}'s source
@@ -907,7 +973,7 @@ void ntt_inner_low(const Ctx& c, const KsJob* jobs, const uint64_t* X, uint64_t*
     const double n = c.n;
     // per job and special row: its digits and the key words of both components, the pass's output
     TimeScope ts(c, HC_KT_NTT_INV, st, 8.0 * n * M * c.K * (dn + 2.0 * dn + 2.0), 2.0 * M * c.K * (n / 2) * 8);
-    hipLaunchKernelGGL(ntt_inner_low_kernel, dim3(1u << (16 - TILE_LOG), (unsigned)(2 * M), (unsigned)c.K),
+    hc_launch(ntt_inner_low_kernel, dim3(1u << (16 - TILE_LOG), (unsigned)(2 * M), (unsigned)c.K),
                        dim3(NTT_THREADS), 0, st, jobs, X, T, tab, c.d_qinv, Lc, c.K, c.L, c.nq, dn, hoisted ? 1 : 0);
 }
 
@@ -917,7 +983,7 @@ void ntt_take_c1_low(const Ctx& c, const KsJob* jobs, uint64_t* tmpC, uint64_t* 
     const double n = c.n;
     // reads the rotated c1 rows, writes them to X and the pass's output: 24 bytes per word
     TimeScope ts(c, HC_KT_NTT_INV, st, 24.0 * n * U * Lc, (double)U * Lc * (n / 2) * 8);
-    hipLaunchKernelGGL(ntt_take_c1_low_kernel, dim3(1u << (16 - TILE_LOG), (unsigned)U, (unsigned)Lc),
+    hc_launch(ntt_take_c1_low_kernel, dim3(1u << (16 - TILE_LOG), (unsigned)U, (unsigned)Lc),
                        dim3(NTT_THREADS), 0, st, jobs, tmpC, X, tab, Lc, c.alpha, Lc + c.K, Lc / c.alpha);
 }
 

@@ -186,7 +186,7 @@ void kb_modup(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, bo
     TimeScope ts(c, HC_KT_MODUP, st,
                  8.0 * n * U * ((double)Lc + (double)dn * (R - (own_rows ? 0 : c.alpha))),
                  n * U * dn * (double)(R - c.alpha) * c.alpha);
-    hipLaunchKernelGGL(kb_modup_kernel, ew_grid(c.n, dn, U), dim3(EW_THREADS), 0, st, X, tmpC, c.d_mods,
+    hc_launch(kb_modup_kernel, ew_grid(c.n, dn, U), dim3(EW_THREADS), 0, st, X, tmpC, c.d_mods,
                        c.d_qinv, c.d_modup_inv, c.d_modup_c, c.n, c.nq, c.alpha, c.L, Lc, c.K, dn,
                        own_rows ? 1 : 0);
 }
@@ -241,7 +241,7 @@ void kb_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const KsJob* jobs, c
     // per run and row: the key (2 dn words) once; per job: its raised digits and T
     const double rows = (double)(R - row0) * c.n;
     TimeScope ts(c, HC_KT_KS_INNER, st, 8.0 * rows * (2.0 * dn * nruns + (dn + 2.0) * M), 2.0 * dn * rows * M);
-    hipLaunchKernelGGL(kb_inner_kernel, ew_grid(c.n, R - row0, nruns), dim3(EW_THREADS), 0, st, T, X, jobs, runs,
+    hc_launch(kb_inner_kernel, ew_grid(c.n, R - row0, nruns), dim3(EW_THREADS), 0, st, T, X, jobs, runs,
                        c.d_mods, c.d_qinv, c.n, c.logn, c.nq, c.L, Lc, c.K, dn, hoisted ? 1 : 0, row0);
 }
 
@@ -306,7 +306,7 @@ void kb_final_inner(const Ctx& c, const KsJob* jobs, const KsRun* runs, int nrun
     // conversions, the rotated c0 and the two outputs
     const double rows = (double)Lc * c.n;
     TimeScope ts(c, HC_KT_KS_INNER, st, 8.0 * rows * (2.0 * dn * nruns + (dn + 5.0) * M), 2.0 * dn * rows * M);
-    hipLaunchKernelGGL(kb_final_inner_kernel, ew_grid(c.n, Lc, nruns), dim3(EW_THREADS), 0, st, jobs, runs, X, conv,
+    hc_launch(kb_final_inner_kernel, ew_grid(c.n, Lc, nruns), dim3(EW_THREADS), 0, st, jobs, runs, X, conv,
                        c.d_mods, c.d_qinv, c.d_pinv, c.n, c.logn, c.nq, Lc, c.K, dn, hoisted ? 1 : 0,
                        diag_split_h(c, Lc));
 }
@@ -461,7 +461,7 @@ void kb_inner_sum(const Ctx& c, uint64_t* TA, uint64_t* C0A, const uint64_t* X, 
     const uint32_t ntiles = (uint32_t)((c.n + EW_THREADS - 1) / EW_THREADS);
     const uint64_t work = (uint64_t)nranges * ntiles * (uint32_t)(R + Lc);
     const uint32_t per_xcd = (uint32_t)((work + 7) / 8);
-    hipLaunchKernelGGL(kb_inner_sum_kernel, dim3(per_xcd * 8), dim3(EW_THREADS), 0, st, TA, C0A, X, jobs, ranges,
+    hc_launch(kb_inner_sum_kernel, dim3(per_xcd * 8), dim3(EW_THREADS), 0, st, TA, C0A, X, jobs, ranges,
                        members, c.d_mods, c.d_qinv, c.n, c.logn, c.nq, c.L, Lc, c.K, dn, fold < 1 ? 1 : fold,
                        (uint32_t)nranges, ntiles, (uint32_t)work, per_xcd);
 }
@@ -502,8 +502,8 @@ void k_sum_cts(const Ctx& c, uint64_t* y, const uint64_t* src, int groups, int c
 // ct [count][2][L][n] (L = the source level) with the dropped rows Lc..L-1 in the
 // coefficient domain; blockIdx.z = t*2+comp.
 // A thread covers CONV_ROWS consecutive kept primes: each dropped residue is read and
-// scaled once.
-template <int NI>
+// scaled once (PRE: the rows already hold [ct_j (D/q_j)^-1]_{q_j}).
+template <int NI, bool PRE>
 __global__ void ms_conv_kernel(uint64_t* __restrict__ conv, const uint64_t* __restrict__ ct,
                                const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv,
                                const uint64_t* __restrict__ inv, const uint64_t* __restrict__ cst,
@@ -531,8 +531,12 @@ __global__ void ms_conv_kernel(uint64_t* __restrict__ conv, const uint64_t* __re
         for (int b = 0; b < MS_BATCH; b++) {
             const int j = j0 + b;
             if (j < nd) {
-                const uint64_t qj = mods[Lc + j], w = inv[2 * j], wp = inv[2 * j + 1];
-                const uint64_t y0 = shoup(v[b].x, w, wp, qj), y1 = shoup(v[b].y, w, wp, qj);
+                uint64_t y0 = v[b].x, y1 = v[b].y;
+                if (!PRE) {
+                    const uint64_t qj = mods[Lc + j], w = inv[2 * j], wp = inv[2 * j + 1];
+                    y0 = shoup(y0, w, wp, qj);
+                    y1 = shoup(y1, w, wp, qj);
+                }
                 const uint64_t* cj = cst + (size_t)j * Lc + i0;
                 #pragma unroll
                 for (int u = 0; u < NI; u++) {
@@ -589,8 +593,12 @@ void k_ms_conv(const Ctx& c, uint64_t* conv, const uint64_t* ct, const uint64_t*
     for (int i0 = 0; i0 < Lc; i0 += CONV_ROWS)
         with_rows(std::min(CONV_ROWS, Lc - i0), [&](auto ni_c) {
             constexpr int NI = decltype(ni_c)::value;
-            hipLaunchKernelGGL((ms_conv_kernel<NI>), ew_grid(c.n / 2, 1, 2 * count), dim3(EW_THREADS), 0, st, conv, ct,
-                               c.d_mods, c.d_qinv, inv, cst, c.n, Lin, Lc, i0);
+            if (inv)
+                hipLaunchKernelGGL((ms_conv_kernel<NI, false>), ew_grid(c.n / 2, 1, 2 * count), dim3(EW_THREADS), 0, st,
+                                   conv, ct, c.d_mods, c.d_qinv, inv, cst, c.n, Lin, Lc, i0);
+            else
+                hipLaunchKernelGGL((ms_conv_kernel<NI, true>), ew_grid(c.n / 2, 1, 2 * count), dim3(EW_THREADS), 0, st,
+                                   conv, ct, c.d_mods, c.d_qinv, inv, cst, c.n, Lin, Lc, i0);
         });
 }
 
@@ -615,6 +623,7 @@ __global__ void ew_jobs_kernel(const EwJob* __restrict__ jobs, const uint64_t* _
 
 __global__ void mask_jobs_kernel(const MaskJob* __restrict__ jobs, const uint64_t* __restrict__ mods,
                                  const uint64_t* __restrict__ qinv, int n, int L) {
+    // blockIdx.y = row (the grid covers the rows asked for)
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     const MaskJob jb = jobs[blockIdx.z];
@@ -631,10 +640,10 @@ __global__ void mask_jobs_kernel(const MaskJob* __restrict__ jobs, const uint64_
     }
 }
 
-void k_mask_jobs(const Ctx& c, const MaskJob* jobs, int M, int L, hipStream_t st) {
-    if (M <= 0) return;
-    hipLaunchKernelGGL(mask_jobs_kernel, ew_grid(c.n, L, M), dim3(EW_THREADS), 0, st, jobs, c.d_mods, c.d_qinv, c.n,
-                       L);
+void k_mask_jobs(const Ctx& c, const MaskJob* jobs, int M, int rows, int L, hipStream_t st) {
+    if (M <= 0 || rows <= 0) return;
+    hipLaunchKernelGGL(mask_jobs_kernel, ew_grid(c.n, rows, M), dim3(EW_THREADS), 0, st, jobs, c.d_mods, c.d_qinv,
+                       c.n, L);
 }
 
 void k_ew_jobs(const Ctx& c, const EwJob* jobs, int M, int Lc, bool mul, hipStream_t st) {
@@ -1305,15 +1314,15 @@ hc_status k_diag_mac(const Ctx& c, uint64_t* const* A, const uint64_t* Rt, const
     static_assert(DIAG_T * DIAG_NS == 16, "variants below assume 16 terms per round");
     switch (c.tune_mac) {
         case 1:
-            hipLaunchKernelGGL((diag_mac_kernel<GC, 2, 8>), dim3(a.per_xcd * 8), dim3(256), 0, st, A, Rt, D, c.d_mods,
+            hc_launch((diag_mac_kernel<GC, 2, 8>), dim3(a.per_xcd * 8), dim3(256), 0, st, A, Rt, D, c.d_mods,
                                c.d_qinv, c.d_r2, a);
             break;
         case 2:
-            hipLaunchKernelGGL((diag_mac_kernel<GC, 8, 2>), dim3(a.per_xcd * 8), dim3(256), 0, st, A, Rt, D, c.d_mods,
+            hc_launch((diag_mac_kernel<GC, 8, 2>), dim3(a.per_xcd * 8), dim3(256), 0, st, A, Rt, D, c.d_mods,
                                c.d_qinv, c.d_r2, a);
             break;
         default:
-            hipLaunchKernelGGL((diag_mac_kernel<GC, DIAG_T, DIAG_NS>), dim3(a.per_xcd * 8), dim3(256), 0, st, A, Rt,
+            hc_launch((diag_mac_kernel<GC, DIAG_T, DIAG_NS>), dim3(a.per_xcd * 8), dim3(256), 0, st, A, Rt,
                                D, c.d_mods, c.d_qinv, c.d_r2, a);
     }
     return HC_OK;
@@ -1414,6 +1423,75 @@ extern "C" hc_status hc_probe_copy(hc_context* c, uint64_t bytes) {
     HC_CHECK(hipFree(a));
     HC_CHECK(hipFree(b));
     return HC_OK;
+}
+
+namespace hc {
+// Block b reads `rchunk` consecutive 16-byte units of src (eight per thread per round of
+// 4096 units, all issued before use) and, spread evenly over its rounds, writes `wchunk`
+// consecutive units of dst; the written values depend on what was read.
+__global__ __launch_bounds__(512) void probe_stream_kernel(ulonglong2* __restrict__ dst,
+                                                           const ulonglong2* __restrict__ src, size_t runits,
+                                                           size_t wunits, size_t rchunk, size_t wchunk) {
+    const size_t r0 = (size_t)blockIdx.x * rchunk, w0 = (size_t)blockIdx.x * wchunk;
+    const size_t rounds = (rchunk + 4095) / 4096, wpr = (wchunk + rounds - 1) / rounds;
+    uint64_t acc = 0;
+    size_t wdone = 0;
+    for (size_t off = threadIdx.x; off < rchunk + threadIdx.x; off += 4096) {
+        ulonglong2 v[8];
+        #pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const size_t o = off + 512 * (size_t)u, k = r0 + o;
+            v[u] = (o < rchunk && k < runits) ? src[k] : ulonglong2{0, 0};
+        }
+        #pragma unroll
+        for (int u = 0; u < 8; u++) acc += v[u].x ^ v[u].y;
+        const size_t wend = wdone + wpr < wchunk ? wdone + wpr : wchunk;
+        for (size_t o = wdone + threadIdx.x; o < wend; o += 512)
+            if (w0 + o < wunits) dst[w0 + o] = ulonglong2{acc, o};
+        wdone = wend;
+    }
+}
+}  // namespace hc
+
+extern "C" hc_status hc_probe_stream(hc_context* c, uint64_t read_bytes, uint64_t write_bytes, int reps,
+                                     double* ms_out) {
+    if (!c || !ms_out || read_bytes < 16 || reps < 1) return HC_EINVAL;
+    HC_CHECK(hipSetDevice(c->device));
+    const size_t runits = read_bytes / 16, wunits = write_bytes / 16;
+    const size_t rchunk = 57344;  // 896 KiB per block
+    const size_t blocks = (runits + rchunk - 1) / rchunk, wchunk = (wunits + blocks - 1) / blocks;
+    if (blocks > 0x7fffffffu) return HC_EINVAL;
+    ulonglong2 *src = nullptr, *dst = nullptr;
+    HC_CHECK(hipMalloc((void**)&src, runits * 16));
+    if (wunits && hipMalloc((void**)&dst, wunits * 16) != hipSuccess) {
+        (void)hipFree(src);
+        return HC_ENOMEM;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hc_status st = HC_OK;
+    float ms = 0;
+    if (hipMemset(src, 0x5a, runits * 16) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess) {
+        st = HC_EDEVICE;
+    } else {
+        auto launch = [&] {
+            hipLaunchKernelGGL(hc::probe_stream_kernel, dim3((unsigned)blocks), dim3(512), 0, 0, dst, src, runits, wunits,
+                               rchunk, wchunk);
+        };
+        launch();
+        if (hipEventRecord(e0, 0) != hipSuccess) st = HC_EDEVICE;
+        for (int i = 0; i < reps && st == HC_OK; i++) launch();
+        if (st == HC_OK && (hipEventRecord(e1, 0) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st = HC_EDEVICE;
+    }
+    if (hipGetLastError() != hipSuccess) st = HC_EDEVICE;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(src);
+    if (dst) (void)hipFree(dst);
+    if (st == HC_OK) *ms_out = ms / reps;
+    return st;
 }
 
 extern "C" hc_status hc_probe_mul32_rate(hc_context* c, double ms, double* rate_out) {

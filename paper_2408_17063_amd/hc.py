@@ -152,6 +152,7 @@ _sig("hc_timing_read", _st, c_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
      ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
 _sig("hc_probe_mul32_rate", _st, c_vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double))
 _sig("hc_probe_copy", _st, c_vp, ctypes.c_uint64)
+_sig("hc_probe_stream", _st, c_vp, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(ctypes.c_double))
 _sig("hc_diag_prepare", _st, c_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
      ctypes.POINTER(ctypes.c_uint64))
 _sig("hc_diag_release", None, c_vp)
@@ -178,7 +179,7 @@ EXPORTED = [
     "hc_decrypt", "hc_decompress", "hc_ntt", "hc_rotate", "hc_rotate_level", "hc_rotate_level_noalloc", "hc_mod_switch",
     "hc_rotate_hoisted", "hc_mul_plain",
     "hc_modup", "hc_moddown", "hc_sample", "hc_encode_diagonal", "hc_export_sk", "hc_export_pk",
-    "hc_export_gk", "hc_timing_enable", "hc_timing_read", "hc_probe_mul32_rate", "hc_probe_copy",
+    "hc_export_gk", "hc_timing_enable", "hc_timing_read", "hc_probe_mul32_rate", "hc_probe_copy", "hc_probe_stream",
     "hc_graph_create", "hc_graph_launch", "hc_graph_nodes", "hc_graph_destroy",
     "hc_autotune", "hc_tune_set", "hc_tune_get",
     "hc_relin_keygen", "hc_mul", "hc_power", "hc_match", "hc_compress_generic",
@@ -547,6 +548,13 @@ class Context:
 
     def probe_copy(self, nbytes):
         _check(_lib.hc_probe_copy(self.h, int(nbytes)), "hc_probe_copy")
+
+    def probe_stream(self, read_bytes, write_bytes, reps=3):
+        """Mean ms per launch of the read/write stream probe (hc_probe_stream)."""
+        ms = ctypes.c_double(0)
+        _check(_lib.hc_probe_stream(self.h, int(read_bytes), int(write_bytes), int(reps), ctypes.byref(ms)),
+               "hc_probe_stream")
+        return ms.value
 
     def export_sk(self, sk):
         out = np.zeros(self.n, dtype=np.int64)
