@@ -466,6 +466,11 @@ extern "C" void hc_context_destroy(hc_context* c) {
     for (auto& kv : c->prefix_masks) (void)hipFree(kv.second);
     for (auto& kv : c->diag_tabs) (void)hipFree(kv.second.d);
     c->lane.release();
+    for (auto& t : c->tlaunches) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -552,7 +557,13 @@ extern "C" hc_status hc_timing_enable(hc_context* c, int enable) {
     if (!c) return HC_EINVAL;
     HC_CHECK(hipSetDevice(c->device));
     HC_CHECK(hipDeviceSynchronize());
-    for (auto& t : c->tlaunches) { c->event_pool.push_back(t.a); c->event_pool.push_back(t.b); }
+    // An event a kernel launch carried stays bound to that launch, which holds on to the
+    // device memory the kernel used (memory freed since stays allocated): such events are
+    // destroyed here, never reused.
+    for (auto& t : c->tlaunches) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
     c->tlaunches.clear();
     c->timing = enable != 0;
     return HC_OK;
