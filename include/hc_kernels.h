@@ -140,7 +140,11 @@ enum {
     HC_KT_COUNT = 6
 };
 
-/* Start (enable = 1) or stop timing; starting clears the totals. */
+/* Start (enable = 1) or stop timing; either call clears the totals (read them with
+ * hc_timing_read before stopping). Each timed launch carries its own start/stop events
+ * (hipExtLaunchKernel), which keep the launch, and with it the device memory its kernel
+ * used, alive: memory the library frees while timing is on is returned to the device
+ * only when timing is stopped (or restarted). Synchronises the device. */
 hc_status hc_timing_enable(hc_context* ctx, int enable);
 
 /* Totals since timing was enabled for class `kind`: device milliseconds,
