@@ -41,6 +41,8 @@
 // the bound, so 16 stages from below 8q stay below 72q < 2^64, and the last launch
 // reduces with one truncated product by 1. The last launch brings every value to
 // [0, q).
+#include <algorithm>
+
 #include "hc_internal.h"
 
 namespace hc {
@@ -903,8 +905,12 @@ void ntt_mask_low(const Ctx& c, const MaskJob* jobs, int M, int cmax, int nprod,
     // per job row its words once; per product row the plaintext row and the pass's output
     TimeScope ts(c, HC_KT_NTT_INV, st, 8.0 * n * 2.0 * nd * (M + 2.0 * nprod), 2.0 * nd * nprod * (n / 2) * 8);
     static_assert((1u << (16 - TILE_LOG)) % 8 == 0, "tiles per row a multiple of the XCD count");
-    hc_launch(ntt_mask_low_kernel, dim3(1u << (16 - TILE_LOG), (unsigned)(2 * M * cmax), (unsigned)(c.L - Lc)),
-                       dim3(NTT_THREADS), 0, st, jobs, tab, c.d_qinv, c.L, Lc, cmax);
+    const int per_launch = std::max(1, 65535 / (2 * cmax));  // grid y stays within its limit
+    for (int j0 = 0; j0 < M; j0 += per_launch) {
+        const int mj = std::min(per_launch, M - j0);
+        hc_launch(ntt_mask_low_kernel, dim3(1u << (16 - TILE_LOG), (unsigned)(2 * mj * cmax), (unsigned)(c.L - Lc)),
+                  dim3(NTT_THREADS), 0, st, jobs + j0, tab, c.d_qinv, c.L, Lc, cmax);
+    }
 }
 
 void ntt64_inverse_high_tab(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb_first, int nlimbs,
