@@ -560,6 +560,7 @@ extern "C" hc_status hc_timing_enable(hc_context* c, int enable) {
     // An event a kernel launch carried stays bound to that launch, which holds on to the
     // device memory the kernel used (memory freed since stays allocated): such events are
     // destroyed here, never reused.
+    std::lock_guard<std::mutex> g(c->timing_mu);
     for (auto& t : c->tlaunches) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
@@ -576,6 +577,7 @@ extern "C" hc_status hc_timing_read(hc_context* c, int kind, double* total_ms, u
     HC_CHECK(hipDeviceSynchronize());
     double ms = 0, by = 0, op = 0;
     uint64_t cnt = 0;
+    std::lock_guard<std::mutex> g(c->timing_mu);
     for (auto& t : c->tlaunches) {
         if (t.kind != kind) continue;
         float e = 0;
