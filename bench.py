@@ -810,7 +810,7 @@ def small_config_latency(wl_name, reps=20, config=None):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large-65536")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -839,7 +839,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel variants")
     ap.add_argument("--ntt-variant", type=int, default=-1,
                     help="set this NTT pass variant after tuning (counter collection per variant)")
-    ap.add_argument("--graph-steps", type=int, default=5,
+    ap.add_argument("--graph-steps", type=int, default=20,
                     help="also time this many replays of the headline compression captured in a graph (0: skip)")
     ap.add_argument("--plain-db-steps", type=int, default=2,
                     help="also time the unencrypted-database form on the headline query (0: skip)")
