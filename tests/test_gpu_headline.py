@@ -102,6 +102,39 @@ def test_reduced_large_parameters_bit_identical_to_oracle():
         gold["noise_bits_level3"], gold["budget_bits_level3"], gold["noise_bits_level1"], gold["budget_bits_level1"]))
 
 
+def test_reduced_large_batch_equals_single_calls():
+    """Three queries of the reduced instance (own index vectors, one ciphertext each) in
+    one batched call at the full ring-2^16 parameters, so one launch of the fused Mask /
+    inverse-transform pass serves every query's jobs: each answer equals its query's
+    single call, and the first query's equals the oracle's stored digest."""
+    from oracle import slots
+    from paper_2408_17063_amd import hc
+    gold = load("ring65536_reduced.json")
+    wl = W.WORKLOADS["reduced-65536"]
+    ctx = context(RING)
+    say("reduced large instance, batch of 3")
+    v0, db = W.query_inputs(wl)
+    keys, _ = ctx.plan(wl.N, wl.ncol, wl.t)
+    sk, pk = ctx.keygen(W.seed32("sk", 0))
+    gk = ctx.galois_keygen(sk, keys, W.seed32("gk", 0))
+    dbh = ctx.db_upload(db)
+    vs = [v0] + [W.query_inputs(wl, query=q)[0] for q in (1, 2)]
+    qs = []
+    for qi, v in enumerate(vs):
+        vm = slots.vector_to_slot_matrices(v, ctx.n, 1)
+        cts = ctx.ct_tensor(1)
+        ctx.encrypt(pk, vm[0], W.seed32("enc", 0, 0) if qi == 0 else W.seed32("enc", 7, qi), out=cts[0])
+        qs.append((cts, wl.N, wl.t, ctx.ct_tensor(1)[0]))
+    st, statuses, infos = ctx.compress_batch(gk, dbh, qs)
+    assert st == hc.HC_OK and all(x == hc.HC_OK for x in statuses)
+    for qi, ((cts, N, t, o), inf) in enumerate(zip(qs, infos)):
+        alone, ainfo = ctx.compress(gk, dbh, cts, N, t)
+        got = to_host(ctx.output(o, inf))
+        assert np.array_equal(got, to_host(ctx.output(alone, ainfo))), qi
+        if qi == 0:
+            check(got, gold["compress_level3"], "batched reduced instance at 3 primes")
+
+
 def test_headline_query_decrypts_and_decompresses():
     """The benchmark query itself (resident diagonals, as timed): the one-prime answer
     decrypts to Eq. (1)'s products in all 6 bands and decompresses exactly; the
