@@ -389,6 +389,15 @@ void k_mul_mont(const Ctx& c, uint64_t* out, const uint64_t* a, const uint64_t* 
 // encryption finish (coefficient domain): c0 += e0 + Delta m ; c1 += e1
 void k_enc_finish(const Ctx& c, uint64_t* ct, const uint64_t* e0, const uint64_t* e1,
                   const uint32_t* m, hipStream_t st);
+// Device memory reached through a pointer held in a job table, as a global (not a
+// generic) pointer: loads through a generic pointer might read LDS, so they cannot move
+// past a kernel's LDS stores, and every load of a loop that also fills LDS then waits
+// for the one before it.
+typedef __attribute__((address_space(1))) const uint64_t gl_cu64;
+typedef __attribute__((address_space(1))) uint64_t gl_mu64;
+__device__ __forceinline__ gl_cu64* gl(const uint64_t* p) { return (gl_cu64*)p; }
+__device__ __forceinline__ gl_mu64* gl(uint64_t* p) { return (gl_mu64*)p; }
+
 // NTT-domain index that sigma_k pulls from: entry i holds a(psi^(2 brv(i)+1)),
 // so sigma_k(a) at i equals a at the entry whose exponent is (2 brv(i)+1) k.
 __device__ __forceinline__ uint32_t galois_src(uint32_t i, uint32_t k, int logn) {

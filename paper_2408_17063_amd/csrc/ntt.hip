@@ -826,16 +826,24 @@ ntt_take_c1_low_kernel(const KsJob* __restrict__ jobs, uint64_t* __restrict__ tm
     const uint64_t* tw2 = tab.tw2 + (((size_t)prime * 2 + 1) * gridDim.x + bx) * (size_t)TL::TW_PASS * TL::THREADS * 2;
     const uint32_t sp0 = bx * TL::P;
     const KsJob jb = jobs[u];
-    const uint64_t* in = jb.in + (size_t)(Lc + (int)r) * N;
+    gl_cu64* in = gl(jb.in) + (size_t)(Lc + (int)r) * N;
     uint64_t* own = X + (((size_t)u * dn + r / alpha) * R + r) * N;
+    // every gather first, then the stores (a store between two loads of the same
+    // thread would keep the second waiting for the first)
+    uint64_t vv[NTT_EPT];
     #pragma unroll
     for (int i = 0; i < NTT_EPT; i++) {
         const uint32_t f = tid + i * TL::THREADS;
         const uint32_t e = ((f & ((1u << S) - 1u)) << TL::LOGP) | (f >> S);
         const uint32_t g = TL::gidx(e, sp0);
-        const uint64_t v = in[jb.k == 1 ? g : galois_src(g, jb.k, LOGN)];
-        own[g] = v;
-        lds[TL::lpos(e)] = v;
+        vv[i] = in[jb.k == 1 ? g : galois_src(g, jb.k, LOGN)];
+    }
+    #pragma unroll
+    for (int i = 0; i < NTT_EPT; i++) {
+        const uint32_t f = tid + i * TL::THREADS;
+        const uint32_t e = ((f & ((1u << S) - 1u)) << TL::LOGP) | (f >> S);
+        own[TL::gidx(e, sp0)] = vv[i];
+        lds[TL::lpos(e)] = vv[i];
     }
     __syncthreads();
     TL::template round<RR, 0, 0>(lds, sp0, tw, tw2, q);
@@ -876,8 +884,8 @@ ntt_mask_low_kernel(const MaskJob* __restrict__ jobs, NttTab<uint64_t> tab, cons
     const uint64_t* tw2 = tab.tw2 + (((size_t)prime * 2 + 1) * gridDim.x + bx) * (size_t)TL::TW_PASS * TL::THREADS * 2;
     const uint32_t sp0 = bx * TL::P;
     const size_t row = ((size_t)comp * L + prime) * N;
-    const uint64_t* av = jb.a + row;
-    const uint64_t* pt = jb.b + (size_t)col * jb.b_step + (size_t)prime * N;
+    gl_cu64* av = gl(jb.a) + row;
+    gl_cu64* pt = gl(jb.b) + (size_t)col * jb.b_step + (size_t)prime * N;
     #pragma unroll
     for (int i = 0; i < NTT_EPT; i++) {
         const uint32_t f = tid + i * TL::THREADS;
@@ -893,7 +901,7 @@ ntt_mask_low_kernel(const MaskJob* __restrict__ jobs, NttTab<uint64_t> tab, cons
     #pragma unroll
     for (int v = 0; v < NTT_EPT; v++) x[v] = lds[TL::lpos(insert_bits(gh, v, PH, RR))];
     TL::template butterflies<RR, RR, RR>(x, gh, 0, sp0, tw, tw2, q);
-    uint64_t* o = jb.out + (size_t)col * jb.out_step + row;
+    gl_mu64* o = gl(jb.out) + (size_t)col * jb.out_step + row;
     #pragma unroll
     for (int v = 0; v < NTT_EPT; v++) o[TL::gidx(insert_bits(gh, v, PH, RR), sp0)] = x[v];
 }
@@ -945,18 +953,41 @@ ntt_inner_low_kernel(const KsJob* __restrict__ jobs, const uint64_t* __restrict_
     const uint32_t sp0 = bx * TL::P;
     const KsJob jb = jobs[m];
     const size_t keyrow = (size_t)nq * N;
-    const uint64_t* kp = jb.key + (size_t)comp * keyrow + (size_t)prime * N;
+    gl_cu64* kp = gl(jb.key) + (size_t)comp * keyrow + (size_t)prime * N;
     const uint64_t* xp = X + ((size_t)jb.xidx * dn * R + Lc + k) * N;
     const bool rot = hoisted && jb.k != 1;
-    #pragma unroll
-    for (int i = 0; i < NTT_EPT; i++) {
-        const uint32_t f = tid + i * TL::THREADS;
-        const uint32_t e = ((f & ((1u << S) - 1u)) << TL::LOGP) | (f >> S);
-        const uint32_t g = TL::gidx(e, sp0);
-        const uint32_t src = rot ? galois_src(g, jb.k, LOGN) : g;
-        u128p acc{0, 0};
-        for (int j = 0; j < dn; j++) add128(acc, mul128(xp[(size_t)j * R * N + src], kp[(size_t)j * 2 * keyrow + g]));
-        lds[TL::lpos(e)] = redc(acc, q, qi);
+    if (dn == 1) {
+        // one digit: the words of 8 elements are loaded together, then multiplied (a
+        // loop over the digits between the loads would make each wait for the last)
+        #pragma unroll
+        for (int h = 0; h < NTT_EPT; h += 8) {
+            uint64_t xv[8], kv[8];
+            #pragma unroll
+            for (int i = 0; i < 8; i++) {
+                const uint32_t f = tid + (h + i) * TL::THREADS;
+                const uint32_t e = ((f & ((1u << S) - 1u)) << TL::LOGP) | (f >> S);
+                const uint32_t g = TL::gidx(e, sp0);
+                xv[i] = xp[rot ? galois_src(g, jb.k, LOGN) : g];
+                kv[i] = kp[g];
+            }
+            #pragma unroll
+            for (int i = 0; i < 8; i++) {
+                const uint32_t f = tid + (h + i) * TL::THREADS;
+                const uint32_t e = ((f & ((1u << S) - 1u)) << TL::LOGP) | (f >> S);
+                lds[TL::lpos(e)] = redc(mul128(xv[i], kv[i]), q, qi);
+            }
+        }
+    } else {
+        #pragma unroll
+        for (int i = 0; i < NTT_EPT; i++) {
+            const uint32_t f = tid + i * TL::THREADS;
+            const uint32_t e = ((f & ((1u << S) - 1u)) << TL::LOGP) | (f >> S);
+            const uint32_t g = TL::gidx(e, sp0);
+            const uint32_t src = rot ? galois_src(g, jb.k, LOGN) : g;
+            u128p acc{0, 0};
+            for (int j = 0; j < dn; j++) add128(acc, mul128(xp[(size_t)j * R * N + src], kp[(size_t)j * 2 * keyrow + g]));
+            lds[TL::lpos(e)] = redc(acc, q, qi);
+        }
     }
     __syncthreads();
     TL::template round<RR, 0, 0>(lds, sp0, tw, tw2, q);

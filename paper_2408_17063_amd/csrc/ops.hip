@@ -249,51 +249,70 @@ void kb_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const KsJob* jobs, c
 // runs (as kb_inner): T0, T1 = sum_j X[xidx][j] (rotated if hoisted) * key[j] (one REDC of
 // the 128-bit sums, the words kb_inner writes), then out as kb_final. kb_inner then only
 // computes the special rows, so the ciphertext rows of T never go through device memory.
-__global__ void kb_final_inner_kernel(const KsJob* __restrict__ jobs, const KsRun* __restrict__ runs,
+__global__ __launch_bounds__(EW_THREADS) void kb_final_inner_kernel(const KsJob* __restrict__ jobs, const KsRun* __restrict__ runs,
                                       const uint64_t* __restrict__ X, const uint64_t* __restrict__ conv,
                                       const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv,
                                       const uint64_t* __restrict__ pinv, int n, int logn, int nq, int Lc, int K,
-                                      int dn, int hoisted, int h) {
+                                      int dn, int hoisted, int sh) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     const int i = blockIdx.y, R = Lc + K;
     const KsRun run = runs[blockIdx.z];
+    const int cnt = (int)run.cnt;
     const size_t keyrow = (size_t)nq * n;
-    const uint64_t* kp = jobs[run.j0].key + (size_t)i * n + x;
+    gl_cu64* kp = gl(jobs[run.j0].key) + (size_t)i * n + x;
+    // The run's loads are issued together and unconditionally (a job slot past the run
+    // reads the run's first job again and is not used): one conditional load per job
+    // would wait for each before the next.
     u128p a0[KS_RUN], a1[KS_RUN];
     #pragma unroll
     for (int u = 0; u < KS_RUN; u++) { a0[u] = u128p{0, 0}; a1[u] = u128p{0, 0}; }
     for (int j = 0; j < dn; j++) {
         const uint64_t k0 = kp[(size_t)j * 2 * keyrow], k1 = kp[(size_t)j * 2 * keyrow + keyrow];
+        uint64_t xv[KS_RUN];
         #pragma unroll
         for (int u = 0; u < KS_RUN; u++) {
-            if (u < (int)run.cnt) {
-                const KsJob jb = jobs[run.j0 + u];
-                const uint32_t src = (!hoisted || jb.k == 1) ? x : galois_src(x, jb.k, logn);
-                const uint64_t xv = X[((size_t)jb.xidx * dn + j) * R * n + (size_t)i * n + src];
-                add128(a0[u], mul128(xv, k0));
-                add128(a1[u], mul128(xv, k1));
-            }
+            const KsJob jb = jobs[run.j0 + (u < cnt ? u : 0)];
+            const uint32_t src = (!hoisted || jb.k == 1) ? x : galois_src(x, jb.k, logn);
+            xv[u] = X[((size_t)jb.xidx * dn + j) * R * n + (size_t)i * n + src];
+        }
+        #pragma unroll
+        for (int u = 0; u < KS_RUN; u++) {
+            add128(a0[u], mul128(xv[u], k0));
+            add128(a1[u], mul128(xv[u], k1));
         }
     }
     const uint64_t q = mods[i], qi = qinv[i], pi = pinv[2 * i], pis = pinv[2 * i + 1];
+    // the outputs in two halves of the run (all of a half's loads first)
+    constexpr int HALF = KS_RUN / 2;
     #pragma unroll
-    for (int u = 0; u < KS_RUN; u++) {
-        if (u < (int)run.cnt) {
-            const int m = (int)run.j0 + u;
+    for (int h = 0; h < KS_RUN; h += HALF) {
+        uint64_t cv0[HALF], cv1[HALF], c0v[HALF];
+        #pragma unroll
+        for (int v = 0; v < HALF; v++) {
+            const int m = (int)run.j0 + (h + v < cnt ? h + v : 0);
             const KsJob jb = jobs[m];
             const uint64_t* Cm = conv + (size_t)m * 2 * Lc * n + (size_t)i * n + x;
-            const uint64_t d0 = shoup(sub_mod(redc(a0[u], q, qi), Cm[0], q), pi, pis, q);
-            const uint64_t d1 = shoup(sub_mod(redc(a1[u], q, qi), Cm[(size_t)Lc * n], q), pi, pis, q);
-            const uint32_t src = (jb.k == 1) ? x : galois_src(x, jb.k, logn);
-            const uint64_t c0 = jb.in[(size_t)i * n + src];
+            cv0[v] = Cm[0];
+            cv1[v] = Cm[(size_t)Lc * n];
+            c0v[v] = gl(jb.in)[(size_t)i * n + ((jb.k == 1) ? x : galois_src(x, jb.k, logn))];
+        }
+        #pragma unroll
+        for (int v = 0; v < HALF; v++) {
+            const int u = h + v;
+            if (u >= cnt) continue;
+            const KsJob jb = jobs[run.j0 + u];
+            const uint64_t d0 = shoup(sub_mod(redc(a0[u], q, qi), cv0[v], q), pi, pis, q);
+            const uint64_t d1 = shoup(sub_mod(redc(a1[u], q, qi), cv1[v], q), pi, pis, q);
+            gl_mu64* out = gl(jb.out);
             if (jb.tstride) {
                 const size_t o = ((size_t)i * (n >> 6) + (x >> 6)) * jb.tstride + 2 * (x & 63);
-                *reinterpret_cast<ulonglong2*>(jb.out + o) =
-                    ulonglong2{split_word(add_mod(d0, c0, q), h), split_word(d1, h)};
+                typedef unsigned long long w2 __attribute__((ext_vector_type(2)));
+                *reinterpret_cast<__attribute__((address_space(1))) w2*>(out + o) =
+                    w2{split_word(add_mod(d0, c0v[v], q), sh), split_word(d1, sh)};
             } else {
-                jb.out[(size_t)i * n + x] = add_mod(d0, c0, q);
-                jb.out[((size_t)Lc + i) * n + x] = d1;
+                out[(size_t)i * n + x] = add_mod(d0, c0v[v], q);
+                out[((size_t)Lc + i) * n + x] = d1;
             }
         }
     }
@@ -412,7 +431,7 @@ __global__ void kb_inner_sum_kernel(uint64_t* __restrict__ TA, uint64_t* __restr
         int terms = 0;
         for (uint32_t u = gr.j0; u < gr.j1; u++) {
             const KsJob jb = jobs[members[u]];
-            const uint64_t* kp = jb.key + (size_t)pr * n + x;
+            gl_cu64* kp = gl(jb.key) + (size_t)pr * n + x;
             const uint64_t* xp = X + ((size_t)jb.xidx * dn * R + row) * n + x;
             for (int j = 0; j < dn; j++) {
                 const uint64_t xv = xp[(size_t)j * R * n];
@@ -440,7 +459,7 @@ __global__ void kb_inner_sum_kernel(uint64_t* __restrict__ TA, uint64_t* __restr
         for (uint32_t u = gr.j0; u < gr.j1; u++) {
             const KsJob jb = jobs[members[u]];
             const uint32_t src = (jb.k == 1) ? x : galois_src(x, jb.k, logn);
-            acc = add_mod(acc, jb.in[(size_t)i * n + src], q);
+            acc = add_mod(acc, gl(jb.in)[(size_t)i * n + src], q);
         }
         *ca = acc;
     }
