@@ -532,13 +532,23 @@ conv_fused_kernel(ConvFused f, NttTab<uint64_t> tab, uint32_t nout, uint32_t wor
         uint64_t c[A];
         #pragma unroll
         for (int a = 0; a < A; a++) c[a] = cst0[(size_t)a * f.cst_stride];
+        // the input words of 8 elements are loaded together, then converted
         #pragma unroll
-        for (int v = 0; v < NTT_EPT; v++) {
-            const uint32_t e = TF::gidx(insert_bits(tid, v, P_HI, R), sp0);
-            u128p acc{0, 0};
+        for (int h = 0; h < NTT_EPT; h += 8) {
+            uint64_t sv[8][A];
             #pragma unroll
-            for (int a = 0; a < A; a++) add128(acc, mul128(src[(size_t)a * N + e], c[a]));
-            x[v] = redc(acc, q, qi);
+            for (int v = 0; v < 8; v++) {
+                const uint32_t e = TF::gidx(insert_bits(tid, h + v, P_HI, R), sp0);
+                #pragma unroll
+                for (int a = 0; a < A; a++) sv[v][a] = src[(size_t)a * N + e];
+            }
+            #pragma unroll
+            for (int v = 0; v < 8; v++) {
+                u128p acc{0, 0};
+                #pragma unroll
+                for (int a = 0; a < A; a++) add128(acc, mul128(sv[v][a], c[a]));
+                x[h + v] = redc(acc, q, qi);
+            }
         }
     }
     const uint64_t* tw = tab.base + ((size_t)prime * 2) * 2 * N;
@@ -886,12 +896,22 @@ ntt_mask_low_kernel(const MaskJob* __restrict__ jobs, NttTab<uint64_t> tab, cons
     const size_t row = ((size_t)comp * L + prime) * N;
     gl_cu64* av = gl(jb.a) + row;
     gl_cu64* pt = gl(jb.b) + (size_t)col * jb.b_step + (size_t)prime * N;
+    // the words of 8 elements are loaded together, then multiplied
     #pragma unroll
-    for (int i = 0; i < NTT_EPT; i++) {
-        const uint32_t f = tid + i * TL::THREADS;
-        const uint32_t e = ((f & ((1u << S) - 1u)) << TL::LOGP) | (f >> S);
-        const uint32_t g = TL::gidx(e, sp0);
-        lds[TL::lpos(e)] = mont_mul(av[g], pt[g], q, qi);
+    for (int h = 0; h < NTT_EPT; h += 8) {
+        uint64_t a[8], b[8];
+        #pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const uint32_t f = tid + (h + i) * TL::THREADS;
+            const uint32_t g = TL::gidx(((f & ((1u << S) - 1u)) << TL::LOGP) | (f >> S), sp0);
+            a[i] = av[g];
+            b[i] = pt[g];
+        }
+        #pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const uint32_t f = tid + (h + i) * TL::THREADS;
+            lds[TL::lpos(((f & ((1u << S) - 1u)) << TL::LOGP) | (f >> S))] = mont_mul(a[i], b[i], q, qi);
+        }
     }
     __syncthreads();
     TL::template round<RR, 0, 0>(lds, sp0, tw, tw2, q);
