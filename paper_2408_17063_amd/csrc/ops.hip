@@ -197,7 +197,7 @@ void kb_modup(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, bo
 // block (jobs sorted by key): each key word is read once per run, and each job's
 // raised digit (rotated on the fly for hoisted jobs) is multiplied into its own
 // 128-bit sums, reduced once.
-__global__ void kb_inner_kernel(uint64_t* __restrict__ T, const uint64_t* __restrict__ X,
+__global__ __launch_bounds__(EW_THREADS) void kb_inner_kernel(uint64_t* __restrict__ T, const uint64_t* __restrict__ X,
                                 const KsJob* __restrict__ jobs, const KsRun* __restrict__ runs,
                                 const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv, int n,
                                 int logn, int nq, int L, int Lc, int K, int dn, int hoisted, int row0) {
@@ -207,22 +207,27 @@ __global__ void kb_inner_kernel(uint64_t* __restrict__ T, const uint64_t* __rest
     const KsRun run = runs[blockIdx.z];
     const int pr = row_prime(row, Lc, L);
     const size_t keyrow = (size_t)nq * n;
-    const uint64_t* kp = jobs[run.j0].key + (size_t)pr * n + x;
+    const int cnt = (int)run.cnt;
+    gl_cu64* kp = gl(jobs[run.j0].key) + (size_t)pr * n + x;
     u128p a0[KS_RUN], a1[KS_RUN];
     #pragma unroll
     for (int i = 0; i < KS_RUN; i++) { a0[i] = u128p{0, 0}; a1[i] = u128p{0, 0}; }
     for (int j = 0; j < dn; j++) {
         const uint64_t k0 = kp[(size_t)j * 2 * keyrow], k1 = kp[(size_t)j * 2 * keyrow + keyrow];
+        // the run's words loaded together and unconditionally (a slot past the run rereads
+        // its first job and is not stored)
+        uint64_t xv[KS_RUN];
         #pragma unroll
         for (int i = 0; i < KS_RUN; i++) {
-            if (i < (int)run.cnt) {
-                const KsJob jb = jobs[run.j0 + i];
-                // plain jobs raised their already-rotated c1; hoisted jobs rotate the shared raised digits
-                const uint32_t src = (!hoisted || jb.k == 1) ? x : galois_src(x, jb.k, logn);
-                const uint64_t xv = X[((size_t)jb.xidx * dn + j) * R * n + (size_t)row * n + src];
-                add128(a0[i], mul128(xv, k0));
-                add128(a1[i], mul128(xv, k1));
-            }
+            const KsJob jb = jobs[run.j0 + (i < cnt ? i : 0)];
+            // plain jobs raised their already-rotated c1; hoisted jobs rotate the shared raised digits
+            const uint32_t src = (!hoisted || jb.k == 1) ? x : galois_src(x, jb.k, logn);
+            xv[i] = X[((size_t)jb.xidx * dn + j) * R * n + (size_t)row * n + src];
+        }
+        #pragma unroll
+        for (int i = 0; i < KS_RUN; i++) {
+            add128(a0[i], mul128(xv[i], k0));
+            add128(a1[i], mul128(xv[i], k1));
         }
     }
     const uint64_t q = mods[pr], qi = qinv[pr];
