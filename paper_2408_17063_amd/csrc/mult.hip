@@ -22,6 +22,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "compress.h"
@@ -29,37 +30,59 @@
 namespace hc {
 
 // Device constants of the exact conversions (one allocation, word offsets below).
-// Multipliers are stored in Montgomery form mod the prime they multiply under.
+// The MRC multipliers are Shoup pairs (w, floor(w 2^64 / q)); the base-conversion
+// multipliers are in Montgomery form mod the prime they multiply under and split into
+// 31-bit limbs, low limb in the low word (see conv_sum). The kernels hold a
+// coefficient's digits in registers, in arrays of compile-time length:
+// CQ = L rounded up to a multiple of 8 over Q, CB = CQ + 1 over B (nb = L + 1). The
+// tables are laid out at those lengths; the rows past L (past nb) are padding whose
+// multipliers are 0 and whose modulus is the basis's first prime, so their digits stay
+// exactly 0 and add nothing to any sum or comparison.
 struct MultTab {
-    const uint64_t* invq;   // [L][L]   q_k^-1 mod q_i (k < i), Montgomery mod q_i
-    const uint64_t* hq;     // [L]      digits of (Q-1)/2 in the radix of Q
-    const uint64_t* mqb;    // [nb][L]  prod_{k<i} q_k mod b_j, Montgomery mod b_j
-    const uint64_t* qmodb;  // [nb]     Q mod b_j
-    const uint64_t* qinvb;  // [nb]     Q^-1 mod b_j, Montgomery mod b_j
-    const uint64_t* hmod;   // [L + nb] (Q-1)/2 mod q_i, then mod b_j
-    const uint64_t* pmont;  // [L + nb] p in Montgomery form mod q_i, then mod b_j
-    const uint64_t* invb;   // [nb][nb] b_k^-1 mod b_j (k < j), Montgomery mod b_j
-    const uint64_t* hb;     // [nb]     digits of (prod B - 1)/2 in the radix of B
-    const uint64_t* mbq;    // [L][nb]  prod_{k<j} b_k mod q_i, Montgomery mod q_i
-    const uint64_t* bmodq;  // [L]      prod B mod q_i
+    const uint64_t* modq;   // [CQ]      q_i (padding: q_0)
+    const uint64_t* qiq;    // [CQ]      -q_i^-1 mod 2^64
+    const uint64_t* modb;   // [CB]      b_j (padding: b_0)
+    const uint64_t* qib;    // [CB]      -b_j^-1 mod 2^64
+    const uint64_t* invq;   // [CQ][CQ][2] [k][i]: q_k^-1 mod q_i (k < i < L), Shoup pair mod q_i
+    const uint64_t* hq;     // [CQ]      digits of (Q-1)/2 in the radix of Q
+    const uint64_t* mqb;    // [nb][CQ]  prod_{k<i} q_k mod b_j, Montgomery mod b_j, limbs
+    const uint64_t* qmodb;  // [nb]      Q mod b_j
+    const uint64_t* qinvb;  // [nb]      Q^-1 mod b_j, Montgomery mod b_j
+    const uint64_t* hmodq;  // [CQ]      (Q-1)/2 mod q_i
+    const uint64_t* pmontq; // [CQ]      p in Montgomery form mod q_i
+    const uint64_t* hmodb;  // [nb]      (Q-1)/2 mod b_j
+    const uint64_t* pmontb; // [nb]      p in Montgomery form mod b_j
+    const uint64_t* invb;   // [CB][CB][2] [k][j]: b_k^-1 mod b_j (k < j < nb), Shoup pair mod b_j
+    const uint64_t* hb;     // [CB]      digits of (prod B - 1)/2 in the radix of B
+    const uint64_t* mbq;    // [L][CB]   prod_{k<j} b_k mod q_i, Montgomery mod q_i, limbs
+    const uint64_t* bmodq;  // [L]       prod B mod q_i
 };
 constexpr int MAX_DIG = 48;  // limit on L + 1 (context creation keeps L + K <= 64; products need L <= 47)
 
+// Digit capacity over Q for L primes: L rounded up to a multiple of 8.
+static int mult_cq(int L) { return (L + 7) / 8 * 8; }
+
 static MultTab mult_tab(const Ctx& c) {
-    const int L = c.L, nb = c.nb;
+    const int L = c.L, nb = c.nb, CQ = mult_cq(L), CB = CQ + 1;
     const uint64_t* d = c.d_mult;
     MultTab t;
     size_t o = 0;
-    t.invq = d + o; o += (size_t)L * L;
-    t.hq = d + o; o += L;
-    t.mqb = d + o; o += (size_t)nb * L;
+    t.modq = d + o; o += CQ;
+    t.qiq = d + o; o += CQ;
+    t.modb = d + o; o += CB;
+    t.qib = d + o; o += CB;
+    t.invq = d + o; o += (size_t)2 * CQ * CQ;
+    t.hq = d + o; o += CQ;
+    t.mqb = d + o; o += (size_t)nb * CQ;
     t.qmodb = d + o; o += nb;
     t.qinvb = d + o; o += nb;
-    t.hmod = d + o; o += L + nb;
-    t.pmont = d + o; o += L + nb;
-    t.invb = d + o; o += (size_t)nb * nb;
-    t.hb = d + o; o += nb;
-    t.mbq = d + o; o += (size_t)L * nb;
+    t.hmodq = d + o; o += CQ;
+    t.pmontq = d + o; o += CQ;
+    t.hmodb = d + o; o += nb;
+    t.pmontb = d + o; o += nb;
+    t.invb = d + o; o += (size_t)2 * CB * CB;
+    t.hb = d + o; o += CB;
+    t.mbq = d + o; o += (size_t)L * CB;
     t.bmodq = d + o;
     return t;
 }
@@ -80,27 +103,44 @@ static std::vector<uint64_t> h_mrc(const std::vector<uint64_t>& res, const std::
     return y;
 }
 
+// v < 2^62 as two 31-bit limbs: v mod 2^31 in the low word, v >> 31 in the high word
+__host__ __device__ __forceinline__ uint64_t limbs31(uint64_t v) {
+    return (v & 0x7fffffffull) | ((v >> 31) << 32);
+}
+
 hc_status build_mult_tables(Ctx& c) {
     const int L = c.L, nb = c.nb, nq = c.nq;
     if (L + 1 > MAX_DIG || nb != L + 1) return HC_OK;  // products unavailable (context limit)
+    const int CQ = mult_cq(L), CB = CQ + 1;
     std::vector<uint64_t> Qp(c.primes.begin(), c.primes.begin() + L),
         Bp(c.primes.begin() + nq, c.primes.begin() + nq + nb);
     std::vector<uint64_t> all;
-    // invq
-    for (int i = 0; i < L; i++)
-        for (int k = 0; k < L; k++)
-            all.push_back(k < i ? h_to_mont(h_invmod(Qp[k] % Qp[i], Qp[i]), Qp[i]) : 0);
+    auto pad = [&](size_t count) { all.insert(all.end(), count, 0); };
+    // moduli and Montgomery constants, padded with the basis's first prime
+    for (int i = 0; i < CQ; i++) all.push_back(Qp[i < L ? i : 0]);
+    for (int i = 0; i < CQ; i++) all.push_back(h_mont_qinv(Qp[i < L ? i : 0]));
+    for (int j = 0; j < CB; j++) all.push_back(Bp[j < nb ? j : 0]);
+    for (int j = 0; j < CB; j++) all.push_back(h_mont_qinv(Bp[j < nb ? j : 0]));
+    // invq [k][i]: Shoup pairs
+    for (int k = 0; k < CQ; k++)
+        for (int i = 0; i < CQ; i++) {
+            const uint64_t w = k < i && i < L ? h_invmod(Qp[k] % Qp[i], Qp[i]) : 0;
+            all.push_back(w);
+            all.push_back(w ? h_shoup_const(w, Qp[i]) : 0);
+        }
     // hq: (Q-1)/2 = (q_i - 1)/2 mod q_i
     std::vector<uint64_t> hres(L);
     for (int i = 0; i < L; i++) hres[i] = (Qp[i] - 1) / 2;
     for (uint64_t x : h_mrc(hres, Qp)) all.push_back(x);
-    // mqb
+    pad(CQ - L);
+    // mqb [j][i]
     for (int j = 0; j < nb; j++) {
         uint64_t pr = 1;
         for (int i = 0; i < L; i++) {
-            all.push_back(h_to_mont(pr, Bp[j]));
+            all.push_back(limbs31(h_to_mont(pr, Bp[j])));
             pr = h_mulmod(pr, Qp[i] % Bp[j], Bp[j]);
         }
+        pad(CQ - L);
     }
     // qmodb, qinvb
     std::vector<uint64_t> qmb(nb);
@@ -111,28 +151,34 @@ hc_status build_mult_tables(Ctx& c) {
         all.push_back(pr);
     }
     for (int j = 0; j < nb; j++) all.push_back(h_to_mont(h_invmod(qmb[j], Bp[j]), Bp[j]));
-    // hmod: (Q-1)/2 mod q_i and mod b_j = (Q mod b - 1) 2^-1 mod b
+    // (Q-1)/2 and p over Q (padded), then over B: (Q-1)/2 mod b = (Q mod b - 1) 2^-1 mod b
     for (int i = 0; i < L; i++) all.push_back((Qp[i] - 1) / 2);
+    pad(CQ - L);
+    for (int i = 0; i < L; i++) all.push_back(h_to_mont(c.p % Qp[i], Qp[i]));
+    pad(CQ - L);
     for (int j = 0; j < nb; j++)
         all.push_back(h_mulmod((qmb[j] + Bp[j] - 1) % Bp[j], h_invmod(2, Bp[j]), Bp[j]));
-    // pmont
-    for (int i = 0; i < L; i++) all.push_back(h_to_mont(c.p % Qp[i], Qp[i]));
     for (int j = 0; j < nb; j++) all.push_back(h_to_mont(c.p % Bp[j], Bp[j]));
-    // invb
-    for (int j = 0; j < nb; j++)
-        for (int k = 0; k < nb; k++)
-            all.push_back(k < j ? h_to_mont(h_invmod(Bp[k] % Bp[j], Bp[j]), Bp[j]) : 0);
+    // invb [k][j]: Shoup pairs
+    for (int k = 0; k < CB; k++)
+        for (int j = 0; j < CB; j++) {
+            const uint64_t w = k < j && j < nb ? h_invmod(Bp[k] % Bp[j], Bp[j]) : 0;
+            all.push_back(w);
+            all.push_back(w ? h_shoup_const(w, Bp[j]) : 0);
+        }
     // hb: (prod B - 1)/2 = (b_j - 1)/2 mod b_j
     std::vector<uint64_t> hbres(nb);
     for (int j = 0; j < nb; j++) hbres[j] = (Bp[j] - 1) / 2;
     for (uint64_t x : h_mrc(hbres, Bp)) all.push_back(x);
-    // mbq, bmodq
+    pad(CB - nb);
+    // mbq [i][j], bmodq
     for (int i = 0; i < L; i++) {
         uint64_t pr = 1;
         for (int j = 0; j < nb; j++) {
-            all.push_back(h_to_mont(pr, Qp[i]));
+            all.push_back(limbs31(h_to_mont(pr, Qp[i])));
             pr = h_mulmod(pr, Bp[j] % Qp[i], Qp[i]);
         }
+        pad(CB - nb);
     }
     for (int i = 0; i < L; i++) {
         uint64_t pr = 1;
@@ -145,50 +191,117 @@ hc_status build_mult_tables(Ctx& c) {
     return HC_OK;
 }
 
-// MRC digits of x (residues over m primes starting at prime index p0): y_i < m_i.
-// Digit k is below its own prime; every prime of a basis lies in [2^(t-1), 2^t) for
-// one t, so y_k mod m_i is y_k or y_k - m_i.
-template <int MAXM>
-__device__ __forceinline__ void mrc(uint64_t* y, const uint64_t* x, int m, const uint64_t* mods,
-                                    const uint64_t* qinv, const uint64_t* inv, int p0) {
-    for (int i = 0; i < m; i++) {
-        const uint64_t q = mods[p0 + i], qi = qinv[p0 + i];
-        uint64_t t = x[i];
-        for (int k = 0; k < i; k++) {
-            const uint64_t yk = csub(y[k], q);
-            t = sub_mod(t, yk, q);
-            t = mont_mul(t, inv[(size_t)i * m + k], q, qi);
+// The digit arrays of one coefficient live in registers, indexed only at compile time:
+// loops over digits are unrolled (the padding rows compute exact zeros), and where a
+// loop runs over a runtime index (the MRC step, the output prime) the element it needs
+// is picked by selects.
+
+// MRC digits in place: t[i] (residues over the M primes of mods) become the digits
+// y_i < m_i. Step k takes digit k off every later residue and divides by m_k; the rows
+// of a step are independent, updated in chunks of 8 (chunks wholly at or before k are
+// skipped, and only the chunk holding k needs a select). Digit k lies below 2 m_i (every
+// prime of a basis lies in [2^(t-1), 2^t) for one t), so t_i + 2 m_i - y_k lies in
+// (0, 3 m_i) and one Shoup product by m_k^-1 (inv: [k][i] pairs) brings it to [0, 2 m_i).
+template <int M>
+__device__ __forceinline__ void mrc(uint64_t (&t)[M], const uint64_t* __restrict__ mods,
+                                    const uint64_t* __restrict__ inv) {
+    for (int k = 0; k + 1 < M; k++) {
+        uint64_t yk = t[0];
+        #pragma unroll
+        for (int i = 1; i < M; i++) yk = i == k ? t[i] : yk;
+        const uint64_t* ik = inv + (size_t)2 * k * M;
+        #pragma unroll
+        for (int c = 0; c < M; c += 8) {
+            constexpr int W = 8;
+            const int ce = c + W < M ? c + W : M;
+            if (c > k) {
+                #pragma unroll
+                for (int i = c; i < ce; i++) {
+                    const uint64_t q = mods[i];
+                    t[i] = csub(shoup_lazy(t[i] + 2 * q - yk, ik[2 * i], ik[2 * i + 1], q), q);
+                }
+            } else if (ce > k + 1) {
+                #pragma unroll
+                for (int i = c; i < ce; i++) {
+                    const uint64_t q = mods[i];
+                    const uint64_t v = csub(shoup_lazy(t[i] + 2 * q - yk, ik[2 * i], ik[2 * i + 1], q), q);
+                    t[i] = i > k ? v : t[i];
+                }
+            }
         }
-        y[i] = t;
     }
 }
 
-// x > h for digit vectors (most significant digit last)
-__device__ __forceinline__ bool digits_gt(const uint64_t* y, const uint64_t* h, int m) {
-    for (int i = m - 1; i >= 0; i--) {
-        if (y[i] != h[i]) return y[i] > h[i];
+// y > h for digit vectors (most significant digit last)
+template <int M>
+__device__ __forceinline__ bool digits_gt(const uint64_t (&y)[M], const uint64_t* __restrict__ h) {
+    bool gt = false, decided = false;
+    #pragma unroll
+    for (int i = M - 1; i >= 0; i--) {
+        const uint64_t hv = h[i];
+        gt = decided ? gt : y[i] > hv;
+        decided = decided || y[i] != hv;
     }
-    return false;
+    return gt;
+}
+
+// Digits to 31-bit limb form (see limbs31), for conv_sum.
+template <int M>
+__device__ __forceinline__ void to_limbs(uint64_t (&y)[M]) {
+    #pragma unroll
+    for (int i = 0; i < M; i++) y[i] = limbs31(y[i]);
+}
+
+// sum_i y_i c_i mod q for y_i < 2^61 and c_i < q in Montgomery form, both as 31-bit
+// limbs (y = y0 + y1 2^31): each term is four 32x32-bit multiply-adds into the column
+// sums a0 (y0 c0), a1 (y0 c1 + y1 c0) and a2 (y1 c1), which hold 4 terms below 2^64;
+// T = a0 + a1 2^31 + a2 2^62 collects 8 terms (below 2^64 q) per reduction.
+template <int M>
+__device__ __forceinline__ uint64_t conv_sum(const uint64_t (&y)[M], const uint64_t* __restrict__ c, uint64_t q,
+                                             uint64_t qi) {
+    uint64_t v = 0;
+    #pragma unroll
+    for (int i8 = 0; i8 < M; i8 += 8) {
+        u128p T{0, 0};
+        #pragma unroll
+        for (int i4 = i8; i4 < (i8 + 8 < M ? i8 + 8 : M); i4 += 4) {
+            uint64_t a0 = 0, a1 = 0, a2 = 0;
+            #pragma unroll
+            for (int i = i4; i < (i4 + 4 < M ? i4 + 4 : M); i++) {
+                const uint32_t y0 = (uint32_t)y[i], y1 = (uint32_t)(y[i] >> 32);
+                const uint32_t c0 = (uint32_t)c[i], c1 = (uint32_t)(c[i] >> 32);
+                a0 += (uint64_t)y0 * c0;
+                a1 += (uint64_t)y0 * c1;
+                a1 += (uint64_t)y1 * c0;
+                a2 += (uint64_t)y1 * c1;
+            }
+            add128(T, u128p{a0, 0});
+            add128(T, u128p{a1 << 31, a1 >> 33});
+            add128(T, u128p{a2 << 62, a2 >> 2});
+        }
+        v = add_mod(v, redc(T, q, qi), q);
+    }
+    return v;
 }
 
 // out[t][j] = centred lift of in[t] (over Q, coefficient domain) mod b_j, t < count
-__global__ void bext_kernel(uint64_t* __restrict__ out, const uint64_t* __restrict__ in, MultTab tb,
-                            const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv, int n, int L,
-                            int nq, int nb) {
+template <int CQ>
+__global__ void __launch_bounds__(256) bext_kernel(uint64_t* __restrict__ out, const uint64_t* __restrict__ in, MultTab tb,
+                                                   int n, int L, int nb) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     const int t = blockIdx.z;
     const uint64_t* a = in + (size_t)t * L * n + x;
-    uint64_t r[MAX_DIG], y[MAX_DIG];
-    for (int i = 0; i < L; i++) r[i] = a[(size_t)i * n];
-    mrc<MAX_DIG>(y, r, L, mods, qinv, tb.invq, 0);
-    const bool neg = digits_gt(y, tb.hq, L);
+    uint64_t y[CQ];
+    #pragma unroll
+    for (int i = 0; i < CQ; i++) y[i] = i < L ? a[(size_t)i * n] : 0;
+    mrc<CQ>(y, tb.modq, tb.invq);
+    const bool neg = digits_gt<CQ>(y, tb.hq);
+    to_limbs<CQ>(y);
     uint64_t* o = out + (size_t)t * nb * n + x;
     for (int j = 0; j < nb; j++) {
-        const int pj = nq + j;
-        const uint64_t b = mods[pj], bi = qinv[pj];
-        uint64_t v = 0;
-        for (int i = 0; i < L; i++) v = add_mod(v, mont_mul(y[i], tb.mqb[(size_t)j * L + i], b, bi), b);
+        const uint64_t b = tb.modb[j], bi = tb.qib[j];
+        uint64_t v = conv_sum<CQ>(y, tb.mqb + (size_t)j * CQ, b, bi);
         if (neg) v = sub_mod(v, tb.qmodb[j], b);
         o[(size_t)j * n] = v;
     }
@@ -214,42 +327,60 @@ __global__ void tensor_kernel(uint64_t* __restrict__ e, const uint64_t* __restri
 
 // z[slot[t]] (over Q, coefficient domain) = round(p e_t / Q) mod Q from e_t over Q (eq)
 // and over B (eb), coefficient domain, t < 3
-__global__ void scale_round_kernel(uint64_t* __restrict__ z, const uint64_t* __restrict__ eq,
-                                   const uint64_t* __restrict__ eb, MultTab tb, const uint64_t* __restrict__ mods,
-                                   const uint64_t* __restrict__ qinv, int n, int L, int nq, int nb, int s0, int s1,
-                                   int s2) {
+template <int CQ>
+__global__ void __launch_bounds__(256) scale_round_kernel(uint64_t* __restrict__ z, const uint64_t* __restrict__ eq,
+                                                          const uint64_t* __restrict__ eb, MultTab tb, int n, int L,
+                                                          int nb, int s0, int s1, int s2) {
+    constexpr int CB = CQ + 1;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     const int t = blockIdx.z;
     const int slot = t == 0 ? s0 : (t == 1 ? s1 : s2);
-    uint64_t r[MAX_DIG], y[MAX_DIG];
+    uint64_t r[CQ], y[CB];
     // r = (p e + H) mod Q, exactly, as MRC digits over Q
-    for (int i = 0; i < L; i++) {
-        const uint64_t q = mods[i], qi = qinv[i];
-        const uint64_t ev = eq[((size_t)t * L + i) * n + x];
-        r[i] = add_mod(mont_mul(ev, tb.pmont[i], q, qi), tb.hmod[i], q);
+    #pragma unroll
+    for (int i = 0; i < CQ; i++) r[i] = i < L ? eq[((size_t)t * L + i) * n + x] : 0;
+    #pragma unroll
+    for (int i = 0; i < CQ; i++) {
+        const uint64_t q = tb.modq[i];
+        r[i] = add_mod(mont_mul(r[i], tb.pmontq[i], q, tb.qiq[i]), tb.hmodq[i], q);
     }
-    mrc<MAX_DIG>(y, r, L, mods, qinv, tb.invq, 0);
+    mrc<CQ>(r, tb.modq, tb.invq);
+    to_limbs<CQ>(r);
     // z mod b_j = (p e + H - r) Q^-1 mod b_j (the division is exact)
+    #pragma unroll
+    for (int j = 0; j < CB; j++) y[j] = 0;
     for (int j = 0; j < nb; j++) {
-        const int pj = nq + j;
-        const uint64_t b = mods[pj], bi = qinv[pj];
-        uint64_t rv = 0;
-        for (int i = 0; i < L; i++) rv = add_mod(rv, mont_mul(y[i], tb.mqb[(size_t)j * L + i], b, bi), b);
+        const uint64_t b = tb.modb[j], bi = tb.qib[j];
         const uint64_t ev = eb[((size_t)t * nb + j) * n + x];
-        uint64_t v = add_mod(mont_mul(ev, tb.pmont[L + j], b, bi), tb.hmod[L + j], b);
-        v = sub_mod(v, rv, b);
-        r[j] = mont_mul(v, tb.qinvb[j], b, bi);
+        const uint64_t rv = conv_sum<CQ>(r, tb.mqb + (size_t)j * CQ, b, bi);
+        const uint64_t v = add_mod(mont_mul(ev, tb.pmontb[j], b, bi), tb.hmodb[j], b);
+        const uint64_t zj = mont_mul(sub_mod(v, rv, b), tb.qinvb[j], b, bi);
+        #pragma unroll
+        for (int jj = 0; jj < CB; jj++) y[jj] = jj == j ? zj : y[jj];
     }
     // z (|z| < prod B / 2) from its residues over B, back to Q
-    mrc<MAX_DIG>(y, r, nb, mods, qinv, tb.invb, nq);
-    const bool neg = digits_gt(y, tb.hb, nb);
+    mrc<CB>(y, tb.modb, tb.invb);
+    const bool neg = digits_gt<CB>(y, tb.hb);
+    to_limbs<CB>(y);
     for (int i = 0; i < L; i++) {
-        const uint64_t q = mods[i], qi = qinv[i];
-        uint64_t v = 0;
-        for (int j = 0; j < nb; j++) v = add_mod(v, mont_mul(y[j], tb.mbq[(size_t)i * nb + j], q, qi), q);
+        const uint64_t q = tb.modq[i];
+        uint64_t v = conv_sum<CB>(y, tb.mbq + (size_t)i * CB, q, tb.qiq[i]);
         if (neg) v = sub_mod(v, tb.bmodq[i], q);
         z[((size_t)slot * L + i) * n + x] = v;
+    }
+}
+
+// Calls f(integral_constant<int, CQ>) with the digit capacity over Q for L primes.
+template <typename F>
+static void with_cap(int L, F&& f) {
+    switch (mult_cq(L)) {
+        case 8: f(std::integral_constant<int, 8>{}); break;
+        case 16: f(std::integral_constant<int, 16>{}); break;
+        case 24: f(std::integral_constant<int, 24>{}); break;
+        case 32: f(std::integral_constant<int, 32>{}); break;
+        case 40: f(std::integral_constant<int, 40>{}); break;
+        default: f(std::integral_constant<int, 48>{}); break;
     }
 }
 
@@ -287,11 +418,14 @@ static hc_status mul_ct(Ctx& c, Lane& l, KsScratch& ks, const uint64_t* rk, cons
     const MultTab tb = mult_tab(c);
     const bool sq = a == b;
     // 1. the centred lifts over B
-    hipLaunchKernelGGL(bext_kernel, dim3((unsigned)((n + 255) / 256), 1, 2), dim3(256), 0, st, aB, a, tb, c.d_mods,
-                       c.d_qinv, (int)n, L, nq, nb);
-    if (!sq)
-        hipLaunchKernelGGL(bext_kernel, dim3((unsigned)((n + 255) / 256), 1, 2), dim3(256), 0, st, bB, b, tb,
-                           c.d_mods, c.d_qinv, (int)n, L, nq, nb);
+    with_cap(L, [&](auto cap) {
+        constexpr int C = decltype(cap)::value;
+        hipLaunchKernelGGL(bext_kernel<C>, dim3((unsigned)((n + 255) / 256), 1, 2), dim3(256), 0, st, aB, a, tb,
+                           (int)n, L, nb);
+        if (!sq)
+            hipLaunchKernelGGL(bext_kernel<C>, dim3((unsigned)((n + 255) / 256), 1, 2), dim3(256), 0, st, bB, b, tb,
+                               (int)n, L, nb);
+    });
     // 2. NTT domain over Q and B, the tensor, back
     HC_CHECK(hipMemcpyAsync(aN, a, sizeof(uint64_t) * 2 * QW, hipMemcpyDeviceToDevice, st));
     ntt64(c, aN, QW, 2, 0, L, false, st);
@@ -308,8 +442,11 @@ static hc_status mul_ct(Ctx& c, Lane& l, KsScratch& ks, const uint64_t* rk, cons
     ntt64(c, eQ, QW, 3, 0, L, true, st);
     ntt64(c, eB, BW, 3, nq, nb, true, st);
     // 3. z = round(p e / Q), stored (z0, z2, z1) so that (z0, z2) is a ciphertext to key-switch
-    hipLaunchKernelGGL(scale_round_kernel, dim3((unsigned)((n + 255) / 256), 1, 3), dim3(256), 0, st, z, eQ, eB, tb,
-                       c.d_mods, c.d_qinv, (int)n, L, nq, nb, 0, 2, 1);
+    with_cap(L, [&](auto cap) {
+        constexpr int C = decltype(cap)::value;
+        hipLaunchKernelGGL(scale_round_kernel<C>, dim3((unsigned)((n + 255) / 256), 1, 3), dim3(256), 0, st, z, eQ,
+                           eB, tb, (int)n, L, nb, 0, 2, 1);
+    });
     // 4. relinearisation: (z0 + KS(z2)_0, z1 + KS(z2)_1)
     ntt64(c, z, QW, 3, 0, L, false, st);
     std::vector<KsJob> jobs{KsJob{z, ko, rk, 1u, 0}};
