@@ -255,13 +255,15 @@ hc_status hc_power(hc_context* ctx, const hc_gk* rk, const uint64_t* ct_in, uint
  * hc_db_upload), the index-vector ciphertexts ct_v [ceil(N/n)][2][L][n] with
  * v_r = 1 - (x - k_r)^(p-1): the query minus the keys' plaintext, Power_{p-1}, one minus
  * the result; in the last ciphertext the slots past record N are multiplied by 0.
- * Their output feeds hc_compress as ct_v. Synchronises. Errors: as hc_mul. */
+ * Their output feeds hc_compress as ct_v. The powers of up to 16 ciphertexts run in
+ * lockstep, each product step one pass over all of them (workspace: about 0.4 GB per
+ * ciphertext at 24 primes and ring 2^16). Synchronises. Errors: as hc_mul. */
 hc_status hc_match(hc_context* ctx, const hc_gk* rk, const hc_db* keys, const uint64_t* ct_x, uint64_t N,
                    uint64_t* ct_v, hipStream_t stream);
 
 /* Comp of Alg. 5 on ciphertexts of a sparse vector d alone (no index vector given):
- * v = Power_{p-1}(d) ciphertext by ciphertext at the full level, then the compression
- * of the pair (v, d) exactly as hc_compress with one value column whose masked
+ * v = Power_{p-1}(d) at the full level (the ciphertexts in lockstep, as hc_match), then
+ * the compression of the pair (v, d) exactly as hc_compress with one value column whose masked
  * ciphertexts are d's own. ct_d: device [ceil(N/n)][2][L][n]. Other arguments as
  * hc_compress (gk: hc_plan's key set for ncol = 1). Synchronises. */
 hc_status hc_compress_generic(hc_context* ctx, const hc_gk* gk, const hc_gk* rk, const uint64_t* ct_d, uint64_t N,

@@ -308,7 +308,7 @@ __global__ void __launch_bounds__(256) bext_kernel(uint64_t* __restrict__ out, c
 }
 
 // e = (a0 b0, a0 b1 + a1 b0, a1 b1) pointwise (NTT domain) on R rows of prime indices
-// prime0 + row; a, b: [2][R][n]; e: [3][R][n]
+// prime0 + row, for ciphertext blockIdx.z; a, b: [count][2][R][n]; e: [count][3][R][n]
 __global__ void tensor_kernel(uint64_t* __restrict__ e, const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
                               const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv,
                               const uint64_t* __restrict__ r2, int n, int R, int prime0) {
@@ -316,7 +316,10 @@ __global__ void tensor_kernel(uint64_t* __restrict__ e, const uint64_t* __restri
     if (x >= n) return;
     const int row = blockIdx.y, pi = prime0 + row;
     const uint64_t q = mods[pi], qi = qinv[pi], rr = r2[pi];
-    const size_t o = (size_t)row * n + x, P = (size_t)R * n;
+    const size_t P = (size_t)R * n, o = (size_t)row * n + x, ct = blockIdx.z;
+    a += ct * 2 * P;
+    b += ct * 2 * P;
+    e += ct * 3 * P;
     // b to Montgomery form: mont_mul(b, 2^128 mod q) = b 2^64 mod q
     const uint64_t b0 = mont_mul(b[o], rr, q, qi), b1 = mont_mul(b[P + o], rr, q, qi);
     const uint64_t a0 = a[o], a1 = a[P + o];
@@ -325,8 +328,9 @@ __global__ void tensor_kernel(uint64_t* __restrict__ e, const uint64_t* __restri
     e[2 * P + o] = mont_mul(a1, b1, q, qi);
 }
 
-// z[slot[t]] (over Q, coefficient domain) = round(p e_t / Q) mod Q from e_t over Q (eq)
-// and over B (eb), coefficient domain, t < 3
+// z[ct][slot[t]] (over Q, coefficient domain) = round(p e_t / Q) mod Q from e_t over Q
+// (eq, [count][3][L][n]) and over B (eb, [count][3][nb][n]), coefficient domain;
+// blockIdx.z = 3 ct + t
 template <int CQ>
 __global__ void __launch_bounds__(256) scale_round_kernel(uint64_t* __restrict__ z, const uint64_t* __restrict__ eq,
                                                           const uint64_t* __restrict__ eb, MultTab tb, int n, int L,
@@ -334,8 +338,12 @@ __global__ void __launch_bounds__(256) scale_round_kernel(uint64_t* __restrict__
     constexpr int CB = CQ + 1;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
-    const int t = blockIdx.z;
+    const int t = blockIdx.z % 3;
+    const size_t ct = blockIdx.z / 3;
     const int slot = t == 0 ? s0 : (t == 1 ? s1 : s2);
+    eq += ct * 3 * L * n;
+    eb += ct * 3 * nb * n;
+    z += ct * 3 * L * n;
     uint64_t r[CQ], y[CB];
     // r = (p e + H) mod Q, exactly, as MRC digits over Q
     #pragma unroll
@@ -369,6 +377,18 @@ __global__ void __launch_bounds__(256) scale_round_kernel(uint64_t* __restrict__
         if (neg) v = sub_mod(v, tb.bmodq[i], q);
         z[((size_t)slot * L + i) * n + x] = v;
     }
+}
+
+// out[ct][1] += z[ct][2] over the first L primes (ciphertext ct = blockIdx.z; out:
+// [count][2][L][n], z: [count][3][L][n])
+__global__ void add_z1_kernel(uint64_t* __restrict__ out, const uint64_t* __restrict__ z,
+                              const uint64_t* __restrict__ mods, int n, int L) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int r = blockIdx.y;
+    const size_t ct = blockIdx.z, Ln = (size_t)L * n, o = (size_t)r * n + x;
+    uint64_t* d = out + ct * 2 * Ln + Ln + o;
+    *d = add_mod(*d, z[ct * 3 * Ln + 2 * Ln + o], mods[r]);
 }
 
 // Calls f(integral_constant<int, CQ>) with the digit capacity over Q for L primes.
@@ -406,10 +426,12 @@ __global__ void one_minus_kernel(uint64_t* ct, const uint64_t* mods, const uint6
     ct[o] = sub_mod(d, ct[o], q);
 }
 
-// One product at the full level: out = relin(round(p/Q (a x b))). a, b, out: [2][L][n]
-// coefficient domain (out may alias a or b). Workspace from the arena a_ (reset by the caller).
+// Products of `count` pairs at the full level, all in one pass per step: out[i] =
+// relin(round(p/Q (a[i] x b[i]))). a, b, out: [count][2][L][n] coefficient domain (out
+// may alias a or b; b == a squares). Every launch covers the whole batch, and the
+// relinearisations are one key-switching pass whose jobs share the key.
 static hc_status mul_ct(Ctx& c, Lane& l, KsScratch& ks, const uint64_t* rk, const uint64_t* a, const uint64_t* b,
-                        uint64_t* out, uint64_t* const* buf, hipStream_t st) {
+                        uint64_t* out, int count, uint64_t* const* buf, hipStream_t st) {
     const size_t n = c.n;
     const int L = c.L, nb = c.nb, nq = c.nq;
     const size_t QW = (size_t)L * n, BW = (size_t)nb * n;
@@ -417,89 +439,101 @@ static hc_status mul_ct(Ctx& c, Lane& l, KsScratch& ks, const uint64_t* rk, cons
              *ko = buf[7];
     const MultTab tb = mult_tab(c);
     const bool sq = a == b;
+    const unsigned gx = (unsigned)((n + 255) / 256), cnt = (unsigned)count;
     // 1. the centred lifts over B
     with_cap(L, [&](auto cap) {
         constexpr int C = decltype(cap)::value;
-        hipLaunchKernelGGL(bext_kernel<C>, dim3((unsigned)((n + 255) / 256), 1, 2), dim3(256), 0, st, aB, a, tb,
-                           (int)n, L, nb);
-        if (!sq)
-            hipLaunchKernelGGL(bext_kernel<C>, dim3((unsigned)((n + 255) / 256), 1, 2), dim3(256), 0, st, bB, b, tb,
-                               (int)n, L, nb);
+        hipLaunchKernelGGL(bext_kernel<C>, dim3(gx, 1, 2 * cnt), dim3(256), 0, st, aB, a, tb, (int)n, L, nb);
+        if (!sq) hipLaunchKernelGGL(bext_kernel<C>, dim3(gx, 1, 2 * cnt), dim3(256), 0, st, bB, b, tb, (int)n, L, nb);
     });
     // 2. NTT domain over Q and B, the tensor, back
-    HC_CHECK(hipMemcpyAsync(aN, a, sizeof(uint64_t) * 2 * QW, hipMemcpyDeviceToDevice, st));
-    ntt64(c, aN, QW, 2, 0, L, false, st);
-    ntt64(c, aB, BW, 2, nq, nb, false, st);
+    HC_CHECK(hipMemcpyAsync(aN, a, sizeof(uint64_t) * 2 * QW * count, hipMemcpyDeviceToDevice, st));
+    ntt64(c, aN, QW, 2 * count, 0, L, false, st);
+    ntt64(c, aB, BW, 2 * count, nq, nb, false, st);
     if (!sq) {
-        HC_CHECK(hipMemcpyAsync(bN, b, sizeof(uint64_t) * 2 * QW, hipMemcpyDeviceToDevice, st));
-        ntt64(c, bN, QW, 2, 0, L, false, st);
-        ntt64(c, bB, BW, 2, nq, nb, false, st);
+        HC_CHECK(hipMemcpyAsync(bN, b, sizeof(uint64_t) * 2 * QW * count, hipMemcpyDeviceToDevice, st));
+        ntt64(c, bN, QW, 2 * count, 0, L, false, st);
+        ntt64(c, bB, BW, 2 * count, nq, nb, false, st);
     }
-    hipLaunchKernelGGL(tensor_kernel, dim3((unsigned)((n + 255) / 256), L), dim3(256), 0, st, eQ, aN, sq ? aN : bN,
-                       c.d_mods, c.d_qinv, c.d_r2, (int)n, L, 0);
-    hipLaunchKernelGGL(tensor_kernel, dim3((unsigned)((n + 255) / 256), nb), dim3(256), 0, st, eB, aB, sq ? aB : bB,
-                       c.d_mods, c.d_qinv, c.d_r2, (int)n, nb, nq);
-    ntt64(c, eQ, QW, 3, 0, L, true, st);
-    ntt64(c, eB, BW, 3, nq, nb, true, st);
+    hipLaunchKernelGGL(tensor_kernel, dim3(gx, L, cnt), dim3(256), 0, st, eQ, aN, sq ? aN : bN, c.d_mods, c.d_qinv,
+                       c.d_r2, (int)n, L, 0);
+    hipLaunchKernelGGL(tensor_kernel, dim3(gx, nb, cnt), dim3(256), 0, st, eB, aB, sq ? aB : bB, c.d_mods, c.d_qinv,
+                       c.d_r2, (int)n, nb, nq);
+    ntt64(c, eQ, QW, 3 * count, 0, L, true, st);
+    ntt64(c, eB, BW, 3 * count, nq, nb, true, st);
     // 3. z = round(p e / Q), stored (z0, z2, z1) so that (z0, z2) is a ciphertext to key-switch
     with_cap(L, [&](auto cap) {
         constexpr int C = decltype(cap)::value;
-        hipLaunchKernelGGL(scale_round_kernel<C>, dim3((unsigned)((n + 255) / 256), 1, 3), dim3(256), 0, st, z, eQ,
-                           eB, tb, (int)n, L, nb, 0, 2, 1);
+        hipLaunchKernelGGL(scale_round_kernel<C>, dim3(gx, 1, 3 * cnt), dim3(256), 0, st, z, eQ, eB, tb, (int)n, L, nb,
+                           0, 2, 1);
     });
     // 4. relinearisation: (z0 + KS(z2)_0, z1 + KS(z2)_1)
-    ntt64(c, z, QW, 3, 0, L, false, st);
-    std::vector<KsJob> jobs{KsJob{z, ko, rk, 1u, 0}};
+    ntt64(c, z, QW, 3 * count, 0, L, false, st);
+    std::vector<KsJob> jobs;
+    for (int i = 0; i < count; i++) jobs.push_back(KsJob{z + (size_t)i * 3 * QW, ko + (size_t)i * 2 * QW, rk, 1u, 0});
     hc_status s = ks_run(c, l, ks, jobs, nullptr, L, st);
     if (s != HC_OK) return s;
-    k_add(c, ko + QW, ko + QW, z + 2 * QW, 0, L, 1, QW, st);
-    ntt64(c, ko, QW, 2, 0, L, true, st);
-    HC_CHECK(hipMemcpyAsync(out, ko, sizeof(uint64_t) * 2 * QW, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(add_z1_kernel, dim3(gx, L, cnt), dim3(256), 0, st, ko, z, c.d_mods, (int)n, L);
+    ntt64(c, ko, QW, 2 * count, 0, L, true, st);
+    HC_CHECK(hipMemcpyAsync(out, ko, sizeof(uint64_t) * 2 * QW * count, hipMemcpyDeviceToDevice, st));
     return HC_OK;
 }
 
-// Workspace of products: 8 buffers + key-switching scratch for one job at level L.
+// Ciphertexts a product pass takes at once (the workspace grows with it: about 0.4 GB
+// per ciphertext at 24 primes and ring 2^16).
+constexpr int MUL_BATCH = 16;
+
+// Workspace of products for up to `count` ciphertexts: 8 buffers, two spare ciphertext
+// arrays and key-switching scratch for `count` jobs at level L.
 struct MulWs {
     KsScratch ks;
     uint64_t* buf[8];
-    uint64_t* t0;  // [2][L][n] spare ciphertexts
+    uint64_t* t0;  // [count][2][L][n] spare ciphertexts
     uint64_t* t1;
 };
 
-static size_t mul_ws_bytes(const Ctx& c) {
-    const size_t QW = (size_t)c.L * c.n, BW = (size_t)c.nb * c.n;
-    return 8 * (2 * QW + 2 * QW + 2 * BW + 2 * BW + 3 * QW + 3 * BW + 3 * QW + 2 * QW + 2 * QW + 2 * QW) +
-           ks_scratch_bytes(c, c.L, 1) + 16 * 256;
+static void mul_ws_sizes(const Ctx& c, int count, size_t (&sizes)[10]) {
+    const size_t QW = (size_t)c.L * c.n, BW = (size_t)c.nb * c.n, k = (size_t)count;
+    const size_t sz[10] = {2 * QW, 2 * QW, 2 * BW, 2 * BW, 3 * QW, 3 * BW, 3 * QW, 2 * QW, 2 * QW, 2 * QW};
+    for (int i = 0; i < 10; i++) sizes[i] = k * sz[i];
 }
 
-static hc_status mul_ws(Ctx& c, Arena& a, MulWs& w) {
-    const size_t QW = (size_t)c.L * c.n, BW = (size_t)c.nb * c.n;
-    w.ks = ks_scratch(c, a, c.L, 1);
-    const size_t sizes[8] = {2 * QW, 2 * QW, 2 * BW, 2 * BW, 3 * QW, 3 * BW, 3 * QW, 2 * QW};
+static size_t mul_ws_bytes(const Ctx& c, int count) {
+    size_t sizes[10], b = 0;
+    mul_ws_sizes(c, count, sizes);
+    for (size_t v : sizes) b += 8 * v + 256;
+    return b + ks_scratch_bytes(c, c.L, count) + 16 * 256;
+}
+
+static hc_status mul_ws(Ctx& c, Arena& a, int count, MulWs& w) {
+    size_t sizes[10];
+    mul_ws_sizes(c, count, sizes);
+    w.ks = ks_scratch(c, a, c.L, count);
     for (int i = 0; i < 8; i++) {
         w.buf[i] = a.take<uint64_t>(sizes[i]);
         if (!w.buf[i]) return HC_ENOMEM;
     }
-    w.t0 = a.take<uint64_t>(2 * QW);
-    w.t1 = a.take<uint64_t>(2 * QW);
+    w.t0 = a.take<uint64_t>(sizes[8]);
+    w.t1 = a.take<uint64_t>(sizes[9]);
     if (!w.t0 || !w.t1 || !w.ks.tmpC) return HC_ENOMEM;
     return HC_OK;
 }
 
-// out = in^e by left-to-right binary exponentiation (coefficient domain, may alias)
+// out[i] = in[i]^e for i < count by left-to-right binary exponentiation, the count
+// ciphertexts in lockstep (coefficient domain, [count][2][L][n]; out may alias in)
 static hc_status power_ct(Ctx& c, Lane& l, MulWs& w, const uint64_t* rk, const uint64_t* in, uint32_t e,
-                          uint64_t* out, hipStream_t st) {
-    const size_t CW = 2 * (size_t)c.L * c.n;
+                          uint64_t* out, int count, hipStream_t st) {
+    const size_t CW = 2 * (size_t)c.L * c.n * count;
     int top = 31;
     while (top > 0 && !((e >> top) & 1u)) top--;
-    // acc in t0, the input kept in t1 (out may alias in)
+    // acc in t0, the inputs kept in t1 (out may alias in)
     HC_CHECK(hipMemcpyAsync(w.t1, in, sizeof(uint64_t) * CW, hipMemcpyDeviceToDevice, st));
     HC_CHECK(hipMemcpyAsync(w.t0, in, sizeof(uint64_t) * CW, hipMemcpyDeviceToDevice, st));
     for (int bit = top - 1; bit >= 0; bit--) {
-        hc_status s = mul_ct(c, l, w.ks, rk, w.t0, w.t0, w.t0, w.buf, st);
+        hc_status s = mul_ct(c, l, w.ks, rk, w.t0, w.t0, w.t0, count, w.buf, st);
         if (s != HC_OK) return s;
         if ((e >> bit) & 1u) {
-            s = mul_ct(c, l, w.ks, rk, w.t0, w.t1, w.t0, w.buf, st);
+            s = mul_ct(c, l, w.ks, rk, w.t0, w.t1, w.t0, count, w.buf, st);
             if (s != HC_OK) return s;
         }
     }
@@ -520,12 +554,15 @@ hc_status power_many(Ctx& c, const hc_gk* rk, const uint64_t* in, uint32_t n_ct,
     if (s != HC_OK) return s;
     if (!c.d_mult) return HC_EINVAL;
     stage_reset(c.lane, st);
-    if (c.lane.ws.reserve(mul_ws_bytes(c)) != HC_OK) return HC_ENOMEM;
+    const int batch = (int)std::min<uint32_t>(n_ct, MUL_BATCH);
+    if (c.lane.ws.reserve(mul_ws_bytes(c, batch)) != HC_OK) return HC_ENOMEM;
     MulWs w;
-    if ((s = mul_ws(c, c.lane.ws, w)) != HC_OK) return s;
+    if ((s = mul_ws(c, c.lane.ws, batch, w)) != HC_OK) return s;
     const size_t CW = 2 * (size_t)c.L * c.n;
-    for (uint32_t i = 0; i < n_ct; i++)
-        if ((s = power_ct(c, c.lane, w, key, in + i * CW, e, out + i * CW, st)) != HC_OK) return s;
+    for (uint32_t i = 0; i < n_ct; i += batch) {
+        const int cnt = (int)std::min<uint32_t>(batch, n_ct - i);
+        if ((s = power_ct(c, c.lane, w, key, in + i * CW, e, out + i * CW, cnt, st)) != HC_OK) return s;
+    }
     return HC_OK;
 }
 
@@ -548,10 +585,10 @@ extern "C" hc_status hc_mul(hc_context* cp, const hc_gk* rk, const uint64_t* ct_
     if (s != HC_OK) return s;
     if (!c.d_mult) return HC_EINVAL;
     stage_reset(c.lane, st);
-    if (c.lane.ws.reserve(mul_ws_bytes(c)) != HC_OK) return HC_ENOMEM;
+    if (c.lane.ws.reserve(mul_ws_bytes(c, 1)) != HC_OK) return HC_ENOMEM;
     MulWs w;
-    if ((s = mul_ws(c, c.lane.ws, w)) != HC_OK) return s;
-    if ((s = mul_ct(c, c.lane, w.ks, key, ct_a, ct_b, ct_out, w.buf, st)) != HC_OK) return s;
+    if ((s = mul_ws(c, c.lane.ws, 1, w)) != HC_OK) return s;
+    if ((s = mul_ct(c, c.lane, w.ks, key, ct_a, ct_b, ct_out, 1, w.buf, st)) != HC_OK) return s;
     HC_CHECK(hipGetLastError());
     HC_CHECK(hipStreamSynchronize(st));
     return HC_OK;
@@ -637,7 +674,7 @@ extern "C" hc_status hc_compress_generic(hc_context* cp, const hc_gk* gk, const 
     std::vector<QueryRun> qs(1);
     hc_status s = make_plan(c, N, 1, t_bound, comp_level, out_level, qs[0].pl);
     if (s != HC_OK) return s;
-    // v = Power_{p-1}(d), ciphertext by ciphertext at the full level
+    // v = Power_{p-1}(d) at the full level, the ciphertexts in lockstep
     const size_t CW = 2 * (size_t)c.L * c.n;
     uint64_t* v = nullptr;
     HC_CHECK(hipMalloc((void**)&v, sizeof(uint64_t) * CW * qs[0].pl.n_ct));
