@@ -16,9 +16,9 @@
 //     and z (|z| < prod B / 2) is brought back to Q by MRC over B with its sign;
 //  4. relinearisation: (z0, z2) is key-switched like a rotation with k = 1 by the key
 //     for s^2 (ModUp, inner product over PQ, ModDown) and z1 is added to the second
-//     component.
-// One thread handles one coefficient of every polynomial of a step, so the digits
-// stay in registers.
+//     component (in the coefficient domain: z1 is never transformed).
+// One thread handles one coefficient of one polynomial, its digits in registers. The
+// products of several ciphertexts (Power and Match) run as one batch per step.
 #include <string.h>
 
 #include <algorithm>
@@ -328,22 +328,23 @@ __global__ void tensor_kernel(uint64_t* __restrict__ e, const uint64_t* __restri
     e[2 * P + o] = mont_mul(a1, b1, q, qi);
 }
 
-// z[ct][slot[t]] (over Q, coefficient domain) = round(p e_t / Q) mod Q from e_t over Q
-// (eq, [count][3][L][n]) and over B (eb, [count][3][nb][n]), coefficient domain;
-// blockIdx.z = 3 ct + t
+// round(p e_t / Q) mod Q (over Q, coefficient domain) from e_t over Q (eq,
+// [count][3][L][n]) and over B (eb, [count][3][nb][n]), coefficient domain; blockIdx.z =
+// 3 ct + t. t = 0 and 2 go to zc[ct] = (z0, z2) ([count][2][L][n], the ciphertext to
+// relinearise), t = 1 to z1[ct] ([count][L][n]).
 template <int CQ>
-__global__ void __launch_bounds__(256) scale_round_kernel(uint64_t* __restrict__ z, const uint64_t* __restrict__ eq,
+__global__ void __launch_bounds__(256) scale_round_kernel(uint64_t* __restrict__ zc, uint64_t* __restrict__ z1,
+                                                          const uint64_t* __restrict__ eq,
                                                           const uint64_t* __restrict__ eb, MultTab tb, int n, int L,
-                                                          int nb, int s0, int s1, int s2) {
+                                                          int nb) {
     constexpr int CB = CQ + 1;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     const int t = blockIdx.z % 3;
-    const size_t ct = blockIdx.z / 3;
-    const int slot = t == 0 ? s0 : (t == 1 ? s1 : s2);
-    eq += ct * 3 * L * n;
+    const size_t ct = blockIdx.z / 3, Ln = (size_t)L * n;
+    eq += ct * 3 * Ln;
     eb += ct * 3 * nb * n;
-    z += ct * 3 * L * n;
+    uint64_t* z = t == 1 ? z1 + ct * Ln : zc + ct * 2 * Ln + (t == 2 ? Ln : 0);
     uint64_t r[CQ], y[CB];
     // r = (p e + H) mod Q, exactly, as MRC digits over Q
     #pragma unroll
@@ -375,12 +376,12 @@ __global__ void __launch_bounds__(256) scale_round_kernel(uint64_t* __restrict__
         const uint64_t q = tb.modq[i];
         uint64_t v = conv_sum<CB>(y, tb.mbq + (size_t)i * CB, q, tb.qiq[i]);
         if (neg) v = sub_mod(v, tb.bmodq[i], q);
-        z[((size_t)slot * L + i) * n + x] = v;
+        z[(size_t)i * n + x] = v;
     }
 }
 
-// out[ct][1] += z[ct][2] over the first L primes (ciphertext ct = blockIdx.z; out:
-// [count][2][L][n], z: [count][3][L][n])
+// out[ct][1] += z1[ct] over the first L primes (ciphertext ct = blockIdx.z; out:
+// [count][2][L][n], z1: [count][L][n])
 __global__ void add_z1_kernel(uint64_t* __restrict__ out, const uint64_t* __restrict__ z,
                               const uint64_t* __restrict__ mods, int n, int L) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -388,7 +389,7 @@ __global__ void add_z1_kernel(uint64_t* __restrict__ out, const uint64_t* __rest
     const int r = blockIdx.y;
     const size_t ct = blockIdx.z, Ln = (size_t)L * n, o = (size_t)r * n + x;
     uint64_t* d = out + ct * 2 * Ln + Ln + o;
-    *d = add_mod(*d, z[ct * 3 * Ln + 2 * Ln + o], mods[r]);
+    *d = add_mod(*d, z[ct * Ln + o], mods[r]);
 }
 
 // Calls f(integral_constant<int, CQ>) with the digit capacity over Q for L primes.
@@ -428,15 +429,16 @@ __global__ void one_minus_kernel(uint64_t* ct, const uint64_t* mods, const uint6
 
 // Products of `count` pairs at the full level, all in one pass per step: out[i] =
 // relin(round(p/Q (a[i] x b[i]))). a, b, out: [count][2][L][n] coefficient domain (out
-// may alias a or b; b == a squares). Every launch covers the whole batch, and the
-// relinearisations are one key-switching pass whose jobs share the key.
-static hc_status mul_ct(Ctx& c, Lane& l, KsScratch& ks, const uint64_t* rk, const uint64_t* a, const uint64_t* b,
-                        uint64_t* out, int count, uint64_t* const* buf, hipStream_t st) {
+// may alias a or b; b == a squares). a_scratch: a may be overwritten (it is then
+// transformed in place instead of copied). Every launch covers the whole batch, and the
+// relinearisations are one key-switching pass whose jobs share the key and write out.
+static hc_status mul_ct(Ctx& c, Lane& l, KsScratch& ks, const uint64_t* rk, uint64_t* a, const uint64_t* b,
+                        uint64_t* out, int count, bool a_scratch, uint64_t* const* buf, hipStream_t st) {
     const size_t n = c.n;
     const int L = c.L, nb = c.nb, nq = c.nq;
     const size_t QW = (size_t)L * n, BW = (size_t)nb * n;
-    uint64_t *aN = buf[0], *bN = buf[1], *aB = buf[2], *bB = buf[3], *eQ = buf[4], *eB = buf[5], *z = buf[6],
-             *ko = buf[7];
+    uint64_t *aN = a_scratch ? a : buf[0], *bN = buf[1], *aB = buf[2], *bB = buf[3], *eQ = buf[4], *eB = buf[5],
+             *z = buf[6];
     const MultTab tb = mult_tab(c);
     const bool sq = a == b;
     const unsigned gx = (unsigned)((n + 255) / 256), cnt = (unsigned)count;
@@ -447,7 +449,7 @@ static hc_status mul_ct(Ctx& c, Lane& l, KsScratch& ks, const uint64_t* rk, cons
         if (!sq) hipLaunchKernelGGL(bext_kernel<C>, dim3(gx, 1, 2 * cnt), dim3(256), 0, st, bB, b, tb, (int)n, L, nb);
     });
     // 2. NTT domain over Q and B, the tensor, back
-    HC_CHECK(hipMemcpyAsync(aN, a, sizeof(uint64_t) * 2 * QW * count, hipMemcpyDeviceToDevice, st));
+    if (!a_scratch) HC_CHECK(hipMemcpyAsync(aN, a, sizeof(uint64_t) * 2 * QW * count, hipMemcpyDeviceToDevice, st));
     ntt64(c, aN, QW, 2 * count, 0, L, false, st);
     ntt64(c, aB, BW, 2 * count, nq, nb, false, st);
     if (!sq) {
@@ -461,21 +463,22 @@ static hc_status mul_ct(Ctx& c, Lane& l, KsScratch& ks, const uint64_t* rk, cons
                        c.d_r2, (int)n, nb, nq);
     ntt64(c, eQ, QW, 3 * count, 0, L, true, st);
     ntt64(c, eB, BW, 3 * count, nq, nb, true, st);
-    // 3. z = round(p e / Q), stored (z0, z2, z1) so that (z0, z2) is a ciphertext to key-switch
+    // 3. z = round(p e / Q): (z0, z2) in z, a ciphertext to key-switch; z1 apart (buf[0],
+    //    free once the tensor is formed, holds it). a and b are not read after the tensor.
+    uint64_t* z1 = buf[0];
     with_cap(L, [&](auto cap) {
         constexpr int C = decltype(cap)::value;
-        hipLaunchKernelGGL(scale_round_kernel<C>, dim3(gx, 1, 3 * cnt), dim3(256), 0, st, z, eQ, eB, tb, (int)n, L, nb,
-                           0, 2, 1);
+        hipLaunchKernelGGL(scale_round_kernel<C>, dim3(gx, 1, 3 * cnt), dim3(256), 0, st, z, z1, eQ, eB, tb, (int)n,
+                           L, nb);
     });
-    // 4. relinearisation: (z0 + KS(z2)_0, z1 + KS(z2)_1)
-    ntt64(c, z, QW, 3 * count, 0, L, false, st);
+    // 4. relinearisation: (z0 + KS(z2)_0, z1 + KS(z2)_1), z1 added in the coefficient domain
+    ntt64(c, z, QW, 2 * count, 0, L, false, st);
     std::vector<KsJob> jobs;
-    for (int i = 0; i < count; i++) jobs.push_back(KsJob{z + (size_t)i * 3 * QW, ko + (size_t)i * 2 * QW, rk, 1u, 0});
+    for (int i = 0; i < count; i++) jobs.push_back(KsJob{z + (size_t)i * 2 * QW, out + (size_t)i * 2 * QW, rk, 1u, 0});
     hc_status s = ks_run(c, l, ks, jobs, nullptr, L, st);
     if (s != HC_OK) return s;
-    hipLaunchKernelGGL(add_z1_kernel, dim3(gx, L, cnt), dim3(256), 0, st, ko, z, c.d_mods, (int)n, L);
-    ntt64(c, ko, QW, 2 * count, 0, L, true, st);
-    HC_CHECK(hipMemcpyAsync(out, ko, sizeof(uint64_t) * 2 * QW * count, hipMemcpyDeviceToDevice, st));
+    ntt64(c, out, QW, 2 * count, 0, L, true, st);
+    hipLaunchKernelGGL(add_z1_kernel, dim3(gx, L, cnt), dim3(256), 0, st, out, z1, c.d_mods, (int)n, L);
     return HC_OK;
 }
 
@@ -483,38 +486,38 @@ static hc_status mul_ct(Ctx& c, Lane& l, KsScratch& ks, const uint64_t* rk, cons
 // per ciphertext at 24 primes and ring 2^16).
 constexpr int MUL_BATCH = 16;
 
-// Workspace of products for up to `count` ciphertexts: 8 buffers, two spare ciphertext
+// Workspace of products for up to `count` ciphertexts: 7 buffers, two spare ciphertext
 // arrays and key-switching scratch for `count` jobs at level L.
 struct MulWs {
     KsScratch ks;
-    uint64_t* buf[8];
+    uint64_t* buf[7];
     uint64_t* t0;  // [count][2][L][n] spare ciphertexts
     uint64_t* t1;
 };
 
-static void mul_ws_sizes(const Ctx& c, int count, size_t (&sizes)[10]) {
+static void mul_ws_sizes(const Ctx& c, int count, size_t (&sizes)[9]) {
     const size_t QW = (size_t)c.L * c.n, BW = (size_t)c.nb * c.n, k = (size_t)count;
-    const size_t sz[10] = {2 * QW, 2 * QW, 2 * BW, 2 * BW, 3 * QW, 3 * BW, 3 * QW, 2 * QW, 2 * QW, 2 * QW};
-    for (int i = 0; i < 10; i++) sizes[i] = k * sz[i];
+    const size_t sz[9] = {2 * QW, 2 * QW, 2 * BW, 2 * BW, 3 * QW, 3 * BW, 2 * QW, 2 * QW, 2 * QW};
+    for (int i = 0; i < 9; i++) sizes[i] = k * sz[i];
 }
 
 static size_t mul_ws_bytes(const Ctx& c, int count) {
-    size_t sizes[10], b = 0;
+    size_t sizes[9], b = 0;
     mul_ws_sizes(c, count, sizes);
     for (size_t v : sizes) b += 8 * v + 256;
     return b + ks_scratch_bytes(c, c.L, count) + 16 * 256;
 }
 
 static hc_status mul_ws(Ctx& c, Arena& a, int count, MulWs& w) {
-    size_t sizes[10];
+    size_t sizes[9];
     mul_ws_sizes(c, count, sizes);
     w.ks = ks_scratch(c, a, c.L, count);
-    for (int i = 0; i < 8; i++) {
+    for (int i = 0; i < 7; i++) {
         w.buf[i] = a.take<uint64_t>(sizes[i]);
         if (!w.buf[i]) return HC_ENOMEM;
     }
-    w.t0 = a.take<uint64_t>(sizes[8]);
-    w.t1 = a.take<uint64_t>(sizes[9]);
+    w.t0 = a.take<uint64_t>(sizes[7]);
+    w.t1 = a.take<uint64_t>(sizes[8]);
     if (!w.t0 || !w.t1 || !w.ks.tmpC) return HC_ENOMEM;
     return HC_OK;
 }
@@ -530,10 +533,10 @@ static hc_status power_ct(Ctx& c, Lane& l, MulWs& w, const uint64_t* rk, const u
     HC_CHECK(hipMemcpyAsync(w.t1, in, sizeof(uint64_t) * CW, hipMemcpyDeviceToDevice, st));
     HC_CHECK(hipMemcpyAsync(w.t0, in, sizeof(uint64_t) * CW, hipMemcpyDeviceToDevice, st));
     for (int bit = top - 1; bit >= 0; bit--) {
-        hc_status s = mul_ct(c, l, w.ks, rk, w.t0, w.t0, w.t0, count, w.buf, st);
+        hc_status s = mul_ct(c, l, w.ks, rk, w.t0, w.t0, w.t0, count, true, w.buf, st);
         if (s != HC_OK) return s;
         if ((e >> bit) & 1u) {
-            s = mul_ct(c, l, w.ks, rk, w.t0, w.t1, w.t0, count, w.buf, st);
+            s = mul_ct(c, l, w.ks, rk, w.t0, w.t1, w.t0, count, true, w.buf, st);
             if (s != HC_OK) return s;
         }
     }
@@ -588,7 +591,8 @@ extern "C" hc_status hc_mul(hc_context* cp, const hc_gk* rk, const uint64_t* ct_
     if (c.lane.ws.reserve(mul_ws_bytes(c, 1)) != HC_OK) return HC_ENOMEM;
     MulWs w;
     if ((s = mul_ws(c, c.lane.ws, 1, w)) != HC_OK) return s;
-    if ((s = mul_ct(c, c.lane, w.ks, key, ct_a, ct_b, ct_out, 1, w.buf, st)) != HC_OK) return s;
+    if ((s = mul_ct(c, c.lane, w.ks, key, const_cast<uint64_t*>(ct_a), ct_b, ct_out, 1, false, w.buf, st)) != HC_OK)
+        return s;
     HC_CHECK(hipGetLastError());
     HC_CHECK(hipStreamSynchronize(st));
     return HC_OK;

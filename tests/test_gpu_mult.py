@@ -49,6 +49,10 @@ def test_product_and_powers_bit_identical(keys):
     got = to_host(ctx.mul(rk, ca, cb))
     assert np.array_equal(got, mult.mul(pr, oa, ob, ork).stack())
     assert np.array_equal(ctx.decrypt(sk, got), a * b % pr.p)
+    # the output may alias either input
+    for alias in (0, 1):
+        x, y = ca.clone(), cb.clone()
+        assert np.array_equal(to_host(ctx.mul(rk, x, y, out=(x, y)[alias])), got), alias
     for e in (2, 3, 6, pr.p - 1):
         got = to_host(ctx.power(rk, ca, e))
         assert np.array_equal(got, mult.power(pr, oa, e, ork).stack()), e
