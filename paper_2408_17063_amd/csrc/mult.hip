@@ -198,38 +198,44 @@ hc_status build_mult_tables(Ctx& c) {
 
 // MRC digits in place: t[i] (residues over the M primes of mods) become the digits
 // y_i < m_i. Step k takes digit k off every later residue and divides by m_k; the rows
-// of a step are independent, updated in chunks of 8 (chunks wholly at or before k are
-// skipped, and only the chunk holding k needs a select). Digit k lies below 2 m_i (every
+// of a step are independent, updated in chunks of 4 (chunks wholly at or before k are
+// skipped, and only the chunk holding k needs selects). Digit k lies below 2 m_i (every
 // prime of a basis lies in [2^(t-1), 2^t) for one t), so t_i + 2 m_i - y_k lies in
-// (0, 3 m_i) and one Shoup product by m_k^-1 (inv: [k][i] pairs) brings it to [0, 2 m_i).
+// (0, 4 m_i) for a row kept lazily in [0, 2 m_i), and one Shoup product by m_k^-1 (inv:
+// [k][i] pairs) brings it back to [0, 2 m_i). A row is reduced to [0, m_i) when it
+// becomes a digit (for the next step) and once more at the end.
 template <int M>
 __device__ __forceinline__ void mrc(uint64_t (&t)[M], const uint64_t* __restrict__ mods,
                                     const uint64_t* __restrict__ inv) {
+    constexpr int W = 4;
+    uint64_t yk = t[0];
     for (int k = 0; k + 1 < M; k++) {
-        uint64_t yk = t[0];
-        #pragma unroll
-        for (int i = 1; i < M; i++) yk = i == k ? t[i] : yk;
         const uint64_t* ik = inv + (size_t)2 * k * M;
+        uint64_t next = 0;
         #pragma unroll
-        for (int c = 0; c < M; c += 8) {
-            constexpr int W = 8;
+        for (int c = 0; c < M; c += W) {
             const int ce = c + W < M ? c + W : M;
             if (c > k) {
                 #pragma unroll
                 for (int i = c; i < ce; i++) {
                     const uint64_t q = mods[i];
-                    t[i] = csub(shoup_lazy(t[i] + 2 * q - yk, ik[2 * i], ik[2 * i + 1], q), q);
+                    t[i] = shoup_lazy(t[i] + 2 * q - yk, ik[2 * i], ik[2 * i + 1], q);
                 }
+                next = c == k + 1 ? t[c] : next;
             } else if (ce > k + 1) {
                 #pragma unroll
                 for (int i = c; i < ce; i++) {
                     const uint64_t q = mods[i];
-                    const uint64_t v = csub(shoup_lazy(t[i] + 2 * q - yk, ik[2 * i], ik[2 * i + 1], q), q);
+                    const uint64_t v = shoup_lazy(t[i] + 2 * q - yk, ik[2 * i], ik[2 * i + 1], q);
                     t[i] = i > k ? v : t[i];
+                    next = i == k + 1 ? v : next;
                 }
             }
         }
+        yk = csub(next, mods[k + 1]);
     }
+    #pragma unroll
+    for (int i = 1; i < M; i++) t[i] = csub(t[i], mods[i]);
 }
 
 // y > h for digit vectors (most significant digit last)
