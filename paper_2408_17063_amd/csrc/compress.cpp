@@ -272,13 +272,10 @@ hc_status compress_many(Ctx& c, Lane& l, const hc_gk* gk, const hc_db* db, std::
         // ciphertext i times every column's plaintext i, into slot (1 + col) n_ct + i
         std::vector<MaskJob> mj;
         for (auto& q : qs) {
-            HC_CHECK(hipMemcpyAsync(q.ctf, q.ct_v, sizeof(uint64_t) * q.CWF * q.pl.n_ct, hipMemcpyDeviceToDevice, st));
-            ntt64(c, q.ctf, (size_t)c.L * n, 2 * (int)q.pl.n_ct, 0, c.L, false, st);
+            ntt64(c, q.ctf, (size_t)c.L * n, 2 * (int)q.pl.n_ct, 0, c.L, false, st, q.ct_v);
             if (q.ct_d) {  // the value vector given (generic Comp): no Mask
                 uint64_t* dst = q.ctf + (size_t)q.pl.n_ct * q.CWF;
-                HC_CHECK(hipMemcpyAsync(dst, q.ct_d, sizeof(uint64_t) * q.CWF * q.pl.n_ct, hipMemcpyDeviceToDevice,
-                                        st));
-                ntt64(c, dst, (size_t)c.L * n, 2 * (int)q.pl.n_ct, 0, c.L, false, st);
+                ntt64(c, dst, (size_t)c.L * n, 2 * (int)q.pl.n_ct, 0, c.L, false, st, q.ct_d);
                 continue;
             }
             if (q.pl.ncol > 0)

@@ -257,9 +257,10 @@ inline void hc_launch(void (*kernel)(Formals...), dim3 grid, dim3 block, uint32_
 
 // ------------------------------------------------------------------ NTT (ntt.hip)
 // data: `count` polynomials spaced poly_stride elements apart; data points at
-// the first transformed row, whose prime index is limb_first.
+// the first transformed row, whose prime index is limb_first. src (optional): the input,
+// laid out as data and left unchanged; the result goes to data (no copy first).
 void ntt64(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb_first, int nlimbs,
-           bool inverse, hipStream_t stream);
+           bool inverse, hipStream_t stream, const uint64_t* src = nullptr);
 // mod-p transforms of `count` contiguous length-n rows.
 void ntt32(const Ctx& c, uint32_t* data, int count, bool inverse, hipStream_t stream);
 // builds d_tw2 from d_tw (context creation; synchronises the device)

@@ -710,8 +710,7 @@ static hc_status rotate_common(hc_context* cp, const hc_gk* gk, const uint32_t* 
         if (!key) return HC_ENOKEY;
         jobs[i] = KsJob{inN, outN + i * Ln2, key, elts[i], 0};
     }
-    HC_CHECK(hipMemcpyAsync(inN, ct_in, sizeof(uint64_t) * Ln2, hipMemcpyDeviceToDevice, st));
-    ntt64(c, inN, (size_t)Lc * c.n, 2, 0, Lc, false, st);
+    ntt64(c, inN, (size_t)Lc * c.n, 2, 0, Lc, false, st, ct_in);
     std::vector<const uint64_t*> srcs{inN};
     hc_status stt = ks_run(c, c.lane, s, jobs, hoisted ? &srcs : nullptr, Lc, st);
     if (stt != HC_OK) return stt;
@@ -755,8 +754,7 @@ extern "C" hc_status hc_rotate_level_noalloc(hc_context* cp, const hc_gk* gk, ui
     KsScratch s = ks_scratch(c, a, Lc, 1);
     if (!inN || !s.tmpC || !s.X || !s.T || !s.conv) return HC_ESCRATCH;
     stage_reset(c.lane, st);  // job tables go through the context's pinned staging area
-    HC_CHECK(hipMemcpyAsync(inN, ct_in, sizeof(uint64_t) * Ln2, hipMemcpyDeviceToDevice, st));
-    ntt64(c, inN, (size_t)Lc * c.n, 2, 0, Lc, false, st);
+    ntt64(c, inN, (size_t)Lc * c.n, 2, 0, Lc, false, st, ct_in);
     // the result goes to the caller's output in the NTT domain and is transformed there
     std::vector<KsJob> jobs{KsJob{inN, ct_out, key, element, 0}};
     hc_status stt = ks_run(c, c.lane, s, jobs, nullptr, Lc, st);
@@ -806,8 +804,7 @@ extern "C" hc_status hc_mul_plain(hc_context* cp, const uint64_t* ct_in, const u
     if (!pt || !tmp) return HC_ENOMEM;
     hc_status s = encode_plain(c, pt, slots, 1, true, st);
     if (s != HC_OK) return s;
-    HC_CHECK(hipMemcpyAsync(tmp, ct_in, sizeof(uint64_t) * 2 * Ln, hipMemcpyDeviceToDevice, st));
-    ntt64(c, tmp, Ln, 2, 0, c.L, false, st);
+    ntt64(c, tmp, Ln, 2, 0, c.L, false, st, ct_in);
     k_mul_plain(c, tmp, tmp, pt, c.L, st);
     ntt64(c, tmp, Ln, 2, 0, c.L, true, st);
     HC_CHECK(hipMemcpyAsync(ct_out, tmp, sizeof(uint64_t) * 2 * Ln, hipMemcpyDeviceToDevice, st));

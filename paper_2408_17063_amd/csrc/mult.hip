@@ -436,7 +436,7 @@ __global__ void one_minus_kernel(uint64_t* ct, const uint64_t* mods, const uint6
 // Products of `count` pairs at the full level, all in one pass per step: out[i] =
 // relin(round(p/Q (a[i] x b[i]))). a, b, out: [count][2][L][n] coefficient domain (out
 // may alias a or b; b == a squares). a_scratch: a may be overwritten (it is then
-// transformed in place instead of copied). Every launch covers the whole batch, and the
+// transformed in place; otherwise the transform reads a and writes the workspace). Every launch covers the whole batch, and the
 // relinearisations are one key-switching pass whose jobs share the key and write out.
 static hc_status mul_ct(Ctx& c, Lane& l, KsScratch& ks, const uint64_t* rk, uint64_t* a, const uint64_t* b,
                         uint64_t* out, int count, bool a_scratch, uint64_t* const* buf, hipStream_t st) {
@@ -455,12 +455,10 @@ static hc_status mul_ct(Ctx& c, Lane& l, KsScratch& ks, const uint64_t* rk, uint
         if (!sq) hipLaunchKernelGGL(bext_kernel<C>, dim3(gx, 1, 2 * cnt), dim3(256), 0, st, bB, b, tb, (int)n, L, nb);
     });
     // 2. NTT domain over Q and B, the tensor, back
-    if (!a_scratch) HC_CHECK(hipMemcpyAsync(aN, a, sizeof(uint64_t) * 2 * QW * count, hipMemcpyDeviceToDevice, st));
-    ntt64(c, aN, QW, 2 * count, 0, L, false, st);
+    ntt64(c, aN, QW, 2 * count, 0, L, false, st, a_scratch ? nullptr : a);
     ntt64(c, aB, BW, 2 * count, nq, nb, false, st);
     if (!sq) {
-        HC_CHECK(hipMemcpyAsync(bN, b, sizeof(uint64_t) * 2 * QW * count, hipMemcpyDeviceToDevice, st));
-        ntt64(c, bN, QW, 2 * count, 0, L, false, st);
+        ntt64(c, bN, QW, 2 * count, 0, L, false, st, b);
         ntt64(c, bB, BW, 2 * count, nq, nb, false, st);
     }
     hipLaunchKernelGGL(tensor_kernel, dim3(gx, L, cnt), dim3(256), 0, st, eQ, aN, sq ? aN : bN, c.d_mods, c.d_qinv,

@@ -349,10 +349,12 @@ struct Tile {
 };
 
 // One tile of one pass: tile bx of polynomial by, row (limb) bz; ntiles tiles per row.
+// src (nullptr: in place): the pass reads its input there, at data's offsets, and
+// writes data.
 template <typename T, bool INV, int LOGN, int S, int BLO, int ST0, bool LAST>
 __device__ __forceinline__ void ntt_tile(T* __restrict__ data, size_t poly_stride, int limb_first,
                                          const NttTab<T>& tab, T* lds, uint32_t bx, uint32_t by, uint32_t bz,
-                                         uint32_t ntiles) {
+                                         uint32_t ntiles, const T* __restrict__ src = nullptr) {
     typedef Tile<T, INV, LOGN, S, BLO, ST0> TL;
     constexpr int THREADS = TL::THREADS;  // the launch's block size
     const uint32_t tid = threadIdx.x;
@@ -362,6 +364,7 @@ __device__ __forceinline__ void ntt_tile(T* __restrict__ data, size_t poly_strid
     const T q = tab.mods[prime];
     const T* tw = tab.base + ((size_t)prime * 2 + (INV ? 1 : 0)) * 2 * TL::N;
     T* a = data + (size_t)by * poly_stride + (size_t)row * TL::N;
+    const T* ain = src ? src + (a - data) : a;
     const uint32_t sp0 = bx * TL::P;
     const T* ni = tab.ninv + 4 * prime;
     constexpr bool FOLD = INV && LAST;
@@ -395,7 +398,7 @@ __device__ __forceinline__ void ntt_tile(T* __restrict__ data, size_t poly_strid
             constexpr int P2 = TL::LOGP + (INV ? R : 0);  // second round
             T x[NTT_EPT];
             #pragma unroll
-            for (int v = 0; v < NTT_EPT; v++) x[v] = a[TL::gidx(insert_bits(tid, v, P1, R), sp0)];
+            for (int v = 0; v < NTT_EPT; v++) x[v] = ain[TL::gidx(insert_bits(tid, v, P1, R), sp0)];
             TL::template butterflies<R, P1 - TL::LOGP, 0, NR>(x, tid, 0, sp0, tw, nullptr, q);
             #pragma unroll
             for (int v = 0; v < NTT_EPT; v++) lds[insert_bits(tid, v, P1, R)] = x[v];
@@ -420,7 +423,7 @@ __device__ __forceinline__ void ntt_tile(T* __restrict__ data, size_t poly_strid
             T x[NTT_EPT];
             if constexpr (!INV) {
                 #pragma unroll
-                for (int v = 0; v < NTT_EPT; v++) x[v] = a[TL::gidx(insert_bits(gh, v, PH, R), sp0)];
+                for (int v = 0; v < NTT_EPT; v++) x[v] = ain[TL::gidx(insert_bits(gh, v, PH, R), sp0)];
                 TL::template butterflies<R, R, 0, NR>(x, gh, 0, sp0, tw, tw2, q);
                 #pragma unroll
                 for (int v = 0; v < NTT_EPT; v++) lds[TL::lpos(insert_bits(gh, v, PH, R))] = x[v];
@@ -432,7 +435,7 @@ __device__ __forceinline__ void ntt_tile(T* __restrict__ data, size_t poly_strid
                 for (int i = 0; i < NTT_EPT; i++) {
                     const uint32_t f = tid + i * THREADS;
                     const uint32_t e = ((f & ((1u << S) - 1u)) << TL::LOGP) | (f >> S);
-                    lds[TL::lpos(e)] = a[TL::gidx(e, sp0)];
+                    lds[TL::lpos(e)] = ain[TL::gidx(e, sp0)];
                 }
                 __syncthreads();
                 TL::template round<R, 0, 0>(lds, sp0, tw, tw2, q);
@@ -453,7 +456,7 @@ __device__ __forceinline__ void ntt_tile(T* __restrict__ data, size_t poly_strid
                 if (BLO == 0) { spl = f >> S; k = f & ((1u << S) - 1u); }
                 else { k = f >> TL::LOGP; spl = f & (TL::P - 1); }
                 const uint32_t e = (k << TL::LOGP) | spl;
-                lds[TL::lpos(e)] = a[TL::gidx(e, sp0)];
+                lds[TL::lpos(e)] = ain[TL::gidx(e, sp0)];
             }
             __syncthreads();
             TL::template rounds<0, NR, FOLD>(lds, sp0, tw, tw2, q, ni);
@@ -644,11 +647,11 @@ void k_moddown_fused(const Ctx& c, uint64_t* conv, const uint64_t* T, int M, int
 // registers must allow (1 = no constraint).
 template <typename T, bool INV, int LOGN, int S, int BLO, int ST0, bool LAST, int WPE>
 __global__ void __launch_bounds__(NTT_THREADS) __attribute__((amdgpu_waves_per_eu(WPE)))
-ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab<T> tab) {
+ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab<T> tab, const T* __restrict__ src) {
     typedef Tile<T, INV, LOGN, S, BLO, ST0> TL;
     __shared__ T lds[TL::LDS_WORDS];
     ntt_tile<T, INV, LOGN, S, BLO, ST0, LAST>(data, poly_stride, limb_first, tab, lds, blockIdx.x, blockIdx.y,
-                                              blockIdx.z, gridDim.x);
+                                              blockIdx.z, gridDim.x, src);
 }
 
 // The same pass as a persistent grid: a fixed number of blocks (the device's resident
@@ -661,21 +664,22 @@ ntt_tile_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab
 template <typename T, bool INV, int LOGN, int S, int BLO, int ST0, bool LAST, int WPE>
 __global__ void __launch_bounds__(NTT_THREADS) __attribute__((amdgpu_waves_per_eu(WPE)))
 ntt_tile_persistent_kernel(T* __restrict__ data, size_t poly_stride, int limb_first, NttTab<T> tab,
-                           uint32_t ntiles, uint32_t count, uint32_t items) {
+                           uint32_t ntiles, uint32_t count, uint32_t items, const T* __restrict__ src) {
     typedef Tile<T, INV, LOGN, S, BLO, ST0> TL;
     __shared__ T lds[TL::LDS_WORDS];
     for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
         if (it != blockIdx.x) __syncthreads();  // the previous item's LDS reads are done
         const uint32_t bx = it % ntiles, rest = it / ntiles;
         ntt_tile<T, INV, LOGN, S, BLO, ST0, LAST>(data, poly_stride, limb_first, tab, lds, bx, rest % count,
-                                                  rest / count, ntiles);
+                                                  rest / count, ntiles, src);
     }
 }
 
-// Launch one pass; `ops` butterflies and `bytes` moved for the timing record.
+// Launch one pass; `ops` butterflies and `bytes` moved for the timing record. src: as
+// ntt_tile.
 template <typename T, bool INV, int LOGN, int S, int BLO, int ST0, bool LAST>
 static void pass(const Ctx& c, int kind, T* data, size_t stride, int count, int lf, int nl,
-                 NttTab<T> tab, hipStream_t st) {
+                 NttTab<T> tab, hipStream_t st, const T* src = nullptr) {
     constexpr int TLOG = LOGN < TILE_LOG ? LOGN : TILE_LOG;
     constexpr int THREADS = (1 << TLOG) / NTT_EPT;
     static_assert(THREADS <= NTT_THREADS, "tile");
@@ -692,12 +696,12 @@ static void pass(const Ctx& c, int kind, T* data, size_t stride, int count, int 
         if constexpr (TUNED) {
             if (var == 1) {
                 hc_launch((ntt_tile_kernel<T, INV, LOGN, S, BLO, ST0, LAST, 3>), grid, dim3(THREADS), 0, st,
-                                   data, stride, lf, tab);
+                                   data, stride, lf, tab, src);
                 return;
             }
             if (var == 2) {
                 hc_launch((ntt_tile_kernel<T, INV, LOGN, S, BLO, ST0, LAST, 5>), grid, dim3(THREADS), 0, st,
-                                   data, stride, lf, tab);
+                                   data, stride, lf, tab, src);
                 return;
             }
             if (var == 3) {
@@ -705,12 +709,12 @@ static void pass(const Ctx& c, int kind, T* data, size_t stride, int count, int 
                 const uint32_t cap = (uint32_t)c.cus * 4;  // four 4-wave blocks per CU (4 waves per SIMD)
                 hc_launch((ntt_tile_persistent_kernel<T, INV, LOGN, S, BLO, ST0, LAST, 4>),
                                    dim3(items < cap ? items : cap), dim3(THREADS), 0, st, data, stride, lf, tab,
-                                   grid.x, (uint32_t)count, items);
+                                   grid.x, (uint32_t)count, items, src);
                 return;
             }
         }
         hc_launch((ntt_tile_kernel<T, INV, LOGN, S, BLO, ST0, LAST, TUNED ? 4 : 1>), grid, dim3(THREADS), 0,
-                           st, data, stride, lf, tab);
+                           st, data, stride, lf, tab, src);
     };
     if (kind >= 0) {
         TimeScope ts(c, kind, st, bytes, ops);
@@ -720,18 +724,19 @@ static void pass(const Ctx& c, int kind, T* data, size_t stride, int count, int 
     }
 }
 
+// src (nullptr: in place): the first pass reads the input there, at data's offsets.
 template <typename T, bool INV, int LOGN>
 static void run_logn(const Ctx& c, int kind, T* data, size_t stride, int count, int lf, int nl,
-                     NttTab<T> tab, hipStream_t st) {
+                     NttTab<T> tab, hipStream_t st, const T* src) {
     if constexpr (LOGN <= TILE_LOG) {
-        pass<T, INV, LOGN, LOGN, 0, 0, true>(c, kind, data, stride, count, lf, nl, tab, st);
+        pass<T, INV, LOGN, LOGN, 0, 0, true>(c, kind, data, stride, count, lf, nl, tab, st, src);
     } else {
         constexpr int SL = 8, SH = LOGN - 8;
         if (!INV) {
-            pass<T, false, LOGN, SH, SL, 0, false>(c, kind, data, stride, count, lf, nl, tab, st);
+            pass<T, false, LOGN, SH, SL, 0, false>(c, kind, data, stride, count, lf, nl, tab, st, src);
             pass<T, false, LOGN, SL, 0, SH, true>(c, kind, data, stride, count, lf, nl, tab, st);
         } else {
-            pass<T, true, LOGN, SL, 0, 0, false>(c, kind, data, stride, count, lf, nl, tab, st);
+            pass<T, true, LOGN, SL, 0, 0, false>(c, kind, data, stride, count, lf, nl, tab, st, src);
             pass<T, true, LOGN, SH, SL, SL, true>(c, kind, data, stride, count, lf, nl, tab, st);
         }
     }
@@ -739,15 +744,15 @@ static void run_logn(const Ctx& c, int kind, T* data, size_t stride, int count, 
 
 template <typename T, bool INV>
 static void run_ntt(const Ctx& c, int kind, T* data, size_t stride, int count, int lf, int nl,
-                    NttTab<T> tab, hipStream_t st) {
+                    NttTab<T> tab, hipStream_t st, const T* src = nullptr) {
     switch (c.logn) {
-        case 10: run_logn<T, INV, 10>(c, kind, data, stride, count, lf, nl, tab, st); break;
-        case 11: run_logn<T, INV, 11>(c, kind, data, stride, count, lf, nl, tab, st); break;
-        case 12: run_logn<T, INV, 12>(c, kind, data, stride, count, lf, nl, tab, st); break;
-        case 13: run_logn<T, INV, 13>(c, kind, data, stride, count, lf, nl, tab, st); break;
-        case 14: run_logn<T, INV, 14>(c, kind, data, stride, count, lf, nl, tab, st); break;
-        case 15: run_logn<T, INV, 15>(c, kind, data, stride, count, lf, nl, tab, st); break;
-        case 16: run_logn<T, INV, 16>(c, kind, data, stride, count, lf, nl, tab, st); break;
+        case 10: run_logn<T, INV, 10>(c, kind, data, stride, count, lf, nl, tab, st, src); break;
+        case 11: run_logn<T, INV, 11>(c, kind, data, stride, count, lf, nl, tab, st, src); break;
+        case 12: run_logn<T, INV, 12>(c, kind, data, stride, count, lf, nl, tab, st, src); break;
+        case 13: run_logn<T, INV, 13>(c, kind, data, stride, count, lf, nl, tab, st, src); break;
+        case 14: run_logn<T, INV, 14>(c, kind, data, stride, count, lf, nl, tab, st, src); break;
+        case 15: run_logn<T, INV, 15>(c, kind, data, stride, count, lf, nl, tab, st, src); break;
+        case 16: run_logn<T, INV, 16>(c, kind, data, stride, count, lf, nl, tab, st, src); break;
         default: break;
     }
 }
@@ -792,11 +797,12 @@ hc_status ntt_build_tw2(Ctx& c) {
 }
 
 void ntt64(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb_first, int nlimbs,
-           bool inverse, hipStream_t stream) {
+           bool inverse, hipStream_t stream, const uint64_t* src) {
     if (count <= 0 || nlimbs <= 0) return;
     NttTab<uint64_t> tab{c.d_tw, c.d_ninv, c.d_mods, c.d_tw2};
-    if (inverse) run_ntt<uint64_t, true>(c, HC_KT_NTT_INV, data, poly_stride, count, limb_first, nlimbs, tab, stream);
-    else run_ntt<uint64_t, false>(c, HC_KT_NTT_FWD, data, poly_stride, count, limb_first, nlimbs, tab, stream);
+    if (inverse)
+        run_ntt<uint64_t, true>(c, HC_KT_NTT_INV, data, poly_stride, count, limb_first, nlimbs, tab, stream, src);
+    else run_ntt<uint64_t, false>(c, HC_KT_NTT_FWD, data, poly_stride, count, limb_first, nlimbs, tab, stream, src);
 }
 
 // Only the low-bit pass of a two-pass ring: the inverse transform's first pass or the
