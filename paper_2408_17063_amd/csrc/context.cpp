@@ -27,6 +27,7 @@ hc_status Arena::reserve(size_t bytes) {
     release();
     hipError_t e = hipMalloc((void**)&base, bytes);
     if (e != hipSuccess) {
+        (void)hipGetLastError();  // an allocation that did not fit leaves no error behind
         base = nullptr;
         cap = 0;
         return HC_ENOMEM;

@@ -561,8 +561,12 @@ hc_status power_many(Ctx& c, const hc_gk* rk, const uint64_t* in, uint32_t n_ct,
     if (s != HC_OK) return s;
     if (!c.d_mult) return HC_EINVAL;
     stage_reset(c.lane, st);
-    const int batch = (int)std::min<uint32_t>(n_ct, MUL_BATCH);
-    if (c.lane.ws.reserve(mul_ws_bytes(c, batch)) != HC_OK) return HC_ENOMEM;
+    // the largest batch whose workspace fits (halved until it does)
+    int batch = (int)std::min<uint32_t>(n_ct, MUL_BATCH);
+    while (c.lane.ws.reserve(mul_ws_bytes(c, batch)) != HC_OK) {
+        if (batch == 1) return HC_ENOMEM;
+        batch = (batch + 1) / 2;
+    }
     MulWs w;
     if ((s = mul_ws(c, c.lane.ws, batch, w)) != HC_OK) return s;
     const size_t CW = 2 * (size_t)c.L * c.n;
