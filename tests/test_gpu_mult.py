@@ -79,6 +79,25 @@ def test_match_bit_identical(keys):
     assert np.array_equal(dec[:N], v) and not dec[N:].any()
 
 
+def test_match_over_more_ciphertexts_than_one_batch(keys):
+    """Match over 17 ciphertexts (the powers run as a batch of 16, then 1): every slot
+    decrypts to the predicate, and a ciphertext's words do not depend on its batch (the
+    first ciphertext equals a one-ciphertext Match of the same keys)."""
+    ctx, pr, sk, pk, rk, osk, opk, ork = keys
+    say("match over 17 ciphertexts")
+    N = 16 * pr.n + 300
+    kv, x, v = W.match_inputs(N, 40, pr.p, seed=3)
+    kdb = ctx.db_upload(kv.reshape(1, -1))
+    cx = ctx.encrypt(pk, np.full((2, pr.nh), x), W.seed32("enc", 75))
+    got = to_host(ctx.match(rk, kdb, cx, N))
+    assert got.shape[0] == 17
+    dec = np.concatenate([ctx.decrypt(sk, got[i]).reshape(-1) for i in range(got.shape[0])])
+    assert np.array_equal(dec[:N], v) and not dec[N:].any()
+    kdb1 = ctx.db_upload(kv[:pr.n].reshape(1, -1))
+    one = to_host(ctx.match(rk, kdb1, cx, pr.n))
+    assert np.array_equal(one[0], got[0])
+
+
 def test_generic_comp_bit_identical(keys):
     """Alg. 5 on ciphertexts of d alone, answer switched to one prime."""
     from oracle import bfv, compress as C, mult, slots
