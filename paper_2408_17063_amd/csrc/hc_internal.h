@@ -323,9 +323,10 @@ void kb_modup(const Ctx& c, uint64_t* X, const uint64_t* tmpC, int U, int Lc, bo
 void kb_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const KsJob* jobs, const KsRun* runs, int nruns, int M,
               int Lc, bool hoisted, hipStream_t st, int row0 = 0);
 // kb_final for the jobs of a pass in key runs, the ciphertext rows of T computed in place
-// from X and the keys (kb_inner need only have computed the special rows)
+// from X and the keys (kb_inner need only have computed the special rows). maxrun: the
+// longest run's job count (1 selects the kernel built for runs of one job).
 void kb_final_inner(const Ctx& c, const KsJob* jobs, const KsRun* runs, int nruns, const uint64_t* X,
-                    const uint64_t* conv, int M, int Lc, bool hoisted, hipStream_t st);
+                    const uint64_t* conv, int M, int Lc, bool hoisted, hipStream_t st, int maxrun);
 // conv [M][2][Lc][n] = Conv_{P->Q} of the special rows of T (coefficient domain)
 void kb_conv(const Ctx& c, uint64_t* conv, const uint64_t* T, int M, int Lc, hipStream_t st);
 // out_m = (sigma_k(c0_m) + (T0 - conv0) P^-1, (T1 - conv1) P^-1), NTT domain

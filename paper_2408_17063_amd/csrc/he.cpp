@@ -221,7 +221,7 @@ hc_status ks_run(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
     const size_t n = c.n;
     const int R = Lc + c.K;
     auto raise = [&](const KsJob* d, int U, bool permute) { ks_raise(c, s, d, U, Lc, permute, st); };
-    auto finish = [&](const KsJob* d, const KsRun* runs, int nruns, int M, bool hoisted) {
+    auto finish = [&](const KsJob* d, const KsRun* runs, int nruns, int M, bool hoisted, int maxrun) {
         // the key products' special rows inside the inverse transform's first pass (ring
         // 2^16) or by kb_inner, their ciphertext rows inside the final step
         if (conv_fused_ring(c)) {
@@ -233,7 +233,12 @@ hc_status ks_run(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
             kb_inner(c, s.T, s.X, d, runs, nruns, M, Lc, hoisted, st, Lc);
             moddown_conv(c, s.conv, s.T, M, Lc, st);
         }
-        kb_final_inner(c, d, runs, nruns, s.X, s.conv, M, Lc, hoisted, st);
+        kb_final_inner(c, d, runs, nruns, s.X, s.conv, M, Lc, hoisted, st, maxrun);
+    };
+    auto longest = [](const std::vector<KsRun>& runs) {
+        uint32_t m = 0;
+        for (const KsRun& r : runs) m = std::max(m, r.cnt);
+        return (int)m;
     };
     if (!srcs) {
         std::vector<KsJob> all(jobs);
@@ -248,7 +253,7 @@ hc_status ks_run(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
                             st))
                 return HC_ENOMEM;
             raise((const KsJob*)d, M, true);
-            finish((const KsJob*)d, (const KsRun*)dr, (int)runs.size(), M, false);
+            finish((const KsJob*)d, (const KsRun*)dr, (int)runs.size(), M, false, longest(runs));
         }
         return HC_OK;
     }
@@ -277,7 +282,7 @@ hc_status ks_run(Ctx& c, Lane& l, KsScratch& s, const std::vector<KsJob>& jobs,
                             st))
                 return HC_ENOMEM;
             if (first) raise((const KsJob*)ds, Uc, false);
-            if (M > 0) finish((const KsJob*)d, (const KsRun*)dr, (int)runs.size(), M, true);
+            if (M > 0) finish((const KsJob*)d, (const KsRun*)dr, (int)runs.size(), M, true, longest(runs));
         }
     }
     return HC_OK;

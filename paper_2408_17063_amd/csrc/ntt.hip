@@ -959,7 +959,9 @@ void ntt64_inverse_high_tab(const Ctx& c, uint64_t* data, size_t poly_stride, in
 // sum_j X[xidx_m][j][Lc + k][src(g)] key_m[j][comp][L + k][g] (src: sigma_{k_m}'s source
 // if hoisted), one REDC of the 128-bit sum -- the words kb_inner writes. Blocks of
 // consecutive jobs at one tile run on one XCD (the grid's x is the 16 tiles), so jobs
-// sharing a key read it through that XCD's L2.
+// sharing a key read it through that XCD's L2. MULTI: more than one digit (a separate
+// build, so the one-digit kernel keeps its registers).
+template <bool MULTI>
 __global__ void __launch_bounds__(NTT_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 ntt_inner_low_kernel(const KsJob* __restrict__ jobs, const uint64_t* __restrict__ X, uint64_t* __restrict__ T,
                      NttTab<uint64_t> tab, const uint64_t* __restrict__ qinv, int Lc, int K, int L, int nq, int dn,
@@ -982,7 +984,7 @@ ntt_inner_low_kernel(const KsJob* __restrict__ jobs, const uint64_t* __restrict_
     gl_cu64* kp = gl(jb.key) + (size_t)comp * keyrow + (size_t)prime * N;
     const uint64_t* xp = X + ((size_t)jb.xidx * dn * R + Lc + k) * N;
     const bool rot = hoisted && jb.k != 1;
-    if (dn == 1) {
+    if constexpr (!MULTI) {
         // one digit: the words of 8 elements are loaded together, then multiplied (a
         // loop over the digits between the loads would make each wait for the last)
         #pragma unroll
@@ -1004,15 +1006,38 @@ ntt_inner_low_kernel(const KsJob* __restrict__ jobs, const uint64_t* __restrict_
             }
         }
     } else {
+        // several digits: per quarter of the thread's elements, digit after digit, each
+        // digit's words of the 4 elements loaded together
+        gl_cu64* xg = gl(xp);
         #pragma unroll
-        for (int i = 0; i < NTT_EPT; i++) {
-            const uint32_t f = tid + i * TL::THREADS;
-            const uint32_t e = ((f & ((1u << S) - 1u)) << TL::LOGP) | (f >> S);
-            const uint32_t g = TL::gidx(e, sp0);
-            const uint32_t src = rot ? galois_src(g, jb.k, LOGN) : g;
-            u128p acc{0, 0};
-            for (int j = 0; j < dn; j++) add128(acc, mul128(xp[(size_t)j * R * N + src], kp[(size_t)j * 2 * keyrow + g]));
-            lds[TL::lpos(e)] = redc(acc, q, qi);
+        for (int h = 0; h < NTT_EPT; h += 4) {
+            uint32_t gg[4], ss[4];
+            #pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const uint32_t f = tid + (h + i) * TL::THREADS;
+                const uint32_t e = ((f & ((1u << S) - 1u)) << TL::LOGP) | (f >> S);
+                gg[i] = TL::gidx(e, sp0);
+                ss[i] = rot ? galois_src(gg[i], jb.k, LOGN) : gg[i];
+            }
+            u128p acc[4];
+            #pragma unroll
+            for (int i = 0; i < 4; i++) acc[i] = u128p{0, 0};
+            for (int j = 0; j < dn; j++) {
+                uint64_t xv[4], kv[4];
+                #pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    xv[i] = xg[(size_t)j * R * N + ss[i]];
+                    kv[i] = kp[(size_t)j * 2 * keyrow + gg[i]];
+                }
+                #pragma unroll
+                for (int i = 0; i < 4; i++) add128(acc[i], mul128(xv[i], kv[i]));
+            }
+            #pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const uint32_t f = tid + (h + i) * TL::THREADS;
+                const uint32_t e = ((f & ((1u << S) - 1u)) << TL::LOGP) | (f >> S);
+                lds[TL::lpos(e)] = redc(acc[i], q, qi);
+            }
         }
     }
     __syncthreads();
@@ -1036,8 +1061,13 @@ void ntt_inner_low(const Ctx& c, const KsJob* jobs, const uint64_t* X, uint64_t*
     const double n = c.n;
     // per job and special row: its digits and the key words of both components, the pass's output
     TimeScope ts(c, HC_KT_NTT_INV, st, 8.0 * n * M * c.K * (dn + 2.0 * dn + 2.0), 2.0 * M * c.K * (n / 2) * 8);
-    hc_launch(ntt_inner_low_kernel, dim3(1u << (16 - TILE_LOG), (unsigned)(2 * M), (unsigned)c.K),
-                       dim3(NTT_THREADS), 0, st, jobs, X, T, tab, c.d_qinv, Lc, c.K, c.L, c.nq, dn, hoisted ? 1 : 0);
+    const dim3 grid(1u << (16 - TILE_LOG), (unsigned)(2 * M), (unsigned)c.K);
+    if (dn == 1)
+        hc_launch(ntt_inner_low_kernel<false>, grid, dim3(NTT_THREADS), 0, st, jobs, X, T, tab, c.d_qinv, Lc, c.K,
+                  c.L, c.nq, dn, hoisted ? 1 : 0);
+    else
+        hc_launch(ntt_inner_low_kernel<true>, grid, dim3(NTT_THREADS), 0, st, jobs, X, T, tab, c.d_qinv, Lc, c.K,
+                  c.L, c.nq, dn, hoisted ? 1 : 0);
 }
 
 void ntt_take_c1_low(const Ctx& c, const KsJob* jobs, uint64_t* tmpC, uint64_t* X, int U, int Lc, hipStream_t st) {

@@ -254,6 +254,8 @@ void kb_inner(const Ctx& c, uint64_t* T, const uint64_t* X, const KsJob* jobs, c
 // runs (as kb_inner): T0, T1 = sum_j X[xidx][j] (rotated if hoisted) * key[j] (one REDC of
 // the 128-bit sums, the words kb_inner writes), then out as kb_final. kb_inner then only
 // computes the special rows, so the ciphertext rows of T never go through device memory.
+// RUN: the longest run of the launch (KS_RUN, or 1 when no two jobs share a key).
+template <int RUN>
 __global__ __launch_bounds__(EW_THREADS) void kb_final_inner_kernel(const KsJob* __restrict__ jobs, const KsRun* __restrict__ runs,
                                       const uint64_t* __restrict__ X, const uint64_t* __restrict__ conv,
                                       const uint64_t* __restrict__ mods, const uint64_t* __restrict__ qinv,
@@ -269,29 +271,29 @@ __global__ __launch_bounds__(EW_THREADS) void kb_final_inner_kernel(const KsJob*
     // The run's loads are issued together and unconditionally (a job slot past the run
     // reads the run's first job again and is not used): one conditional load per job
     // would wait for each before the next.
-    u128p a0[KS_RUN], a1[KS_RUN];
+    u128p a0[RUN], a1[RUN];
     #pragma unroll
-    for (int u = 0; u < KS_RUN; u++) { a0[u] = u128p{0, 0}; a1[u] = u128p{0, 0}; }
+    for (int u = 0; u < RUN; u++) { a0[u] = u128p{0, 0}; a1[u] = u128p{0, 0}; }
     for (int j = 0; j < dn; j++) {
         const uint64_t k0 = kp[(size_t)j * 2 * keyrow], k1 = kp[(size_t)j * 2 * keyrow + keyrow];
-        uint64_t xv[KS_RUN];
+        uint64_t xv[RUN];
         #pragma unroll
-        for (int u = 0; u < KS_RUN; u++) {
+        for (int u = 0; u < RUN; u++) {
             const KsJob jb = jobs[run.j0 + (u < cnt ? u : 0)];
             const uint32_t src = (!hoisted || jb.k == 1) ? x : galois_src(x, jb.k, logn);
             xv[u] = X[((size_t)jb.xidx * dn + j) * R * n + (size_t)i * n + src];
         }
         #pragma unroll
-        for (int u = 0; u < KS_RUN; u++) {
+        for (int u = 0; u < RUN; u++) {
             add128(a0[u], mul128(xv[u], k0));
             add128(a1[u], mul128(xv[u], k1));
         }
     }
     const uint64_t q = mods[i], qi = qinv[i], pi = pinv[2 * i], pis = pinv[2 * i + 1];
     // the outputs in two halves of the run (all of a half's loads first)
-    constexpr int HALF = KS_RUN / 2;
+    constexpr int HALF = RUN > 1 ? RUN / 2 : 1;
     #pragma unroll
-    for (int h = 0; h < KS_RUN; h += HALF) {
+    for (int h = 0; h < RUN; h += HALF) {
         uint64_t cv0[HALF], cv1[HALF], c0v[HALF];
         #pragma unroll
         for (int v = 0; v < HALF; v++) {
@@ -324,15 +326,20 @@ __global__ __launch_bounds__(EW_THREADS) void kb_final_inner_kernel(const KsJob*
 }
 
 void kb_final_inner(const Ctx& c, const KsJob* jobs, const KsRun* runs, int nruns, const uint64_t* X,
-                    const uint64_t* conv, int M, int Lc, bool hoisted, hipStream_t st) {
+                    const uint64_t* conv, int M, int Lc, bool hoisted, hipStream_t st, int maxrun) {
     const int dn = Lc / c.alpha;
     // per run and row the key (2 dn words) once; per job its digits (dn), the two
     // conversions, the rotated c0 and the two outputs
     const double rows = (double)Lc * c.n;
     TimeScope ts(c, HC_KT_KS_INNER, st, 8.0 * rows * (2.0 * dn * nruns + (dn + 5.0) * M), 2.0 * dn * rows * M);
-    hc_launch(kb_final_inner_kernel, ew_grid(c.n, Lc, nruns), dim3(EW_THREADS), 0, st, jobs, runs, X, conv,
-                       c.d_mods, c.d_qinv, c.d_pinv, c.n, c.logn, c.nq, Lc, c.K, dn, hoisted ? 1 : 0,
-                       diag_split_h(c, Lc));
+    if (maxrun == 1)
+        hc_launch(kb_final_inner_kernel<1>, ew_grid(c.n, Lc, nruns), dim3(EW_THREADS), 0, st, jobs, runs, X, conv,
+                  c.d_mods, c.d_qinv, c.d_pinv, c.n, c.logn, c.nq, Lc, c.K, dn, hoisted ? 1 : 0,
+                  diag_split_h(c, Lc));
+    else
+        hc_launch(kb_final_inner_kernel<KS_RUN>, ew_grid(c.n, Lc, nruns), dim3(EW_THREADS), 0, st, jobs, runs, X,
+                  conv, c.d_mods, c.d_qinv, c.d_pinv, c.n, c.logn, c.nq, Lc, c.K, dn, hoisted ? 1 : 0,
+                  diag_split_h(c, Lc));
 }
 
 // conv[m][comp][i][x] = sum_k [T_{p_k}(x) (P/p_k)^-1]_{p_k} (P/p_k) mod q_i (coefficient domain).
