@@ -271,6 +271,11 @@ hc_status ntt_build_tw2(Ctx& c);
 bool conv_fused_ring(const Ctx& c);
 void ntt64_low_pass(const Ctx& c, uint64_t* data, size_t poly_stride, int count, int limb_first, int nlimbs,
                     bool inverse, hipStream_t stream);
+// ModUp's forward low-bit pass (ring 2^16) over the ciphertext rows of every raised digit
+// in one launch: X holds `count` = sources x dn polynomials spaced poly_stride apart
+// (digit y % dn of source y / dn), rows 0..Lc-1; a digit's own rows are left as they are.
+// Nothing is launched for dn < 2.
+void ntt64_low_raise(const Ctx& c, uint64_t* X, size_t poly_stride, int count, int Lc, int dn, hipStream_t st);
 // The inverse transform of rows limb_first.. (ciphertext primes of whole digits, or special
 // primes) scaled by the base conversion's factor: [x (D_j/q_i)^-1]_{q_i} or
 // [x (P/p_k)^-1]_{p_k} per coefficient, canonical (one multiplication folded into n^-1).

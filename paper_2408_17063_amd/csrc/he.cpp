@@ -168,13 +168,7 @@ static void ks_raise(Ctx& c, KsScratch& s, const KsJob* d, int U, int Lc, bool p
         ntt_take_c1_low(c, d, s.tmpC, s.X, U, Lc, st);
         ntt64_inverse_high_conv(c, s.tmpC, (size_t)Lc * n, U, 0, Lc, st);
         k_modup_fused(c, s.X, s.tmpC, U, Lc, st);
-        for (int j = 0; j < dn; j++) {
-            uint64_t* Xj = s.X + (size_t)j * R * n;
-            if (j > 0) ntt64_low_pass(c, Xj, (size_t)dn * R * n, U, 0, j * a, false, st);
-            if ((j + 1) * a < Lc)
-                ntt64_low_pass(c, Xj + (size_t)(j + 1) * a * n, (size_t)dn * R * n, U, (j + 1) * a,
-                               Lc - (j + 1) * a, false, st);
-        }
+        ntt64_low_raise(c, s.X, (size_t)R * n, U * dn, Lc, dn, st);
         ntt64_low_pass(c, s.X + (size_t)Lc * n, (size_t)R * n, U * dn, c.L, c.K, false, st);
         return;
     }

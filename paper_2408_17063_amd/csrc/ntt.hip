@@ -822,6 +822,28 @@ void ntt64_low_pass(const Ctx& c, uint64_t* data, size_t poly_stride, int count,
     low_pass_logn<16>(c, data, poly_stride, count, limb_first, nlimbs, inverse, stream);
 }
 
+// The forward low-bit pass (ring 2^16) of the ciphertext rows ModUp computes, every
+// digit in one launch: polynomial y (stride poly_stride) is digit y % dn of its source,
+// and its rows [j alpha, (j + 1) alpha) of digit j are the digit's own (copied in the NTT
+// domain), which the blocks of those rows skip.
+__global__ void __launch_bounds__(NTT_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+ntt_low_raise_kernel(uint64_t* __restrict__ data, size_t poly_stride, NttTab<uint64_t> tab, int dn, int alpha) {
+    typedef Tile<uint64_t, false, 16, 8, 0, 8> TL;
+    __shared__ uint64_t lds[TL::LDS_WORDS];
+    if ((int)blockIdx.z / alpha == (int)(blockIdx.y % (uint32_t)dn)) return;  // whole block
+    ntt_tile<uint64_t, false, 16, 8, 0, 8, true>(data, poly_stride, 0, tab, lds, blockIdx.x, blockIdx.y, blockIdx.z,
+                                                 gridDim.x);
+}
+
+void ntt64_low_raise(const Ctx& c, uint64_t* X, size_t poly_stride, int count, int Lc, int dn, hipStream_t st) {
+    if (count <= 0 || dn < 2 || c.logn != 16) return;
+    NttTab<uint64_t> tab{c.d_tw, c.d_ninv, c.d_mods, c.d_tw2};
+    const double rows = (double)count * (Lc - c.alpha);  // rows transformed
+    TimeScope ts(c, HC_KT_NTT_FWD, st, 16.0 * rows * c.n, rows * (c.n / 2) * 8);
+    hc_launch(ntt_low_raise_kernel, dim3(1u << (16 - TILE_LOG), (unsigned)count, (unsigned)Lc), dim3(NTT_THREADS), 0,
+              st, X, poly_stride, tab, dn, c.alpha);
+}
+
 // The inverse transform's first pass (the low index bits, ring 2^16) of ModUp's inputs,
 // loading them from the jobs' ciphertexts: word g of row r of polynomial u is c1 of
 // jobs[u].in at sigma_{k_u}'s source of g, and it is also stored to the digit's own row
