@@ -260,31 +260,31 @@ __device__ __forceinline__ void to_limbs(uint64_t (&y)[M]) {
 
 // sum_i y_i c_i mod q for y_i < 2^61 and c_i < q in Montgomery form, both as 31-bit
 // limbs (y = y0 + y1 2^31): each term is four 32x32-bit multiply-adds into the column
-// sums a0 (y0 c0), a1 (y0 c1 + y1 c0) and a2 (y1 c1), which hold 4 terms below 2^64;
-// T = a0 + a1 2^31 + a2 2^62 collects 8 terms (below 2^64 q) per reduction.
+// sums of a batch of 8 terms: y0 c0 alternately into a0e and a0o (4 terms each below
+// 2^64), y0 c1 into a1x and y1 c0 into a1y (each below 2^61 a term), y1 c1 into a2. The
+// batch's T = a0e + a0o + (a1x + a1y) 2^31 + a2 2^62 lies below 2^64 q: one REDC.
 template <int M>
 __device__ __forceinline__ uint64_t conv_sum(const uint64_t (&y)[M], const uint64_t* __restrict__ c, uint64_t q,
                                              uint64_t qi) {
     uint64_t v = 0;
     #pragma unroll
     for (int i8 = 0; i8 < M; i8 += 8) {
-        u128p T{0, 0};
+        uint64_t a0e = 0, a0o = 0, a1x = 0, a1y = 0, a2 = 0;
         #pragma unroll
-        for (int i4 = i8; i4 < (i8 + 8 < M ? i8 + 8 : M); i4 += 4) {
-            uint64_t a0 = 0, a1 = 0, a2 = 0;
-            #pragma unroll
-            for (int i = i4; i < (i4 + 4 < M ? i4 + 4 : M); i++) {
-                const uint32_t y0 = (uint32_t)y[i], y1 = (uint32_t)(y[i] >> 32);
-                const uint32_t c0 = (uint32_t)c[i], c1 = (uint32_t)(c[i] >> 32);
-                a0 += (uint64_t)y0 * c0;
-                a1 += (uint64_t)y0 * c1;
-                a1 += (uint64_t)y1 * c0;
-                a2 += (uint64_t)y1 * c1;
-            }
-            add128(T, u128p{a0, 0});
-            add128(T, u128p{a1 << 31, a1 >> 33});
-            add128(T, u128p{a2 << 62, a2 >> 2});
+        for (int i = i8; i < (i8 + 8 < M ? i8 + 8 : M); i++) {
+            const uint32_t y0 = (uint32_t)y[i], y1 = (uint32_t)(y[i] >> 32);
+            const uint32_t c0 = (uint32_t)c[i], c1 = (uint32_t)(c[i] >> 32);
+            if ((i - i8) & 1) a0o += (uint64_t)y0 * c0;
+            else a0e += (uint64_t)y0 * c0;
+            a1x += (uint64_t)y0 * c1;
+            a1y += (uint64_t)y1 * c0;
+            a2 += (uint64_t)y1 * c1;
         }
+        const uint64_t s1 = a1x + a1y, carry = s1 < a1x ? 1 : 0;  // a1x + a1y = s1 + carry 2^64
+        u128p T{a0e, 0};
+        add128(T, u128p{a0o, 0});
+        add128(T, u128p{s1 << 31, (s1 >> 33) | (carry << 31)});
+        add128(T, u128p{a2 << 62, a2 >> 2});
         v = add_mod(v, redc(T, q, qi), q);
     }
     return v;
